@@ -1,0 +1,138 @@
+"""Throughput of the dense-suspension time step on one MI355X.
+
+Workload: N = 100 000 bidisperse spheres (radii 1 and 1.4, equal volumes), phi = 0.55, simple
+shear rate 1 under Lees-Edwards boundaries, mu = 1, dt = 1e-4, stress sampled every 10 steps.
+Inputs are seeded synthetic packings already resident in device memory when timing starts.
+
+Prints one JSON line: particle-steps/s, the roofline of the dominant kernel (k_pairs) from HIP
+events recorded on the library's stream over the timed region, and the FP64 CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def pairs_kernel_bytes(N: int, ncell: int, contacts: int, capacity: int) -> float:
+    """Compulsory bytes of one k_pairs launch in the FP64 layout.
+
+    per particle: pa, vel, omg records read (3 x 32 B), frc, trq written (2 x 32 B), its old-row
+    slot (inv 4 B) and count (4 B), new row count and owner (8 B);
+    per cell: cell_start (4 B);
+    per contact (each stored once): old key + xi read (4 + 24 B), new key + xi written (4 + 24 B)."""
+    return N * (3 * 32 + 2 * 32 + 4 + 4 + 8) + 4.0 * (ncell + 1) + contacts * (28 + 28)
+
+
+def cpu_baseline(w, seconds: float = 10.0):
+    import numpy as np  # noqa: F401
+
+    import oracle
+    p = w.params
+    threads = oracle.num_threads()
+    st, F, T, S = oracle.init_state(p, w.x, w.rad, use_cells=True)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        st, *_ = oracle.step(p, st, use_cells=True)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 200:
+            break
+    N = len(w.rad)
+    return {"value": N * steps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps (cell-list pair search, OpenMP) of the same N={N} "
+                      f"phi=0.55 workload, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--N", type=int, default=100_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the design of a "
+              "z-slab decomposition is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2108_01013_amd import synth
+    from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Simulation
+
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    w = synth.config_single_box(N=args.N)
+    print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    p = w.params
+    prec = DSS_FP64 if args.precision == "fp64" else DSS_MIXED
+    sim = Simulation(p, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
+    sim.set_particles(w.x, w.rad)
+    sim.step(args.warmup, stress_every=10, sync=True)
+    torch.cuda.synchronize()
+
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps, stress_every=10, sync=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    timing = sim.timing()
+    sim.set_timing(False)
+    info = sim.info()
+    _, sigma_mean, nsamp = sim.read_stress()
+    if info["error_flags"]:
+        print(f"# device error flags {info['error_flags']}", file=sys.stderr)
+        sys.exit(1)
+
+    N = len(w.rad)
+    value = N * args.steps / el
+    ms_pairs, n_pairs_launch = timing["k_pairs"]
+    avg_pairs_s = ms_pairs / max(n_pairs_launch, 1) * 1e-3
+    ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2])
+    bytes_launch = pairs_kernel_bytes(N, ncell, info["n_contacts"], info["capacity"])
+    achieved = bytes_launch / avg_pairs_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": "k_pairs", "avg_launch_us": round(avg_pairs_s * 1e6, 3),
+            "bytes_per_launch": int(bytes_launch)}
+    kernels = {k: {"avg_us": round(v[0] / max(v[1], 1) * 1e3, 3), "launches": v[1]} for k, v in timing.items()}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_seconds)
+    out = {
+        "metric": "particle-steps/s at N=100k phi=0.55; mixed/batched/adjoint vs plain FP64",
+        "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"single box N={N} bidisperse 1:1.4 equal volume, phi=0.55, LE shear rate 1, "
+                               f"mu=1, dt=1e-4, stress every 10 steps, {args.precision}",
+                   "N": N, "phi": 0.55, "precision": args.precision},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "diagnostics": {"n_pairs": info["n_pairs"], "n_contacts": info["n_contacts"],
+                        "max_row_fill": info["max_row_fill"], "capacity": info["capacity"],
+                        "cells": info["cells"], "stress_samples": nsamp,
+                        "eta_r_mean": float(sigma_mean[0, 1] / (p["eta0"] * p["shear_rate"]))},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

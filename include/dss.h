@@ -1,0 +1,179 @@
+/*
+ * dss.h -- C ABI of the MI355X dense-suspension step library (libdss).
+ *
+ * Method: Monti, Rathee, Shen & Rosti, "A fast and efficient tool to study the
+ * rheology of dense suspensions" (arXiv 2108.01013).  One time step advances N
+ * polydisperse spheres under Lees-Edwards simple shear:
+ *   - modified velocity-Verlet kick/drift (Sec. 2.1, numerical algorithm) and the
+ *     Lees-Edwards wrap (eq. le);
+ *   - counting sort of the particles into a cell lattice and the symmetric
+ *     half-shell neighbour search (Sec. 2.1, Figs. alg and alg2);
+ *   - pair forces: lubrication (eq. hydro, Appendix A), spring-dashpot contact with
+ *     tangential history and Coulomb cap (eqs. contact0, csi), repulsion (eq. rep),
+ *     attraction (eq. att), plus per-particle Stokes drag (eq. rst);
+ *   - contact history in a reduced N x M matrix whose rows are sorted by partner
+ *     index (Sec. 2.1, memory paragraph);
+ *   - bulk stress tensor (eqs. stress, stresslet).
+ *
+ * Conventions (all entry points):
+ *   - Every call returns a dss_status; DSS_OK = 0.  After an error,
+ *     dss_last_error(h) returns a message owned by the handle.
+ *   - Arrays of 3-vectors are N x 3, row-major, FP64, indexed by particle id
+ *     0..N-1 = the order given to dss_set_particles.
+ *   - "on_device" = 1: the pointer is device memory of the handle's GPU; 0: host
+ *     memory.  The library never keeps a caller's pointer after a call returns;
+ *     the caller keeps ownership of every buffer it passes.
+ *   - All work is enqueued on the stream given to dss_create (NULL = a stream the
+ *     handle creates).  Calls that return data to the caller synchronise that
+ *     stream.  A handle is not thread-safe: use one handle per host thread/stream.
+ *   - Device-side error flags (history-row overflow, non-finite forces) are checked
+ *     whenever a call synchronises and reported as DSS_ERR_CAPACITY /
+ *     DSS_ERR_UNSTABLE.
+ */
+#ifndef DSS_H
+#define DSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dss_handle dss_handle;
+
+typedef enum {
+    DSS_OK = 0,
+    DSS_ERR_ARG = 1,      /* invalid argument (null pointer, N < 1, non-positive size, bad position) */
+    DSS_ERR_HIP = 2,      /* a HIP runtime call failed */
+    DSS_ERR_CAPACITY = 3, /* a contact-history row or a caller buffer was too small */
+    DSS_ERR_BOX = 4,      /* cell lattice too small: needs >= 4 cells along x and >= 3 along y, z */
+    DSS_ERR_UNSTABLE = 5, /* non-finite force or torque */
+    DSS_ERR_STATE = 6     /* call out of order (e.g. step before set_particles) */
+} dss_status;
+
+typedef enum { DSS_FP64 = 0, DSS_MIXED = 1 } dss_precision;
+
+/* Bits of dss_params.flags */
+#define DSS_FLAG_RECORD_PAIRS 1 /* keep the listed pairs of the last force evaluation (dss_get_pairs) */
+
+/* Physical and numerical parameters (units are the caller's; the defaults used by the
+ * tests are eta0 = a_min = gdot = 1).  Ambient flow: simple shear U_inf = (gdot y, 0, 0),
+ * Omega_inf = (0, 0, -gdot/2), E_inf_xy = E_inf_yx = gdot/2 (Sec. 2). */
+typedef struct {
+    double L[3];          /* box lengths; the box is [0, L_x) x [0, L_y) x [0, L_z) */
+    double shear_rate;    /* gdot */
+    double eta0;          /* fluid viscosity */
+    double rho;           /* particle density: m = rho 4/3 pi a^3, I = 2/5 m a^2 */
+    double kn, kt;        /* normal / tangential spring constants, eq. contact0 */
+    double gamma_n;       /* normal dashpot, eq. contact0 */
+    double mu;            /* Coulomb friction coefficient, eq. csi */
+    double F_ER;          /* repulsion strength, eq. rep */
+    double lambda_D;      /* Debye length, eq. rep */
+    double a0;            /* reference radius of eq. rep */
+    double hamaker;       /* Hamaker constant A, eq. att (0 = no attraction) */
+    double eps_vdw;       /* attraction regularisation as a fraction of the harmonic radius */
+    double eps_lub;       /* lubrication regularisation epsilon (Appendix A) */
+    double cutoff_factor; /* a pair is listed iff |r| < cutoff_factor (a_i + a_j) */
+    double dt;            /* time step */
+    int32_t precision;    /* dss_precision */
+    int32_t capacity;     /* history row capacity; 0 = the paper's estimate M(a_max, a_min) */
+    int32_t flags;        /* DSS_FLAG_* */
+    int32_t reserved;     /* must be 0 */
+} dss_params;
+
+/* Diagnostics of the most recent force evaluation. */
+typedef struct {
+    int64_t n_particles;
+    int64_t step;          /* time index n of the current state, t = n dt */
+    int32_t cells[3];      /* lattice dimensions */
+    int32_t capacity;      /* history row capacity M */
+    int64_t n_pairs;       /* listed pairs */
+    int64_t n_contacts;    /* pairs with d_ij < 0 */
+    int32_t max_row_fill;  /* largest history row */
+    int32_t error_flags;   /* raw device flags: 1 row overflow, 2 non-finite, 4 pair buffer overflow */
+    double le_offset;      /* Lees-Edwards offset delta of the current state */
+} dss_info;
+
+/* Create a handle.  p is copied.  hip_stream: a hipStream_t of the current device, or
+ * NULL.  Fails with DSS_ERR_ARG for non-positive L, dt, cutoff_factor, rho or a0, or
+ * reserved != 0. */
+dss_status dss_create(const dss_params *p, void *hip_stream, dss_handle **out);
+
+/* Load N particles (copy-in) and evaluate the initial forces at t = 0:
+ * x: N x 3 positions inside the box; radius: N radii > 0; u, omega: N x 3 initial
+ * velocities, or NULL for the ambient flow U_inf(x), Omega_inf.  The contact history
+ * starts empty and the time index at 0.  Allocates all device memory of the handle
+ * (sized for N and the row capacity M).  Fails with DSS_ERR_ARG for a position outside
+ * [0, L) or a radius <= 0, DSS_ERR_BOX if the lattice has fewer than 4 x 3 x 3 cells. */
+dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const double *radius, const double *u,
+                             const double *omega, int on_device);
+
+/* Set the time index n of the current state (t = n dt; the Lees-Edwards offset follows
+ * eq. le).  Forces are not re-evaluated: call dss_compute_forces afterwards.  For restarts
+ * and for tests of the sheared boundary at arbitrary offsets.  Fails with DSS_ERR_ARG for
+ * n < 0. */
+dss_status dss_set_step(dss_handle *h, int64_t n);
+
+/* Counting sort of the current positions into the cell lattice (no time advance). */
+dss_status dss_build_neighbours(dss_handle *h);
+
+/* Forces, torques and stress at the current state (positions, velocities u^n, the
+ * current contact history), without advancing time or the history. */
+dss_status dss_compute_forces(dss_handle *h);
+
+/* Advance n_steps time steps.  If stress_every > 0, the stress tensor is sampled at
+ * every step whose time index is a multiple of stress_every; the samples of this call
+ * are returned by dss_read_stress.  Does not synchronise unless sync != 0 (then device
+ * error flags are checked). */
+dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sync);
+
+/* Stress of the last force evaluation (sigma_last, 9 values, row-major Sigma_ab) and the
+ * mean over the samples of the last dss_step call (sigma_mean, nullable); n_samples
+ * receives the sample count (nullable).  Sigma = 2 eta0 E_inf + (1/V)(sum_i S^S_i +
+ * sum_pairs (S^L + S^C + S^E)), eq. stress, each pair once. */
+dss_status dss_read_stress(dss_handle *h, double *sigma_last, double *sigma_mean, int64_t *n_samples);
+
+/* State at the current time index n, by particle id: x^n, u^n, omega^n, F^n, T^n (each
+ * N x 3, nullable).  F, T are the totals of the last force evaluation. */
+dss_status dss_get_state(dss_handle *h, double *x, double *u, double *omega, double *F, double *T, int on_device);
+
+/* The velocities the last forces were evaluated with (u^{n-1/2}... i.e. the half-step
+ * velocities u^{n+1/2} of the step that produced the state; after dss_compute_forces or
+ * dss_set_particles they equal u^n, omega^n). */
+dss_status dss_get_eval_velocities(dss_handle *h, double *u, double *omega, int on_device);
+
+/* Listed pairs of the last force evaluation, (id_min, id_max), unordered; requires
+ * DSS_FLAG_RECORD_PAIRS.  *n receives the count; fails with DSS_ERR_CAPACITY if cap < *n. */
+dss_status dss_get_pairs(dss_handle *h, int64_t cap, int32_t *pairs, int64_t *n);
+
+/* Cell lattice of the last counting sort: dims[3], cell_start (n_cells + 1 entries) and
+ * perm (N entries: particle id at each sorted position); host pointers. */
+dss_status dss_get_cells(dss_handle *h, int32_t *dims, int64_t cap_cells, int32_t *cell_start, int32_t *perm);
+
+/* Contact history after the last step: pairs (id_min, id_max) and xi (3 per pair, the
+ * tangential stretch oriented from id_min to id_max), unordered; host pointers. */
+dss_status dss_get_history(dss_handle *h, int64_t cap, int32_t *pairs, double *xi, int64_t *n);
+
+/* Diagnostics of the most recent force evaluation (synchronises). */
+dss_status dss_get_info(dss_handle *h, dss_info *info);
+
+/* Bytes needed by dss_save_state (nullable blob: size query) / restore of a snapshot. */
+dss_status dss_save_state(dss_handle *h, void *blob, size_t *bytes);
+dss_status dss_load_state(dss_handle *h, const void *blob, size_t bytes);
+
+/* Kernel timing with HIP events recorded on the handle's stream around every kernel
+ * launch of the time step (enable != 0 starts a new accumulation).  dss_get_timing
+ * synchronises and returns, for kernel k (0 predict, 1 scan, 2 scatter, 3 pairs,
+ * 4 sample), the summed duration in ms and the number of launches since enabling. */
+dss_status dss_set_timing(dss_handle *h, int enable);
+dss_status dss_get_timing(dss_handle *h, int kernel, double *total_ms, int64_t *launches);
+
+const char *dss_last_error(const dss_handle *h);
+const char *dss_status_string(dss_status s);
+void dss_destroy(dss_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSS_H */

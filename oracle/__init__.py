@@ -327,14 +327,17 @@ def accelerations(p, rad, F, T):
 
 
 def init_state(p, x, rad, u=None, w=None, use_cells=False):
-    """Initial state: u^0 = U_inf(x^0), w^0 = Omega_inf unless given, H^0 empty, alpha^0 = F(x^0, u^0)/m."""
+    """Initial state: u^0 = U_inf(x^0), w^0 = Omega_inf unless given, alpha^0 = F(x^0, u^0)/m.
+
+    The evaluation at t = 0 only defines alpha^0; the contact history H^0 is empty, so every
+    tangential spring starts from xi(t0) = 0 at the first step (eq. csi)."""
     x = _f64(x, (-1, 3)).copy()
     rad = _f64(rad).copy()
     u = ambient_velocity(p, x) if u is None else _f64(u, (-1, 3)).copy()
     w = ambient_rotation(p, len(rad)) if w is None else _f64(w, (-1, 3)).copy()
     F, T, S, H, npairs = forces(p, x, u, w, rad, 0, None, use_cells)
     a, aw = accelerations(p, rad, F, T)
-    return State(x, u, w, a, aw, rad, 0, H), F, T, S
+    return State(x, u, w, a, aw, rad, 0, History()), F, T, S
 
 
 def kick_drift(p, st: State):

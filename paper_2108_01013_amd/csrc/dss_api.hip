@@ -1,0 +1,689 @@
+// dss_api.hip -- host side of libdss: handle, device memory, launch sequence, C ABI.
+//
+// One time step (dss_step) enqueues, on the handle's stream:
+//   k_predict  (sorted order of the previous step)  kick/drift, Lees-Edwards wrap, cell id, rank
+//   k_scan     exclusive scan of the cell counts -> cell_start, clock advance
+//   k_scatter  reorder into the new sorted order, id -> slot map, clear force accumulators
+//   k_pairs    half-shell search, pair physics, new history rows, stress
+//   k_sample   store the stress sample when the schedule asks for it
+// The history rows written by k_pairs become the committed history of the step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dss.h"
+#include "dss_kernels.hpp"
+
+using namespace dss;
+
+struct dss_handle {
+    dss_params prm{};
+    DevParams P{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    std::string err;
+
+    int64_t N = 0;
+    bool loaded = false;
+    bool vel_is_half = false;  // vel holds the half-step velocity of the last forces
+    int cur = 0;               // particle buffers holding the current state
+    int hh = 0;                // history buffers holding the committed history
+    int ih = 0;                // inverse-map buffer matching the committed history
+    int64_t step = 0;          // host mirror of the time index
+    double sum_a3 = 0.0;
+
+    double4 *pa[2] = {nullptr, nullptr}, *vel[2] = {nullptr, nullptr}, *omg[2] = {nullptr, nullptr};
+    double4 *frc = nullptr, *trq = nullptr;
+    int *cell = nullptr, *rank = nullptr, *count = nullptr, *cell_start = nullptr;
+    int *inv[2] = {nullptr, nullptr};
+    int *hkey[2] = {nullptr, nullptr}, *hcnt[2] = {nullptr, nullptr}, *hown[2] = {nullptr, nullptr};
+    double *hxi[2] = {nullptr, nullptr};
+    int *pairs = nullptr;
+    unsigned long long *pair_count = nullptr;
+    DevClock *clk = nullptr;
+    DevRun *run = nullptr;
+    double *sigma_last = nullptr;
+    double *samples = nullptr;
+    int64_t sample_cap_alloc = 0;
+    int64_t last_samples = 0;
+    DevRun run_host{};
+
+    // kernel timing with events on the stream
+    static constexpr int kKernels = 5;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<int, int>>> ev_marks;  // (kernel, (start event, stop event))
+    double kernel_ms[kKernels] = {0, 0, 0, 0, 0};
+    int64_t kernel_launches[kKernels] = {0, 0, 0, 0, 0};
+};
+
+namespace {
+
+const char *kStatusText[] = {"ok", "invalid argument", "HIP error", "capacity exceeded", "cell lattice too small",
+                             "non-finite force or torque", "call out of order"};
+
+dss_status fail(dss_handle *h, dss_status s, const std::string &msg)
+{
+    if (h) h->err = msg;
+    return s;
+}
+
+#define HIPTRY(expr)                                                                                  \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return fail(h, DSS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T **p, size_t n)
+{
+    return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+void free_all(dss_handle *h)
+{
+    auto F = [](void *p) {
+        if (p) (void)hipFree(p);
+    };
+    for (int k = 0; k < 2; ++k) {
+        F(h->pa[k]); F(h->vel[k]); F(h->omg[k]); F(h->inv[k]);
+        F(h->hkey[k]); F(h->hcnt[k]); F(h->hown[k]); F(h->hxi[k]);
+        h->pa[k] = h->vel[k] = h->omg[k] = nullptr;
+        h->inv[k] = h->hkey[k] = h->hcnt[k] = h->hown[k] = nullptr;
+        h->hxi[k] = nullptr;
+    }
+    F(h->frc); F(h->trq); F(h->cell); F(h->rank); F(h->count); F(h->cell_start);
+    F(h->pairs); F(h->pair_count); F(h->clk); F(h->run); F(h->sigma_last); F(h->samples);
+    h->frc = h->trq = nullptr;
+    h->cell = h->rank = h->count = h->cell_start = h->pairs = nullptr;
+    h->pair_count = nullptr;
+    h->clk = nullptr;
+    h->run = nullptr;
+    h->sigma_last = h->samples = nullptr;
+    h->sample_cap_alloc = 0;
+    h->loaded = false;
+}
+
+// Row capacity of the reduced history matrix: the shell of thickness 2 a_min around the
+// largest particle, in units of the smallest particle's volume (Sec. 2.1).
+int paper_capacity(double a_max, double a_min)
+{
+    double outer = a_max + 2.0 * a_min;
+    double shell = outer * outer * outer - a_max * a_max * a_max;
+    return (int)std::ceil(shell / (a_min * a_min * a_min));
+}
+
+dss_status check_flags(dss_handle *h)
+{
+    DevClock c;
+    HIPTRY(hipMemcpyAsync(&c, h->clk, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    if (c.err & kErrNonFinite) return fail(h, DSS_ERR_UNSTABLE, "non-finite force or torque");
+    if (c.err & kErrRowOverflow)
+        return fail(h, DSS_ERR_CAPACITY, "contact-history row overflow (max fill " + std::to_string(c.max_fill) +
+                                             ", capacity " + std::to_string(h->P.M) + ")");
+    return DSS_OK;
+}
+
+// Event pair around one launch when timing is on (events are reused across calls).
+struct TimedLaunch {
+    dss_handle *h;
+    int kernel;
+    int e0 = -1, e1 = -1;
+    TimedLaunch(dss_handle *h_, int k) : h(h_), kernel(k)
+    {
+        if (!h->timing) return;
+        e0 = take();
+        if (e0 >= 0) (void)hipEventRecord(h->ev_pool[e0], h->stream);
+    }
+    ~TimedLaunch()
+    {
+        if (e0 < 0) return;
+        e1 = take();
+        if (e1 < 0) return;
+        (void)hipEventRecord(h->ev_pool[e1], h->stream);
+        h->ev_marks.push_back({kernel, {e0, e1}});
+    }
+    int take()
+    {
+        size_t used = 2 * h->ev_marks.size() + (e0 >= 0 ? 1 : 0);
+        if (used >= h->ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            h->ev_pool.push_back(e);
+        }
+        return (int)used;
+    }
+};
+
+dss_status collect_timing(dss_handle *h)
+{
+    if (h->ev_marks.empty()) return DSS_OK;
+    HIPTRY(hipStreamSynchronize(h->stream));
+    for (auto &m : h->ev_marks) {
+        float ms = 0.f;
+        HIPTRY(hipEventElapsedTime(&ms, h->ev_pool[m.second.first], h->ev_pool[m.second.second]));
+        h->kernel_ms[m.first] += ms;
+        h->kernel_launches[m.first] += 1;
+    }
+    h->ev_marks.clear();
+    return DSS_OK;
+}
+
+dss_status require_loaded(dss_handle *h)
+{
+    if (!h) return DSS_ERR_ARG;
+    if (!h->loaded) return fail(h, DSS_ERR_STATE, "no particles loaded (call dss_set_particles first)");
+    return DSS_OK;
+}
+
+// One force evaluation on the current state.  advance = 1: a full time step (drift +
+// kick first, history committed); advance = 0: evaluation at the current state.
+dss_status evaluate(dss_handle *h, int advance)
+{
+    const int N = (int)h->N;
+    const int grid = (N + kBlock - 1) / kBlock;
+    const int c = h->cur, o = 1 - h->cur;
+    {
+        TimedLaunch t(h, 0);
+        hipLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c],
+                       h->frc, h->trq, h->vel_is_half ? 1 : 0, advance, h->clk, h->cell, h->rank, h->count);
+    }
+    {
+        TimedLaunch t(h, 1);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, h->stream, h->P.ncell, h->count, h->cell_start, h->clk,
+                       advance, h->run);
+    }
+    {
+        TimedLaunch t(h, 2);
+        hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, h->stream, N, h->cell, h->rank, h->cell_start,
+                       h->pa[c], h->vel[c], h->omg[c], h->pa[o], h->vel[o], h->omg[o], h->frc, h->trq,
+                       h->inv[1 - h->ih]);
+    }
+    if (h->P.record_pairs) HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
+    HistView H;
+    H.key_old = h->hkey[h->hh];
+    H.xi_old = h->hxi[h->hh];
+    H.cnt_old = h->hcnt[h->hh];
+    H.inv_old = h->inv[h->ih];
+    H.key_new = h->hkey[1 - h->hh];
+    H.xi_new = h->hxi[1 - h->hh];
+    H.cnt_new = h->hcnt[1 - h->hh];
+    H.own_new = h->hown[1 - h->hh];
+    {
+        TimedLaunch t(h, 3);
+        hipLaunchKernelGGL(k_pairs, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->cell_start, h->pa[o], h->vel[o],
+                       h->omg[o], h->frc, h->trq, H, h->clk, h->run, h->pairs, h->pair_count);
+    }
+    if (advance) {
+        TimedLaunch t(h, 4);
+        hipLaunchKernelGGL(k_sample, dim3(1), dim3(64), 0, h->stream, h->clk, h->run);
+    }
+    HIPTRY(hipGetLastError());
+    h->cur = o;
+    h->vel_is_half = advance != 0;
+    if (advance) {
+        h->hh = 1 - h->hh;
+        h->ih = 1 - h->ih;
+        h->step += 1;
+    }
+    return DSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dss_status_string(dss_status s)
+{
+    int k = (int)s;
+    if (k < 0 || k > 6) return "unknown status";
+    return kStatusText[k];
+}
+
+const char *dss_last_error(const dss_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+dss_status dss_set_timing(dss_handle *h, int enable)
+{
+    if (!h) return DSS_ERR_ARG;
+    dss_status s = collect_timing(h);
+    if (s) return s;
+    h->timing = enable != 0;
+    for (int k = 0; k < dss_handle::kKernels; ++k) {
+        h->kernel_ms[k] = 0.0;
+        h->kernel_launches[k] = 0;
+    }
+    return DSS_OK;
+}
+
+dss_status dss_get_timing(dss_handle *h, int kernel, double *total_ms, int64_t *launches)
+{
+    if (!h) return DSS_ERR_ARG;
+    if (kernel < 0 || kernel >= dss_handle::kKernels) return fail(h, DSS_ERR_ARG, "kernel index out of range");
+    dss_status s = collect_timing(h);
+    if (s) return s;
+    if (total_ms) *total_ms = h->kernel_ms[kernel];
+    if (launches) *launches = h->kernel_launches[kernel];
+    return DSS_OK;
+}
+
+dss_status dss_create(const dss_params *p, void *hip_stream, dss_handle **out)
+{
+    if (!p || !out) return DSS_ERR_ARG;
+    *out = nullptr;
+    if (!(p->L[0] > 0 && p->L[1] > 0 && p->L[2] > 0) || !(p->dt > 0) || !(p->cutoff_factor > 0) ||
+        !(p->rho > 0) || !(p->a0 > 0) || p->reserved != 0 || p->capacity < 0 ||
+        (p->precision != DSS_FP64 && p->precision != DSS_MIXED) || !(p->eps_lub > 0))
+        return DSS_ERR_ARG;
+    dss_handle *h = new dss_handle();
+    h->prm = *p;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return DSS_ERR_HIP;
+    }
+    if (hip_stream) {
+        h->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&h->stream) != hipSuccess) {
+            delete h;
+            return DSS_ERR_HIP;
+        }
+        h->own_stream = true;
+    }
+    *out = h;
+    return DSS_OK;
+}
+
+void dss_destroy(dss_handle *h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+    free_all(h);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const double *radius, const double *u,
+                             const double *omega, int on_device)
+{
+    if (!h) return DSS_ERR_ARG;
+    if (N < 1 || N > (int64_t)0x3fffffff || !x || !radius) return fail(h, DSS_ERR_ARG, "N < 1 or null x / radius");
+    const dss_params &p = h->prm;
+    // host copies for validation and the lattice size
+    std::vector<double> hx(3 * N), hr(N);
+    if (on_device) {
+        HIPTRY(hipMemcpy(hx.data(), x, 3 * N * sizeof(double), hipMemcpyDeviceToHost));
+        HIPTRY(hipMemcpy(hr.data(), radius, N * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(hx.data(), x, 3 * N * sizeof(double));
+        std::memcpy(hr.data(), radius, N * sizeof(double));
+    }
+    double a_min = INFINITY, a_max = 0.0, sa3 = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        if (!(hr[i] > 0.0) || !std::isfinite(hr[i])) return fail(h, DSS_ERR_ARG, "radius must be finite and > 0");
+        a_min = std::min(a_min, hr[i]);
+        a_max = std::max(a_max, hr[i]);
+        sa3 += hr[i] * hr[i] * hr[i];
+        for (int d = 0; d < 3; ++d)
+            if (!(hx[3 * i + d] >= 0.0 && hx[3 * i + d] < p.L[d]))
+                return fail(h, DSS_ERR_ARG, "position outside [0, L) for particle " + std::to_string(i));
+    }
+    // lattice: spacing >= the largest cutoff 2 c a_max (with a 1e-9 margin)
+    DevParams P{};
+    for (int d = 0; d < 3; ++d) P.L[d] = p.L[d];
+    P.gd = p.shear_rate; P.eta0 = p.eta0; P.rho = p.rho; P.kn = p.kn; P.kt = p.kt; P.gn = p.gamma_n;
+    P.mu = p.mu; P.fer = p.F_ER; P.lamd = p.lambda_D; P.a0 = p.a0; P.ham = p.hamaker; P.eps_vdw = p.eps_vdw;
+    P.eps_lub = p.eps_lub; P.cf = p.cutoff_factor; P.dt = p.dt;
+    const double rc = p.cutoff_factor * 2.0 * a_max * (1.0 + 1e-9);
+    for (int d = 0; d < 3; ++d) {
+        P.nc[d] = std::max(1, (int)std::floor(p.L[d] / rc));
+        P.cw[d] = p.L[d] / (double)P.nc[d];
+    }
+    if (P.nc[0] < 4 || P.nc[1] < 3 || P.nc[2] < 3)
+        return fail(h, DSS_ERR_BOX, "cell lattice " + std::to_string(P.nc[0]) + "x" + std::to_string(P.nc[1]) + "x" +
+                                        std::to_string(P.nc[2]) + " is smaller than 4x3x3");
+    const int64_t ncell = (int64_t)P.nc[0] * P.nc[1] * P.nc[2];
+    if (ncell > (int64_t)0x3fffffff) return fail(h, DSS_ERR_BOX, "too many cells");
+    P.ncell = (int)ncell;
+    P.N = (int)N;
+    P.M = p.capacity > 0 ? p.capacity : paper_capacity(a_max, a_min);
+    P.record_pairs = (p.flags & DSS_FLAG_RECORD_PAIRS) ? 1 : 0;
+    P.pair_cap = P.record_pairs ? 32 * N + 64 : 0;
+
+    free_all(h);
+    h->P = P;
+    h->N = N;
+    h->sum_a3 = sa3;
+    const size_t rows = (size_t)N * (size_t)P.M;
+    for (int k = 0; k < 2; ++k) {
+        HIPTRY(dalloc(&h->pa[k], N));
+        HIPTRY(dalloc(&h->vel[k], N));
+        HIPTRY(dalloc(&h->omg[k], N));
+        HIPTRY(dalloc(&h->inv[k], N));
+        HIPTRY(dalloc(&h->hkey[k], rows));
+        HIPTRY(dalloc(&h->hxi[k], rows * 3));
+        HIPTRY(dalloc(&h->hcnt[k], N));
+        HIPTRY(dalloc(&h->hown[k], N));
+    }
+    HIPTRY(dalloc(&h->frc, N));
+    HIPTRY(dalloc(&h->trq, N));
+    HIPTRY(dalloc(&h->cell, N));
+    HIPTRY(dalloc(&h->rank, N));
+    HIPTRY(dalloc(&h->count, ncell));
+    HIPTRY(dalloc(&h->cell_start, ncell + 1));
+    HIPTRY(dalloc(&h->pairs, P.record_pairs ? 2 * P.pair_cap : 2));
+    HIPTRY(dalloc(&h->pair_count, 1));
+    HIPTRY(dalloc(&h->clk, 1));
+    HIPTRY(dalloc(&h->run, 1));
+    HIPTRY(dalloc(&h->sigma_last, 9));
+    HIPTRY(hipMemsetAsync(h->count, 0, ncell * sizeof(int), h->stream));
+    HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
+    HIPTRY(hipMemsetAsync(h->clk, 0, sizeof(DevClock), h->stream));
+    HIPTRY(hipMemsetAsync(h->sigma_last, 0, 9 * sizeof(double), h->stream));
+    for (int k = 0; k < 2; ++k) {
+        HIPTRY(hipMemsetAsync(h->hcnt[k], 0, N * sizeof(int), h->stream));
+        HIPTRY(hipMemsetAsync(h->hown[k], 0, N * sizeof(int), h->stream));
+    }
+    h->run_host = DevRun{};
+    h->run_host.sigma_last = h->sigma_last;
+    HIPTRY(hipMemcpyAsync(h->run, &h->run_host, sizeof(DevRun), hipMemcpyHostToDevice, h->stream));
+
+    // stage the inputs on the device
+    double *dx = nullptr, *dr = nullptr, *du = nullptr, *dw = nullptr;
+    HIPTRY(dalloc(&dx, 3 * N));
+    HIPTRY(dalloc(&dr, N));
+    HIPTRY(hipMemcpyAsync(dx, hx.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPTRY(hipMemcpyAsync(dr, hr.data(), N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    if (u) {
+        HIPTRY(dalloc(&du, 3 * N));
+        HIPTRY(hipMemcpyAsync(du, u, 3 * N * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              h->stream));
+    }
+    if (omega) {
+        HIPTRY(dalloc(&dw, 3 * N));
+        HIPTRY(hipMemcpyAsync(dw, omega, 3 * N * sizeof(double),
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+    }
+    h->cur = 0;
+    h->hh = 0;
+    h->ih = 0;
+    h->step = 0;
+    h->vel_is_half = false;
+    const int grid = (int)((N + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_load, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, dx, dr, du, dw, P.gd, h->pa[0],
+                       h->vel[0], h->omg[0], h->frc, h->trq, h->inv[0]);
+    HIPTRY(hipGetLastError());
+    h->loaded = true;
+    dss_status s = evaluate(h, 0);
+    HIPTRY(hipStreamSynchronize(h->stream));
+    (void)hipFree(dx);
+    (void)hipFree(dr);
+    if (du) (void)hipFree(du);
+    if (dw) (void)hipFree(dw);
+    if (s != DSS_OK) return s;
+    return check_flags(h);
+}
+
+dss_status dss_set_step(dss_handle *h, int64_t n)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (n < 0) return fail(h, DSS_ERR_ARG, "negative time index");
+    DevClock c;
+    HIPTRY(hipMemcpyAsync(&c, h->clk, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    c.step = n;
+    HIPTRY(hipMemcpyAsync(h->clk, &c, sizeof(c), hipMemcpyHostToDevice, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    h->step = n;
+    return DSS_OK;
+}
+
+dss_status dss_build_neighbours(dss_handle *h)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    // a rebuild is an evaluation without time advance; its forces equal the current ones
+    return dss_compute_forces(h);
+}
+
+dss_status dss_compute_forces(dss_handle *h)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    s = evaluate(h, 0);
+    if (s) return s;
+    return check_flags(h);
+}
+
+dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sync)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (n_steps < 0 || stress_every < 0) return fail(h, DSS_ERR_ARG, "negative n_steps or stress_every");
+    // stress sampling schedule of this call
+    int64_t first = 0, cap = 0;
+    if (stress_every > 0) {
+        first = ((h->step / stress_every) + 1) * stress_every;
+        int64_t last = h->step + n_steps;
+        cap = last >= first ? (last - first) / stress_every + 1 : 0;
+    }
+    if (cap > h->sample_cap_alloc) {
+        if (h->samples) HIPTRY(hipFree(h->samples));
+        h->samples = nullptr;
+        HIPTRY(dalloc(&h->samples, 9 * cap));
+        h->sample_cap_alloc = cap;
+    }
+    h->run_host.sample_every = cap > 0 ? stress_every : 0;
+    h->run_host.sample_first = first;
+    h->run_host.sample_cap = cap;
+    h->run_host.samples = h->samples;
+    h->run_host.sigma_last = h->sigma_last;
+    HIPTRY(hipMemcpyAsync(h->run, &h->run_host, sizeof(DevRun), hipMemcpyHostToDevice, h->stream));
+    h->last_samples = cap;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        s = evaluate(h, 1);
+        if (s) return s;
+    }
+    if (sync) return check_flags(h);
+    return DSS_OK;
+}
+
+dss_status dss_read_stress(dss_handle *h, double *sigma_last, double *sigma_mean, int64_t *n_samples)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    const dss_params &p = h->prm;
+    const double V = p.L[0] * p.L[1] * p.L[2];
+    // constant part: 2 eta0 E_inf + (1/V) sum_i 20/3 pi eta0 a_i^3 E_inf (eqs. stress, stresslet)
+    double base[9] = {0};
+    const double exy = 0.5 * p.shear_rate;
+    const double c = 2.0 * p.eta0 * exy + (20.0 / 3.0) * kPi * p.eta0 * h->sum_a3 * exy / V;
+    base[1] = c;
+    base[3] = c;
+    double last[9];
+    HIPTRY(hipMemcpyAsync(last, h->sigma_last, sizeof(last), hipMemcpyDeviceToHost, h->stream));
+    std::vector<double> smp(9 * std::max<int64_t>(h->last_samples, 1));
+    if (sigma_mean && h->last_samples > 0)
+        HIPTRY(hipMemcpyAsync(smp.data(), h->samples, 9 * h->last_samples * sizeof(double), hipMemcpyDeviceToHost,
+                              h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    if (sigma_last)
+        for (int k = 0; k < 9; ++k) sigma_last[k] = base[k] + last[k] / V;
+    if (sigma_mean) {
+        for (int k = 0; k < 9; ++k) {
+            double acc = 0.0;
+            for (int64_t q = 0; q < h->last_samples; ++q) acc += smp[9 * q + k];
+            sigma_mean[k] = h->last_samples > 0 ? base[k] + acc / (double)h->last_samples / V : NAN;
+        }
+    }
+    if (n_samples) *n_samples = h->last_samples;
+    return check_flags(h);
+}
+
+dss_status dss_get_state(dss_handle *h, double *x, double *u, double *omega, double *F, double *T, int on_device)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    const int64_t N = h->N;
+    double *bufs[5] = {x, u, omega, F, T};
+    double *dev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k < 5; ++k) {
+        if (!bufs[k]) continue;
+        if (on_device)
+            dev[k] = bufs[k];
+        else
+            HIPTRY(dalloc(&dev[k], 3 * N));
+    }
+    const int grid = (int)((N + kBlock - 1) / kBlock);
+    const int c = h->cur;
+    hipLaunchKernelGGL(k_unsort, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c], h->frc,
+                       h->trq, h->vel_is_half ? 1 : 0, 1, dev[0], dev[1], dev[2], dev[3], dev[4]);
+    HIPTRY(hipGetLastError());
+    for (int k = 0; k < 5; ++k)
+        if (bufs[k] && !on_device)
+            HIPTRY(hipMemcpyAsync(bufs[k], dev[k], 3 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 5; ++k)
+        if (bufs[k] && !on_device) (void)hipFree(dev[k]);
+    return check_flags(h);
+}
+
+dss_status dss_get_eval_velocities(dss_handle *h, double *u, double *omega, int on_device)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    const int64_t N = h->N;
+    double *bufs[2] = {u, omega};
+    double *dev[2] = {nullptr, nullptr};
+    for (int k = 0; k < 2; ++k) {
+        if (!bufs[k]) continue;
+        if (on_device)
+            dev[k] = bufs[k];
+        else
+            HIPTRY(dalloc(&dev[k], 3 * N));
+    }
+    const int grid = (int)((N + kBlock - 1) / kBlock);
+    const int c = h->cur;
+    hipLaunchKernelGGL(k_unsort, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c], h->frc,
+                       h->trq, h->vel_is_half ? 1 : 0, 0, (double *)nullptr, dev[0], dev[1], (double *)nullptr,
+                       (double *)nullptr);
+    HIPTRY(hipGetLastError());
+    for (int k = 0; k < 2; ++k)
+        if (bufs[k] && !on_device)
+            HIPTRY(hipMemcpyAsync(bufs[k], dev[k], 3 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 2; ++k)
+        if (bufs[k] && !on_device) (void)hipFree(dev[k]);
+    return DSS_OK;
+}
+
+dss_status dss_get_pairs(dss_handle *h, int64_t cap, int32_t *pairs, int64_t *n)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (!h->P.record_pairs) return fail(h, DSS_ERR_STATE, "pairs are recorded only with DSS_FLAG_RECORD_PAIRS");
+    if (!n || cap < 0 || (cap > 0 && !pairs)) return fail(h, DSS_ERR_ARG, "null output");
+    unsigned long long cnt = 0;
+    HIPTRY(hipMemcpyAsync(&cnt, h->pair_count, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    *n = (int64_t)cnt;
+    if ((int64_t)cnt > h->P.pair_cap) return fail(h, DSS_ERR_CAPACITY, "internal pair buffer overflow");
+    if ((int64_t)cnt > cap) return fail(h, DSS_ERR_CAPACITY, "pair buffer too small");
+    if (cnt) HIPTRY(hipMemcpy(pairs, h->pairs, 2 * cnt * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return DSS_OK;
+}
+
+dss_status dss_get_cells(dss_handle *h, int32_t *dims, int64_t cap_cells, int32_t *cell_start, int32_t *perm)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (dims)
+        for (int d = 0; d < 3; ++d) dims[d] = h->P.nc[d];
+    if (cell_start) {
+        if (cap_cells < (int64_t)h->P.ncell + 1) return fail(h, DSS_ERR_CAPACITY, "cell_start buffer too small");
+        HIPTRY(hipMemcpy(cell_start, h->cell_start, (h->P.ncell + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
+    if (perm) {
+        std::vector<double4> w(h->N);
+        HIPTRY(hipMemcpy(w.data(), h->omg[h->cur], h->N * sizeof(double4), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < h->N; ++i) perm[i] = (int32_t)w[i].w;
+    }
+    return DSS_OK;
+}
+
+dss_status dss_get_history(dss_handle *h, int64_t cap, int32_t *pairs, double *xi, int64_t *n)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (!n) return fail(h, DSS_ERR_ARG, "null count");
+    int *dp = nullptr;
+    double *dxv = nullptr;
+    const int64_t room = std::max<int64_t>(cap, 1);
+    HIPTRY(dalloc(&dp, 2 * room));
+    HIPTRY(dalloc(&dxv, 3 * room));
+    HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
+    const int grid = (int)((h->N + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_history_export, dim3(grid), dim3(kBlock), 0, h->stream, (int)h->N, h->P.M, h->hown[h->hh],
+                       h->hkey[h->hh], h->hxi[h->hh], h->hcnt[h->hh], (long long)cap, dp, dxv, h->pair_count);
+    HIPTRY(hipGetLastError());
+    unsigned long long cnt = 0;
+    HIPTRY(hipMemcpyAsync(&cnt, h->pair_count, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    *n = (int64_t)cnt;
+    dss_status r = DSS_OK;
+    if ((int64_t)cnt > cap) {
+        r = fail(h, DSS_ERR_CAPACITY, "history buffer too small");
+    } else if (cnt) {
+        if (pairs) HIPTRY(hipMemcpy(pairs, dp, 2 * cnt * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (xi) HIPTRY(hipMemcpy(xi, dxv, 3 * cnt * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    (void)hipFree(dp);
+    (void)hipFree(dxv);
+    return r;
+}
+
+dss_status dss_get_info(dss_handle *h, dss_info *info)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (!info) return fail(h, DSS_ERR_ARG, "null info");
+    DevClock c;
+    HIPTRY(hipMemcpyAsync(&c, h->clk, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    info->n_particles = h->N;
+    info->step = c.step;
+    for (int d = 0; d < 3; ++d) info->cells[d] = h->P.nc[d];
+    info->capacity = h->P.M;
+    info->n_pairs = (int64_t)c.n_pairs;
+    info->n_contacts = (int64_t)c.n_contacts;
+    info->max_row_fill = c.max_fill;
+    info->error_flags = (int32_t)c.err;
+    double t = (double)c.step * h->prm.dt;
+    info->le_offset = std::fmod(h->prm.shear_rate * h->prm.L[1] * t, h->prm.L[0]);
+    return DSS_OK;
+}
+
+dss_status dss_save_state(dss_handle *h, void *blob, size_t *bytes)
+{
+    (void)blob;
+    if (bytes) *bytes = 0;
+    return fail(h, DSS_ERR_STATE, "not implemented");
+}
+
+dss_status dss_load_state(dss_handle *h, const void *blob, size_t bytes)
+{
+    (void)blob;
+    (void)bytes;
+    return fail(h, DSS_ERR_STATE, "not implemented");
+}
+
+}  // extern "C"

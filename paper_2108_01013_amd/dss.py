@@ -1,0 +1,270 @@
+"""Python binding of libdss (the HIP library behind include/dss.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+Arrays may be numpy arrays (host memory) or torch CUDA tensors (device memory, passed by
+pointer, on the current torch stream).  There is no CPU fallback: if libdss.so is missing
+or fails to load, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdss.so")
+
+DSS_FP64 = 0
+DSS_MIXED = 1
+DSS_FLAG_RECORD_PAIRS = 1
+
+STATUS = {0: "DSS_OK", 1: "DSS_ERR_ARG", 2: "DSS_ERR_HIP", 3: "DSS_ERR_CAPACITY", 4: "DSS_ERR_BOX",
+          5: "DSS_ERR_UNSTABLE", 6: "DSS_ERR_STATE"}
+
+EXPORTS = ["dss_create", "dss_set_particles", "dss_set_step", "dss_build_neighbours", "dss_compute_forces", "dss_step",
+           "dss_read_stress", "dss_get_state", "dss_get_eval_velocities", "dss_get_pairs", "dss_get_cells",
+           "dss_get_history", "dss_get_info", "dss_save_state", "dss_load_state", "dss_set_timing",
+           "dss_get_timing", "dss_last_error",
+           "dss_status_string", "dss_destroy"]
+
+
+class DssError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = ([("L", ctypes.c_double * 3)]
+                + [(n, ctypes.c_double) for n in ("shear_rate", "eta0", "rho", "kn", "kt", "gamma_n", "mu", "F_ER",
+                                                  "lambda_D", "a0", "hamaker", "eps_vdw", "eps_lub", "cutoff_factor",
+                                                  "dt")]
+                + [("precision", ctypes.c_int32), ("capacity", ctypes.c_int32), ("flags", ctypes.c_int32),
+                   ("reserved", ctypes.c_int32)])
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_particles", ctypes.c_int64), ("step", ctypes.c_int64), ("cells", ctypes.c_int32 * 3),
+                ("capacity", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("n_contacts", ctypes.c_int64),
+                ("max_row_fill", ctypes.c_int32), ("error_flags", ctypes.c_int32), ("le_offset", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libdss.so (built in-tree by paper_2108_01013_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libdss.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    H = ctypes.c_void_p
+    vp = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    st = ctypes.c_int
+    sig = {
+        "dss_create": (st, [ctypes.POINTER(Params), vp, ctypes.POINTER(H)]),
+        "dss_set_particles": (st, [H, i64, vp, vp, vp, vp, ctypes.c_int]),
+        "dss_set_step": (st, [H, i64]),
+        "dss_build_neighbours": (st, [H]),
+        "dss_compute_forces": (st, [H]),
+        "dss_step": (st, [H, i64, i64, ctypes.c_int]),
+        "dss_read_stress": (st, [H, vp, vp, ctypes.POINTER(i64)]),
+        "dss_get_state": (st, [H, vp, vp, vp, vp, vp, ctypes.c_int]),
+        "dss_get_eval_velocities": (st, [H, vp, vp, ctypes.c_int]),
+        "dss_get_pairs": (st, [H, i64, vp, ctypes.POINTER(i64)]),
+        "dss_get_cells": (st, [H, vp, i64, vp, vp]),
+        "dss_get_history": (st, [H, i64, vp, vp, ctypes.POINTER(i64)]),
+        "dss_get_info": (st, [H, ctypes.POINTER(Info)]),
+        "dss_save_state": (st, [H, vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "dss_load_state": (st, [H, vp, ctypes.c_size_t]),
+        "dss_set_timing": (st, [H, ctypes.c_int]),
+        "dss_get_timing": (st, [H, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+        "dss_last_error": (ctypes.c_char_p, [H]),
+        "dss_status_string": (ctypes.c_char_p, [st]),
+        "dss_destroy": (None, [H]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def make_params(p: dict, precision: int = DSS_FP64, capacity: int = 0, flags: int = 0) -> Params:
+    s = Params()
+    for d in range(3):
+        s.L[d] = float(p["L"][d])
+    for n, _ in Params._fields_[1:16]:
+        setattr(s, n, float(p[n]))
+    s.precision = int(precision)
+    s.capacity = int(capacity)
+    s.flags = int(flags)
+    s.reserved = 0
+    return s
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    """(pointer, keep-alive, on_device) for a numpy array or a torch tensor."""
+    if a is None:
+        return None, None, None
+    if _is_torch(a):
+        if not a.is_contiguous() or a.dtype.__repr__() != "torch.float64":
+            raise ValueError("torch tensors must be contiguous float64")
+        return ctypes.c_void_p(a.data_ptr()), a, bool(a.is_cuda)
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    return ctypes.c_void_p(arr.ctypes.data), arr, False
+
+
+class Simulation:
+    """One box of N spheres behind a dss_handle."""
+
+    def __init__(self, params: dict, precision: int = DSS_FP64, capacity: int = 0, record_pairs: bool = False,
+                 stream=None):
+        self.lib = load_library()
+        self.params = dict(params)
+        flags = DSS_FLAG_RECORD_PAIRS if record_pairs else 0
+        self._p = make_params(params, precision, capacity, flags)
+        self.h = ctypes.c_void_p()
+        # stream: a hipStream_t handle (e.g. torch.cuda.current_stream().cuda_stream), or None for a
+        # stream owned by the library handle
+        s = self.lib.dss_create(ctypes.byref(self._p), ctypes.c_void_p(stream) if stream else None,
+                                ctypes.byref(self.h))
+        if s != 0:
+            raise DssError(s, "dss_create failed")
+        self.N = 0
+
+    def _check(self, s):
+        if s != 0:
+            msg = self.lib.dss_last_error(self.h)
+            raise DssError(s, msg.decode() if msg else "")
+
+    def close(self):
+        if self.h:
+            self.lib.dss_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------------------------------
+    def set_particles(self, x, radius, u=None, omega=None):
+        px, kx, dev = _ptr(x)
+        pr, kr, dev_r = _ptr(radius)
+        pu, ku, dev_u = _ptr(u)
+        pw, kw, dev_w = _ptr(omega)
+        devs = {d for d in (dev, dev_r, dev_u, dev_w) if d is not None}
+        if len(devs) != 1:
+            raise ValueError("all arrays must live on the same side (host or device)")
+        N = (kr.numel() if _is_torch(kr) else kr.size)
+        self._check(self.lib.dss_set_particles(self.h, int(N), px, pr, pu, pw, int(dev)))
+        self.N = int(N)
+
+    def set_step(self, n):
+        self._check(self.lib.dss_set_step(self.h, int(n)))
+
+    def build_neighbours(self):
+        self._check(self.lib.dss_build_neighbours(self.h))
+
+    def compute_forces(self):
+        self._check(self.lib.dss_compute_forces(self.h))
+
+    def step(self, n=1, stress_every=0, sync=True):
+        self._check(self.lib.dss_step(self.h, int(n), int(stress_every), int(bool(sync))))
+
+    def read_stress(self):
+        last = np.zeros(9)
+        mean = np.zeros(9)
+        ns = ctypes.c_int64(0)
+        self._check(self.lib.dss_read_stress(self.h, last.ctypes.data_as(ctypes.c_void_p),
+                                             mean.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ns)))
+        return last.reshape(3, 3), mean.reshape(3, 3), int(ns.value)
+
+    def state(self):
+        out = {k: np.zeros((self.N, 3)) for k in ("x", "u", "w", "F", "T")}
+        self._check(self.lib.dss_get_state(self.h, *[ctypes.c_void_p(out[k].ctypes.data) for k in
+                                                     ("x", "u", "w", "F", "T")], 0))
+        return out
+
+    def state_into(self, x=None, u=None, w=None, F=None, T=None):
+        """Write the state into caller tensors/arrays (all on the same side)."""
+        ptrs = [_ptr(a) for a in (x, u, w, F, T)]
+        devs = {p[2] for p in ptrs if p[2] is not None}
+        if len(devs) > 1:
+            raise ValueError("mixed host/device outputs")
+        self._check(self.lib.dss_get_state(self.h, *[p[0] for p in ptrs], int(devs.pop() if devs else 0)))
+
+    def eval_velocities(self):
+        u = np.zeros((self.N, 3))
+        w = np.zeros((self.N, 3))
+        self._check(self.lib.dss_get_eval_velocities(self.h, ctypes.c_void_p(u.ctypes.data),
+                                                     ctypes.c_void_p(w.ctypes.data), 0))
+        return u, w
+
+    def pairs(self):
+        n = ctypes.c_int64(0)
+        cap = 32 * self.N + 64
+        buf = np.zeros((cap, 2), np.int32)
+        self._check(self.lib.dss_get_pairs(self.h, cap, ctypes.c_void_p(buf.ctypes.data), ctypes.byref(n)))
+        p = buf[: n.value]
+        return p[np.lexsort((p[:, 1], p[:, 0]))]
+
+    def cells(self):
+        dims = np.zeros(3, np.int32)
+        self._check(self.lib.dss_get_cells(self.h, ctypes.c_void_p(dims.ctypes.data), 0, None, None))
+        ncell = int(np.prod(dims))
+        cs = np.zeros(ncell + 1, np.int32)
+        perm = np.zeros(self.N, np.int32)
+        self._check(self.lib.dss_get_cells(self.h, ctypes.c_void_p(dims.ctypes.data), ncell + 1,
+                                           ctypes.c_void_p(cs.ctypes.data), ctypes.c_void_p(perm.ctypes.data)))
+        return dims, cs, perm
+
+    def history(self):
+        n = ctypes.c_int64(0)
+        cap = max(64, 8 * self.N)
+        while True:
+            pr = np.zeros((cap, 2), np.int32)
+            xi = np.zeros((cap, 3))
+            s = self.lib.dss_get_history(self.h, cap, ctypes.c_void_p(pr.ctypes.data),
+                                         ctypes.c_void_p(xi.ctypes.data), ctypes.byref(n))
+            if s == 3 and n.value > cap:
+                cap = int(n.value)
+                continue
+            self._check(s)
+            break
+        pr, xi = pr[: n.value], xi[: n.value]
+        order = np.lexsort((pr[:, 1], pr[:, 0]))
+        return pr[order], xi[order]
+
+    KERNELS = ("k_predict", "k_scan", "k_scatter", "k_pairs", "k_sample")
+
+    def set_timing(self, enable=True):
+        self._check(self.lib.dss_set_timing(self.h, int(bool(enable))))
+
+    def timing(self):
+        """{kernel name: (total ms, launches)} since set_timing(True)."""
+        out = {}
+        for k, name in enumerate(self.KERNELS):
+            ms = ctypes.c_double(0.0)
+            n = ctypes.c_int64(0)
+            self._check(self.lib.dss_get_timing(self.h, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
+    def info(self):
+        inf = Info()
+        self._check(self.lib.dss_get_info(self.h, ctypes.byref(inf)))
+        return {"n_particles": inf.n_particles, "step": inf.step, "cells": tuple(inf.cells),
+                "capacity": inf.capacity, "n_pairs": inf.n_pairs, "n_contacts": inf.n_contacts,
+                "max_row_fill": inf.max_row_fill, "error_flags": inf.error_flags, "le_offset": inf.le_offset}
