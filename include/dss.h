@@ -162,10 +162,11 @@ dss_status dss_get_info(dss_handle *h, dss_info *info);
 dss_status dss_save_state(dss_handle *h, void *blob, size_t *bytes);
 dss_status dss_load_state(dss_handle *h, const void *blob, size_t bytes);
 
-/* Kernel timing with HIP events recorded on the handle's stream around every kernel
- * launch of the time step (enable != 0 starts a new accumulation).  dss_get_timing
- * synchronises and returns, for kernel k (0 predict, 1 scan, 2 scatter, 3 pairs,
- * 4 sample), the summed duration in ms and the number of launches since enabling. */
+/* Kernel timing with HIP events recorded on the handle's stream around the launches of
+ * the kernels selected by enable (bit k: kernel k; -1: all; 0: off); every call starts a
+ * new accumulation.  dss_get_timing synchronises and returns, for kernel k (0 predict or
+ * velocity completion, 1 scan, 2 scatter, 3 pairs, 4 finish), the summed duration in ms
+ * and the number of timed launches. */
 dss_status dss_set_timing(dss_handle *h, int enable);
 dss_status dss_get_timing(dss_handle *h, int kernel, double *total_ms, int64_t *launches);
 

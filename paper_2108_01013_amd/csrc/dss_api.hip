@@ -4,8 +4,8 @@
 //   k_predict  (sorted order of the previous step)  kick/drift, Lees-Edwards wrap, cell id, rank
 //   k_scan     exclusive scan of the cell counts -> cell_start, clock advance
 //   k_scatter  reorder into the new sorted order, id -> slot map, clear force accumulators
-//   k_pairs    half-shell search, pair physics, new history rows, stress
-//   k_sample   store the stress sample when the schedule asks for it
+//   k_pairs    half-shell search, pair physics, new history rows, per-workgroup stress partials
+//   k_finish   stress and counters from the partials, stress sample
 // The history rows written by k_pairs become the committed history of the step.
 #include <hip/hip_runtime.h>
 
@@ -34,14 +34,13 @@ struct dss_handle {
     bool vel_is_half = false;  // vel holds the half-step velocity of the last forces
     int cur = 0;               // particle buffers holding the current state
     int hh = 0;                // history buffers holding the committed history
-    int ih = 0;                // inverse-map buffer matching the committed history
     int64_t step = 0;          // host mirror of the time index
     double sum_a3 = 0.0;
 
     double4 *pa[2] = {nullptr, nullptr}, *vel[2] = {nullptr, nullptr}, *omg[2] = {nullptr, nullptr};
-    double4 *frc = nullptr, *trq = nullptr;
+    double *ft_own = nullptr, *ft_nb = nullptr, *ft_x = nullptr;  // force records (ForceBufs)
     int *cell = nullptr, *rank = nullptr, *count = nullptr, *cell_start = nullptr;
-    int *inv[2] = {nullptr, nullptr};
+    int *prev = nullptr;       // slot -> slot at the previous sort
     int *hkey[2] = {nullptr, nullptr}, *hcnt[2] = {nullptr, nullptr}, *hown[2] = {nullptr, nullptr};
     double *hxi[2] = {nullptr, nullptr};
     int *pairs = nullptr;
@@ -49,14 +48,28 @@ struct dss_handle {
     DevClock *clk = nullptr;
     DevRun *run = nullptr;
     double *sigma_last = nullptr;
+    double *partials = nullptr;  // 12 doubles per k_pairs workgroup
     double *samples = nullptr;
     int64_t sample_cap_alloc = 0;
     int64_t last_samples = 0;
+    int scan_c4 = 1;           // int4 chunks per lane of the cell-count scan
+    size_t tile_lds = 0;       // dynamic LDS bytes of a k_pairs workgroup
+    int finish_r = 1;          // partial records per lane of k_finish
+
+    ForceBufs fb() const
+    {
+        ForceBufs b;
+        b.own = ft_own;
+        b.nb = ft_nb;
+        b.x = ft_x;
+        b.n = N;
+        return b;
+    }
     DevRun run_host{};
 
     // kernel timing with events on the stream
     static constexpr int kKernels = 5;
-    bool timing = false;
+    unsigned timing = 0;       // bit k: time kernel k
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<int, int>>> ev_marks;  // (kernel, (start event, stop event))
     double kernel_ms[kKernels] = {0, 0, 0, 0, 0};
@@ -93,20 +106,22 @@ void free_all(dss_handle *h)
         if (p) (void)hipFree(p);
     };
     for (int k = 0; k < 2; ++k) {
-        F(h->pa[k]); F(h->vel[k]); F(h->omg[k]); F(h->inv[k]);
+        F(h->pa[k]); F(h->vel[k]); F(h->omg[k]);
         F(h->hkey[k]); F(h->hcnt[k]); F(h->hown[k]); F(h->hxi[k]);
         h->pa[k] = h->vel[k] = h->omg[k] = nullptr;
-        h->inv[k] = h->hkey[k] = h->hcnt[k] = h->hown[k] = nullptr;
+        h->hkey[k] = h->hcnt[k] = h->hown[k] = nullptr;
         h->hxi[k] = nullptr;
     }
-    F(h->frc); F(h->trq); F(h->cell); F(h->rank); F(h->count); F(h->cell_start);
-    F(h->pairs); F(h->pair_count); F(h->clk); F(h->run); F(h->sigma_last); F(h->samples);
-    h->frc = h->trq = nullptr;
+    F(h->ft_own); F(h->ft_nb); F(h->ft_x); F(h->prev);
+    F(h->cell); F(h->rank); F(h->count); F(h->cell_start);
+    F(h->pairs); F(h->pair_count); F(h->clk); F(h->run); F(h->sigma_last); F(h->samples); F(h->partials);
+    h->ft_own = h->ft_nb = h->ft_x = nullptr;
+    h->prev = nullptr;
     h->cell = h->rank = h->count = h->cell_start = h->pairs = nullptr;
     h->pair_count = nullptr;
     h->clk = nullptr;
     h->run = nullptr;
-    h->sigma_last = h->samples = nullptr;
+    h->sigma_last = h->samples = h->partials = nullptr;
     h->sample_cap_alloc = 0;
     h->loaded = false;
 }
@@ -139,7 +154,7 @@ struct TimedLaunch {
     int e0 = -1, e1 = -1;
     TimedLaunch(dss_handle *h_, int k) : h(h_), kernel(k)
     {
-        if (!h->timing) return;
+        if (!(h->timing & (1u << k))) return;
         e0 = take();
         if (e0 >= 0) (void)hipEventRecord(h->ev_pool[e0], h->stream);
     }
@@ -184,54 +199,91 @@ dss_status require_loaded(dss_handle *h)
     return DSS_OK;
 }
 
-// One force evaluation on the current state.  advance = 1: a full time step (drift +
-// kick first, history committed); advance = 0: evaluation at the current state.
-dss_status evaluate(dss_handle *h, int advance)
+// One force evaluation.
+//   EVAL_STEP:    a full time step: drift + kick, counting sort, pairs; history committed.
+//   EVAL_SORT:    counting sort of the current positions, then pairs (initial evaluation).
+//   EVAL_INPLACE: pairs at the current state and order (velocities completed to u^n).
+enum EvalMode { EVAL_STEP = 0, EVAL_SORT = 1, EVAL_INPLACE = 2 };
+
+dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample)
 {
-    const int N = (int)h->N;
-    const int grid = (N + kBlock - 1) / kBlock;
-    const int c = h->cur, o = 1 - h->cur;
-    {
-        TimedLaunch t(h, 0);
-        hipLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c],
-                       h->frc, h->trq, h->vel_is_half ? 1 : 0, advance, h->clk, h->cell, h->rank, h->count);
-    }
-    {
-        TimedLaunch t(h, 1);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, h->stream, h->P.ncell, h->count, h->cell_start, h->clk,
-                       advance, h->run);
-    }
-    {
-        TimedLaunch t(h, 2);
-        hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, h->stream, N, h->cell, h->rank, h->cell_start,
-                       h->pa[c], h->vel[c], h->omg[c], h->pa[o], h->vel[o], h->omg[o], h->frc, h->trq,
-                       h->inv[1 - h->ih]);
-    }
-    if (h->P.record_pairs) HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
     HistView H;
     H.key_old = h->hkey[h->hh];
     H.xi_old = h->hxi[h->hh];
     H.cnt_old = h->hcnt[h->hh];
-    H.inv_old = h->inv[h->ih];
+    H.prev = prev;
     H.key_new = h->hkey[1 - h->hh];
     H.xi_new = h->hxi[1 - h->hh];
     H.cnt_new = h->hcnt[1 - h->hh];
     H.own_new = h->hown[1 - h->hh];
+    if (h->P.record_pairs) HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
     {
         TimedLaunch t(h, 3);
-        hipLaunchKernelGGL(k_pairs, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->cell_start, h->pa[o], h->vel[o],
-                       h->omg[o], h->frc, h->trq, H, h->clk, h->run, h->pairs, h->pair_count);
+        hipLaunchKernelGGL(k_pairs, dim3(h->P.nc[1] * h->P.nc[2]), dim3(kBlock), h->tile_lds, h->stream, h->P,
+                           h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(), H, h->clk, h->partials,
+                           h->pairs, h->pair_count);
     }
-    if (advance) {
-        TimedLaunch t(h, 4);
-        hipLaunchKernelGGL(k_sample, dim3(1), dim3(64), 0, h->stream, h->clk, h->run);
+    TimedLaunch t(h, 4);
+    switch (h->finish_r) {
+    case 1: hipLaunchKernelGGL(k_finish<1>, dim3(1), dim3(1024), 0, h->stream, h->partials, h->clk, h->run, sample); break;
+    case 2: hipLaunchKernelGGL(k_finish<2>, dim3(1), dim3(1024), 0, h->stream, h->partials, h->clk, h->run, sample); break;
+    case 3: hipLaunchKernelGGL(k_finish<3>, dim3(1), dim3(1024), 0, h->stream, h->partials, h->clk, h->run, sample); break;
+    case 4: hipLaunchKernelGGL(k_finish<4>, dim3(1), dim3(1024), 0, h->stream, h->partials, h->clk, h->run, sample); break;
+    default: return fail(h, DSS_ERR_BOX, "too many cell rows");
     }
+    return DSS_OK;
+}
+
+dss_status evaluate(dss_handle *h, EvalMode mode)
+{
+    const int N = (int)h->N;
+    const int grid = (N + kBlock - 1) / kBlock;
+    const int c = h->cur, o = 1 - h->cur;
+    const int advance = mode == EVAL_STEP ? 1 : 0;
+    if (mode == EVAL_INPLACE) {
+        if (h->vel_is_half) {
+            TimedLaunch t(h, 0);
+            hipLaunchKernelGGL(k_complete, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c],
+                               h->omg[c], h->fb());
+        }
+        HIPTRY(hipMemsetAsync(h->ft_x, 0, 6 * h->N * sizeof(double), h->stream));
+        dss_status s = launch_pairs(h, c, nullptr, 0);
+        if (s) return s;
+        HIPTRY(hipGetLastError());
+        h->vel_is_half = false;
+        return DSS_OK;
+    }
+    {
+        TimedLaunch t(h, 0);
+        hipLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c],
+                           h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk, h->cell, h->rank, h->count);
+    }
+    {
+        TimedLaunch t(h, 1);
+#define DSS_SCAN(C4)                                                                                            \
+    case C4:                                                                                                    \
+        hipLaunchKernelGGL(k_scan<C4>, dim3(1), dim3(1024), 0, h->stream, h->count, h->cell_start, h->clk, advance); \
+        break;
+        switch (h->scan_c4) {
+            DSS_SCAN(1) DSS_SCAN(2) DSS_SCAN(3) DSS_SCAN(4) DSS_SCAN(5) DSS_SCAN(6) DSS_SCAN(7) DSS_SCAN(8)
+            DSS_SCAN(9) DSS_SCAN(10) DSS_SCAN(11) DSS_SCAN(12) DSS_SCAN(13) DSS_SCAN(14) DSS_SCAN(15) DSS_SCAN(16)
+        default:
+            return fail(h, DSS_ERR_BOX, "cell lattice too large for the scan");
+        }
+#undef DSS_SCAN
+    }
+    {
+        TimedLaunch t(h, 2);
+        hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, h->stream, N, h->cell, h->rank, h->cell_start,
+                           h->pa[c], h->vel[c], h->omg[c], h->pa[o], h->vel[o], h->omg[o], h->ft_x, h->prev);
+    }
+    dss_status s = launch_pairs(h, o, h->prev, advance);
+    if (s) return s;
     HIPTRY(hipGetLastError());
     h->cur = o;
     h->vel_is_half = advance != 0;
     if (advance) {
         h->hh = 1 - h->hh;
-        h->ih = 1 - h->ih;
         h->step += 1;
     }
     return DSS_OK;
@@ -255,7 +307,7 @@ dss_status dss_set_timing(dss_handle *h, int enable)
     if (!h) return DSS_ERR_ARG;
     dss_status s = collect_timing(h);
     if (s) return s;
-    h->timing = enable != 0;
+    h->timing = enable < 0 ? 0xffffffffu : (unsigned)enable;
     for (int k = 0; k < dss_handle::kKernels; ++k) {
         h->kernel_ms[k] = 0.0;
         h->kernel_launches[k] = 0;
@@ -342,6 +394,10 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
     P.gd = p.shear_rate; P.eta0 = p.eta0; P.rho = p.rho; P.kn = p.kn; P.kt = p.kt; P.gn = p.gamma_n;
     P.mu = p.mu; P.fer = p.F_ER; P.lamd = p.lambda_D; P.a0 = p.a0; P.ham = p.hamaker; P.eps_vdw = p.eps_vdw;
     P.eps_lub = p.eps_lub; P.cf = p.cutoff_factor; P.dt = p.dt;
+    P.k6 = 6.0 * kPi * p.eta0;
+    P.k8 = 8.0 * kPi * p.eta0;
+    P.inv_lamd = p.lambda_D > 0.0 ? 1.0 / p.lambda_D : 0.0;
+    P.fer_a0 = p.F_ER / p.a0;
     const double rc = p.cutoff_factor * 2.0 * a_max * (1.0 + 1e-9);
     for (int d = 0; d < 3; ++d) {
         P.nc[d] = std::max(1, (int)std::floor(p.L[d] / rc));
@@ -351,15 +407,40 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
         return fail(h, DSS_ERR_BOX, "cell lattice " + std::to_string(P.nc[0]) + "x" + std::to_string(P.nc[1]) + "x" +
                                         std::to_string(P.nc[2]) + " is smaller than 4x3x3");
     const int64_t ncell = (int64_t)P.nc[0] * P.nc[1] * P.nc[2];
-    if (ncell > (int64_t)0x3fffffff) return fail(h, DSS_ERR_BOX, "too many cells");
+    // the single-workgroup scan holds 16 int4 chunks per lane: up to 65535 cells
+    if (ncell + 1 > 4096 * 16) return fail(h, DSS_ERR_BOX, "more than 65535 cells in one box");
+    const int scan_c4 = (int)((ncell + 1 + 4095) / 4096);
+    const int64_t ncell_pad = 4096 * (int64_t)scan_c4;
     P.ncell = (int)ncell;
     P.N = (int)N;
     P.M = p.capacity > 0 ? p.capacity : paper_capacity(a_max, a_min);
     P.record_pairs = (p.flags & DSS_FLAG_RECORD_PAIRS) ? 1 : 0;
+    // row-tile capacities of k_pairs from the mean occupancy of a cell row (own row and the
+    // five rows of the half shell); rows beyond them take the per-particle path
+    {
+        const double mean_row = (double)N / ((double)P.nc[1] * P.nc[2]);
+        auto up = [](double v, int m) { return ((int)std::ceil(v) + m - 1) / m * m; };
+        int own_cap = up(1.5 * mean_row + 16.0, 32);
+        int stage_cap = up(6.25 * mean_row + 32.0, 64);
+        int qcap = up(8.0 * mean_row + 64.0, 64);
+        const size_t lds_max = 150 * 1024;
+        while (tile_lds_bytes(own_cap, stage_cap, qcap) > lds_max && own_cap > 32) {
+            own_cap = std::max(32, own_cap * 3 / 4 / 32 * 32);
+            stage_cap = std::max(64, stage_cap * 3 / 4 / 64 * 64);
+            qcap = std::max(64, qcap * 3 / 4 / 64 * 64);
+        }
+        own_cap = std::min(own_cap, 4096);
+        stage_cap = std::min(stage_cap, 65535 / 64 * 64);
+        P.own_cap = own_cap;
+        P.stage_cap = stage_cap;
+        P.qcap = qcap;
+    }
     P.pair_cap = P.record_pairs ? 32 * N + 64 : 0;
 
     free_all(h);
     h->P = P;
+    h->tile_lds = tile_lds_bytes(P.own_cap, P.stage_cap, P.qcap);
+    HIPTRY(hipFuncSetAttribute((const void *)k_pairs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->tile_lds));
     h->N = N;
     h->sum_a3 = sa3;
     const size_t rows = (size_t)N * (size_t)P.M;
@@ -367,24 +448,34 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
         HIPTRY(dalloc(&h->pa[k], N));
         HIPTRY(dalloc(&h->vel[k], N));
         HIPTRY(dalloc(&h->omg[k], N));
-        HIPTRY(dalloc(&h->inv[k], N));
         HIPTRY(dalloc(&h->hkey[k], rows));
         HIPTRY(dalloc(&h->hxi[k], rows * 3));
         HIPTRY(dalloc(&h->hcnt[k], N));
         HIPTRY(dalloc(&h->hown[k], N));
     }
-    HIPTRY(dalloc(&h->frc, N));
-    HIPTRY(dalloc(&h->trq, N));
+    HIPTRY(dalloc(&h->ft_own, 6 * N));
+    HIPTRY(dalloc(&h->ft_nb, 24 * N));
+    HIPTRY(dalloc(&h->ft_x, 6 * N));
+    HIPTRY(dalloc(&h->prev, N));
     HIPTRY(dalloc(&h->cell, N));
     HIPTRY(dalloc(&h->rank, N));
-    HIPTRY(dalloc(&h->count, ncell));
-    HIPTRY(dalloc(&h->cell_start, ncell + 1));
+    HIPTRY(dalloc(&h->count, ncell_pad));
+    HIPTRY(dalloc(&h->cell_start, ncell_pad));
+    h->scan_c4 = scan_c4;
     HIPTRY(dalloc(&h->pairs, P.record_pairs ? 2 * P.pair_cap : 2));
     HIPTRY(dalloc(&h->pair_count, 1));
     HIPTRY(dalloc(&h->clk, 1));
     HIPTRY(dalloc(&h->run, 1));
     HIPTRY(dalloc(&h->sigma_last, 9));
-    HIPTRY(hipMemsetAsync(h->count, 0, ncell * sizeof(int), h->stream));
+    {
+        const int rows = P.nc[1] * P.nc[2];
+        h->finish_r = (rows + 1023) / 1024;
+        if (h->finish_r > 4) return fail(h, DSS_ERR_BOX, "more than 4096 cell rows in one box");
+        h->P.pstride = 1024 * h->finish_r;
+        HIPTRY(dalloc(&h->partials, 12 * (size_t)1024 * h->finish_r));
+        HIPTRY(hipMemsetAsync(h->partials, 0, 12 * (size_t)1024 * h->finish_r * sizeof(double), h->stream));
+    }
+    HIPTRY(hipMemsetAsync(h->count, 0, ncell_pad * sizeof(int), h->stream));
     HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
     HIPTRY(hipMemsetAsync(h->clk, 0, sizeof(DevClock), h->stream));
     HIPTRY(hipMemsetAsync(h->sigma_last, 0, 9 * sizeof(double), h->stream));
@@ -414,15 +505,14 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
     }
     h->cur = 0;
     h->hh = 0;
-    h->ih = 0;
     h->step = 0;
     h->vel_is_half = false;
     const int grid = (int)((N + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_load, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, dx, dr, du, dw, P.gd, h->pa[0],
-                       h->vel[0], h->omg[0], h->frc, h->trq, h->inv[0]);
+                       h->vel[0], h->omg[0], h->fb());
     HIPTRY(hipGetLastError());
     h->loaded = true;
-    dss_status s = evaluate(h, 0);
+    dss_status s = evaluate(h, EVAL_SORT);
     HIPTRY(hipStreamSynchronize(h->stream));
     (void)hipFree(dx);
     (void)hipFree(dr);
@@ -459,7 +549,7 @@ dss_status dss_compute_forces(dss_handle *h)
 {
     dss_status s = require_loaded(h);
     if (s) return s;
-    s = evaluate(h, 0);
+    s = evaluate(h, EVAL_INPLACE);
     if (s) return s;
     return check_flags(h);
 }
@@ -490,7 +580,7 @@ dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sy
     HIPTRY(hipMemcpyAsync(h->run, &h->run_host, sizeof(DevRun), hipMemcpyHostToDevice, h->stream));
     h->last_samples = cap;
     for (int64_t k = 0; k < n_steps; ++k) {
-        s = evaluate(h, 1);
+        s = evaluate(h, EVAL_STEP);
         if (s) return s;
     }
     if (sync) return check_flags(h);
@@ -545,8 +635,8 @@ dss_status dss_get_state(dss_handle *h, double *x, double *u, double *omega, dou
     }
     const int grid = (int)((N + kBlock - 1) / kBlock);
     const int c = h->cur;
-    hipLaunchKernelGGL(k_unsort, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c], h->frc,
-                       h->trq, h->vel_is_half ? 1 : 0, 1, dev[0], dev[1], dev[2], dev[3], dev[4]);
+    hipLaunchKernelGGL(k_unsort, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c],
+                       h->fb(), h->vel_is_half ? 1 : 0, 1, dev[0], dev[1], dev[2], dev[3], dev[4]);
     HIPTRY(hipGetLastError());
     for (int k = 0; k < 5; ++k)
         if (bufs[k] && !on_device)
@@ -573,8 +663,8 @@ dss_status dss_get_eval_velocities(dss_handle *h, double *u, double *omega, int 
     }
     const int grid = (int)((N + kBlock - 1) / kBlock);
     const int c = h->cur;
-    hipLaunchKernelGGL(k_unsort, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c], h->frc,
-                       h->trq, h->vel_is_half ? 1 : 0, 0, (double *)nullptr, dev[0], dev[1], (double *)nullptr,
+    hipLaunchKernelGGL(k_unsort, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c],
+                       h->fb(), h->vel_is_half ? 1 : 0, 0, (double *)nullptr, dev[0], dev[1], (double *)nullptr,
                        (double *)nullptr);
     HIPTRY(hipGetLastError());
     for (int k = 0; k < 2; ++k)

@@ -4,13 +4,13 @@
 //   pa  double4 [N]  (x, y, z, radius)
 //   vel double4 [N]  (u_x, u_y, u_z, 0): the velocity the last forces were evaluated with
 //   omg double4 [N]  (w_x, w_y, w_z, id): angular velocity and the particle id (as a double)
-//   frc double4 [N]  (F_x, F_y, F_z, 0), trq double4 [N]: totals of the last evaluation
+//   force records: 6 doubles (F, T) per particle in six buffers (see ForceBufs)
 // One 32-byte record per particle and quantity, so a neighbour gather is one 32-byte
 // access per array; streaming kernels read them as two 16-byte loads per lane.
 //
 // Step kernels: k_predict (kick/drift, Lees-Edwards wrap, cell id, histogram rank),
-// k_scan (exclusive scan of the cell counts), k_scatter (reorder), k_pairs (half-shell
-// search + pair physics + history rows + stress).
+// k_scan (exclusive scan of the counts), k_scatter (reorder), k_pairs (half-shell
+// search + pair physics + history rows + stress), k_finish (stress and counters).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,12 +30,17 @@ struct DevParams {
     double L[3];
     double gd, eta0, rho, kn, kt, gn, mu, fer, lamd, a0, ham, eps_vdw, eps_lub, cf, dt;
     double cw[3];      // cell widths L/n
+    double k6, k8;     // 6 pi eta0, 8 pi eta0
+    double inv_lamd;   // 1 / lambda_D (0 if lambda_D <= 0)
+    double fer_a0;     // F_ER / a0
     int nc[3];         // cells per dimension
     int ncell;
     int N;
     int M;             // history row capacity
     int record_pairs;
     long long pair_cap;
+    int own_cap, stage_cap, qcap;   // row-tile capacities of k_pairs
+    int pstride;                    // stride of the partial records (1024 R)
 };
 
 // Device-side clock and per-evaluation counters.  step = time index of the state.
@@ -75,8 +80,11 @@ __device__ __forceinline__ int cell_coord(double xd, double cw, int n)
     return c;
 }
 
-// Nearest image of b seen from a under Lees-Edwards shear; r = x_b - x_a.  Evaluated
-// without contraction so that the listed-pair test is the IEEE expression as written.
+// Nearest image of b seen from a under Lees-Edwards shear; r = x_b - x_a.  Rows above /
+// below are displaced by +delta / -delta along x.  Periodic wraps by comparison: for every
+// pair closer than L/2 along x and z this equals r - L round(r / L) bit for bit (the
+// subtractions of L and 2 L are exact by Sterbenz's lemma), so the listed-pair test is the
+// IEEE expression as written.  Evaluated without contraction.
 __device__ __forceinline__ void min_image(const DevParams &P, double delta, double xa, double ya, double za,
                                           double xb, double yb, double zb, double &dx, double &dy, double &dz)
 {
@@ -91,8 +99,18 @@ __device__ __forceinline__ void min_image(const DevParams &P, double delta, doub
         dy += P.L[1];
         dx += delta;
     }
-    dx -= P.L[0] * rint(dx / P.L[0]);
-    dz -= P.L[2] * rint(dz / P.L[2]);
+    const double hx = 0.5 * P.L[0];
+    if (dx > hx) {
+        dx -= P.L[0];
+        if (dx > hx) dx -= P.L[0];
+    } else if (dx < -hx) {
+        dx += P.L[0];
+        if (dx < -hx) dx += P.L[0];
+    }
+    if (dz > 0.5 * P.L[2])
+        dz -= P.L[2];
+    else if (dz < -0.5 * P.L[2])
+        dz += P.L[2];
 }
 
 __device__ __forceinline__ bool listed(const DevParams &P, double dx, double dy, double dz, double aa, double ab,
@@ -108,6 +126,17 @@ __device__ __forceinline__ double pmass(const DevParams &P, double a)
 {
 #pragma clang fp contract(off)
     return P.rho * (4.0 / 3.0) * kPi * a * a * a;
+}
+
+// 1/x from the hardware reciprocal refined by two Newton steps (relative error ~1e-16);
+// used in the pair physics only, never in the listed-pair test.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
 }
 
 __device__ __forceinline__ double warp_sum(double v)
@@ -132,20 +161,131 @@ __device__ __forceinline__ int warp_max(int v)
 }
 
 // ----------------------------------------------------------------------------------
+// Force records.  The totals of one evaluation are the sum of six 48-byte records per
+// particle (sorted order): the workgroup that owns the particle's cell row writes its own
+// part (own row pairs + Stokes terms), and for each of the four other rows of the half
+// shell exactly one workgroup writes the partner-side part it accumulated (nb[0..3]);
+// ft_x receives atomic additions only from rows evaluated by the per-particle path.
+// All plain stores: no atomics on the hot path, every record written every evaluation.
+// ----------------------------------------------------------------------------------
+struct ForceBufs {
+    double *own;     // N x 6
+    double *nb;      // 4 x N x 6
+    double *x;       // N x 6, atomic accumulation, cleared by k_scatter
+    long long n;     // N (stride of nb)
+};
+
+__device__ __forceinline__ void load_ft(const double *__restrict__ rec, double f[6])
+{
+    const double2 *q = reinterpret_cast<const double2 *>(rec);
+    double2 a = q[0], b = q[1], c = q[2];
+    f[0] = a.x; f[1] = a.y; f[2] = b.x; f[3] = b.y; f[4] = c.x; f[5] = c.y;
+}
+
+__device__ __forceinline__ void store_ft(double *__restrict__ rec, const double f[6])
+{
+    double2 *q = reinterpret_cast<double2 *>(rec);
+    q[0] = make_double2(f[0], f[1]);
+    q[1] = make_double2(f[2], f[3]);
+    q[2] = make_double2(f[4], f[5]);
+}
+
+// Total force (f[0..2]) and torque (f[3..5]) of slot p, summed in a fixed order.
+__device__ __forceinline__ void total_ft(const ForceBufs &B, int p, double f[6])
+{
+    double a[6];
+    load_ft(B.own + 6LL * p, f);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        load_ft(B.nb + 6LL * (r * B.n + p), a);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) f[k] += a[k];
+    }
+    load_ft(B.x + 6LL * p, a);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) f[k] += a[k];
+}
+
+// ----------------------------------------------------------------------------------
+// k_scan: exclusive scan of the cell counts by one workgroup of 1024 lanes, cell_start =
+// exscan(count), count reset to 0, clock advanced.  The counts are read as C4 tiles of
+// 1024 int4 chunks (lane t holds chunk k 1024 + t of every tile k: each load instruction
+// of a wavefront covers one contiguous KB).  Prefix of a chunk = totals of the earlier
+// tiles + the lanes before it in its tile (wavefront shuffles, then the 16 wavefront
+// totals through LDS).  count and cell_start are padded to 4096 C4 entries (padding
+// counts stay 0), so the entry at index n_cells receives the total.
+// ----------------------------------------------------------------------------------
+template <int C4>
+__global__ void __launch_bounds__(1024) k_scan(int *__restrict__ count, int *__restrict__ cell_start,
+                                               DevClock *__restrict__ clk, int advance)
+{
+    __shared__ int wsum[C4][16];
+    __shared__ int wpre[C4][16];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wid = t >> 6;
+    int4 *cnt4 = reinterpret_cast<int4 *>(count);
+    int4 *out4 = reinterpret_cast<int4 *>(cell_start);
+    int4 v[C4];
+#pragma unroll
+    for (int k = 0; k < C4; ++k) v[k] = cnt4[k * 1024 + t];
+    int s[C4], incl[C4];
+#pragma unroll
+    for (int k = 0; k < C4; ++k) {
+        s[k] = v[k].x + v[k].y + v[k].z + v[k].w;
+        incl[k] = s[k];
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int k = 0; k < C4; ++k) {
+            const int u = __shfl_up(incl[k], o, 64);
+            if (lane >= o) incl[k] += u;
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < C4; ++k) wsum[k][wid] = incl[k];
+    }
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int k = 0; k < C4; ++k)
+            for (int w = 0; w < 16; ++w) {
+                wpre[k][w] = run;
+                run += wsum[k][w];
+            }
+    }
+    __syncthreads();
+    const int4 zero = make_int4(0, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < C4; ++k) {
+        int4 o;
+        o.x = wpre[k][wid] + incl[k] - s[k];
+        o.y = o.x + v[k].x;
+        o.z = o.y + v[k].y;
+        o.w = o.z + v[k].z;
+        out4[k * 1024 + t] = o;
+        cnt4[k * 1024 + t] = zero;
+    }
+    if (t == 0 && advance) clk->step += 1;
+}
+
+// ----------------------------------------------------------------------------------
 // k_predict: velocity-Verlet drift + half kick (advance = 1) or velocity completion
 // only (advance = 0), Lees-Edwards wrap at t_{n+1}, cell id and histogram rank.
-//   vel_is_half = 1: vel holds the half-step velocity u^{n-1/2} of the forces frc, and
+//   vel_is_half = 1: vel holds the half-step velocity u^{n-1/2} of the forces, and
 //   u^n = u^{n-1/2} + dt/2 F^n / m completes the previous step.
 // ----------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, double4 *__restrict__ pa, double4 *__restrict__ vel,
-                                                     double4 *__restrict__ omg, const double4 *__restrict__ frc,
-                                                     const double4 *__restrict__ trq, int vel_is_half, int advance,
-                                                     const DevClock *__restrict__ clk, int *__restrict__ cell,
-                                                     int *__restrict__ rank, int *__restrict__ count)
+                                                     double4 *__restrict__ omg, ForceBufs B, int vel_is_half,
+                                                     int advance, const DevClock *__restrict__ clk,
+                                                     int *__restrict__ cell, int *__restrict__ rank,
+                                                     int *__restrict__ count)
 {
 #pragma clang fp contract(off)
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P.N) return;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = p < P.N;
+    int c = -1;
+    if (active) {
     double4 X = pa[p];
     double4 V = vel[p];
     double4 W = omg[p];
@@ -153,10 +293,10 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, double4 *__rest
     double a = X.w;
     double m = pmass(P, a);
     double I = 0.4 * m * a * a;
-    double4 Fp = frc[p];
-    double4 Tp = trq[p];
-    double ax = Fp.x / m, ay = Fp.y / m, az = Fp.z / m;
-    double bx = Tp.x / I, by = Tp.y / I, bz = Tp.z / I;
+    double f[6];
+    total_ft(B, p, f);
+    double ax = f[0] / m, ay = f[1] / m, az = f[2] / m;
+    double bx = f[3] / I, by = f[4] / I, bz = f[5] / I;
     if (vel_is_half) {  // finish the previous step: u^n = u^{n-1/2} + dt/2 alpha^n
         V.x = V.x + 0.5 * dt * ax;
         V.y = V.y + 0.5 * dt * ay;
@@ -195,63 +335,57 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, double4 *__rest
     int cx = cell_coord(X.x, P.cw[0], P.nc[0]);
     int cy = cell_coord(X.y, P.cw[1], P.nc[1]);
     int cz = cell_coord(X.z, P.cw[2], P.nc[2]);
-    int c = (cz * P.nc[1] + cy) * P.nc[0] + cx;
-    cell[p] = c;
-    rank[p] = atomicAdd(&count[c], 1);
+    c = (cz * P.nc[1] + cy) * P.nc[0] + cx;
+    }
+    // histogram rank: lanes of a wavefront with equal consecutive cell ids (the input is
+    // sorted by the previous step's cells) form runs; the first lane of a run claims the
+    // run's slots with one atomic and the others take consecutive ranks
+    const int lane = threadIdx.x & 63;
+    const int cprev = __shfl_up(c, 1, 64);
+    const unsigned long long starts = __ballot(lane == 0 || c != cprev);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    const int rs = 63 - __clzll(starts & upto);
+    const unsigned long long after = starts & ~upto;
+    const int re = after ? __ffsll((long long)after) - 1 : 64;
+    int base = 0;
+    if (active && lane == rs) base = atomicAdd(&count[c], re - rs);
+    base = __shfl(base, rs, 64);
+    if (active) {
+        cell[p] = c;
+        rank[p] = base + (lane - rs);
+    }
 }
 
-// ----------------------------------------------------------------------------------
-// k_scan: cell_start = exclusive scan of count (ncell + 1 entries), count reset to 0,
-// per-evaluation counters reset, clock advanced.  One workgroup of 1024 lanes; each lane
-// owns a contiguous chunk, chunk sums are scanned across the 16 wavefronts.
-// ----------------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_scan(int ncell, int *__restrict__ count, int *__restrict__ cell_start,
-                                               DevClock *__restrict__ clk, int advance, DevRun *__restrict__ run)
+// k_complete: vel <- u^n = u^{n-1/2} + dt/2 F^n/m in place (an evaluation at the current
+// state, without a re-sort).
+__global__ void __launch_bounds__(kBlock) k_complete(DevParams P, const double4 *__restrict__ pa,
+                                                      double4 *__restrict__ vel, double4 *__restrict__ omg,
+                                                      ForceBufs B)
 {
-    __shared__ int wsum[16];
-    const int t = threadIdx.x;
-    const int chunk = (ncell + 1023) / 1024;
-    const int lo = t * chunk;
-    const int hi = min(lo + chunk, ncell);
-    int s = 0;
-    for (int c = lo; c < hi; ++c) s += count[c];
-    // inclusive scan of s across the wavefront
-    int lane = t & 63, wid = t >> 6;
-    int v = s;
-    for (int o = 1; o < 64; o <<= 1) {
-        int u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
-    if (lane == 63) wsum[wid] = v;
-    __syncthreads();
-    if (wid == 0) {
-        int w = lane < 16 ? wsum[lane] : 0;
-        for (int o = 1; o < 16; o <<= 1) {
-            int u = __shfl_up(w, o, 64);
-            if (lane >= o) w += u;
-        }
-        if (lane < 16) wsum[lane] = w;
-    }
-    __syncthreads();
-    int base = v - s + (wid > 0 ? wsum[wid - 1] : 0);
-    for (int c = lo; c < hi; ++c) {
-        int k = count[c];
-        cell_start[c] = base;
-        base += k;
-        count[c] = 0;
-    }
-    if (t == 1023) cell_start[ncell] = base;
-    if (t == 0) {
-        if (advance) clk->step += 1;
-        clk->n_pairs = 0;
-        clk->n_contacts = 0;
-        clk->max_fill = 0;
-        for (int k = 0; k < 9; ++k) run->sigma_last[k] = 0.0;
-    }
+#pragma clang fp contract(off)
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P.N) return;
+    const double a = pa[p].w;
+    const double m = pmass(P, a);
+    const double I = 0.4 * m * a * a;
+    const double dt = P.dt;
+    double f[6];
+    total_ft(B, p, f);
+    double4 V = vel[p];
+    double4 W = omg[p];
+    V.x = V.x + 0.5 * dt * (f[0] / m);
+    V.y = V.y + 0.5 * dt * (f[1] / m);
+    V.z = V.z + 0.5 * dt * (f[2] / m);
+    W.x = W.x + 0.5 * dt * (f[3] / I);
+    W.y = W.y + 0.5 * dt * (f[4] / I);
+    W.z = W.z + 0.5 * dt * (f[5] / I);
+    vel[p] = V;
+    omg[p] = W;
 }
 
 // ----------------------------------------------------------------------------------
-// k_scatter: move every particle to its sorted slot, record id -> slot, clear forces.
+// k_scatter: move every particle to its sorted slot, remember its previous slot (where
+// its contact-history row of the last step lives), clear the atomic force records.
 // ----------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_scatter(int N, const int *__restrict__ cell, const int *__restrict__ rank,
                                                      const int *__restrict__ cell_start,
@@ -259,19 +393,17 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int N, const int *__restrict
                                                      const double4 *__restrict__ vel_in,
                                                      const double4 *__restrict__ omg_in, double4 *__restrict__ pa_out,
                                                      double4 *__restrict__ vel_out, double4 *__restrict__ omg_out,
-                                                     double4 *__restrict__ frc_out, double4 *__restrict__ trq_out,
-                                                     int *__restrict__ inv)
+                                                     double *__restrict__ ft_x, int *__restrict__ prev)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     int dst = cell_start[cell[p]] + rank[p];
-    double4 W = omg_in[p];
     pa_out[dst] = pa_in[p];
     vel_out[dst] = vel_in[p];
-    omg_out[dst] = W;
-    frc_out[dst] = make_double4(0.0, 0.0, 0.0, 0.0);
-    trq_out[dst] = make_double4(0.0, 0.0, 0.0, 0.0);
-    inv[(int)W.w] = dst;
+    omg_out[dst] = omg_in[p];
+    const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    store_ft(ft_x + 6LL * dst, z);
+    prev[dst] = p;
 }
 
 // ----------------------------------------------------------------------------------
@@ -288,18 +420,16 @@ struct PairOut {
     double Fi[3];   // total pair force on i (F_j = -F_i)
     double Ti[3];   // torque on i
     double Tj[3];   // torque on j
-    double S[9];    // stresslet r (x) F summed over kinds (lubrication part symmetrised)
     double xi[3];   // new tangential stretch, oriented i -> j
     bool contact;
 };
 
-__device__ __forceinline__ void pair_physics(const DevParams &P, double dx, double dy, double dz, double r2,
+__device__ __forceinline__ void pair_physics(const DevParams &P, double dx, double dy, double dz, double dist,
                                              double ai, double aj, double yi, double yj, const double4 &Vi,
                                              const double4 &Vj, const double4 &Wi, const double4 &Wj,
-                                             const double xo[3], bool want_stress, PairOut &o)
+                                             const double xo[3], double *S, PairOut &o)
 {
-    const double dist = sqrt(r2);
-    const double inv_d = 1.0 / dist;
+    const double inv_d = rcp_nr(dist);
     const double nx = dx * inv_d, ny = dy * inv_d, nz = dz * inv_d;
     const double h = dist - ai - aj;
     const double s = ai + aj;
@@ -315,11 +445,11 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double dx, doub
     double dstar = 2.0 * h / s;
     dstar = dstar > 0.0 ? dstar : 0.0;
     const double g = dstar + P.eps_lub;
-    const double invg = 1.0 / g;
+    const double invg = rcp_nr(g);
     const double lg = -log(g);
-    const double K = 6.0 * kPi * P.eta0;
+    const double K = P.k6;
     const double ai2 = ai * ai, aj2 = aj * aj;
-    const double is = 1.0 / s;
+    const double is = rcp_nr(s);
     const double is2 = is * is, is3 = is2 * is;
     const double XA = K * 2.0 * ai2 * aj2 * is3 * invg;
     const double YA = K * (4.0 / 15.0) * ai * aj * (2.0 * ai2 + ai * aj + 2.0 * aj2) * is3 * lg;
@@ -356,7 +486,7 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double dx, doub
     // ---------------- electro-chemical (central): repulsion eq. rep, attraction eq. att
     const double abar = 2.0 * ai * aj * is;
     double fe = 0.0;
-    if (P.fer != 0.0) fe -= P.fer * (abar / P.a0) * (h >= 0.0 ? (P.lamd > 0.0 ? exp(-h / P.lamd) : 0.0) : 1.0);
+    if (P.fer != 0.0) fe -= P.fer_a0 * abar * (h >= 0.0 ? (P.lamd > 0.0 ? exp(-h * P.inv_lamd) : 0.0) : 1.0);
     if (P.ham != 0.0) {
         const double e = P.eps_vdw * abar;
         fe += P.ham * abar / (12.0 * ((h >= 0.0 ? h * h : 0.0) + e * e));
@@ -419,14 +549,15 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double dx, doub
     o.Fi[0] = FLx + FCx + Fex;
     o.Fi[1] = FLy + FCy + Fey;
     o.Fi[2] = FLz + FCz + Fez;
-    if (want_stress) {
+    // stresslet r (x) F_i of the pair, the lubrication part symmetrised (eq. stresslet)
+    {
         const double r[3] = {dx, dy, dz};
         const double FL[3] = {FLx, FLy, FLz};
         const double FO[3] = {FCx + Fex, FCy + Fey, FCz + Fez};
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) o.S[3 * a + b] = 0.5 * (r[a] * FL[b] + r[b] * FL[a]) + r[a] * FO[b];
+            for (int b = 0; b < 3; ++b) S[3 * a + b] += 0.5 * (r[a] * FL[b] + r[b] * FL[a]) + r[a] * FO[b];
     }
 }
 
@@ -454,151 +585,145 @@ __device__ __forceinline__ bool row_find(const int *__restrict__ hkey, const dou
 }
 
 struct HistView {
-    const int *key_old;
+    const int *key_old;    // rows of the committed history, at the slots of the last step
     const double *xi_old;
     const int *cnt_old;
-    const int *inv_old;
+    const int *prev;       // slot -> slot of the same particle at the last step (null: same slot)
     int *key_new;
     double *xi_new;
     int *cnt_new;
-    int *own_new;   // owner id of each new row
+    int *own_new;          // owner id of each new row
 };
 
 // ----------------------------------------------------------------------------------
-// k_pairs: one lane per sorted particle i.  Scans its own cell (later slots only) and
-// the 13 forward cells of the half shell: (dz > 0) or (dz = 0, dy > 0) or
-// (dz = dy = 0, dx > 0).  A row reached across a y face is a window of 4 x-cells
-// around the Lees-Edwards-shifted position.  Cells with consecutive cx are contiguous
-// in sorted order, so each row is one or two contiguous slot ranges.
+// Half shell of a cell (cx, cy, cz): its own cell (later slots only) and the 13 forward
+// cells (dz > 0) or (dz = 0, dy > 0) or (dz = dy = 0, dx > 0).  Grouped by (dz, dy) into
+// five x-rows:  r = 0 (0, 0) cells cx..cx+1;  r = 1 (0, +1);  r = 2 (+1, -1);
+// r = 3 (+1, 0);  r = 4 (+1, +1), each cells cx-1..cx+1.  A row reached across a y face
+// (images displaced by the Lees-Edwards offset) is the window of 4 x-cells around the
+// shifted position instead.  Cells with consecutive cx are contiguous in sorted order,
+// so a window is one or two contiguous slot ranges (two when it wraps in x).
 // ----------------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_pairs(DevParams P, const int *__restrict__ cell_start,
-                                                   const double4 *__restrict__ pa, const double4 *__restrict__ vel,
-                                                   const double4 *__restrict__ omg, double4 *__restrict__ frc,
-                                                   double4 *__restrict__ trq, HistView H, DevClock *__restrict__ clk,
-                                                   DevRun *__restrict__ run, int *__restrict__ pair_out,
-                                                   unsigned long long *__restrict__ pair_count)
+__device__ __forceinline__ void shell_row(int r, int &dz, int &dy)
 {
-    __shared__ double red[kBlock / 64][12];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const long long step = clk->step;
-    const bool want_stress = true;
-    const double delta = le_offset(P, step);
-    double Fi[3] = {0, 0, 0}, Ti[3] = {0, 0, 0}, S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    long long npair = 0, ncont = 0;
-    int fill = 0;
-    if (i < P.N) {
-        const double4 Xi = pa[i];
-        const double4 Vi = vel[i];
-        const double4 Wi = omg[i];
-        const int idi = (int)Wi.w;
-        const int cx = cell_coord(Xi.x, P.cw[0], P.nc[0]);
-        const int cy = cell_coord(Xi.y, P.cw[1], P.nc[1]);
-        const int cz = cell_coord(Xi.z, P.cw[2], P.nc[2]);
-        const int nxc = P.nc[0], nyc = P.nc[1], nzc = P.nc[2];
-        int *krow = H.key_new + (long long)i * P.M;
-        double *xrow = H.xi_new + (long long)i * P.M * 3;
-        const int pi_old = H.inv_old[idi];
+    dz = r >= 2 ? 1 : 0;
+    dy = r == 0 ? 0 : (r == 1 ? 1 : r - 3);
+}
 
-        // rows of the half shell: (dz, dy) with x window [xlo, xhi] (may wrap)
-        // row 0: own row, cells cx .. cx+1 with j > i in the own cell
-        for (int row = 0; row < 5; ++row) {
-            int dz, dy;
-            if (row == 0) { dz = 0; dy = 0; }
-            else if (row == 1) { dz = 0; dy = 1; }
-            else { dz = 1; dy = row - 3; }
-            int yy = cy + dy;
-            int zz = cz + dz;
-            zz = zz >= nzc ? zz - nzc : zz;
-            int xlo, xhi;
-            if (yy < 0 || yy >= nyc) {
-                // across a y face: images displaced by +delta (top) / -delta (bottom)
-                double sh = yy >= nyc ? -delta : delta;
-                int k0 = (int)floor(((double)cx * P.cw[0] + sh) / P.cw[0]);
-                xlo = k0 - 1;
-                xhi = k0 + 2;
-                yy = yy < 0 ? yy + nyc : yy - nyc;
-            } else if (row == 0) {
-                xlo = cx;
-                xhi = cx + 1;
-            } else {
-                xlo = cx - 1;
-                xhi = cx + 1;
-            }
-            const int rbase = (zz * nyc + yy) * nxc;
-            // split the window into at most two contiguous cell ranges
-            int xl = ((xlo % nxc) + nxc) % nxc;
-            int span = xhi - xlo + 1;
-            for (int part = 0; part < 2 && span > 0; ++part) {
-                int len = (xl + span <= nxc) ? span : nxc - xl;
-                int jb = cell_start[rbase + xl];
-                int je = cell_start[rbase + xl + len];
-                if (row == 0 && part == 0) jb = i + 1;  // own cell first: only later slots
-                for (int j = jb; j < je; ++j) {
-                    const double4 Xj = pa[j];
-                    double dx, dy2, dz2, r2;
-                    min_image(P, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy2, dz2);
-                    if (!listed(P, dx, dy2, dz2, Xi.w, Xj.w, r2)) continue;
-                    const double4 Vj = vel[j];
-                    const double4 Wj = omg[j];
-                    const int idj = (int)Wj.w;
-                    ++npair;
-                    if (P.record_pairs) {
-                        unsigned long long k = atomicAdd(pair_count, 1ull);
-                        if ((long long)k < P.pair_cap) {
-                            pair_out[2 * k] = idi < idj ? idi : idj;
-                            pair_out[2 * k + 1] = idi < idj ? idj : idi;
-                        } else {
-                            atomicOr(&clk->err, kErrPairBuffer);
-                        }
-                    }
-                    // stored stretch, canonical orientation min id -> max id
-                    double xo[3] = {0.0, 0.0, 0.0};
-                    const double rc_h = sqrt(r2) - Xi.w - Xj.w;
-                    if (rc_h < 0.0) {
-                        bool found = row_find(H.key_old, H.xi_old, H.cnt_old, P.M, pi_old, idj, xo);
-                        if (!found) found = row_find(H.key_old, H.xi_old, H.cnt_old, P.M, H.inv_old[idj], idi, xo);
-                        if (found && idi > idj) {
-                            xo[0] = -xo[0];
-                            xo[1] = -xo[1];
-                            xo[2] = -xo[2];
-                        }
-                    }
-                    PairOut o;
-                    pair_physics(P, dx, dy2, dz2, r2, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, want_stress, o);
-                    Fi[0] += o.Fi[0];
-                    Fi[1] += o.Fi[1];
-                    Fi[2] += o.Fi[2];
-                    Ti[0] += o.Ti[0];
-                    Ti[1] += o.Ti[1];
-                    Ti[2] += o.Ti[2];
-                    atomicAdd(&frc[j].x, -o.Fi[0]);
-                    atomicAdd(&frc[j].y, -o.Fi[1]);
-                    atomicAdd(&frc[j].z, -o.Fi[2]);
-                    atomicAdd(&trq[j].x, o.Tj[0]);
-                    atomicAdd(&trq[j].y, o.Tj[1]);
-                    atomicAdd(&trq[j].z, o.Tj[2]);
+// x window [xlo, xhi] (unwrapped) of row r for a particle in cell column cx, given whether
+// the row is reached across the top (+1) or bottom (-1) face (0: interior).
+__device__ __forceinline__ void shell_window(const DevParams &P, int r, int cx, int cross, double delta, int &xlo,
+                                             int &xhi)
+{
+    if (cross != 0) {
+        // top face: images displaced by +delta, so look around x - delta; bottom: x + delta
+        const double sh = cross > 0 ? -delta : delta;
+        const int k0 = (int)floor(((double)cx * P.cw[0] + sh) / P.cw[0]);
+        xlo = k0 - 1;
+        xhi = k0 + 2;
+    } else if (r == 0) {
+        xlo = cx;
+        xhi = cx + 1;
+    } else {
+        xlo = cx - 1;
+        xhi = cx + 1;
+    }
+}
+
+// Evaluate one listed pair (i at slot gi, j at slot gj): history lookup (stored stretch
+// of this pair in the row of either particle, canonical orientation min id -> max id) and
+// the pair physics.
+__device__ __forceinline__ void evaluate_pair(const DevParams &P, const HistView &H, int gi, int gj, int idi, int idj,
+                                              const double4 &Xi, const double4 &Xj, const double4 &Vi,
+                                              const double4 &Wi, const double4 &Vj, const double4 &Wj, double dx,
+                                              double dy, double dz, double r2, double *S, PairOut &o)
+{
+    double xo[3] = {0.0, 0.0, 0.0};
+    const double dist = sqrt(r2);
+    if (dist - Xi.w - Xj.w < 0.0) {
+        const int pi_ = H.prev ? H.prev[gi] : gi;
+        const int pj_ = H.prev ? H.prev[gj] : gj;
+        bool found = row_find(H.key_old, H.xi_old, H.cnt_old, P.M, pi_, idj, xo);
+        if (!found) found = row_find(H.key_old, H.xi_old, H.cnt_old, P.M, pj_, idi, xo);
+        if (found && idi > idj) {
+            xo[0] = -xo[0];
+            xo[1] = -xo[1];
+            xo[2] = -xo[2];
+        }
+    }
+    pair_physics(P, dx, dy, dz, dist, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, S, o);
+}
+
+__device__ __forceinline__ void record_pair(const DevParams &P, int idi, int idj, int *pair_out,
+                                            unsigned long long *pair_count, DevClock *clk)
+{
+    unsigned long long k = atomicAdd(pair_count, 1ull);
+    if ((long long)k < P.pair_cap) {
+        pair_out[2 * k] = idi < idj ? idi : idj;
+        pair_out[2 * k + 1] = idi < idj ? idj : idi;
+    } else {
+        atomicOr(&clk->err, kErrPairBuffer);
+    }
+}
+
+__device__ __forceinline__ void store_history(const HistView &H, int M, int gi, int slot, int idi, int idj,
+                                              const PairOut &o, DevClock *clk)
+{
+    if (slot < M) {
+        const double sg = idi < idj ? 1.0 : -1.0;
+        H.key_new[(long long)gi * M + slot] = idj;
+        double *x = H.xi_new + ((long long)gi * M + slot) * 3;
+        x[0] = sg * o.xi[0];
+        x[1] = sg * o.xi[1];
+        x[2] = sg * o.xi[2];
+    } else {
+        atomicOr(&clk->err, kErrRowOverflow);
+    }
+}
+
+// Sort history row gi by partner id and publish it (the per-row sort of the contact
+// map).  Rows of up to 8 entries are sorted in registers (odd-even transposition on
+// (key, index), then one permuted copy); longer rows by insertion in place.
+__device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int fill, int idi)
+{
+    int *krow = H.key_new + (long long)gi * M;
+    double *xrow = H.xi_new + (long long)gi * M * 3;
+    const int nrow = fill < M ? fill : M;
+    if (nrow >= 2 && nrow <= 8) {
+        int key[8], idx[8];
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) S[k] += o.S[k];
-                    if (o.contact) {
-                        ++ncont;
-                        if (fill < P.M) {
-                            const double sg = idi < idj ? 1.0 : -1.0;
-                            krow[fill] = idj;
-                            xrow[3 * fill + 0] = sg * o.xi[0];
-                            xrow[3 * fill + 1] = sg * o.xi[1];
-                            xrow[3 * fill + 2] = sg * o.xi[2];
-                        } else {
-                            atomicOr(&clk->err, kErrRowOverflow);
-                        }
-                        ++fill;
-                    }
+        for (int a = 0; a < 8; ++a) {
+            key[a] = a < nrow ? krow[a] : 0x7fffffff;
+            idx[a] = a;
+        }
+#pragma unroll
+        for (int round = 0; round < 8; ++round) {
+#pragma unroll
+            for (int a = round & 1; a + 1 < 8; a += 2) {
+                if (key[a] > key[a + 1]) {
+                    int tk = key[a]; key[a] = key[a + 1]; key[a + 1] = tk;
+                    int ti = idx[a]; idx[a] = idx[a + 1]; idx[a + 1] = ti;
                 }
-                xl = 0;
-                span -= len;
             }
         }
-        // sort the new row by partner id (insertion sort; rows are short)
-        const int nrow = fill < P.M ? fill : P.M;
+        double x[8][3];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            if (a < nrow) {
+                const double *q = xrow + 3 * idx[a];
+                x[a][0] = q[0];
+                x[a][1] = q[1];
+                x[a][2] = q[2];
+            }
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            if (a < nrow) {
+                krow[a] = key[a];
+                xrow[3 * a] = x[a][0];
+                xrow[3 * a + 1] = x[a][1];
+                xrow[3 * a + 2] = x[a][2];
+            }
+    } else if (nrow > 8) {
         for (int a = 1; a < nrow; ++a) {
             int key = krow[a];
             double x0 = xrow[3 * a], x1 = xrow[3 * a + 1], x2 = xrow[3 * a + 2];
@@ -615,37 +740,132 @@ __global__ void __launch_bounds__(kBlock) k_pairs(DevParams P, const int *__rest
             xrow[3 * (b + 1) + 1] = x1;
             xrow[3 * (b + 1) + 2] = x2;
         }
-        H.cnt_new[i] = nrow;
-        H.own_new[i] = idi;
-
-        // per-particle terms: Stokes drag and rotational drag (eq. rst)
-        const double K = 6.0 * kPi * P.eta0;
-        Fi[0] += -K * Xi.w * (Vi.x - P.gd * Xi.y);
-        Fi[1] += -K * Xi.w * Vi.y;
-        Fi[2] += -K * Xi.w * Vi.z;
-        const double KR = 8.0 * kPi * P.eta0 * Xi.w * Xi.w * Xi.w;
-        Ti[0] += -KR * Wi.x;
-        Ti[1] += -KR * Wi.y;
-        Ti[2] += -KR * (Wi.z + 0.5 * P.gd);
-        atomicAdd(&frc[i].x, Fi[0]);
-        atomicAdd(&frc[i].y, Fi[1]);
-        atomicAdd(&frc[i].z, Fi[2]);
-        atomicAdd(&trq[i].x, Ti[0]);
-        atomicAdd(&trq[i].y, Ti[1]);
-        atomicAdd(&trq[i].z, Ti[2]);
-        if (!(isfinite(Fi[0]) && isfinite(Fi[1]) && isfinite(Fi[2]) && isfinite(Ti[0]) && isfinite(Ti[1]) &&
-              isfinite(Ti[2])))
-            atomicOr(&clk->err, kErrNonFinite);
     }
-    // block reduction of the stress and the counters
+    H.cnt_new[gi] = nrow;
+    H.own_new[gi] = idi;
+}
+
+// Stokes drag and rotational drag of one particle (eq. rst), added to f (force 0..2,
+// torque 3..5).
+__device__ __forceinline__ void stokes_terms(const DevParams &P, const double4 &Xi, const double4 &Vi,
+                                             const double4 &Wi, double f[6])
+{
+    const double K = P.k6;
+    f[0] += -K * Xi.w * (Vi.x - P.gd * Xi.y);
+    f[1] += -K * Xi.w * Vi.y;
+    f[2] += -K * Xi.w * Vi.z;
+    const double KR = P.k8 * Xi.w * Xi.w * Xi.w;
+    f[3] += -KR * Wi.x;
+    f[4] += -KR * Wi.y;
+    f[5] += -KR * (Wi.z + 0.5 * P.gd);
+}
+
+__device__ __forceinline__ bool finite6(const double f[6])
+{
+    return isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2]) && isfinite(f[3]) && isfinite(f[4]) &&
+           isfinite(f[5]);
+}
+
+struct PairTally {
+    double S[9];
+    long long npair, ncont;
+    int fill;
+};
+
+// ----------------------------------------------------------------------------------
+// Per-particle path, for a cell row too large for the LDS tile: one lane walks the half
+// shell of particle i, keeps its own side in registers (stored into its own record) and
+// adds the partner side atomically to ft_x.
+// ----------------------------------------------------------------------------------
+__device__ void particle_pairs_global(const DevParams &P, int i, double delta, const int *__restrict__ cell_start,
+                                      const double4 *__restrict__ pa, const double4 *__restrict__ vel,
+                                      const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
+                                      DevClock *clk, int *pair_out, unsigned long long *pair_count,
+                                      PairTally &tally)
+{
+    const double4 Xi = pa[i];
+    const double4 Vi = vel[i];
+    const double4 Wi = omg[i];
+    const int idi = (int)Wi.w;
+    const int cx = cell_coord(Xi.x, P.cw[0], P.nc[0]);
+    const int cy = cell_coord(Xi.y, P.cw[1], P.nc[1]);
+    const int cz = cell_coord(Xi.z, P.cw[2], P.nc[2]);
+    const int nxc = P.nc[0], nyc = P.nc[1], nzc = P.nc[2];
+    double f[6] = {0, 0, 0, 0, 0, 0};
+    int fill = 0;
+    for (int r = 0; r < 5; ++r) {
+        int dz, dy;
+        shell_row(r, dz, dy);
+        int yy = cy + dy;
+        int zz = cz + dz;
+        zz = zz >= nzc ? zz - nzc : zz;
+        const int cross = yy >= nyc ? 1 : (yy < 0 ? -1 : 0);
+        yy = yy < 0 ? yy + nyc : (yy >= nyc ? yy - nyc : yy);
+        int xlo, xhi;
+        shell_window(P, r, cx, cross, delta, xlo, xhi);
+        const int rbase = (zz * nyc + yy) * nxc;
+        int xl = ((xlo % nxc) + nxc) % nxc;
+        int span = xhi - xlo + 1;
+        for (int part = 0; part < 2 && span > 0; ++part) {
+            const int len = (xl + span <= nxc) ? span : nxc - xl;
+            int jb = cell_start[rbase + xl];
+            const int je = cell_start[rbase + xl + len];
+            if (r == 0 && part == 0) jb = i + 1;
+            for (int j = jb; j < je; ++j) {
+                const double4 Xj = pa[j];
+                double dx, dy2, dz2, r2;
+                min_image(P, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy2, dz2);
+                if (!listed(P, dx, dy2, dz2, Xi.w, Xj.w, r2)) continue;
+                const double4 Vj = vel[j];
+                const double4 Wj = omg[j];
+                const int idj = (int)Wj.w;
+                ++tally.npair;
+                if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
+                PairOut o;
+                evaluate_pair(P, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    f[k] += o.Fi[k];
+                    f[3 + k] += o.Ti[k];
+                }
+                double *xr = B.x + 6LL * j;
+                atomicAdd(xr + 0, -o.Fi[0]);
+                atomicAdd(xr + 1, -o.Fi[1]);
+                atomicAdd(xr + 2, -o.Fi[2]);
+                atomicAdd(xr + 3, o.Tj[0]);
+                atomicAdd(xr + 4, o.Tj[1]);
+                atomicAdd(xr + 5, o.Tj[2]);
+                if (o.contact) {
+                    ++tally.ncont;
+                    store_history(H, P.M, i, fill, idi, idj, o, clk);
+                    ++fill;
+                }
+            }
+            xl = 0;
+            span -= len;
+        }
+    }
+    finish_row(H, P.M, i, fill, idi);
+    tally.fill = max(tally.fill, fill);
+    stokes_terms(P, Xi, Vi, Wi, f);
+    store_ft(B.own + 6LL * i, f);
+    if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
+}
+
+// Block reduction of the stress and counters of a workgroup into its partial record
+// (12 doubles: 9 stress components, pairs, contacts, largest row; component k of workgroup
+// w at partials[k pstride + w]), summed by k_finish.
+__device__ __forceinline__ void reduce_tally(PairTally &tally, double (*red)[12], double *__restrict__ partials,
+                                             int pstride)
+{
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        double v = warp_sum(S[k]);
+        double v = warp_sum(tally.S[k]);
         if (lane == 0) red[wid][k] = v;
     }
-    long long np_ = warp_sum_ll(npair), nc_ = warp_sum_ll(ncont);
-    int mf = warp_max(fill);
+    long long np_ = warp_sum_ll(tally.npair), nc_ = warp_sum_ll(tally.ncont);
+    int mf = warp_max(tally.fill);
     if (lane == 0) {
         red[wid][9] = (double)np_;
         red[wid][10] = (double)nc_;
@@ -656,72 +876,399 @@ __global__ void __launch_bounds__(kBlock) k_pairs(DevParams P, const int *__rest
         const int k = threadIdx.x;
         double v = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) v = (k == 11) ? fmax(v, red[w][k]) : v + red[w][k];
-        if (k < 9) {
-            atomicAdd(&run->sigma_last[k], v);
-        } else if (k == 9) {
-            atomicAdd(&clk->n_pairs, (unsigned long long)v);
-        } else if (k == 10) {
-            atomicAdd(&clk->n_contacts, (unsigned long long)v);
+        partials[(long long)k * pstride + blockIdx.x] = v;
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// k_pairs: one workgroup per x-row of cells (cz, cy).  The particles of the five rows of
+// the half shell are staged in LDS (one 32-byte position/radius record each).
+//   A1  every (particle, shell row) task turns its window into at most two ranges of
+//       staged indices; a block scan of the range lengths flattens all candidates;
+//   A2  every lane tests an equal contiguous share of the candidates from LDS and queues
+//       the listed pairs in LDS;
+//   B   all lanes evaluate the queued pairs; both sides accumulate in LDS (FP64 LDS
+//       atomics), history rows of the own particles get their slots from LDS counters;
+//   C   own particles: Stokes terms, own force record, history row sorted by partner id;
+//       particles of the other four shell rows: partner-side force records.
+// Tile capacities (P.own_cap, P.stage_cap, P.qcap) are sized from the mean row
+// occupancy; a row beyond them takes the per-particle path.  The LDS layout is dynamic.
+// ----------------------------------------------------------------------------------
+struct TileShared {
+    int rs[5], re[5], ro[6], rbase[5], rcross[5];
+    int qn;
+    int wsum[kBlock / 64];
+    double red[kBlock / 64][12];
+};
+
+struct TileView {
+    double4 *sp;        // stage_cap
+    double *acc;        // stage_cap x 6
+    unsigned *queue;    // qcap
+    uint2 *trange;      // 5 own_cap
+    int *tpre;          // 5 own_cap + 1
+    int *rowcnt;        // own_cap
+};
+
+__host__ __device__ inline size_t tile_lds_bytes(int own_cap, int stage_cap, int qcap)
+{
+    return (size_t)stage_cap * 32 + (size_t)stage_cap * 48 + (size_t)qcap * 4 + (size_t)5 * own_cap * 8 +
+           (size_t)(5 * own_cap + 1) * 4 + (size_t)own_cap * 4;
+}
+
+__device__ __forceinline__ void tile_pair(const DevParams &P, const HistView &H, const TileShared &T,
+                                          const TileView &V, int il, int jl, double delta,
+                                          const double4 *__restrict__ vel, const double4 *__restrict__ omg,
+                                          DevClock *clk, int *pair_out, unsigned long long *pair_count,
+                                          PairTally &tally)
+{
+    const double4 Xi = V.sp[il];
+    const double4 Xj = V.sp[jl];
+    double dx, dy, dz, r2;
+    min_image(P, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy, dz);
+    listed(P, dx, dy, dz, Xi.w, Xj.w, r2);
+    const int r = (jl >= T.ro[1]) + (jl >= T.ro[2]) + (jl >= T.ro[3]) + (jl >= T.ro[4]);
+    const int gi = T.rs[0] + il;
+    const int gj = T.rs[r] + (jl - T.ro[r]);
+    const double4 Vi = vel[gi];
+    const double4 Wi = omg[gi];
+    const double4 Vj = vel[gj];
+    const double4 Wj = omg[gj];
+    const int idi = (int)Wi.w, idj = (int)Wj.w;
+    ++tally.npair;
+    if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
+    PairOut o;
+    evaluate_pair(P, H, gi, gj, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy, dz, r2, tally.S, o);
+    double *ai = V.acc + 6 * il;
+    double *aj = V.acc + 6 * jl;
+    atomicAdd(ai + 0, o.Fi[0]);
+    atomicAdd(ai + 1, o.Fi[1]);
+    atomicAdd(ai + 2, o.Fi[2]);
+    atomicAdd(ai + 3, o.Ti[0]);
+    atomicAdd(ai + 4, o.Ti[1]);
+    atomicAdd(ai + 5, o.Ti[2]);
+    atomicAdd(aj + 0, -o.Fi[0]);
+    atomicAdd(aj + 1, -o.Fi[1]);
+    atomicAdd(aj + 2, -o.Fi[2]);
+    atomicAdd(aj + 3, o.Tj[0]);
+    atomicAdd(aj + 4, o.Tj[1]);
+    atomicAdd(aj + 5, o.Tj[2]);
+    if (o.contact) {
+        ++tally.ncont;
+        const int slot = atomicAdd(&V.rowcnt[il], 1);
+        store_history(H, P.M, gi, slot, idi, idj, o, clk);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__restrict__ cell_start,
+                                                      const double4 *__restrict__ pa, const double4 *__restrict__ vel,
+                                                      const double4 *__restrict__ omg, ForceBufs B, HistView H,
+                                                      DevClock *__restrict__ clk, double *__restrict__ partials,
+                                                      int *__restrict__ pair_out,
+                                                      unsigned long long *__restrict__ pair_count)
+{
+    __shared__ TileShared T;
+    extern __shared__ double4 dyn_lds[];
+    TileView V;
+    V.sp = dyn_lds;
+    V.acc = reinterpret_cast<double *>(V.sp + P.stage_cap);
+    V.queue = reinterpret_cast<unsigned *>(V.acc + 6 * P.stage_cap);
+    V.trange = reinterpret_cast<uint2 *>(V.queue + P.qcap);
+    V.tpre = reinterpret_cast<int *>(V.trange + 5 * P.own_cap);
+    V.rowcnt = V.tpre + 5 * P.own_cap + 1;
+
+    const int t = threadIdx.x;
+    const int nxc = P.nc[0], nyc = P.nc[1], nzc = P.nc[2];
+    const int row = blockIdx.x;
+    const int cz = row / nyc, cy = row - (row / nyc) * nyc;
+    const double delta = le_offset(P, clk->step);
+    PairTally tally;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
+    tally.npair = tally.ncont = 0;
+    tally.fill = 0;
+
+    if (t < 5) {
+        int dz, dy;
+        shell_row(t, dz, dy);
+        int zz = cz + dz;
+        zz = zz >= nzc ? zz - nzc : zz;
+        int yy = cy + dy;
+        T.rcross[t] = yy >= nyc ? 1 : (yy < 0 ? -1 : 0);
+        yy = yy < 0 ? yy + nyc : (yy >= nyc ? yy - nyc : yy);
+        const int base = (zz * nyc + yy) * nxc;
+        T.rbase[t] = base;
+        T.rs[t] = cell_start[base];
+        T.re[t] = cell_start[base + nxc];
+    }
+    __syncthreads();
+    if (t == 0) {
+        int o = 0;
+        for (int r = 0; r < 5; ++r) {
+            T.ro[r] = o;
+            o += T.re[r] - T.rs[r];
+        }
+        T.ro[5] = o;
+        T.qn = 0;
+    }
+    __syncthreads();
+    const int n_own = T.re[0] - T.rs[0];
+    const int total = T.ro[5];
+    if (n_own > P.own_cap || total > P.stage_cap) {
+        // tile does not fit: per-particle path; the partner records of this row stay zero
+        for (int i = T.rs[0] + t; i < T.re[0]; i += kBlock)
+            particle_pairs_global(P, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, tally);
+        const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int r = 1; r < 5; ++r)
+            for (int g = T.rs[r] + t; g < T.re[r]; g += kBlock) store_ft(B.nb + 6LL * ((r - 1) * B.n + g), z);
+        reduce_tally(tally, T.red, partials, P.pstride);
+        return;
+    }
+    // stage the shell rows
+    for (int k = t; k < total; k += kBlock) {
+        const int r = (k >= T.ro[1]) + (k >= T.ro[2]) + (k >= T.ro[3]) + (k >= T.ro[4]);
+        V.sp[k] = pa[T.rs[r] + (k - T.ro[r])];
+    }
+    for (int k = t; k < 6 * total; k += kBlock) V.acc[k] = 0.0;
+    for (int k = t; k < n_own; k += kBlock) V.rowcnt[k] = 0;
+    __syncthreads();
+
+    // A1: candidate ranges of every (particle, shell row) task, as LDS indices
+    const int ntask = 5 * n_own;
+    for (int task = t; task < ntask; task += kBlock) {
+        const int r = task / n_own;
+        const int il = task - r * n_own;
+        const int cx = cell_coord(V.sp[il].x, P.cw[0], nxc);
+        int xlo, xhi;
+        shell_window(P, r, cx, T.rcross[r], delta, xlo, xhi);
+        int xl = ((xlo % nxc) + nxc) % nxc;
+        int span = xhi - xlo + 1;
+        unsigned rng[2] = {0u, 0u};
+        int cnt = 0;
+        for (int part = 0; part < 2 && span > 0; ++part) {
+            const int len = (xl + span <= nxc) ? span : nxc - xl;
+            int jb = cell_start[T.rbase[r] + xl];
+            const int je = cell_start[T.rbase[r] + xl + len];
+            if (r == 0 && part == 0) jb = T.rs[0] + il + 1;
+            const int n = je > jb ? je - jb : 0;
+            rng[part] = (unsigned)(T.ro[r] + (jb - T.rs[r])) | ((unsigned)n << 16);
+            cnt += n;
+            xl = 0;
+            span -= len;
+        }
+        V.trange[task] = make_uint2(rng[0], rng[1]);
+        V.tpre[task] = cnt;
+    }
+    __syncthreads();
+    // exclusive scan of the task counts: lane t owns tasks per .. per + per - 1
+    {
+        const int per = (ntask + kBlock - 1) / kBlock;
+        int s_ = 0;
+        for (int k = 0; k < per; ++k) {
+            const int task = per * t + k;
+            s_ += task < ntask ? V.tpre[task] : 0;
+        }
+        const int lane = t & 63, wid = t >> 6;
+        int incl = s_;
+        for (int o = 1; o < 64; o <<= 1) {
+            int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) T.wsum[wid] = incl;
+        __syncthreads();
+        int base = incl - s_;
+        for (int w = 0; w < wid; ++w) base += T.wsum[w];
+        for (int k = 0; k < per; ++k) {
+            const int task = per * t + k;
+            if (task < ntask) {
+                const int c = V.tpre[task];
+                V.tpre[task] = base;
+                base += c;
+            }
+        }
+        if (t == kBlock - 1) V.tpre[ntask] = base;
+    }
+    __syncthreads();
+
+    // A2: every lane tests an equal, contiguous share of all candidates of the tile
+    {
+        const int C = V.tpre[ntask];
+        const int chunk = (C + kBlock - 1) / kBlock;
+        const int k0 = t * chunk;
+        const int k1 = min(k0 + chunk, C);
+        if (k0 < k1) {
+            int lo = 0, hi = ntask;  // last task whose prefix is <= k0
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (V.tpre[mid] <= k0) lo = mid; else hi = mid;
+            }
+            int task = lo;
+            int il = task % n_own;
+            double4 Xi = V.sp[il];
+            uint2 rg = V.trange[task];
+            int tb = V.tpre[task], te = V.tpre[task + 1];
+            for (int k = k0; k < k1; ++k) {
+                if (k >= te) {
+                    do {
+                        ++task;
+                        tb = V.tpre[task];
+                        te = V.tpre[task + 1];
+                    } while (k >= te);
+                    il = task % n_own;
+                    Xi = V.sp[il];
+                    rg = V.trange[task];
+                }
+                const int o = k - tb;
+                const int len0 = (int)(rg.x >> 16);
+                const int jl = o < len0 ? (int)(rg.x & 0xffffu) + o : (int)(rg.y & 0xffffu) + (o - len0);
+                const double4 Xj = V.sp[jl];
+                double dx, dy, dz, r2;
+                min_image(P, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy, dz);
+                if (!listed(P, dx, dy, dz, Xi.w, Xj.w, r2)) continue;
+                const int q = atomicAdd(&T.qn, 1);
+                if (q < P.qcap)
+                    V.queue[q] = ((unsigned)il << 16) | (unsigned)jl;
+                else  // queue full: evaluate now
+                    tile_pair(P, H, T, V, il, jl, delta, vel, omg, clk, pair_out, pair_count, tally);
+            }
+        }
+    }
+    __syncthreads();
+
+    // B: evaluate the queued pairs
+    const int nq = T.qn < P.qcap ? T.qn : P.qcap;
+    for (int q = t; q < nq; q += kBlock) {
+        const unsigned e = V.queue[q];
+        tile_pair(P, H, T, V, (int)(e >> 16), (int)(e & 0xffffu), delta, vel, omg, clk, pair_out, pair_count, tally);
+    }
+    __syncthreads();
+
+    // C: own particles (Stokes terms, own record, history row), then partner records
+    for (int il = t; il < n_own; il += kBlock) {
+        const int gi = T.rs[0] + il;
+        const double4 Xi = V.sp[il];
+        const double4 Vi = vel[gi];
+        const double4 Wi = omg[gi];
+        double f[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) f[c] = V.acc[6 * il + c];
+        stokes_terms(P, Xi, Vi, Wi, f);
+        store_ft(B.own + 6LL * gi, f);
+        if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
+        const int fill = V.rowcnt[il];
+        finish_row(H, P.M, gi, fill, (int)Wi.w);
+        tally.fill = max(tally.fill, fill);
+    }
+    for (int k = T.ro[1] + t; k < total; k += kBlock) {
+        const int r = (k >= T.ro[2]) + (k >= T.ro[3]) + (k >= T.ro[4]) + 1;
+        const int g = T.rs[r] + (k - T.ro[r]);
+        double f[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) f[c] = V.acc[6 * k + c];
+        store_ft(B.nb + 6LL * ((r - 1) * B.n + g), f);
+    }
+    reduce_tally(tally, T.red, partials, P.pstride);
+}
+
+// ----------------------------------------------------------------------------------
+// k_finish: sum the per-workgroup partial records of k_pairs in a fixed order (so the
+// stress of an evaluation does not depend on scheduling), publish the pair part of the
+// stress and the counters, and store the stress sample of the current time index when the
+// schedule asks for it.  One workgroup of 1024 lanes; lane t loads the records t, t + 1024,
+// ... of every component at once, coalesced (the buffer is padded with zero records).
+// ----------------------------------------------------------------------------------
+template <int R>
+__global__ void __launch_bounds__(1024) k_finish(const double *__restrict__ partials, DevClock *__restrict__ clk,
+                                                  DevRun *__restrict__ run, int sample)
+// partials: 12 components x (1024 R) records
+{
+    __shared__ double red[16][12];
+    const int t = threadIdx.x;
+    double v[R][12];
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[m][k] = partials[(long long)k * (1024 * R) + m * 1024 + t];
+    double acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = v[0][k];
+#pragma unroll
+    for (int m = 1; m < R; ++m) {
+#pragma unroll
+        for (int k = 0; k < 11; ++k) acc[k] += v[m][k];
+        acc[11] = fmax(acc[11], v[m][11]);
+    }
+    const int lane = t & 63, wid = t >> 6;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) {
+        double x = warp_sum(acc[k]);
+        if (lane == 0) red[wid][k] = x;
+    }
+    double mx = acc[11];
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) red[wid][11] = mx;
+    __syncthreads();
+    if (t < 12) {
+        double x = 0.0;
+        for (int w = 0; w < 16; ++w) x = (t == 11) ? fmax(x, red[w][t]) : x + red[w][t];
+        if (t < 9) {
+            run->sigma_last[t] = x;
+            const long long n = clk->step;
+            if (sample && run->sample_every > 0 && n % run->sample_every == 0 && n >= run->sample_first) {
+                const long long slot = (n - run->sample_first) / run->sample_every;
+                if (slot < run->sample_cap) run->samples[slot * 9 + t] = x;
+            }
+        } else if (t == 9) {
+            clk->n_pairs = (unsigned long long)x;
+        } else if (t == 10) {
+            clk->n_contacts = (unsigned long long)x;
         } else {
-            atomicMax(&clk->max_fill, (int)v);
+            clk->max_fill = (int)x;
         }
     }
 }
 
 // ----------------------------------------------------------------------------------
-// k_sample: copy the pair part of the stress of this evaluation into the sample slot of
-// the current time index, when the schedule asks for it.  One lane.
-// ----------------------------------------------------------------------------------
-__global__ void k_sample(const DevClock *__restrict__ clk, DevRun *__restrict__ run)
-{
-    if (threadIdx.x >= 9) return;
-    const long long n = clk->step;
-    if (run->sample_every <= 0 || n % run->sample_every != 0 || n < run->sample_first) return;
-    const long long slot = (n - run->sample_first) / run->sample_every;
-    if (slot >= run->sample_cap) return;
-    run->samples[slot * 9 + threadIdx.x] = run->sigma_last[threadIdx.x];
-}
-
-// ----------------------------------------------------------------------------------
 // k_unsort: state by particle id.  Completes u^n = vel + dt/2 F/m when vel holds the
-// half-step velocity.
+// half-step velocity and complete != 0.
 // ----------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_unsort(DevParams P, const double4 *__restrict__ pa,
                                                     const double4 *__restrict__ vel, const double4 *__restrict__ omg,
-                                                    const double4 *__restrict__ frc, const double4 *__restrict__ trq,
-                                                    int vel_is_half, int complete, double *__restrict__ x,
-                                                    double *__restrict__ u, double *__restrict__ w,
-                                                    double *__restrict__ F, double *__restrict__ T)
+                                                    ForceBufs B, int vel_is_half, int complete,
+                                                    double *__restrict__ x, double *__restrict__ u,
+                                                    double *__restrict__ w, double *__restrict__ F,
+                                                    double *__restrict__ T)
 {
 #pragma clang fp contract(off)
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P.N) return;
-    double4 X = pa[p], V = vel[p], W = omg[p], Fp = frc[p], Tp = trq[p];
+    double4 X = pa[p], V = vel[p], W = omg[p];
+    double f[6];
+    total_ft(B, p, f);
     int id = (int)W.w;
     if (vel_is_half && complete) {
         double m = pmass(P, X.w);
         double I = 0.4 * m * X.w * X.w;
         const double dt = P.dt;
-        V.x = V.x + 0.5 * dt * (Fp.x / m);
-        V.y = V.y + 0.5 * dt * (Fp.y / m);
-        V.z = V.z + 0.5 * dt * (Fp.z / m);
-        W.x = W.x + 0.5 * dt * (Tp.x / I);
-        W.y = W.y + 0.5 * dt * (Tp.y / I);
-        W.z = W.z + 0.5 * dt * (Tp.z / I);
+        V.x = V.x + 0.5 * dt * (f[0] / m);
+        V.y = V.y + 0.5 * dt * (f[1] / m);
+        V.z = V.z + 0.5 * dt * (f[2] / m);
+        W.x = W.x + 0.5 * dt * (f[3] / I);
+        W.y = W.y + 0.5 * dt * (f[4] / I);
+        W.z = W.z + 0.5 * dt * (f[5] / I);
     }
     if (x) { x[3 * id] = X.x; x[3 * id + 1] = X.y; x[3 * id + 2] = X.z; }
     if (u) { u[3 * id] = V.x; u[3 * id + 1] = V.y; u[3 * id + 2] = V.z; }
     if (w) { w[3 * id] = W.x; w[3 * id + 1] = W.y; w[3 * id + 2] = W.z; }
-    if (F) { F[3 * id] = Fp.x; F[3 * id + 1] = Fp.y; F[3 * id + 2] = Fp.z; }
-    if (T) { T[3 * id] = Tp.x; T[3 * id + 1] = Tp.y; T[3 * id + 2] = Tp.z; }
+    if (F) { F[3 * id] = f[0]; F[3 * id + 1] = f[1]; F[3 * id + 2] = f[2]; }
+    if (T) { T[3 * id] = f[3]; T[3 * id + 1] = f[4]; T[3 * id + 2] = f[5]; }
 }
 
-// k_load: particles by id -> unsorted records (slot = id).
+// k_load: particles by id -> unsorted records (slot = id), force records cleared.
 __global__ void __launch_bounds__(kBlock) k_load(int N, const double *__restrict__ x, const double *__restrict__ rad,
                                                   const double *__restrict__ u, const double *__restrict__ w,
                                                   double gd, double4 *__restrict__ pa, double4 *__restrict__ vel,
-                                                  double4 *__restrict__ omg, double4 *__restrict__ frc,
-                                                  double4 *__restrict__ trq, int *__restrict__ inv)
+                                                  double4 *__restrict__ omg, ForceBufs B)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
@@ -734,9 +1281,10 @@ __global__ void __launch_bounds__(kBlock) k_load(int N, const double *__restrict
         omg[p] = make_double4(w[3 * p], w[3 * p + 1], w[3 * p + 2], (double)p);
     else
         omg[p] = make_double4(0.0, 0.0, -0.5 * gd, (double)p);
-    frc[p] = make_double4(0.0, 0.0, 0.0, 0.0);
-    trq[p] = make_double4(0.0, 0.0, 0.0, 0.0);
-    inv[p] = p;
+    const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    store_ft(B.own + 6LL * p, z);
+    store_ft(B.x + 6LL * p, z);
+    for (int r = 0; r < 4; ++r) store_ft(B.nb + 6LL * (r * B.n + p), z);
 }
 
 // k_history_export: rows -> (id_min, id_max, xi) list in canonical orientation.

@@ -247,10 +247,17 @@ class Simulation:
         order = np.lexsort((pr[:, 1], pr[:, 0]))
         return pr[order], xi[order]
 
-    KERNELS = ("k_predict", "k_scan", "k_scatter", "k_pairs", "k_sample")
+    KERNELS = ("k_predict", "k_scan", "k_scatter", "k_pairs", "k_finish")
 
-    def set_timing(self, enable=True):
-        self._check(self.lib.dss_set_timing(self.h, int(bool(enable))))
+    def set_timing(self, enable=True, kernels=None):
+        """Time the named kernels (all if None) with HIP events; enable=False stops."""
+        if not enable:
+            mask = 0
+        elif kernels is None:
+            mask = -1
+        else:
+            mask = sum(1 << self.KERNELS.index(k) for k in kernels)
+        self._check(self.lib.dss_set_timing(self.h, int(mask)))
 
     def timing(self):
         """{kernel name: (total ms, launches)} since set_timing(True)."""
