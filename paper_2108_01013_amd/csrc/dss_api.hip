@@ -219,9 +219,14 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample)
     if (h->P.record_pairs) HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
     {
         TimedLaunch t(h, 3);
-        hipLaunchKernelGGL(k_pairs, dim3(h->P.nc[1] * h->P.nc[2]), dim3(kBlock), h->tile_lds, h->stream, h->P,
-                           h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(), H, h->clk, h->partials,
-                           h->pairs, h->pair_count);
+        if (h->prm.precision == DSS_MIXED)
+            hipLaunchKernelGGL(k_pairs<float>, dim3(h->P.nc[1] * h->P.nc[2]), dim3(kBlock), h->tile_lds, h->stream,
+                               h->P, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(), H, h->clk,
+                               h->partials, h->pairs, h->pair_count);
+        else
+            hipLaunchKernelGGL(k_pairs<double>, dim3(h->P.nc[1] * h->P.nc[2]), dim3(kBlock), h->tile_lds, h->stream,
+                               h->P, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(), H, h->clk,
+                               h->partials, h->pairs, h->pair_count);
     }
     TimedLaunch t(h, 4);
     switch (h->finish_r) {
@@ -440,7 +445,10 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
     free_all(h);
     h->P = P;
     h->tile_lds = tile_lds_bytes(P.own_cap, P.stage_cap, P.qcap);
-    HIPTRY(hipFuncSetAttribute((const void *)k_pairs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->tile_lds));
+    HIPTRY(hipFuncSetAttribute((const void *)k_pairs<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)h->tile_lds));
+    HIPTRY(hipFuncSetAttribute((const void *)k_pairs<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)h->tile_lds));
     h->N = N;
     h->sum_a3 = sa3;
     const size_t rows = (size_t)N * (size_t)P.M;

@@ -424,111 +424,138 @@ struct PairOut {
     bool contact;
 };
 
-__device__ __forceinline__ void pair_physics(const DevParams &P, double dx, double dy, double dz, double dist,
-                                             double ai, double aj, double yi, double yj, const double4 &Vi,
+// Arithmetic of the pair physics in type Real: double (FP64 mode) or float (mixed mode).
+__device__ __forceinline__ double rcp_r(double x) { return rcp_nr(x); }
+__device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double log_r(double x) { return log(x); }
+__device__ __forceinline__ float log_r(float x) { return __logf(x); }
+__device__ __forceinline__ double exp_r(double x) { return exp(x); }
+__device__ __forceinline__ float exp_r(float x) { return __expf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_sqrtf(x); }
+
+// Pair physics.  In FP64 mode (Real = double) everything is FP64.  In mixed mode (Real =
+// float) the gap h, the lubrication argument d* + eps and its reciprocal, and the velocity
+// differences (which cancel the large ambient-flow values) are formed in FP64 and rounded
+// once; the unit vector, coefficients, log/exp, contact model and stresslet are FP32; the
+// results are accumulated in FP64 by the caller.
+template <typename Real>
+__device__ __forceinline__ void pair_physics(const DevParams &P, double dx_d, double dy_d, double dz_d, double dist,
+                                             double ai_d, double aj_d, double yi, double yj, const double4 &Vi,
                                              const double4 &Vj, const double4 &Wi, const double4 &Wj,
                                              const double xo[3], double *S, PairOut &o)
 {
-    const double inv_d = rcp_nr(dist);
-    const double nx = dx * inv_d, ny = dy * inv_d, nz = dz * inv_d;
-    const double h = dist - ai - aj;
-    const double s = ai + aj;
-    const double gd = P.gd;
-    // fluctuation velocities u' = u - U_inf(x); w' = w - Omega_inf
-    const double dux = (Vj.x - gd * yj) - (Vi.x - gd * yi);
-    const double duy = Vj.y - Vi.y;
-    const double duz = Vj.z - Vi.z;
-    const double wix = Wi.x, wiy = Wi.y, wiz = Wi.z + 0.5 * gd;
-    const double wjx = Wj.x, wjy = Wj.y, wjz = Wj.z + 0.5 * gd;
+    // ---------------- FP64 in both modes: gap, lubrication argument, velocity differences
+    const double h_d = dist - ai_d - aj_d;
+    const double s_d = ai_d + aj_d;
+    double dstar = 2.0 * h_d / s_d;
+    dstar = dstar > 0.0 ? dstar : 0.0;
+    const double g_d = dstar + P.eps_lub;
+    const double gd_d = P.gd;
+    const Real invg = (Real)rcp_nr(g_d);
+    const Real lg = -log_r((Real)g_d);
+    const Real dux = (Real)((Vj.x - gd_d * yj) - (Vi.x - gd_d * yi));
+    const Real duy = (Real)(Vj.y - Vi.y);
+    const Real duz = (Real)(Vj.z - Vi.z);
+    const Real h = (Real)h_d;
+
+    // ---------------- type Real from here
+    const Real dx = (Real)dx_d, dy = (Real)dy_d, dz = (Real)dz_d;
+    const Real inv_d = rcp_r((Real)dist);
+    const Real nx = dx * inv_d, ny = dy * inv_d, nz = dz * inv_d;
+    const Real ai = (Real)ai_d, aj = (Real)aj_d;
+    const Real s = ai + aj;
+    const Real gd = (Real)gd_d;
+    const Real wix = (Real)Wi.x, wiy = (Real)Wi.y, wiz = (Real)(Wi.z + 0.5 * gd_d);
+    const Real wjx = (Real)Wj.x, wjy = (Real)Wj.y, wjz = (Real)(Wj.z + 0.5 * gd_d);
 
     // ---------------- lubrication
-    double dstar = 2.0 * h / s;
-    dstar = dstar > 0.0 ? dstar : 0.0;
-    const double g = dstar + P.eps_lub;
-    const double invg = rcp_nr(g);
-    const double lg = -log(g);
-    const double K = P.k6;
-    const double ai2 = ai * ai, aj2 = aj * aj;
-    const double is = rcp_nr(s);
-    const double is2 = is * is, is3 = is2 * is;
-    const double XA = K * 2.0 * ai2 * aj2 * is3 * invg;
-    const double YA = K * (4.0 / 15.0) * ai * aj * (2.0 * ai2 + ai * aj + 2.0 * aj2) * is3 * lg;
-    const double YBi = -K * (2.0 / 15.0) * ai2 * aj * (4.0 * ai + aj) * is2 * lg;
-    const double YBj = K * (2.0 / 15.0) * ai * aj2 * (ai + 4.0 * aj) * is2 * lg;
-    const double YCii = K * (8.0 / 15.0) * ai2 * ai * aj * is * lg;
-    const double YCij = K * (2.0 / 15.0) * ai2 * aj2 * is * lg;
-    const double YCjj = K * (8.0 / 15.0) * ai * aj2 * aj * is * lg;
+    const Real K = (Real)P.k6;
+    const Real ai2 = ai * ai, aj2 = aj * aj;
+    const Real is = rcp_r(s);
+    const Real is2 = is * is, is3 = is2 * is;
+    const Real XA = K * (Real)2.0 * ai2 * aj2 * is3 * invg;
+    const Real YA = K * (Real)(4.0 / 15.0) * ai * aj * ((Real)2.0 * ai2 + ai * aj + (Real)2.0 * aj2) * is3 * lg;
+    const Real YBi = -K * (Real)(2.0 / 15.0) * ai2 * aj * ((Real)4.0 * ai + aj) * is2 * lg;
+    const Real YBj = K * (Real)(2.0 / 15.0) * ai * aj2 * (ai + (Real)4.0 * aj) * is2 * lg;
+    const Real YCii = K * (Real)(8.0 / 15.0) * ai2 * ai * aj * is * lg;
+    const Real YCij = K * (Real)(2.0 / 15.0) * ai2 * aj2 * is * lg;
+    const Real YCjj = K * (Real)(8.0 / 15.0) * ai * aj2 * aj * is * lg;
     // v = du + s E n, E n = gd/2 (n_y, n_x, 0)
-    const double vx = dux + s * 0.5 * gd * ny;
-    const double vy = duy + s * 0.5 * gd * nx;
-    const double vz = duz;
-    const double vn = vx * nx + vy * ny + vz * nz;
+    const Real vx = dux + s * (Real)0.5 * gd * ny;
+    const Real vy = duy + s * (Real)0.5 * gd * nx;
+    const Real vz = duz;
+    const Real vn = vx * nx + vy * ny + vz * nz;
     // n x w'
-    const double cix = ny * wiz - nz * wiy, ciy = nz * wix - nx * wiz, ciz = nx * wiy - ny * wix;
-    const double cjx = ny * wjz - nz * wjy, cjy = nz * wjx - nx * wjz, cjz = nx * wjy - ny * wjx;
-    double FLx = XA * vn * nx + YA * (vx - vn * nx) - YBi * cix + YBj * cjx;
-    double FLy = XA * vn * ny + YA * (vy - vn * ny) - YBi * ciy + YBj * cjy;
-    double FLz = XA * vn * nz + YA * (vz - vn * nz) - YBi * ciz + YBj * cjz;
+    const Real cix = ny * wiz - nz * wiy, ciy = nz * wix - nx * wiz, ciz = nx * wiy - ny * wix;
+    const Real cjx = ny * wjz - nz * wjy, cjy = nz * wjx - nx * wjz, cjz = nx * wjy - ny * wjx;
+    const Real FLx = XA * vn * nx + YA * (vx - vn * nx) - YBi * cix + YBj * cjx;
+    const Real FLy = XA * vn * ny + YA * (vy - vn * ny) - YBi * ciy + YBj * cjy;
+    const Real FLz = XA * vn * nz + YA * (vz - vn * nz) - YBi * ciz + YBj * cjz;
     // n x v
-    const double nvx = ny * vz - nz * vy, nvy = nz * vx - nx * vz, nvz = nx * vy - ny * vx;
+    const Real nvx = ny * vz - nz * vy, nvy = nz * vx - nx * vz, nvz = nx * vy - ny * vx;
     // T w' = w' - (w'.n) n
-    const double win = wix * nx + wiy * ny + wiz * nz;
-    const double wjn = wjx * nx + wjy * ny + wjz * nz;
-    const double tix = wix - win * nx, tiy = wiy - win * ny, tiz = wiz - win * nz;
-    const double tjx = wjx - wjn * nx, tjy = wjy - wjn * ny, tjz = wjz - wjn * nz;
-    o.Ti[0] = -YBi * nvx - YCii * tix - YCij * tjx;
-    o.Ti[1] = -YBi * nvy - YCii * tiy - YCij * tjy;
-    o.Ti[2] = -YBi * nvz - YCii * tiz - YCij * tjz;
-    o.Tj[0] = YBj * nvx - YCij * tix - YCjj * tjx;
-    o.Tj[1] = YBj * nvy - YCij * tiy - YCjj * tjy;
-    o.Tj[2] = YBj * nvz - YCij * tiz - YCjj * tjz;
+    const Real win = wix * nx + wiy * ny + wiz * nz;
+    const Real wjn = wjx * nx + wjy * ny + wjz * nz;
+    const Real tix = wix - win * nx, tiy = wiy - win * ny, tiz = wiz - win * nz;
+    const Real tjx = wjx - wjn * nx, tjy = wjy - wjn * ny, tjz = wjz - wjn * nz;
+    Real Ti0 = -YBi * nvx - YCii * tix - YCij * tjx;
+    Real Ti1 = -YBi * nvy - YCii * tiy - YCij * tjy;
+    Real Ti2 = -YBi * nvz - YCii * tiz - YCij * tjz;
+    Real Tj0 = YBj * nvx - YCij * tix - YCjj * tjx;
+    Real Tj1 = YBj * nvy - YCij * tiy - YCjj * tjy;
+    Real Tj2 = YBj * nvz - YCij * tiz - YCjj * tjz;
 
     // ---------------- electro-chemical (central): repulsion eq. rep, attraction eq. att
-    const double abar = 2.0 * ai * aj * is;
-    double fe = 0.0;
-    if (P.fer != 0.0) fe -= P.fer_a0 * abar * (h >= 0.0 ? (P.lamd > 0.0 ? exp(-h * P.inv_lamd) : 0.0) : 1.0);
+    const Real abar = (Real)2.0 * ai * aj * is;
+    Real fe = (Real)0.0;
+    if (P.fer != 0.0)
+        fe -= (Real)P.fer_a0 * abar *
+              (h >= (Real)0.0 ? (P.lamd > 0.0 ? exp_r(-h * (Real)P.inv_lamd) : (Real)0.0) : (Real)1.0);
     if (P.ham != 0.0) {
-        const double e = P.eps_vdw * abar;
-        fe += P.ham * abar / (12.0 * ((h >= 0.0 ? h * h : 0.0) + e * e));
+        const Real e = (Real)P.eps_vdw * abar;
+        fe += (Real)P.ham * abar * rcp_r((Real)12.0 * ((h >= (Real)0.0 ? h * h : (Real)0.0) + e * e));
     }
 
     // ---------------- contact eqs. contact0, csi
-    double FCx = 0.0, FCy = 0.0, FCz = 0.0;
-    o.contact = h < 0.0;
+    Real FCx = 0, FCy = 0, FCz = 0;
+    o.contact = h_d < 0.0;
     o.xi[0] = o.xi[1] = o.xi[2] = 0.0;
     if (o.contact) {
         // true relative velocity of the image pair: ambient difference gd r_y along x
-        const double Dx = dux + gd * dy, Dy = duy, Dz = duz;
-        const double un = Dx * nx + Dy * ny + Dz * nz;
-        const double fn = P.kn * h + P.gn * un;
-        const double Fnx = fn * nx, Fny = fn * ny, Fnz = fn * nz;
-        const double sx = ai * Wi.x + aj * Wj.x, sy = ai * Wi.y + aj * Wj.y, sz = ai * Wi.z + aj * Wj.z;
+        const Real Dx = dux + gd * dy, Dy = duy, Dz = duz;
+        const Real un = Dx * nx + Dy * ny + Dz * nz;
+        const Real fn = (Real)P.kn * h + (Real)P.gn * un;
+        const Real Fnx = fn * nx, Fny = fn * ny, Fnz = fn * nz;
+        const Real sx = (Real)(ai_d * Wi.x + aj_d * Wj.x), sy = (Real)(ai_d * Wi.y + aj_d * Wj.y),
+                   sz = (Real)(ai_d * Wi.z + aj_d * Wj.z);
         // (a_i w_i + a_j w_j) x n
-        const double qx = sy * nz - sz * ny, qy = sz * nx - sx * nz, qz = sx * ny - sy * nx;
-        const double tx = Dx - qx, ty = Dy - qy, tz = Dz - qz;
-        const double tn = tx * nx + ty * ny + tz * nz;
-        double xx = xo[0] + (tx - tn * nx) * P.dt;
-        double xy = xo[1] + (ty - tn * ny) * P.dt;
-        double xz = xo[2] + (tz - tn * nz) * P.dt;
-        const double xn = xx * nx + xy * ny + xz * nz;
+        const Real qx = sy * nz - sz * ny, qy = sz * nx - sx * nz, qz = sx * ny - sy * nx;
+        const Real tx = Dx - qx, ty = Dy - qy, tz = Dz - qz;
+        const Real tn = tx * nx + ty * ny + tz * nz;
+        const Real dtR = (Real)P.dt;
+        Real xx = (Real)xo[0] + (tx - tn * nx) * dtR;
+        Real xy = (Real)xo[1] + (ty - tn * ny) * dtR;
+        Real xz = (Real)xo[2] + (tz - tn * nz) * dtR;
+        const Real xn = xx * nx + xy * ny + xz * nz;
         xx -= xn * nx;
         xy -= xn * ny;
         xz -= xn * nz;
-        double Ftx = 0.0, Fty = 0.0, Ftz = 0.0;
+        Real Ftx = 0, Fty = 0, Ftz = 0;
         if (P.kt > 0.0) {
-            const double cap = P.mu * fabs(fn) / P.kt;
-            const double xm = sqrt(xx * xx + xy * xy + xz * xz);
-            if (xm >= cap && xm > 0.0) {
-                const double sc = cap / xm;
+            const Real cap = (Real)P.mu * fabs(fn) * (Real)(1.0 / P.kt);
+            const Real xm = sqrt_r(xx * xx + xy * xy + xz * xz);
+            if (xm >= cap && xm > (Real)0.0) {
+                const Real sc = cap * rcp_r(xm);
                 xx *= sc;
                 xy *= sc;
                 xz *= sc;
             }
-            Ftx = P.kt * xx;
-            Fty = P.kt * xy;
-            Ftz = P.kt * xz;
+            Ftx = (Real)P.kt * xx;
+            Fty = (Real)P.kt * xy;
+            Ftz = (Real)P.kt * xz;
         } else {
-            xx = xy = xz = 0.0;
+            xx = xy = xz = 0;
         }
         o.xi[0] = xx;
         o.xi[1] = xy;
@@ -537,27 +564,33 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double dx, doub
         FCy = Fny + Fty;
         FCz = Fnz + Ftz;
         // T_i = a_i n x F_t, T_j = a_j n x F_t
-        const double mx = ny * Ftz - nz * Fty, my = nz * Ftx - nx * Ftz, mz = nx * Fty - ny * Ftx;
-        o.Ti[0] += ai * mx;
-        o.Ti[1] += ai * my;
-        o.Ti[2] += ai * mz;
-        o.Tj[0] += aj * mx;
-        o.Tj[1] += aj * my;
-        o.Tj[2] += aj * mz;
+        const Real mx = ny * Ftz - nz * Fty, my = nz * Ftx - nx * Ftz, mz = nx * Fty - ny * Ftx;
+        Ti0 += ai * mx;
+        Ti1 += ai * my;
+        Ti2 += ai * mz;
+        Tj0 += aj * mx;
+        Tj1 += aj * my;
+        Tj2 += aj * mz;
     }
-    const double Fex = fe * nx, Fey = fe * ny, Fez = fe * nz;
+    const Real Fex = fe * nx, Fey = fe * ny, Fez = fe * nz;
     o.Fi[0] = FLx + FCx + Fex;
     o.Fi[1] = FLy + FCy + Fey;
     o.Fi[2] = FLz + FCz + Fez;
+    o.Ti[0] = Ti0;
+    o.Ti[1] = Ti1;
+    o.Ti[2] = Ti2;
+    o.Tj[0] = Tj0;
+    o.Tj[1] = Tj1;
+    o.Tj[2] = Tj2;
     // stresslet r (x) F_i of the pair, the lubrication part symmetrised (eq. stresslet)
     {
-        const double r[3] = {dx, dy, dz};
-        const double FL[3] = {FLx, FLy, FLz};
-        const double FO[3] = {FCx + Fex, FCy + Fey, FCz + Fez};
+        const Real r[3] = {dx, dy, dz};
+        const Real FL[3] = {FLx, FLy, FLz};
+        const Real FO[3] = {FCx + Fex, FCy + Fey, FCz + Fez};
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) S[3 * a + b] += 0.5 * (r[a] * FL[b] + r[b] * FL[a]) + r[a] * FO[b];
+            for (int b = 0; b < 3; ++b) S[3 * a + b] += (double)((Real)0.5 * (r[a] * FL[b] + r[b] * FL[a]) + r[a] * FO[b]);
     }
 }
 
@@ -633,6 +666,7 @@ __device__ __forceinline__ void shell_window(const DevParams &P, int r, int cx, 
 // Evaluate one listed pair (i at slot gi, j at slot gj): history lookup (stored stretch
 // of this pair in the row of either particle, canonical orientation min id -> max id) and
 // the pair physics.
+template <typename Real>
 __device__ __forceinline__ void evaluate_pair(const DevParams &P, const HistView &H, int gi, int gj, int idi, int idj,
                                               const double4 &Xi, const double4 &Xj, const double4 &Vi,
                                               const double4 &Wi, const double4 &Vj, const double4 &Wj, double dx,
@@ -651,7 +685,7 @@ __device__ __forceinline__ void evaluate_pair(const DevParams &P, const HistView
             xo[2] = -xo[2];
         }
     }
-    pair_physics(P, dx, dy, dz, dist, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, S, o);
+    pair_physics<Real>(P, dx, dy, dz, dist, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, S, o);
 }
 
 __device__ __forceinline__ void record_pair(const DevParams &P, int idi, int idj, int *pair_out,
@@ -777,6 +811,7 @@ struct PairTally {
 // shell of particle i, keeps its own side in registers (stored into its own record) and
 // adds the partner side atomically to ft_x.
 // ----------------------------------------------------------------------------------
+template <typename Real>
 __device__ void particle_pairs_global(const DevParams &P, int i, double delta, const int *__restrict__ cell_start,
                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                       const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
@@ -822,7 +857,7 @@ __device__ void particle_pairs_global(const DevParams &P, int i, double delta, c
                 ++tally.npair;
                 if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
                 PairOut o;
-                evaluate_pair(P, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
+                evaluate_pair<Real>(P, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     f[k] += o.Fi[k];
@@ -897,6 +932,7 @@ __device__ __forceinline__ void reduce_tally(PairTally &tally, double (*red)[12]
 struct TileShared {
     int rs[5], re[5], ro[6], rbase[5], rcross[5];
     int qn;
+    int ovf;            // tile overflow: the row is redone on the per-particle path
     int wsum[kBlock / 64];
     double red[kBlock / 64][12];
 };
@@ -916,6 +952,7 @@ __host__ __device__ inline size_t tile_lds_bytes(int own_cap, int stage_cap, int
            (size_t)(5 * own_cap + 1) * 4 + (size_t)own_cap * 4;
 }
 
+template <typename Real>
 __device__ __forceinline__ void tile_pair(const DevParams &P, const HistView &H, const TileShared &T,
                                           const TileView &V, int il, int jl, double delta,
                                           const double4 *__restrict__ vel, const double4 *__restrict__ omg,
@@ -938,7 +975,7 @@ __device__ __forceinline__ void tile_pair(const DevParams &P, const HistView &H,
     ++tally.npair;
     if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
     PairOut o;
-    evaluate_pair(P, H, gi, gj, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy, dz, r2, tally.S, o);
+    evaluate_pair<Real>(P, H, gi, gj, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy, dz, r2, tally.S, o);
     double *ai = V.acc + 6 * il;
     double *aj = V.acc + 6 * jl;
     atomicAdd(ai + 0, o.Fi[0]);
@@ -960,6 +997,7 @@ __device__ __forceinline__ void tile_pair(const DevParams &P, const HistView &H,
     }
 }
 
+template <typename Real>
 __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__restrict__ cell_start,
                                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                                       const double4 *__restrict__ omg, ForceBufs B, HistView H,
@@ -1010,18 +1048,23 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
         }
         T.ro[5] = o;
         T.qn = 0;
+        T.ovf = 0;
     }
     __syncthreads();
     const int n_own = T.re[0] - T.rs[0];
     const int total = T.ro[5];
-    if (n_own > P.own_cap || total > P.stage_cap) {
-        // tile does not fit: per-particle path; the partner records of this row stay zero
+    // per-particle path for this row (tile too large, or a tile limit was hit below); the
+    // partner records of the row are zero, partners receive atomic additions instead
+    auto row_fallback = [&]() {
         for (int i = T.rs[0] + t; i < T.re[0]; i += kBlock)
-            particle_pairs_global(P, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, tally);
+            particle_pairs_global<Real>(P, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, tally);
         const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int r = 1; r < 5; ++r)
             for (int g = T.rs[r] + t; g < T.re[r]; g += kBlock) store_ft(B.nb + 6LL * ((r - 1) * B.n + g), z);
         reduce_tally(tally, T.red, partials, P.pstride);
+    };
+    if (n_own > P.own_cap || total > P.stage_cap) {
+        row_fallback();
         return;
     }
     // stage the shell rows
@@ -1033,7 +1076,11 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
     for (int k = t; k < n_own; k += kBlock) V.rowcnt[k] = 0;
     __syncthreads();
 
-    // A1: candidate ranges of every (particle, shell row) task, as LDS indices
+    // A1: candidate ranges of every (particle, shell row) task, as LDS indices, with the
+    // periodic image of each range: a range word holds start (16 bits), length (11 bits)
+    // and w + 4 (3 bits), w = the number of box lengths L_x the range's cells lie beyond
+    // the row; the first word also holds the y-face crossing + 1 (bits 30-31), the second
+    // whether the row is reached across the z face (bit 30).
     const int ntask = 5 * n_own;
     for (int task = t; task < ntask; task += kBlock) {
         const int r = task / n_own;
@@ -1041,7 +1088,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
         const int cx = cell_coord(V.sp[il].x, P.cw[0], nxc);
         int xlo, xhi;
         shell_window(P, r, cx, T.rcross[r], delta, xlo, xhi);
-        int xl = ((xlo % nxc) + nxc) % nxc;
+        int w = xlo >= 0 ? xlo / nxc : -((-xlo + nxc - 1) / nxc);  // floor(xlo / nx)
+        int xl = xlo - w * nxc;
         int span = xhi - xlo + 1;
         unsigned rng[2] = {0u, 0u};
         int cnt = 0;
@@ -1051,11 +1099,16 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
             const int je = cell_start[T.rbase[r] + xl + len];
             if (r == 0 && part == 0) jb = T.rs[0] + il + 1;
             const int n = je > jb ? je - jb : 0;
-            rng[part] = (unsigned)(T.ro[r] + (jb - T.rs[r])) | ((unsigned)n << 16);
+            if (n > 2047) T.ovf = 1;
+            rng[part] = (unsigned)(T.ro[r] + (jb - T.rs[r])) | ((unsigned)(n & 2047) << 16) |
+                        ((unsigned)(w + 4) << 27);
             cnt += n;
             xl = 0;
             span -= len;
+            ++w;
         }
+        rng[0] |= (unsigned)(T.rcross[r] + 1) << 30;
+        if (r >= 2 && cz == nzc - 1) rng[1] |= 1u << 30;
         V.trange[task] = make_uint2(rng[0], rng[1]);
         V.tpre[task] = cnt;
     }
@@ -1090,7 +1143,10 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
     }
     __syncthreads();
 
-    // A2: every lane tests an equal, contiguous share of all candidates of the tile
+    // A2: every lane tests an equal, contiguous share of all candidates of the tile.  The
+    // image of a candidate is known from its range, so the nearest-image vector is the
+    // difference plus the range's shifts, added in the order and with the values of the
+    // general formula (same IEEE result for every listed pair, no data-dependent branch).
     {
         const int C = V.tpre[ntask];
         const int chunk = (C + kBlock - 1) / kBlock;
@@ -1103,43 +1159,71 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
                 if (V.tpre[mid] <= k0) lo = mid; else hi = mid;
             }
             int task = lo;
-            int il = task % n_own;
-            double4 Xi = V.sp[il];
-            uint2 rg = V.trange[task];
-            int tb = V.tpre[task], te = V.tpre[task + 1];
+            int il = 0, tb = 0, te = 0, len0 = 0, j0 = 0, j1 = 0;
+            double4 Xi;
+            double sy = 0.0, sxd = 0.0, sz = 0.0, sx0 = 0.0, sx1 = 0.0;
+            bool fresh = true;
             for (int k = k0; k < k1; ++k) {
-                if (k >= te) {
-                    do {
-                        ++task;
-                        tb = V.tpre[task];
-                        te = V.tpre[task + 1];
-                    } while (k >= te);
+                if (fresh || k >= te) {
+                    if (!fresh) {
+                        do {
+                            ++task;
+                        } while (k >= V.tpre[task + 1]);
+                    }
+                    fresh = false;
+                    tb = V.tpre[task];
+                    te = V.tpre[task + 1];
                     il = task % n_own;
                     Xi = V.sp[il];
-                    rg = V.trange[task];
+                    const uint2 rg = V.trange[task];
+                    len0 = (int)((rg.x >> 16) & 2047u);
+                    j0 = (int)(rg.x & 0xffffu);
+                    j1 = (int)(rg.y & 0xffffu);
+                    const int cross = (int)(rg.x >> 30) - 1;
+                    sy = cross > 0 ? P.L[1] : (cross < 0 ? -P.L[1] : 0.0);
+                    sxd = cross > 0 ? delta : (cross < 0 ? -delta : 0.0);
+                    sx0 = (double)((int)((rg.x >> 27) & 7u) - 4) * P.L[0];
+                    sx1 = (double)((int)((rg.y >> 27) & 7u) - 4) * P.L[0];
+                    sz = (rg.y >> 30) ? P.L[2] : 0.0;
                 }
                 const int o = k - tb;
-                const int len0 = (int)(rg.x >> 16);
-                const int jl = o < len0 ? (int)(rg.x & 0xffffu) + o : (int)(rg.y & 0xffffu) + (o - len0);
+                const bool second = o >= len0;
+                const int jl = second ? j1 + (o - len0) : j0 + o;
                 const double4 Xj = V.sp[jl];
                 double dx, dy, dz, r2;
-                min_image(P, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy, dz);
+                {
+#pragma clang fp contract(off)
+                    dx = Xj.x - Xi.x;
+                    dy = Xj.y - Xi.y;
+                    dz = Xj.z - Xi.z;
+                    dy = dy + sy;
+                    dx = dx + sxd;
+                    dx = dx + (second ? sx1 : sx0);
+                    dz = dz + sz;
+                }
                 if (!listed(P, dx, dy, dz, Xi.w, Xj.w, r2)) continue;
                 const int q = atomicAdd(&T.qn, 1);
                 if (q < P.qcap)
                     V.queue[q] = ((unsigned)il << 16) | (unsigned)jl;
-                else  // queue full: evaluate now
-                    tile_pair(P, H, T, V, il, jl, delta, vel, omg, clk, pair_out, pair_count, tally);
+                else
+                    T.ovf = 1;
             }
         }
     }
     __syncthreads();
+    if (T.ovf) {
+        // a tile limit was hit: discard the tile and redo the row on the per-particle path
+        for (int k = t; k < n_own; k += kBlock) V.rowcnt[k] = 0;
+        row_fallback();
+        return;
+    }
 
     // B: evaluate the queued pairs
-    const int nq = T.qn < P.qcap ? T.qn : P.qcap;
+    const int nq = T.qn;
     for (int q = t; q < nq; q += kBlock) {
         const unsigned e = V.queue[q];
-        tile_pair(P, H, T, V, (int)(e >> 16), (int)(e & 0xffffu), delta, vel, omg, clk, pair_out, pair_count, tally);
+        tile_pair<Real>(P, H, T, V, (int)(e >> 16), (int)(e & 0xffffu), delta, vel, omg, clk, pair_out, pair_count,
+                        tally);
     }
     __syncthreads();
 

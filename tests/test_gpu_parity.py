@@ -314,3 +314,54 @@ def test_abi_errors():
     sim.step(1)
     assert sim.info()["max_row_fill"] >= 2
     sim.close()
+
+
+# ---------------------------------------------------------------------------------------------
+# Mixed precision (FP32 pair arithmetic, FP64 gap / lubrication argument / accumulation):
+# pair sets and positions still bit-identical; forces, torques, stress and history within
+# 1e-5 of the FP64 oracle.  The measured errors are printed per result.
+# ---------------------------------------------------------------------------------------------
+TOL_MIXED = 1e-5
+
+
+def _mixed_errors(p, sim, rad, hp, hx, nstep):
+    st, s0 = oracle_state_from_gpu(p, sim, rad, hp, hx, nstep)
+    x_o = oracle.kick_drift(p, st)[0]
+    sim.step(1)
+    s1 = sim.state()
+    uh, wh = sim.eval_velocities()
+    assert np.array_equal(s1["x"], x_o)
+    po = oracle.pairs_cells(p, s1["x"], rad, oracle.le_offset(p, nstep + 1))
+    assert np.array_equal(sim.pairs(), po)
+    F, T, S, H, npairs = oracle.forces(p, s1["x"], uh, wh, rad, nstep + 1, st.history, use_cells=True)
+    last, _, _ = sim.read_stress()
+    hp2, hx2 = sim.history()
+    assert np.array_equal(hp2, H.pairs)
+    err = {"F": rel_inf(s1["F"], F), "T": rel_inf(s1["T"], T), "Sigma": rel_inf(last, S),
+           "eta_r": abs(last[0, 1] - S[0, 1]) / abs(S[0, 1]),
+           "xi": float(np.max(np.abs(hx2 - H.xi)) / max(np.max(np.abs(H.xi)), 1e-300)) if len(hx2) else 0.0}
+    return err, hp2, hx2
+
+
+@pytest.mark.parametrize("which", ["small", "100k"])
+def test_mixed_precision_parity(which):
+    from paper_2108_01013_amd.dss import DSS_MIXED
+    w = synth.config_small() if which == "small" else synth.config_single_box()
+    p = w.params
+    say(f"case: mixed precision {which}")
+    sim = _sim(p, precision=DSS_MIXED, record_pairs=True)
+    sim.set_particles(w.x, w.rad)
+    sim.step(5)
+    hp, hx = sim.history()
+    worst = {}
+    nstep = 5
+    for k in range(3):
+        err, hp, hx = _mixed_errors(p, sim, w.rad, hp, hx, nstep)
+        nstep += 1
+        for key, v in err.items():
+            worst[key] = max(worst.get(key, 0.0), v)
+    say(f"mixed precision max relative errors ({which}, N={len(w.rad)}): " +
+        ", ".join(f"{k}={v:.2e}" for k, v in worst.items()))
+    for key in ("F", "T", "Sigma", "eta_r", "xi"):
+        assert worst[key] < TOL_MIXED, (key, worst[key])
+    sim.close()
