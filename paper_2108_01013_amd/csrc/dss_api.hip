@@ -5,7 +5,8 @@
 //   k_scan     exclusive scan of the cell counts -> cell_start, clock advance
 //   k_scatter  reorder into the new sorted order, id -> slot map, clear force accumulators
 //   k_pairs    half-shell search, pair physics, new history rows, per-workgroup stress partials
-//   k_finish   stress and counters from the partials, stress sample
+//   k_finish   stress and counters from the partials, stress sample (only on steps that take
+//              a stress sample and on the last step of a dss_step call)
 // The history rows written by k_pairs become the committed history of the step.
 #include <hip/hip_runtime.h>
 
@@ -205,7 +206,7 @@ dss_status require_loaded(dss_handle *h)
 //   EVAL_INPLACE: pairs at the current state and order (velocities completed to u^n).
 enum EvalMode { EVAL_STEP = 0, EVAL_SORT = 1, EVAL_INPLACE = 2 };
 
-dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample)
+dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, bool finish)
 {
     HistView H;
     H.key_old = h->hkey[h->hh];
@@ -228,6 +229,7 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample)
                                h->P, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(), H, h->clk,
                                h->partials, h->pairs, h->pair_count);
     }
+    if (!finish) return DSS_OK;
     TimedLaunch t(h, 4);
     switch (h->finish_r) {
     case 1: hipLaunchKernelGGL(k_finish<1>, dim3(1), dim3(1024), 0, h->stream, h->partials, h->clk, h->run, sample); break;
@@ -239,7 +241,7 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample)
     return DSS_OK;
 }
 
-dss_status evaluate(dss_handle *h, EvalMode mode)
+dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
 {
     const int N = (int)h->N;
     const int grid = (N + kBlock - 1) / kBlock;
@@ -252,7 +254,7 @@ dss_status evaluate(dss_handle *h, EvalMode mode)
                                h->omg[c], h->fb());
         }
         HIPTRY(hipMemsetAsync(h->ft_x, 0, 6 * h->N * sizeof(double), h->stream));
-        dss_status s = launch_pairs(h, c, nullptr, 0);
+        dss_status s = launch_pairs(h, c, nullptr, 0, true);
         if (s) return s;
         HIPTRY(hipGetLastError());
         h->vel_is_half = false;
@@ -282,7 +284,7 @@ dss_status evaluate(dss_handle *h, EvalMode mode)
         hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, h->stream, N, h->cell, h->rank, h->cell_start,
                            h->pa[c], h->vel[c], h->omg[c], h->pa[o], h->vel[o], h->omg[o], h->ft_x, h->prev);
     }
-    dss_status s = launch_pairs(h, o, h->prev, advance);
+    dss_status s = launch_pairs(h, o, h->prev, advance, finish);
     if (s) return s;
     HIPTRY(hipGetLastError());
     h->cur = o;
@@ -588,7 +590,10 @@ dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sy
     HIPTRY(hipMemcpyAsync(h->run, &h->run_host, sizeof(DevRun), hipMemcpyHostToDevice, h->stream));
     h->last_samples = cap;
     for (int64_t k = 0; k < n_steps; ++k) {
-        s = evaluate(h, EVAL_STEP);
+        // the stress and counters are summed only when a sample is due and after the last step
+        const int64_t n_next = h->step + 1;
+        const bool finish = k == n_steps - 1 || (stress_every > 0 && n_next % stress_every == 0);
+        s = evaluate(h, EVAL_STEP, finish);
         if (s) return s;
     }
     if (sync) return check_flags(h);
