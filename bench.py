@@ -33,9 +33,7 @@ def pairs_kernel_bytes(N: int, ncell: int, contacts: int, capacity: int) -> floa
     return N * (3 * 32 + 2 * 32 + 4 + 4 + 8) + 4.0 * (ncell + 1) + contacts * (28 + 28)
 
 
-def cpu_baseline(w, seconds: float = 10.0):
-    import numpy as np  # noqa: F401
-
+def cpu_baseline(w, seconds: float = 10.0, label: str = "the same"):
     import oracle
     p = w.params
     threads = oracle.num_threads()
@@ -50,8 +48,136 @@ def cpu_baseline(w, seconds: float = 10.0):
             break
     N = len(w.rad)
     return {"value": N * steps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} FP64 oracle steps (cell-list pair search, OpenMP) of the same N={N} "
-                      f"phi=0.55 workload, {el:.1f} s"}
+            "sample": f"{steps} FP64 oracle steps (cell-list pair search, OpenMP) of {label} workload "
+                      f"(N={N}), {el:.1f} s"}
+
+
+def timed_run(sim, N, args, stress_every):
+    """Warm-up, then the timed region with HIP events around k_pairs; then an untimed
+    per-kernel breakdown.  Returns (seconds, k_pairs timing, breakdown)."""
+    import torch
+    sim.step(args.warmup, stress_every=stress_every, sync=True)
+    torch.cuda.synchronize()
+    sim.set_timing(True, kernels=["k_pairs"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps, stress_every=stress_every, sync=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    timing = sim.timing()
+    sim.set_timing(True)
+    sim.step(min(args.steps, 50), stress_every=stress_every, sync=True)
+    breakdown = sim.timing()
+    sim.set_timing(False)
+    return el, timing, breakdown
+
+
+def roofline(timing, N, ncell, contacts, capacity):
+    ms_pairs, n_pairs_launch = timing["k_pairs"]
+    avg_pairs_s = ms_pairs / max(n_pairs_launch, 1) * 1e-3
+    bytes_launch = pairs_kernel_bytes(N, ncell, contacts, capacity)
+    achieved = bytes_launch / avg_pairs_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": "k_pairs", "avg_launch_us": round(avg_pairs_s * 1e6, 3),
+            "bytes_per_launch": int(bytes_launch)}
+
+
+def kernel_table(breakdown):
+    return {k: {"avg_us": round(v[0] / max(v[1], 1) * 1e3, 3), "launches": v[1]} for k, v in breakdown.items()
+            if v[1] > 0}
+
+
+def run_single(args):
+    from paper_2108_01013_amd import synth
+
+    t_gen = time.perf_counter()
+    w = synth.config_single_box(N=args.N)
+    print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    import torch
+
+    from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Simulation
+    prec = DSS_FP64 if args.precision == "fp64" else DSS_MIXED
+    torch.cuda.set_device(0)
+    p = w.params
+    sim = Simulation(p, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
+    sim.set_particles(w.x, w.rad)
+    N = len(w.rad)
+    el, timing, breakdown = timed_run(sim, N, args, 10)
+    info = sim.info()
+    _, sigma_mean, nsamp = sim.read_stress()
+    if info["error_flags"]:
+        print(f"# device error flags {info['error_flags']}", file=sys.stderr)
+        sys.exit(1)
+    ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2])
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_seconds, "the same N=100k phi=0.55")
+    return {
+        "metric": "particle-steps/s at N=100k phi=0.55; mixed/batched/adjoint vs plain FP64",
+        "value": round(N * args.steps / el, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"single box N={N} bidisperse 1:1.4 equal volume, phi=0.55, LE shear rate 1, "
+                               f"mu=1, dt=1e-4, stress every 10 steps, {args.precision}",
+                   "N": N, "phi": 0.55, "precision": args.precision},
+        "roofline": roofline(timing, N, ncell, info["n_contacts"], info["capacity"]),
+        "cpu_baseline": cpu,
+        "kernels": kernel_table(breakdown),
+        "diagnostics": {"n_pairs": info["n_pairs"], "n_contacts": info["n_contacts"],
+                        "max_row_fill": info["max_row_fill"], "capacity": info["capacity"],
+                        "cells": info["cells"], "stress_samples": nsamp,
+                        "eta_r_mean": float(sigma_mean[0, 1] / (p["eta0"] * p["shear_rate"]))},
+    }
+
+
+def run_sweep(args):
+    import numpy as np
+
+    from paper_2108_01013_amd import synth
+
+    # the boxes are relaxed in a process pool, before anything loads the HIP runtime
+    t_gen = time.perf_counter()
+    ws, gds = synth.config_sweep(B=args.boxes, workers=args.workers)
+    print(f"# {len(ws)} boxes generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    import torch
+
+    from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Batch
+    prec = DSS_FP64 if args.precision == "fp64" else DSS_MIXED
+    torch.cuda.set_device(0)
+    params = [dict(w.params, shear_rate=g) for w, g in zip(ws, gds)]
+    sim = Batch(params, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
+    sim.set_particles([w.x for w in ws], [w.rad for w in ws])
+    N = sim.N
+    el, timing, breakdown = timed_run(sim, N, args, 10)
+    info = sim.info()
+    _, sigma_mean, nsamp = sim.read_stress()
+    if info["error_flags"]:
+        print(f"# device error flags {info['error_flags']}", file=sys.stderr)
+        sys.exit(1)
+    boxes = [sim.box_info(b) for b in range(sim.B)]
+    ncell = int(sum(np.prod(b["cells"]) for b in boxes))
+    eta = [float(sigma_mean[b, 0, 1] / (params[b]["eta0"] * gds[b])) for b in range(sim.B)]
+    mid = min(range(len(ws)), key=lambda b: abs(len(ws[b].rad) - 20_000))
+    cpu = None if args.no_cpu_baseline else cpu_baseline(ws[mid], args.cpu_seconds,
+                                                         f"box {mid} of the sweep (phi={synth.SWEEP_PHI[mid % 5]})")
+    return {
+        "metric": "particle-steps/s, batched flow-curve sweep",
+        "value": round(N * args.steps / el, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{sim.B} boxes, N_b uniform on 2000..50000 (sum {N}), phi_b in "
+                               f"{list(synth.SWEEP_PHI)}, shear rate 1e-2..1e1, bidisperse 1:1.4, mu=1, "
+                               f"dt=1e-4, stress every 10 steps, {args.precision}",
+                   "boxes": sim.B, "N": N, "precision": args.precision},
+        "roofline": roofline(timing, N, ncell, info["n_contacts"], info["capacity"]),
+        "cpu_baseline": cpu,
+        "kernels": kernel_table(breakdown),
+        "diagnostics": {"n_pairs": info["n_pairs"], "n_contacts": info["n_contacts"],
+                        "max_row_fill": info["max_row_fill"], "capacity": info["capacity"],
+                        "cells_total": ncell, "stress_samples": nsamp,
+                        "eta_r_mean": [round(e, 4) for e in eta]},
+    }
 
 
 def main():
@@ -60,7 +186,11 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--mode", choices=["single", "sweep"], default="single",
+                    help="single: one box of N particles; sweep: the batched flow-curve sweep")
     ap.add_argument("--N", type=int, default=100_000)
+    ap.add_argument("--boxes", type=int, default=64)
+    ap.add_argument("--workers", type=int, default=16, help="processes generating the sweep's boxes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
@@ -70,73 +200,7 @@ def main():
               "z-slab decomposition is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-
-    from paper_2108_01013_amd import synth
-    from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Simulation
-
-    torch.cuda.set_device(0)
-    t_gen = time.perf_counter()
-    w = synth.config_single_box(N=args.N)
-    print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
-    p = w.params
-    prec = DSS_FP64 if args.precision == "fp64" else DSS_MIXED
-    sim = Simulation(p, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
-    sim.set_particles(w.x, w.rad)
-    sim.step(args.warmup, stress_every=10, sync=True)
-    torch.cuda.synchronize()
-
-    # timed region: HIP events around the dominant kernel only (k_pairs)
-    sim.set_timing(True, kernels=["k_pairs"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps, stress_every=10, sync=False)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    timing = sim.timing()
-    # per-kernel breakdown, outside the timed region
-    sim.set_timing(True)
-    sim.step(min(args.steps, 50), stress_every=10, sync=True)
-    breakdown = sim.timing()
-    sim.set_timing(False)
-    info = sim.info()
-    _, sigma_mean, nsamp = sim.read_stress()
-    if info["error_flags"]:
-        print(f"# device error flags {info['error_flags']}", file=sys.stderr)
-        sys.exit(1)
-
-    N = len(w.rad)
-    value = N * args.steps / el
-    ms_pairs, n_pairs_launch = timing["k_pairs"]
-    avg_pairs_s = ms_pairs / max(n_pairs_launch, 1) * 1e-3
-    ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2])
-    bytes_launch = pairs_kernel_bytes(N, ncell, info["n_contacts"], info["capacity"])
-    achieved = bytes_launch / avg_pairs_s / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-            "kernel": "k_pairs", "avg_launch_us": round(avg_pairs_s * 1e6, 3),
-            "bytes_per_launch": int(bytes_launch)}
-    kernels = {k: {"avg_us": round(v[0] / max(v[1], 1) * 1e3, 3), "launches": v[1]} for k, v in breakdown.items()
-               if v[1] > 0}
-
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_seconds)
-    out = {
-        "metric": "particle-steps/s at N=100k phi=0.55; mixed/batched/adjoint vs plain FP64",
-        "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"single box N={N} bidisperse 1:1.4 equal volume, phi=0.55, LE shear rate 1, "
-                               f"mu=1, dt=1e-4, stress every 10 steps, {args.precision}",
-                   "N": N, "phi": 0.55, "precision": args.precision},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "kernels": kernels,
-        "diagnostics": {"n_pairs": info["n_pairs"], "n_contacts": info["n_contacts"],
-                        "max_row_fill": info["max_row_fill"], "capacity": info["capacity"],
-                        "cells": info["cells"], "stress_samples": nsamp,
-                        "eta_r_mean": float(sigma_mean[0, 1] / (p["eta0"] * p["shear_rate"]))},
-    }
+    out = run_single(args) if args.mode == "single" else run_sweep(args)
     print(json.dumps(out), flush=True)
 
 

@@ -95,10 +95,36 @@ typedef struct {
     double le_offset;      /* Lees-Edwards offset delta of the current state */
 } dss_info;
 
+/* Diagnostics of one box of a batch handle (dss_create_batch). */
+typedef struct {
+    int64_t n_particles;
+    int64_t first_id;      /* the box's particles have ids first_id .. first_id + n_particles - 1 */
+    int32_t cells[3];      /* lattice dimensions of the box */
+    int32_t first_cell;    /* index of the box's first cell in the cell_start of dss_get_cells */
+    int64_t n_pairs;       /* listed pairs of the last summed evaluation */
+    int64_t n_contacts;
+    int32_t max_row_fill;
+    int32_t reserved;
+    double L[3];
+    double shear_rate;
+    double le_offset;      /* Lees-Edwards offset of the current state */
+} dss_box_info;
+
 /* Create a handle.  p is copied.  hip_stream: a hipStream_t of the current device, or
  * NULL.  Fails with DSS_ERR_ARG for non-positive L, dt, cutoff_factor, rho or a0, or
  * reserved != 0. */
 dss_status dss_create(const dss_params *p, void *hip_stream, dss_handle **out);
+
+/* Batched flow-curve sweep: one handle advances n_boxes independent boxes together (one
+ * counting sort over the concatenated cell lattices, one pair launch over the cell rows of
+ * every box, one stress tensor per box).  per_box: n_boxes parameter sets that may differ
+ * only in L and shear_rate (each box has its own Lees-Edwards offset, eq. le); every other
+ * field must equal per_box[0], else DSS_ERR_ARG.  A handle from dss_create is the
+ * n_boxes = 1 case.  Particles are loaded with dss_set_particles_batch and the stress is
+ * read with dss_read_stress_batch; every other entry point works on the whole batch with
+ * particle ids running over the boxes in order (box b holds the ids first_id .. of
+ * dss_get_box_info). */
+dss_status dss_create_batch(const dss_params *per_box, int32_t n_boxes, void *hip_stream, dss_handle **out);
 
 /* Load N particles (copy-in) and evaluate the initial forces at t = 0:
  * x: N x 3 positions inside the box; radius: N radii > 0; u, omega: N x 3 initial
@@ -108,6 +134,15 @@ dss_status dss_create(const dss_params *p, void *hip_stream, dss_handle **out);
  * [0, L) or a radius <= 0, DSS_ERR_BOX if the lattice has fewer than 4 x 3 x 3 cells. */
 dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const double *radius, const double *u,
                              const double *omega, int on_device);
+
+/* dss_set_particles for a batch handle: n_per_box[b] >= 1 particles per box, stored box
+ * after box in x, radius, u, omega (same layouts as dss_set_particles, N = the sum).
+ * Positions of box b must lie in its own [0, L_b).  Each box gets its own lattice
+ * (spacing >= 2 cutoff_factor times its largest radius); the history row capacity M is
+ * taken over all particles.  Fails with DSS_ERR_BOX when a box has fewer than 4 x 3 x 3
+ * cells or more than 4096 cell rows (n_y n_z). */
+dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, const double *x, const double *radius,
+                                   const double *u, const double *omega, int on_device);
 
 /* Set the time index n of the current state (t = n dt; the Lees-Edwards offset follows
  * eq. le).  Forces are not re-evaluated: call dss_compute_forces afterwards.  For restarts
@@ -134,6 +169,10 @@ dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sy
  * sum_pairs (S^L + S^C + S^E)), eq. stress, each pair once. */
 dss_status dss_read_stress(dss_handle *h, double *sigma_last, double *sigma_mean, int64_t *n_samples);
 
+/* dss_read_stress for a batch handle: sigma_last and sigma_mean hold n_boxes x 9 values
+ * (box-major), each box's stress with its own volume and shear rate. */
+dss_status dss_read_stress_batch(dss_handle *h, double *sigma_last, double *sigma_mean, int64_t *n_samples);
+
 /* State at the current time index n, by particle id: x^n, u^n, omega^n, F^n, T^n (each
  * N x 3, nullable).  F, T are the totals of the last force evaluation. */
 dss_status dss_get_state(dss_handle *h, double *x, double *u, double *omega, double *F, double *T, int on_device);
@@ -147,16 +186,22 @@ dss_status dss_get_eval_velocities(dss_handle *h, double *u, double *omega, int 
  * DSS_FLAG_RECORD_PAIRS.  *n receives the count; fails with DSS_ERR_CAPACITY if cap < *n. */
 dss_status dss_get_pairs(dss_handle *h, int64_t cap, int32_t *pairs, int64_t *n);
 
-/* Cell lattice of the last counting sort: dims[3], cell_start (n_cells + 1 entries) and
- * perm (N entries: particle id at each sorted position); host pointers. */
+/* Cell lattice of the last counting sort: dims[3] (of box 0), cell_start (n_cells + 1
+ * entries over the cells of every box, box after box) and perm (N entries: particle id at
+ * each sorted position); host pointers. */
 dss_status dss_get_cells(dss_handle *h, int32_t *dims, int64_t cap_cells, int32_t *cell_start, int32_t *perm);
 
 /* Contact history after the last step: pairs (id_min, id_max) and xi (3 per pair, the
  * tangential stretch oriented from id_min to id_max), unordered; host pointers. */
 dss_status dss_get_history(dss_handle *h, int64_t cap, int32_t *pairs, double *xi, int64_t *n);
 
-/* Diagnostics of the most recent force evaluation (synchronises). */
+/* Diagnostics of the most recent force evaluation (synchronises).  For a batch handle the
+ * counts are summed over the boxes (max_row_fill: the largest), cells and le_offset are
+ * those of box 0. */
 dss_status dss_get_info(dss_handle *h, dss_info *info);
+
+/* Diagnostics of box `box` (0 <= box < n_boxes) after the last summed evaluation. */
+dss_status dss_get_box_info(dss_handle *h, int32_t box, dss_box_info *info);
 
 /* Bytes needed by dss_save_state (nullable blob: size query) / restore of a snapshot. */
 dss_status dss_save_state(dss_handle *h, void *blob, size_t *bytes);

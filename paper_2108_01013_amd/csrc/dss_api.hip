@@ -23,8 +23,19 @@
 using namespace dss;
 
 struct dss_handle {
-    dss_params prm{};
+    dss_params prm{};          // parameters of box 0 (the physical constants of every box)
     DevParams P{};
+    int nbox = 1;
+    std::vector<dss_params> bprm;     // per box (boxes differ only in L and shear_rate)
+    std::vector<BoxParams> boxes;     // per box, host copy of the device table
+    std::vector<int64_t> box_n;       // particles per box
+    std::vector<double> box_sa3;      // sum of a^3 per box
+    BoxParams *d_boxes = nullptr;
+    int *d_row_box = nullptr;         // cell row -> box
+    double *box_diag = nullptr;       // nbox x 3: listed pairs, contacts, largest history row
+    int *tile_sum = nullptr;          // totals of the multi-workgroup scan
+    int ncell_total = 0, nrow_total = 0;
+    int scan_tiles = 0;               // 0: one-workgroup scan (scan_c4), else workgroups of 16384 cells
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
@@ -36,7 +47,6 @@ struct dss_handle {
     int cur = 0;               // particle buffers holding the current state
     int hh = 0;                // history buffers holding the committed history
     int64_t step = 0;          // host mirror of the time index
-    double sum_a3 = 0.0;
 
     double4 *pa[2] = {nullptr, nullptr}, *vel[2] = {nullptr, nullptr}, *omg[2] = {nullptr, nullptr};
     double *ft_own = nullptr, *ft_nb = nullptr, *ft_x = nullptr;  // force records (ForceBufs)
@@ -116,6 +126,10 @@ void free_all(dss_handle *h)
     F(h->ft_own); F(h->ft_nb); F(h->ft_x); F(h->prev);
     F(h->cell); F(h->rank); F(h->count); F(h->cell_start);
     F(h->pairs); F(h->pair_count); F(h->clk); F(h->run); F(h->sigma_last); F(h->samples); F(h->partials);
+    F(h->d_boxes); F(h->d_row_box); F(h->box_diag); F(h->tile_sum);
+    h->d_boxes = nullptr;
+    h->d_row_box = h->tile_sum = nullptr;
+    h->box_diag = nullptr;
     h->ft_own = h->ft_nb = h->ft_x = nullptr;
     h->prev = nullptr;
     h->cell = h->rank = h->count = h->cell_start = h->pairs = nullptr;
@@ -136,15 +150,30 @@ int paper_capacity(double a_max, double a_min)
     return (int)std::ceil(shell / (a_min * a_min * a_min));
 }
 
+// Per-box counters of the last summed evaluation (nbox x 3).
+dss_status read_diag(dss_handle *h, std::vector<double> &d)
+{
+    d.assign(3 * (size_t)h->nbox, 0.0);
+    HIPTRY(hipMemcpyAsync(d.data(), h->box_diag, d.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    return DSS_OK;
+}
+
 dss_status check_flags(dss_handle *h)
 {
     DevClock c;
     HIPTRY(hipMemcpyAsync(&c, h->clk, sizeof(c), hipMemcpyDeviceToHost, h->stream));
     HIPTRY(hipStreamSynchronize(h->stream));
     if (c.err & kErrNonFinite) return fail(h, DSS_ERR_UNSTABLE, "non-finite force or torque");
-    if (c.err & kErrRowOverflow)
-        return fail(h, DSS_ERR_CAPACITY, "contact-history row overflow (max fill " + std::to_string(c.max_fill) +
+    if (c.err & kErrRowOverflow) {
+        std::vector<double> d;
+        dss_status s = read_diag(h, d);
+        if (s) return s;
+        double mf = 0.0;
+        for (int b = 0; b < h->nbox; ++b) mf = std::max(mf, d[3 * b + 2]);
+        return fail(h, DSS_ERR_CAPACITY, "contact-history row overflow (max fill " + std::to_string((int)mf) +
                                              ", capacity " + std::to_string(h->P.M) + ")");
+    }
     return DSS_OK;
 }
 
@@ -221,23 +250,27 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, boo
     {
         TimedLaunch t(h, 3);
         if (h->prm.precision == DSS_MIXED)
-            hipLaunchKernelGGL(k_pairs<float>, dim3(h->P.nc[1] * h->P.nc[2]), dim3(kBlock), h->tile_lds, h->stream,
-                               h->P, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(), H, h->clk,
-                               h->partials, h->pairs, h->pair_count);
+            hipLaunchKernelGGL(k_pairs<float>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, h->P,
+                               h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(),
+                               H, h->clk, h->partials, h->pairs, h->pair_count);
         else
-            hipLaunchKernelGGL(k_pairs<double>, dim3(h->P.nc[1] * h->P.nc[2]), dim3(kBlock), h->tile_lds, h->stream,
-                               h->P, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(), H, h->clk,
-                               h->partials, h->pairs, h->pair_count);
+            hipLaunchKernelGGL(k_pairs<double>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, h->P,
+                               h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(),
+                               H, h->clk, h->partials, h->pairs, h->pair_count);
     }
     if (!finish) return DSS_OK;
     TimedLaunch t(h, 4);
+#define DSS_FINISH(R)                                                                                           \
+    case R:                                                                                                     \
+        hipLaunchKernelGGL(k_finish<R>, dim3(h->nbox), dim3(1024), 0, h->stream, h->d_boxes, h->partials,       \
+                           h->P.pstride, h->clk, h->run, sample);                                               \
+        break;
     switch (h->finish_r) {
-    case 1: hipLaunchKernelGGL(k_finish<1>, dim3(1), dim3(1024), 0, h->stream, h->partials, h->clk, h->run, sample); break;
-    case 2: hipLaunchKernelGGL(k_finish<2>, dim3(1), dim3(1024), 0, h->stream, h->partials, h->clk, h->run, sample); break;
-    case 3: hipLaunchKernelGGL(k_finish<3>, dim3(1), dim3(1024), 0, h->stream, h->partials, h->clk, h->run, sample); break;
-    case 4: hipLaunchKernelGGL(k_finish<4>, dim3(1), dim3(1024), 0, h->stream, h->partials, h->clk, h->run, sample); break;
-    default: return fail(h, DSS_ERR_BOX, "too many cell rows");
+        DSS_FINISH(1) DSS_FINISH(2) DSS_FINISH(3) DSS_FINISH(4)
+    default:
+        return fail(h, DSS_ERR_BOX, "too many cell rows");
     }
+#undef DSS_FINISH
     return DSS_OK;
 }
 
@@ -262,14 +295,21 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
     }
     {
         TimedLaunch t(h, 0);
-        hipLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c],
-                           h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk, h->cell, h->rank, h->count);
+        hipLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->d_boxes, h->pa[c], h->vel[c],
+                           h->omg[c], h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk, h->cell, h->rank, h->count);
     }
-    {
+    if (h->scan_tiles > 0) {
+        TimedLaunch t(h, 1);
+        hipLaunchKernelGGL(k_scan<4>, dim3(h->scan_tiles), dim3(1024), 0, h->stream, h->count, h->cell_start, h->clk,
+                           advance, h->tile_sum);
+        hipLaunchKernelGGL(k_scan_add, dim3(h->scan_tiles), dim3(1024), 0, h->stream, h->cell_start, h->tile_sum,
+                           4 * 1024, h->clk, advance);
+    } else {
         TimedLaunch t(h, 1);
 #define DSS_SCAN(C4)                                                                                            \
     case C4:                                                                                                    \
-        hipLaunchKernelGGL(k_scan<C4>, dim3(1), dim3(1024), 0, h->stream, h->count, h->cell_start, h->clk, advance); \
+        hipLaunchKernelGGL(k_scan<C4>, dim3(1), dim3(1024), 0, h->stream, h->count, h->cell_start, h->clk, advance, \
+                           (int *)nullptr);                                                                     \
         break;
         switch (h->scan_c4) {
             DSS_SCAN(1) DSS_SCAN(2) DSS_SCAN(3) DSS_SCAN(4) DSS_SCAN(5) DSS_SCAN(6) DSS_SCAN(7) DSS_SCAN(8)
@@ -333,16 +373,33 @@ dss_status dss_get_timing(dss_handle *h, int kernel, double *total_ms, int64_t *
     return DSS_OK;
 }
 
-dss_status dss_create(const dss_params *p, void *hip_stream, dss_handle **out)
+static bool valid_params(const dss_params *p)
 {
-    if (!p || !out) return DSS_ERR_ARG;
+    return (p->L[0] > 0 && p->L[1] > 0 && p->L[2] > 0) && p->dt > 0 && p->cutoff_factor > 0 && p->rho > 0 &&
+           p->a0 > 0 && p->reserved == 0 && p->capacity >= 0 &&
+           (p->precision == DSS_FP64 || p->precision == DSS_MIXED) && p->eps_lub > 0 &&
+           std::isfinite(p->shear_rate);
+}
+
+// Parameters of two boxes agree in everything but the box lengths and the shear rate.
+static bool same_physics(const dss_params &a, const dss_params &b)
+{
+    dss_params x = a, y = b;
+    for (int d = 0; d < 3; ++d) x.L[d] = y.L[d] = 0.0;
+    x.shear_rate = y.shear_rate = 0.0;
+    return std::memcmp(&x, &y, sizeof(dss_params)) == 0;
+}
+
+dss_status dss_create_batch(const dss_params *per_box, int32_t n_boxes, void *hip_stream, dss_handle **out)
+{
+    if (!per_box || !out || n_boxes < 1 || n_boxes > 65535) return DSS_ERR_ARG;
     *out = nullptr;
-    if (!(p->L[0] > 0 && p->L[1] > 0 && p->L[2] > 0) || !(p->dt > 0) || !(p->cutoff_factor > 0) ||
-        !(p->rho > 0) || !(p->a0 > 0) || p->reserved != 0 || p->capacity < 0 ||
-        (p->precision != DSS_FP64 && p->precision != DSS_MIXED) || !(p->eps_lub > 0))
-        return DSS_ERR_ARG;
+    for (int b = 0; b < n_boxes; ++b)
+        if (!valid_params(&per_box[b]) || !same_physics(per_box[0], per_box[b])) return DSS_ERR_ARG;
     dss_handle *h = new dss_handle();
-    h->prm = *p;
+    h->prm = per_box[0];
+    h->nbox = n_boxes;
+    h->bprm.assign(per_box, per_box + n_boxes);
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return DSS_ERR_HIP;
@@ -360,6 +417,11 @@ dss_status dss_create(const dss_params *p, void *hip_stream, dss_handle **out)
     return DSS_OK;
 }
 
+dss_status dss_create(const dss_params *p, void *hip_stream, dss_handle **out)
+{
+    return dss_create_batch(p, 1, hip_stream, out);
+}
+
 void dss_destroy(dss_handle *h)
 {
     if (!h) return;
@@ -370,13 +432,20 @@ void dss_destroy(dss_handle *h)
     delete h;
 }
 
-dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const double *radius, const double *u,
-                             const double *omega, int on_device)
+dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, const double *x, const double *radius,
+                                   const double *u, const double *omega, int on_device)
 {
     if (!h) return DSS_ERR_ARG;
-    if (N < 1 || N > (int64_t)0x3fffffff || !x || !radius) return fail(h, DSS_ERR_ARG, "N < 1 or null x / radius");
+    if (!n_per_box || !x || !radius) return fail(h, DSS_ERR_ARG, "null n_per_box, x or radius");
+    const int B = h->nbox;
+    int64_t N = 0;
+    for (int b = 0; b < B; ++b) {
+        if (n_per_box[b] < 1) return fail(h, DSS_ERR_ARG, "every box needs at least one particle");
+        N += n_per_box[b];
+    }
+    if (N > (int64_t)0x3fffffff) return fail(h, DSS_ERR_ARG, "too many particles");
     const dss_params &p = h->prm;
-    // host copies for validation and the lattice size
+    // host copies for validation and the lattice sizes
     std::vector<double> hx(3 * N), hr(N);
     if (on_device) {
         HIPTRY(hipMemcpy(hx.data(), x, 3 * N * sizeof(double), hipMemcpyDeviceToHost));
@@ -385,47 +454,81 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
         std::memcpy(hx.data(), x, 3 * N * sizeof(double));
         std::memcpy(hr.data(), radius, N * sizeof(double));
     }
-    double a_min = INFINITY, a_max = 0.0, sa3 = 0.0;
-    for (int64_t i = 0; i < N; ++i) {
-        if (!(hr[i] > 0.0) || !std::isfinite(hr[i])) return fail(h, DSS_ERR_ARG, "radius must be finite and > 0");
-        a_min = std::min(a_min, hr[i]);
-        a_max = std::max(a_max, hr[i]);
-        sa3 += hr[i] * hr[i] * hr[i];
-        for (int d = 0; d < 3; ++d)
-            if (!(hx[3 * i + d] >= 0.0 && hx[3 * i + d] < p.L[d]))
-                return fail(h, DSS_ERR_ARG, "position outside [0, L) for particle " + std::to_string(i));
+    std::vector<BoxParams> boxes(B);
+    std::vector<double> box_sa3(B, 0.0);
+    std::vector<int> pbox(N);
+    std::vector<int> row_box;
+    double a_min = INFINITY, a_max = 0.0, max_mean_row = 0.0;
+    int64_t ncell = 0, part = 0;
+    int nrow = 0, max_rows_box = 0;
+    for (int b = 0; b < B; ++b) {
+        const dss_params &q = h->bprm[b];
+        BoxParams &G = boxes[b];
+        double bmax = 0.0;
+        for (int64_t i = part; i < part + n_per_box[b]; ++i) {
+            if (!(hr[i] > 0.0) || !std::isfinite(hr[i])) return fail(h, DSS_ERR_ARG, "radius must be finite and > 0");
+            a_min = std::min(a_min, hr[i]);
+            bmax = std::max(bmax, hr[i]);
+            box_sa3[b] += hr[i] * hr[i] * hr[i];
+            for (int d = 0; d < 3; ++d)
+                if (!(hx[3 * i + d] >= 0.0 && hx[3 * i + d] < q.L[d]))
+                    return fail(h, DSS_ERR_ARG, "position outside [0, L) for particle " + std::to_string(i));
+            pbox[i] = b;
+        }
+        a_max = std::max(a_max, bmax);
+        // lattice: spacing >= the largest cutoff 2 c a_max of the box (with a 1e-9 margin)
+        const double rc = p.cutoff_factor * 2.0 * bmax * (1.0 + 1e-9);
+        for (int d = 0; d < 3; ++d) {
+            G.L[d] = q.L[d];
+            G.nc[d] = std::max(1, (int)std::floor(q.L[d] / rc));
+            G.cw[d] = q.L[d] / (double)G.nc[d];
+        }
+        G.gd = q.shear_rate;
+        if (G.nc[0] < 4 || G.nc[1] < 3 || G.nc[2] < 3)
+            return fail(h, DSS_ERR_BOX, "cell lattice " + std::to_string(G.nc[0]) + "x" + std::to_string(G.nc[1]) +
+                                            "x" + std::to_string(G.nc[2]) + " of box " + std::to_string(b) +
+                                            " is smaller than 4x3x3");
+        const int rows = G.nc[1] * G.nc[2];
+        if (rows > 4096) return fail(h, DSS_ERR_BOX, "more than 4096 cell rows in box " + std::to_string(b));
+        G.cell_off = (int)ncell;
+        G.row_off = nrow;
+        G.part_off = (int)part;
+        G.n_part = (int)n_per_box[b];
+        ncell += (int64_t)G.nc[0] * rows;
+        if (ncell > (int64_t)0x3fffffff) return fail(h, DSS_ERR_BOX, "too many cells");
+        nrow += rows;
+        row_box.insert(row_box.end(), rows, b);
+        max_rows_box = std::max(max_rows_box, rows);
+        max_mean_row = std::max(max_mean_row, (double)n_per_box[b] / (double)rows);
+        part += n_per_box[b];
     }
-    // lattice: spacing >= the largest cutoff 2 c a_max (with a 1e-9 margin)
+    // cell-count scan: one workgroup up to 65535 cells, else workgroups of 16384 cells
+    int scan_c4 = 0, scan_tiles = 0;
+    int64_t ncell_pad;
+    if (ncell + 1 <= 4096 * 16) {
+        scan_c4 = (int)((ncell + 1 + 4095) / 4096);
+        ncell_pad = 4096 * (int64_t)scan_c4;
+    } else {
+        scan_tiles = (int)((ncell + 1 + 16383) / 16384);
+        ncell_pad = 16384 * (int64_t)scan_tiles;
+    }
     DevParams P{};
-    for (int d = 0; d < 3; ++d) P.L[d] = p.L[d];
-    P.gd = p.shear_rate; P.eta0 = p.eta0; P.rho = p.rho; P.kn = p.kn; P.kt = p.kt; P.gn = p.gamma_n;
+    P.eta0 = p.eta0; P.rho = p.rho; P.kn = p.kn; P.kt = p.kt; P.gn = p.gamma_n;
     P.mu = p.mu; P.fer = p.F_ER; P.lamd = p.lambda_D; P.a0 = p.a0; P.ham = p.hamaker; P.eps_vdw = p.eps_vdw;
     P.eps_lub = p.eps_lub; P.cf = p.cutoff_factor; P.dt = p.dt;
     P.k6 = 6.0 * kPi * p.eta0;
     P.k8 = 8.0 * kPi * p.eta0;
     P.inv_lamd = p.lambda_D > 0.0 ? 1.0 / p.lambda_D : 0.0;
     P.fer_a0 = p.F_ER / p.a0;
-    const double rc = p.cutoff_factor * 2.0 * a_max * (1.0 + 1e-9);
-    for (int d = 0; d < 3; ++d) {
-        P.nc[d] = std::max(1, (int)std::floor(p.L[d] / rc));
-        P.cw[d] = p.L[d] / (double)P.nc[d];
-    }
-    if (P.nc[0] < 4 || P.nc[1] < 3 || P.nc[2] < 3)
-        return fail(h, DSS_ERR_BOX, "cell lattice " + std::to_string(P.nc[0]) + "x" + std::to_string(P.nc[1]) + "x" +
-                                        std::to_string(P.nc[2]) + " is smaller than 4x3x3");
-    const int64_t ncell = (int64_t)P.nc[0] * P.nc[1] * P.nc[2];
-    // the single-workgroup scan holds 16 int4 chunks per lane: up to 65535 cells
-    if (ncell + 1 > 4096 * 16) return fail(h, DSS_ERR_BOX, "more than 65535 cells in one box");
-    const int scan_c4 = (int)((ncell + 1 + 4095) / 4096);
-    const int64_t ncell_pad = 4096 * (int64_t)scan_c4;
-    P.ncell = (int)ncell;
+    P.nbox = B;
     P.N = (int)N;
     P.M = p.capacity > 0 ? p.capacity : paper_capacity(a_max, a_min);
     P.record_pairs = (p.flags & DSS_FLAG_RECORD_PAIRS) ? 1 : 0;
     // row-tile capacities of k_pairs from the mean occupancy of a cell row (own row and the
-    // five rows of the half shell); rows beyond them take the per-particle path
+    // five rows of the half shell) of the densest box; rows beyond them take the
+    // per-particle path
     {
-        const double mean_row = (double)N / ((double)P.nc[1] * P.nc[2]);
+        const double mean_row = max_mean_row;
         auto up = [](double v, int m) { return ((int)std::ceil(v) + m - 1) / m * m; };
         int own_cap = up(1.5 * mean_row + 16.0, 32);
         int stage_cap = up(6.25 * mean_row + 32.0, 64);
@@ -446,13 +549,19 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
 
     free_all(h);
     h->P = P;
+    h->boxes = boxes;
+    h->box_n.assign(n_per_box, n_per_box + B);
+    h->box_sa3 = box_sa3;
+    h->ncell_total = (int)ncell;
+    h->nrow_total = nrow;
+    h->scan_c4 = scan_c4;
+    h->scan_tiles = scan_tiles;
     h->tile_lds = tile_lds_bytes(P.own_cap, P.stage_cap, P.qcap);
     HIPTRY(hipFuncSetAttribute((const void *)k_pairs<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)h->tile_lds));
     HIPTRY(hipFuncSetAttribute((const void *)k_pairs<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)h->tile_lds));
     h->N = N;
-    h->sum_a3 = sa3;
     const size_t rows = (size_t)N * (size_t)P.M;
     for (int k = 0; k < 2; ++k) {
         HIPTRY(dalloc(&h->pa[k], N));
@@ -471,38 +580,46 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
     HIPTRY(dalloc(&h->rank, N));
     HIPTRY(dalloc(&h->count, ncell_pad));
     HIPTRY(dalloc(&h->cell_start, ncell_pad));
-    h->scan_c4 = scan_c4;
+    HIPTRY(dalloc(&h->tile_sum, std::max(scan_tiles, 1)));
     HIPTRY(dalloc(&h->pairs, P.record_pairs ? 2 * P.pair_cap : 2));
     HIPTRY(dalloc(&h->pair_count, 1));
     HIPTRY(dalloc(&h->clk, 1));
     HIPTRY(dalloc(&h->run, 1));
-    HIPTRY(dalloc(&h->sigma_last, 9));
+    HIPTRY(dalloc(&h->sigma_last, 9 * (size_t)B));
+    HIPTRY(dalloc(&h->box_diag, 3 * (size_t)B));
+    HIPTRY(dalloc(&h->d_boxes, B));
+    HIPTRY(dalloc(&h->d_row_box, nrow));
+    HIPTRY(hipMemcpyAsync(h->d_boxes, boxes.data(), B * sizeof(BoxParams), hipMemcpyHostToDevice, h->stream));
+    HIPTRY(hipMemcpyAsync(h->d_row_box, row_box.data(), nrow * sizeof(int), hipMemcpyHostToDevice, h->stream));
     {
-        const int rows = P.nc[1] * P.nc[2];
-        h->finish_r = (rows + 1023) / 1024;
-        if (h->finish_r > 4) return fail(h, DSS_ERR_BOX, "more than 4096 cell rows in one box");
-        h->P.pstride = 1024 * h->finish_r;
-        HIPTRY(dalloc(&h->partials, 12 * (size_t)1024 * h->finish_r));
-        HIPTRY(hipMemsetAsync(h->partials, 0, 12 * (size_t)1024 * h->finish_r * sizeof(double), h->stream));
+        h->finish_r = (max_rows_box + 1023) / 1024;
+        h->P.pstride = (nrow + 63) / 64 * 64;
+        HIPTRY(dalloc(&h->partials, 12 * (size_t)h->P.pstride));
+        HIPTRY(hipMemsetAsync(h->partials, 0, 12 * (size_t)h->P.pstride * sizeof(double), h->stream));
     }
     HIPTRY(hipMemsetAsync(h->count, 0, ncell_pad * sizeof(int), h->stream));
     HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
     HIPTRY(hipMemsetAsync(h->clk, 0, sizeof(DevClock), h->stream));
-    HIPTRY(hipMemsetAsync(h->sigma_last, 0, 9 * sizeof(double), h->stream));
+    HIPTRY(hipMemsetAsync(h->sigma_last, 0, 9 * (size_t)B * sizeof(double), h->stream));
+    HIPTRY(hipMemsetAsync(h->box_diag, 0, 3 * (size_t)B * sizeof(double), h->stream));
     for (int k = 0; k < 2; ++k) {
         HIPTRY(hipMemsetAsync(h->hcnt[k], 0, N * sizeof(int), h->stream));
         HIPTRY(hipMemsetAsync(h->hown[k], 0, N * sizeof(int), h->stream));
     }
     h->run_host = DevRun{};
     h->run_host.sigma_last = h->sigma_last;
+    h->run_host.box_diag = h->box_diag;
     HIPTRY(hipMemcpyAsync(h->run, &h->run_host, sizeof(DevRun), hipMemcpyHostToDevice, h->stream));
 
     // stage the inputs on the device
     double *dx = nullptr, *dr = nullptr, *du = nullptr, *dw = nullptr;
+    int *dpb = nullptr;
     HIPTRY(dalloc(&dx, 3 * N));
     HIPTRY(dalloc(&dr, N));
+    HIPTRY(dalloc(&dpb, N));
     HIPTRY(hipMemcpyAsync(dx, hx.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIPTRY(hipMemcpyAsync(dr, hr.data(), N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPTRY(hipMemcpyAsync(dpb, pbox.data(), N * sizeof(int), hipMemcpyHostToDevice, h->stream));
     if (u) {
         HIPTRY(dalloc(&du, 3 * N));
         HIPTRY(hipMemcpyAsync(du, u, 3 * N * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -518,18 +635,28 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
     h->step = 0;
     h->vel_is_half = false;
     const int grid = (int)((N + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_load, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, dx, dr, du, dw, P.gd, h->pa[0],
-                       h->vel[0], h->omg[0], h->fb());
+    hipLaunchKernelGGL(k_load, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, dx, dr, du, dw, dpb, h->d_boxes,
+                       h->pa[0], h->vel[0], h->omg[0], h->fb());
     HIPTRY(hipGetLastError());
     h->loaded = true;
     dss_status s = evaluate(h, EVAL_SORT);
     HIPTRY(hipStreamSynchronize(h->stream));
     (void)hipFree(dx);
     (void)hipFree(dr);
+    (void)hipFree(dpb);
     if (du) (void)hipFree(du);
     if (dw) (void)hipFree(dw);
     if (s != DSS_OK) return s;
     return check_flags(h);
+}
+
+dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const double *radius, const double *u,
+                             const double *omega, int on_device)
+{
+    if (!h) return DSS_ERR_ARG;
+    if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "a batch handle takes dss_set_particles_batch");
+    if (N < 1 || N > (int64_t)0x3fffffff || !x || !radius) return fail(h, DSS_ERR_ARG, "N < 1 or null x / radius");
+    return dss_set_particles_batch(h, &N, x, radius, u, omega, on_device);
 }
 
 dss_status dss_set_step(dss_handle *h, int64_t n)
@@ -579,7 +706,7 @@ dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sy
     if (cap > h->sample_cap_alloc) {
         if (h->samples) HIPTRY(hipFree(h->samples));
         h->samples = nullptr;
-        HIPTRY(dalloc(&h->samples, 9 * cap));
+        HIPTRY(dalloc(&h->samples, 9 * (size_t)h->nbox * cap));
         h->sample_cap_alloc = cap;
     }
     h->run_host.sample_every = cap > 0 ? stress_every : 0;
@@ -587,6 +714,7 @@ dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sy
     h->run_host.sample_cap = cap;
     h->run_host.samples = h->samples;
     h->run_host.sigma_last = h->sigma_last;
+    h->run_host.box_diag = h->box_diag;
     HIPTRY(hipMemcpyAsync(h->run, &h->run_host, sizeof(DevRun), hipMemcpyHostToDevice, h->stream));
     h->last_samples = cap;
     for (int64_t k = 0; k < n_steps; ++k) {
@@ -600,36 +728,48 @@ dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sy
     return DSS_OK;
 }
 
-dss_status dss_read_stress(dss_handle *h, double *sigma_last, double *sigma_mean, int64_t *n_samples)
+dss_status dss_read_stress_batch(dss_handle *h, double *sigma_last, double *sigma_mean, int64_t *n_samples)
 {
     dss_status s = require_loaded(h);
     if (s) return s;
-    const dss_params &p = h->prm;
-    const double V = p.L[0] * p.L[1] * p.L[2];
-    // constant part: 2 eta0 E_inf + (1/V) sum_i 20/3 pi eta0 a_i^3 E_inf (eqs. stress, stresslet)
-    double base[9] = {0};
-    const double exy = 0.5 * p.shear_rate;
-    const double c = 2.0 * p.eta0 * exy + (20.0 / 3.0) * kPi * p.eta0 * h->sum_a3 * exy / V;
-    base[1] = c;
-    base[3] = c;
-    double last[9];
-    HIPTRY(hipMemcpyAsync(last, h->sigma_last, sizeof(last), hipMemcpyDeviceToHost, h->stream));
-    std::vector<double> smp(9 * std::max<int64_t>(h->last_samples, 1));
-    if (sigma_mean && h->last_samples > 0)
-        HIPTRY(hipMemcpyAsync(smp.data(), h->samples, 9 * h->last_samples * sizeof(double), hipMemcpyDeviceToHost,
+    const int B = h->nbox;
+    const int64_t ns = h->last_samples;
+    std::vector<double> last(9 * (size_t)B);
+    std::vector<double> smp(9 * (size_t)B * (size_t)std::max<int64_t>(ns, 1));
+    HIPTRY(hipMemcpyAsync(last.data(), h->sigma_last, last.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+    if (sigma_mean && ns > 0)
+        HIPTRY(hipMemcpyAsync(smp.data(), h->samples, 9 * (size_t)B * ns * sizeof(double), hipMemcpyDeviceToHost,
                               h->stream));
     HIPTRY(hipStreamSynchronize(h->stream));
-    if (sigma_last)
-        for (int k = 0; k < 9; ++k) sigma_last[k] = base[k] + last[k] / V;
-    if (sigma_mean) {
-        for (int k = 0; k < 9; ++k) {
-            double acc = 0.0;
-            for (int64_t q = 0; q < h->last_samples; ++q) acc += smp[9 * q + k];
-            sigma_mean[k] = h->last_samples > 0 ? base[k] + acc / (double)h->last_samples / V : NAN;
+    for (int b = 0; b < B; ++b) {
+        const dss_params &p = h->bprm[b];
+        const double V = p.L[0] * p.L[1] * p.L[2];
+        // constant part: 2 eta0 E_inf + (1/V) sum_i 20/3 pi eta0 a_i^3 E_inf (eqs. stress, stresslet)
+        double base[9] = {0};
+        const double exy = 0.5 * p.shear_rate;
+        const double c = 2.0 * p.eta0 * exy + (20.0 / 3.0) * kPi * p.eta0 * h->box_sa3[b] * exy / V;
+        base[1] = c;
+        base[3] = c;
+        if (sigma_last)
+            for (int k = 0; k < 9; ++k) sigma_last[9 * b + k] = base[k] + last[9 * b + k] / V;
+        if (sigma_mean) {
+            for (int k = 0; k < 9; ++k) {
+                double acc = 0.0;
+                for (int64_t q = 0; q < ns; ++q) acc += smp[(q * B + b) * 9 + k];
+                sigma_mean[9 * b + k] = ns > 0 ? base[k] + acc / (double)ns / V : NAN;
+            }
         }
     }
-    if (n_samples) *n_samples = h->last_samples;
+    if (n_samples) *n_samples = ns;
     return check_flags(h);
+}
+
+dss_status dss_read_stress(dss_handle *h, double *sigma_last, double *sigma_mean, int64_t *n_samples)
+{
+    if (!h) return DSS_ERR_ARG;
+    if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "a batch handle takes dss_read_stress_batch");
+    return dss_read_stress_batch(h, sigma_last, sigma_mean, n_samples);
 }
 
 dss_status dss_get_state(dss_handle *h, double *x, double *u, double *omega, double *F, double *T, int on_device)
@@ -710,10 +850,10 @@ dss_status dss_get_cells(dss_handle *h, int32_t *dims, int64_t cap_cells, int32_
     dss_status s = require_loaded(h);
     if (s) return s;
     if (dims)
-        for (int d = 0; d < 3; ++d) dims[d] = h->P.nc[d];
+        for (int d = 0; d < 3; ++d) dims[d] = h->boxes[0].nc[d];
     if (cell_start) {
-        if (cap_cells < (int64_t)h->P.ncell + 1) return fail(h, DSS_ERR_CAPACITY, "cell_start buffer too small");
-        HIPTRY(hipMemcpy(cell_start, h->cell_start, (h->P.ncell + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (cap_cells < (int64_t)h->ncell_total + 1) return fail(h, DSS_ERR_CAPACITY, "cell_start buffer too small");
+        HIPTRY(hipMemcpy(cell_start, h->cell_start, (h->ncell_total + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
     }
     if (perm) {
         std::vector<double4> w(h->N);
@@ -761,17 +901,53 @@ dss_status dss_get_info(dss_handle *h, dss_info *info)
     if (!info) return fail(h, DSS_ERR_ARG, "null info");
     DevClock c;
     HIPTRY(hipMemcpyAsync(&c, h->clk, sizeof(c), hipMemcpyDeviceToHost, h->stream));
-    HIPTRY(hipStreamSynchronize(h->stream));
+    std::vector<double> d;
+    s = read_diag(h, d);
+    if (s) return s;
     info->n_particles = h->N;
     info->step = c.step;
-    for (int d = 0; d < 3; ++d) info->cells[d] = h->P.nc[d];
+    for (int k = 0; k < 3; ++k) info->cells[k] = h->boxes[0].nc[k];
     info->capacity = h->P.M;
-    info->n_pairs = (int64_t)c.n_pairs;
-    info->n_contacts = (int64_t)c.n_contacts;
-    info->max_row_fill = c.max_fill;
+    double np = 0.0, nc = 0.0, mf = 0.0;
+    for (int b = 0; b < h->nbox; ++b) {
+        np += d[3 * b];
+        nc += d[3 * b + 1];
+        mf = std::max(mf, d[3 * b + 2]);
+    }
+    info->n_pairs = (int64_t)np;
+    info->n_contacts = (int64_t)nc;
+    info->max_row_fill = (int32_t)mf;
     info->error_flags = (int32_t)c.err;
     double t = (double)c.step * h->prm.dt;
     info->le_offset = std::fmod(h->prm.shear_rate * h->prm.L[1] * t, h->prm.L[0]);
+    return DSS_OK;
+}
+
+dss_status dss_get_box_info(dss_handle *h, int32_t box, dss_box_info *info)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (!info || box < 0 || box >= h->nbox) return fail(h, DSS_ERR_ARG, "null info or box out of range");
+    DevClock c;
+    HIPTRY(hipMemcpyAsync(&c, h->clk, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+    std::vector<double> d;
+    s = read_diag(h, d);
+    if (s) return s;
+    const BoxParams &G = h->boxes[box];
+    info->n_particles = G.n_part;
+    info->first_id = G.part_off;
+    for (int k = 0; k < 3; ++k) {
+        info->cells[k] = G.nc[k];
+        info->L[k] = G.L[k];
+    }
+    info->first_cell = G.cell_off;
+    info->n_pairs = (int64_t)d[3 * box];
+    info->n_contacts = (int64_t)d[3 * box + 1];
+    info->max_row_fill = (int32_t)d[3 * box + 2];
+    info->reserved = 0;
+    info->shear_rate = G.gd;
+    double t = (double)c.step * h->prm.dt;
+    info->le_offset = std::fmod(G.gd * G.L[1] * t, G.L[0]);
     return DSS_OK;
 }
 

@@ -2,7 +2,8 @@
 //
 // Data layout (all in sorted order = cell-major order of the last counting sort):
 //   pa  double4 [N]  (x, y, z, radius)
-//   vel double4 [N]  (u_x, u_y, u_z, 0): the velocity the last forces were evaluated with
+//   vel double4 [N]  (u_x, u_y, u_z, box): the velocity the last forces were evaluated with,
+//                    and the index of the particle's box
 //   omg double4 [N]  (w_x, w_y, w_z, id): angular velocity and the particle id (as a double)
 //   force records: 6 doubles (F, T) per particle in six buffers (see ForceBufs)
 // One 32-byte record per particle and quantity, so a neighbour gather is one 32-byte
@@ -26,16 +27,14 @@ constexpr unsigned kErrRowOverflow = 1u;
 constexpr unsigned kErrNonFinite = 2u;
 constexpr unsigned kErrPairBuffer = 4u;
 
+// Physical constants and capacities shared by all boxes of a handle.
 struct DevParams {
-    double L[3];
-    double gd, eta0, rho, kn, kt, gn, mu, fer, lamd, a0, ham, eps_vdw, eps_lub, cf, dt;
-    double cw[3];      // cell widths L/n
+    double eta0, rho, kn, kt, gn, mu, fer, lamd, a0, ham, eps_vdw, eps_lub, cf, dt;
     double k6, k8;     // 6 pi eta0, 8 pi eta0
     double inv_lamd;   // 1 / lambda_D (0 if lambda_D <= 0)
     double fer_a0;     // F_ER / a0
-    int nc[3];         // cells per dimension
-    int ncell;
-    int N;
+    int nbox;          // number of independent boxes
+    int N;             // particles over all boxes
     int M;             // history row capacity
     int record_pairs;
     long long pair_cap;
@@ -43,12 +42,23 @@ struct DevParams {
     int pstride;                    // stride of the partial records (1024 R)
 };
 
-// Device-side clock and per-evaluation counters.  step = time index of the state.
+// One box: its geometry, shear rate, cell lattice and its ranges in the global numbering
+// (cells, cell rows and particle ids of all boxes are numbered box after box, so one
+// counting sort orders every box and each box is a contiguous range of sorted slots).
+struct BoxParams {
+    double L[3];       // box lengths
+    double gd;         // shear rate
+    double cw[3];      // cell widths L / nc
+    int nc[3];         // cells per dimension
+    int cell_off;      // first cell of the box
+    int row_off;       // first cell row (nc[1] nc[2] rows per box)
+    int part_off;      // first particle id of the box
+    int n_part;        // particles of the box
+};
+
+// Device-side clock and error flags.  step = time index of the state.
 struct DevClock {
     long long step;
-    unsigned long long n_pairs;
-    unsigned long long n_contacts;
-    int max_fill;
     unsigned err;
 };
 
@@ -57,19 +67,20 @@ struct DevRun {
     long long sample_every;   // 0: no sampling
     long long sample_first;   // first sampled time index of this call
     long long sample_cap;     // number of sample slots
-    double *samples;          // sample_cap x 9
-    double *sigma_last;       // 9: pair part of the stress of the last evaluation
+    double *samples;          // sample_cap x nbox x 9
+    double *sigma_last;       // nbox x 9: pair part of the stress of the last evaluation
+    double *box_diag;         // nbox x 3: listed pairs, contacts, largest history row
 };
 
 // ----------------------------------------------------------------------------------
 // small helpers
 // ----------------------------------------------------------------------------------
-__device__ __forceinline__ double le_offset(const DevParams &P, long long step)
+__device__ __forceinline__ double le_offset(const DevParams &P, const BoxParams &G, long long step)
 {
 #pragma clang fp contract(off)
     double t = (double)step * P.dt;
-    double s = P.gd * P.L[1] * t;
-    return fmod(s, P.L[0]);
+    double s = G.gd * G.L[1] * t;
+    return fmod(s, G.L[0]);
 }
 
 __device__ __forceinline__ int cell_coord(double xd, double cw, int n)
@@ -85,7 +96,7 @@ __device__ __forceinline__ int cell_coord(double xd, double cw, int n)
 // pair closer than L/2 along x and z this equals r - L round(r / L) bit for bit (the
 // subtractions of L and 2 L are exact by Sterbenz's lemma), so the listed-pair test is the
 // IEEE expression as written.  Evaluated without contraction.
-__device__ __forceinline__ void min_image(const DevParams &P, double delta, double xa, double ya, double za,
+__device__ __forceinline__ void min_image(const BoxParams &P, double delta, double xa, double ya, double za,
                                           double xb, double yb, double zb, double &dx, double &dy, double &dz)
 {
 #pragma clang fp contract(off)
@@ -214,17 +225,20 @@ __device__ __forceinline__ void total_ft(const ForceBufs &B, int p, double f[6])
 // tiles + the lanes before it in its tile (wavefront shuffles, then the 16 wavefront
 // totals through LDS).  count and cell_start are padded to 4096 C4 entries (padding
 // counts stay 0), so the entry at index n_cells receives the total.
+// Lattices beyond one workgroup (many boxes): each workgroup scans its own 4096 C4 counts
+// and leaves its total in tile_sum; k_scan_add then adds the totals of the earlier
+// workgroups and advances the clock.
 // ----------------------------------------------------------------------------------
 template <int C4>
 __global__ void __launch_bounds__(1024) k_scan(int *__restrict__ count, int *__restrict__ cell_start,
-                                               DevClock *__restrict__ clk, int advance)
+                                               DevClock *__restrict__ clk, int advance, int *__restrict__ tile_sum)
 {
     __shared__ int wsum[C4][16];
     __shared__ int wpre[C4][16];
     const int t = threadIdx.x;
     const int lane = t & 63, wid = t >> 6;
-    int4 *cnt4 = reinterpret_cast<int4 *>(count);
-    int4 *out4 = reinterpret_cast<int4 *>(cell_start);
+    int4 *cnt4 = reinterpret_cast<int4 *>(count) + (size_t)blockIdx.x * (C4 * 1024);
+    int4 *out4 = reinterpret_cast<int4 *>(cell_start) + (size_t)blockIdx.x * (C4 * 1024);
     int4 v[C4];
 #pragma unroll
     for (int k = 0; k < C4; ++k) v[k] = cnt4[k * 1024 + t];
@@ -253,6 +267,7 @@ __global__ void __launch_bounds__(1024) k_scan(int *__restrict__ count, int *__r
                 wpre[k][w] = run;
                 run += wsum[k][w];
             }
+        if (tile_sum) tile_sum[blockIdx.x] = run;
     }
     __syncthreads();
     const int4 zero = make_int4(0, 0, 0, 0);
@@ -266,7 +281,36 @@ __global__ void __launch_bounds__(1024) k_scan(int *__restrict__ count, int *__r
         out4[k * 1024 + t] = o;
         cnt4[k * 1024 + t] = zero;
     }
-    if (t == 0 && advance) clk->step += 1;
+    if (t == 0 && advance && !tile_sum) clk->step += 1;
+}
+
+// Second pass of the multi-workgroup scan: workgroup b adds the totals of workgroups
+// 0 .. b-1 to its chunk of cell_start (chunks int4 entries per workgroup).
+__global__ void __launch_bounds__(1024) k_scan_add(int *__restrict__ cell_start, const int *__restrict__ tile_sum,
+                                                   int chunks, DevClock *__restrict__ clk, int advance)
+{
+    __shared__ int red[16];
+    const int t = threadIdx.x, b = blockIdx.x;
+    if (b == 0) {
+        if (t == 0 && advance) clk->step += 1;
+        return;
+    }
+    int part = 0;
+    for (int k = t; k < b; k += 1024) part += tile_sum[k];
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if ((t & 63) == 0) red[t >> 6] = part;
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < 16; ++w) off += red[w];
+    int4 *out4 = reinterpret_cast<int4 *>(cell_start) + (size_t)b * chunks;
+    for (int k = t; k < chunks; k += 1024) {
+        int4 v = out4[k];
+        v.x += off;
+        v.y += off;
+        v.z += off;
+        v.w += off;
+        out4[k] = v;
+    }
 }
 
 // ----------------------------------------------------------------------------------
@@ -275,7 +319,8 @@ __global__ void __launch_bounds__(1024) k_scan(int *__restrict__ count, int *__r
 //   vel_is_half = 1: vel holds the half-step velocity u^{n-1/2} of the forces, and
 //   u^n = u^{n-1/2} + dt/2 F^n / m completes the previous step.
 // ----------------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_predict(DevParams P, double4 *__restrict__ pa, double4 *__restrict__ vel,
+__global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams *__restrict__ boxes,
+                                                     double4 *__restrict__ pa, double4 *__restrict__ vel,
                                                      double4 *__restrict__ omg, ForceBufs B, int vel_is_half,
                                                      int advance, const DevClock *__restrict__ clk,
                                                      int *__restrict__ cell, int *__restrict__ rank,
@@ -289,6 +334,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, double4 *__rest
     double4 X = pa[p];
     double4 V = vel[p];
     double4 W = omg[p];
+    const BoxParams &G = boxes[(int)V.w];
     const double dt = P.dt;
     double a = X.w;
     double m = pmass(P, a);
@@ -316,26 +362,26 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, double4 *__rest
         W.y = W.y + 0.5 * dt * by;
         W.z = W.z + 0.5 * dt * bz;
         // Lees-Edwards wrap at t_{n+1}
-        double delta = le_offset(P, clk->step + 1);
-        if (X.y >= P.L[1]) {
-            X.y -= P.L[1];
+        double delta = le_offset(P, G, clk->step + 1);
+        if (X.y >= G.L[1]) {
+            X.y -= G.L[1];
             X.x -= delta;
-            V.x -= P.gd * P.L[1];
+            V.x -= G.gd * G.L[1];
         } else if (X.y < 0.0) {
-            X.y += P.L[1];
+            X.y += G.L[1];
             X.x += delta;
-            V.x += P.gd * P.L[1];
+            V.x += G.gd * G.L[1];
         }
-        X.x -= P.L[0] * floor(X.x / P.L[0]);
-        X.z -= P.L[2] * floor(X.z / P.L[2]);
+        X.x -= G.L[0] * floor(X.x / G.L[0]);
+        X.z -= G.L[2] * floor(X.z / G.L[2]);
         pa[p] = X;
     }
     vel[p] = V;
     omg[p] = W;
-    int cx = cell_coord(X.x, P.cw[0], P.nc[0]);
-    int cy = cell_coord(X.y, P.cw[1], P.nc[1]);
-    int cz = cell_coord(X.z, P.cw[2], P.nc[2]);
-    c = (cz * P.nc[1] + cy) * P.nc[0] + cx;
+    int cx = cell_coord(X.x, G.cw[0], G.nc[0]);
+    int cy = cell_coord(X.y, G.cw[1], G.nc[1]);
+    int cz = cell_coord(X.z, G.cw[2], G.nc[2]);
+    c = G.cell_off + (cz * G.nc[1] + cy) * G.nc[0] + cx;
     }
     // histogram rank: lanes of a wavefront with equal consecutive cell ids (the input is
     // sorted by the previous step's cells) form runs; the first lane of a run claims the
@@ -440,7 +486,8 @@ __device__ __forceinline__ float sqrt_r(float x) { return __builtin_sqrtf(x); }
 // once; the unit vector, coefficients, log/exp, contact model and stresslet are FP32; the
 // results are accumulated in FP64 by the caller.
 template <typename Real>
-__device__ __forceinline__ void pair_physics(const DevParams &P, double dx_d, double dy_d, double dz_d, double dist,
+__device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, double dx_d, double dy_d, double dz_d,
+                                             double dist,
                                              double ai_d, double aj_d, double yi, double yj, const double4 &Vi,
                                              const double4 &Vj, const double4 &Wi, const double4 &Wj,
                                              const double xo[3], double *S, PairOut &o)
@@ -451,7 +498,6 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double dx_d, do
     double dstar = 2.0 * h_d / s_d;
     dstar = dstar > 0.0 ? dstar : 0.0;
     const double g_d = dstar + P.eps_lub;
-    const double gd_d = P.gd;
     const Real invg = (Real)rcp_nr(g_d);
     const Real lg = -log_r((Real)g_d);
     const Real dux = (Real)((Vj.x - gd_d * yj) - (Vi.x - gd_d * yi));
@@ -645,7 +691,7 @@ __device__ __forceinline__ void shell_row(int r, int &dz, int &dy)
 
 // x window [xlo, xhi] (unwrapped) of row r for a particle in cell column cx, given whether
 // the row is reached across the top (+1) or bottom (-1) face (0: interior).
-__device__ __forceinline__ void shell_window(const DevParams &P, int r, int cx, int cross, double delta, int &xlo,
+__device__ __forceinline__ void shell_window(const BoxParams &P, int r, int cx, int cross, double delta, int &xlo,
                                              int &xhi)
 {
     if (cross != 0) {
@@ -667,7 +713,8 @@ __device__ __forceinline__ void shell_window(const DevParams &P, int r, int cx, 
 // of this pair in the row of either particle, canonical orientation min id -> max id) and
 // the pair physics.
 template <typename Real>
-__device__ __forceinline__ void evaluate_pair(const DevParams &P, const HistView &H, int gi, int gj, int idi, int idj,
+__device__ __forceinline__ void evaluate_pair(const DevParams &P, double gd, const HistView &H, int gi, int gj, int idi,
+                                              int idj,
                                               const double4 &Xi, const double4 &Xj, const double4 &Vi,
                                               const double4 &Wi, const double4 &Vj, const double4 &Wj, double dx,
                                               double dy, double dz, double r2, double *S, PairOut &o)
@@ -685,7 +732,7 @@ __device__ __forceinline__ void evaluate_pair(const DevParams &P, const HistView
             xo[2] = -xo[2];
         }
     }
-    pair_physics<Real>(P, dx, dy, dz, dist, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, S, o);
+    pair_physics<Real>(P, gd, dx, dy, dz, dist, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, S, o);
 }
 
 __device__ __forceinline__ void record_pair(const DevParams &P, int idi, int idj, int *pair_out,
@@ -781,17 +828,17 @@ __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int
 
 // Stokes drag and rotational drag of one particle (eq. rst), added to f (force 0..2,
 // torque 3..5).
-__device__ __forceinline__ void stokes_terms(const DevParams &P, const double4 &Xi, const double4 &Vi,
+__device__ __forceinline__ void stokes_terms(const DevParams &P, double gd, const double4 &Xi, const double4 &Vi,
                                              const double4 &Wi, double f[6])
 {
     const double K = P.k6;
-    f[0] += -K * Xi.w * (Vi.x - P.gd * Xi.y);
+    f[0] += -K * Xi.w * (Vi.x - gd * Xi.y);
     f[1] += -K * Xi.w * Vi.y;
     f[2] += -K * Xi.w * Vi.z;
     const double KR = P.k8 * Xi.w * Xi.w * Xi.w;
     f[3] += -KR * Wi.x;
     f[4] += -KR * Wi.y;
-    f[5] += -KR * (Wi.z + 0.5 * P.gd);
+    f[5] += -KR * (Wi.z + 0.5 * gd);
 }
 
 __device__ __forceinline__ bool finite6(const double f[6])
@@ -812,7 +859,8 @@ struct PairTally {
 // adds the partner side atomically to ft_x.
 // ----------------------------------------------------------------------------------
 template <typename Real>
-__device__ void particle_pairs_global(const DevParams &P, int i, double delta, const int *__restrict__ cell_start,
+__device__ void particle_pairs_global(const DevParams &P, const BoxParams &G, int i, double delta,
+                                      const int *__restrict__ cell_start,
                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                       const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
                                       DevClock *clk, int *pair_out, unsigned long long *pair_count,
@@ -822,10 +870,10 @@ __device__ void particle_pairs_global(const DevParams &P, int i, double delta, c
     const double4 Vi = vel[i];
     const double4 Wi = omg[i];
     const int idi = (int)Wi.w;
-    const int cx = cell_coord(Xi.x, P.cw[0], P.nc[0]);
-    const int cy = cell_coord(Xi.y, P.cw[1], P.nc[1]);
-    const int cz = cell_coord(Xi.z, P.cw[2], P.nc[2]);
-    const int nxc = P.nc[0], nyc = P.nc[1], nzc = P.nc[2];
+    const int cx = cell_coord(Xi.x, G.cw[0], G.nc[0]);
+    const int cy = cell_coord(Xi.y, G.cw[1], G.nc[1]);
+    const int cz = cell_coord(Xi.z, G.cw[2], G.nc[2]);
+    const int nxc = G.nc[0], nyc = G.nc[1], nzc = G.nc[2];
     double f[6] = {0, 0, 0, 0, 0, 0};
     int fill = 0;
     for (int r = 0; r < 5; ++r) {
@@ -837,8 +885,8 @@ __device__ void particle_pairs_global(const DevParams &P, int i, double delta, c
         const int cross = yy >= nyc ? 1 : (yy < 0 ? -1 : 0);
         yy = yy < 0 ? yy + nyc : (yy >= nyc ? yy - nyc : yy);
         int xlo, xhi;
-        shell_window(P, r, cx, cross, delta, xlo, xhi);
-        const int rbase = (zz * nyc + yy) * nxc;
+        shell_window(G, r, cx, cross, delta, xlo, xhi);
+        const int rbase = G.cell_off + (zz * nyc + yy) * nxc;
         int xl = ((xlo % nxc) + nxc) % nxc;
         int span = xhi - xlo + 1;
         for (int part = 0; part < 2 && span > 0; ++part) {
@@ -849,7 +897,7 @@ __device__ void particle_pairs_global(const DevParams &P, int i, double delta, c
             for (int j = jb; j < je; ++j) {
                 const double4 Xj = pa[j];
                 double dx, dy2, dz2, r2;
-                min_image(P, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy2, dz2);
+                min_image(G, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy2, dz2);
                 if (!listed(P, dx, dy2, dz2, Xi.w, Xj.w, r2)) continue;
                 const double4 Vj = vel[j];
                 const double4 Wj = omg[j];
@@ -857,7 +905,7 @@ __device__ void particle_pairs_global(const DevParams &P, int i, double delta, c
                 ++tally.npair;
                 if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
                 PairOut o;
-                evaluate_pair<Real>(P, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
+                evaluate_pair<Real>(P, G.gd, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     f[k] += o.Fi[k];
@@ -882,7 +930,7 @@ __device__ void particle_pairs_global(const DevParams &P, int i, double delta, c
     }
     finish_row(H, P.M, i, fill, idi);
     tally.fill = max(tally.fill, fill);
-    stokes_terms(P, Xi, Vi, Wi, f);
+    stokes_terms(P, G.gd, Xi, Vi, Wi, f);
     store_ft(B.own + 6LL * i, f);
     if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
 }
@@ -953,7 +1001,7 @@ __host__ __device__ inline size_t tile_lds_bytes(int own_cap, int stage_cap, int
 }
 
 template <typename Real>
-__device__ __forceinline__ void tile_pair(const DevParams &P, const HistView &H, const TileShared &T,
+__device__ __forceinline__ void tile_pair(const DevParams &P, const BoxParams &G, const HistView &H, const TileShared &T,
                                           const TileView &V, int il, int jl, double delta,
                                           const double4 *__restrict__ vel, const double4 *__restrict__ omg,
                                           DevClock *clk, int *pair_out, unsigned long long *pair_count,
@@ -962,7 +1010,7 @@ __device__ __forceinline__ void tile_pair(const DevParams &P, const HistView &H,
     const double4 Xi = V.sp[il];
     const double4 Xj = V.sp[jl];
     double dx, dy, dz, r2;
-    min_image(P, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy, dz);
+    min_image(G, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy, dz);
     listed(P, dx, dy, dz, Xi.w, Xj.w, r2);
     const int r = (jl >= T.ro[1]) + (jl >= T.ro[2]) + (jl >= T.ro[3]) + (jl >= T.ro[4]);
     const int gi = T.rs[0] + il;
@@ -975,7 +1023,7 @@ __device__ __forceinline__ void tile_pair(const DevParams &P, const HistView &H,
     ++tally.npair;
     if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
     PairOut o;
-    evaluate_pair<Real>(P, H, gi, gj, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy, dz, r2, tally.S, o);
+    evaluate_pair<Real>(P, G.gd, H, gi, gj, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy, dz, r2, tally.S, o);
     double *ai = V.acc + 6 * il;
     double *aj = V.acc + 6 * jl;
     atomicAdd(ai + 0, o.Fi[0]);
@@ -998,7 +1046,8 @@ __device__ __forceinline__ void tile_pair(const DevParams &P, const HistView &H,
 }
 
 template <typename Real>
-__global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__restrict__ cell_start,
+__global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
+                                                      const int *__restrict__ row_box, const int *__restrict__ cell_start,
                                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                                       const double4 *__restrict__ omg, ForceBufs B, HistView H,
                                                       DevClock *__restrict__ clk, double *__restrict__ partials,
@@ -1016,10 +1065,11 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
     V.rowcnt = V.tpre + 5 * P.own_cap + 1;
 
     const int t = threadIdx.x;
-    const int nxc = P.nc[0], nyc = P.nc[1], nzc = P.nc[2];
-    const int row = blockIdx.x;
+    const BoxParams G = boxes[row_box[blockIdx.x]];
+    const int nxc = G.nc[0], nyc = G.nc[1], nzc = G.nc[2];
+    const int row = blockIdx.x - G.row_off;  // cell row within the box
     const int cz = row / nyc, cy = row - (row / nyc) * nyc;
-    const double delta = le_offset(P, clk->step);
+    const double delta = le_offset(P, G, clk->step);
     PairTally tally;
 #pragma unroll
     for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
@@ -1034,7 +1084,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
         int yy = cy + dy;
         T.rcross[t] = yy >= nyc ? 1 : (yy < 0 ? -1 : 0);
         yy = yy < 0 ? yy + nyc : (yy >= nyc ? yy - nyc : yy);
-        const int base = (zz * nyc + yy) * nxc;
+        const int base = G.cell_off + (zz * nyc + yy) * nxc;
         T.rbase[t] = base;
         T.rs[t] = cell_start[base];
         T.re[t] = cell_start[base + nxc];
@@ -1057,7 +1107,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
     // partner records of the row are zero, partners receive atomic additions instead
     auto row_fallback = [&]() {
         for (int i = T.rs[0] + t; i < T.re[0]; i += kBlock)
-            particle_pairs_global<Real>(P, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, tally);
+            particle_pairs_global<Real>(P, G, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count,
+                                        tally);
         const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int r = 1; r < 5; ++r)
             for (int g = T.rs[r] + t; g < T.re[r]; g += kBlock) store_ft(B.nb + 6LL * ((r - 1) * B.n + g), z);
@@ -1085,9 +1136,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
     for (int task = t; task < ntask; task += kBlock) {
         const int r = task / n_own;
         const int il = task - r * n_own;
-        const int cx = cell_coord(V.sp[il].x, P.cw[0], nxc);
+        const int cx = cell_coord(V.sp[il].x, G.cw[0], nxc);
         int xlo, xhi;
-        shell_window(P, r, cx, T.rcross[r], delta, xlo, xhi);
+        shell_window(G, r, cx, T.rcross[r], delta, xlo, xhi);
         int w = xlo >= 0 ? xlo / nxc : -((-xlo + nxc - 1) / nxc);  // floor(xlo / nx)
         int xl = xlo - w * nxc;
         int span = xhi - xlo + 1;
@@ -1180,11 +1231,11 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
                     j0 = (int)(rg.x & 0xffffu);
                     j1 = (int)(rg.y & 0xffffu);
                     const int cross = (int)(rg.x >> 30) - 1;
-                    sy = cross > 0 ? P.L[1] : (cross < 0 ? -P.L[1] : 0.0);
+                    sy = cross > 0 ? G.L[1] : (cross < 0 ? -G.L[1] : 0.0);
                     sxd = cross > 0 ? delta : (cross < 0 ? -delta : 0.0);
-                    sx0 = (double)((int)((rg.x >> 27) & 7u) - 4) * P.L[0];
-                    sx1 = (double)((int)((rg.y >> 27) & 7u) - 4) * P.L[0];
-                    sz = (rg.y >> 30) ? P.L[2] : 0.0;
+                    sx0 = (double)((int)((rg.x >> 27) & 7u) - 4) * G.L[0];
+                    sx1 = (double)((int)((rg.y >> 27) & 7u) - 4) * G.L[0];
+                    sz = (rg.y >> 30) ? G.L[2] : 0.0;
                 }
                 const int o = k - tb;
                 const bool second = o >= len0;
@@ -1222,8 +1273,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
     const int nq = T.qn;
     for (int q = t; q < nq; q += kBlock) {
         const unsigned e = V.queue[q];
-        tile_pair<Real>(P, H, T, V, (int)(e >> 16), (int)(e & 0xffffu), delta, vel, omg, clk, pair_out, pair_count,
-                        tally);
+        tile_pair<Real>(P, G, H, T, V, (int)(e >> 16), (int)(e & 0xffffu), delta, vel, omg, clk, pair_out,
+                        pair_count, tally);
     }
     __syncthreads();
 
@@ -1236,7 +1287,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
         double f[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) f[c] = V.acc[6 * il + c];
-        stokes_terms(P, Xi, Vi, Wi, f);
+        stokes_terms(P, G.gd, Xi, Vi, Wi, f);
         store_ft(B.own + 6LL * gi, f);
         if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
         const int fill = V.rowcnt[il];
@@ -1255,24 +1306,30 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const int *__r
 }
 
 // ----------------------------------------------------------------------------------
-// k_finish: sum the per-workgroup partial records of k_pairs in a fixed order (so the
-// stress of an evaluation does not depend on scheduling), publish the pair part of the
-// stress and the counters, and store the stress sample of the current time index when the
-// schedule asks for it.  One workgroup of 1024 lanes; lane t loads the records t, t + 1024,
-// ... of every component at once, coalesced (the buffer is padded with zero records).
+// k_finish: per box (one workgroup of 1024 lanes each), sum the partial records of the
+// box's cell rows in a fixed order (so the stress does not depend on scheduling), publish
+// the pair part of the box's stress and its counters, and store the stress sample of the
+// current time index when the schedule asks for it.  Lane t loads the records
+// row_off + t, row_off + t + 1024, ... of every component at once, coalesced.
 // ----------------------------------------------------------------------------------
 template <int R>
-__global__ void __launch_bounds__(1024) k_finish(const double *__restrict__ partials, DevClock *__restrict__ clk,
-                                                  DevRun *__restrict__ run, int sample)
-// partials: 12 components x (1024 R) records
+__global__ void __launch_bounds__(1024) k_finish(const BoxParams *__restrict__ boxes,
+                                                  const double *__restrict__ partials, int pstride,
+                                                  DevClock *__restrict__ clk, DevRun *__restrict__ run, int sample)
+// partials: 12 components x pstride records
 {
     __shared__ double red[16][12];
     const int t = threadIdx.x;
+    const int b = blockIdx.x;
+    const BoxParams &G = boxes[b];
+    const int r0 = G.row_off, nrow = G.nc[1] * G.nc[2];
     double v[R][12];
 #pragma unroll
-    for (int m = 0; m < R; ++m)
+    for (int m = 0; m < R; ++m) {
+        const int w = m * 1024 + t;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) v[m][k] = partials[(long long)k * (1024 * R) + m * 1024 + t];
+        for (int k = 0; k < 12; ++k) v[m][k] = w < nrow ? partials[(long long)k * pstride + r0 + w] : 0.0;
+    }
     double acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = v[0][k];
@@ -1296,18 +1353,14 @@ __global__ void __launch_bounds__(1024) k_finish(const double *__restrict__ part
         double x = 0.0;
         for (int w = 0; w < 16; ++w) x = (t == 11) ? fmax(x, red[w][t]) : x + red[w][t];
         if (t < 9) {
-            run->sigma_last[t] = x;
+            run->sigma_last[9 * b + t] = x;
             const long long n = clk->step;
             if (sample && run->sample_every > 0 && n % run->sample_every == 0 && n >= run->sample_first) {
                 const long long slot = (n - run->sample_first) / run->sample_every;
-                if (slot < run->sample_cap) run->samples[slot * 9 + t] = x;
+                if (slot < run->sample_cap) run->samples[(slot * gridDim.x + b) * 9 + t] = x;
             }
-        } else if (t == 9) {
-            clk->n_pairs = (unsigned long long)x;
-        } else if (t == 10) {
-            clk->n_contacts = (unsigned long long)x;
         } else {
-            clk->max_fill = (int)x;
+            run->box_diag[3 * b + (t - 9)] = x;
         }
     }
 }
@@ -1351,16 +1404,20 @@ __global__ void __launch_bounds__(kBlock) k_unsort(DevParams P, const double4 *_
 // k_load: particles by id -> unsorted records (slot = id), force records cleared.
 __global__ void __launch_bounds__(kBlock) k_load(int N, const double *__restrict__ x, const double *__restrict__ rad,
                                                   const double *__restrict__ u, const double *__restrict__ w,
-                                                  double gd, double4 *__restrict__ pa, double4 *__restrict__ vel,
+                                                  const int *__restrict__ pbox, const BoxParams *__restrict__ boxes,
+                                                  double4 *__restrict__ pa, double4 *__restrict__ vel,
                                                   double4 *__restrict__ omg, ForceBufs B)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
+    const int b = pbox[p];
+    const double gd = boxes[b].gd;
     pa[p] = make_double4(x[3 * p], x[3 * p + 1], x[3 * p + 2], rad[p]);
+    // vel.w carries the particle's box index through every reorder
     if (u)
-        vel[p] = make_double4(u[3 * p], u[3 * p + 1], u[3 * p + 2], 0.0);
+        vel[p] = make_double4(u[3 * p], u[3 * p + 1], u[3 * p + 2], (double)b);
     else
-        vel[p] = make_double4(gd * x[3 * p + 1], 0.0, 0.0, 0.0);
+        vel[p] = make_double4(gd * x[3 * p + 1], 0.0, 0.0, (double)b);
     if (w)
         omg[p] = make_double4(w[3 * p], w[3 * p + 1], w[3 * p + 2], (double)p);
     else

@@ -22,8 +22,8 @@ DSS_FLAG_RECORD_PAIRS = 1
 STATUS = {0: "DSS_OK", 1: "DSS_ERR_ARG", 2: "DSS_ERR_HIP", 3: "DSS_ERR_CAPACITY", 4: "DSS_ERR_BOX",
           5: "DSS_ERR_UNSTABLE", 6: "DSS_ERR_STATE"}
 
-EXPORTS = ["dss_create", "dss_set_particles", "dss_set_step", "dss_build_neighbours", "dss_compute_forces", "dss_step",
-           "dss_read_stress", "dss_get_state", "dss_get_eval_velocities", "dss_get_pairs", "dss_get_cells",
+EXPORTS = ["dss_create", "dss_create_batch", "dss_set_particles", "dss_set_particles_batch", "dss_set_step", "dss_build_neighbours", "dss_compute_forces", "dss_step",
+           "dss_read_stress", "dss_read_stress_batch", "dss_get_box_info", "dss_get_state", "dss_get_eval_velocities", "dss_get_pairs", "dss_get_cells",
            "dss_get_history", "dss_get_info", "dss_save_state", "dss_load_state", "dss_set_timing",
            "dss_get_timing", "dss_last_error",
            "dss_status_string", "dss_destroy"]
@@ -50,6 +50,13 @@ class Info(ctypes.Structure):
                 ("max_row_fill", ctypes.c_int32), ("error_flags", ctypes.c_int32), ("le_offset", ctypes.c_double)]
 
 
+class BoxInfo(ctypes.Structure):
+    _fields_ = [("n_particles", ctypes.c_int64), ("first_id", ctypes.c_int64), ("cells", ctypes.c_int32 * 3),
+                ("first_cell", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("n_contacts", ctypes.c_int64),
+                ("max_row_fill", ctypes.c_int32), ("reserved", ctypes.c_int32), ("L", ctypes.c_double * 3),
+                ("shear_rate", ctypes.c_double), ("le_offset", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -67,7 +74,11 @@ def load_library():
     st = ctypes.c_int
     sig = {
         "dss_create": (st, [ctypes.POINTER(Params), vp, ctypes.POINTER(H)]),
+        "dss_create_batch": (st, [ctypes.POINTER(Params), ctypes.c_int32, vp, ctypes.POINTER(H)]),
         "dss_set_particles": (st, [H, i64, vp, vp, vp, vp, ctypes.c_int]),
+        "dss_set_particles_batch": (st, [H, vp, vp, vp, vp, vp, ctypes.c_int]),
+        "dss_read_stress_batch": (st, [H, vp, vp, ctypes.POINTER(i64)]),
+        "dss_get_box_info": (st, [H, ctypes.c_int32, ctypes.POINTER(BoxInfo)]),
         "dss_set_step": (st, [H, i64]),
         "dss_build_neighbours": (st, [H]),
         "dss_compute_forces": (st, [H]),
@@ -220,10 +231,13 @@ class Simulation:
         p = buf[: n.value]
         return p[np.lexsort((p[:, 1], p[:, 0]))]
 
+    def _ncell_total(self, dims):
+        return int(np.prod(dims))
+
     def cells(self):
         dims = np.zeros(3, np.int32)
         self._check(self.lib.dss_get_cells(self.h, ctypes.c_void_p(dims.ctypes.data), 0, None, None))
-        ncell = int(np.prod(dims))
+        ncell = self._ncell_total(dims)
         cs = np.zeros(ncell + 1, np.int32)
         perm = np.zeros(self.N, np.int32)
         self._check(self.lib.dss_get_cells(self.h, ctypes.c_void_p(dims.ctypes.data), ncell + 1,
@@ -275,3 +289,65 @@ class Simulation:
         return {"n_particles": inf.n_particles, "step": inf.step, "cells": tuple(inf.cells),
                 "capacity": inf.capacity, "n_pairs": inf.n_pairs, "n_contacts": inf.n_contacts,
                 "max_row_fill": inf.max_row_fill, "error_flags": inf.error_flags, "le_offset": inf.le_offset}
+
+
+class Batch(Simulation):
+    """B independent boxes (flow-curve sweep) behind one dss_handle: per-box L and shear rate,
+    one counting sort and one pair launch per step over all boxes, one stress tensor per box.
+    Particle ids run over the boxes in order (box b: ids first_id .. first_id + N_b - 1)."""
+
+    def __init__(self, params_list, precision: int = DSS_FP64, capacity: int = 0, record_pairs: bool = False,
+                 stream=None):
+        self.lib = load_library()
+        self.params_list = [dict(p) for p in params_list]
+        self.params = self.params_list[0]
+        self.B = len(self.params_list)
+        flags = DSS_FLAG_RECORD_PAIRS if record_pairs else 0
+        arr = (Params * self.B)(*[make_params(p, precision, capacity, flags) for p in self.params_list])
+        self._p = arr
+        self.h = ctypes.c_void_p()
+        s = self.lib.dss_create_batch(arr, self.B, ctypes.c_void_p(stream) if stream else None,
+                                      ctypes.byref(self.h))
+        if s != 0:
+            raise DssError(s, "dss_create_batch failed")
+        self.N = 0
+        self.sizes = None
+
+    def set_particles(self, xs, radii, us=None, omegas=None):
+        """xs, radii (, us, omegas): one host array per box."""
+        sizes = np.array([len(r) for r in radii], np.int64)
+        x = np.ascontiguousarray(np.concatenate(xs), np.float64)
+        r = np.ascontiguousarray(np.concatenate(radii), np.float64)
+        u = None if us is None else np.ascontiguousarray(np.concatenate(us), np.float64)
+        w = None if omegas is None else np.ascontiguousarray(np.concatenate(omegas), np.float64)
+        vp = ctypes.c_void_p
+        self._check(self.lib.dss_set_particles_batch(
+            self.h, vp(sizes.ctypes.data), vp(x.ctypes.data), vp(r.ctypes.data),
+            vp(u.ctypes.data) if u is not None else None, vp(w.ctypes.data) if w is not None else None, 0))
+        self.sizes = sizes
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)])
+        self.N = int(sizes.sum())
+
+    def read_stress(self):
+        """(last, mean, n_samples): last and mean are B x 3 x 3."""
+        last = np.zeros(9 * self.B)
+        mean = np.zeros(9 * self.B)
+        ns = ctypes.c_int64(0)
+        self._check(self.lib.dss_read_stress_batch(self.h, last.ctypes.data_as(ctypes.c_void_p),
+                                                   mean.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ns)))
+        return last.reshape(self.B, 3, 3), mean.reshape(self.B, 3, 3), int(ns.value)
+
+    def box_info(self, b):
+        inf = BoxInfo()
+        self._check(self.lib.dss_get_box_info(self.h, int(b), ctypes.byref(inf)))
+        return {"n_particles": inf.n_particles, "first_id": inf.first_id, "cells": tuple(inf.cells),
+                "first_cell": inf.first_cell, "n_pairs": inf.n_pairs, "n_contacts": inf.n_contacts,
+                "max_row_fill": inf.max_row_fill, "L": tuple(inf.L), "shear_rate": inf.shear_rate,
+                "le_offset": inf.le_offset}
+
+    def _ncell_total(self, dims):
+        last = self.box_info(self.B - 1)
+        return int(last["first_cell"] + np.prod(last["cells"]))
+
+    def box_slice(self, b):
+        return slice(int(self.offsets[b]), int(self.offsets[b + 1]))

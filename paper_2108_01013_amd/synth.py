@@ -144,3 +144,29 @@ def config_small(seed: int = 1) -> Workload:
 def config_single_box(seed: int = 2, N: int = 100_000) -> Workload:
     """N = 100k bidisperse (1 : 1.4, equal volumes), phi = 0.55, mu = 1, gdot = 1, dt = 1e-4."""
     return bidisperse_box(N, 0.55, seed)
+
+
+SWEEP_PHI = (0.40, 0.45, 0.50, 0.55, 0.58)
+
+
+def _sweep_box(args):
+    b, n, phi, seed = args
+    return bidisperse_box(int(n), phi, seed=seed + 17 * b)
+
+
+def config_sweep(B: int = 64, seed: int = 3, n_lo: int = 2000, n_hi: int = 50_000, workers: int = 0):
+    """Flow-curve sweep: B bidisperse boxes (1 : 1.4, equal volumes), N_b uniform on
+    {n_lo .. n_hi}, phi_b = SWEEP_PHI[b mod 5], shear rate 10^(-2 + 3 b / (B - 1)) spanning
+    three decades.  Returns (workloads, shear rates).  workers > 1 relaxes the boxes in that
+    many processes (call before any GPU work: the pool forks)."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(n_lo, n_hi + 1, size=B)
+    jobs = [(b, sizes[b], SWEEP_PHI[b % len(SWEEP_PHI)], seed) for b in range(B)]
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            ws = pool.map(_sweep_box, jobs, chunksize=1)
+    else:
+        ws = [_sweep_box(j) for j in jobs]
+    gds = [10.0 ** (-2.0 + 3.0 * b / max(B - 1, 1)) for b in range(B)]
+    return ws, gds

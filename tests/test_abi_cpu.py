@@ -54,3 +54,18 @@ def test_create_rejects_bad_params_without_touching_the_device():
     h = ctypes.c_void_p()
     assert lib.dss_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
     assert not h.value
+
+
+def test_create_batch_rejects_mixed_physics_without_touching_the_device():
+    from paper_2108_01013_amd import dss, synth
+    lib = dss.load_library()
+    a = synth.default_params([10.0, 10.0, 10.0])
+    b = synth.default_params([12.0, 11.0, 13.0], shear_rate=3.0)      # allowed to differ
+    c = synth.default_params([10.0, 10.0, 10.0], eta0=2.0)            # not allowed
+    h = ctypes.c_void_p()
+    arr = (dss.Params * 2)(dss.make_params(a), dss.make_params(c))
+    assert lib.dss_create_batch(arr, 2, None, ctypes.byref(h)) == 1
+    assert not h.value
+    arr = (dss.Params * 2)(dss.make_params(a), dss.make_params(b))
+    assert lib.dss_create_batch(arr, 0, None, ctypes.byref(h)) == 1
+    assert ctypes.sizeof(dss.BoxInfo) == 8 + 8 + 12 + 4 + 8 + 8 + 4 + 4 + 24 + 8 + 8
