@@ -52,9 +52,25 @@ def cpu_baseline(w, seconds: float = 10.0, label: str = "the same"):
                       f"(N={N}), {el:.1f} s"}
 
 
+def maybe_tune(sim, args):
+    """Autotune the launch (its trial steps are ordinary steps, before the warm-up)."""
+    if not args.tune:
+        return None
+    import tempfile
+
+    from paper_2108_01013_amd import tune
+    path = args.tune_cache or os.path.join(tempfile.gettempdir(), "dss_tuning_bench.json")
+    rec = tune.autotune(sim, trial_steps=args.tune_steps, cache_path=path,
+                        log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    return {"choice": rec["tuning"], "ms_per_step": round(rec["ms_per_step"], 5), "cached": rec["cached"],
+            "trials": [{"tuning": t["tuning"], "ms_per_step": round(t["ms_per_step"], 5)}
+                       for t in rec.get("trials", [])]}
+
+
 def timed_run(sim, N, args, stress_every):
     """Warm-up, then the timed region with HIP events around k_pairs; then an untimed
-    per-kernel breakdown.  Returns (seconds, k_pairs timing, breakdown)."""
+    per-kernel breakdown (kernel timing replaces graph replay by direct launches).
+    Returns (seconds, k_pairs timing, breakdown)."""
     import torch
     sim.step(args.warmup, stress_every=stress_every, sync=True)
     torch.cuda.synchronize()
@@ -103,6 +119,7 @@ def run_single(args):
     sim = Simulation(p, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
     sim.set_particles(w.x, w.rad)
     N = len(w.rad)
+    tuned = maybe_tune(sim, args)
     el, timing, breakdown = timed_run(sim, N, args, 10)
     info = sim.info()
     _, sigma_mean, nsamp = sim.read_stress()
@@ -123,6 +140,7 @@ def run_single(args):
         "roofline": roofline(timing, N, ncell, info["n_contacts"], info["capacity"]),
         "cpu_baseline": cpu,
         "kernels": kernel_table(breakdown),
+        "tuning": tuned or sim.tuning(),
         "diagnostics": {"n_pairs": info["n_pairs"], "n_contacts": info["n_contacts"],
                         "max_row_fill": info["max_row_fill"], "capacity": info["capacity"],
                         "cells": info["cells"], "stress_samples": nsamp,
@@ -148,6 +166,7 @@ def run_sweep(args):
     sim = Batch(params, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
     sim.set_particles([w.x for w in ws], [w.rad for w in ws])
     N = sim.N
+    tuned = maybe_tune(sim, args)
     el, timing, breakdown = timed_run(sim, N, args, 10)
     info = sim.info()
     _, sigma_mean, nsamp = sim.read_stress()
@@ -173,6 +192,7 @@ def run_sweep(args):
         "roofline": roofline(timing, N, ncell, info["n_contacts"], info["capacity"]),
         "cpu_baseline": cpu,
         "kernels": kernel_table(breakdown),
+        "tuning": tuned or sim.tuning(),
         "diagnostics": {"n_pairs": info["n_pairs"], "n_contacts": info["n_contacts"],
                         "max_row_fill": info["max_row_fill"], "capacity": info["capacity"],
                         "cells_total": ncell, "stress_samples": nsamp,
@@ -191,9 +211,15 @@ def main():
     ap.add_argument("--N", type=int, default=100_000)
     ap.add_argument("--boxes", type=int, default=64)
     ap.add_argument("--workers", type=int, default=16, help="processes generating the sweep's boxes")
+    ap.add_argument("--tune", type=int, default=None,
+                    help="1: autotune the launch first (default: on for the sweep, off for one box)")
+    ap.add_argument("--tune-steps", type=int, default=20)
+    ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
+    if args.tune is None:
+        args.tune = 1 if args.mode == "sweep" else 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the design of a "

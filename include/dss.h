@@ -144,6 +144,31 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
 dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, const double *x, const double *radius,
                                    const double *u, const double *omega, int on_device);
 
+/* Launch tuning of a handle.  None of these changes results: the pair set, forces and
+ * stress do not depend on them (the summation order of the force atomics aside).
+ *   cell_scale: lattice spacing = cell_scale x the box's largest pair cutoff (>= 1, <= 4;
+ *               1 = the smallest legal cells); larger cells mean fewer, fuller cell rows;
+ *   tile_scale: scale (0.25 .. 4) of the k_pairs row-tile capacities, which are sized from
+ *               the mean occupancy of a cell row; rows beyond them take the per-particle path;
+ *   tiled:      1 = stage cell rows in LDS; 0 = every row takes the per-particle path;
+ *   graph:      1 = dss_step replays HIP graphs of one time step (captured on first use;
+ *               not while kernel timing is on or pairs are recorded).
+ * Defaults: {1, 1, 1, 1}.  reserved must be 0. */
+typedef struct {
+    double cell_scale;
+    double tile_scale;
+    int32_t tiled;
+    int32_t graph;
+    int32_t reserved[4];
+} dss_tuning;
+
+/* Set the launch tuning.  Before dss_set_particles it applies to the first lattice; after,
+ * a new lattice takes effect at the counting sort of the next dss_step (dss_compute_forces
+ * before that step still uses the current one).  Fails with DSS_ERR_ARG for values out of
+ * range and DSS_ERR_BOX when a loaded box would get fewer than 4 x 3 x 3 cells. */
+dss_status dss_set_tuning(dss_handle *h, const dss_tuning *t);
+dss_status dss_get_tuning(dss_handle *h, dss_tuning *t);
+
 /* Set the time index n of the current state (t = n dt; the Lees-Edwards offset follows
  * eq. le).  Forces are not re-evaluated: call dss_compute_forces afterwards.  For restarts
  * and for tests of the sheared boundary at arbitrary offsets.  Fails with DSS_ERR_ARG for

@@ -36,6 +36,14 @@ struct dss_handle {
     int *tile_sum = nullptr;          // totals of the multi-workgroup scan
     int ncell_total = 0, nrow_total = 0;
     int scan_tiles = 0;               // 0: one-workgroup scan (scan_c4), else workgroups of 16384 cells
+    std::vector<double> box_amax;     // largest radius per box
+    double max_mean_row = 0.0;        // mean particles per cell row of the densest box
+    dss_tuning tune{1.0, 1.0, 1, 1, {0, 0, 0, 0}};
+    bool tune_pending = false;        // lattice to rebuild before the next time step
+    // HIP graphs of one time step, keyed by (current buffers, committed history buffers,
+    // half-step velocities, stress summation)
+    hipGraphExec_t graph[16] = {};
+    bool graph_broken = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
@@ -111,11 +119,32 @@ hipError_t dalloc(T **p, size_t n)
     return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
 }
 
+void destroy_graphs(dss_handle *h)
+{
+    for (auto &g : h->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+void free_lattice(dss_handle *h)
+{
+    auto F = [](void *p) {
+        if (p) (void)hipFree(p);
+    };
+    destroy_graphs(h);
+    F(h->count); F(h->cell_start); F(h->tile_sum); F(h->partials); F(h->d_boxes); F(h->d_row_box);
+    h->count = h->cell_start = h->tile_sum = h->d_row_box = nullptr;
+    h->partials = nullptr;
+    h->d_boxes = nullptr;
+}
+
 void free_all(dss_handle *h)
 {
     auto F = [](void *p) {
         if (p) (void)hipFree(p);
     };
+    free_lattice(h);
     for (int k = 0; k < 2; ++k) {
         F(h->pa[k]); F(h->vel[k]); F(h->omg[k]);
         F(h->hkey[k]); F(h->hcnt[k]); F(h->hown[k]); F(h->hxi[k]);
@@ -124,19 +153,17 @@ void free_all(dss_handle *h)
         h->hxi[k] = nullptr;
     }
     F(h->ft_own); F(h->ft_nb); F(h->ft_x); F(h->prev);
-    F(h->cell); F(h->rank); F(h->count); F(h->cell_start);
-    F(h->pairs); F(h->pair_count); F(h->clk); F(h->run); F(h->sigma_last); F(h->samples); F(h->partials);
-    F(h->d_boxes); F(h->d_row_box); F(h->box_diag); F(h->tile_sum);
-    h->d_boxes = nullptr;
-    h->d_row_box = h->tile_sum = nullptr;
+    F(h->cell); F(h->rank);
+    F(h->pairs); F(h->pair_count); F(h->clk); F(h->run); F(h->sigma_last); F(h->samples);
+    F(h->box_diag);
     h->box_diag = nullptr;
     h->ft_own = h->ft_nb = h->ft_x = nullptr;
     h->prev = nullptr;
-    h->cell = h->rank = h->count = h->cell_start = h->pairs = nullptr;
+    h->cell = h->rank = h->pairs = nullptr;
     h->pair_count = nullptr;
     h->clk = nullptr;
     h->run = nullptr;
-    h->sigma_last = h->samples = h->partials = nullptr;
+    h->sigma_last = h->samples = nullptr;
     h->sample_cap_alloc = 0;
     h->loaded = false;
 }
@@ -229,6 +256,129 @@ dss_status require_loaded(dss_handle *h)
     return DSS_OK;
 }
 
+// Cell lattice of every box: spacing >= cell_scale times the box's largest pair cutoff
+// 2 c a_max (with a 1e-9 margin), boxes numbered one after the other.  Returns false (and
+// why) when a box has fewer than 4 x 3 x 3 cells or more than 4096 cell rows.
+bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, double cf, double cell_scale,
+                std::string &why)
+{
+    int64_t ncell = 0;
+    int nrow = 0;
+    for (size_t b = 0; b < boxes.size(); ++b) {
+        BoxParams &G = boxes[b];
+        const double rc = cf * 2.0 * amax[b] * (1.0 + 1e-9) * cell_scale;
+        for (int d = 0; d < 3; ++d) {
+            G.nc[d] = std::max(1, (int)std::floor(G.L[d] / rc));
+            G.cw[d] = G.L[d] / (double)G.nc[d];
+        }
+        if (G.nc[0] < 4 || G.nc[1] < 3 || G.nc[2] < 3) {
+            why = "cell lattice " + std::to_string(G.nc[0]) + "x" + std::to_string(G.nc[1]) + "x" +
+                  std::to_string(G.nc[2]) + " of box " + std::to_string(b) + " is smaller than 4x3x3";
+            return false;
+        }
+        const int rows = G.nc[1] * G.nc[2];
+        if (rows > 4096) {
+            why = "more than 4096 cell rows in box " + std::to_string(b);
+            return false;
+        }
+        G.cell_off = (int)ncell;
+        G.row_off = nrow;
+        ncell += (int64_t)G.nc[0] * rows;
+        nrow += rows;
+        if (ncell > (int64_t)0x3fffffff) {
+            why = "too many cells";
+            return false;
+        }
+    }
+    return true;
+}
+
+// (Re)build everything that depends on the cell lattice: the box table, the cell-row ->
+// box map, cell counts and starts, the scan layout, the per-row stress partials and the
+// row-tile capacities of k_pairs.  The particles keep their slots; the next counting sort
+// uses the new lattice.
+dss_status setup_lattice(dss_handle *h)
+{
+    std::string why;
+    if (!lattice_of(h->boxes, h->box_amax, h->prm.cutoff_factor, h->tune.cell_scale, why))
+        return fail(h, DSS_ERR_BOX, why);
+    free_lattice(h);
+    const int B = h->nbox;
+    int64_t ncell = 0;
+    int nrow = 0, max_rows_box = 0;
+    double max_mean_row = 0.0;
+    std::vector<int> row_box;
+    for (int b = 0; b < B; ++b) {
+        const BoxParams &G = h->boxes[b];
+        const int rows = G.nc[1] * G.nc[2];
+        row_box.insert(row_box.end(), rows, b);
+        ncell += (int64_t)G.nc[0] * rows;
+        nrow += rows;
+        max_rows_box = std::max(max_rows_box, rows);
+        max_mean_row = std::max(max_mean_row, (double)G.n_part / (double)rows);
+    }
+    // cell-count scan: one workgroup up to 65535 cells, else workgroups of 16384 cells
+    int64_t ncell_pad;
+    if (ncell + 1 <= 4096 * 16) {
+        h->scan_c4 = (int)((ncell + 1 + 4095) / 4096);
+        h->scan_tiles = 0;
+        ncell_pad = 4096 * (int64_t)h->scan_c4;
+    } else {
+        h->scan_c4 = 0;
+        h->scan_tiles = (int)((ncell + 1 + 16383) / 16384);
+        ncell_pad = 16384 * (int64_t)h->scan_tiles;
+    }
+    h->ncell_total = (int)ncell;
+    h->nrow_total = nrow;
+    h->max_mean_row = max_mean_row;
+    // row-tile capacities of k_pairs from the mean occupancy of a cell row (own row and the
+    // five rows of the half shell) of the densest box, times tile_scale; rows beyond them
+    // take the per-particle path, which every row takes when tiling is off
+    DevParams &P = h->P;
+    {
+        const double mean_row = max_mean_row * h->tune.tile_scale;
+        auto up = [](double v, int m) { return ((int)std::ceil(v) + m - 1) / m * m; };
+        int own_cap = up(1.5 * mean_row + 16.0, 32);
+        int stage_cap = up(6.25 * mean_row + 32.0, 64);
+        int qcap = up(8.0 * mean_row + 64.0, 64);
+        const size_t lds_max = 150 * 1024;
+        while (tile_lds_bytes(own_cap, stage_cap, qcap) > lds_max && own_cap > 32) {
+            own_cap = std::max(32, own_cap * 3 / 4 / 32 * 32);
+            stage_cap = std::max(64, stage_cap * 3 / 4 / 64 * 64);
+            qcap = std::max(64, qcap * 3 / 4 / 64 * 64);
+        }
+        own_cap = std::min(own_cap, 4096);
+        stage_cap = std::min(stage_cap, 65535 / 64 * 64);
+        if (!h->tune.tiled) {
+            own_cap = 32;
+            stage_cap = 64;
+            qcap = 64;
+        }
+        h->tile_lds = tile_lds_bytes(own_cap, stage_cap, qcap);
+        P.own_cap = own_cap;
+        P.tiled = h->tune.tiled ? 1 : 0;
+        P.stage_cap = stage_cap;
+        P.qcap = qcap;
+    }
+    HIPTRY(hipFuncSetAttribute((const void *)k_pairs<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)h->tile_lds));
+    HIPTRY(hipFuncSetAttribute((const void *)k_pairs<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)h->tile_lds));
+    h->finish_r = (max_rows_box + 1023) / 1024;
+    P.pstride = (nrow + 63) / 64 * 64;
+    HIPTRY(dalloc(&h->count, ncell_pad));
+    HIPTRY(dalloc(&h->cell_start, ncell_pad));
+    HIPTRY(dalloc(&h->tile_sum, std::max(h->scan_tiles, 1)));
+    HIPTRY(dalloc(&h->partials, 12 * (size_t)P.pstride));
+    HIPTRY(dalloc(&h->d_boxes, B));
+    HIPTRY(dalloc(&h->d_row_box, nrow));
+    HIPTRY(hipMemcpyAsync(h->d_boxes, h->boxes.data(), B * sizeof(BoxParams), hipMemcpyHostToDevice, h->stream));
+    HIPTRY(hipMemcpyAsync(h->d_row_box, row_box.data(), nrow * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIPTRY(hipMemsetAsync(h->partials, 0, 12 * (size_t)P.pstride * sizeof(double), h->stream));
+    HIPTRY(hipMemsetAsync(h->count, 0, ncell_pad * sizeof(int), h->stream));
+    return DSS_OK;
+}
+
 // One force evaluation.
 //   EVAL_STEP:    a full time step: drift + kick, counting sort, pairs; history committed.
 //   EVAL_SORT:    counting sort of the current positions, then pairs (initial evaluation).
@@ -272,6 +422,18 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, boo
     }
 #undef DSS_FINISH
     return DSS_OK;
+}
+
+// Host bookkeeping after an evaluation: the particles now live in the other buffers; a
+// time step commits the new history rows and advances the clock.
+void commit_eval(dss_handle *h, bool advance)
+{
+    h->cur = 1 - h->cur;
+    h->vel_is_half = advance;
+    if (advance) {
+        h->hh = 1 - h->hh;
+        h->step += 1;
+    }
 }
 
 dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
@@ -327,12 +489,43 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
     dss_status s = launch_pairs(h, o, h->prev, advance, finish);
     if (s) return s;
     HIPTRY(hipGetLastError());
-    h->cur = o;
-    h->vel_is_half = advance != 0;
-    if (advance) {
-        h->hh = 1 - h->hh;
-        h->step += 1;
+    commit_eval(h, advance != 0);
+    return DSS_OK;
+}
+
+// One time step through a HIP graph: captured on first use of its key, replayed after.
+// Graphs are used only without kernel timing and pair recording (the pair counter reset is
+// a memset, which is not recorded into graphs).
+dss_status graph_step(dss_handle *h, bool finish)
+{
+    const int key = h->cur | (h->hh << 1) | ((h->vel_is_half ? 1 : 0) << 2) | ((finish ? 1 : 0) << 3);
+    if (!h->graph[key]) {
+        hipGraph_t g = nullptr;
+        const int cur = h->cur, hh = h->hh;
+        const bool vih = h->vel_is_half;
+        const int64_t step = h->step;
+        HIPTRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        dss_status s = evaluate(h, EVAL_STEP, finish);
+        hipError_t e = hipStreamEndCapture(h->stream, &g);
+        // the capture recorded the launches without running them
+        h->cur = cur;
+        h->hh = hh;
+        h->vel_is_half = vih;
+        h->step = step;
+        if (s) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return fail(h, DSS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&h->graph[key], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            h->graph[key] = nullptr;
+            return fail(h, DSS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
     }
+    HIPTRY(hipGraphLaunch(h->graph[key], h->stream));
+    commit_eval(h, true);
     return DSS_OK;
 }
 
@@ -455,62 +648,29 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
         std::memcpy(hr.data(), radius, N * sizeof(double));
     }
     std::vector<BoxParams> boxes(B);
-    std::vector<double> box_sa3(B, 0.0);
+    std::vector<double> box_sa3(B, 0.0), box_amax(B, 0.0);
     std::vector<int> pbox(N);
-    std::vector<int> row_box;
-    double a_min = INFINITY, a_max = 0.0, max_mean_row = 0.0;
-    int64_t ncell = 0, part = 0;
-    int nrow = 0, max_rows_box = 0;
+    double a_min = INFINITY, a_max = 0.0;
+    int64_t part = 0;
     for (int b = 0; b < B; ++b) {
         const dss_params &q = h->bprm[b];
         BoxParams &G = boxes[b];
-        double bmax = 0.0;
         for (int64_t i = part; i < part + n_per_box[b]; ++i) {
             if (!(hr[i] > 0.0) || !std::isfinite(hr[i])) return fail(h, DSS_ERR_ARG, "radius must be finite and > 0");
             a_min = std::min(a_min, hr[i]);
-            bmax = std::max(bmax, hr[i]);
+            box_amax[b] = std::max(box_amax[b], hr[i]);
             box_sa3[b] += hr[i] * hr[i] * hr[i];
             for (int d = 0; d < 3; ++d)
                 if (!(hx[3 * i + d] >= 0.0 && hx[3 * i + d] < q.L[d]))
                     return fail(h, DSS_ERR_ARG, "position outside [0, L) for particle " + std::to_string(i));
             pbox[i] = b;
         }
-        a_max = std::max(a_max, bmax);
-        // lattice: spacing >= the largest cutoff 2 c a_max of the box (with a 1e-9 margin)
-        const double rc = p.cutoff_factor * 2.0 * bmax * (1.0 + 1e-9);
-        for (int d = 0; d < 3; ++d) {
-            G.L[d] = q.L[d];
-            G.nc[d] = std::max(1, (int)std::floor(q.L[d] / rc));
-            G.cw[d] = q.L[d] / (double)G.nc[d];
-        }
+        a_max = std::max(a_max, box_amax[b]);
+        for (int d = 0; d < 3; ++d) G.L[d] = q.L[d];
         G.gd = q.shear_rate;
-        if (G.nc[0] < 4 || G.nc[1] < 3 || G.nc[2] < 3)
-            return fail(h, DSS_ERR_BOX, "cell lattice " + std::to_string(G.nc[0]) + "x" + std::to_string(G.nc[1]) +
-                                            "x" + std::to_string(G.nc[2]) + " of box " + std::to_string(b) +
-                                            " is smaller than 4x3x3");
-        const int rows = G.nc[1] * G.nc[2];
-        if (rows > 4096) return fail(h, DSS_ERR_BOX, "more than 4096 cell rows in box " + std::to_string(b));
-        G.cell_off = (int)ncell;
-        G.row_off = nrow;
         G.part_off = (int)part;
         G.n_part = (int)n_per_box[b];
-        ncell += (int64_t)G.nc[0] * rows;
-        if (ncell > (int64_t)0x3fffffff) return fail(h, DSS_ERR_BOX, "too many cells");
-        nrow += rows;
-        row_box.insert(row_box.end(), rows, b);
-        max_rows_box = std::max(max_rows_box, rows);
-        max_mean_row = std::max(max_mean_row, (double)n_per_box[b] / (double)rows);
         part += n_per_box[b];
-    }
-    // cell-count scan: one workgroup up to 65535 cells, else workgroups of 16384 cells
-    int scan_c4 = 0, scan_tiles = 0;
-    int64_t ncell_pad;
-    if (ncell + 1 <= 4096 * 16) {
-        scan_c4 = (int)((ncell + 1 + 4095) / 4096);
-        ncell_pad = 4096 * (int64_t)scan_c4;
-    } else {
-        scan_tiles = (int)((ncell + 1 + 16383) / 16384);
-        ncell_pad = 16384 * (int64_t)scan_tiles;
     }
     DevParams P{};
     P.eta0 = p.eta0; P.rho = p.rho; P.kn = p.kn; P.kt = p.kt; P.gn = p.gamma_n;
@@ -524,43 +684,21 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     P.N = (int)N;
     P.M = p.capacity > 0 ? p.capacity : paper_capacity(a_max, a_min);
     P.record_pairs = (p.flags & DSS_FLAG_RECORD_PAIRS) ? 1 : 0;
-    // row-tile capacities of k_pairs from the mean occupancy of a cell row (own row and the
-    // five rows of the half shell) of the densest box; rows beyond them take the
-    // per-particle path
-    {
-        const double mean_row = max_mean_row;
-        auto up = [](double v, int m) { return ((int)std::ceil(v) + m - 1) / m * m; };
-        int own_cap = up(1.5 * mean_row + 16.0, 32);
-        int stage_cap = up(6.25 * mean_row + 32.0, 64);
-        int qcap = up(8.0 * mean_row + 64.0, 64);
-        const size_t lds_max = 150 * 1024;
-        while (tile_lds_bytes(own_cap, stage_cap, qcap) > lds_max && own_cap > 32) {
-            own_cap = std::max(32, own_cap * 3 / 4 / 32 * 32);
-            stage_cap = std::max(64, stage_cap * 3 / 4 / 64 * 64);
-            qcap = std::max(64, qcap * 3 / 4 / 64 * 64);
-        }
-        own_cap = std::min(own_cap, 4096);
-        stage_cap = std::min(stage_cap, 65535 / 64 * 64);
-        P.own_cap = own_cap;
-        P.stage_cap = stage_cap;
-        P.qcap = qcap;
-    }
     P.pair_cap = P.record_pairs ? 32 * N + 64 : 0;
+    // the lattice is checked before anything is freed or allocated
+    {
+        std::vector<BoxParams> trial = boxes;
+        std::string why;
+        if (!lattice_of(trial, box_amax, p.cutoff_factor, h->tune.cell_scale, why))
+            return fail(h, DSS_ERR_BOX, why);
+    }
 
     free_all(h);
     h->P = P;
     h->boxes = boxes;
     h->box_n.assign(n_per_box, n_per_box + B);
     h->box_sa3 = box_sa3;
-    h->ncell_total = (int)ncell;
-    h->nrow_total = nrow;
-    h->scan_c4 = scan_c4;
-    h->scan_tiles = scan_tiles;
-    h->tile_lds = tile_lds_bytes(P.own_cap, P.stage_cap, P.qcap);
-    HIPTRY(hipFuncSetAttribute((const void *)k_pairs<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)h->tile_lds));
-    HIPTRY(hipFuncSetAttribute((const void *)k_pairs<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)h->tile_lds));
+    h->box_amax = box_amax;
     h->N = N;
     const size_t rows = (size_t)N * (size_t)P.M;
     for (int k = 0; k < 2; ++k) {
@@ -578,26 +716,14 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     HIPTRY(dalloc(&h->prev, N));
     HIPTRY(dalloc(&h->cell, N));
     HIPTRY(dalloc(&h->rank, N));
-    HIPTRY(dalloc(&h->count, ncell_pad));
-    HIPTRY(dalloc(&h->cell_start, ncell_pad));
-    HIPTRY(dalloc(&h->tile_sum, std::max(scan_tiles, 1)));
     HIPTRY(dalloc(&h->pairs, P.record_pairs ? 2 * P.pair_cap : 2));
     HIPTRY(dalloc(&h->pair_count, 1));
     HIPTRY(dalloc(&h->clk, 1));
     HIPTRY(dalloc(&h->run, 1));
     HIPTRY(dalloc(&h->sigma_last, 9 * (size_t)B));
     HIPTRY(dalloc(&h->box_diag, 3 * (size_t)B));
-    HIPTRY(dalloc(&h->d_boxes, B));
-    HIPTRY(dalloc(&h->d_row_box, nrow));
-    HIPTRY(hipMemcpyAsync(h->d_boxes, boxes.data(), B * sizeof(BoxParams), hipMemcpyHostToDevice, h->stream));
-    HIPTRY(hipMemcpyAsync(h->d_row_box, row_box.data(), nrow * sizeof(int), hipMemcpyHostToDevice, h->stream));
-    {
-        h->finish_r = (max_rows_box + 1023) / 1024;
-        h->P.pstride = (nrow + 63) / 64 * 64;
-        HIPTRY(dalloc(&h->partials, 12 * (size_t)h->P.pstride));
-        HIPTRY(hipMemsetAsync(h->partials, 0, 12 * (size_t)h->P.pstride * sizeof(double), h->stream));
-    }
-    HIPTRY(hipMemsetAsync(h->count, 0, ncell_pad * sizeof(int), h->stream));
+    dss_status ls = setup_lattice(h);
+    if (ls) return ls;
     HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
     HIPTRY(hipMemsetAsync(h->clk, 0, sizeof(DevClock), h->stream));
     HIPTRY(hipMemsetAsync(h->sigma_last, 0, 9 * (size_t)B * sizeof(double), h->stream));
@@ -634,6 +760,7 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     h->hh = 0;
     h->step = 0;
     h->vel_is_half = false;
+    h->tune_pending = false;
     const int grid = (int)((N + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_load, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, dx, dr, du, dw, dpb, h->d_boxes,
                        h->pa[0], h->vel[0], h->omg[0], h->fb());
@@ -657,6 +784,35 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
     if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "a batch handle takes dss_set_particles_batch");
     if (N < 1 || N > (int64_t)0x3fffffff || !x || !radius) return fail(h, DSS_ERR_ARG, "N < 1 or null x / radius");
     return dss_set_particles_batch(h, &N, x, radius, u, omega, on_device);
+}
+
+dss_status dss_set_tuning(dss_handle *h, const dss_tuning *t)
+{
+    if (!h || !t) return DSS_ERR_ARG;
+    if (!(t->cell_scale >= 1.0 && t->cell_scale <= 4.0) || !(t->tile_scale >= 0.25 && t->tile_scale <= 4.0) ||
+        (t->tiled != 0 && t->tiled != 1) || (t->graph != 0 && t->graph != 1) || t->reserved[0] || t->reserved[1] ||
+        t->reserved[2] || t->reserved[3])
+        return fail(h, DSS_ERR_ARG, "tuning out of range (cell_scale in [1, 4], tile_scale in [0.25, 4], flags 0/1)");
+    if (h->loaded) {
+        // the lattice must still be legal for every box
+        std::vector<BoxParams> trial = h->boxes;
+        std::string why;
+        if (!lattice_of(trial, h->box_amax, h->prm.cutoff_factor, t->cell_scale, why))
+            return fail(h, DSS_ERR_BOX, why);
+    }
+    const bool lattice = t->cell_scale != h->tune.cell_scale || t->tile_scale != h->tune.tile_scale ||
+                         t->tiled != h->tune.tiled;
+    h->tune = *t;
+    if (!t->graph) destroy_graphs(h);
+    if (h->loaded && lattice) h->tune_pending = true;
+    return DSS_OK;
+}
+
+dss_status dss_get_tuning(dss_handle *h, dss_tuning *t)
+{
+    if (!h || !t) return DSS_ERR_ARG;
+    *t = h->tune;
+    return DSS_OK;
 }
 
 dss_status dss_set_step(dss_handle *h, int64_t n)
@@ -717,11 +873,18 @@ dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sy
     h->run_host.box_diag = h->box_diag;
     HIPTRY(hipMemcpyAsync(h->run, &h->run_host, sizeof(DevRun), hipMemcpyHostToDevice, h->stream));
     h->last_samples = cap;
+    if (h->tune_pending && n_steps > 0) {
+        // a new lattice takes effect at the counting sort of this step
+        s = setup_lattice(h);
+        if (s) return s;
+        h->tune_pending = false;
+    }
+    const bool graphs = h->tune.graph && !h->graph_broken && h->timing == 0 && !h->P.record_pairs;
     for (int64_t k = 0; k < n_steps; ++k) {
         // the stress and counters are summed only when a sample is due and after the last step
         const int64_t n_next = h->step + 1;
         const bool finish = k == n_steps - 1 || (stress_every > 0 && n_next % stress_every == 0);
-        s = evaluate(h, EVAL_STEP, finish);
+        s = graphs ? graph_step(h, finish) : evaluate(h, EVAL_STEP, finish);
         if (s) return s;
     }
     if (sync) return check_flags(h);

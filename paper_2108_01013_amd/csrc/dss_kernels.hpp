@@ -39,6 +39,7 @@ struct DevParams {
     int record_pairs;
     long long pair_cap;
     int own_cap, stage_cap, qcap;   // row-tile capacities of k_pairs
+    int tiled;                      // 0: every row takes the per-particle path
     int pstride;                    // stride of the partial records (1024 R)
 };
 
@@ -1114,7 +1115,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const BoxParam
             for (int g = T.rs[r] + t; g < T.re[r]; g += kBlock) store_ft(B.nb + 6LL * ((r - 1) * B.n + g), z);
         reduce_tally(tally, T.red, partials, P.pstride);
     };
-    if (n_own > P.own_cap || total > P.stage_cap) {
+    if (!P.tiled || n_own > P.own_cap || total > P.stage_cap) {
         row_fallback();
         return;
     }

@@ -25,7 +25,7 @@ STATUS = {0: "DSS_OK", 1: "DSS_ERR_ARG", 2: "DSS_ERR_HIP", 3: "DSS_ERR_CAPACITY"
 EXPORTS = ["dss_create", "dss_create_batch", "dss_set_particles", "dss_set_particles_batch", "dss_set_step", "dss_build_neighbours", "dss_compute_forces", "dss_step",
            "dss_read_stress", "dss_read_stress_batch", "dss_get_box_info", "dss_get_state", "dss_get_eval_velocities", "dss_get_pairs", "dss_get_cells",
            "dss_get_history", "dss_get_info", "dss_save_state", "dss_load_state", "dss_set_timing",
-           "dss_get_timing", "dss_last_error",
+           "dss_get_timing", "dss_set_tuning", "dss_get_tuning", "dss_last_error",
            "dss_status_string", "dss_destroy"]
 
 
@@ -55,6 +55,11 @@ class BoxInfo(ctypes.Structure):
                 ("first_cell", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("n_contacts", ctypes.c_int64),
                 ("max_row_fill", ctypes.c_int32), ("reserved", ctypes.c_int32), ("L", ctypes.c_double * 3),
                 ("shear_rate", ctypes.c_double), ("le_offset", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("cell_scale", ctypes.c_double), ("tile_scale", ctypes.c_double), ("tiled", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 _lib = None
@@ -94,6 +99,8 @@ def load_library():
         "dss_load_state": (st, [H, vp, ctypes.c_size_t]),
         "dss_set_timing": (st, [H, ctypes.c_int]),
         "dss_get_timing": (st, [H, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+        "dss_set_tuning": (st, [H, ctypes.POINTER(Tuning)]),
+        "dss_get_tuning": (st, [H, ctypes.POINTER(Tuning)]),
         "dss_last_error": (ctypes.c_char_p, [H]),
         "dss_status_string": (ctypes.c_char_p, [st]),
         "dss_destroy": (None, [H]),
@@ -152,6 +159,7 @@ class Simulation:
         if s != 0:
             raise DssError(s, "dss_create failed")
         self.N = 0
+        self.precision = int(precision)
 
     def _check(self, s):
         if s != 0:
@@ -181,6 +189,14 @@ class Simulation:
         N = (kr.numel() if _is_torch(kr) else kr.size)
         self._check(self.lib.dss_set_particles(self.h, int(N), px, pr, pu, pw, int(dev)))
         self.N = int(N)
+        rad = (kr.detach().cpu().numpy() if _is_torch(kr) else kr)
+        self._set_class([rad], [self.params])
+
+    def _set_class(self, radii, params):
+        """Volume fraction and size ratio of the loaded boxes (the autotuner's workload class)."""
+        phis = [float(np.sum(r ** 3)) * 4.0 * np.pi / 3.0 / float(np.prod(p["L"])) for r, p in zip(radii, params)]
+        self.phi_mean = float(np.mean(phis))
+        self.size_ratio = float(max(np.max(r) for r in radii) / min(np.min(r) for r in radii))
 
     def set_step(self, n):
         self._check(self.lib.dss_set_step(self.h, int(n)))
@@ -263,6 +279,26 @@ class Simulation:
 
     KERNELS = ("k_predict", "k_scan", "k_scatter", "k_pairs", "k_finish")
 
+    def set_tuning(self, cell_scale=None, tile_scale=None, tiled=None, graph=None):
+        """Change launch tuning (results do not depend on it); unspecified fields keep their value."""
+        t = Tuning()
+        self._check(self.lib.dss_get_tuning(self.h, ctypes.byref(t)))
+        if cell_scale is not None:
+            t.cell_scale = float(cell_scale)
+        if tile_scale is not None:
+            t.tile_scale = float(tile_scale)
+        if tiled is not None:
+            t.tiled = int(bool(tiled))
+        if graph is not None:
+            t.graph = int(bool(graph))
+        self._check(self.lib.dss_set_tuning(self.h, ctypes.byref(t)))
+
+    def tuning(self):
+        t = Tuning()
+        self._check(self.lib.dss_get_tuning(self.h, ctypes.byref(t)))
+        return {"cell_scale": t.cell_scale, "tile_scale": t.tile_scale, "tiled": bool(t.tiled),
+                "graph": bool(t.graph)}
+
     def set_timing(self, enable=True, kernels=None):
         """Time the named kernels (all if None) with HIP events; enable=False stops."""
         if not enable:
@@ -312,6 +348,7 @@ class Batch(Simulation):
             raise DssError(s, "dss_create_batch failed")
         self.N = 0
         self.sizes = None
+        self.precision = int(precision)
 
     def set_particles(self, xs, radii, us=None, omegas=None):
         """xs, radii (, us, omegas): one host array per box."""
@@ -327,6 +364,7 @@ class Batch(Simulation):
         self.sizes = sizes
         self.offsets = np.concatenate([[0], np.cumsum(sizes)])
         self.N = int(sizes.sum())
+        self._set_class([np.asarray(a, np.float64) for a in radii], self.params_list)
 
     def read_stress(self):
         """(last, mean, n_samples): last and mean are B x 3 x 3."""

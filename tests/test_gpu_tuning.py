@@ -1,0 +1,151 @@
+"""Launch tuning and HIP-graph replay change how a step is launched, never its results:
+checked against the FP64 oracle (lockstep, the tolerances of the single-box tests) under
+non-default lattices and tile sizes, with every row on the per-particle path, with a lattice
+change in the middle of a run, and with graph replay of the time step."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2108_01013_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_inf(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def lockstep(sim, p, rad, steps, nstep, check_pairs=True, on_step=None):
+    hp, hx = sim.history()
+    for k in range(steps):
+        if on_step:
+            on_step(k)
+        s0 = sim.state()
+        a, aw = oracle.accelerations(p, rad, s0["F"], s0["T"])
+        st = oracle.State(s0["x"], s0["u"], s0["w"], a, aw, rad.copy(), nstep,
+                          oracle.History(hp.astype(np.int32), hx))
+        x_o = oracle.kick_drift(p, st)[0]
+        sim.step(1)
+        nstep += 1
+        s1 = sim.state()
+        uh, wh = sim.eval_velocities()
+        assert np.array_equal(s1["x"], x_o), f"step {k}: positions"
+        if check_pairs:
+            po = oracle.pairs_cells(p, s1["x"], rad, oracle.le_offset(p, nstep))
+            assert np.array_equal(sim.pairs(), po), f"step {k}: pairs"
+        F, T, S, H, npairs = oracle.forces(p, s1["x"], uh, wh, rad, nstep, st.history, use_cells=True)
+        assert rel_inf(s1["F"], F) < TOL, f"step {k}: F"
+        assert rel_inf(s1["T"], T) < TOL, f"step {k}: T"
+        last, _, _ = sim.read_stress()
+        assert rel_inf(last, S) < TOL, f"step {k}: Sigma"
+        hp, hx = sim.history()
+        assert np.array_equal(hp, H.pairs), f"step {k}: history"
+    return nstep
+
+
+@pytest.mark.parametrize("tuning", [
+    {"cell_scale": 1.3, "tile_scale": 1.0, "tiled": True},
+    {"cell_scale": 1.0, "tile_scale": 0.25, "tiled": True},
+    {"cell_scale": 1.15, "tile_scale": 1.0, "tiled": False},
+])
+def test_tuned_lattice_parity(tuning):
+    from paper_2108_01013_amd.dss import Simulation
+    w = synth.bidisperse_box(4000, 0.50, seed=11)
+    p = w.params
+    say(f"case: tuning {tuning} N=4000")
+    sim = Simulation(p, record_pairs=True)
+    sim.set_tuning(**tuning)
+    sim.set_particles(w.x, w.rad)
+    lockstep(sim, p, w.rad, 4, 0)
+    sim.close()
+
+
+def test_lattice_change_mid_run():
+    from paper_2108_01013_amd.dss import Simulation
+    w = synth.bidisperse_box(4000, 0.55, seed=12)
+    p = w.params
+    say("case: lattice change mid-run N=4000")
+    sim = Simulation(p, record_pairs=True)
+    sim.set_particles(w.x, w.rad)
+    sim.step(5)
+
+    def change(k):
+        if k == 1:
+            sim.set_tuning(cell_scale=1.3, tile_scale=0.5)
+        if k == 3:
+            sim.set_tuning(cell_scale=1.0, tile_scale=1.0, tiled=False)
+        if k == 5:
+            sim.set_tuning(tiled=True)
+
+    lockstep(sim, p, w.rad, 7, 5, on_step=change)
+    sim.close()
+
+
+def test_graph_replay_parity():
+    """Steps replayed from HIP graphs (pairs not recorded, so the graphs are used) against the
+    oracle; both buffer parities, with and without the stress summation, are replayed."""
+    from paper_2108_01013_amd.dss import Simulation
+    w = synth.bidisperse_box(4000, 0.55, seed=13)
+    p = w.params
+    say("case: graph replay N=4000")
+    sim = Simulation(p)
+    assert sim.tuning()["graph"]
+    sim.set_particles(w.x, w.rad)
+    sim.step(6, stress_every=3)          # captures the graphs of both parities
+    lockstep(sim, p, w.rad, 4, 6, check_pairs=False)
+    sim.close()
+
+
+def test_graph_replay_equals_direct_launches():
+    from paper_2108_01013_amd.dss import Simulation
+    w = synth.config_small()
+    p = w.params
+    say("case: graph vs direct N=1000")
+    out = []
+    for graph in (True, False):
+        sim = Simulation(p)
+        sim.set_tuning(graph=graph)
+        sim.set_particles(w.x, w.rad)
+        sim.step(40, stress_every=10)
+        last, mean, ns = sim.read_stress()
+        out.append((sim.state(), last, mean, ns, sim.info()))
+        sim.close()
+    (s1, l1, m1, n1, i1), (s2, l2, m2, n2, i2) = out
+    assert n1 == n2 == 4
+    assert i1["step"] == i2["step"] == 40 and i1["n_pairs"] == i2["n_pairs"]
+    assert rel_inf(s1["x"], s2["x"]) < 1e-12
+    assert rel_inf(s1["F"], s2["F"]) < 1e-8
+    assert rel_inf(m1, m2) < 1e-8 and rel_inf(l1, l2) < 1e-8
+
+
+def test_autotune_batch_then_cache(tmp_path):
+    from paper_2108_01013_amd import tune
+    from paper_2108_01013_amd.dss import Batch
+    ws = [synth.bidisperse_box(3000, f, seed=90 + b) for b, f in enumerate((0.45, 0.55))]
+    params = [dict(w.params, shear_rate=g) for w, g in zip(ws, (0.1, 1.0))]
+    say("case: autotune batch of 2")
+    sim = Batch(params)
+    sim.set_particles([w.x for w in ws], [w.rad for w in ws])
+    path = str(tmp_path / "tune.json")
+    rec = tune.autotune(sim, trial_steps=5, cache_path=path, log=say)
+    assert not rec["cached"] and len(rec["trials"]) >= 3
+    t = sim.tuning()
+    for k, v in rec["tuning"].items():
+        assert t[k] == v
+    sim.step(5, stress_every=5)
+    assert sim.info()["error_flags"] == 0
+    sim.close()
+    sim = Batch(params)
+    sim.set_particles([w.x for w in ws], [w.rad for w in ws])
+    rec2 = tune.autotune(sim, trial_steps=5, cache_path=path)
+    assert rec2["cached"] and rec2["tuning"] == rec["tuning"]
+    sim.close()
