@@ -228,6 +228,24 @@ dss_status dss_get_info(dss_handle *h, dss_info *info);
 /* Diagnostics of box `box` (0 <= box < n_boxes) after the last summed evaluation. */
 dss_status dss_get_box_info(dss_handle *h, int32_t box, dss_box_info *info);
 
+/* Gradient of a stress objective by the discrete adjoint of the time step (reverse mode,
+ * hand-written kernels).  Runs n_steps time steps from the current state, sampling the
+ * stress every stress_every steps as dss_step does, and returns
+ *   J = sum_ab weight[ab] mean_samples(Sigma_ab)      (weight: 9 values, row-major)
+ * with its gradient with respect to the friction coefficient mu and the repulsion strength
+ * F_ER (dJ_dparams[0], [1]) and to the state at the call, by particle id (dJ_dx, dJ_du,
+ * dJ_dw: N x 3 each, nullable; host or device per on_device).  The derivative is that of
+ * the recorded run with its pair set, contact states and Coulomb-cap states held fixed
+ * (the step is smooth between these events); the contact history at the call is held
+ * fixed.  State is checkpointed every ckpt_every steps and each segment is recomputed
+ * forward before its reverse sweep (memory: one state and history copy per checkpoint plus
+ * a segment of ckpt_every recorded steps).  On return the handle stands at the end of the
+ * run, as after dss_step(h, n_steps, stress_every, 1).  Requires a single-box handle whose
+ * forces were evaluated at u^n (right after dss_set_particles or dss_compute_forces: else
+ * DSS_ERR_STATE) and at least one stress sample in the run (else DSS_ERR_ARG). */
+dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress_every, int64_t ckpt_every, const double *weight,
+                       double *J, double *dJ_dparams, double *dJ_dx, double *dJ_du, double *dJ_dw, int on_device);
+
 /* Bytes needed by dss_save_state (nullable blob: size query) / restore of a snapshot. */
 dss_status dss_save_state(dss_handle *h, void *blob, size_t *bytes);
 dss_status dss_load_state(dss_handle *h, const void *blob, size_t bytes);

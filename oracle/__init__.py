@@ -379,3 +379,20 @@ def rheology(Sigma, p):
     g = p["shear_rate"] * p["eta0"]
     out["eta_r"] = sig / g if g != 0 else float("nan")
     return out
+
+
+def stress_objective(p, x0, rad, u0, w0, n_steps: int, stress_every: int, weight, use_cells=False):
+    """J = sum_ab weight_ab mean_samples(Sigma_ab) over a run of n_steps steps from (x0, u0, w0)
+    with an empty initial history, Sigma sampled at the time indices that are multiples of
+    stress_every (eq. stress).  Also returns the run's branch record per step (listed pairs
+    and contact pairs), so that a finite difference of J can be checked to stay on one
+    branch.  The adjoint's reference is the central finite difference of this function."""
+    st, F, T, S = init_state(p, x0, rad, u0, w0, use_cells)
+    W = np.asarray(weight, dtype=np.float64).reshape(3, 3)
+    samples, branch = [], []
+    for n in range(1, n_steps + 1):
+        st, F, T, S, npairs, _ = step(p, st, use_cells)
+        branch.append((npairs, st.history.pairs.tobytes()))
+        if n % stress_every == 0:
+            samples.append(np.asarray(S).reshape(3, 3))
+    return float(np.sum(W * np.mean(samples, axis=0))), branch

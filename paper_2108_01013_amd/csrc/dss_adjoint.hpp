@@ -1,0 +1,279 @@
+// dss_adjoint.hpp -- kernels of the discrete adjoint of the time step.
+//
+// The forward step (Sec. 2.1, numerical algorithm) is, per particle,
+//   uh_{n+1} = uh_n + c_n dt F_n / m     (c = 1/2 on the first step from a state u^n, else 1)
+//   x_{n+1}  = x_n + dt uh_{n+1}         (the Lees-Edwards wrap shifts by constants)
+//   (F, T, Sigma, xi)_{n+1} = pair and Stokes terms at (x_{n+1}, uh_{n+1}, wh_{n+1}, xi_n)
+// and the same for the rotation with T / I.  With the pair set, contact states and
+// Coulomb-cap states of the forward run held fixed, the reverse sweep carries the adjoints
+// of x, uh, wh (by particle id) and of the contact stretches (in canonical history rows)
+// backwards one step at a time.  Everything here works on the recorded run ("tape") by
+// particle id: positions, half-step velocities, the listed pairs (id_min, id_max) and the
+// contact history in canonical rows (row of the smaller id, sorted by partner id).
+#pragma once
+
+#include "dss_kernels.hpp"
+#include "pair_vjp.hpp"
+
+namespace dss {
+
+// Position of contact (a < b) in canonical rows, or -1.
+__device__ __forceinline__ long long canon_find(const int *__restrict__ key, const int *__restrict__ cnt, int M, int a,
+                                                int b)
+{
+    const int n = cnt[a];
+    const int *kr = key + (long long)a * M;
+    for (int k = 0; k < n; ++k) {
+        const int kk = kr[k];
+        if (kk == b) return (long long)a * M + k;
+        if (kk > b) break;
+    }
+    return -1;
+}
+
+// Committed history rows (slot rows with owner ids and partner keys, stretch oriented from
+// the smaller to the larger id) -> canonical rows by id.  Pass 1 appends each contact to the
+// row of its smaller id; pass 2 sorts every row by partner id.  ccnt must be zero on entry.
+__global__ void __launch_bounds__(kBlock) k_canon_fill(int N, int M, const int *__restrict__ own,
+                                                       const int *__restrict__ key, const double *__restrict__ xi,
+                                                       const int *__restrict__ cnt, int *__restrict__ ckey,
+                                                       double *__restrict__ cxi, int *__restrict__ ccnt,
+                                                       DevClock *__restrict__ clk)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int id = own[p];
+    const int n = cnt[p];
+    for (int k = 0; k < n; ++k) {
+        const int partner = key[(long long)p * M + k];
+        const int a = id < partner ? id : partner, b = id < partner ? partner : id;
+        const int s = atomicAdd(&ccnt[a], 1);
+        if (s < M) {
+            ckey[(long long)a * M + s] = b;
+            const double *x = xi + ((long long)p * M + k) * 3;
+            double *y = cxi + ((long long)a * M + s) * 3;
+            y[0] = x[0];
+            y[1] = x[1];
+            y[2] = x[2];
+        } else {
+            atomicOr(&clk->err, kErrRowOverflow);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_canon_sort(int N, int M, int *__restrict__ ckey, double *__restrict__ cxi,
+                                                       int *__restrict__ ccnt)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    int n = ccnt[a];
+    n = n < M ? n : M;
+    ccnt[a] = n;
+    int *kr = ckey + (long long)a * M;
+    double *xr = cxi + (long long)a * M * 3;
+    for (int i = 1; i < n; ++i) {
+        const int k = kr[i];
+        const double x0 = xr[3 * i], x1 = xr[3 * i + 1], x2 = xr[3 * i + 2];
+        int j = i - 1;
+        while (j >= 0 && kr[j] > k) {
+            kr[j + 1] = kr[j];
+            xr[3 * (j + 1)] = xr[3 * j];
+            xr[3 * (j + 1) + 1] = xr[3 * j + 1];
+            xr[3 * (j + 1) + 2] = xr[3 * j + 2];
+            --j;
+        }
+        kr[j + 1] = k;
+        xr[3 * (j + 1)] = x0;
+        xr[3 * (j + 1) + 1] = x1;
+        xr[3 * (j + 1) + 2] = x2;
+    }
+}
+
+// Stretch adjoints from canonical rows A to canonical rows B (the same contacts, possibly
+// laid out differently): every contact of B takes the adjoint of its match in A, or 0.
+__global__ void __launch_bounds__(kBlock) k_canon_rekey(int N, int M, const int *__restrict__ keyA,
+                                                        const int *__restrict__ cntA, const double *__restrict__ gA,
+                                                        const int *__restrict__ keyB, const int *__restrict__ cntB,
+                                                        double *__restrict__ gB)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    const int n = cntB[a];
+    for (int k = 0; k < n; ++k) {
+        const long long q = (long long)a * M + k;
+        const long long s = canon_find(keyA, cntA, M, a, keyB[q]);
+        gB[3 * q] = s >= 0 ? gA[3 * s] : 0.0;
+        gB[3 * q + 1] = s >= 0 ? gA[3 * s + 1] : 0.0;
+        gB[3 * q + 2] = s >= 0 ? gA[3 * s + 2] : 0.0;
+    }
+}
+
+__device__ __forceinline__ void atomic_add3(double *p, double a, double b, double c)
+{
+    atomicAdd(p, a);
+    atomicAdd(p + 1, b);
+    atomicAdd(p + 2, c);
+}
+
+// ----------------------------------------------------------------------------------
+// k_pairs_vjp: reverse of the pair terms of one force evaluation (time index `step`).
+// One lane per listed pair (a, b), a < b, r = x_b - x_a (Lees-Edwards minimum image):
+// the stretch before the step is looked up in the canonical rows of the previous
+// history, the cotangents of the pair's outputs are gathered (force cotangent
+// Fb_a - Fb_b since F_b = -F_a, torque cotangents, the stretch cotangent from the rows
+// after the step, the stress weights), and pair_vjp pulls them back.  Gradients are
+// added into ax, au, aw by id (FP64 atomics), the old-stretch adjoint is stored at the
+// contact's position in the previous rows, and the parameter gradients (mu, F_ER) are
+// summed per workgroup, then added once.
+// ----------------------------------------------------------------------------------
+struct VjpTape {
+    const int *pairs;       // 2 x npairs (id_min, id_max)
+    const double *x, *u, *w, *rad;   // by id: positions, evaluation velocities, radii
+    const int *key_old, *cnt_old;    // canonical rows before the step (null: empty)
+    const double *xi_old;
+    const int *key_new, *cnt_new;    // canonical rows after the step (null: not committed)
+};
+
+__global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, long long step, int npairs,
+                                                      VjpTape tp, const double *__restrict__ xib_new,
+                                                      double *__restrict__ xib_old, const double *__restrict__ Fb,
+                                                      const double *__restrict__ Tb, const double *__restrict__ Sb,
+                                                      double *__restrict__ ax, double *__restrict__ au,
+                                                      double *__restrict__ aw, double *__restrict__ theta_b)
+{
+    __shared__ double red[kBlock / 64][2];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double gmu = 0.0, gfer = 0.0;
+    if (k < npairs) {
+        const int a = tp.pairs[2 * k], b = tp.pairs[2 * k + 1];
+        const double delta = le_offset(P, G, step);
+        const double *xa = tp.x + 3LL * a, *xb = tp.x + 3LL * b;
+        double r[3];
+        min_image(G, delta, xa[0], xa[1], xa[2], xb[0], xb[1], xb[2], r[0], r[1], r[2]);
+        double xo[3] = {0.0, 0.0, 0.0};
+        long long pold = -1;
+        if (tp.key_old) {
+            pold = canon_find(tp.key_old, tp.cnt_old, P.M, a, b);
+            if (pold >= 0) {
+                xo[0] = tp.xi_old[3 * pold];
+                xo[1] = tp.xi_old[3 * pold + 1];
+                xo[2] = tp.xi_old[3 * pold + 2];
+            }
+        }
+        PairBar bar;
+        for (int c = 0; c < 3; ++c) {
+            bar.Fi[c] = Fb[3LL * a + c] - Fb[3LL * b + c];
+            bar.Ti[c] = Tb[3LL * a + c];
+            bar.Tj[c] = Tb[3LL * b + c];
+            bar.xi[c] = 0.0;
+        }
+        if (tp.key_new && xib_new) {
+            const long long pn = canon_find(tp.key_new, tp.cnt_new, P.M, a, b);
+            if (pn >= 0)
+                for (int c = 0; c < 3; ++c) bar.xi[c] = xib_new[3 * pn + c];
+        }
+        for (int c = 0; c < 9; ++c) bar.S[c] = Sb ? Sb[c] : 0.0;
+        PairConst C;
+        C.k6 = P.k6; C.kn = P.kn; C.kt = P.kt; C.gn = P.gn; C.mu = P.mu; C.fer = P.fer; C.a0 = P.a0;
+        C.lamd = P.lamd; C.ham = P.ham; C.eps_vdw = P.eps_vdw; C.eps_lub = P.eps_lub; C.dt = P.dt;
+        PairGrad g = {};
+        pair_vjp(C, G.gd, r, tp.rad[a], tp.rad[b], xa[1], xb[1], tp.u + 3LL * a, tp.u + 3LL * b, tp.w + 3LL * a,
+                 tp.w + 3LL * b, xo, bar, g, nullptr);
+        atomic_add3(ax + 3LL * a, -g.r[0], -g.r[1] + g.yi, -g.r[2]);
+        atomic_add3(ax + 3LL * b, g.r[0], g.r[1] + g.yj, g.r[2]);
+        atomic_add3(au + 3LL * a, g.ui[0], g.ui[1], g.ui[2]);
+        atomic_add3(au + 3LL * b, g.uj[0], g.uj[1], g.uj[2]);
+        atomic_add3(aw + 3LL * a, g.wi[0], g.wi[1], g.wi[2]);
+        atomic_add3(aw + 3LL * b, g.wj[0], g.wj[1], g.wj[2]);
+        if (pold >= 0 && xib_old)
+            for (int c = 0; c < 3; ++c) xib_old[3 * pold + c] = g.xo[c];
+        gmu = g.mu;
+        gfer = g.fer;
+    }
+    gmu = warp_sum(gmu);
+    gfer = warp_sum(gfer);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[wid][0] = gmu;
+        red[wid][1] = gfer;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int q = 0; q < kBlock / 64; ++q) {
+            s0 += red[q][0];
+            s1 += red[q][1];
+        }
+        atomicAdd(theta_b, s0);
+        atomicAdd(theta_b + 1, s1);
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// k_integrate_vjp: per particle, the reverse of the Stokes terms of the evaluation at
+// step n (F^S = -6 pi eta0 a (uh - gd y e_x), T^S = -8 pi eta0 a^3 (wh + gd/2 e_z)), then
+// of the drift and kick that produced x_n, uh_n:
+//   xb' = xb + ax,  ub' = ub + au + dt xb',  wb' = wb + aw,
+//   Fb_{n-1} = c dt ub' / m,  Tb_{n-1} = c dt wb' / I
+// (xb, ub, wb in: adjoints of x_n, uh_{n+1}, wh_{n+1} from the later steps; out: of x_{n-1},
+// uh_n, wh_n).  final != 0: the evaluation at the initial state; the adjoints of the
+// initial x, u, w are xb + ax, ub + au, wb + aw.  ax, au, aw are cleared.
+// ----------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_integrate_vjp(DevParams P, double gd, int N, double c, int final,
+                                                          const double *__restrict__ rad,
+                                                          const double *__restrict__ Fb, const double *__restrict__ Tb,
+                                                          double *__restrict__ ax, double *__restrict__ au,
+                                                          double *__restrict__ aw, double *__restrict__ xb,
+                                                          double *__restrict__ ub, double *__restrict__ wb,
+                                                          double *__restrict__ Fb_prev, double *__restrict__ Tb_prev)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const double a = rad[p];
+    const double K = P.k6 * a, KR = P.k8 * a * a * a;
+    const double m = pmass(P, a), I = 0.4 * m * a * a;
+    const double dt = P.dt;
+    double gx[3], gu[3], gw[3];
+    for (int k = 0; k < 3; ++k) {
+        const long long q = 3LL * p + k;
+        gx[k] = ax[q];
+        gu[k] = au[q] - K * Fb[q];
+        gw[k] = aw[q] - KR * Tb[q];
+        ax[q] = 0.0;
+        au[q] = 0.0;
+        aw[q] = 0.0;
+    }
+    gx[1] += K * gd * Fb[3LL * p];
+    for (int k = 0; k < 3; ++k) {
+        const long long q = 3LL * p + k;
+        if (final) {
+            xb[q] += gx[k];
+            ub[q] += gu[k];
+            wb[q] += gw[k];
+        } else {
+            const double X = xb[q] + gx[k];
+            const double U = ub[q] + gu[k] + dt * X;
+            const double W = wb[q] + gw[k];
+            xb[q] = X;
+            ub[q] = U;
+            wb[q] = W;
+            Fb_prev[q] = c * dt * U / m;
+            Tb_prev[q] = c * dt * W / I;
+        }
+    }
+}
+
+}  // namespace dss
+
+namespace dss {
+
+// Radius of every particle by id.
+__global__ void __launch_bounds__(kBlock) k_rad_by_id(int N, const double4 *__restrict__ pa,
+                                                      const double4 *__restrict__ omg, double *__restrict__ rad)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    rad[(int)omg[p].w] = pa[p].w;
+}
+
+}  // namespace dss

@@ -19,6 +19,7 @@
 
 #include "dss.h"
 #include "dss_kernels.hpp"
+#include "dss_adjoint.hpp"
 
 using namespace dss;
 
@@ -1113,6 +1114,367 @@ dss_status dss_get_box_info(dss_handle *h, int32_t box, dss_box_info *info)
     info->le_offset = std::fmod(G.gd * G.L[1] * t, G.L[0]);
     return DSS_OK;
 }
+
+}  // extern "C"
+
+// ======================================================================================
+// Adjoint: checkpointed reverse sweep over a run of n_steps time steps.
+// ======================================================================================
+namespace {
+
+// Device copy of everything a time step reads from the previous one.
+struct Snapshot {
+    double4 *pa = nullptr, *vel = nullptr, *omg = nullptr;
+    double *ft = nullptr;   // own 6N, nb 24N, x 6N
+    int *hkey = nullptr, *hcnt = nullptr, *hown = nullptr;
+    double *hxi = nullptr;
+    DevClock *clk = nullptr;
+    double *sig = nullptr;  // sigma_last (9) and box_diag (3) of box 0
+    int cur = 0, hh = 0;
+    int64_t step = 0;
+    bool vel_is_half = false;
+    void release()
+    {
+        void *ps[] = {pa, vel, omg, ft, hkey, hcnt, hown, hxi, clk, sig};
+        for (void *q : ps)
+            if (q) (void)hipFree(q);
+        *this = Snapshot{};
+    }
+};
+
+dss_status snap_save(dss_handle *h, Snapshot &s)
+{
+    const int64_t N = h->N, M = h->P.M;
+    if (!s.pa) {
+        HIPTRY(dalloc(&s.pa, N));
+        HIPTRY(dalloc(&s.vel, N));
+        HIPTRY(dalloc(&s.omg, N));
+        HIPTRY(dalloc(&s.ft, 36 * N));
+        HIPTRY(dalloc(&s.hkey, N * M));
+        HIPTRY(dalloc(&s.hxi, 3 * N * M));
+        HIPTRY(dalloc(&s.hcnt, N));
+        HIPTRY(dalloc(&s.hown, N));
+        HIPTRY(dalloc(&s.clk, 1));
+        HIPTRY(dalloc(&s.sig, 12));
+    }
+    const hipMemcpyKind D = hipMemcpyDeviceToDevice;
+    hipStream_t st = h->stream;
+    HIPTRY(hipMemcpyAsync(s.pa, h->pa[h->cur], N * sizeof(double4), D, st));
+    HIPTRY(hipMemcpyAsync(s.vel, h->vel[h->cur], N * sizeof(double4), D, st));
+    HIPTRY(hipMemcpyAsync(s.omg, h->omg[h->cur], N * sizeof(double4), D, st));
+    HIPTRY(hipMemcpyAsync(s.ft, h->ft_own, 6 * N * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(s.ft + 6 * N, h->ft_nb, 24 * N * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(s.ft + 30 * N, h->ft_x, 6 * N * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(s.hkey, h->hkey[h->hh], N * M * sizeof(int), D, st));
+    HIPTRY(hipMemcpyAsync(s.hxi, h->hxi[h->hh], 3 * N * M * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(s.hcnt, h->hcnt[h->hh], N * sizeof(int), D, st));
+    HIPTRY(hipMemcpyAsync(s.hown, h->hown[h->hh], N * sizeof(int), D, st));
+    HIPTRY(hipMemcpyAsync(s.clk, h->clk, sizeof(DevClock), D, st));
+    HIPTRY(hipMemcpyAsync(s.sig, h->sigma_last, 9 * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(s.sig + 9, h->box_diag, 3 * sizeof(double), D, st));
+    s.cur = h->cur;
+    s.hh = h->hh;
+    s.step = h->step;
+    s.vel_is_half = h->vel_is_half;
+    return DSS_OK;
+}
+
+dss_status snap_restore(dss_handle *h, const Snapshot &s)
+{
+    const int64_t N = h->N, M = h->P.M;
+    const hipMemcpyKind D = hipMemcpyDeviceToDevice;
+    hipStream_t st = h->stream;
+    HIPTRY(hipMemcpyAsync(h->pa[s.cur], s.pa, N * sizeof(double4), D, st));
+    HIPTRY(hipMemcpyAsync(h->vel[s.cur], s.vel, N * sizeof(double4), D, st));
+    HIPTRY(hipMemcpyAsync(h->omg[s.cur], s.omg, N * sizeof(double4), D, st));
+    HIPTRY(hipMemcpyAsync(h->ft_own, s.ft, 6 * N * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(h->ft_nb, s.ft + 6 * N, 24 * N * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(h->ft_x, s.ft + 30 * N, 6 * N * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(h->hkey[s.hh], s.hkey, N * M * sizeof(int), D, st));
+    HIPTRY(hipMemcpyAsync(h->hxi[s.hh], s.hxi, 3 * N * M * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(h->hcnt[s.hh], s.hcnt, N * sizeof(int), D, st));
+    HIPTRY(hipMemcpyAsync(h->hown[s.hh], s.hown, N * sizeof(int), D, st));
+    HIPTRY(hipMemcpyAsync(h->clk, s.clk, sizeof(DevClock), D, st));
+    HIPTRY(hipMemcpyAsync(h->sigma_last, s.sig, 9 * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(h->box_diag, s.sig + 9, 3 * sizeof(double), D, st));
+    h->cur = s.cur;
+    h->hh = s.hh;
+    h->step = s.step;
+    h->vel_is_half = s.vel_is_half;
+    return DSS_OK;
+}
+
+// One recorded evaluation: state by id, listed pairs, committed history in canonical rows.
+struct TapeEntry {
+    double *x = nullptr, *u = nullptr, *w = nullptr;
+    int *pairs = nullptr;
+    int64_t npairs = 0;
+    int *ckey = nullptr, *ccnt = nullptr;
+    double *cxi = nullptr;
+    void release()
+    {
+        void *ps[] = {x, u, w, pairs, ckey, ccnt, cxi};
+        for (void *q : ps)
+            if (q) (void)hipFree(q);
+        *this = TapeEntry{};
+    }
+};
+
+dss_status tape_alloc(dss_handle *h, TapeEntry &t)
+{
+    const int64_t N = h->N, M = h->P.M;
+    HIPTRY(dalloc(&t.x, 3 * N));
+    HIPTRY(dalloc(&t.u, 3 * N));
+    HIPTRY(dalloc(&t.w, 3 * N));
+    HIPTRY(dalloc(&t.pairs, 2 * h->P.pair_cap));
+    HIPTRY(dalloc(&t.ckey, N * M));
+    HIPTRY(dalloc(&t.ccnt, N));
+    HIPTRY(dalloc(&t.cxi, 3 * N * M));
+    return DSS_OK;
+}
+
+// Committed history -> canonical rows of a tape entry.
+dss_status tape_rows(dss_handle *h, TapeEntry &t)
+{
+    const int N = (int)h->N, M = h->P.M;
+    const int grid = (N + kBlock - 1) / kBlock;
+    HIPTRY(hipMemsetAsync(t.ccnt, 0, N * sizeof(int), h->stream));
+    hipLaunchKernelGGL(k_canon_fill, dim3(grid), dim3(kBlock), 0, h->stream, N, M, h->hown[h->hh], h->hkey[h->hh],
+                       h->hxi[h->hh], h->hcnt[h->hh], t.ckey, t.cxi, t.ccnt, h->clk);
+    hipLaunchKernelGGL(k_canon_sort, dim3(grid), dim3(kBlock), 0, h->stream, N, M, t.ckey, t.cxi, t.ccnt);
+    HIPTRY(hipGetLastError());
+    return DSS_OK;
+}
+
+// State by id and the listed pairs of the last evaluation -> tape entry.
+dss_status tape_state(dss_handle *h, TapeEntry &t)
+{
+    const int N = (int)h->N;
+    const int grid = (N + kBlock - 1) / kBlock;
+    const int c = h->cur;
+    hipLaunchKernelGGL(k_unsort, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c],
+                       h->fb(), h->vel_is_half ? 1 : 0, 0, t.x, t.u, t.w, (double *)nullptr, (double *)nullptr);
+    HIPTRY(hipGetLastError());
+    unsigned long long cnt = 0;
+    HIPTRY(hipMemcpyAsync(&cnt, h->pair_count, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    if ((int64_t)cnt > h->P.pair_cap) return fail(h, DSS_ERR_CAPACITY, "internal pair buffer overflow");
+    t.npairs = (int64_t)cnt;
+    if (cnt)
+        HIPTRY(hipMemcpyAsync(t.pairs, h->pairs, 2 * cnt * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+    return DSS_OK;
+}
+
+struct AdjointScratch {
+    std::vector<Snapshot> ck;
+    Snapshot fin;
+    std::vector<TapeEntry> tape;
+    std::vector<void *> bufs;
+    ~AdjointScratch()
+    {
+        for (auto &s : ck) s.release();
+        fin.release();
+        for (auto &t : tape) t.release();
+        for (void *q : bufs)
+            if (q) (void)hipFree(q);
+    }
+    template <class T>
+    hipError_t get(T **p, size_t n)
+    {
+        hipError_t e = dalloc(p, n);
+        if (e == hipSuccess) bufs.push_back((void *)*p);
+        return e;
+    }
+};
+
+}  // namespace
+
+extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress_every, int64_t ckpt_every,
+                                  const double *weight, double *J, double *dJ_dparams, double *dJ_dx, double *dJ_du,
+                                  double *dJ_dw, int on_device)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "the adjoint runs on single-box handles");
+    if (h->vel_is_half)
+        return fail(h, DSS_ERR_STATE, "the adjoint starts from a state with forces at u^n: call it right after "
+                                      "dss_set_particles or dss_compute_forces");
+    if (n_steps < 1 || stress_every < 1 || ckpt_every < 1 || !weight)
+        return fail(h, DSS_ERR_ARG, "n_steps, stress_every, ckpt_every must be >= 1 and weight non-null");
+    const int64_t n0 = h->step, K = n_steps, C = ckpt_every;
+    const int64_t first = ((n0 / stress_every) + 1) * stress_every;
+    if (first > n0 + K) return fail(h, DSS_ERR_ARG, "no stress sample in the run (n_steps < stress_every)");
+    const int64_t ns = (n0 + K - first) / stress_every + 1;
+    const int N = (int)h->N, M = h->P.M;
+    const int grid = (N + kBlock - 1) / kBlock;
+    destroy_graphs(h);
+    // pair recording for the tape
+    const int rec0 = h->P.record_pairs;
+    if (!rec0) {
+        const int64_t cap = 32 * (int64_t)N + 64;
+        if (h->P.pair_cap < cap) {
+            if (h->pairs) HIPTRY(hipFree(h->pairs));
+            h->pairs = nullptr;
+            HIPTRY(dalloc(&h->pairs, 2 * cap));
+            h->P.pair_cap = cap;
+        }
+    }
+    AdjointScratch W;
+    const int64_t nck = (K + C - 1) / C;
+    W.ck.resize(nck);
+
+    // ---------------- forward run with checkpoints and stress samples
+    if (ns > h->sample_cap_alloc) {
+        if (h->samples) HIPTRY(hipFree(h->samples));
+        h->samples = nullptr;
+        HIPTRY(dalloc(&h->samples, 9 * (size_t)h->nbox * ns));
+        h->sample_cap_alloc = ns;
+    }
+    h->run_host.sample_every = stress_every;
+    h->run_host.sample_first = first;
+    h->run_host.sample_cap = ns;
+    h->run_host.samples = h->samples;
+    h->run_host.sigma_last = h->sigma_last;
+    h->run_host.box_diag = h->box_diag;
+    HIPTRY(hipMemcpyAsync(h->run, &h->run_host, sizeof(DevRun), hipMemcpyHostToDevice, h->stream));
+    h->last_samples = ns;
+    for (int64_t k = 0; k < K; ++k) {
+        if (k % C == 0) {
+            s = snap_save(h, W.ck[k / C]);
+            if (s) return s;
+        }
+        const int64_t n_next = h->step + 1;
+        const bool finish = k == K - 1 || n_next % stress_every == 0;
+        s = evaluate(h, EVAL_STEP, finish);
+        if (s) return s;
+    }
+    double last[9], mean[9];
+    int64_t nsr = 0;
+    s = dss_read_stress_batch(h, last, mean, &nsr);
+    if (s) return s;
+    double Jv = 0.0;
+    for (int k = 0; k < 9; ++k) Jv += weight[k] * mean[k];
+    s = snap_save(h, W.fin);
+    if (s) return s;
+
+    // ---------------- reverse sweep
+    const size_t n3 = 3 * (size_t)N;
+    double *xb, *ub, *wb, *ax, *au, *aw, *Fb, *Tb, *Fb2, *Tb2, *theta, *rad, *Sb, *xibA, *xibB;
+    int *bkey, *bcnt;
+    HIPTRY(W.get(&xb, n3)); HIPTRY(W.get(&ub, n3)); HIPTRY(W.get(&wb, n3));
+    HIPTRY(W.get(&ax, n3)); HIPTRY(W.get(&au, n3)); HIPTRY(W.get(&aw, n3));
+    HIPTRY(W.get(&Fb, n3)); HIPTRY(W.get(&Tb, n3)); HIPTRY(W.get(&Fb2, n3)); HIPTRY(W.get(&Tb2, n3));
+    HIPTRY(W.get(&theta, 2)); HIPTRY(W.get(&rad, N)); HIPTRY(W.get(&Sb, 9));
+    HIPTRY(W.get(&xibA, 3 * (size_t)N * M)); HIPTRY(W.get(&xibB, 3 * (size_t)N * M));
+    HIPTRY(W.get(&bkey, (size_t)N * M)); HIPTRY(W.get(&bcnt, N));
+    double *zero_list[] = {xb, ub, wb, ax, au, aw, Fb, Tb, Fb2, Tb2};
+    for (double *q : zero_list) HIPTRY(hipMemsetAsync(q, 0, n3 * sizeof(double), h->stream));
+    HIPTRY(hipMemsetAsync(theta, 0, 2 * sizeof(double), h->stream));
+    HIPTRY(hipMemsetAsync(xibA, 0, 3 * (size_t)N * M * sizeof(double), h->stream));
+    HIPTRY(hipMemsetAsync(bcnt, 0, N * sizeof(int), h->stream));
+    {
+        const double V = h->prm.L[0] * h->prm.L[1] * h->prm.L[2];
+        double sb[9];
+        for (int k = 0; k < 9; ++k) sb[k] = weight[k] / ((double)ns * V);
+        HIPTRY(hipMemcpyAsync(Sb, sb, sizeof(sb), hipMemcpyHostToDevice, h->stream));
+    }
+    hipLaunchKernelGGL(k_rad_by_id, dim3(grid), dim3(kBlock), 0, h->stream, N, h->pa[h->cur], h->omg[h->cur], rad);
+    W.tape.resize(C + 1);
+    for (auto &t : W.tape) {
+        s = tape_alloc(h, t);
+        if (s) return s;
+    }
+    DevParams Prec = h->P;
+    Prec.record_pairs = 1;
+    const BoxParams G = h->boxes[0];
+    double *xib_in = xibA, *xib_out = xibB;
+    h->P.record_pairs = 1;
+    for (int64_t seg = nck - 1; seg >= 0; --seg) {
+        const int64_t s0 = n0 + seg * C;
+        const int64_t len = std::min<int64_t>(C, K - seg * C);
+        s = snap_restore(h, W.ck[seg]);
+        if (s) break;
+        s = tape_rows(h, W.tape[0]);
+        if (s) break;
+        if (seg == 0) {
+            // the evaluation at the initial state (pairs, state by id)
+            s = evaluate(h, EVAL_INPLACE);
+            if (s) break;
+            s = tape_state(h, W.tape[0]);
+            if (s) break;
+        }
+        for (int64_t k = 1; k <= len; ++k) {
+            s = evaluate(h, EVAL_STEP, false);
+            if (s) break;
+            s = tape_state(h, W.tape[k]);
+            if (s) break;
+            s = tape_rows(h, W.tape[k]);
+            if (s) break;
+        }
+        if (s) break;
+        if (seg < nck - 1) {
+            // stretch adjoints at the segment boundary: rows of the later segment -> this one
+            hipLaunchKernelGGL(k_canon_rekey, dim3(grid), dim3(kBlock), 0, h->stream, N, M, bkey, bcnt, xib_in,
+                               W.tape[len].ckey, W.tape[len].ccnt, xib_out);
+            std::swap(xib_in, xib_out);
+        }
+        for (int64_t k = len; k >= 1; --k) {
+            const int64_t n = s0 + k;
+            const TapeEntry &T1 = W.tape[k], &T0 = W.tape[k - 1];
+            HIPTRY(hipMemsetAsync(xib_out, 0, 3 * (size_t)N * M * sizeof(double), h->stream));
+            VjpTape tp{T1.pairs, T1.x, T1.u, T1.w, rad, T0.ckey, T0.ccnt, T0.cxi, T1.ckey, T1.ccnt};
+            const bool sampled = n >= first && (n - first) % stress_every == 0;
+            const int pgrid = (int)std::max<int64_t>(1, (T1.npairs + kBlock - 1) / kBlock);
+            hipLaunchKernelGGL(k_pairs_vjp, dim3(pgrid), dim3(kBlock), 0, h->stream, Prec, G, (long long)n,
+                               (int)T1.npairs, tp, xib_in, xib_out, Fb, Tb, sampled ? Sb : (const double *)nullptr,
+                               ax, au, aw, theta);
+            const double c = (n - 1 == n0) ? 0.5 : 1.0;
+            hipLaunchKernelGGL(k_integrate_vjp, dim3(grid), dim3(kBlock), 0, h->stream, Prec, G.gd, N, c, 0, rad, Fb,
+                               Tb, ax, au, aw, xb, ub, wb, Fb2, Tb2);
+            std::swap(Fb, Fb2);
+            std::swap(Tb, Tb2);
+            std::swap(xib_in, xib_out);
+        }
+        HIPTRY(hipMemcpyAsync(bkey, W.tape[0].ckey, (size_t)N * M * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+        HIPTRY(hipMemcpyAsync(bcnt, W.tape[0].ccnt, N * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+        HIPTRY(hipGetLastError());
+    }
+    h->P.record_pairs = rec0;
+    if (s) return s;
+    {
+        // the evaluation at the initial state; the stretch of the initial history is held fixed
+        const TapeEntry &T0 = W.tape[0];
+        VjpTape tp{T0.pairs, T0.x, T0.u, T0.w, rad, T0.ckey, T0.ccnt, T0.cxi, nullptr, nullptr};
+        const int pgrid = (int)std::max<int64_t>(1, (T0.npairs + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_pairs_vjp, dim3(pgrid), dim3(kBlock), 0, h->stream, Prec, G, (long long)n0,
+                           (int)T0.npairs, tp, (const double *)nullptr, (double *)nullptr, Fb, Tb,
+                           (const double *)nullptr, ax, au, aw, theta);
+        hipLaunchKernelGGL(k_integrate_vjp, dim3(grid), dim3(kBlock), 0, h->stream, Prec, G.gd, N, 0.0, 1, rad, Fb, Tb,
+                           ax, au, aw, xb, ub, wb, Fb2, Tb2);
+        HIPTRY(hipGetLastError());
+    }
+    s = check_flags(h);
+    if (s) return s;
+    // outputs
+    const hipMemcpyKind out = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (dJ_dx) HIPTRY(hipMemcpyAsync(dJ_dx, xb, n3 * sizeof(double), out, h->stream));
+    if (dJ_du) HIPTRY(hipMemcpyAsync(dJ_du, ub, n3 * sizeof(double), out, h->stream));
+    if (dJ_dw) HIPTRY(hipMemcpyAsync(dJ_dw, wb, n3 * sizeof(double), out, h->stream));
+    double th[2];
+    HIPTRY(hipMemcpyAsync(th, theta, sizeof(th), hipMemcpyDeviceToHost, h->stream));
+    // leave the handle at the end of the run, as dss_step would
+    s = snap_restore(h, W.fin);
+    if (s) return s;
+    HIPTRY(hipStreamSynchronize(h->stream));
+    if (J) *J = Jv;
+    if (dJ_dparams) {
+        dJ_dparams[0] = th[0];
+        dJ_dparams[1] = th[1];
+    }
+    return DSS_OK;
+}
+
+extern "C" {
 
 dss_status dss_save_state(dss_handle *h, void *blob, size_t *bytes)
 {

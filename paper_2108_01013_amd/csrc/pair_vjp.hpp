@@ -1,0 +1,340 @@
+// pair_vjp.hpp -- reverse-mode derivative of the FP64 pair physics of one listed pair.
+//
+// The pair function maps (r = x_j - x_i, y_i, y_j, u_i, u_j, w_i, w_j, xi_old; mu, F_ER) to
+// (F_i, T_i, T_j, xi_new, S): lubrication in the reduced form of the resistance matrices of
+// Appendix A, repulsion (eq. rep), attraction (eq. att), the spring-dashpot contact with its
+// tangential stretch and Coulomb cap (eqs. contact0, csi), and the pair stresslet (eq.
+// stresslet); F_j = -F_i.  pair_vjp recomputes the primal with the forward's formulas and
+// branch decisions (listed pair, contact h < 0, Coulomb cap active, h >= 0 for the
+// electro-chemical terms, d* > 0), then pulls a cotangent of the outputs back to every
+// input: the vector-Jacobian product of the branch that the primal takes.  Plain C++ with
+// a host/device qualifier, so the same code is differentiated numerically on the CPU.
+#pragma once
+
+#include <cmath>
+
+#ifdef __HIPCC__
+#define DSS_HD __host__ __device__
+#else
+#define DSS_HD
+#endif
+
+namespace dss {
+
+// Constants the pair function reads (eta0 through k6 = 6 pi eta0).
+struct PairConst {
+    double k6, kn, kt, gn, mu, fer, a0, lamd, ham, eps_vdw, eps_lub, dt;
+};
+
+// Cotangents of the outputs.  S: 9 weights of the pair's stresslet entries S_ab.
+struct PairBar {
+    double Fi[3], Ti[3], Tj[3], xi[3], S[9];
+};
+
+// Gradients with respect to the inputs.
+struct PairGrad {
+    double r[3], yi, yj, ui[3], uj[3], wi[3], wj[3], xo[3], mu, fer;
+};
+
+// Primal outputs (for checks against the forward).
+struct PairVal {
+    double Fi[3], Ti[3], Tj[3], xi[3], S[9];
+    bool contact, capped;
+};
+
+DSS_HD inline double vdot(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+DSS_HD inline void vcross(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// out += s * a
+DSS_HD inline void vaxpy(double s, const double a[3], double out[3])
+{
+    out[0] += s * a[0];
+    out[1] += s * a[1];
+    out[2] += s * a[2];
+}
+
+// g must be zero on entry; val may be null.
+DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], double ai, double aj, double yi,
+                            double yj, const double ui[3], const double uj[3], const double Wi[3], const double Wj[3],
+                            const double xo[3], const PairBar &bar, PairGrad &g, PairVal *val)
+{
+    // ------------------------------------------------------------------ primal
+    const double dist = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    const double h = dist - ai - aj;
+    const double s = ai + aj;
+    const double dsr = 2.0 * h / s;
+    const bool dpos = dsr > 0.0;
+    const double gg = (dpos ? dsr : 0.0) + C.eps_lub;
+    const double invg = 1.0 / gg;
+    const double lg = -log(gg);
+    const double dux = (uj[0] - gd * yj) - (ui[0] - gd * yi);
+    const double duy = uj[1] - ui[1], duz = uj[2] - ui[2];
+    const double inv_d = 1.0 / dist;
+    const double n[3] = {r[0] * inv_d, r[1] * inv_d, r[2] * inv_d};
+    const double wi[3] = {Wi[0], Wi[1], Wi[2] + 0.5 * gd};
+    const double wj[3] = {Wj[0], Wj[1], Wj[2] + 0.5 * gd};
+    const double K = C.k6;
+    const double ai2 = ai * ai, aj2 = aj * aj;
+    const double is = 1.0 / s, is2 = is * is, is3 = is2 * is;
+    const double cXA = K * 2.0 * ai2 * aj2 * is3;
+    const double cYA = K * (4.0 / 15.0) * ai * aj * (2.0 * ai2 + ai * aj + 2.0 * aj2) * is3;
+    const double cYBi = -K * (2.0 / 15.0) * ai2 * aj * (4.0 * ai + aj) * is2;
+    const double cYBj = K * (2.0 / 15.0) * ai * aj2 * (ai + 4.0 * aj) * is2;
+    const double cYCii = K * (8.0 / 15.0) * ai2 * ai * aj * is;
+    const double cYCij = K * (2.0 / 15.0) * ai2 * aj2 * is;
+    const double cYCjj = K * (8.0 / 15.0) * ai * aj2 * aj * is;
+    const double XA = cXA * invg, YA = cYA * lg, YBi = cYBi * lg, YBj = cYBj * lg;
+    const double YCii = cYCii * lg, YCij = cYCij * lg, YCjj = cYCjj * lg;
+    const double v[3] = {dux + s * 0.5 * gd * n[1], duy + s * 0.5 * gd * n[0], duz};
+    const double vn = vdot(v, n);
+    double ci[3], cj[3], nv[3];
+    vcross(n, wi, ci);
+    vcross(n, wj, cj);
+    vcross(n, v, nv);
+    double FL[3];
+    for (int k = 0; k < 3; ++k) FL[k] = XA * vn * n[k] + YA * (v[k] - vn * n[k]) - YBi * ci[k] + YBj * cj[k];
+    const double win = vdot(wi, n), wjn = vdot(wj, n);
+    double ti[3], tj[3], Ti[3], Tj[3];
+    for (int k = 0; k < 3; ++k) {
+        ti[k] = wi[k] - win * n[k];
+        tj[k] = wj[k] - wjn * n[k];
+        Ti[k] = -YBi * nv[k] - YCii * ti[k] - YCij * tj[k];
+        Tj[k] = YBj * nv[k] - YCij * ti[k] - YCjj * tj[k];
+    }
+    const double abar = 2.0 * ai * aj * is;
+    const double E = h >= 0.0 ? (C.lamd > 0.0 ? exp(-h / C.lamd) : 0.0) : 1.0;
+    double fe = 0.0;
+    if (C.fer != 0.0) fe -= (C.fer / C.a0) * abar * E;
+    const double ev = C.eps_vdw * abar;
+    const double Q = (h >= 0.0 ? h * h : 0.0) + ev * ev;
+    if (C.ham != 0.0) fe += C.ham * abar / (12.0 * Q);
+    const bool contact = h < 0.0;
+    double FC[3] = {0.0, 0.0, 0.0}, Ft[3] = {0.0, 0.0, 0.0}, xpp[3] = {0.0, 0.0, 0.0};
+    double D[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0}, sv[3] = {0.0, 0.0, 0.0}, xs[3] = {0.0, 0.0, 0.0};
+    double xp[3] = {0.0, 0.0, 0.0};
+    double fn = 0.0, tn = 0.0, xsn = 0.0, cap = 0.0, xm = 0.0, sc = 1.0;
+    bool capped = false;
+    if (contact) {
+        D[0] = dux + gd * r[1];
+        D[1] = duy;
+        D[2] = duz;
+        const double un = vdot(D, n);
+        fn = C.kn * h + C.gn * un;
+        for (int k = 0; k < 3; ++k) sv[k] = ai * Wi[k] + aj * Wj[k];
+        double q[3];
+        vcross(sv, n, q);
+        for (int k = 0; k < 3; ++k) t[k] = D[k] - q[k];
+        tn = vdot(t, n);
+        for (int k = 0; k < 3; ++k) xs[k] = xo[k] + (t[k] - tn * n[k]) * C.dt;
+        xsn = vdot(xs, n);
+        for (int k = 0; k < 3; ++k) xp[k] = xs[k] - xsn * n[k];
+        if (C.kt > 0.0) {
+            cap = C.mu * fabs(fn) / C.kt;
+            xm = sqrt(vdot(xp, xp));
+            capped = xm >= cap && xm > 0.0;
+            sc = capped ? cap / xm : 1.0;
+            for (int k = 0; k < 3; ++k) {
+                xpp[k] = xp[k] * sc;
+                Ft[k] = C.kt * xpp[k];
+            }
+        }
+        double m[3];
+        vcross(n, Ft, m);
+        for (int k = 0; k < 3; ++k) {
+            FC[k] = fn * n[k] + Ft[k];
+            Ti[k] += ai * m[k];
+            Tj[k] += aj * m[k];
+        }
+    }
+    double FO[3];
+    for (int k = 0; k < 3; ++k) FO[k] = FC[k] + fe * n[k];
+    if (val) {
+        for (int k = 0; k < 3; ++k) {
+            val->Fi[k] = FL[k] + FO[k];
+            val->Ti[k] = Ti[k];
+            val->Tj[k] = Tj[k];
+            val->xi[k] = xpp[k];
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) val->S[3 * a + b] = 0.5 * (r[a] * FL[b] + r[b] * FL[a]) + r[a] * FO[b];
+        val->contact = contact;
+        val->capped = capped;
+    }
+
+    // ------------------------------------------------------------------ reverse
+    double rb[3] = {0.0, 0.0, 0.0}, nb[3] = {0.0, 0.0, 0.0};
+    double hb = 0.0, duxb = 0.0, duyb = 0.0, duzb = 0.0;
+    double wib[3] = {0.0, 0.0, 0.0}, wjb[3] = {0.0, 0.0, 0.0};
+    // stresslet S_ab = (r_a FL_b + r_b FL_a) / 2 + r_a FO_b, F_i = FL + FO
+    double FLb[3], FOb[3];
+    for (int b = 0; b < 3; ++b) {
+        FLb[b] = bar.Fi[b];
+        FOb[b] = bar.Fi[b];
+        for (int a = 0; a < 3; ++a) {
+            FLb[b] += 0.5 * (bar.S[3 * a + b] + bar.S[3 * b + a]) * r[a];
+            FOb[b] += bar.S[3 * a + b] * r[a];
+        }
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) rb[a] += 0.5 * (bar.S[3 * a + b] + bar.S[3 * b + a]) * FL[b] + bar.S[3 * a + b] * FO[b];
+    // FO = FC + fe n
+    const double feb = vdot(FOb, n);
+    vaxpy(fe, FOb, nb);
+    if (C.fer != 0.0) {
+        g.fer += -(abar / C.a0) * E * feb;
+        if (h >= 0.0 && C.lamd > 0.0) hb += (C.fer / C.a0) * abar * E * feb / C.lamd;
+    }
+    if (C.ham != 0.0 && h >= 0.0) hb += -C.ham * abar * 2.0 * h / (12.0 * Q * Q) * feb;
+    double Tib[3] = {bar.Ti[0], bar.Ti[1], bar.Ti[2]}, Tjb[3] = {bar.Tj[0], bar.Tj[1], bar.Tj[2]};
+    if (contact) {
+        // m = n x Ft feeds T_i += a_i m, T_j += a_j m
+        double mb[3], tmp[3];
+        for (int k = 0; k < 3; ++k) mb[k] = ai * Tib[k] + aj * Tjb[k];
+        double Ftb[3];
+        vcross(Ft, mb, tmp);
+        vaxpy(1.0, tmp, nb);
+        vcross(mb, n, Ftb);
+        // FC = fn n + Ft
+        for (int k = 0; k < 3; ++k) Ftb[k] += FOb[k];
+        double fnb = vdot(FOb, n);
+        vaxpy(fn, FOb, nb);
+        double xpb[3] = {0.0, 0.0, 0.0};
+        if (C.kt > 0.0) {
+            double xppb[3];
+            for (int k = 0; k < 3; ++k) xppb[k] = C.kt * Ftb[k] + bar.xi[k];
+            if (capped) {
+                // xpp = xp cap / |xp|, cap = mu |fn| / kt
+                const double scb = vdot(xppb, xp);
+                const double capb = scb / xm;
+                const double xmb = -scb * cap / (xm * xm);
+                for (int k = 0; k < 3; ++k) xpb[k] = sc * xppb[k] + xmb * xp[k] / xm;
+                g.mu += fabs(fn) / C.kt * capb;
+                fnb += (fn > 0.0 ? 1.0 : (fn < 0.0 ? -1.0 : 0.0)) * C.mu / C.kt * capb;
+            } else {
+                for (int k = 0; k < 3; ++k) xpb[k] = xppb[k];
+            }
+        }
+        // xp = xs - (xs.n) n
+        const double xpn = vdot(xpb, n);
+        double xsb[3];
+        for (int k = 0; k < 3; ++k) {
+            xsb[k] = xpb[k] - xpn * n[k];
+            nb[k] += -xpn * xs[k] - xsn * xpb[k];
+        }
+        // xs = xo + (t - (t.n) n) dt
+        for (int k = 0; k < 3; ++k) g.xo[k] += xsb[k];
+        double yb[3] = {C.dt * xsb[0], C.dt * xsb[1], C.dt * xsb[2]};
+        const double ybn = vdot(yb, n);
+        double tb[3];
+        for (int k = 0; k < 3; ++k) {
+            tb[k] = yb[k] - ybn * n[k];
+            nb[k] += -ybn * t[k] - tn * yb[k];
+        }
+        // t = D - q, q = sv x n, sv = a_i w_i + a_j w_j
+        double Db[3] = {tb[0], tb[1], tb[2]};
+        const double qb[3] = {-tb[0], -tb[1], -tb[2]};
+        double svb[3];
+        vcross(n, qb, svb);
+        vcross(qb, sv, tmp);
+        vaxpy(1.0, tmp, nb);
+        for (int k = 0; k < 3; ++k) {
+            g.wi[k] += ai * svb[k];
+            g.wj[k] += aj * svb[k];
+        }
+        // fn = kn h + gn (D.n)
+        hb += C.kn * fnb;
+        const double unb = C.gn * fnb;
+        vaxpy(unb, n, Db);
+        vaxpy(unb, D, nb);
+        // D = (dux + gd r_y, duy, duz)
+        duxb += Db[0];
+        rb[1] += gd * Db[0];
+        duyb += Db[1];
+        duzb += Db[2];
+    }
+    // lubrication torques
+    {
+        double nvb[3], tib[3], tjb[3];
+        for (int k = 0; k < 3; ++k) {
+            nvb[k] = -YBi * Tib[k] + YBj * Tjb[k];
+            tib[k] = -YCii * Tib[k] - YCij * Tjb[k];
+            tjb[k] = -YCij * Tib[k] - YCjj * Tjb[k];
+        }
+        double YBib = -vdot(Tib, nv), YBjb = vdot(Tjb, nv);
+        const double YCiib = -vdot(Tib, ti), YCijb = -(vdot(Tib, tj) + vdot(Tjb, ti)), YCjjb = -vdot(Tjb, tj);
+        // ti = wi - (wi.n) n
+        const double tin = vdot(tib, n), tjn = vdot(tjb, n);
+        for (int k = 0; k < 3; ++k) {
+            wib[k] += tib[k] - tin * n[k];
+            wjb[k] += tjb[k] - tjn * n[k];
+            nb[k] += -tin * wi[k] - win * tib[k] - tjn * wj[k] - wjn * tjb[k];
+        }
+        // nv = n x v
+        double vb[3], tmp[3];
+        vcross(v, nvb, tmp);
+        vaxpy(1.0, tmp, nb);
+        vcross(nvb, n, vb);
+        // FL = XA vn n + YA (v - vn n) - YBi ci + YBj cj
+        const double FLn = vdot(FLb, n);
+        const double XAb = vn * FLn;
+        const double YAb = vdot(FLb, v) - vn * FLn;
+        YBib += -vdot(FLb, ci);
+        YBjb += vdot(FLb, cj);
+        const double vnb = (XA - YA) * FLn;
+        vaxpy((XA - YA) * vn, FLb, nb);
+        vaxpy(YA, FLb, vb);
+        double cib[3], cjb[3];
+        for (int k = 0; k < 3; ++k) {
+            cib[k] = -YBi * FLb[k];
+            cjb[k] = YBj * FLb[k];
+        }
+        // c = n x w
+        vcross(wi, cib, tmp);
+        vaxpy(1.0, tmp, nb);
+        vcross(wj, cjb, tmp);
+        vaxpy(1.0, tmp, nb);
+        vcross(cib, n, tmp);
+        vaxpy(1.0, tmp, wib);
+        vcross(cjb, n, tmp);
+        vaxpy(1.0, tmp, wjb);
+        // vn = v.n
+        vaxpy(vnb, n, vb);
+        vaxpy(vnb, v, nb);
+        // v = (dux + s gd n_y / 2, duy + s gd n_x / 2, duz)
+        duxb += vb[0];
+        nb[1] += 0.5 * s * gd * vb[0];
+        duyb += vb[1];
+        nb[0] += 0.5 * s * gd * vb[1];
+        duzb += vb[2];
+        // coefficients: X = c invg, Y = c lg, invg = 1 / g, lg = -log g, g = max(2h/s, 0) + eps
+        const double invgb = cXA * XAb;
+        const double lgb = cYA * YAb + cYBi * YBib + cYBj * YBjb + cYCii * YCiib + cYCij * YCijb + cYCjj * YCjjb;
+        const double ggb = -invg * invg * invgb - lgb / gg;
+        if (dpos) hb += 2.0 / s * ggb;
+    }
+    // w' = w + (0, 0, gd / 2)
+    for (int k = 0; k < 3; ++k) {
+        g.wi[k] += wib[k];
+        g.wj[k] += wjb[k];
+    }
+    // du = (u_j - gd y_j x) - (u_i - gd y_i x)
+    g.uj[0] += duxb;
+    g.ui[0] -= duxb;
+    g.yj += -gd * duxb;
+    g.yi += gd * duxb;
+    g.uj[1] += duyb;
+    g.ui[1] -= duyb;
+    g.uj[2] += duzb;
+    g.ui[2] -= duzb;
+    // n = r / |r|, h = |r| - a_i - a_j
+    const double nn = vdot(nb, n);
+    for (int k = 0; k < 3; ++k) g.r[k] += rb[k] + (nb[k] - nn * n[k]) * inv_d + hb * n[k];
+}
+
+}  // namespace dss

@@ -25,7 +25,7 @@ STATUS = {0: "DSS_OK", 1: "DSS_ERR_ARG", 2: "DSS_ERR_HIP", 3: "DSS_ERR_CAPACITY"
 EXPORTS = ["dss_create", "dss_create_batch", "dss_set_particles", "dss_set_particles_batch", "dss_set_step", "dss_build_neighbours", "dss_compute_forces", "dss_step",
            "dss_read_stress", "dss_read_stress_batch", "dss_get_box_info", "dss_get_state", "dss_get_eval_velocities", "dss_get_pairs", "dss_get_cells",
            "dss_get_history", "dss_get_info", "dss_save_state", "dss_load_state", "dss_set_timing",
-           "dss_get_timing", "dss_set_tuning", "dss_get_tuning", "dss_last_error",
+           "dss_get_timing", "dss_set_tuning", "dss_get_tuning", "dss_adjoint", "dss_last_error",
            "dss_status_string", "dss_destroy"]
 
 
@@ -72,6 +72,12 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libdss.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    # torch ships its own HIP runtime under the same soname; loading torch first makes libdss
+    # bind to that one, so a process that also uses torch on the GPU holds a single runtime
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     H = ctypes.c_void_p
     vp = ctypes.c_void_p
@@ -101,6 +107,8 @@ def load_library():
         "dss_get_timing": (st, [H, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         "dss_set_tuning": (st, [H, ctypes.POINTER(Tuning)]),
         "dss_get_tuning": (st, [H, ctypes.POINTER(Tuning)]),
+        "dss_adjoint": (st, [H, i64, i64, i64, vp, ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp,
+                             ctypes.c_int]),
         "dss_last_error": (ctypes.c_char_p, [H]),
         "dss_status_string": (ctypes.c_char_p, [st]),
         "dss_destroy": (None, [H]),
@@ -292,6 +300,39 @@ class Simulation:
         if graph is not None:
             t.graph = int(bool(graph))
         self._check(self.lib.dss_set_tuning(self.h, ctypes.byref(t)))
+
+    def adjoint(self, n_steps, stress_every, ckpt_every=20, weight=None):
+        """Run n_steps steps and return J = sum weight * mean Sigma and its gradient by the
+        discrete adjoint: {"J", "dmu", "dF_ER", "dx", "du", "dw"} (by id, host arrays).
+        weight: 3 x 3 (default: the shear stress Sigma_xy)."""
+        if weight is None:
+            weight = np.zeros((3, 3))
+            weight[0, 1] = 1.0
+        wt = np.ascontiguousarray(np.asarray(weight, np.float64).reshape(9))
+        J = ctypes.c_double(0.0)
+        th = np.zeros(2)
+        dx = np.zeros((self.N, 3))
+        du = np.zeros((self.N, 3))
+        dw = np.zeros((self.N, 3))
+        vp = ctypes.c_void_p
+        self._check(self.lib.dss_adjoint(self.h, int(n_steps), int(stress_every), int(ckpt_every),
+                                         vp(wt.ctypes.data), ctypes.byref(J), vp(th.ctypes.data),
+                                         vp(dx.ctypes.data), vp(du.ctypes.data), vp(dw.ctypes.data), 0))
+        return {"J": J.value, "dmu": th[0], "dF_ER": th[1], "dx": dx, "du": du, "dw": dw}
+
+    def adjoint_into(self, n_steps, stress_every, ckpt_every, weight, dx, du, dw):
+        """As adjoint(), writing the state gradients into device tensors; returns (J, dmu, dF_ER)."""
+        wt = np.ascontiguousarray(np.asarray(weight, np.float64).reshape(9))
+        J = ctypes.c_double(0.0)
+        th = np.zeros(2)
+        ptrs = [_ptr(a) for a in (dx, du, dw)]
+        devs = {q[2] for q in ptrs if q[2] is not None}
+        if devs != {True}:
+            raise ValueError("adjoint_into takes device tensors")
+        self._check(self.lib.dss_adjoint(self.h, int(n_steps), int(stress_every), int(ckpt_every),
+                                         ctypes.c_void_p(wt.ctypes.data), ctypes.byref(J),
+                                         ctypes.c_void_p(th.ctypes.data), *[q[0] for q in ptrs], 1))
+        return J.value, th[0], th[1]
 
     def tuning(self):
         t = Tuning()

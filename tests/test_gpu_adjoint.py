@@ -1,0 +1,187 @@
+"""Discrete adjoint of the time step (dss_adjoint) on an MI355X against central finite
+differences of the FP64 oracle's stress objective J = mean_samples(Sigma_xy).
+
+The derivative is that of the run with its pair set, contact states and Coulomb-cap states
+held fixed, so every finite difference is checked to stay on the unperturbed run's branch
+(same listed-pair counts and contact sets at every step).  Window: N = 400 bidisperse
+spheres at phi = 0.52, mu = 0.1 (sliding contacts, so dJ/dmu != 0), 20 steps, stress every 5,
+checkpoints every 7 steps (segments of 7, 7, 6: the segment boundaries and a ragged last
+segment are crossed)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2108_01013_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+# finite-difference steps: small enough to stay on the run's branch, large enough that the
+# rounding noise of J (~1e-13 absolute) stays below the tolerances
+EPS = {"mu": 1e-6, "F_ER": 1e-5, "x": 1e-7, "u": 1e-6, "w": 1e-6}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def window():
+    w = synth.bidisperse_box(400, 0.52, seed=21)
+    p = dict(w.params, mu=0.1)
+    u0 = oracle.ambient_velocity(p, w.x)
+    w0 = oracle.ambient_rotation(p, len(w.rad))
+    W = np.zeros((3, 3))
+    W[0, 1] = 1.0
+    return w, p, u0, w0, W
+
+
+def gpu_adjoint(p, w, u0, w0, W, K=20, se=5, C=7):
+    from paper_2108_01013_amd.dss import Simulation
+    sim = Simulation(p)
+    sim.set_particles(w.x, w.rad, u0, w0)
+    r = sim.adjoint(K, se, C, W)
+    info = sim.info()
+    last, mean, ns = sim.read_stress()
+    sim.close()
+    return r, info, mean, ns
+
+
+def fd(p, w, u0, w0, W, br0, perturb, eps, K=20, se=5):
+    """Central difference of the oracle's J, or None if a perturbed run left the branch."""
+    vals = []
+    for sgn in (1.0, -1.0):
+        pp, x, u, ww = perturb(sgn * eps)
+        J, br = oracle.stress_objective(pp, x, w.rad, u, ww, K, se, W)
+        if br != br0:
+            return None
+        vals.append(J)
+    return (vals[0] - vals[1]) / (2 * eps)
+
+
+def test_adjoint_objective_and_end_state(window):
+    w, p, u0, w0, W = window
+    say("case: adjoint J and end state N=400")
+    r, info, mean, ns = gpu_adjoint(p, w, u0, w0, W)
+    J0, _ = oracle.stress_objective(p, w.x, w.rad, u0, w0, 20, 5, W)
+    assert abs(r["J"] - J0) <= 1e-10 * abs(J0)
+    assert ns == 4 and abs(mean[0, 1] - J0) <= 1e-10 * abs(J0)
+    assert info["step"] == 20 and info["error_flags"] == 0
+
+
+def test_adjoint_parameters_vs_oracle_fd(window):
+    w, p, u0, w0, W = window
+    say("case: adjoint dJ/dmu, dJ/dF_ER N=400")
+    r, *_ = gpu_adjoint(p, w, u0, w0, W)
+    _, br0 = oracle.stress_objective(p, w.x, w.rad, u0, w0, 20, 5, W)
+    for name, key, tol in (("mu", "dmu", 1e-5), ("F_ER", "dF_ER", 1e-3)):
+        g = fd(p, w, u0, w0, W, br0, lambda e: (dict(p, **{name: p[name] + e}), w.x, u0, w0), EPS[name])
+        assert g is not None, "finite difference left the branch of the run"
+        say(f"d J / d {name}: adjoint {r[key]:.10e}  oracle FD {g:.10e}")
+        assert abs(r[key] - g) <= tol * abs(g) + 1e-8, (name, r[key], g)
+    assert abs(r["dmu"]) > 1e-3    # sliding contacts: the Coulomb cap is active
+
+
+@pytest.mark.parametrize("which", ["x", "u", "w"])
+def test_adjoint_state_vs_oracle_fd(window, which):
+    w, p, u0, w0, W = window
+    say(f"case: adjoint dJ/d{which}0 N=400")
+    r, *_ = gpu_adjoint(p, w, u0, w0, W)
+    _, br0 = oracle.stress_objective(p, w.x, w.rad, u0, w0, 20, 5, W)
+    rng = np.random.default_rng({"x": 1, "u": 2, "w": 3}[which])
+    checked = 0
+    for d in range(8):
+        if checked == 3:
+            break
+        v = rng.normal(size=w.x.shape)
+        if which == "x":
+            L = np.array(p["L"])
+            v[np.any((w.x < 1e-4) | (w.x > L - 1e-4), axis=1)] = 0.0   # stay inside the box
+            pert = lambda e: (p, w.x + e * v, u0, w0)  # noqa: E731
+        elif which == "u":
+            pert = lambda e: (p, w.x, u0 + e * v, w0)  # noqa: E731
+        else:
+            pert = lambda e: (p, w.x, u0, w0 + e * v)  # noqa: E731
+        g = fd(p, w, u0, w0, W, br0, pert, EPS[which])
+        if g is None:
+            say(f"direction {d}: a listed pair crosses the cutoff within the step; skipped")
+            continue
+        ad = float(np.sum(r["d" + which] * v))
+        say(f"direction {d}: adjoint {ad:.10e}  oracle FD {g:.10e}")
+        assert abs(ad - g) <= 1e-5 * abs(g) + 1e-6, (which, d, ad, g)
+        checked += 1
+    assert checked == 3
+
+
+def test_adjoint_checkpoint_spacing_invariance(window):
+    """The gradient does not depend on the checkpoint spacing (1 segment vs segments of 3)."""
+    w, p, u0, w0, W = window
+    say("case: adjoint checkpoint spacing N=400")
+    a, *_ = gpu_adjoint(p, w, u0, w0, W, C=20)
+    b, *_ = gpu_adjoint(p, w, u0, w0, W, C=3)
+    for k in ("dx", "du", "dw"):
+        assert np.max(np.abs(a[k] - b[k])) <= 1e-8 * np.max(np.abs(a[k])), k
+    assert abs(a["dmu"] - b["dmu"]) <= 1e-8 * abs(a["dmu"])
+
+
+def test_adjoint_torch_function(window):
+    """torch.autograd through StressObjective equals the direct adjoint."""
+    import torch
+
+    from paper_2108_01013_amd.adjoint import stress_objective
+    w, p, u0, w0, W = window
+    say("case: adjoint torch.autograd N=400")
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(w.x, device=dev, requires_grad=True)
+    u = torch.tensor(u0, device=dev, requires_grad=True)
+    om = torch.tensor(w0, device=dev, requires_grad=True)
+    mu = torch.tensor(p["mu"], dtype=torch.float64, requires_grad=True)
+    fer = torch.tensor(p["F_ER"], dtype=torch.float64, requires_grad=True)
+    J = stress_objective(x, u, om, mu, fer, torch.tensor(w.rad, device=dev), p, 20, 5, 7)
+    (2.0 * J).backward()
+    r, *_ = gpu_adjoint(p, w, u0, w0, W)
+    assert abs(J.item() - r["J"]) <= 1e-10 * abs(r["J"])
+    assert np.max(np.abs(x.grad.cpu().numpy() - 2 * r["dx"])) <= 1e-8 * np.max(np.abs(r["dx"]))
+    assert abs(mu.grad.item() - 2 * r["dmu"]) <= 1e-8 * abs(r["dmu"])
+
+
+def test_adjoint_full_size_50k():
+    """The adjoint workload (N = 50k, phi = 0.56, 200 steps, checkpoints every 20): J equals
+    the forward run's, the gradient is finite, and a directional derivative in F_ER matches
+    a GPU finite difference over a 10-step window."""
+    from paper_2108_01013_amd.dss import Simulation
+    w = synth.bidisperse_box(50_000, 0.56, seed=5)
+    p = w.params
+    W = np.zeros((3, 3))
+    W[0, 1] = 1.0
+    say("case: adjoint N=50000 200 steps")
+    sim = Simulation(p)
+    sim.set_particles(w.x, w.rad)
+    r = sim.adjoint(200, 10, 20, W)
+    sim.close()
+    for k in ("dx", "du", "dw"):
+        assert np.all(np.isfinite(r[k]))
+    sim = Simulation(p)
+    sim.set_particles(w.x, w.rad)
+    sim.step(200, stress_every=10)
+    _, mean, ns = sim.read_stress()
+    sim.close()
+    assert ns == 20 and abs(mean[0, 1] - r["J"]) <= 1e-8 * abs(r["J"])
+    # short window: FD in F_ER on the GPU forward
+    sim = Simulation(p)
+    sim.set_particles(w.x, w.rad)
+    r10 = sim.adjoint(10, 5, 5, W)
+    sim.close()
+    vals = []
+    for sgn in (1.0, -1.0):
+        s2 = Simulation(dict(p, F_ER=p["F_ER"] + sgn * 1e-5))
+        s2.set_particles(w.x, w.rad)
+        s2.step(10, stress_every=5)
+        _, m2, _ = s2.read_stress()
+        s2.close()
+        vals.append(m2[0, 1])
+    g = (vals[0] - vals[1]) / 2e-5
+    say(f"N=50000 d J / d F_ER over 10 steps: adjoint {r10['dF_ER']:.8e}  GPU FD {g:.8e}")
+    assert abs(r10["dF_ER"] - g) <= 1e-3 * abs(g) + 1e-9

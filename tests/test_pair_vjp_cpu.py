@@ -1,0 +1,106 @@
+"""The pair VJP of the HIP library (paper_2108_01013_amd/csrc/pair_vjp.hpp), compiled for the
+CPU, against central finite differences of its own primal, on every branch: lubrication
+only, attraction, contact below the Coulomb cap (stick), contact at the cap (slip).  The
+adjoint of the whole step is checked against finite differences of the oracle on the GPU."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2108_01013_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def lib(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("vjp") / "libpairvjp.so")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-I", CSRC,
+                           os.path.join(ROOT, "tests", "pair_vjp_harness.cpp"), "-o", out])
+    L = ctypes.CDLL(out)
+    L.pair_vjp_host.restype = None
+    L.pair_vjp_host.argtypes = [ctypes.c_void_p] * 5
+    return L
+
+
+def call(L, x, cst, bar):
+    grad = np.zeros(22)
+    val = np.zeros(23)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    x = np.ascontiguousarray(x, np.float64)
+    L.pair_vjp_host(ptr(x), ptr(cst), ptr(bar), ptr(grad), ptr(val))
+    return grad, val
+
+
+# differentiable inputs inside the 25-value input vector (gd, a_i, a_j are constants)
+DIFF = [1, 2, 3, 6, 7] + list(range(8, 23)) + [23, 24]
+
+
+def make_case(kind, rng, balanced=False):
+    ai, aj = 1.0, 1.4
+    n = rng.normal(size=3)
+    n /= np.linalg.norm(n)
+    gap = {"lub": 0.08, "attr": 0.05, "stick": -2e-3, "slip": -2e-3}[kind]
+    r = (ai + aj + gap) * n
+    x = np.zeros(25)
+    x[0] = 0.7                       # shear rate
+    x[1:4] = r
+    x[4], x[5] = ai, aj
+    x[6], x[7] = 3.1, 3.1 + r[1]      # y_i, y_j
+    x[8:20] = rng.normal(size=12) * 0.3
+    xi_dir = np.cross(n, rng.normal(size=3))
+    x[20:23] = xi_dir / np.linalg.norm(xi_dir) * (1e-6 if kind == "stick" else 5e-3)
+    x[23] = 0.5 if kind == "slip" else 1e3     # mu
+    x[24] = 1.3                                 # F_ER
+    cst = np.array([6 * np.pi, 4e5, 4e5 * 2 / 7, 0.04, 1.0, 0.05, 0.2 if kind == "attr" else 0.0, 0.01, 0.02,
+                    1e-4])
+    if balanced:
+        # constants that make every term of the same order, so that no term hides in the tolerance
+        cst = np.array([0.5, 50.0, 20.0, 5.0, 1.0, 0.3, 0.2 if kind == "attr" else 0.0, 0.01, 0.02, 0.05])
+        if kind == "slip":
+            x[23] = 0.05
+        if kind == "stick":
+            x[20:23] *= 1e-3
+    return x, cst
+
+
+@pytest.mark.parametrize("balanced", [False, True])
+@pytest.mark.parametrize("kind", ["lub", "attr", "stick", "slip"])
+def test_pair_vjp_matches_finite_differences(lib, kind, balanced):
+    rng = np.random.default_rng({"lub": 1, "attr": 2, "stick": 3, "slip": 4}[kind])
+    x, cst = make_case(kind, rng, balanced)
+    bar = rng.normal(size=21)
+    g, val = call(lib, x, cst, bar)
+    assert val[21] == (1.0 if kind in ("stick", "slip") else 0.0)
+    assert val[22] == (1.0 if kind == "slip" else 0.0)   # the intended branch of the Coulomb cap
+    fd = np.zeros(22)
+    for k, idx in enumerate(DIFF):
+        eps = 1e-6 * max(1.0, abs(x[idx]))
+        if idx in (20, 21, 22):
+            eps = 1e-9
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += eps
+        xm[idx] -= eps
+        _, vp = call(lib, xp, cst, bar)
+        _, vm = call(lib, xm, cst, bar)
+        assert vp[21] == vm[21] == val[21] and vp[22] == vm[22] == val[22]
+        fd[k] = np.dot(bar, (vp[:21] - vm[:21]) / (2 * eps))
+    scale = np.max(np.abs(fd))
+    err = np.max(np.abs(g - fd)) / scale
+    assert err < 1e-6, (kind, err, np.argmax(np.abs(g - fd)))
+
+
+def test_pair_vjp_action_reaction_and_translation(lib):
+    """Moving both particles together (r fixed, y_i = y_j shifted, u_i = u_j shifted by the
+    ambient flow) leaves the pair unchanged: the gradients of those directions vanish."""
+    rng = np.random.default_rng(7)
+    x, cst = make_case("stick", rng)
+    bar = rng.normal(size=21)
+    g, _ = call(lib, x, cst, bar)
+    # d/dy of a common y shift of both particles, with the ambient velocity following it
+    gd = x[0]
+    common = g[3] + g[4] + gd * (g[5] + g[8])
+    assert abs(common) < 1e-9 * np.max(np.abs(g))
+    # a common velocity shift
+    assert np.max(np.abs(g[5:8] + g[8:11])) < 1e-9 * np.max(np.abs(g))
