@@ -104,11 +104,37 @@ def kernel_table(breakdown):
             if v[1] > 0}
 
 
+def cached_workload(args, make):
+    """The seeded workload, or its copy saved by an earlier run of the same command (profiling
+    passes re-run the benchmark; --workload-cache keeps them from regenerating it)."""
+    import numpy as np
+    if args.workload_cache and os.path.exists(args.workload_cache):
+        from paper_2108_01013_amd import synth
+        z = np.load(args.workload_cache)
+        L = float(z["L"])
+        return synth.Workload(str(z["name"]), z["x"], z["rad"], L, synth.default_params([L, L, L]))
+    w = make()
+    if args.workload_cache:
+        np.savez(args.workload_cache, x=w.x, rad=w.rad, L=w.L, name=w.name)
+    return w
+
+
+def copy_probe(nbytes: int = 1 << 28, reps: int = 3):
+    """A plain device copy of known size (calibration of the HBM byte counters)."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"# copy probe: {reps} copies of {nbytes} bytes", file=sys.stderr, flush=True)
+
+
 def run_single(args):
     from paper_2108_01013_amd import synth
 
     t_gen = time.perf_counter()
-    w = synth.config_single_box(N=args.N)
+    w = cached_workload(args, lambda: synth.config_single_box(N=args.N))
     print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     import torch
 
@@ -200,14 +226,104 @@ def run_sweep(args):
     }
 
 
+def vjp_kernel_bytes(N: int, pairs: int, contacts: int) -> float:
+    """Compulsory bytes of one k_pairs_vjp launch: per particle x, u, w, radius read (80 B),
+    force / torque cotangents read (48 B), x, u, w adjoints added (72 B read + 72 B written);
+    per pair its two ids (8 B); per contact the old and new stretch with their keys
+    (2 x 28 B) and the old-stretch adjoint written and the new one read (2 x 24 B)."""
+    return N * (80 + 48 + 144) + pairs * 8 + contacts * (56 + 48)
+
+
+def run_adjoint(args):
+    import numpy as np
+
+    from paper_2108_01013_amd import synth
+
+    t_gen = time.perf_counter()
+    N = args.N if args.N != 100_000 else 50_000
+    w = synth.bidisperse_box(N, 0.56, seed=5)
+    print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    import torch
+
+    from paper_2108_01013_amd.dss import Simulation
+    torch.cuda.set_device(0)
+    p = w.params
+    K, se, C = args.steps, 10, args.ckpt
+    Wt = np.zeros((3, 3))
+    Wt[0, 1] = 1.0
+    sim = Simulation(p, stream=torch.cuda.current_stream().cuda_stream)
+    sim.set_particles(w.x, w.rad)
+    # warm-up: a short adjoint (allocations, first launches), then back to a state at u^n
+    sim.adjoint(min(args.warmup, K) or 1, 1, C, Wt)
+    sim.compute_forces()
+    torch.cuda.synchronize()
+    # forward only, for the ratio
+    t0 = time.perf_counter()
+    sim.step(K, stress_every=se, sync=True)
+    fwd = time.perf_counter() - t0
+    sim.compute_forces()
+    sim.set_timing(True, kernels=["k_pairs_vjp"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = sim.adjoint(K, se, C, Wt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tm = sim.timing()
+    sim.set_timing(False)
+    info = sim.info()
+    ms, nl = tm["k_pairs_vjp"]
+    avg = ms / max(nl, 1) * 1e-3
+    bytes_launch = vjp_kernel_bytes(N, info["n_pairs"], info["n_contacts"])
+    ach = bytes_launch / avg / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_pairs_vjp",
+            "avg_launch_us": round(avg * 1e6, 3), "bytes_per_launch": int(bytes_launch)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's forward objective on a bounded window; its gradient would be 2 runs per
+        # component by finite differences
+        import oracle
+        small = synth.bidisperse_box(2000, 0.56, seed=5)
+        u0 = oracle.ambient_velocity(small.params, small.x)
+        w0 = oracle.ambient_rotation(small.params, len(small.rad))
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < args.cpu_seconds and k < 10:
+            oracle.stress_objective(small.params, small.x, small.rad, u0, w0, 20, 10, Wt, use_cells=True)
+            k += 1
+        ec = time.perf_counter() - t0
+        cpu = {"value": 2000 * 20 * k / ec, "unit": "particle-steps/s (forward objective only)",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"{k} oracle runs of the stress objective, N=2000 phi=0.56, 20 steps each, {ec:.1f} s; "
+                         "a finite-difference gradient costs 2 such runs per component"}
+    return {
+        "metric": "adjoint particle-steps/s (forward + checkpointed recompute + reverse)",
+        "value": round(N * K / el, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(el / K * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"adjoint of mean Sigma_xy over {K} steps, N={N} bidisperse 1:1.4, phi=0.56, "
+                               f"stress every {se}, checkpoints every {C}, gradients w.r.t. x0, u0, w0, mu, F_ER",
+                   "N": N, "ckpt_every": C},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "forward_only_ms_per_step": round(fwd / K * 1e3, 5),
+        "adjoint_over_forward": round(el / fwd, 3),
+        "diagnostics": {"J": r["J"], "dJ_dmu": r["dmu"], "dJ_dF_ER": r["dF_ER"],
+                        "grad_x_norm": float(np.linalg.norm(r["dx"])), "n_pairs": info["n_pairs"],
+                        "n_contacts": info["n_contacts"]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--mode", choices=["single", "sweep"], default="single",
-                    help="single: one box of N particles; sweep: the batched flow-curve sweep")
+    ap.add_argument("--mode", choices=["single", "sweep", "adjoint"], default="single",
+                    help="single: one box of N particles; sweep: the batched flow-curve sweep; "
+                         "adjoint: gradient of the mean shear stress (N=50k)")
+    ap.add_argument("--ckpt", type=int, default=20, help="adjoint checkpoint spacing")
     ap.add_argument("--N", type=int, default=100_000)
     ap.add_argument("--boxes", type=int, default=64)
     ap.add_argument("--workers", type=int, default=16, help="processes generating the sweep's boxes")
@@ -216,6 +332,8 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=20)
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload-cache", default=None, help="npz file to reuse the single-box workload")
+    ap.add_argument("--copy-probe", action="store_true", help="end with plain 256 MiB device copies")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.tune is None:
@@ -226,7 +344,9 @@ def main():
               "z-slab decomposition is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    out = run_single(args) if args.mode == "single" else run_sweep(args)
+    out = {"single": run_single, "sweep": run_sweep, "adjoint": run_adjoint}[args.mode](args)
+    if args.copy_probe:
+        copy_probe()
     print(json.dumps(out), flush=True)
 
 

@@ -8,6 +8,7 @@
 //   k_finish   stress and counters from the partials, stress sample (only on steps that take
 //              a stress sample and on the last step of a dss_step call)
 // The history rows written by k_pairs become the committed history of the step.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -88,12 +89,12 @@ struct dss_handle {
     DevRun run_host{};
 
     // kernel timing with events on the stream
-    static constexpr int kKernels = 5;
+    static constexpr int kKernels = 7;
     unsigned timing = 0;       // bit k: time kernel k
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<int, int>>> ev_marks;  // (kernel, (start event, stop event))
-    double kernel_ms[kKernels] = {0, 0, 0, 0, 0};
-    int64_t kernel_launches[kKernels] = {0, 0, 0, 0, 0};
+    double kernel_ms[kKernels] = {};
+    int64_t kernel_launches[kKernels] = {};
 };
 
 namespace {
@@ -205,29 +206,34 @@ dss_status check_flags(dss_handle *h)
     return DSS_OK;
 }
 
-// Event pair around one launch when timing is on (events are reused across calls).
+// Start / stop events of one timed launch (events are reused across calls).  The kernel is
+// launched with hipExtLaunchKernelGGL, which records them at the kernel's own start and end,
+// so the measured time is the kernel's execution without the launch gaps.
 struct TimedLaunch {
     dss_handle *h;
     int kernel;
-    int e0 = -1, e1 = -1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int i0 = -1, i1 = -1;
     TimedLaunch(dss_handle *h_, int k) : h(h_), kernel(k)
     {
         if (!(h->timing & (1u << k))) return;
-        e0 = take();
-        if (e0 >= 0) (void)hipEventRecord(h->ev_pool[e0], h->stream);
+        i0 = take(0);
+        i1 = take(1);
+        if (i0 < 0 || i1 < 0) {
+            i0 = i1 = -1;
+            return;
+        }
+        e0 = h->ev_pool[i0];
+        e1 = h->ev_pool[i1];
     }
     ~TimedLaunch()
     {
-        if (e0 < 0) return;
-        e1 = take();
-        if (e1 < 0) return;
-        (void)hipEventRecord(h->ev_pool[e1], h->stream);
-        h->ev_marks.push_back({kernel, {e0, e1}});
+        if (i0 >= 0) h->ev_marks.push_back({kernel, {i0, i1}});
     }
-    int take()
+    int take(int off)
     {
-        size_t used = 2 * h->ev_marks.size() + (e0 >= 0 ? 1 : 0);
-        if (used >= h->ev_pool.size()) {
+        const size_t used = 2 * h->ev_marks.size() + off;
+        while (used >= h->ev_pool.size()) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) return -1;
             h->ev_pool.push_back(e);
@@ -401,20 +407,20 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, boo
     {
         TimedLaunch t(h, 3);
         if (h->prm.precision == DSS_MIXED)
-            hipLaunchKernelGGL(k_pairs<float>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, h->P,
-                               h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(),
-                               H, h->clk, h->partials, h->pairs, h->pair_count);
+            hipExtLaunchKernelGGL(k_pairs<float>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0, t.e1,
+                                  0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
+                                  h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count);
         else
-            hipLaunchKernelGGL(k_pairs<double>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, h->P,
-                               h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(),
-                               H, h->clk, h->partials, h->pairs, h->pair_count);
+            hipExtLaunchKernelGGL(k_pairs<double>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0,
+                                  t.e1, 0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
+                                  h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count);
     }
     if (!finish) return DSS_OK;
     TimedLaunch t(h, 4);
 #define DSS_FINISH(R)                                                                                           \
     case R:                                                                                                     \
-        hipLaunchKernelGGL(k_finish<R>, dim3(h->nbox), dim3(1024), 0, h->stream, h->d_boxes, h->partials,       \
-                           h->P.pstride, h->clk, h->run, sample);                                               \
+        hipExtLaunchKernelGGL(k_finish<R>, dim3(h->nbox), dim3(1024), 0, h->stream, t.e0, t.e1, 0, h->d_boxes,  \
+                              h->partials, h->P.pstride, h->clk, h->run, sample);                       \
         break;
     switch (h->finish_r) {
         DSS_FINISH(1) DSS_FINISH(2) DSS_FINISH(3) DSS_FINISH(4)
@@ -446,8 +452,8 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
     if (mode == EVAL_INPLACE) {
         if (h->vel_is_half) {
             TimedLaunch t(h, 0);
-            hipLaunchKernelGGL(k_complete, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c],
-                               h->omg[c], h->fb());
+            hipExtLaunchKernelGGL(k_complete, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P, h->pa[c],
+                                  h->vel[c], h->omg[c], h->fb());
         }
         HIPTRY(hipMemsetAsync(h->ft_x, 0, 6 * h->N * sizeof(double), h->stream));
         dss_status s = launch_pairs(h, c, nullptr, 0, true);
@@ -458,21 +464,22 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
     }
     {
         TimedLaunch t(h, 0);
-        hipLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->d_boxes, h->pa[c], h->vel[c],
-                           h->omg[c], h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk, h->cell, h->rank, h->count);
+        hipExtLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P, h->d_boxes,
+                              h->pa[c], h->vel[c], h->omg[c], h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk,
+                              h->cell, h->rank, h->count);
     }
     if (h->scan_tiles > 0) {
         TimedLaunch t(h, 1);
-        hipLaunchKernelGGL(k_scan<4>, dim3(h->scan_tiles), dim3(1024), 0, h->stream, h->count, h->cell_start, h->clk,
-                           advance, h->tile_sum);
-        hipLaunchKernelGGL(k_scan_add, dim3(h->scan_tiles), dim3(1024), 0, h->stream, h->cell_start, h->tile_sum,
-                           4 * 1024, h->clk, advance);
+        hipExtLaunchKernelGGL(k_scan<4>, dim3(h->scan_tiles), dim3(1024), 0, h->stream, t.e0, (hipEvent_t) nullptr,
+                              0, h->count, h->cell_start, h->clk, advance, h->tile_sum);
+        hipExtLaunchKernelGGL(k_scan_add, dim3(h->scan_tiles), dim3(1024), 0, h->stream, (hipEvent_t) nullptr, t.e1,
+                              0, h->cell_start, h->tile_sum, 4 * 1024, h->clk, advance);
     } else {
         TimedLaunch t(h, 1);
 #define DSS_SCAN(C4)                                                                                            \
     case C4:                                                                                                    \
-        hipLaunchKernelGGL(k_scan<C4>, dim3(1), dim3(1024), 0, h->stream, h->count, h->cell_start, h->clk, advance, \
-                           (int *)nullptr);                                                                     \
+        hipExtLaunchKernelGGL(k_scan<C4>, dim3(1), dim3(1024), 0, h->stream, t.e0, t.e1, 0, h->count,            \
+                              h->cell_start, h->clk, advance, (int *)nullptr);                          \
         break;
         switch (h->scan_c4) {
             DSS_SCAN(1) DSS_SCAN(2) DSS_SCAN(3) DSS_SCAN(4) DSS_SCAN(5) DSS_SCAN(6) DSS_SCAN(7) DSS_SCAN(8)
@@ -484,8 +491,9 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
     }
     {
         TimedLaunch t(h, 2);
-        hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, h->stream, N, h->cell, h->rank, h->cell_start,
-                           h->pa[c], h->vel[c], h->omg[c], h->pa[o], h->vel[o], h->omg[o], h->ft_x, h->prev);
+        hipExtLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, N, h->cell, h->rank,
+                              h->cell_start, h->pa[c], h->vel[c], h->omg[c], h->pa[o], h->vel[o], h->omg[o], h->ft_x,
+                              h->prev);
     }
     dss_status s = launch_pairs(h, o, h->prev, advance, finish);
     if (s) return s;
@@ -1425,12 +1433,18 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
             VjpTape tp{T1.pairs, T1.x, T1.u, T1.w, rad, T0.ckey, T0.ccnt, T0.cxi, T1.ckey, T1.ccnt};
             const bool sampled = n >= first && (n - first) % stress_every == 0;
             const int pgrid = (int)std::max<int64_t>(1, (T1.npairs + kBlock - 1) / kBlock);
-            hipLaunchKernelGGL(k_pairs_vjp, dim3(pgrid), dim3(kBlock), 0, h->stream, Prec, G, (long long)n,
-                               (int)T1.npairs, tp, xib_in, xib_out, Fb, Tb, sampled ? Sb : (const double *)nullptr,
-                               ax, au, aw, theta);
+            {
+                TimedLaunch tl(h, 5);
+                hipExtLaunchKernelGGL(k_pairs_vjp, dim3(pgrid), dim3(kBlock), 0, h->stream, tl.e0, tl.e1, 0, Prec, G,
+                                      (long long)n, (int)T1.npairs, tp, xib_in, xib_out, Fb, Tb,
+                                      sampled ? Sb : (const double *)nullptr, ax, au, aw, theta);
+            }
             const double c = (n - 1 == n0) ? 0.5 : 1.0;
-            hipLaunchKernelGGL(k_integrate_vjp, dim3(grid), dim3(kBlock), 0, h->stream, Prec, G.gd, N, c, 0, rad, Fb,
-                               Tb, ax, au, aw, xb, ub, wb, Fb2, Tb2);
+            {
+                TimedLaunch ti(h, 6);
+                hipExtLaunchKernelGGL(k_integrate_vjp, dim3(grid), dim3(kBlock), 0, h->stream, ti.e0, ti.e1, 0, Prec,
+                                      G.gd, N, c, 0, rad, Fb, Tb, ax, au, aw, xb, ub, wb, Fb2, Tb2);
+            }
             std::swap(Fb, Fb2);
             std::swap(Tb, Tb2);
             std::swap(xib_in, xib_out);
