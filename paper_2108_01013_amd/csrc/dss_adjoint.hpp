@@ -17,14 +17,14 @@
 
 namespace dss {
 
-// Position of contact (a < b) in canonical rows, or -1.
+// Position of contact (a < b) in canonical rows, or -1 (keys carry the cap flag in bit 30).
 __device__ __forceinline__ long long canon_find(const int *__restrict__ key, const int *__restrict__ cnt, int M, int a,
                                                 int b)
 {
     const int n = cnt[a];
     const int *kr = key + (long long)a * M;
     for (int k = 0; k < n; ++k) {
-        const int kk = kr[k];
+        const int kk = kr[k] & kKeyMask;
         if (kk == b) return (long long)a * M + k;
         if (kk > b) break;
     }
@@ -45,11 +45,12 @@ __global__ void __launch_bounds__(kBlock) k_canon_fill(int N, int M, const int *
     const int id = own[p];
     const int n = cnt[p];
     for (int k = 0; k < n; ++k) {
-        const int partner = key[(long long)p * M + k];
+        const int kw = key[(long long)p * M + k];
+        const int partner = kw & kKeyMask;
         const int a = id < partner ? id : partner, b = id < partner ? partner : id;
         const int s = atomicAdd(&ccnt[a], 1);
         if (s < M) {
-            ckey[(long long)a * M + s] = b;
+            ckey[(long long)a * M + s] = b | (kw & kCapBit);
             const double *x = xi + ((long long)p * M + k) * 3;
             double *y = cxi + ((long long)a * M + s) * 3;
             y[0] = x[0];
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(kBlock) k_canon_sort(int N, int M, int *__rest
         const int k = kr[i];
         const double x0 = xr[3 * i], x1 = xr[3 * i + 1], x2 = xr[3 * i + 2];
         int j = i - 1;
-        while (j >= 0 && kr[j] > k) {
+        while (j >= 0 && (kr[j] & kKeyMask) > (k & kKeyMask)) {
             kr[j + 1] = kr[j];
             xr[3 * (j + 1)] = xr[3 * j];
             xr[3 * (j + 1) + 1] = xr[3 * j + 1];
@@ -101,7 +102,7 @@ __global__ void __launch_bounds__(kBlock) k_canon_rekey(int N, int M, const int 
     const int n = cntB[a];
     for (int k = 0; k < n; ++k) {
         const long long q = (long long)a * M + k;
-        const long long s = canon_find(keyA, cntA, M, a, keyB[q]);
+        const long long s = canon_find(keyA, cntA, M, a, keyB[q] & kKeyMask);
         gB[3 * q] = s >= 0 ? gA[3 * s] : 0.0;
         gB[3 * q + 1] = s >= 0 ? gA[3 * s + 1] : 0.0;
         gB[3 * q + 2] = s >= 0 ? gA[3 * s + 2] : 0.0;
@@ -167,9 +168,15 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
             bar.Tj[c] = Tb[3LL * b + c];
             bar.xi[c] = 0.0;
         }
-        if (tp.key_new && xib_new) {
+        // branch of the forward run: a pair is a contact after the step iff its rows hold it,
+        // and the rows record whether its Coulomb cap was active (at the initial evaluation,
+        // which commits no rows, the branch is recomputed)
+        int f_contact = -1, f_capped = -1;
+        if (tp.key_new) {
             const long long pn = canon_find(tp.key_new, tp.cnt_new, P.M, a, b);
-            if (pn >= 0)
+            f_contact = pn >= 0 ? 1 : 0;
+            f_capped = pn >= 0 ? ((tp.key_new[pn] & kCapBit) ? 1 : 0) : 0;
+            if (pn >= 0 && xib_new)
                 for (int c = 0; c < 3; ++c) bar.xi[c] = xib_new[3 * pn + c];
         }
         for (int c = 0; c < 9; ++c) bar.S[c] = Sb ? Sb[c] : 0.0;
@@ -178,7 +185,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
         C.lamd = P.lamd; C.ham = P.ham; C.eps_vdw = P.eps_vdw; C.eps_lub = P.eps_lub; C.dt = P.dt;
         PairGrad g = {};
         pair_vjp(C, G.gd, r, tp.rad[a], tp.rad[b], xa[1], xb[1], tp.u + 3LL * a, tp.u + 3LL * b, tp.w + 3LL * a,
-                 tp.w + 3LL * b, xo, bar, g, nullptr);
+                 tp.w + 3LL * b, xo, bar, g, nullptr, f_contact, f_capped);
         atomic_add3(ax + 3LL * a, -g.r[0], -g.r[1] + g.yi, -g.r[2]);
         atomic_add3(ax + 3LL * b, g.r[0], g.r[1] + g.yj, g.r[2]);
         atomic_add3(au + 3LL * a, g.ui[0], g.ui[1], g.ui[2]);

@@ -355,7 +355,7 @@ dss_status setup_lattice(dss_handle *h)
             qcap = std::max(64, qcap * 3 / 4 / 64 * 64);
         }
         own_cap = std::min(own_cap, 4096);
-        stage_cap = std::min(stage_cap, 65535 / 64 * 64);
+        stage_cap = std::min(stage_cap, 16384 - 64);  // staged indices are 14-bit
         if (!h->tune.tiled) {
             own_cap = 32;
             stage_cap = 64;
@@ -1130,10 +1130,12 @@ dss_status dss_get_box_info(dss_handle *h, int32_t box, dss_box_info *info)
 // ======================================================================================
 namespace {
 
-// Device copy of everything a time step reads from the previous one.
+// Device copy of everything a time step, or an evaluation in place, reads from the
+// previous one (including cell_start, which must match the sorted order of the records).
 struct Snapshot {
     double4 *pa = nullptr, *vel = nullptr, *omg = nullptr;
     double *ft = nullptr;   // own 6N, nb 24N, x 6N
+    int *cs = nullptr;      // cell_start, n_cells + 1
     int *hkey = nullptr, *hcnt = nullptr, *hown = nullptr;
     double *hxi = nullptr;
     DevClock *clk = nullptr;
@@ -1143,7 +1145,7 @@ struct Snapshot {
     bool vel_is_half = false;
     void release()
     {
-        void *ps[] = {pa, vel, omg, ft, hkey, hcnt, hown, hxi, clk, sig};
+        void *ps[] = {pa, vel, omg, ft, cs, hkey, hcnt, hown, hxi, clk, sig};
         for (void *q : ps)
             if (q) (void)hipFree(q);
         *this = Snapshot{};
@@ -1158,6 +1160,7 @@ dss_status snap_save(dss_handle *h, Snapshot &s)
         HIPTRY(dalloc(&s.vel, N));
         HIPTRY(dalloc(&s.omg, N));
         HIPTRY(dalloc(&s.ft, 36 * N));
+        HIPTRY(dalloc(&s.cs, (size_t)h->ncell_total + 1));
         HIPTRY(dalloc(&s.hkey, N * M));
         HIPTRY(dalloc(&s.hxi, 3 * N * M));
         HIPTRY(dalloc(&s.hcnt, N));
@@ -1173,6 +1176,7 @@ dss_status snap_save(dss_handle *h, Snapshot &s)
     HIPTRY(hipMemcpyAsync(s.ft, h->ft_own, 6 * N * sizeof(double), D, st));
     HIPTRY(hipMemcpyAsync(s.ft + 6 * N, h->ft_nb, 24 * N * sizeof(double), D, st));
     HIPTRY(hipMemcpyAsync(s.ft + 30 * N, h->ft_x, 6 * N * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(s.cs, h->cell_start, ((size_t)h->ncell_total + 1) * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(s.hkey, h->hkey[h->hh], N * M * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(s.hxi, h->hxi[h->hh], 3 * N * M * sizeof(double), D, st));
     HIPTRY(hipMemcpyAsync(s.hcnt, h->hcnt[h->hh], N * sizeof(int), D, st));
@@ -1198,6 +1202,7 @@ dss_status snap_restore(dss_handle *h, const Snapshot &s)
     HIPTRY(hipMemcpyAsync(h->ft_own, s.ft, 6 * N * sizeof(double), D, st));
     HIPTRY(hipMemcpyAsync(h->ft_nb, s.ft + 6 * N, 24 * N * sizeof(double), D, st));
     HIPTRY(hipMemcpyAsync(h->ft_x, s.ft + 30 * N, 6 * N * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(h->cell_start, s.cs, ((size_t)h->ncell_total + 1) * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(h->hkey[s.hh], s.hkey, N * M * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(h->hxi[s.hh], s.hxi, 3 * N * M * sizeof(double), D, st));
     HIPTRY(hipMemcpyAsync(h->hcnt[s.hh], s.hcnt, N * sizeof(int), D, st));

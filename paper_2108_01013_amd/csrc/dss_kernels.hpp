@@ -27,6 +27,11 @@ constexpr unsigned kErrRowOverflow = 1u;
 constexpr unsigned kErrNonFinite = 2u;
 constexpr unsigned kErrPairBuffer = 4u;
 
+// A history entry's key is the partner id (below 2^30) with bit 30 set when the contact's
+// Coulomb cap was active at the step that wrote it (read by the adjoint).
+constexpr int kKeyMask = 0x3fffffff;
+constexpr int kCapBit = 0x40000000;
+
 // Physical constants and capacities shared by all boxes of a handle.
 struct DevParams {
     double eta0, rho, kn, kt, gn, mu, fer, lamd, a0, ham, eps_vdw, eps_lub, cf, dt;
@@ -131,6 +136,23 @@ __device__ __forceinline__ bool listed(const DevParams &P, double dx, double dy,
 #pragma clang fp contract(off)
     r2 = (dx * dx + dy * dy) + dz * dz;
     double rc = P.cf * (aa + ab);
+    return r2 < rc * rc;
+}
+
+// Listed test of a candidate whose periodic image is known: r = x_j - x_i plus the image
+// shifts (y face sy with its x offset sxd, x period sx, z period sz), added in the order of
+// the general formula, so that r2 is bit-identical to min_image + listed.
+__device__ __forceinline__ bool image_listed(const double4 &Xi, const double4 &Xj, double sy, double sxd, double sx,
+                                             double sz, double cf)
+{
+#pragma clang fp contract(off)
+    double dx = Xj.x - Xi.x, dy = Xj.y - Xi.y, dz = Xj.z - Xi.z;
+    dy = dy + sy;
+    dx = dx + sxd;
+    dx = dx + sx;
+    dz = dz + sz;
+    const double r2 = (dx * dx + dy * dy) + dz * dz;
+    const double rc = cf * (Xi.w + Xj.w);
     return r2 < rc * rc;
 }
 
@@ -469,6 +491,7 @@ struct PairOut {
     double Tj[3];   // torque on j
     double xi[3];   // new tangential stretch, oriented i -> j
     bool contact;
+    bool capped;    // the Coulomb cap rescaled the stretch
 };
 
 // Arithmetic of the pair physics in type Real: double (FP64 mode) or float (mixed mode).
@@ -567,6 +590,7 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
     // ---------------- contact eqs. contact0, csi
     Real FCx = 0, FCy = 0, FCz = 0;
     o.contact = h_d < 0.0;
+    o.capped = false;
     o.xi[0] = o.xi[1] = o.xi[2] = 0.0;
     if (o.contact) {
         // true relative velocity of the image pair: ambient difference gd r_y along x
@@ -593,6 +617,7 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
             const Real cap = (Real)P.mu * fabs(fn) * (Real)(1.0 / P.kt);
             const Real xm = sqrt_r(xx * xx + xy * xy + xz * xz);
             if (xm >= cap && xm > (Real)0.0) {
+                o.capped = true;
                 const Real sc = cap * rcp_r(xm);
                 xx *= sc;
                 xy *= sc;
@@ -651,7 +676,7 @@ __device__ __forceinline__ bool row_find(const int *__restrict__ hkey, const dou
     const int n = hcnt[p];
     const int *kr = hkey + (long long)p * M;
     for (int k = 0; k < n; ++k) {
-        int kk = kr[k];
+        const int kk = kr[k] & kKeyMask;
         if (kk == key) {
             const double *x = hxi + ((long long)p * M + k) * 3;
             out[0] = x[0];
@@ -753,7 +778,7 @@ __device__ __forceinline__ void store_history(const HistView &H, int M, int gi, 
 {
     if (slot < M) {
         const double sg = idi < idj ? 1.0 : -1.0;
-        H.key_new[(long long)gi * M + slot] = idj;
+        H.key_new[(long long)gi * M + slot] = idj | (o.capped ? kCapBit : 0);
         double *x = H.xi_new + ((long long)gi * M + slot) * 3;
         x[0] = sg * o.xi[0];
         x[1] = sg * o.xi[1];
@@ -782,7 +807,7 @@ __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int
         for (int round = 0; round < 8; ++round) {
 #pragma unroll
             for (int a = round & 1; a + 1 < 8; a += 2) {
-                if (key[a] > key[a + 1]) {
+                if ((key[a] & kKeyMask) > (key[a + 1] & kKeyMask)) {
                     int tk = key[a]; key[a] = key[a + 1]; key[a + 1] = tk;
                     int ti = idx[a]; idx[a] = idx[a + 1]; idx[a + 1] = ti;
                 }
@@ -810,7 +835,7 @@ __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int
             int key = krow[a];
             double x0 = xrow[3 * a], x1 = xrow[3 * a + 1], x2 = xrow[3 * a + 2];
             int b = a - 1;
-            while (b >= 0 && krow[b] > key) {
+            while (b >= 0 && (krow[b] & kKeyMask) > (key & kKeyMask)) {
                 krow[b + 1] = krow[b];
                 xrow[3 * (b + 1)] = xrow[3 * b];
                 xrow[3 * (b + 1) + 1] = xrow[3 * b + 1];
@@ -1124,7 +1149,6 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const BoxParam
         const int r = (k >= T.ro[1]) + (k >= T.ro[2]) + (k >= T.ro[3]) + (k >= T.ro[4]);
         V.sp[k] = pa[T.rs[r] + (k - T.ro[r])];
     }
-    for (int k = t; k < 6 * total; k += kBlock) V.acc[k] = 0.0;
     for (int k = t; k < n_own; k += kBlock) V.rowcnt[k] = 0;
     __syncthreads();
 
@@ -1195,71 +1219,84 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const BoxParam
     }
     __syncthreads();
 
-    // A2: every lane tests an equal, contiguous share of all candidates of the tile.  The
-    // image of a candidate is known from its range, so the nearest-image vector is the
-    // difference plus the range's shifts, added in the order and with the values of the
-    // general formula (same IEEE result for every listed pair, no data-dependent branch).
-    {
-        const int C = V.tpre[ntask];
-        const int chunk = (C + kBlock - 1) / kBlock;
-        const int k0 = t * chunk;
-        const int k1 = min(k0 + chunk, C);
-        if (k0 < k1) {
-            int lo = 0, hi = ntask;  // last task whose prefix is <= k0
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (V.tpre[mid] <= k0) lo = mid; else hi = mid;
+    // A1b: the flat candidate list.  Candidate word: staged partner index jl (bits 0-13),
+    // il (bits 14-25), and the image of its range (bits 26-31: y-face crossing + 1, x period
+    // w + 4, z wrap).  The list lives in the LDS of the force accumulators, which are
+    // cleared after A2.
+    unsigned *const cand = reinterpret_cast<unsigned *>(V.acc);
+    const int ncand = V.tpre[ntask];
+    if (ncand > 12 * P.stage_cap || ncand > 64 * kBlock) {
+        if (t == 0) T.ovf = 1;
+    } else {
+        for (int task = t; task < ntask; task += kBlock) {
+            const int r = task / n_own;
+            const int il = task - r * n_own;
+            const int b0 = V.tpre[task], n = V.tpre[task + 1] - b0;
+            const uint2 rg = V.trange[task];
+            const int len0 = (int)((rg.x >> 16) & 2047u);
+            const unsigned common = ((unsigned)il << 14) | ((rg.x >> 30) << 26) | ((rg.y >> 30) << 31);
+            // image bits of each part; the staged index (below 2^14) is added to them
+            const unsigned c0 = common | (((rg.x >> 27) & 7u) << 28);
+            const unsigned c1 = common | (((rg.y >> 27) & 7u) << 28);
+            const int j0 = (int)(rg.x & 0xffffu), j1 = (int)(rg.y & 0xffffu) - len0;
+            for (int o = 0; o < n; ++o) cand[b0 + o] = o < len0 ? c0 + (unsigned)(j0 + o) : c1 + (unsigned)(j1 + o);
+        }
+    }
+    __syncthreads();
+
+    // A2: the candidates in lane-strided order (lane t tests k = t + 256 j, two per pass),
+    // every lane running the same straight-line test: the nearest-image vector is the
+    // difference plus the shifts of the candidate's range (y face with its x offset, x period,
+    // z period), added in the order and with the values of the general formula (same IEEE
+    // result for every listed pair).  Hits are kept as a bit mask per lane; a block scan of
+    // the hit counts gives every lane its slots in the pair queue (no atomics).
+    if (!T.ovf) {
+        const int lane = t & 63, wid = t >> 6;
+        auto test = [&](unsigned wd) -> bool {
+            const int jl = (int)(wd & 0x3fffu);
+            const int il = (int)((wd >> 14) & 0xfffu);
+            const int cross = (int)((wd >> 26) & 3u) - 1;
+            const double sy = cross > 0 ? G.L[1] : (cross < 0 ? -G.L[1] : 0.0);
+            const double sxd = cross > 0 ? delta : (cross < 0 ? -delta : 0.0);
+            const double sx = (double)((int)((wd >> 28) & 7u) - 4) * G.L[0];
+            const double sz = (wd >> 31) ? G.L[2] : 0.0;
+            return image_listed(V.sp[il], V.sp[jl], sy, sxd, sx, sz, P.cf);
+        };
+        unsigned long long bits = 0ull;
+        int j = 0;
+        for (int k = t; k < ncand; k += 2 * kBlock, j += 2) {
+            const int k2 = k + kBlock;
+            const unsigned w0 = cand[k];
+            const unsigned w1 = k2 < ncand ? cand[k2] : w0;
+            const bool h0 = test(w0);
+            const bool h1 = test(w1) && k2 < ncand;
+            bits |= (h0 ? 1ull : 0ull) << j;
+            bits |= (h1 ? 1ull : 0ull) << (j + 1);
+        }
+        const int c = __popcll(bits);
+        int incl = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) T.wsum[wid] = incl;
+        __syncthreads();
+        int q = incl - c;
+        int nhit = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            q += w < wid ? T.wsum[w] : 0;
+            nhit += T.wsum[w];
+        }
+        if (nhit > P.qcap) {
+            if (t == 0) T.ovf = 1;
+        } else {
+            while (bits) {
+                const int jj = __ffsll((long long)bits) - 1;
+                bits &= bits - 1ull;
+                const unsigned wd = cand[t + jj * kBlock];
+                V.queue[q++] = (((wd >> 14) & 0xfffu) << 16) | (wd & 0x3fffu);
             }
-            int task = lo;
-            int il = 0, tb = 0, te = 0, len0 = 0, j0 = 0, j1 = 0;
-            double4 Xi;
-            double sy = 0.0, sxd = 0.0, sz = 0.0, sx0 = 0.0, sx1 = 0.0;
-            bool fresh = true;
-            for (int k = k0; k < k1; ++k) {
-                if (fresh || k >= te) {
-                    if (!fresh) {
-                        do {
-                            ++task;
-                        } while (k >= V.tpre[task + 1]);
-                    }
-                    fresh = false;
-                    tb = V.tpre[task];
-                    te = V.tpre[task + 1];
-                    il = task % n_own;
-                    Xi = V.sp[il];
-                    const uint2 rg = V.trange[task];
-                    len0 = (int)((rg.x >> 16) & 2047u);
-                    j0 = (int)(rg.x & 0xffffu);
-                    j1 = (int)(rg.y & 0xffffu);
-                    const int cross = (int)(rg.x >> 30) - 1;
-                    sy = cross > 0 ? G.L[1] : (cross < 0 ? -G.L[1] : 0.0);
-                    sxd = cross > 0 ? delta : (cross < 0 ? -delta : 0.0);
-                    sx0 = (double)((int)((rg.x >> 27) & 7u) - 4) * G.L[0];
-                    sx1 = (double)((int)((rg.y >> 27) & 7u) - 4) * G.L[0];
-                    sz = (rg.y >> 30) ? G.L[2] : 0.0;
-                }
-                const int o = k - tb;
-                const bool second = o >= len0;
-                const int jl = second ? j1 + (o - len0) : j0 + o;
-                const double4 Xj = V.sp[jl];
-                double dx, dy, dz, r2;
-                {
-#pragma clang fp contract(off)
-                    dx = Xj.x - Xi.x;
-                    dy = Xj.y - Xi.y;
-                    dz = Xj.z - Xi.z;
-                    dy = dy + sy;
-                    dx = dx + sxd;
-                    dx = dx + (second ? sx1 : sx0);
-                    dz = dz + sz;
-                }
-                if (!listed(P, dx, dy, dz, Xi.w, Xj.w, r2)) continue;
-                const int q = atomicAdd(&T.qn, 1);
-                if (q < P.qcap)
-                    V.queue[q] = ((unsigned)il << 16) | (unsigned)jl;
-                else
-                    T.ovf = 1;
-            }
+            if (t == 0) T.qn = nhit;
         }
     }
     __syncthreads();
@@ -1269,6 +1306,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const BoxParam
         row_fallback();
         return;
     }
+
+    for (int k = t; k < 6 * total; k += kBlock) V.acc[k] = 0.0;
+    __syncthreads();
 
     // B: evaluate the queued pairs
     const int nq = T.qn;
@@ -1441,7 +1481,7 @@ __global__ void __launch_bounds__(kBlock) k_history_export(int N, int M, const i
     int id = own[p];
     int n = cnt[p];
     for (int k = 0; k < n; ++k) {
-        int partner = key[(long long)p * M + k];
+        const int partner = key[(long long)p * M + k] & kKeyMask;
         unsigned long long s = atomicAdd(n_out, 1ull);
         if ((long long)s < cap) {
             out_pairs[2 * s] = id < partner ? id : partner;

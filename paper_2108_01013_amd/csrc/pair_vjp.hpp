@@ -59,10 +59,12 @@ DSS_HD inline void vaxpy(double s, const double a[3], double out[3])
     out[2] += s * a[2];
 }
 
-// g must be zero on entry; val may be null.
+// g must be zero on entry; val may be null.  force_contact / force_capped: the branch to
+// differentiate (0 or 1, as decided by the forward run), or -1 to decide it here.
 DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], double ai, double aj, double yi,
                             double yj, const double ui[3], const double uj[3], const double Wi[3], const double Wj[3],
-                            const double xo[3], const PairBar &bar, PairGrad &g, PairVal *val)
+                            const double xo[3], const PairBar &bar, PairGrad &g, PairVal *val,
+                            int force_contact = -1, int force_capped = -1)
 {
     // ------------------------------------------------------------------ primal
     const double dist = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
@@ -114,7 +116,7 @@ DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], do
     const double ev = C.eps_vdw * abar;
     const double Q = (h >= 0.0 ? h * h : 0.0) + ev * ev;
     if (C.ham != 0.0) fe += C.ham * abar / (12.0 * Q);
-    const bool contact = h < 0.0;
+    const bool contact = force_contact >= 0 ? force_contact != 0 : h < 0.0;
     double FC[3] = {0.0, 0.0, 0.0}, Ft[3] = {0.0, 0.0, 0.0}, xpp[3] = {0.0, 0.0, 0.0};
     double D[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0}, sv[3] = {0.0, 0.0, 0.0}, xs[3] = {0.0, 0.0, 0.0};
     double xp[3] = {0.0, 0.0, 0.0};
@@ -137,7 +139,7 @@ DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], do
         if (C.kt > 0.0) {
             cap = C.mu * fabs(fn) / C.kt;
             xm = sqrt(vdot(xp, xp));
-            capped = xm >= cap && xm > 0.0;
+            capped = (force_capped >= 0 ? force_capped != 0 : xm >= cap) && xm > 0.0;
             sc = capped ? cap / xm : 1.0;
             for (int k = 0; k < 3; ++k) {
                 xpp[k] = xp[k] * sc;
