@@ -340,7 +340,10 @@ dss_status setup_lattice(dss_handle *h)
     h->max_mean_row = max_mean_row;
     // row-tile capacities of k_pairs from the mean occupancy of a cell row (own row and the
     // five rows of the half shell) of the densest box, times tile_scale; rows beyond them
-    // take the per-particle path, which every row takes when tiling is off
+    // take the per-particle path, which every row takes when tiling is off.  When the
+    // capacities can shrink to fit three workgroups per CU (160 KB of LDS) and still keep a
+    // margin of two standard deviations over the mean row occupancy, they do: latency
+    // hiding of the three-workgroup occupancy outweighs the few rows that fall back.
     DevParams &P = h->P;
     {
         const double mean_row = max_mean_row * h->tune.tile_scale;
@@ -348,6 +351,17 @@ dss_status setup_lattice(dss_handle *h)
         int own_cap = up(1.5 * mean_row + 16.0, 32);
         int stage_cap = up(6.25 * mean_row + 32.0, 64);
         int qcap = up(8.0 * mean_row + 64.0, 64);
+        const size_t lds_three = 160 * 1024 / 3 - 1024;
+        if (tile_lds_bytes(own_cap, stage_cap, qcap) > lds_three) {
+            const int own3 = up(1.3 * mean_row + 8.0, 32);
+            const int stage3 = up(5.0 * mean_row + 2.0 * std::sqrt(5.0 * mean_row), 32);
+            const int q3 = up(4.5 * mean_row + 64.0, 64);
+            if (tile_lds_bytes(own3, stage3, q3) <= lds_three) {
+                own_cap = own3;
+                stage_cap = stage3;
+                qcap = q3;
+            }
+        }
         const size_t lds_max = 150 * 1024;
         while (tile_lds_bytes(own_cap, stage_cap, qcap) > lds_max && own_cap > 32) {
             own_cap = std::max(32, own_cap * 3 / 4 / 32 * 32);

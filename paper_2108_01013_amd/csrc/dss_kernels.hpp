@@ -1072,7 +1072,7 @@ __device__ __forceinline__ void tile_pair(const DevParams &P, const BoxParams &G
 }
 
 template <typename Real>
-__global__ void __launch_bounds__(kBlock, 2) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
+__global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
                                                       const int *__restrict__ row_box, const int *__restrict__ cell_start,
                                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                                       const double4 *__restrict__ omg, ForceBufs B, HistView H,
