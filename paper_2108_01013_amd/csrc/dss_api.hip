@@ -36,6 +36,8 @@ struct dss_handle {
     int *d_row_box = nullptr;         // cell row -> box
     double *box_diag = nullptr;       // nbox x 3: listed pairs, contacts, largest history row
     int *tile_sum = nullptr;          // totals of the multi-workgroup scan
+    int *fb_rows = nullptr, *fb_count = nullptr;  // rows deferred to the per-particle path
+    int deferred_hint = -1;           // deferred rows at the last synchronised evaluation
     int ncell_total = 0, nrow_total = 0;
     int scan_tiles = 0;               // 0: one-workgroup scan (scan_c4), else workgroups of 16384 cells
     std::vector<double> box_amax;     // largest radius per box
@@ -89,7 +91,7 @@ struct dss_handle {
     DevRun run_host{};
 
     // kernel timing with events on the stream
-    static constexpr int kKernels = 7;
+    static constexpr int kKernels = 8;
     unsigned timing = 0;       // bit k: time kernel k
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<int, int>>> ev_marks;  // (kernel, (start event, stop event))
@@ -136,7 +138,8 @@ void free_lattice(dss_handle *h)
     };
     destroy_graphs(h);
     F(h->count); F(h->cell_start); F(h->tile_sum); F(h->partials); F(h->d_boxes); F(h->d_row_box);
-    h->count = h->cell_start = h->tile_sum = h->d_row_box = nullptr;
+    F(h->fb_rows); F(h->fb_count);
+    h->count = h->cell_start = h->tile_sum = h->d_row_box = h->fb_rows = h->fb_count = nullptr;
     h->partials = nullptr;
     h->d_boxes = nullptr;
 }
@@ -193,6 +196,7 @@ dss_status check_flags(dss_handle *h)
     DevClock c;
     HIPTRY(hipMemcpyAsync(&c, h->clk, sizeof(c), hipMemcpyDeviceToHost, h->stream));
     HIPTRY(hipStreamSynchronize(h->stream));
+    h->deferred_hint = c.deferred;
     if (c.err & kErrNonFinite) return fail(h, DSS_ERR_UNSTABLE, "non-finite force or torque");
     if (c.err & kErrRowOverflow) {
         std::vector<double> d;
@@ -337,6 +341,7 @@ dss_status setup_lattice(dss_handle *h)
     }
     h->ncell_total = (int)ncell;
     h->nrow_total = nrow;
+    h->deferred_hint = -1;
     h->max_mean_row = max_mean_row;
     // row-tile capacities of k_pairs from the mean occupancy of a cell row (own row and the
     // five rows of the half shell) of the densest box, times tile_scale; rows beyond them
@@ -393,6 +398,9 @@ dss_status setup_lattice(dss_handle *h)
     HIPTRY(dalloc(&h->partials, 12 * (size_t)P.pstride));
     HIPTRY(dalloc(&h->d_boxes, B));
     HIPTRY(dalloc(&h->d_row_box, nrow));
+    HIPTRY(dalloc(&h->fb_rows, nrow));
+    HIPTRY(dalloc(&h->fb_count, 1));
+    HIPTRY(hipMemsetAsync(h->fb_count, 0, sizeof(int), h->stream));
     HIPTRY(hipMemcpyAsync(h->d_boxes, h->boxes.data(), B * sizeof(BoxParams), hipMemcpyHostToDevice, h->stream));
     HIPTRY(hipMemcpyAsync(h->d_row_box, row_box.data(), nrow * sizeof(int), hipMemcpyHostToDevice, h->stream));
     HIPTRY(hipMemsetAsync(h->partials, 0, 12 * (size_t)P.pstride * sizeof(double), h->stream));
@@ -423,11 +431,31 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, boo
         if (h->prm.precision == DSS_MIXED)
             hipExtLaunchKernelGGL(k_pairs<float>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0, t.e1,
                                   0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
-                                  h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count);
+                                  h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, h->fb_rows,
+                                  h->fb_count);
         else
             hipExtLaunchKernelGGL(k_pairs<double>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0,
                                   t.e1, 0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
-                                  h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count);
+                                  h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, h->fb_rows,
+                                  h->fb_count);
+    }
+    {
+        // deferred rows: workgroups striding over the list, as many as the rows deferred at
+        // the last synchronised evaluation (a few when that is unknown or none), one per row
+        // when every row takes the per-particle path
+        TimedLaunch t(h, 7);
+        const int hint = h->deferred_hint < 0 ? 64 : h->deferred_hint + h->deferred_hint / 4 + 8;
+        const int grid = h->tune.tiled ? std::min(h->nrow_total, hint) : h->nrow_total;
+        if (h->prm.precision == DSS_MIXED)
+            hipExtLaunchKernelGGL(k_pairs_rows<float>, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P,
+                                  h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf],
+                                  h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count,
+                                  (const int *)h->fb_rows, (const int *)h->fb_count);
+        else
+            hipExtLaunchKernelGGL(k_pairs_rows<double>, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P,
+                                  h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf],
+                                  h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count,
+                                  (const int *)h->fb_rows, (const int *)h->fb_count);
     }
     if (!finish) return DSS_OK;
     TimedLaunch t(h, 4);
@@ -470,6 +498,7 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
                                   h->vel[c], h->omg[c], h->fb());
         }
         HIPTRY(hipMemsetAsync(h->ft_x, 0, 6 * h->N * sizeof(double), h->stream));
+        HIPTRY(hipMemsetAsync(h->fb_count, 0, sizeof(int), h->stream));
         dss_status s = launch_pairs(h, c, nullptr, 0, true);
         if (s) return s;
         HIPTRY(hipGetLastError());
@@ -480,7 +509,7 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
         TimedLaunch t(h, 0);
         hipExtLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P, h->d_boxes,
                               h->pa[c], h->vel[c], h->omg[c], h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk,
-                              h->cell, h->rank, h->count);
+                              h->cell, h->rank, h->count, h->fb_count);
     }
     if (h->scan_tiles > 0) {
         TimedLaunch t(h, 1);

@@ -66,6 +66,7 @@ struct BoxParams {
 struct DevClock {
     long long step;
     unsigned err;
+    int deferred;   // rows k_pairs left to the per-particle path at the last evaluation
 };
 
 // Run descriptor of a dss_step call: stress sampling schedule.
@@ -347,10 +348,11 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
                                                      double4 *__restrict__ omg, ForceBufs B, int vel_is_half,
                                                      int advance, const DevClock *__restrict__ clk,
                                                      int *__restrict__ cell, int *__restrict__ rank,
-                                                     int *__restrict__ count)
+                                                     int *__restrict__ count, int *__restrict__ fb_count)
 {
 #pragma clang fp contract(off)
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) *fb_count = 0;  // rows deferred by this step's k_pairs
     const bool active = p < P.N;
     int c = -1;
     if (active) {
@@ -965,7 +967,7 @@ __device__ void particle_pairs_global(const DevParams &P, const BoxParams &G, in
 // (12 doubles: 9 stress components, pairs, contacts, largest row; component k of workgroup
 // w at partials[k pstride + w]), summed by k_finish.
 __device__ __forceinline__ void reduce_tally(PairTally &tally, double (*red)[12], double *__restrict__ partials,
-                                             int pstride)
+                                             int pstride, int rec)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -985,7 +987,7 @@ __device__ __forceinline__ void reduce_tally(PairTally &tally, double (*red)[12]
         const int k = threadIdx.x;
         double v = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) v = (k == 11) ? fmax(v, red[w][k]) : v + red[w][k];
-        partials[(long long)k * pstride + blockIdx.x] = v;
+        partials[(long long)k * pstride + rec] = v;
     }
 }
 
@@ -1071,37 +1073,14 @@ __device__ __forceinline__ void tile_pair(const DevParams &P, const BoxParams &G
     }
 }
 
-template <typename Real>
-__global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
-                                                      const int *__restrict__ row_box, const int *__restrict__ cell_start,
-                                                      const double4 *__restrict__ pa, const double4 *__restrict__ vel,
-                                                      const double4 *__restrict__ omg, ForceBufs B, HistView H,
-                                                      DevClock *__restrict__ clk, double *__restrict__ partials,
-                                                      int *__restrict__ pair_out,
-                                                      unsigned long long *__restrict__ pair_count)
+// Slot ranges of the five half-shell rows of cell row `row` of box G (shared), with the
+// y-face crossing of each row; ends with a barrier.
+__device__ __forceinline__ void row_bounds(const BoxParams &G, int row, const int *__restrict__ cell_start,
+                                           TileShared &T)
 {
-    __shared__ TileShared T;
-    extern __shared__ double4 dyn_lds[];
-    TileView V;
-    V.sp = dyn_lds;
-    V.acc = reinterpret_cast<double *>(V.sp + P.stage_cap);
-    V.queue = reinterpret_cast<unsigned *>(V.acc + 6 * P.stage_cap);
-    V.trange = reinterpret_cast<uint2 *>(V.queue + P.qcap);
-    V.tpre = reinterpret_cast<int *>(V.trange + 5 * P.own_cap);
-    V.rowcnt = V.tpre + 5 * P.own_cap + 1;
-
     const int t = threadIdx.x;
-    const BoxParams G = boxes[row_box[blockIdx.x]];
     const int nxc = G.nc[0], nyc = G.nc[1], nzc = G.nc[2];
-    const int row = blockIdx.x - G.row_off;  // cell row within the box
     const int cz = row / nyc, cy = row - (row / nyc) * nyc;
-    const double delta = le_offset(P, G, clk->step);
-    PairTally tally;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
-    tally.npair = tally.ncont = 0;
-    tally.fill = 0;
-
     if (t < 5) {
         int dz, dy;
         shell_row(t, dz, dy);
@@ -1127,21 +1106,49 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
         T.ovf = 0;
     }
     __syncthreads();
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
+                                                      const int *__restrict__ row_box, const int *__restrict__ cell_start,
+                                                      const double4 *__restrict__ pa, const double4 *__restrict__ vel,
+                                                      const double4 *__restrict__ omg, ForceBufs B, HistView H,
+                                                      DevClock *__restrict__ clk, double *__restrict__ partials,
+                                                      int *__restrict__ pair_out,
+                                                      unsigned long long *__restrict__ pair_count,
+                                                      int *__restrict__ fb_rows, int *__restrict__ fb_count)
+{
+    __shared__ TileShared T;
+    extern __shared__ double4 dyn_lds[];
+    TileView V;
+    V.sp = dyn_lds;
+    V.acc = reinterpret_cast<double *>(V.sp + P.stage_cap);
+    V.queue = reinterpret_cast<unsigned *>(V.acc + 6 * P.stage_cap);
+    V.trange = reinterpret_cast<uint2 *>(V.queue + P.qcap);
+    V.tpre = reinterpret_cast<int *>(V.trange + 5 * P.own_cap);
+    V.rowcnt = V.tpre + 5 * P.own_cap + 1;
+
+    const int t = threadIdx.x;
+    const BoxParams G = boxes[row_box[blockIdx.x]];
+    const int nxc = G.nc[0], nzc = G.nc[2];
+    const int row = blockIdx.x - G.row_off;  // cell row within the box
+    const int cz = row / G.nc[1];
+    const double delta = le_offset(P, G, clk->step);
+    PairTally tally;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
+    tally.npair = tally.ncont = 0;
+    tally.fill = 0;
+    row_bounds(G, row, cell_start, T);
     const int n_own = T.re[0] - T.rs[0];
     const int total = T.ro[5];
-    // per-particle path for this row (tile too large, or a tile limit was hit below); the
-    // partner records of the row are zero, partners receive atomic additions instead
-    auto row_fallback = [&]() {
-        for (int i = T.rs[0] + t; i < T.re[0]; i += kBlock)
-            particle_pairs_global<Real>(P, G, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count,
-                                        tally);
-        const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int r = 1; r < 5; ++r)
-            for (int g = T.rs[r] + t; g < T.re[r]; g += kBlock) store_ft(B.nb + 6LL * ((r - 1) * B.n + g), z);
-        reduce_tally(tally, T.red, partials, P.pstride);
+    // a row beyond the tile capacities (or one that hits a tile limit below) is left to
+    // k_pairs_rows, which takes it on the per-particle path; nothing of it is written here
+    auto defer_row = [&]() {
+        if (t == 0) fb_rows[atomicAdd(fb_count, 1)] = blockIdx.x;
     };
     if (!P.tiled || n_own > P.own_cap || total > P.stage_cap) {
-        row_fallback();
+        defer_row();
         return;
     }
     // stage the shell rows
@@ -1301,9 +1308,8 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
     }
     __syncthreads();
     if (T.ovf) {
-        // a tile limit was hit: discard the tile and redo the row on the per-particle path
-        for (int k = t; k < n_own; k += kBlock) V.rowcnt[k] = 0;
-        row_fallback();
+        // a tile limit was hit: discard the tile and defer the row to the per-particle path
+        defer_row();
         return;
     }
 
@@ -1343,7 +1349,51 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
         for (int c = 0; c < 6; ++c) f[c] = V.acc[6 * k + c];
         store_ft(B.nb + 6LL * ((r - 1) * B.n + g), f);
     }
-    reduce_tally(tally, T.red, partials, P.pstride);
+    reduce_tally(tally, T.red, partials, P.pstride, blockIdx.x);
+}
+
+// ----------------------------------------------------------------------------------
+// k_pairs_rows: the cell rows that k_pairs deferred (beyond the tile capacities), on the
+// per-particle path: one lane per own particle walks its half shell with global loads, keeps
+// its own side in registers and adds the partner side to the atomic force record; the
+// partner records of the row's four shell rows are zero; the row's stress partial as in
+// k_pairs.  Workgroups stride over the list of deferred rows.
+// ----------------------------------------------------------------------------------
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) k_pairs_rows(DevParams P, const BoxParams *__restrict__ boxes,
+                                                       const int *__restrict__ row_box,
+                                                       const int *__restrict__ cell_start,
+                                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
+                                                       const double4 *__restrict__ omg, ForceBufs B, HistView H,
+                                                       DevClock *__restrict__ clk, double *__restrict__ partials,
+                                                       int *__restrict__ pair_out,
+                                                       unsigned long long *__restrict__ pair_count,
+                                                       const int *__restrict__ fb_rows,
+                                                       const int *__restrict__ fb_count)
+{
+    __shared__ TileShared T;
+    const int t = threadIdx.x;
+    const int n = *fb_count;
+    if (blockIdx.x == 0 && t == 0) clk->deferred = n;
+    for (int e = blockIdx.x; e < n; e += gridDim.x) {
+        const int grow = fb_rows[e];
+        const BoxParams G = boxes[row_box[grow]];
+        const double delta = le_offset(P, G, clk->step);
+        PairTally tally;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
+        tally.npair = tally.ncont = 0;
+        tally.fill = 0;
+        row_bounds(G, grow - G.row_off, cell_start, T);
+        for (int i = T.rs[0] + t; i < T.re[0]; i += kBlock)
+            particle_pairs_global<Real>(P, G, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count,
+                                        tally);
+        const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int r = 1; r < 5; ++r)
+            for (int g = T.rs[r] + t; g < T.re[r]; g += kBlock) store_ft(B.nb + 6LL * ((r - 1) * B.n + g), z);
+        reduce_tally(tally, T.red, partials, P.pstride, grow);
+        __syncthreads();
+    }
 }
 
 // ----------------------------------------------------------------------------------

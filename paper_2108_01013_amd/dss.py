@@ -285,7 +285,8 @@ class Simulation:
         order = np.lexsort((pr[:, 1], pr[:, 0]))
         return pr[order], xi[order]
 
-    KERNELS = ("k_predict", "k_scan", "k_scatter", "k_pairs", "k_finish", "k_pairs_vjp", "k_integrate_vjp")
+    KERNELS = ("k_predict", "k_scan", "k_scatter", "k_pairs", "k_finish", "k_pairs_vjp", "k_integrate_vjp",
+               "k_pairs_rows")
 
     def set_tuning(self, cell_scale=None, tile_scale=None, tiled=None, graph=None):
         """Change launch tuning (results do not depend on it); unspecified fields keep their value."""
