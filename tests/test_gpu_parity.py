@@ -365,3 +365,45 @@ def test_mixed_precision_parity(which):
     for key in ("F", "T", "Sigma", "eta_r", "xi"):
         assert worst[key] < TOL_MIXED, (key, worst[key])
     sim.close()
+
+
+# ---------------------------------------------------------------------------------------------
+# High size ratio: lognormal radii truncated to [1, 10] (the history capacity is the paper's
+# estimate for the largest particle), on the row tiles and with every row on the per-particle
+# path; FP64 within 1e-10 and mixed within 1e-5 of the oracle.
+# ---------------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def poly_box():
+    rad = synth.lognormal_radii(3000, seed=7)
+    L = synth.box_for_fraction(rad, 0.55)
+    x = synth.relax_positions(rad, L, seed=8)
+    return synth.Workload("lognormal N=3000 phi=0.55", x, rad, L, synth.default_params([L, L, L]))
+
+
+@pytest.mark.parametrize("tiled,precision", [(True, 0), (False, 0), (True, 1)])
+def test_high_size_ratio(poly_box, tiled, precision):
+    w = poly_box
+    p = w.params
+    say(f"case: size ratio {w.rad.max() / w.rad.min():.1f} N=3000 tiled={tiled} precision={precision}")
+    sim = _sim(p, record_pairs=True, precision=precision)
+    sim.set_tuning(tiled=tiled)
+    sim.set_particles(w.x, w.rad)
+    assert sim.info()["capacity"] == oracle.history_capacity(w.rad.max(), w.rad.min())
+    sim.step(3)
+    hp, hx = sim.history()
+    tol = TOL_F if precision == 0 else TOL_MIXED
+    for k in range(2):
+        st, s0 = oracle_state_from_gpu(p, sim, w.rad, hp, hx, 3 + k)
+        x_o = oracle.kick_drift(p, st)[0]
+        sim.step(1)
+        s1 = sim.state()
+        uh, wh = sim.eval_velocities()
+        assert np.array_equal(s1["x"], x_o)
+        assert np.array_equal(sim.pairs(), oracle.pairs_brute(p, s1["x"], w.rad, oracle.le_offset(p, 4 + k)))
+        F, T, S, H, npairs = oracle.forces(p, s1["x"], uh, wh, w.rad, 4 + k, st.history)
+        assert rel_inf(s1["F"], F) < tol and rel_inf(s1["T"], T) < tol
+        last, _, _ = sim.read_stress()
+        assert rel_inf(last, S) < tol
+        hp, hx = sim.history()
+        assert np.array_equal(hp, H.pairs)
+    sim.close()
