@@ -246,8 +246,18 @@ dss_status dss_get_box_info(dss_handle *h, int32_t box, dss_box_info *info);
 dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress_every, int64_t ckpt_every, const double *weight,
                        double *J, double *dJ_dparams, double *dJ_dx, double *dJ_du, double *dJ_dw, int on_device);
 
-/* Bytes needed by dss_save_state (nullable blob: size query) / restore of a snapshot. */
+/* Snapshot of the whole time-stepping state into host memory: particle records (sorted
+ * order), force records of the last evaluation, cell_start, committed contact history,
+ * time index, last stress and counters.  blob = NULL: *bytes receives the size needed.
+ * Otherwise *bytes is the capacity of blob (DSS_ERR_CAPACITY, with *bytes set to the size,
+ * if too small) and receives the size written.  Synchronises the handle's stream. */
 dss_status dss_save_state(dss_handle *h, void *blob, size_t *bytes);
+
+/* Restore a snapshot of dss_save_state into a loaded handle of the same configuration (same
+ * particle count, history capacity, boxes and cell lattice: the same handle, or one created
+ * with the same parameters and loaded with the same particles).  Continuing from it repeats
+ * the run from the snapshot's time index (up to the summation order of force atomics).
+ * DSS_ERR_ARG for a malformed blob, DSS_ERR_STATE for another configuration. */
 dss_status dss_load_state(dss_handle *h, const void *blob, size_t bytes);
 
 /* Kernel timing with HIP events recorded on the handle's stream around the launches of

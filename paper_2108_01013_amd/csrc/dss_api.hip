@@ -1536,20 +1536,109 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     return DSS_OK;
 }
 
+// Snapshot layout: header, then the current records, force records, cell_start, committed
+// history, clock, last stress and counters, each as stored on the device.
+namespace {
+struct StateHeader {
+    char magic[8];
+    int32_t version, nbox;
+    int64_t N, M, ncell, step;
+    int32_t vel_is_half, reserved;
+};
+constexpr int32_t kStateVersion = 1;
+
+struct StatePart {
+    void *dev;
+    size_t bytes;
+};
+
+std::vector<StatePart> state_parts(dss_handle *h, int cur, int hh)
+{
+    const size_t N = (size_t)h->N, M = (size_t)h->P.M, B = (size_t)h->nbox;
+    return {{h->pa[cur], N * sizeof(double4)},
+            {h->vel[cur], N * sizeof(double4)},
+            {h->omg[cur], N * sizeof(double4)},
+            {h->ft_own, 6 * N * sizeof(double)},
+            {h->ft_nb, 24 * N * sizeof(double)},
+            {h->ft_x, 6 * N * sizeof(double)},
+            {h->cell_start, ((size_t)h->ncell_total + 1) * sizeof(int)},
+            {h->hkey[hh], N * M * sizeof(int)},
+            {h->hxi[hh], 3 * N * M * sizeof(double)},
+            {h->hcnt[hh], N * sizeof(int)},
+            {h->hown[hh], N * sizeof(int)},
+            {h->clk, sizeof(DevClock)},
+            {h->sigma_last, 9 * B * sizeof(double)},
+            {h->box_diag, 3 * B * sizeof(double)}};
+}
+}  // namespace
+
 extern "C" {
 
 dss_status dss_save_state(dss_handle *h, void *blob, size_t *bytes)
 {
-    (void)blob;
-    if (bytes) *bytes = 0;
-    return fail(h, DSS_ERR_STATE, "not implemented");
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (!bytes) return fail(h, DSS_ERR_ARG, "null size");
+    auto parts = state_parts(h, h->cur, h->hh);
+    size_t need = sizeof(StateHeader);
+    for (auto &q : parts) need += q.bytes;
+    if (!blob) {
+        *bytes = need;
+        return DSS_OK;
+    }
+    if (*bytes < need) {
+        *bytes = need;
+        return fail(h, DSS_ERR_CAPACITY, "state buffer too small");
+    }
+    StateHeader hd{};
+    std::memcpy(hd.magic, "DSSSTATE", 8);
+    hd.version = kStateVersion;
+    hd.nbox = h->nbox;
+    hd.N = h->N;
+    hd.M = h->P.M;
+    hd.ncell = h->ncell_total;
+    hd.step = h->step;
+    hd.vel_is_half = h->vel_is_half ? 1 : 0;
+    char *out = static_cast<char *>(blob);
+    std::memcpy(out, &hd, sizeof(hd));
+    size_t off = sizeof(hd);
+    HIPTRY(hipStreamSynchronize(h->stream));
+    for (auto &q : parts) {
+        HIPTRY(hipMemcpy(out + off, q.dev, q.bytes, hipMemcpyDeviceToHost));
+        off += q.bytes;
+    }
+    *bytes = need;
+    return DSS_OK;
 }
 
 dss_status dss_load_state(dss_handle *h, const void *blob, size_t bytes)
 {
-    (void)blob;
-    (void)bytes;
-    return fail(h, DSS_ERR_STATE, "not implemented");
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (!blob || bytes < sizeof(StateHeader)) return fail(h, DSS_ERR_ARG, "null or short state");
+    StateHeader hd;
+    std::memcpy(&hd, blob, sizeof(hd));
+    if (std::memcmp(hd.magic, "DSSSTATE", 8) != 0 || hd.version != kStateVersion)
+        return fail(h, DSS_ERR_ARG, "not a state snapshot of this library version");
+    if (hd.N != h->N || hd.M != h->P.M || hd.nbox != h->nbox || hd.ncell != h->ncell_total || h->tune_pending)
+        return fail(h, DSS_ERR_STATE, "snapshot of another configuration (particle count, history capacity, boxes "
+                                      "or cell lattice differ)");
+    auto parts = state_parts(h, 0, 0);
+    size_t need = sizeof(StateHeader);
+    for (auto &q : parts) need += q.bytes;
+    if (bytes != need) return fail(h, DSS_ERR_ARG, "state size does not match");
+    const char *in = static_cast<const char *>(blob);
+    size_t off = sizeof(hd);
+    HIPTRY(hipStreamSynchronize(h->stream));
+    for (auto &q : parts) {
+        HIPTRY(hipMemcpy(q.dev, in + off, q.bytes, hipMemcpyHostToDevice));
+        off += q.bytes;
+    }
+    h->cur = 0;
+    h->hh = 0;
+    h->step = hd.step;
+    h->vel_is_half = hd.vel_is_half != 0;
+    return DSS_OK;
 }
 
 }  // extern "C"

@@ -335,6 +335,19 @@ class Simulation:
                                          ctypes.c_void_p(th.ctypes.data), *[q[0] for q in ptrs], 1))
         return J.value, th[0], th[1]
 
+    def save_state(self) -> bytes:
+        """Snapshot of the whole time-stepping state (host bytes)."""
+        n = ctypes.c_size_t(0)
+        self._check(self.lib.dss_save_state(self.h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self.lib.dss_save_state(self.h, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def load_state(self, blob: bytes):
+        """Restore a snapshot taken with save_state on a handle of the same configuration."""
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(self.lib.dss_load_state(self.h, buf, ctypes.c_size_t(len(blob))))
+
     def tuning(self):
         t = Tuning()
         self._check(self.lib.dss_get_tuning(self.h, ctypes.byref(t)))

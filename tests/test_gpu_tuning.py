@@ -149,3 +149,47 @@ def test_autotune_batch_then_cache(tmp_path):
     rec2 = tune.autotune(sim, trial_steps=5, cache_path=path)
     assert rec2["cached"] and rec2["tuning"] == rec["tuning"]
     sim.close()
+
+
+def test_save_and_load_state():
+    """A run continued from a restored snapshot repeats the original continuation, on the same
+    handle and on a second handle loaded with the same particles; snapshots of another
+    configuration are refused."""
+    from paper_2108_01013_amd.dss import DssError, Simulation
+    w = synth.bidisperse_box(4000, 0.55, seed=14)
+    p = w.params
+    say("case: save / load state N=4000")
+    sim = Simulation(p)
+    sim.set_particles(w.x, w.rad)
+    sim.step(15, stress_every=5)
+    blob = sim.save_state()
+    sim.step(10, stress_every=5)
+    a = sim.state()
+    ha = sim.history()
+    la, ma, _ = sim.read_stress()
+    sim.load_state(blob)
+    assert sim.info()["step"] == 15
+    sim.step(10, stress_every=5)
+    b = sim.state()
+    lb, mb, _ = sim.read_stress()
+    for k in ("x", "u", "w", "F", "T"):
+        assert rel_inf(b[k], a[k]) < 1e-11, k
+    assert np.array_equal(sim.history()[0], ha[0])
+    assert rel_inf(mb, ma) < 1e-10
+    sim2 = Simulation(p)
+    sim2.set_particles(w.x, w.rad)
+    sim2.load_state(blob)
+    sim2.step(10, stress_every=5)
+    c = sim2.state()
+    assert rel_inf(c["x"], a["x"]) < 1e-11
+    sim2.close()
+    other = Simulation(p)
+    other.set_particles(w.x[:3000], w.rad[:3000])
+    with pytest.raises(DssError) as e:
+        other.load_state(blob)
+    assert e.value.status == 6
+    with pytest.raises(DssError) as e:
+        other.load_state(b"not a snapshot" * 10)
+    assert e.value.status == 1
+    other.close()
+    sim.close()
