@@ -109,6 +109,17 @@ __global__ void __launch_bounds__(kBlock) k_canon_rekey(int N, int M, const int 
     }
 }
 
+// Clear the stretch adjoints of the contacts in canonical rows (the entries that exist).
+__global__ void __launch_bounds__(kBlock) k_canon_zero(int N, int M, const int *__restrict__ cnt,
+                                                       double *__restrict__ g)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    const int n = cnt[a];
+    double *r = g + (long long)a * M * 3;
+    for (int k = 0; k < 3 * n; ++k) r[k] = 0.0;
+}
+
 __device__ __forceinline__ void atomic_add3(double *p, double a, double b, double c)
 {
     atomicAdd(p, a);

@@ -1303,7 +1303,8 @@ dss_status tape_rows(dss_handle *h, TapeEntry &t)
 }
 
 // State by id and the listed pairs of the last evaluation -> tape entry.
-dss_status tape_state(dss_handle *h, TapeEntry &t)
+// The pair count goes to a device slot; the host reads the counts of a whole segment at once.
+dss_status tape_state(dss_handle *h, TapeEntry &t, unsigned long long *count_slot)
 {
     const int N = (int)h->N;
     const int grid = (N + kBlock - 1) / kBlock;
@@ -1311,13 +1312,24 @@ dss_status tape_state(dss_handle *h, TapeEntry &t)
     hipLaunchKernelGGL(k_unsort, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c],
                        h->fb(), h->vel_is_half ? 1 : 0, 0, t.x, t.u, t.w, (double *)nullptr, (double *)nullptr);
     HIPTRY(hipGetLastError());
-    unsigned long long cnt = 0;
-    HIPTRY(hipMemcpyAsync(&cnt, h->pair_count, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipMemcpyAsync(count_slot, h->pair_count, sizeof(unsigned long long), hipMemcpyDeviceToDevice,
+                          h->stream));
+    HIPTRY(hipMemcpyAsync(t.pairs, h->pairs, 2 * (size_t)h->P.pair_cap * sizeof(int), hipMemcpyDeviceToDevice,
+                          h->stream));
+    return DSS_OK;
+}
+
+// Pair counts of tape entries lo .. hi from their device slots.
+dss_status tape_counts(dss_handle *h, std::vector<TapeEntry> &tape, const unsigned long long *slots, int lo, int hi)
+{
+    std::vector<unsigned long long> c(hi - lo + 1);
+    HIPTRY(hipMemcpyAsync(c.data(), slots + lo, c.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          h->stream));
     HIPTRY(hipStreamSynchronize(h->stream));
-    if ((int64_t)cnt > h->P.pair_cap) return fail(h, DSS_ERR_CAPACITY, "internal pair buffer overflow");
-    t.npairs = (int64_t)cnt;
-    if (cnt)
-        HIPTRY(hipMemcpyAsync(t.pairs, h->pairs, 2 * cnt * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+    for (int k = lo; k <= hi; ++k) {
+        if ((int64_t)c[k - lo] > h->P.pair_cap) return fail(h, DSS_ERR_CAPACITY, "internal pair buffer overflow");
+        tape[k].npairs = (int64_t)c[k - lo];
+    }
     return DSS_OK;
 }
 
@@ -1417,6 +1429,8 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     const size_t n3 = 3 * (size_t)N;
     double *xb, *ub, *wb, *ax, *au, *aw, *Fb, *Tb, *Fb2, *Tb2, *theta, *rad, *Sb, *xibA, *xibB;
     int *bkey, *bcnt;
+    unsigned long long *slots;
+    HIPTRY(W.get(&slots, (size_t)C + 1));
     HIPTRY(W.get(&xb, n3)); HIPTRY(W.get(&ub, n3)); HIPTRY(W.get(&wb, n3));
     HIPTRY(W.get(&ax, n3)); HIPTRY(W.get(&au, n3)); HIPTRY(W.get(&aw, n3));
     HIPTRY(W.get(&Fb, n3)); HIPTRY(W.get(&Tb, n3)); HIPTRY(W.get(&Fb2, n3)); HIPTRY(W.get(&Tb2, n3));
@@ -1456,17 +1470,19 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
             // the evaluation at the initial state (pairs, state by id)
             s = evaluate(h, EVAL_INPLACE);
             if (s) break;
-            s = tape_state(h, W.tape[0]);
+            s = tape_state(h, W.tape[0], slots);
             if (s) break;
         }
         for (int64_t k = 1; k <= len; ++k) {
             s = evaluate(h, EVAL_STEP, false);
             if (s) break;
-            s = tape_state(h, W.tape[k]);
+            s = tape_state(h, W.tape[k], slots + k);
             if (s) break;
             s = tape_rows(h, W.tape[k]);
             if (s) break;
         }
+        if (s) break;
+        s = tape_counts(h, W.tape, slots, seg == 0 ? 0 : 1, (int)len);
         if (s) break;
         if (seg < nck - 1) {
             // stretch adjoints at the segment boundary: rows of the later segment -> this one
@@ -1477,7 +1493,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         for (int64_t k = len; k >= 1; --k) {
             const int64_t n = s0 + k;
             const TapeEntry &T1 = W.tape[k], &T0 = W.tape[k - 1];
-            HIPTRY(hipMemsetAsync(xib_out, 0, 3 * (size_t)N * M * sizeof(double), h->stream));
+            hipLaunchKernelGGL(k_canon_zero, dim3(grid), dim3(kBlock), 0, h->stream, N, M, T0.ccnt, xib_out);
             VjpTape tp{T1.pairs, T1.x, T1.u, T1.w, rad, T0.ckey, T0.ccnt, T0.cxi, T1.ckey, T1.ccnt};
             const bool sampled = n >= first && (n - first) % stress_every == 0;
             const int pgrid = (int)std::max<int64_t>(1, (T1.npairs + kBlock - 1) / kBlock);
