@@ -268,13 +268,14 @@ def run_adjoint(args):
     print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     import torch
 
-    from paper_2108_01013_amd.dss import Simulation
+    from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Simulation
     torch.cuda.set_device(0)
     p = w.params
+    prec = DSS_FP64 if args.precision == "fp64" else DSS_MIXED
     K, se, C = args.steps, 10, args.ckpt
     Wt = np.zeros((3, 3))
     Wt[0, 1] = 1.0
-    sim = Simulation(p, stream=torch.cuda.current_stream().cuda_stream)
+    sim = Simulation(p, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
     sim.set_particles(w.x, w.rad)
     # warm-up: a short adjoint (allocations, first launches), then back to a state at u^n
     sim.adjoint(min(args.warmup, K) or 1, 1, C, Wt)
@@ -323,10 +324,12 @@ def run_adjoint(args):
         "metric": "adjoint particle-steps/s (forward + checkpointed recompute + reverse)",
         "value": round(N * K / el, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(el / K * 1e3, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
         "config": {"workload": f"adjoint of mean Sigma_xy over {K} steps, N={N} bidisperse 1:1.4, phi=0.56, "
-                               f"stress every {se}, checkpoints every {C}, gradients w.r.t. x0, u0, w0, mu, F_ER",
-                   "N": N, "ckpt_every": C},
+                               f"stress every {se}, checkpoints every {C}, gradients w.r.t. x0, u0, w0, mu, F_ER, "
+                               f"forward in {args.precision}, reverse in FP64",
+                   "N": N, "ckpt_every": C, "precision": args.precision},
         "roofline": roof,
         "cpu_baseline": cpu,
         "forward_only_ms_per_step": round(fwd / K * 1e3, 5),

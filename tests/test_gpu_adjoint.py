@@ -185,3 +185,27 @@ def test_adjoint_full_size_50k():
     g = (vals[0] - vals[1]) / 2e-5
     say(f"N=50000 d J / d F_ER over 10 steps: adjoint {r10['dF_ER']:.8e}  GPU FD {g:.8e}")
     assert abs(r10["dF_ER"] - g) <= 1e-3 * abs(g) + 1e-9
+
+
+def test_adjoint_mixed_forward(window):
+    """Forward in mixed precision (FP32 pair arithmetic), reverse in FP64: the gradient agrees
+    with the FP64 oracle's finite differences to the mixed mode's accuracy."""
+    from paper_2108_01013_amd.dss import DSS_MIXED, Simulation
+    w, p, u0, w0, W = window
+    say("case: adjoint with a mixed-precision forward N=400")
+    sim = Simulation(p, precision=DSS_MIXED)
+    sim.set_particles(w.x, w.rad, u0, w0)
+    r = sim.adjoint(20, 5, 7, W)
+    sim.close()
+    J0, br0 = oracle.stress_objective(p, w.x, w.rad, u0, w0, 20, 5, W)
+    assert abs(r["J"] - J0) <= 1e-5 * abs(J0)
+    g = fd(p, w, u0, w0, W, br0, lambda e: (dict(p, mu=p["mu"] + e), w.x, u0, w0), EPS["mu"])
+    assert g is not None and abs(r["dmu"] - g) <= 1e-4 * abs(g)
+    v = np.random.default_rng(9).normal(size=w.x.shape)
+    L = np.array(p["L"])
+    v[np.any((w.x < 1e-4) | (w.x > L - 1e-4), axis=1)] = 0.0
+    g = fd(p, w, u0, w0, W, br0, lambda e: (p, w.x + e * v, u0, w0), EPS["x"])
+    if g is not None:
+        ad = float(np.sum(r["dx"] * v))
+        say(f"mixed forward: d J / d x0 . v adjoint {ad:.8e} oracle FD {g:.8e}")
+        assert abs(ad - g) <= 1e-4 * abs(g)
