@@ -104,7 +104,7 @@ typedef struct {
     int64_t n_pairs;       /* listed pairs of the last summed evaluation */
     int64_t n_contacts;
     int32_t max_row_fill;
-    int32_t reserved;
+    int32_t size_classes;  /* size classes of the cell numbering (1 unless size-class stencils) */
     double L[3];
     double shear_rate;
     double le_offset;      /* Lees-Edwards offset of the current state */
@@ -148,18 +148,29 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
  * stress do not depend on them (the summation order of the force atomics aside).
  *   cell_scale: lattice spacing = cell_scale x the box's largest pair cutoff (>= 1, <= 4;
  *               1 = the smallest legal cells); larger cells mean fewer, fuller cell rows;
+ *               with size-class stencils, cell_scale x the smallest pair cutoff 2 c a_min;
  *   tile_scale: scale (0.25 .. 4) of the k_pairs row-tile capacities, which are sized from
  *               the mean occupancy of a cell row; rows beyond them take the per-particle path;
  *   tiled:      1 = stage cell rows in LDS; 0 = every row takes the per-particle path;
  *   graph:      1 = dss_step replays HIP graphs of one time step (captured on first use;
- *               not while kernel timing is on or pairs are recorded).
- * Defaults: {1, 1, 1, 1}.  reserved must be 0. */
+ *               not while kernel timing is on or pairs are recorded);
+ *   sized:      1 = size-class stencils for boxes of high size ratio (Section 2.2: cells
+ *               fitted to the smallest particles, the stencil widened for larger ones): a
+ *               particle of radius a searches a stencil of radius R(a) = floor(2 c a / cw) + 1
+ *               cells, each pair is found by its larger member, the sort is class-major
+ *               (dss_get_cells returns size_classes x n_cells + 1 starts); one box only
+ *               (DSS_ERR_ARG on a batch handle); tile_scale and tiled are then unused;
+ *   wave_class: with sized, size classes from this one up (stencil radius wave_class + 1
+ *               and more) take one wavefront per particle; 0 = 3.
+ * Defaults: {1, 1, 1, 1, 0, 0}.  reserved must be 0. */
 typedef struct {
     double cell_scale;
     double tile_scale;
     int32_t tiled;
     int32_t graph;
-    int32_t reserved[4];
+    int32_t sized;
+    int32_t wave_class;
+    int32_t reserved[2];
 } dss_tuning;
 
 /* Set the launch tuning.  Before dss_set_particles it applies to the first lattice; after,

@@ -21,6 +21,7 @@
 #include "dss.h"
 #include "dss_kernels.hpp"
 #include "dss_adjoint.hpp"
+#include "dss_sized.hpp"
 
 using namespace dss;
 
@@ -41,8 +42,11 @@ struct dss_handle {
     int ncell_total = 0, nrow_total = 0;
     int scan_tiles = 0;               // 0: one-workgroup scan (scan_c4), else workgroups of 16384 cells
     std::vector<double> box_amax;     // largest radius per box
+    double a_min = 0.0;               // smallest radius of all boxes
+    std::vector<double> rad_host;     // radii by id (size-class counts of the stencil path)
+    int sized_grid[2] = {0, 0};       // workgroups of k_pairs_sized and k_pairs_sized_wave
     double max_mean_row = 0.0;        // mean particles per cell row of the densest box
-    dss_tuning tune{1.0, 1.0, 1, 1, {0, 0, 0, 0}};
+    dss_tuning tune{1.0, 1.0, 1, 1, 0, 0, {0, 0}};
     bool tune_pending = false;        // lattice to rebuild before the next time step
     // HIP graphs of one time step, keyed by (current buffers, committed history buffers,
     // half-step velocities, stress summation)
@@ -86,6 +90,7 @@ struct dss_handle {
         b.nb = ft_nb;
         b.x = ft_x;
         b.n = N;
+        b.nnb = P.sized ? 0 : 4;
         return b;
     }
     DevRun run_host{};
@@ -267,12 +272,57 @@ dss_status require_loaded(dss_handle *h)
     return DSS_OK;
 }
 
+// Size classes of the stencil path: class of radius a = floor(a cls_mul) (the same product
+// on host and device), ncls classes.
+struct SizeClasses {
+    int ncls = 1;
+    double cls_mul = 0.0;
+};
+
 // Cell lattice of every box: spacing >= cell_scale times the box's largest pair cutoff
 // 2 c a_max (with a 1e-9 margin), boxes numbered one after the other.  Returns false (and
 // why) when a box has fewer than 4 x 3 x 3 cells or more than 4096 cell rows.
-bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, double cf, double cell_scale,
-                std::string &why)
+// Size-class stencils (one box): spacing >= cell_scale times the smallest pair cutoff
+// 2 c a_min, coarsened until the largest stencil (R_max = ncls cells) fits the box without
+// reaching a cell twice: n_x >= 2 R_max + 2 (the window of a sheared row), n_y, n_z >=
+// 2 R_max + 1.  Cells are numbered class-major: ncls x n_x n_y n_z sort keys.
+bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, double amin, double cf,
+                double cell_scale, bool sized, SizeClasses &sc, std::string &why)
 {
+    sc = SizeClasses{};
+    if (sized) {
+        if (boxes.size() != 1) {
+            why = "size-class stencils need a handle of one box";
+            return false;
+        }
+        BoxParams &G = boxes[0];
+        const double rc = cf * 2.0 * amin * (1.0 + 1e-9) * cell_scale;
+        int n[3];
+        for (int d = 0; d < 3; ++d) n[d] = std::max(1, (int)std::floor(G.L[d] / rc));
+        for (;;) {
+            if (n[0] < 4 || n[1] < 3 || n[2] < 3) {
+                why = "box too small for size-class stencils (largest stencil does not fit)";
+                return false;
+            }
+            const double cwmin = std::min(G.L[0] / n[0], std::min(G.L[1] / n[1], G.L[2] / n[2]));
+            sc.cls_mul = cf * 2.0 * (1.0 + 1e-9) / cwmin;
+            sc.ncls = (int)std::floor(amax[0] * sc.cls_mul) + 1;
+            if (n[0] >= 2 * sc.ncls + 2 && n[1] >= 2 * sc.ncls + 1 && n[2] >= 2 * sc.ncls + 1) break;
+            for (int d = 0; d < 3; ++d) n[d] -= std::max(1, n[d] / 16);
+        }
+        for (int d = 0; d < 3; ++d) {
+            G.nc[d] = n[d];
+            G.cw[d] = G.L[d] / (double)n[d];
+        }
+        G.cell_off = 0;
+        G.row_off = 0;
+        G.nrec = 1;
+        if ((int64_t)sc.ncls * n[0] * n[1] * n[2] > (int64_t)0x3fffffff) {
+            why = "too many cells";
+            return false;
+        }
+        return true;
+    }
     int64_t ncell = 0;
     int nrow = 0;
     for (size_t b = 0; b < boxes.size(); ++b) {
@@ -294,6 +344,7 @@ bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, 
         }
         G.cell_off = (int)ncell;
         G.row_off = nrow;
+        G.nrec = rows;
         ncell += (int64_t)G.nc[0] * rows;
         nrow += rows;
         if (ncell > (int64_t)0x3fffffff) {
@@ -311,7 +362,9 @@ bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, 
 dss_status setup_lattice(dss_handle *h)
 {
     std::string why;
-    if (!lattice_of(h->boxes, h->box_amax, h->prm.cutoff_factor, h->tune.cell_scale, why))
+    SizeClasses sc;
+    const bool sized = h->tune.sized != 0;
+    if (!lattice_of(h->boxes, h->box_amax, h->a_min, h->prm.cutoff_factor, h->tune.cell_scale, sized, sc, why))
         return fail(h, DSS_ERR_BOX, why);
     free_lattice(h);
     const int B = h->nbox;
@@ -327,6 +380,30 @@ dss_status setup_lattice(dss_handle *h)
         nrow += rows;
         max_rows_box = std::max(max_rows_box, rows);
         max_mean_row = std::max(max_mean_row, (double)G.n_part / (double)rows);
+    }
+    {
+        // size-class stencils: class-major sort keys, one lane per particle below wave_cls
+        // (stencil radius 4 and up by default), one wavefront per particle above; the stress
+        // partial records are the workgroups of the two kernels
+        DevParams &P = h->P;
+        P.sized = sized ? 1 : 0;
+        P.ncls = sc.ncls;
+        P.cls_mul = sc.cls_mul;
+        P.wave_cls = h->tune.wave_class > 0 ? h->tune.wave_class : 3;
+        h->sized_grid[0] = h->sized_grid[1] = 0;
+        if (sized) {
+            ncell *= sc.ncls;
+            int64_t n_big = 0;
+            for (double a : h->rad_host)
+                n_big += std::min((int)std::floor(a * sc.cls_mul), sc.ncls - 1) >= P.wave_cls ? 1 : 0;
+            const int64_t n_lane = h->N - n_big;
+            const int g_wave = P.wave_cls < sc.ncls ? (int)std::min<int64_t>(std::max<int64_t>((n_big + 3) / 4, 1), 1024) : 0;
+            const int g_lane = (int)std::min<int64_t>(std::max<int64_t>((n_lane + kBlock - 1) / kBlock, 1), 4096 - g_wave);
+            h->sized_grid[0] = g_lane;
+            h->sized_grid[1] = g_wave;
+            h->boxes[0].nrec = g_lane + g_wave;
+            max_rows_box = g_lane + g_wave;
+        }
     }
     // cell-count scan: one workgroup up to 65535 cells, else workgroups of 16384 cells
     int64_t ncell_pad;
@@ -391,7 +468,7 @@ dss_status setup_lattice(dss_handle *h)
     HIPTRY(hipFuncSetAttribute((const void *)k_pairs<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)h->tile_lds));
     h->finish_r = (max_rows_box + 1023) / 1024;
-    P.pstride = (nrow + 63) / 64 * 64;
+    P.pstride = (std::max(nrow, max_rows_box) + 63) / 64 * 64;
     HIPTRY(dalloc(&h->count, ncell_pad));
     HIPTRY(dalloc(&h->cell_start, ncell_pad));
     HIPTRY(dalloc(&h->tile_sum, std::max(h->scan_tiles, 1)));
@@ -426,6 +503,32 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, boo
     H.cnt_new = h->hcnt[1 - h->hh];
     H.own_new = h->hown[1 - h->hh];
     if (h->P.record_pairs) HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
+    if (h->P.sized) {
+        {
+            TimedLaunch t(h, 3);
+            if (h->prm.precision == DSS_MIXED)
+                hipExtLaunchKernelGGL(k_pairs_sized<float>, dim3(h->sized_grid[0]), dim3(kBlock), 0, h->stream, t.e0,
+                                      t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf],
+                                      h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count);
+            else
+                hipExtLaunchKernelGGL(k_pairs_sized<double>, dim3(h->sized_grid[0]), dim3(kBlock), 0, h->stream, t.e0,
+                                      t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf],
+                                      h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count);
+        }
+        if (h->sized_grid[1] > 0) {
+            TimedLaunch t(h, 7);
+            if (h->prm.precision == DSS_MIXED)
+                hipExtLaunchKernelGGL(k_pairs_sized_wave<float>, dim3(h->sized_grid[1]), dim3(kBlock), 0, h->stream,
+                                      t.e0, t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf],
+                                      h->omg[buf], h->fb(), H, h->clk, h->partials, h->sized_grid[0], h->pairs,
+                                      h->pair_count);
+            else
+                hipExtLaunchKernelGGL(k_pairs_sized_wave<double>, dim3(h->sized_grid[1]), dim3(kBlock), 0, h->stream,
+                                      t.e0, t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf],
+                                      h->omg[buf], h->fb(), H, h->clk, h->partials, h->sized_grid[0], h->pairs,
+                                      h->pair_count);
+        }
+    } else {
     {
         TimedLaunch t(h, 3);
         if (h->prm.precision == DSS_MIXED)
@@ -456,6 +559,7 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, boo
                                   h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf],
                                   h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count,
                                   (const int *)h->fb_rows, (const int *)h->fb_count);
+    }
     }
     if (!finish) return DSS_OK;
     TimedLaunch t(h, 4);
@@ -535,8 +639,7 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
     {
         TimedLaunch t(h, 2);
         hipExtLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, N, h->cell, h->rank,
-                              h->cell_start, h->pa[c], h->vel[c], h->omg[c], h->pa[o], h->vel[o], h->omg[o], h->ft_x,
-                              h->prev);
+                              h->cell_start, h->pa[c], h->vel[c], h->omg[c], h->pa[o], h->vel[o], h->omg[o], h->prev);
     }
     dss_status s = launch_pairs(h, o, h->prev, advance, finish);
     if (s) return s;
@@ -741,7 +844,8 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     {
         std::vector<BoxParams> trial = boxes;
         std::string why;
-        if (!lattice_of(trial, box_amax, p.cutoff_factor, h->tune.cell_scale, why))
+        SizeClasses sc;
+        if (!lattice_of(trial, box_amax, a_min, p.cutoff_factor, h->tune.cell_scale, h->tune.sized != 0, sc, why))
             return fail(h, DSS_ERR_BOX, why);
     }
 
@@ -751,6 +855,8 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     h->box_n.assign(n_per_box, n_per_box + B);
     h->box_sa3 = box_sa3;
     h->box_amax = box_amax;
+    h->a_min = a_min;
+    h->rad_host = hr;
     h->N = N;
     const size_t rows = (size_t)N * (size_t)P.M;
     for (int k = 0; k < 2; ++k) {
@@ -842,18 +948,22 @@ dss_status dss_set_tuning(dss_handle *h, const dss_tuning *t)
 {
     if (!h || !t) return DSS_ERR_ARG;
     if (!(t->cell_scale >= 1.0 && t->cell_scale <= 4.0) || !(t->tile_scale >= 0.25 && t->tile_scale <= 4.0) ||
-        (t->tiled != 0 && t->tiled != 1) || (t->graph != 0 && t->graph != 1) || t->reserved[0] || t->reserved[1] ||
-        t->reserved[2] || t->reserved[3])
-        return fail(h, DSS_ERR_ARG, "tuning out of range (cell_scale in [1, 4], tile_scale in [0.25, 4], flags 0/1)");
+        (t->tiled != 0 && t->tiled != 1) || (t->graph != 0 && t->graph != 1) || (t->sized != 0 && t->sized != 1) ||
+        t->wave_class < 0 || t->wave_class > 64 || t->reserved[0] || t->reserved[1])
+        return fail(h, DSS_ERR_ARG, "tuning out of range (cell_scale in [1, 4], tile_scale in [0.25, 4], "
+                                    "wave_class in [0, 64], flags 0/1)");
+    if (t->sized && h->nbox != 1) return fail(h, DSS_ERR_ARG, "size-class stencils need a handle of one box");
     if (h->loaded) {
         // the lattice must still be legal for every box
         std::vector<BoxParams> trial = h->boxes;
         std::string why;
-        if (!lattice_of(trial, h->box_amax, h->prm.cutoff_factor, t->cell_scale, why))
+        SizeClasses sc;
+        if (!lattice_of(trial, h->box_amax, h->a_min, h->prm.cutoff_factor, t->cell_scale, t->sized != 0, sc, why))
             return fail(h, DSS_ERR_BOX, why);
     }
     const bool lattice = t->cell_scale != h->tune.cell_scale || t->tile_scale != h->tune.tile_scale ||
-                         t->tiled != h->tune.tiled;
+                         t->tiled != h->tune.tiled || t->sized != h->tune.sized ||
+                         t->wave_class != h->tune.wave_class;
     h->tune = *t;
     if (!t->graph) destroy_graphs(h);
     if (h->loaded && lattice) h->tune_pending = true;
@@ -1159,7 +1269,7 @@ dss_status dss_get_box_info(dss_handle *h, int32_t box, dss_box_info *info)
     info->n_pairs = (int64_t)d[3 * box];
     info->n_contacts = (int64_t)d[3 * box + 1];
     info->max_row_fill = (int32_t)d[3 * box + 2];
-    info->reserved = 0;
+    info->size_classes = h->P.sized ? h->P.ncls : 1;
     info->shear_rate = G.gd;
     double t = (double)c.step * h->prm.dt;
     info->le_offset = std::fmod(G.gd * G.L[1] * t, G.L[0]);

@@ -46,6 +46,10 @@ struct DevParams {
     int own_cap, stage_cap, qcap;   // row-tile capacities of k_pairs
     int tiled;                      // 0: every row takes the per-particle path
     int pstride;                    // stride of the partial records (1024 R)
+    int sized;                      // 1: size-class stencils (class-major cell numbering)
+    int ncls;                       // size classes (stencil radius of class k: k + 1 cells)
+    int wave_cls;                   // classes from this one up take a wavefront per particle
+    double cls_mul;                 // class of radius a: floor(a cls_mul)
 };
 
 // One box: its geometry, shear rate, cell lattice and its ranges in the global numbering
@@ -60,6 +64,7 @@ struct BoxParams {
     int row_off;       // first cell row (nc[1] nc[2] rows per box)
     int part_off;      // first particle id of the box
     int n_part;        // particles of the box
+    int nrec;          // stress partial records of the box (from row_off; its cell rows when tiled)
 };
 
 // Device-side clock and error flags.  step = time index of the state.
@@ -96,6 +101,14 @@ __device__ __forceinline__ int cell_coord(double xd, double cw, int n)
     c = c < 0 ? 0 : c;
     c = c > n - 1 ? n - 1 : c;
     return c;
+}
+
+// Size class of radius a under size-class stencils (stencil radius class + 1 cells).
+__device__ __forceinline__ int size_class(const DevParams &P, double a)
+{
+#pragma clang fp contract(off)
+    const int k = (int)floor(a * P.cls_mul);
+    return k < 0 ? 0 : (k > P.ncls - 1 ? P.ncls - 1 : k);
 }
 
 // Nearest image of b seen from a under Lees-Edwards shear; r = x_b - x_a.  Rows above /
@@ -206,8 +219,9 @@ __device__ __forceinline__ int warp_max(int v)
 struct ForceBufs {
     double *own;     // N x 6
     double *nb;      // 4 x N x 6
-    double *x;       // N x 6, atomic accumulation, cleared by k_scatter
+    double *x;       // N x 6, atomic accumulation, cleared by k_predict after use
     long long n;     // N (stride of nb)
+    int nnb;         // partner records in use (4 on the row tiles, 0 with size-class stencils)
 };
 
 __device__ __forceinline__ void load_ft(const double *__restrict__ rec, double f[6])
@@ -225,17 +239,20 @@ __device__ __forceinline__ void store_ft(double *__restrict__ rec, const double 
     q[2] = make_double2(f[4], f[5]);
 }
 
-// Total force (f[0..2]) and torque (f[3..5]) of slot p, summed in a fixed order.
-__device__ __forceinline__ void total_ft(const ForceBufs &B, int p, double f[6])
+// Total force (f[0..2]) and torque (f[3..5]) of slot p, summed in a fixed order.  with_x = 0
+// leaves out the atomic record (all zero when no row took the per-particle path).
+__device__ __forceinline__ void total_ft(const ForceBufs &B, int p, double f[6], bool with_x = true)
 {
     double a[6];
     load_ft(B.own + 6LL * p, f);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+        if (r >= B.nnb) break;
         load_ft(B.nb + 6LL * (r * B.n + p), a);
 #pragma unroll
         for (int k = 0; k < 6; ++k) f[k] += a[k];
     }
+    if (!with_x) return;
     load_ft(B.x + 6LL * p, a);
 #pragma unroll
     for (int k = 0; k < 6; ++k) f[k] += a[k];
@@ -257,6 +274,7 @@ template <int C4>
 __global__ void __launch_bounds__(1024) k_scan(int *__restrict__ count, int *__restrict__ cell_start,
                                                DevClock *__restrict__ clk, int advance, int *__restrict__ tile_sum)
 {
+    static_assert(C4 >= 1 && C4 <= 16, "one wavefront scans at most 256 wavefront totals");
     __shared__ int wsum[C4][16];
     __shared__ int wpre[C4][16];
     const int t = threadIdx.x;
@@ -284,14 +302,31 @@ __global__ void __launch_bounds__(1024) k_scan(int *__restrict__ count, int *__r
         for (int k = 0; k < C4; ++k) wsum[k][wid] = incl[k];
     }
     __syncthreads();
-    if (t == 0) {
-        int run = 0;
-        for (int k = 0; k < C4; ++k)
-            for (int w = 0; w < 16; ++w) {
-                wpre[k][w] = run;
-                run += wsum[k][w];
-            }
-        if (tile_sum) tile_sum[blockIdx.x] = run;
+    if (wid == 0) {
+        // prefix of the C4 x 16 wavefront totals (flat order k 16 + w): four per lane, then
+        // one wavefront scan of the lane sums
+        const int *ws = &wsum[0][0];
+        int *wp = &wpre[0][0];
+        int loc[4], sum = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int q = 4 * lane + e;
+            loc[e] = q < C4 * 16 ? ws[q] : 0;
+            sum += loc[e];
+        }
+        int incl = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        int run = incl - sum;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int q = 4 * lane + e;
+            if (q < C4 * 16) wp[q] = run;
+            run += loc[e];
+        }
+        if (tile_sum && lane == 63) tile_sum[blockIdx.x] = incl;
     }
     __syncthreads();
     const int4 zero = make_int4(0, 0, 0, 0);
@@ -342,6 +377,9 @@ __global__ void __launch_bounds__(1024) k_scan_add(int *__restrict__ cell_start,
 // only (advance = 0), Lees-Edwards wrap at t_{n+1}, cell id and histogram rank.
 //   vel_is_half = 1: vel holds the half-step velocity u^{n-1/2} of the forces, and
 //   u^n = u^{n-1/2} + dt/2 F^n / m completes the previous step.
+// The atomic force record is read, and cleared for the next evaluation, only when the last
+// evaluation deferred rows to the per-particle path (clk->deferred > 0); otherwise it is
+// already zero.
 // ----------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams *__restrict__ boxes,
                                                      double4 *__restrict__ pa, double4 *__restrict__ vel,
@@ -365,7 +403,15 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
     double m = pmass(P, a);
     double I = 0.4 * m * a * a;
     double f[6];
-    total_ft(B, p, f);
+    total_ft(B, p, f, false);
+    if (clk->deferred) {
+        double e[6];
+        load_ft(B.x + 6LL * p, e);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) f[k] += e[k];
+        const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        store_ft(B.x + 6LL * p, z);
+    }
     double ax = f[0] / m, ay = f[1] / m, az = f[2] / m;
     double bx = f[3] / I, by = f[4] / I, bz = f[5] / I;
     if (vel_is_half) {  // finish the previous step: u^n = u^{n-1/2} + dt/2 alpha^n
@@ -407,6 +453,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
     int cy = cell_coord(X.y, G.cw[1], G.nc[1]);
     int cz = cell_coord(X.z, G.cw[2], G.nc[2]);
     c = G.cell_off + (cz * G.nc[1] + cy) * G.nc[0] + cx;
+    if (P.sized) c += size_class(P, X.w) * (G.nc[0] * G.nc[1] * G.nc[2]);
     }
     // histogram rank: lanes of a wavefront with equal consecutive cell ids (the input is
     // sorted by the previous step's cells) form runs; the first lane of a run claims the
@@ -456,7 +503,7 @@ __global__ void __launch_bounds__(kBlock) k_complete(DevParams P, const double4 
 
 // ----------------------------------------------------------------------------------
 // k_scatter: move every particle to its sorted slot, remember its previous slot (where
-// its contact-history row of the last step lives), clear the atomic force records.
+// its contact-history row of the last step lives).
 // ----------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_scatter(int N, const int *__restrict__ cell, const int *__restrict__ rank,
                                                      const int *__restrict__ cell_start,
@@ -464,7 +511,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int N, const int *__restrict
                                                      const double4 *__restrict__ vel_in,
                                                      const double4 *__restrict__ omg_in, double4 *__restrict__ pa_out,
                                                      double4 *__restrict__ vel_out, double4 *__restrict__ omg_out,
-                                                     double *__restrict__ ft_x, int *__restrict__ prev)
+                                                     int *__restrict__ prev)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
@@ -472,8 +519,6 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int N, const int *__restrict
     pa_out[dst] = pa_in[p];
     vel_out[dst] = vel_in[p];
     omg_out[dst] = omg_in[p];
-    const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    store_ft(ft_x + 6LL * dst, z);
     prev[dst] = p;
 }
 
@@ -1413,7 +1458,7 @@ __global__ void __launch_bounds__(1024) k_finish(const BoxParams *__restrict__ b
     const int t = threadIdx.x;
     const int b = blockIdx.x;
     const BoxParams &G = boxes[b];
-    const int r0 = G.row_off, nrow = G.nc[1] * G.nc[2];
+    const int r0 = G.row_off, nrow = G.nrec;
     double v[R][12];
 #pragma unroll
     for (int m = 0; m < R; ++m) {

@@ -53,13 +53,14 @@ class Info(ctypes.Structure):
 class BoxInfo(ctypes.Structure):
     _fields_ = [("n_particles", ctypes.c_int64), ("first_id", ctypes.c_int64), ("cells", ctypes.c_int32 * 3),
                 ("first_cell", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("n_contacts", ctypes.c_int64),
-                ("max_row_fill", ctypes.c_int32), ("reserved", ctypes.c_int32), ("L", ctypes.c_double * 3),
+                ("max_row_fill", ctypes.c_int32), ("size_classes", ctypes.c_int32), ("L", ctypes.c_double * 3),
                 ("shear_rate", ctypes.c_double), ("le_offset", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("cell_scale", ctypes.c_double), ("tile_scale", ctypes.c_double), ("tiled", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("graph", ctypes.c_int32), ("sized", ctypes.c_int32), ("wave_class", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 _lib = None
@@ -256,7 +257,9 @@ class Simulation:
         return p[np.lexsort((p[:, 1], p[:, 0]))]
 
     def _ncell_total(self, dims):
-        return int(np.prod(dims))
+        inf = BoxInfo()
+        self._check(self.lib.dss_get_box_info(self.h, 0, ctypes.byref(inf)))
+        return int(np.prod(dims)) * int(inf.size_classes)
 
     def cells(self):
         dims = np.zeros(3, np.int32)
@@ -288,10 +291,16 @@ class Simulation:
     KERNELS = ("k_predict", "k_scan", "k_scatter", "k_pairs", "k_finish", "k_pairs_vjp", "k_integrate_vjp",
                "k_pairs_rows")
 
-    def set_tuning(self, cell_scale=None, tile_scale=None, tiled=None, graph=None):
-        """Change launch tuning (results do not depend on it); unspecified fields keep their value."""
+    def set_tuning(self, cell_scale=None, tile_scale=None, tiled=None, graph=None, sized=None, wave_class=None):
+        """Change launch tuning (results do not depend on it); unspecified fields keep their value.
+        sized: size-class stencils (one box); wave_class: first size class on one wavefront per
+        particle (0 = default)."""
         t = Tuning()
         self._check(self.lib.dss_get_tuning(self.h, ctypes.byref(t)))
+        if sized is not None:
+            t.sized = int(bool(sized))
+        if wave_class is not None:
+            t.wave_class = int(wave_class)
         if cell_scale is not None:
             t.cell_scale = float(cell_scale)
         if tile_scale is not None:
@@ -352,7 +361,7 @@ class Simulation:
         t = Tuning()
         self._check(self.lib.dss_get_tuning(self.h, ctypes.byref(t)))
         return {"cell_scale": t.cell_scale, "tile_scale": t.tile_scale, "tiled": bool(t.tiled),
-                "graph": bool(t.graph)}
+                "graph": bool(t.graph), "sized": bool(t.sized), "wave_class": int(t.wave_class)}
 
     def set_timing(self, enable=True, kernels=None):
         """Time the named kernels (all if None) with HIP events; enable=False stops."""
@@ -435,8 +444,8 @@ class Batch(Simulation):
         self._check(self.lib.dss_get_box_info(self.h, int(b), ctypes.byref(inf)))
         return {"n_particles": inf.n_particles, "first_id": inf.first_id, "cells": tuple(inf.cells),
                 "first_cell": inf.first_cell, "n_pairs": inf.n_pairs, "n_contacts": inf.n_contacts,
-                "max_row_fill": inf.max_row_fill, "L": tuple(inf.L), "shear_rate": inf.shear_rate,
-                "le_offset": inf.le_offset}
+                "max_row_fill": inf.max_row_fill, "size_classes": inf.size_classes, "L": tuple(inf.L),
+                "shear_rate": inf.shear_rate, "le_offset": inf.le_offset}
 
     def _ncell_total(self, dims):
         last = self.box_info(self.B - 1)

@@ -64,17 +64,35 @@ def _min_image(d, L):
     return d - L * np.round(d / L)
 
 
+def _near_pairs(x: np.ndarray, r: np.ndarray, L: float, skin: float, wide: bool):
+    """Candidate pairs (i, j) with |x_i - x_j| < r_i + r_j + skin, each once.  For a narrow
+    size distribution one fixed-radius query (2 r_max + skin); for a wide one every particle
+    queries 2 r_i + skin and keeps the partners that are smaller (ties: lower index), so the
+    work follows the particle sizes instead of the largest one."""
+    tree = cKDTree(x, boxsize=L)
+    if not wide:
+        return tree.query_pairs(2.0 * float(r.max()) + skin, output_type="ndarray")
+    nb = tree.query_ball_point(x, 2.0 * r + skin, return_sorted=True)
+    cnt = np.fromiter((len(q) for q in nb), np.int64, len(nb))
+    pi = np.repeat(np.arange(len(r)), cnt)
+    pj = np.concatenate([np.asarray(q, np.int64) for q in nb]) if cnt.sum() else np.zeros(0, np.int64)
+    own = (r[pj] < r[pi]) | ((r[pj] == r[pi]) & (pj < pi))
+    return np.stack([pi[own], pj[own]], axis=1)
+
+
 def relax_positions(rad: np.ndarray, L: float, seed: int = 0, tol: float = 1e-3, max_sweeps: int = 20000,
                     x0: np.ndarray | None = None) -> np.ndarray:
     """Uniform random centres in [0, L)^3, then overlap removal by a soft-sphere push.
 
     Radii are inflated from 0.8x to 1x in stages; at each stage every overlapping pair is pushed
     apart along its centre line (heavy-ball momentum 0.9 on the displacements).  Stops when the
-    largest overlap is below tol * min(a_i, a_j)."""
+    largest overlap is below tol * min(a_i, a_j).  Size ratios above 2 use size-aware
+    neighbour queries."""
     rng = np.random.default_rng(seed)
     N = len(rad)
     x = rng.uniform(0.0, L, size=(N, 3)) if x0 is None else np.array(x0, dtype=np.float64)
     a_max = float(rad.max())
+    wide = a_max > 2.0 * float(rad.min())
     skin = 0.3 * float(rad.min())
     stages = list(np.linspace(0.8, 1.0, 9))
     sweeps = 0
@@ -88,8 +106,7 @@ def relax_positions(rad: np.ndarray, L: float, seed: int = 0, tol: float = 1e-3,
             if x_ref is None or np.max(np.abs(_min_image(x - x_ref, L))) > 0.5 * skin:
                 x %= L
                 x[x >= L] = 0.0
-                tree = cKDTree(x, boxsize=L)
-                prs = tree.query_pairs(2.0 * a_max * scale + skin, output_type="ndarray")
+                prs = _near_pairs(x, r, L, skin, wide)
                 d = _min_image(x[prs[:, 1]] - x[prs[:, 0]], L)
                 keep = np.sqrt(np.einsum("ij,ij->i", d, d)) < r[prs[:, 0]] + r[prs[:, 1]] + skin
                 pi, pj = prs[keep, 0], prs[keep, 1]
@@ -144,6 +161,15 @@ def config_small(seed: int = 1) -> Workload:
 def config_single_box(seed: int = 2, N: int = 100_000) -> Workload:
     """N = 100k bidisperse (1 : 1.4, equal volumes), phi = 0.55, mu = 1, gdot = 1, dt = 1e-4."""
     return bidisperse_box(N, 0.55, seed)
+
+
+def config_high_ratio(seed: int = 3, N: int = 500_000) -> Workload:
+    """N = 500k, ln a ~ Normal(ln 1.5, 0.5) truncated to [1, 10] (size ratio 10), phi = 0.55,
+    mu = 1, gdot = 1, dt = 1e-4."""
+    rad = lognormal_radii(N, seed=seed)
+    L = box_for_fraction(rad, 0.55)
+    x = relax_positions(rad, L, seed=seed + 1000)
+    return Workload(f"lognormal N={N} phi=0.55 a in [1, 10]", x, rad, L, default_params([L, L, L]))
 
 
 SWEEP_PHI = (0.40, 0.45, 0.50, 0.55, 0.58)
