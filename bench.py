@@ -67,14 +67,14 @@ def maybe_tune(sim, args):
                        for t in rec.get("trials", [])]}
 
 
-def timed_run(sim, N, args, stress_every):
-    """Warm-up, then the timed region with HIP events around k_pairs; then an untimed
-    per-kernel breakdown (kernel timing replaces graph replay by direct launches).
-    Returns (seconds, k_pairs timing, breakdown)."""
+def timed_run(sim, N, args, stress_every, kernels=("k_pairs",)):
+    """Warm-up, then the timed region with HIP events around the pair kernel(s); then an
+    untimed per-kernel breakdown (kernel timing replaces graph replay by direct launches).
+    Returns (seconds, pair-kernel timing, breakdown)."""
     import torch
     sim.step(args.warmup, stress_every=stress_every, sync=True)
     torch.cuda.synchronize()
-    sim.set_timing(True, kernels=["k_pairs"])
+    sim.set_timing(True, kernels=list(kernels))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(args.steps, stress_every=stress_every, sync=False)
@@ -156,7 +156,7 @@ def run_single(args):
     from paper_2108_01013_amd import synth
 
     t_gen = time.perf_counter()
-    w = cached_workload(args, lambda: synth.config_single_box(N=args.N))
+    w = cached_workload(args, lambda: synth.config_single_box(N=args.N or 100_000))
     print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     import torch
 
@@ -193,6 +193,66 @@ def run_single(args):
         "diagnostics": {"n_pairs": info["n_pairs"], "n_contacts": info["n_contacts"],
                         "max_row_fill": info["max_row_fill"], "capacity": info["capacity"],
                         "cells": info["cells"], "stress_samples": nsamp,
+                        "eta_r_mean": float(sigma_mean[0, 1] / (p["eta0"] * p["shear_rate"]))},
+    }
+
+
+def run_poly(args):
+    """High size ratio: N = 500k, lognormal radii on [1, 10], phi = 0.55, mixed precision by
+    default, on the size-class stencils (autotuned over cell spacings unless --tune 0)."""
+    from paper_2108_01013_amd import synth
+
+    N = args.N or 500_000
+    t_gen = time.perf_counter()
+    w = cached_workload(args, lambda: synth.config_high_ratio(N=N))
+    print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    import torch
+
+    from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Simulation
+    prec = DSS_FP64 if args.precision == "fp64" else DSS_MIXED
+    torch.cuda.set_device(0)
+    p = w.params
+    sim = Simulation(p, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
+    sim.set_tuning(sized=True, cell_scale=2.0)
+    sim.set_particles(w.x, w.rad)
+    N = len(w.rad)
+    tuned = maybe_tune(sim, args)
+    el, timing, breakdown = timed_run(sim, N, args, 10, kernels=["k_pairs", "k_pairs_rows"])
+    info = sim.info()
+    _, sigma_mean, nsamp = sim.read_stress()
+    if info["error_flags"]:
+        print(f"# device error flags {info['error_flags']}", file=sys.stderr)
+        sys.exit(1)
+    tun = sim.tuning()
+    sized = tun["sized"]
+    names = {"k_pairs": "k_pairs_sized", "k_pairs_rows": "k_pairs_sized_wave"} if sized else {}
+    box = sim.box_info(0)
+    ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2]) * int(box["size_classes"])
+    # dominant pair kernel of the timed region
+    dom = max(("k_pairs", "k_pairs_rows"), key=lambda k: timing.get(k, (0.0, 0))[0])
+    roof = roofline({"k_pairs": timing[dom]}, N, ncell, info["n_contacts"], info["capacity"])
+    roof["kernel"] = names.get(dom, dom)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_seconds, "the same N=500k lognormal")
+    table = {names.get(k, k): v for k, v in kernel_table(breakdown).items()}
+    return {
+        "metric": "particle-steps/s, high size ratio (size-class stencils)",
+        "value": round(N * args.steps / el, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"single box N={N}, ln a ~ Normal(ln 1.5, 0.5) truncated to [1, 10], phi=0.55, "
+                               f"LE shear rate 1, mu=1, dt=1e-4, stress every 10 steps, {args.precision}",
+                   "N": N, "phi": 0.55, "size_ratio": round(float(w.rad.max() / w.rad.min()), 3),
+                   "precision": args.precision},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": table,
+        "tuning": tuned or tun,
+        "diagnostics": {"n_pairs": info["n_pairs"], "n_contacts": info["n_contacts"],
+                        "max_row_fill": info["max_row_fill"], "capacity": info["capacity"],
+                        "cells": info["cells"], "size_classes": box["size_classes"], "stress_samples": nsamp,
                         "eta_r_mean": float(sigma_mean[0, 1] / (p["eta0"] * p["shear_rate"]))},
     }
 
@@ -263,7 +323,7 @@ def run_adjoint(args):
     from paper_2108_01013_amd import synth
 
     t_gen = time.perf_counter()
-    N = args.N if args.N != 100_000 else 50_000
+    N = args.N or 50_000
     w = synth.bidisperse_box(N, 0.56, seed=5)
     print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     import torch
@@ -346,11 +406,12 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--mode", choices=["single", "sweep", "adjoint"], default="single",
+    ap.add_argument("--mode", choices=["single", "sweep", "adjoint", "poly"], default="single",
                     help="single: one box of N particles; sweep: the batched flow-curve sweep; "
-                         "adjoint: gradient of the mean shear stress (N=50k)")
+                         "adjoint: gradient of the mean shear stress (N=50k); poly: size ratio 10 "
+                         "(N=500k, size-class stencils)")
     ap.add_argument("--ckpt", type=int, default=20, help="adjoint checkpoint spacing")
-    ap.add_argument("--N", type=int, default=100_000)
+    ap.add_argument("--N", type=int, default=None, help="particles (default per mode)")
     ap.add_argument("--boxes", type=int, default=64)
     ap.add_argument("--workers", type=int, default=16, help="processes generating the sweep's boxes")
     ap.add_argument("--tune", type=int, default=None,
@@ -366,11 +427,11 @@ def main():
         args.tune = 1 if args.mode == "sweep" else 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the design of a "
-              "z-slab decomposition is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
-    out = {"single": run_single, "sweep": run_sweep, "adjoint": run_adjoint}[args.mode](args)
+    out = {"single": run_single, "sweep": run_sweep, "adjoint": run_adjoint, "poly": run_poly}[args.mode](args)
     if args.copy_probe:
         copy_probe()
     print(json.dumps(out), flush=True)

@@ -1153,6 +1153,17 @@ __device__ __forceinline__ void row_bounds(const BoxParams &G, int row, const in
     __syncthreads();
 }
 
+// Cell row of workgroup b of n.  Workgroups are dispatched to the 8 XCDs in turn (b mod 8),
+// each XCD with its own L2; this bijection gives every XCD one contiguous run of rows, so the
+// shell rows a workgroup stages were mostly fetched into the same L2 by its neighbours.
+__device__ __forceinline__ int xcd_row(int b, int n)
+{
+    constexpr int kXcd = 8;
+    const int q = n / kXcd, r = n % kXcd;
+    const int x = b % kXcd, k = b / kXcd;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 template <typename Real>
 __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
                                                       const int *__restrict__ row_box, const int *__restrict__ cell_start,
@@ -1174,9 +1185,10 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
     V.rowcnt = V.tpre + 5 * P.own_cap + 1;
 
     const int t = threadIdx.x;
-    const BoxParams G = boxes[row_box[blockIdx.x]];
+    const int grow = xcd_row(blockIdx.x, gridDim.x);
+    const BoxParams G = boxes[row_box[grow]];
     const int nxc = G.nc[0], nzc = G.nc[2];
-    const int row = blockIdx.x - G.row_off;  // cell row within the box
+    const int row = grow - G.row_off;  // cell row within the box
     const int cz = row / G.nc[1];
     const double delta = le_offset(P, G, clk->step);
     PairTally tally;
@@ -1190,7 +1202,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
     // a row beyond the tile capacities (or one that hits a tile limit below) is left to
     // k_pairs_rows, which takes it on the per-particle path; nothing of it is written here
     auto defer_row = [&]() {
-        if (t == 0) fb_rows[atomicAdd(fb_count, 1)] = blockIdx.x;
+        if (t == 0) fb_rows[atomicAdd(fb_count, 1)] = grow;
     };
     if (!P.tiled || n_own > P.own_cap || total > P.stage_cap) {
         defer_row();
@@ -1394,7 +1406,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
         for (int c = 0; c < 6; ++c) f[c] = V.acc[6 * k + c];
         store_ft(B.nb + 6LL * ((r - 1) * B.n + g), f);
     }
-    reduce_tally(tally, T.red, partials, P.pstride, blockIdx.x);
+    reduce_tally(tally, T.red, partials, P.pstride, grow);
 }
 
 // ----------------------------------------------------------------------------------

@@ -136,7 +136,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const Bo
     for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
     tally.npair = tally.ncont = 0;
     tally.fill = 0;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n_lane; i += gridDim.x * kBlock) {
+    // XCD-contiguous slot blocks (see xcd_row): neighbouring slots share cells and partners
+    const int lb = xcd_row(blockIdx.x, gridDim.x);
+    for (int i = lb * kBlock + threadIdx.x; i < n_lane; i += gridDim.x * kBlock) {
         const double4 Xi = pa[i];
         const double4 Vi = vel[i];
         const double4 Wi = omg[i];

@@ -1,11 +1,12 @@
 """Autotuner for the launch tuning of a loaded Simulation or Batch.
 
-The tuning (cell_scale, tile_scale, tiled, graph; see dss_set_tuning in include/dss.h) changes
-how the step is launched, never what it computes.  The tuner times a short run of ordinary
-time steps under each candidate -- the steps advance the simulation like any others, so the
-tuning costs no extra work beyond the time spent in slower candidates -- keeps the fastest,
-and caches the choice in a JSON file keyed by the workload class: number of boxes, particles
-per box (power-of-two bucket), volume fraction (0.05 bucket), size ratio and precision.
+The tuning (cell_scale, tile_scale, tiled, graph, sized, wave_class; see dss_set_tuning in
+include/dss.h) changes how the step is launched, never what it computes.  The tuner times a
+short run of ordinary time steps under each candidate -- the steps advance the simulation like
+any others, so the tuning costs no extra work beyond the time spent in slower candidates --
+keeps the fastest, and caches the choice in a JSON file keyed by the workload class: number of
+boxes, particles per box (power-of-two bucket), volume fraction (0.05 bucket), size ratio and
+precision.  One box of size ratio above 2 also tries the size-class stencils.
 """
 from __future__ import annotations
 
@@ -16,13 +17,30 @@ import tempfile
 import time
 
 CANDIDATES = (
-    {"cell_scale": 1.0, "tile_scale": 1.0, "tiled": True},
-    {"cell_scale": 1.0, "tile_scale": 0.75, "tiled": True},
-    {"cell_scale": 1.0, "tile_scale": 1.5, "tiled": True},
-    {"cell_scale": 1.15, "tile_scale": 1.0, "tiled": True},
-    {"cell_scale": 1.3, "tile_scale": 1.0, "tiled": True},
-    {"cell_scale": 1.0, "tile_scale": 1.0, "tiled": False},
+    {"cell_scale": 1.0, "tile_scale": 1.0, "tiled": True, "sized": False},
+    {"cell_scale": 1.0, "tile_scale": 0.75, "tiled": True, "sized": False},
+    {"cell_scale": 1.0, "tile_scale": 1.5, "tiled": True, "sized": False},
+    {"cell_scale": 1.15, "tile_scale": 1.0, "tiled": True, "sized": False},
+    {"cell_scale": 1.3, "tile_scale": 1.0, "tiled": True, "sized": False},
+    {"cell_scale": 1.0, "tile_scale": 1.0, "tiled": False, "sized": False},
 )
+
+# Size-class stencils (one box of high size ratio): cell spacing in units of the smallest pair
+# cutoff; wave_class 0 = the default split between lane and wavefront stencils.
+SIZED_CANDIDATES = (
+    {"cell_scale": 1.0, "sized": True, "wave_class": 0},
+    {"cell_scale": 1.5, "sized": True, "wave_class": 0},
+    {"cell_scale": 2.0, "sized": True, "wave_class": 0},
+    {"cell_scale": 3.0, "sized": True, "wave_class": 0},
+    {"cell_scale": 2.0, "sized": True, "wave_class": 2},
+)
+
+
+def candidates_for(sim):
+    """The row-tile candidates; for one box of size ratio above 2 also the size-class stencils."""
+    if getattr(sim, "B", 1) == 1 and sim.size_ratio > 2.0:
+        return CANDIDATES + SIZED_CANDIDATES
+    return CANDIDATES
 
 
 def default_cache_path() -> str:
@@ -55,7 +73,7 @@ def _store(path, cache):
     os.replace(tmp, path)
 
 
-def autotune(sim, trial_steps: int = 20, cache_path: str | None = None, candidates=CANDIDATES,
+def autotune(sim, trial_steps: int = 20, cache_path: str | None = None, candidates=None,
              force: bool = False, log=None) -> dict:
     """Choose and apply the fastest tuning for `sim` (loaded).  Returns the cache record
     {"tuning": {...}, "ms_per_step": t, "trials": [...], "cached": bool}."""
@@ -70,7 +88,7 @@ def autotune(sim, trial_steps: int = 20, cache_path: str | None = None, candidat
         rec["cached"] = True
         return rec
     trials = []
-    for cand in candidates:
+    for cand in (candidates_for(sim) if candidates is None else candidates):
         try:
             sim.set_tuning(**cand, graph=True)
         except DssError:
