@@ -44,7 +44,11 @@ def build() -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double * 3)] + [(n, ctypes.c_double) for n in (
         "shear_rate", "eta0", "rho", "kn", "kt", "gamma_n", "mu", "F_ER", "lambda_D", "a0",
-        "hamaker", "eps_vdw", "eps_lub", "cutoff_factor", "dt")]
+        "hamaker", "eps_vdw", "eps_lub", "cutoff_factor", "dt", "ec_ranges")]
+
+
+# optional parameters and their defaults (R18: electro-chemical forces over their own ranges)
+_OPTIONAL = {"ec_ranges": 0.0}
 
 
 PARAM_NAMES = [f[0] for f in _Params._fields_]
@@ -106,7 +110,7 @@ def _params(p: dict) -> _Params:
     L = p["L"]
     s.L[0], s.L[1], s.L[2] = float(L[0]), float(L[1]), float(L[2])
     for n in PARAM_NAMES[1:]:
-        setattr(s, n, float(p[n]))
+        setattr(s, n, float(p[n]) if n in p else _OPTIONAL[n])
     return s
 
 

@@ -37,6 +37,10 @@
  *       |F_nor| including the dashpot; xi_old = 0 at first contact;
  *   R12 every listed pair (|r| < c (a_i + a_j)) gets lubrication; repulsion and
  *       attraction are truncated at the same list.
+ *   R18 with ec_ranges = 1 the electro-chemical forces keep the ranges of
+ *       Fig. elch instead: repulsion while the surface distance d_ij < 20 lambda_D,
+ *       attraction while d_ij < 4 a0; lubrication stays on |r| < c (a_i + a_j);
+ *       the pair set is every pair inside any of these ranges.
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no FMA contraction, so
  * the pair test r^2 < r_c^2 is evaluated as written).
@@ -69,6 +73,7 @@ typedef struct {
     double eps_lub;       /* lubrication regularisation epsilon */
     double cutoff_factor; /* pair listed iff |r| < cutoff_factor * (a_i + a_j) */
     double dt;            /* time step */
+    double ec_ranges;     /* 1: electro-chemical forces over their own ranges (R18) */
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
@@ -154,11 +159,33 @@ void orc_min_image(const orc_params *p, double delta, const double *xa, const do
     r[2] = dz;
 }
 
-/* Listed pair test, |r| < cutoff_factor (a_a + a_b), compared on squares. */
+/* Ranges of the electro-chemical forces in surface distance (Fig. elch):     */
+/* repulsion below 20 lambda_D, attraction below 4 a0; 0 for a force that is  */
+/* off.  Only with ec_ranges (R18).                                           */
+static double repulsion_range(const orc_params *p)
+{
+    return (p->F_ER != 0.0 && p->lambda_D > 0.0) ? 20.0 * p->lambda_D : 0.0;
+}
+
+static double attraction_range(const orc_params *p) { return p->hamaker != 0.0 ? 4.0 * p->a0 : 0.0; }
+
+/* Listed pair test on squares: |r| < cutoff_factor (a_a + a_b), or with      */
+/* ec_ranges |r| < max(cutoff_factor (a_a + a_b), a_a + a_b + longest range).  */
+static double pair_cutoff(const orc_params *p, double aa, double ab)
+{
+    double rc = p->cutoff_factor * (aa + ab);
+    if (p->ec_ranges != 0.0) {
+        double rr = repulsion_range(p), ra = attraction_range(p);
+        double ext = (aa + ab) + (rr > ra ? rr : ra);
+        if (ext > rc) rc = ext;
+    }
+    return rc;
+}
+
 static int pair_listed(const orc_params *p, const double *r, double aa, double ab)
 {
     double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
-    double rc = p->cutoff_factor * (aa + ab);
+    double rc = pair_cutoff(p, aa, ab);
     return r2 < rc * rc;
 }
 
@@ -212,7 +239,7 @@ int64_t orc_pairs_brute(const orc_params *p, int64_t N, const double *x, const d
 /* ------------------------------------------------------------------------- */
 void orc_cell_dims(const orc_params *p, double a_max, int32_t *n)
 {
-    double rc = p->cutoff_factor * 2.0 * a_max * (1.0 + 1e-9);
+    double rc = pair_cutoff(p, a_max, a_max) * (1.0 + 1e-9);
     for (int d = 0; d < 3; ++d) {
         n[d] = (int32_t)floor(p->L[d] / rc);
         if (n[d] < 1) n[d] = 1;
@@ -589,6 +616,14 @@ void orc_pair_eval(const orc_params *p, double ai, double aj, const double *r, c
         for (int b = 0; b < 12; ++b) acc += R[a][b] * V[b];
         FL[a] = -acc + strain[a];
     }
+    /* R18: with the electro-chemical ranges the list is longer than the
+     * lubrication range; lubrication acts only inside |r| < c (a_i + a_j) */
+    if (p->ec_ranges != 0.0) {
+        double r2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+        double rl = p->cutoff_factor * (ai + aj);
+        if (!(r2 < rl * rl))
+            for (int a = 0; a < 12; ++a) FL[a] = 0.0;
+    }
     for (int a = 0; a < 12; ++a) out[a] = FL[a];
 
     /* true relative velocity u_j - u_i of the image pair: the ambient flow
@@ -637,15 +672,20 @@ void orc_pair_eval(const orc_params *p, double ai, double aj, const double *r, c
 
     /* --- electro-chemical: repulsion eq. (rep) + attraction eq. (att) */
     double abar = 2.0 * ai * aj / (ai + aj);
+    int rep_on = 1, att_on = 1;
+    if (p->ec_ranges != 0.0) { /* R18: each force over its own range */
+        rep_on = h < repulsion_range(p);
+        att_on = h < attraction_range(p);
+    }
     double FR = 0.0;
-    if (p->F_ER != 0.0) {
+    if (p->F_ER != 0.0 && rep_on) {
         if (h >= 0.0)
             FR = -p->F_ER * (abar / p->a0) * (p->lambda_D > 0.0 ? exp(-h / p->lambda_D) : 0.0);
         else
             FR = -p->F_ER * (abar / p->a0);
     }
     double FA = 0.0;
-    if (p->hamaker != 0.0) {
+    if (p->hamaker != 0.0 && att_on) {
         double eps = p->eps_vdw * abar;
         if (h >= 0.0)
             FA = p->hamaker * abar / (12.0 * (h * h + eps * eps));

@@ -576,3 +576,67 @@ def test_lees_edwards_invariance_both_faces(face):
     assert res[0][4] == res[1][4] == 1
     for k in range(3):
         assert rel(res[1][k], res[0][k]) < 1e-9
+
+
+# ---------------------------------------------------------------------------------------------
+# R18: electro-chemical forces over their own ranges (Fig. elch: repulsion while the surface
+# distance is below 20 lambda_D, attraction while it is below 4 a0), lubrication kept on
+# |r| < c (a_i + a_j).  Closed forms of eqs. (rep) and (att) beyond the lubrication range,
+# the switch-offs at the range ends, the pair set by brute force against the plain distance
+# definition, and the cell search on the longer cutoff.
+# ---------------------------------------------------------------------------------------------
+def test_ec_ranges_closed_forms():
+    ai, aj = 1.0, 1.4
+    abar = 2 * ai * aj / (ai + aj)
+    n = unit([0.3, -0.2, 0.9])
+    up_i, up_j = np.array([0.1, -0.3, 0.2]), np.array([-0.2, 0.05, 0.4])
+    wi, wj = np.array([0.3, 0.1, -0.2]), np.array([-0.1, 0.2, 0.5])
+
+    def ev(pp, h):
+        return oracle.pair_eval(pp, ai, aj, (ai + aj + h) * n, up_i, up_j, wi, wj)
+
+    # repulsion only, beyond the lubrication range (d* = 2 h / (a_i + a_j) > 0.2)
+    p = params(F_ER=2.0, lambda_D=0.05, a0=1.0, hamaker=0.0, ec_ranges=1.0)
+    for h in (0.3, 0.7, 0.99):
+        e = ev(p, h)
+        assert np.all(e["FL_i"] == 0.0) and np.all(e["TL_i"] == 0.0) and np.all(e["TL_j"] == 0.0)
+        assert np.all(e["SL"] == 0.0) and not e["contact"]
+        assert rel(e["FE_i"], -2.0 * abar * math.exp(-h / 0.05) * n) < 1e-12   # h from |r| - s
+        assert rel(e["SE"], np.outer((ai + aj + h) * n, e["FE_i"])) < 1e-14
+    assert np.all(ev(p, 1.0 + 1e-12)["FE_i"] == 0.0)           # 20 lambda_D = 1.0
+    # inside the lubrication range nothing changes against the default reading (R12)
+    p0 = params(F_ER=2.0, lambda_D=0.05, a0=1.0)
+    for h in (0.01, 0.2):
+        e1, e0 = ev(p, h), ev(p0, h)
+        for k in ("FL_i", "TL_i", "TL_j", "FE_i", "SL", "SE"):
+            assert np.array_equal(e1[k], e0[k])
+    # attraction only (F_ER = 0), eq. (att), up to 4 a0
+    pa = params(F_ER=0.0, hamaker=0.5, eps_vdw=0.01, a0=1.0, ec_ranges=1.0)
+    eps = 0.01 * abar
+    for h in (0.5, 2.0, 3.9):
+        e = ev(pa, h)
+        assert np.all(e["FL_i"] == 0.0)
+        assert rel(e["FE_i"], 0.5 * abar / (12 * (h * h + eps * eps)) * n) < 1e-14
+    assert np.all(ev(pa, 4.0 + 1e-12)["FE_i"] == 0.0)
+
+
+def test_ec_ranges_pair_set_and_cells():
+    w = synth.config_small()
+    p = dict(w.params, hamaker=0.02, ec_ranges=1.0)
+    # longest range 4 a0 = 4: a pair is listed iff |r| < max(1.1 s, s + 4), s = a_i + a_j
+    N = 300
+    x, rad = w.x[:N], w.rad[:N]
+    delta = 3.21
+    b = oracle.pairs_brute(p, x, rad, delta)
+    ref = []
+    for i in range(N):
+        for j in range(i + 1, N):
+            r = oracle.min_image(p, delta, x[i], x[j])
+            s = rad[i] + rad[j]
+            if np.dot(r, r) < max(1.1 * s, s + 4.0) ** 2:
+                ref.append((i, j))
+    assert len(ref) > 10 * len(oracle.pairs_brute(w.params, x, rad, delta))
+    assert np.array_equal(b, np.asarray(ref, np.int32).reshape(-1, 2))
+    dims = oracle.cell_dims(p, rad.max())
+    assert np.all(dims == np.floor(np.asarray(p["L"]) / ((2 * rad.max() + 4.0) * (1 + 1e-9))).astype(int))
+    assert np.array_equal(oracle.pairs_cells(p, w.x, w.rad, delta), oracle.pairs_brute(p, w.x, w.rad, delta))
