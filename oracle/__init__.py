@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dss_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libdss_oracle.so")
 
-PAIR_OUT = 61
+PAIR_OUT = 67
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -44,11 +44,12 @@ def build() -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double * 3)] + [(n, ctypes.c_double) for n in (
         "shear_rate", "eta0", "rho", "kn", "kt", "gamma_n", "mu", "F_ER", "lambda_D", "a0",
-        "hamaker", "eps_vdw", "eps_lub", "cutoff_factor", "dt", "ec_ranges")]
+        "hamaker", "eps_vdw", "eps_lub", "cutoff_factor", "dt", "ec_ranges", "kr", "mu_r")]
 
 
-# optional parameters and their defaults (R18: electro-chemical forces over their own ranges)
-_OPTIONAL = {"ec_ranges": 0.0}
+# optional parameters and their defaults (R18: electro-chemical forces over their own ranges;
+# R19: rolling resistance, off at k_r = 0)
+_OPTIONAL = {"ec_ranges": 0.0, "kr": 0.0, "mu_r": 0.0}
 
 
 PARAM_NAMES = [f[0] for f in _Params._fields_]
@@ -83,11 +84,11 @@ def lib():
         "orc_lub_strain_terms": (None, [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _c_double_p,
                                         _c_double_p]),
         "orc_pair_eval": (None, [P, ctypes.c_double, ctypes.c_double, _c_double_p, _c_double_p, _c_double_p,
-                                 _c_double_p, _c_double_p, _c_double_p, _c_double_p]),
+                                 _c_double_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p]),
         "orc_forces": (ctypes.c_int64, [P, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
                                         ctypes.c_int64, ctypes.c_int, ctypes.c_int64, _c_int32_p, _c_double_p,
-                                        ctypes.c_int64, _c_int32_p, _c_double_p, _c_int64_p, _c_double_p,
-                                        _c_double_p, _c_double_p]),
+                                        _c_double_p, ctypes.c_int64, _c_int32_p, _c_double_p, _c_double_p,
+                                        _c_int64_p, _c_double_p, _c_double_p, _c_double_p]),
         "orc_kick_drift": (None, [P, ctypes.c_int64, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p,
                                   _c_double_p, _c_double_p, _c_double_p, _c_double_p]),
         "orc_finish": (None, [P, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
@@ -232,17 +233,18 @@ def lub_strain_terms(p, ai, aj, h, n) -> np.ndarray:
     return out
 
 
-def pair_eval(p, ai, aj, r, upi, upj, wi, wj, xi_old=(0.0, 0.0, 0.0)) -> dict:
-    """One listed pair; velocities u' are fluctuations u - U_inf(x), w raw angular velocities."""
+def pair_eval(p, ai, aj, r, upi, upj, wi, wj, xi_old=(0.0, 0.0, 0.0), xr_old=(0.0, 0.0, 0.0)) -> dict:
+    """One listed pair; velocities u' are fluctuations u - U_inf(x), w raw angular velocities;
+    xi_old, xr_old: stored tangential and rolling stretches."""
     out = np.zeros(PAIR_OUT)
     lib().orc_pair_eval(ctypes.byref(_params(p)), float(ai), float(aj), _d(_f64(r)), _d(_f64(upi)),
-                        _d(_f64(upj)), _d(_f64(wi)), _d(_f64(wj)), _d(_f64(xi_old)), _d(out))
+                        _d(_f64(upj)), _d(_f64(wi)), _d(_f64(wj)), _d(_f64(xi_old)), _d(_f64(xr_old)), _d(out))
     return {
         "FL_i": out[0:3], "FL_j": out[3:6], "TL_i": out[6:9], "TL_j": out[9:12],
         "FC_i": out[12:15], "FC_j": out[15:18], "TC_i": out[18:21], "TC_j": out[21:24],
         "FE_i": out[24:27], "FE_j": out[27:30],
         "SL": out[30:39].reshape(3, 3), "SC": out[39:48].reshape(3, 3), "SE": out[48:57].reshape(3, 3),
-        "xi": out[57:60], "contact": bool(out[60] != 0.0),
+        "xi": out[57:60], "contact": bool(out[60] != 0.0), "xr": out[61:64], "TR_i": out[64:67],
     }
 
 
@@ -251,9 +253,14 @@ def pair_eval(p, ai, aj, r, upi, upj, wi, wj, xi_old=(0.0, 0.0, 0.0)) -> dict:
 # ----------------------------------------------------------------------------------------------
 @dataclass
 class History:
-    """Map {(a, b), a < b} -> xi (tangential stretch oriented for (a, b)), sorted by (a, b)."""
+    """Map {(a, b), a < b} -> xi (tangential stretch oriented for (a, b)) and xr (rolling
+    stretch, the same from either side; zeros without rolling resistance), sorted by (a, b)."""
     pairs: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int32))
     xi: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    xr: np.ndarray | None = None
+
+    def rolling(self):
+        return np.zeros_like(self.xi) if self.xr is None else self.xr
 
     def as_dict(self):
         return {(int(a), int(b)): self.xi[k] for k, (a, b) in enumerate(self.pairs)}
@@ -271,6 +278,7 @@ def forces(p, x, u, w, rad, step, history: History | None = None, use_cells=Fals
     history = history or History()
     hp = np.ascontiguousarray(history.pairs, np.int32).reshape(-1, 2)
     hx = _f64(history.xi, (-1, 3))
+    hr = _f64(history.rolling(), (-1, 3))
     hcap = max(16, 8 * N)
     F = np.zeros((N, 3))
     T = np.zeros((N, 3))
@@ -278,15 +286,16 @@ def forces(p, x, u, w, rad, step, history: History | None = None, use_cells=Fals
     while True:
         hp_new = np.zeros((hcap, 2), np.int32)
         hx_new = np.zeros((hcap, 3))
+        hr_new = np.zeros((hcap, 3))
         nh = ctypes.c_int64(0)
         np_ = lib().orc_forces(ctypes.byref(_params(p)), N, _d(x), _d(u), _d(w), _d(rad), int(step),
-                               int(bool(use_cells)), len(hp), _i32(hp), _d(hx), hcap, _i32(hp_new), _d(hx_new),
-                               ctypes.byref(nh), _d(F), _d(T), _d(S))
+                               int(bool(use_cells)), len(hp), _i32(hp), _d(hx), _d(hr), hcap, _i32(hp_new),
+                               _d(hx_new), _d(hr_new), ctypes.byref(nh), _d(F), _d(T), _d(S))
         if np_ >= 0:
             break
         hcap = int(nh.value)
     k = int(nh.value)
-    return F, T, S.reshape(3, 3), History(hp_new[:k].copy(), hx_new[:k].copy()), int(np_)
+    return F, T, S.reshape(3, 3), History(hp_new[:k].copy(), hx_new[:k].copy(), hr_new[:k].copy()), int(np_)
 
 
 @dataclass
@@ -303,7 +312,8 @@ class State:
 
     def copy(self):
         return State(self.x.copy(), self.u.copy(), self.w.copy(), self.alpha.copy(), self.alpha_w.copy(),
-                     self.rad.copy(), self.step, History(self.history.pairs.copy(), self.history.xi.copy()))
+                     self.rad.copy(), self.step, History(self.history.pairs.copy(), self.history.xi.copy(),
+                                                         self.history.rolling().copy()))
 
 
 def ambient_velocity(p, x):

@@ -37,6 +37,12 @@
  *       |F_nor| including the dashpot; xi_old = 0 at first contact;
  *   R12 every listed pair (|r| < c (a_i + a_j)) gets lubrication; repulsion and
  *       attraction are truncated at the same list.
+ *   R19 rolling resistance (Appendix roll), with k_r > 0: a second spring per
+ *       contact, xi^r* = T(xi^r_old + u_r dt) with u_r = a_ij (n x w_i - n x w_j),
+ *       a_ij = 2 a_i a_j / (a_i + a_j), capped when |xi^r*| >= mu_r |F_nor| / k_r
+ *       (the Coulomb limitation, with its own coefficient mu_r); torques
+ *       T_i = a_ij n x k_r xi^r*, T_j = -T_i; no force and no stress (the
+ *       pseudo-force only drives the torque); xi^r_old = 0 at first contact.
  *   R18 with ec_ranges = 1 the electro-chemical forces keep the ranges of
  *       Fig. elch instead: repulsion while the surface distance d_ij < 20 lambda_D,
  *       attraction while d_ij < 4 a0; lubrication stays on |r| < c (a_i + a_j);
@@ -74,6 +80,8 @@ typedef struct {
     double cutoff_factor; /* pair listed iff |r| < cutoff_factor * (a_i + a_j) */
     double dt;            /* time step */
     double ec_ranges;     /* 1: electro-chemical forces over their own ranges (R18) */
+    double kr;            /* rolling spring stiffness k_r (0: no rolling resistance, R19) */
+    double mu_r;          /* rolling Coulomb coefficient (R19) */
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
@@ -578,18 +586,20 @@ void orc_lub_strain_terms(const orc_params *p, double ai, double aj, double h, c
 /* ------------------------------------------------------------------------- */
 /* One listed pair (i, j): r = x_j - x_i (nearest image), fluctuation         */
 /* velocities u' = u - U_inf(x) (own wrapped position), raw angular           */
-/* velocities w.  xi_old: stored tangential stretch of this pair (zeros if    */
-/* none).  Output layout (61 doubles):                                        */
+/* velocities w.  xi_old, xr_old: stored tangential and rolling stretches of */
+/* this pair (zeros if none).  Output layout (67 doubles):                    */
 /*   [0:3] F^L_i  [3:6] F^L_j  [6:9] T^L_i  [9:12] T^L_j                       */
 /*   [12:15] F^C_i [15:18] F^C_j [18:21] T^C_i [21:24] T^C_j                   */
 /*   [24:27] F^E_i [27:30] F^E_j                                              */
 /*   [30:39] S^L  [39:48] S^C  [48:57] S^E   (row-major 3x3)                  */
 /*   [57:60] xi_new  [60] 1 if in contact (d_ij < 0) else 0                   */
+/*   [61:64] xr_new  [64:67] rolling torque on i (included in T^C_i, T^C_j)   */
 /* ------------------------------------------------------------------------- */
-#define ORC_PAIR_OUT 61
+#define ORC_PAIR_OUT 67
 
 void orc_pair_eval(const orc_params *p, double ai, double aj, const double *r, const double *upi,
-                   const double *upj, const double *wi, const double *wj, const double *xi_old, double *out)
+                   const double *upj, const double *wi, const double *wj, const double *xi_old,
+                   const double *xr_old, double *out)
 {
     memset(out, 0, ORC_PAIR_OUT * sizeof(double));
     double dist = sqrt(dot3(r, r));
@@ -668,6 +678,33 @@ void orc_pair_eval(const orc_params *p, double ai, double aj, const double *r, c
             out[57 + a] = xi[a];
         }
         out[60] = 1.0;
+
+        /* --- rolling resistance, Appendix roll (R19) */
+        if (p->kr > 0.0) {
+            double aij = 2.0 * ai * aj / (ai + aj);
+            double nwi[3], nwj[3];
+            cross3(n, wi, nwi);
+            cross3(n, wj, nwj);
+            double xr[3];
+            for (int a = 0; a < 3; ++a) xr[a] = xr_old[a] + aij * (nwi[a] - nwj[a]) * p->dt;
+            double xrn = dot3(xr, n);
+            for (int a = 0; a < 3; ++a) xr[a] -= xrn * n[a]; /* T (xi^r_old + u_r dt) */
+            double fn_mag = sqrt(dot3(Fn, Fn));
+            double cap = p->mu_r * fn_mag / p->kr;
+            double xm = sqrt(dot3(xr, xr));
+            if (xm >= cap && xm > 0.0)
+                for (int a = 0; a < 3; ++a) xr[a] *= cap / xm;
+            double Fr[3], Tr[3];
+            for (int a = 0; a < 3; ++a) Fr[a] = p->kr * xr[a]; /* pseudo-force */
+            cross3(n, Fr, Tr);
+            for (int a = 0; a < 3; ++a) {
+                Tr[a] *= aij;
+                out[18 + a] += Tr[a];
+                out[21 + a] -= Tr[a];
+                out[61 + a] = xr[a];
+                out[64 + a] = Tr[a];
+            }
+        }
     }
 
     /* --- electro-chemical: repulsion eq. (rep) + attraction eq. (att) */
@@ -717,13 +754,14 @@ static int cmp_pair(const void *k, const void *e)
     return (x[1] > y[1]) - (x[1] < y[1]);
 }
 
-static const double *history_find(int64_t nh, const int32_t *hpair, const double *hxi, int32_t a, int32_t b)
+/* Index of the entry (a, b) in the sorted history, or -1. */
+static int64_t history_find(int64_t nh, const int32_t *hpair, int32_t a, int32_t b)
 {
-    if (nh <= 0) return NULL;
+    if (nh <= 0) return -1;
     int32_t key[2] = {a, b};
     const int32_t *hit = (const int32_t *)bsearch(key, hpair, (size_t)nh, 2 * sizeof(int32_t), cmp_pair);
-    if (!hit) return NULL;
-    return hxi + 3 * ((hit - hpair) / 2);
+    if (!hit) return -1;
+    return (int64_t)((hit - hpair) / 2);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -735,8 +773,8 @@ static const double *history_find(int64_t nh, const int32_t *hpair, const double
 /* ------------------------------------------------------------------------- */
 int64_t orc_forces(const orc_params *p, int64_t N, const double *x, const double *u, const double *w,
                    const double *rad, int64_t step, int use_cells, int64_t nh_old, const int32_t *hpair_old,
-                   const double *hxi_old, int64_t hcap, int32_t *hpair_new, double *hxi_new, int64_t *nh_new,
-                   double *F, double *T, double *Sigma)
+                   const double *hxi_old, const double *hxr_old, int64_t hcap, int32_t *hpair_new,
+                   double *hxi_new, double *hxr_new, int64_t *nh_new, double *F, double *T, double *Sigma)
 {
     double delta = orc_le_offset(p, step);
     int64_t cap = 16 * N + 16;
@@ -762,10 +800,10 @@ int64_t orc_forces(const orc_params *p, int64_t N, const double *x, const double
             upa[c] = u[3 * a + c] - Ua[c];
             upb[c] = u[3 * b + c] - Ub[c];
         }
-        const double *xo = history_find(nh_old, hpair_old, hxi_old, a, b);
+        int64_t e = history_find(nh_old, hpair_old, a, b);
         double zero[3] = {0.0, 0.0, 0.0};
-        orc_pair_eval(p, rad[a], rad[b], r, upa, upb, w + 3 * a, w + 3 * b, xo ? xo : zero,
-                      res + (size_t)k * ORC_PAIR_OUT);
+        orc_pair_eval(p, rad[a], rad[b], r, upa, upb, w + 3 * a, w + 3 * b, e >= 0 ? hxi_old + 3 * e : zero,
+                      (e >= 0 && hxr_old) ? hxr_old + 3 * e : zero, res + (size_t)k * ORC_PAIR_OUT);
     }
 
     /* per-particle terms: Stokes drag and torque, eq. (rst) (the Faxen
@@ -800,6 +838,8 @@ int64_t orc_forces(const orc_params *p, int64_t N, const double *x, const double
                 hpair_new[2 * nh] = a;
                 hpair_new[2 * nh + 1] = b;
                 for (int c = 0; c < 3; ++c) hxi_new[3 * nh + c] = o[57 + c];
+                if (hxr_new)
+                    for (int c = 0; c < 3; ++c) hxr_new[3 * nh + c] = o[61 + c];
             } else {
                 overflow = 1;
             }

@@ -640,3 +640,64 @@ def test_ec_ranges_pair_set_and_cells():
     dims = oracle.cell_dims(p, rad.max())
     assert np.all(dims == np.floor(np.asarray(p["L"]) / ((2 * rad.max() + 4.0) * (1 + 1e-9))).astype(int))
     assert np.array_equal(oracle.pairs_cells(p, w.x, w.rad, delta), oracle.pairs_brute(p, w.x, w.rad, delta))
+
+
+# ---------------------------------------------------------------------------------------------
+# R19: rolling resistance (Appendix roll).  With a_i w_i + a_j w_j = 0 the contact does not
+# slide, and a constant rolling velocity u_r = a_ij n x (w_i - w_j) loads the rolling spring
+# linearly until the Coulomb limit mu_r |F_nor| / k_r; the torques are a_ij n x k_r xi^r on i
+# and its opposite on j; no force, no stress.
+# ---------------------------------------------------------------------------------------------
+def test_rolling_spring_sequence():
+    ai, aj = 1.0, 1.4
+    aij = 2 * ai * aj / (ai + aj)
+    p = params(shear_rate=0.0, eta0=0.0, F_ER=0.0, kr=0.05 * 4e5, mu_r=0.1, gamma_n=0.0)
+    n = unit([0.1, 0.3, 0.95])
+    h = -0.01
+    r = (ai + aj + h) * n
+    Om = np.cross(n, unit([1.0, -0.4, 0.2]))          # perpendicular to n
+    wi, wj = Om, -(ai / aj) * Om                       # a_i w_i + a_j w_j = 0: no sliding
+    ur = aij * np.cross(n, wi - wj)
+    cap = p["mu_r"] * p["kn"] * abs(h) / p["kr"]
+    xr = np.zeros(3)
+    xi = np.zeros(3)
+    saturated = False
+    for k in range(1, 400):
+        e = oracle.pair_eval(p, ai, aj, r, np.zeros(3), np.zeros(3), wi, wj, xi, xr)
+        assert e["contact"]
+        xi, xr = e["xi"], e["xr"]
+        assert np.linalg.norm(xi) < 1e-13                                     # no sliding
+        want = min(k * np.linalg.norm(ur) * p["dt"], cap)
+        assert abs(np.linalg.norm(xr) - want) <= 1e-12 * want
+        assert rel(xr, want * unit(ur)) < 1e-12
+        assert rel(e["TR_i"], aij * np.cross(n, p["kr"] * xr)) < 1e-13
+        assert rel(e["TC_j"], -e["TC_i"]) < 1e-12                # only the rolling torque acts
+        assert rel(e["TC_i"], e["TR_i"]) < 1e-12
+        assert rel(e["FC_i"], p["kn"] * h * n) < 1e-11           # no rolling force (h from |r|)
+        saturated = saturated or want == cap
+    assert saturated
+
+
+def test_rolling_symmetry_and_switch_off():
+    rng = np.random.default_rng(5)
+    ai, aj = 1.0, 1.4
+    pr = params(kr=0.1 * 4e5, mu_r=0.3)
+    p0 = params()
+    for _ in range(20):
+        n = unit(rng.normal(size=3))
+        r = (ai + aj - 0.02 * rng.random()) * n
+        upi, upj = rng.normal(size=3), rng.normal(size=3)
+        wi, wj = rng.normal(size=3), rng.normal(size=3)
+        xi0 = np.cross(n, rng.normal(size=3)) * 1e-6
+        xr0 = np.cross(n, rng.normal(size=3)) * 1e-6
+        a = oracle.pair_eval(pr, ai, aj, r, upi, upj, wi, wj, xi0, xr0)
+        b = oracle.pair_eval(pr, aj, ai, -r, upj, upi, wj, wi, -xi0, xr0)   # the same pair seen from j
+        assert rel(a["xr"], b["xr"]) < 1e-12                     # the rolling stretch has no orientation
+        assert rel(a["TR_i"], -b["TR_i"]) < 1e-12
+        assert rel(a["TC_i"], b["TC_j"]) < 1e-12 and rel(a["TC_j"], b["TC_i"]) < 1e-12
+        z = oracle.pair_eval(p0, ai, aj, r, upi, upj, wi, wj, xi0, xr0)   # k_r = 0: no rolling
+        assert np.all(z["xr"] == 0.0) and np.all(z["TR_i"] == 0.0)
+        for k in ("FC_i", "FC_j", "SC", "SL", "SE", "FL_i", "xi"):
+            assert np.array_equal(a[k], z[k])
+        assert rel(a["TC_i"] - a["TR_i"], z["TC_i"]) < 1e-12
+        assert rel(a["TC_j"] + a["TR_i"], z["TC_j"]) < 1e-12
