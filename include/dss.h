@@ -56,6 +56,13 @@ typedef enum { DSS_FP64 = 0, DSS_MIXED = 1 } dss_precision;
 
 /* Bits of dss_params.flags */
 #define DSS_FLAG_RECORD_PAIRS 1 /* keep the listed pairs of the last force evaluation (dss_get_pairs) */
+/* Electro-chemical forces over their own ranges (Fig. elch): repulsion, eq. rep, while the
+ * surface distance d_ij < 20 lambda_D, attraction, eq. att, while d_ij < 4 a0; lubrication
+ * stays on |r| < cutoff_factor (a_i + a_j).  The pair set (and the cell lattice) then covers
+ * |r| < max(cutoff_factor (a_i + a_j), a_i + a_j + the longest active range).  Without the
+ * flag both forces are truncated at the lubrication list.  Not with size-class stencils or
+ * the adjoint (DSS_ERR_ARG / DSS_ERR_STATE). */
+#define DSS_FLAG_EC_RANGES 2
 
 /* Physical and numerical parameters (units are the caller's; the defaults used by the
  * tests are eta0 = a_min = gdot = 1).  Ambient flow: simple shear U_inf = (gdot y, 0, 0),

@@ -287,12 +287,16 @@ struct SizeClasses {
 // reaching a cell twice: n_x >= 2 R_max + 2 (the window of a sheared row), n_y, n_z >=
 // 2 R_max + 1.  Cells are numbered class-major: ncls x n_x n_y n_z sort keys.
 bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, double amin, double cf,
-                double cell_scale, bool sized, SizeClasses &sc, std::string &why)
+                double rext, double cell_scale, bool sized, SizeClasses &sc, std::string &why)
 {
     sc = SizeClasses{};
     if (sized) {
         if (boxes.size() != 1) {
             why = "size-class stencils need a handle of one box";
+            return false;
+        }
+        if (rext > 0.0) {
+            why = "size-class stencils do not take the electro-chemical ranges";
             return false;
         }
         BoxParams &G = boxes[0];
@@ -327,7 +331,10 @@ bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, 
     int nrow = 0;
     for (size_t b = 0; b < boxes.size(); ++b) {
         BoxParams &G = boxes[b];
-        const double rc = cf * 2.0 * amax[b] * (1.0 + 1e-9) * cell_scale;
+        // largest pair cutoff of the box: c 2 a_max, or with the electro-chemical ranges
+        // max(c 2 a_max, 2 a_max + rext)
+        const double cut = rext > 0.0 ? std::max(cf * 2.0 * amax[b], 2.0 * amax[b] + rext) : cf * 2.0 * amax[b];
+        const double rc = cut * (1.0 + 1e-9) * cell_scale;
         for (int d = 0; d < 3; ++d) {
             G.nc[d] = std::max(1, (int)std::floor(G.L[d] / rc));
             G.cw[d] = G.L[d] / (double)G.nc[d];
@@ -364,7 +371,8 @@ dss_status setup_lattice(dss_handle *h)
     std::string why;
     SizeClasses sc;
     const bool sized = h->tune.sized != 0;
-    if (!lattice_of(h->boxes, h->box_amax, h->a_min, h->prm.cutoff_factor, h->tune.cell_scale, sized, sc, why))
+    if (!lattice_of(h->boxes, h->box_amax, h->a_min, h->prm.cutoff_factor, h->P.ec ? h->P.rext : 0.0,
+                    h->tune.cell_scale, sized, sc, why))
         return fail(h, DSS_ERR_BOX, why);
     free_lattice(h);
     const int B = h->nbox;
@@ -839,13 +847,32 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     P.N = (int)N;
     P.M = p.capacity > 0 ? p.capacity : paper_capacity(a_max, a_min);
     P.record_pairs = (p.flags & DSS_FLAG_RECORD_PAIRS) ? 1 : 0;
-    P.pair_cap = P.record_pairs ? 32 * N + 64 : 0;
+    // electro-chemical ranges (Fig. elch): repulsion below 20 lambda_D, attraction below 4 a0
+    P.ec = (p.flags & DSS_FLAG_EC_RANGES) ? 1 : 0;
+    P.rep_rng = (p.F_ER != 0.0 && p.lambda_D > 0.0) ? 20.0 * p.lambda_D : 0.0;
+    P.att_rng = p.hamaker != 0.0 ? 4.0 * p.a0 : 0.0;
+    P.rext = P.ec ? std::max(P.rep_rng, P.att_rng) : 0.0;
+    // recorded pairs: 32 per particle, plus with the ranges the pairs of a uniform gas within
+    // the longest cutoff (N_b^2 / V_b x 4/3 pi r_c^3 per box, twice the expected count)
+    P.pair_cap = 0;
+    if (P.record_pairs) {
+        double extra = 0.0;
+        if (P.ec && P.rext > 0.0)
+            for (int b = 0; b < B; ++b) {
+                const double rc = 2.0 * box_amax[b] + P.rext;
+                const double V = boxes[b].L[0] * boxes[b].L[1] * boxes[b].L[2];
+                extra += (double)n_per_box[b] * (double)n_per_box[b] / V * (4.0 / 3.0) * kPi * rc * rc * rc;
+            }
+        const double cap = 32.0 * (double)N + 64.0 + std::min(extra, 0.5 * (double)N * (double)N);
+        P.pair_cap = (long long)std::min(cap, 2.0e9);
+    }
     // the lattice is checked before anything is freed or allocated
     {
         std::vector<BoxParams> trial = boxes;
         std::string why;
         SizeClasses sc;
-        if (!lattice_of(trial, box_amax, a_min, p.cutoff_factor, h->tune.cell_scale, h->tune.sized != 0, sc, why))
+        if (!lattice_of(trial, box_amax, a_min, p.cutoff_factor, P.ec ? P.rext : 0.0, h->tune.cell_scale,
+                        h->tune.sized != 0, sc, why))
             return fail(h, DSS_ERR_BOX, why);
     }
 
@@ -958,7 +985,8 @@ dss_status dss_set_tuning(dss_handle *h, const dss_tuning *t)
         std::vector<BoxParams> trial = h->boxes;
         std::string why;
         SizeClasses sc;
-        if (!lattice_of(trial, h->box_amax, h->a_min, h->prm.cutoff_factor, t->cell_scale, t->sized != 0, sc, why))
+        if (!lattice_of(trial, h->box_amax, h->a_min, h->prm.cutoff_factor, h->P.ec ? h->P.rext : 0.0,
+                        t->cell_scale, t->sized != 0, sc, why))
             return fail(h, DSS_ERR_BOX, why);
     }
     const bool lattice = t->cell_scale != h->tune.cell_scale || t->tile_scale != h->tune.tile_scale ||
@@ -1474,6 +1502,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     dss_status s = require_loaded(h);
     if (s) return s;
     if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "the adjoint runs on single-box handles");
+    if (h->P.ec) return fail(h, DSS_ERR_STATE, "the adjoint does not take the electro-chemical ranges");
     if (h->vel_is_half)
         return fail(h, DSS_ERR_STATE, "the adjoint starts from a state with forces at u^n: call it right after "
                                       "dss_set_particles or dss_compute_forces");

@@ -50,6 +50,9 @@ struct DevParams {
     int ncls;                       // size classes (stencil radius of class k: k + 1 cells)
     int wave_cls;                   // classes from this one up take a wavefront per particle
     double cls_mul;                 // class of radius a: floor(a cls_mul)
+    int ec;                         // 1: electro-chemical forces over their own ranges
+    double rext;                    // with ec: longest active range (pair set |r| < max(c s, s + rext))
+    double rep_rng, att_rng;        // with ec: surface-distance ranges of repulsion and attraction
 };
 
 // One box: its geometry, shear rate, cell lattice and its ranges in the global numbering
@@ -150,6 +153,7 @@ __device__ __forceinline__ bool listed(const DevParams &P, double dx, double dy,
 #pragma clang fp contract(off)
     r2 = (dx * dx + dy * dy) + dz * dz;
     double rc = P.cf * (aa + ab);
+    if (P.ec) rc = fmax(rc, (aa + ab) + P.rext);
     return r2 < rc * rc;
 }
 
@@ -157,7 +161,7 @@ __device__ __forceinline__ bool listed(const DevParams &P, double dx, double dy,
 // shifts (y face sy with its x offset sxd, x period sx, z period sz), added in the order of
 // the general formula, so that r2 is bit-identical to min_image + listed.
 __device__ __forceinline__ bool image_listed(const double4 &Xi, const double4 &Xj, double sy, double sxd, double sx,
-                                             double sz, double cf)
+                                             double sz, double cf, double rext)
 {
 #pragma clang fp contract(off)
     double dx = Xj.x - Xi.x, dy = Xj.y - Xi.y, dz = Xj.z - Xi.z;
@@ -166,7 +170,8 @@ __device__ __forceinline__ bool image_listed(const double4 &Xi, const double4 &X
     dx = dx + sx;
     dz = dz + sz;
     const double r2 = (dx * dx + dy * dy) + dz * dz;
-    const double rc = cf * (Xi.w + Xj.w);
+    double rc = cf * (Xi.w + Xj.w);
+    if (rext > 0.0) rc = fmax(rc, (Xi.w + Xj.w) + rext);
     return r2 < rc * rc;
 }
 
@@ -569,8 +574,22 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
     double dstar = 2.0 * h_d / s_d;
     dstar = dstar > 0.0 ? dstar : 0.0;
     const double g_d = dstar + P.eps_lub;
-    const Real invg = (Real)rcp_nr(g_d);
-    const Real lg = -log_r((Real)g_d);
+    Real invg = (Real)rcp_nr(g_d);
+    Real lg = -log_r((Real)g_d);
+    // electro-chemical ranges: the list reaches beyond the lubrication range, where every
+    // lubrication coefficient is zero; each electro-chemical force has its own range
+    bool rep_on = true, att_on = true;
+    if (P.ec) {
+#pragma clang fp contract(off)
+        const double r2 = (dx_d * dx_d + dy_d * dy_d) + dz_d * dz_d;
+        const double rl = P.cf * s_d;
+        if (!(r2 < rl * rl)) {
+            invg = (Real)0.0;
+            lg = (Real)0.0;
+        }
+        rep_on = h_d < P.rep_rng;
+        att_on = h_d < P.att_rng;
+    }
     const Real dux = (Real)((Vj.x - gd_d * yj) - (Vi.x - gd_d * yi));
     const Real duy = (Real)(Vj.y - Vi.y);
     const Real duz = (Real)(Vj.z - Vi.z);
@@ -626,10 +645,10 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
     // ---------------- electro-chemical (central): repulsion eq. rep, attraction eq. att
     const Real abar = (Real)2.0 * ai * aj * is;
     Real fe = (Real)0.0;
-    if (P.fer != 0.0)
+    if (P.fer != 0.0 && rep_on)
         fe -= (Real)P.fer_a0 * abar *
               (h >= (Real)0.0 ? (P.lamd > 0.0 ? exp_r(-h * (Real)P.inv_lamd) : (Real)0.0) : (Real)1.0);
-    if (P.ham != 0.0) {
+    if (P.ham != 0.0 && att_on) {
         const Real e = (Real)P.eps_vdw * abar;
         fe += (Real)P.ham * abar * rcp_r((Real)12.0 * ((h >= (Real)0.0 ? h * h : (Real)0.0) + e * e));
     }
@@ -1324,7 +1343,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
             const double sxd = cross > 0 ? delta : (cross < 0 ? -delta : 0.0);
             const double sx = (double)((int)((wd >> 28) & 7u) - 4) * G.L[0];
             const double sz = (wd >> 31) ? G.L[2] : 0.0;
-            return image_listed(V.sp[il], V.sp[jl], sy, sxd, sx, sz, P.cf);
+            return image_listed(V.sp[il], V.sp[jl], sy, sxd, sx, sz, P.cf, P.ec ? P.rext : 0.0);
         };
         unsigned long long bits = 0ull;
         int j = 0;

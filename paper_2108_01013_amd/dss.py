@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(_PKG, "libdss.so")
 
 DSS_FP64 = 0
 DSS_MIXED = 1
+DSS_ERR_CAPACITY = 3
 DSS_FLAG_RECORD_PAIRS = 1
+DSS_FLAG_EC_RANGES = 2
 
 STATUS = {0: "DSS_OK", 1: "DSS_ERR_ARG", 2: "DSS_ERR_HIP", 3: "DSS_ERR_CAPACITY", 4: "DSS_ERR_BOX",
           5: "DSS_ERR_UNSTABLE", 6: "DSS_ERR_STATE"}
@@ -130,7 +132,7 @@ def make_params(p: dict, precision: int = DSS_FP64, capacity: int = 0, flags: in
         setattr(s, n, float(p[n]))
     s.precision = int(precision)
     s.capacity = int(capacity)
-    s.flags = int(flags)
+    s.flags = int(flags) | (DSS_FLAG_EC_RANGES if p.get("ec_ranges") else 0)
     s.reserved = 0
     return s
 
@@ -170,8 +172,8 @@ class Simulation:
         self.N = 0
         self.precision = int(precision)
 
-    def _check(self, s):
-        if s != 0:
+    def _check(self, s, allow=()):
+        if s != 0 and s not in allow:
             msg = self.lib.dss_last_error(self.h)
             raise DssError(s, msg.decode() if msg else "")
 
@@ -250,9 +252,9 @@ class Simulation:
 
     def pairs(self):
         n = ctypes.c_int64(0)
-        cap = 32 * self.N + 64
-        buf = np.zeros((cap, 2), np.int32)
-        self._check(self.lib.dss_get_pairs(self.h, cap, ctypes.c_void_p(buf.ctypes.data), ctypes.byref(n)))
+        self._check(self.lib.dss_get_pairs(self.h, 0, None, ctypes.byref(n)), allow=(DSS_ERR_CAPACITY,))
+        buf = np.zeros((max(n.value, 1), 2), np.int32)
+        self._check(self.lib.dss_get_pairs(self.h, len(buf), ctypes.c_void_p(buf.ctypes.data), ctypes.byref(n)))
         p = buf[: n.value]
         return p[np.lexsort((p[:, 1], p[:, 0]))]
 

@@ -1,0 +1,85 @@
+"""Electro-chemical forces over their own ranges (DSS_FLAG_EC_RANGES; Fig. elch: repulsion
+while the surface distance is below 20 lambda_D, attraction below 4 a0) against the FP64
+oracle's reading R18, on an MI355X: pair sets bit-identical, forces / torques / stress /
+history within 1e-10 (FP64) or 1e-5 (mixed), in lockstep."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2108_01013_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_F = 1e-10
+TOL_MIXED = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_inf(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def ec_box():
+    w = synth.bidisperse_box(4000, 0.45, seed=11)
+    p = dict(w.params, hamaker=1e-3, F_ER=1.0, ec_ranges=True)
+    return synth.Workload("bidisperse N=4000 phi=0.45, attraction", w.x, w.rad, w.L, p)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ec_ranges_lockstep(ec_box, precision):
+    from paper_2108_01013_amd.dss import Simulation
+    w = ec_box
+    p = w.params
+    tol = TOL_F if precision == 0 else TOL_MIXED
+    say(f"case: electro-chemical ranges N=4000 precision={precision}")
+    sim = Simulation(p, record_pairs=True, precision=precision)
+    sim.set_particles(w.x, w.rad)
+    dims = sim.cells()[0]
+    assert np.array_equal(dims, oracle.cell_dims(p, w.rad.max()))
+    # the pair set reaches 4 a0 beyond contact: far more pairs than the lubrication list
+    n_lub = len(oracle.pairs_brute(dict(p, ec_ranges=False), w.x, w.rad, 0.0))
+    assert sim.info()["n_pairs"] > 10 * n_lub
+    sim.step(2)
+    hp, hx = sim.history()
+    for k in range(3):
+        s = sim.state()
+        a, aw = oracle.accelerations(p, w.rad, s["F"], s["T"])
+        st = oracle.State(s["x"], s["u"], s["w"], a, aw, w.rad.copy(), 2 + k,
+                          oracle.History(hp.astype(np.int32), hx))
+        x_o = oracle.kick_drift(p, st)[0]
+        sim.step(1)
+        s1 = sim.state()
+        uh, wh = sim.eval_velocities()
+        assert np.array_equal(s1["x"], x_o)
+        delta = oracle.le_offset(p, 3 + k)
+        assert np.array_equal(sim.pairs(), oracle.pairs_brute(p, s1["x"], w.rad, delta)), f"step {k}: pairs"
+        F, T, S, H, npairs = oracle.forces(p, s1["x"], uh, wh, w.rad, 3 + k, st.history)
+        assert rel_inf(s1["F"], F) < tol, f"step {k}: F {rel_inf(s1['F'], F)}"
+        assert rel_inf(s1["T"], T) < tol, f"step {k}: T {rel_inf(s1['T'], T)}"
+        last, _, _ = sim.read_stress()
+        assert rel_inf(last, S) < tol, f"step {k}: Sigma"
+        hp, hx = sim.history()
+        assert np.array_equal(hp, H.pairs)
+    sim.close()
+
+
+def test_ec_ranges_refusals(ec_box):
+    from paper_2108_01013_amd.dss import DssError, Simulation
+    w = ec_box
+    sim = Simulation(w.params)
+    sim.set_tuning(sized=True)
+    with pytest.raises(DssError):
+        sim.set_particles(w.x, w.rad)
+    sim.close()
+    sim = Simulation(w.params)
+    sim.set_particles(w.x, w.rad)
+    with pytest.raises(DssError):
+        sim.adjoint(4, 2, 2)
+    sim.close()
