@@ -225,7 +225,7 @@ def run_poly(args):
         sys.exit(1)
     tun = sim.tuning()
     sized = tun["sized"]
-    names = {"k_pairs": "k_pairs_sized", "k_pairs_rows": "k_pairs_sized_wave"} if sized else {}
+    names = {"k_pairs": "k_pairs_sized"} if sized else {}
     box = sim.box_info(0)
     ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2]) * int(box["size_classes"])
     # dominant pair kernel of the timed region

@@ -87,6 +87,8 @@ typedef struct {
     int32_t capacity;     /* history row capacity; 0 = the paper's estimate M(a_max, a_min) */
     int32_t flags;        /* DSS_FLAG_* */
     int32_t reserved;     /* must be 0 */
+    double k_roll;        /* rolling spring stiffness k_r of Appendix roll (0 = no rolling resistance) */
+    double mu_roll;       /* Coulomb coefficient of the rolling spring: |xi^r| <= mu_roll |F_nor| / k_r */
 } dss_params;
 
 /* Diagnostics of the most recent force evaluation. */
@@ -237,6 +239,12 @@ dss_status dss_get_cells(dss_handle *h, int32_t *dims, int64_t cap_cells, int32_
 /* Contact history after the last step: pairs (id_min, id_max) and xi (3 per pair, the
  * tangential stretch oriented from id_min to id_max), unordered; host pointers. */
 dss_status dss_get_history(dss_handle *h, int64_t cap, int32_t *pairs, double *xi, int64_t *n);
+
+/* Rolling stretches of the same contacts (Appendix roll: the spring on the rolling velocity
+ * u_r = a_ij (n x w_i - n x w_j), a_ij = 2 a_i a_j / (a_i + a_j); it has no orientation):
+ * pairs (id_min, id_max) and xr (3 per pair), unordered, host pointers.  Fails with
+ * DSS_ERR_STATE when k_roll = 0, DSS_ERR_CAPACITY when cap < *n (*n is the count). */
+dss_status dss_get_rolling_history(dss_handle *h, int64_t cap, int32_t *pairs, double *xr, int64_t *n);
 
 /* Diagnostics of the most recent force evaluation (synchronises).  For a batch handle the
  * counts are summed over the boxes (max_row_fill: the largest), cells and le_offset are

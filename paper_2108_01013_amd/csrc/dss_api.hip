@@ -44,7 +44,7 @@ struct dss_handle {
     std::vector<double> box_amax;     // largest radius per box
     double a_min = 0.0;               // smallest radius of all boxes
     std::vector<double> rad_host;     // radii by id (size-class counts of the stencil path)
-    int sized_grid[2] = {0, 0};       // workgroups of k_pairs_sized and k_pairs_sized_wave
+    int sized_grid[2] = {0, 0};       // lane and wavefront workgroups of k_pairs_sized
     double max_mean_row = 0.0;        // mean particles per cell row of the densest box
     dss_tuning tune{1.0, 1.0, 1, 1, 0, 0, {0, 0}};
     bool tune_pending = false;        // lattice to rebuild before the next time step
@@ -70,6 +70,7 @@ struct dss_handle {
     int *prev = nullptr;       // slot -> slot at the previous sort
     int *hkey[2] = {nullptr, nullptr}, *hcnt[2] = {nullptr, nullptr}, *hown[2] = {nullptr, nullptr};
     double *hxi[2] = {nullptr, nullptr};
+    double *hxr[2] = {nullptr, nullptr};  // rolling stretches (only with rolling resistance)
     int *pairs = nullptr;
     unsigned long long *pair_count = nullptr;
     DevClock *clk = nullptr;
@@ -157,10 +158,10 @@ void free_all(dss_handle *h)
     free_lattice(h);
     for (int k = 0; k < 2; ++k) {
         F(h->pa[k]); F(h->vel[k]); F(h->omg[k]);
-        F(h->hkey[k]); F(h->hcnt[k]); F(h->hown[k]); F(h->hxi[k]);
+        F(h->hkey[k]); F(h->hcnt[k]); F(h->hown[k]); F(h->hxi[k]); F(h->hxr[k]);
         h->pa[k] = h->vel[k] = h->omg[k] = nullptr;
         h->hkey[k] = h->hcnt[k] = h->hown[k] = nullptr;
-        h->hxi[k] = nullptr;
+        h->hxi[k] = h->hxr[k] = nullptr;
     }
     F(h->ft_own); F(h->ft_nb); F(h->ft_x); F(h->prev);
     F(h->cell); F(h->rank);
@@ -405,7 +406,10 @@ dss_status setup_lattice(dss_handle *h)
             for (double a : h->rad_host)
                 n_big += std::min((int)std::floor(a * sc.cls_mul), sc.ncls - 1) >= P.wave_cls ? 1 : 0;
             const int64_t n_lane = h->N - n_big;
-            const int g_wave = P.wave_cls < sc.ncls ? (int)std::min<int64_t>(std::max<int64_t>((n_big + 3) / 4, 1), 1024) : 0;
+            // wavefront workgroups in multiples of 8 (one per XCD), launched first
+            const int g_wave =
+                P.wave_cls < sc.ncls ? (int)std::min<int64_t>((std::max<int64_t>((n_big + 3) / 4, 1) + 7) / 8 * 8, 1024)
+                                     : 0;
             const int g_lane = (int)std::min<int64_t>(std::max<int64_t>((n_lane + kBlock - 1) / kBlock, 1), 4096 - g_wave);
             h->sized_grid[0] = g_lane;
             h->sized_grid[1] = g_wave;
@@ -471,10 +475,9 @@ dss_status setup_lattice(dss_handle *h)
         P.stage_cap = stage_cap;
         P.qcap = qcap;
     }
-    HIPTRY(hipFuncSetAttribute((const void *)k_pairs<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)h->tile_lds));
-    HIPTRY(hipFuncSetAttribute((const void *)k_pairs<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)h->tile_lds));
+    for (const void *k : {(const void *)k_pairs<double, false>, (const void *)k_pairs<float, false>,
+                          (const void *)k_pairs<double, true>, (const void *)k_pairs<float, true>})
+        HIPTRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->tile_lds));
     h->finish_r = (max_rows_box + 1023) / 1024;
     P.pstride = (std::max(nrow, max_rows_box) + 63) / 64 * 64;
     HIPTRY(dalloc(&h->count, ncell_pad));
@@ -499,6 +502,41 @@ dss_status setup_lattice(dss_handle *h)
 //   EVAL_INPLACE: pairs at the current state and order (velocities completed to u^n).
 enum EvalMode { EVAL_STEP = 0, EVAL_SORT = 1, EVAL_INPLACE = 2 };
 
+// The pair kernels of one evaluation: size-class stencils (lane and wavefront paths), or
+// the row tiles followed by the rows they deferred.  Real: FP64 or mixed arithmetic; Roll:
+// rolling resistance.
+template <typename Real, bool Roll>
+void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
+{
+    if (h->P.sized) {
+        TimedLaunch t(h, 3);
+        hipExtLaunchKernelGGL(k_pairs_sized<Real, Roll>, dim3(h->sized_grid[0] + h->sized_grid[1]), dim3(kBlock), 0,
+                              h->stream, t.e0, t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf],
+                              h->omg[buf], h->fb(), H, h->clk, h->partials, h->sized_grid[1], h->pairs,
+                              h->pair_count);
+        return;
+    }
+    {
+        TimedLaunch t(h, 3);
+        hipExtLaunchKernelGGL(k_pairs<Real, Roll>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0,
+                              t.e1, 0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
+                              h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, h->fb_rows,
+                              h->fb_count);
+    }
+    {
+        // deferred rows: workgroups striding over the list, as many as the rows deferred at
+        // the last synchronised evaluation (a few when that is unknown or none), one per row
+        // when every row takes the per-particle path
+        TimedLaunch t(h, 7);
+        const int hint = h->deferred_hint < 0 ? 64 : h->deferred_hint + h->deferred_hint / 4 + 8;
+        const int grid = h->tune.tiled ? std::min(h->nrow_total, hint) : h->nrow_total;
+        hipExtLaunchKernelGGL(k_pairs_rows<Real, Roll>, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P,
+                              h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(),
+                              H, h->clk, h->partials, h->pairs, h->pair_count, (const int *)h->fb_rows,
+                              (const int *)h->fb_count);
+    }
+}
+
 dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, bool finish)
 {
     HistView H;
@@ -510,64 +548,16 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, boo
     H.xi_new = h->hxi[1 - h->hh];
     H.cnt_new = h->hcnt[1 - h->hh];
     H.own_new = h->hown[1 - h->hh];
+    H.xr_old = h->hxr[h->hh];
+    H.xr_new = h->hxr[1 - h->hh];
     if (h->P.record_pairs) HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
-    if (h->P.sized) {
-        {
-            TimedLaunch t(h, 3);
-            if (h->prm.precision == DSS_MIXED)
-                hipExtLaunchKernelGGL(k_pairs_sized<float>, dim3(h->sized_grid[0]), dim3(kBlock), 0, h->stream, t.e0,
-                                      t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf],
-                                      h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count);
-            else
-                hipExtLaunchKernelGGL(k_pairs_sized<double>, dim3(h->sized_grid[0]), dim3(kBlock), 0, h->stream, t.e0,
-                                      t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf],
-                                      h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count);
-        }
-        if (h->sized_grid[1] > 0) {
-            TimedLaunch t(h, 7);
-            if (h->prm.precision == DSS_MIXED)
-                hipExtLaunchKernelGGL(k_pairs_sized_wave<float>, dim3(h->sized_grid[1]), dim3(kBlock), 0, h->stream,
-                                      t.e0, t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf],
-                                      h->omg[buf], h->fb(), H, h->clk, h->partials, h->sized_grid[0], h->pairs,
-                                      h->pair_count);
-            else
-                hipExtLaunchKernelGGL(k_pairs_sized_wave<double>, dim3(h->sized_grid[1]), dim3(kBlock), 0, h->stream,
-                                      t.e0, t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf],
-                                      h->omg[buf], h->fb(), H, h->clk, h->partials, h->sized_grid[0], h->pairs,
-                                      h->pair_count);
-        }
+    const bool roll = h->P.kr > 0.0;
+    if (h->prm.precision == DSS_MIXED) {
+        if (roll) launch_pair_kernels<float, true>(h, buf, H);
+        else launch_pair_kernels<float, false>(h, buf, H);
     } else {
-    {
-        TimedLaunch t(h, 3);
-        if (h->prm.precision == DSS_MIXED)
-            hipExtLaunchKernelGGL(k_pairs<float>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0, t.e1,
-                                  0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
-                                  h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, h->fb_rows,
-                                  h->fb_count);
-        else
-            hipExtLaunchKernelGGL(k_pairs<double>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0,
-                                  t.e1, 0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
-                                  h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, h->fb_rows,
-                                  h->fb_count);
-    }
-    {
-        // deferred rows: workgroups striding over the list, as many as the rows deferred at
-        // the last synchronised evaluation (a few when that is unknown or none), one per row
-        // when every row takes the per-particle path
-        TimedLaunch t(h, 7);
-        const int hint = h->deferred_hint < 0 ? 64 : h->deferred_hint + h->deferred_hint / 4 + 8;
-        const int grid = h->tune.tiled ? std::min(h->nrow_total, hint) : h->nrow_total;
-        if (h->prm.precision == DSS_MIXED)
-            hipExtLaunchKernelGGL(k_pairs_rows<float>, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P,
-                                  h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf],
-                                  h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count,
-                                  (const int *)h->fb_rows, (const int *)h->fb_count);
-        else
-            hipExtLaunchKernelGGL(k_pairs_rows<double>, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P,
-                                  h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf],
-                                  h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count,
-                                  (const int *)h->fb_rows, (const int *)h->fb_count);
-    }
+        if (roll) launch_pair_kernels<double, true>(h, buf, H);
+        else launch_pair_kernels<double, false>(h, buf, H);
     }
     if (!finish) return DSS_OK;
     TimedLaunch t(h, 4);
@@ -732,7 +722,8 @@ dss_status dss_get_timing(dss_handle *h, int kernel, double *total_ms, int64_t *
 static bool valid_params(const dss_params *p)
 {
     return (p->L[0] > 0 && p->L[1] > 0 && p->L[2] > 0) && p->dt > 0 && p->cutoff_factor > 0 && p->rho > 0 &&
-           p->a0 > 0 && p->reserved == 0 && p->capacity >= 0 &&
+           p->a0 > 0 && p->reserved == 0 && p->capacity >= 0 && p->k_roll >= 0 && p->mu_roll >= 0 &&
+           std::isfinite(p->k_roll) && std::isfinite(p->mu_roll) &&
            (p->precision == DSS_FP64 || p->precision == DSS_MIXED) && p->eps_lub > 0 &&
            std::isfinite(p->shear_rate);
 }
@@ -852,6 +843,8 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     P.rep_rng = (p.F_ER != 0.0 && p.lambda_D > 0.0) ? 20.0 * p.lambda_D : 0.0;
     P.att_rng = p.hamaker != 0.0 ? 4.0 * p.a0 : 0.0;
     P.rext = P.ec ? std::max(P.rep_rng, P.att_rng) : 0.0;
+    P.kr = p.k_roll;
+    P.mu_r = p.mu_roll;
     // recorded pairs: 32 per particle, plus with the ranges the pairs of a uniform gas within
     // the longest cutoff (N_b^2 / V_b x 4/3 pi r_c^3 per box, twice the expected count)
     P.pair_cap = 0;
@@ -892,6 +885,7 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
         HIPTRY(dalloc(&h->omg[k], N));
         HIPTRY(dalloc(&h->hkey[k], rows));
         HIPTRY(dalloc(&h->hxi[k], rows * 3));
+        if (P.kr > 0.0) HIPTRY(dalloc(&h->hxr[k], rows * 3));
         HIPTRY(dalloc(&h->hcnt[k], N));
         HIPTRY(dalloc(&h->hown[k], N));
     }
@@ -1216,11 +1210,14 @@ dss_status dss_get_cells(dss_handle *h, int32_t *dims, int64_t cap_cells, int32_
     return DSS_OK;
 }
 
-dss_status dss_get_history(dss_handle *h, int64_t cap, int32_t *pairs, double *xi, int64_t *n)
+// The committed contact history as (id_min, id_max, stretch) triples: the tangential
+// stretches (rolling = false) or the rolling ones.
+static dss_status export_history(dss_handle *h, int64_t cap, int32_t *pairs, double *xi, int64_t *n, bool rolling)
 {
     dss_status s = require_loaded(h);
     if (s) return s;
     if (!n) return fail(h, DSS_ERR_ARG, "null count");
+    if (rolling && !h->hxr[h->hh]) return fail(h, DSS_ERR_STATE, "no rolling resistance (k_roll = 0)");
     int *dp = nullptr;
     double *dxv = nullptr;
     const int64_t room = std::max<int64_t>(cap, 1);
@@ -1229,7 +1226,8 @@ dss_status dss_get_history(dss_handle *h, int64_t cap, int32_t *pairs, double *x
     HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
     const int grid = (int)((h->N + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_history_export, dim3(grid), dim3(kBlock), 0, h->stream, (int)h->N, h->P.M, h->hown[h->hh],
-                       h->hkey[h->hh], h->hxi[h->hh], h->hcnt[h->hh], (long long)cap, dp, dxv, h->pair_count);
+                       h->hkey[h->hh], rolling ? h->hxr[h->hh] : h->hxi[h->hh], h->hcnt[h->hh], (long long)cap, dp,
+                       dxv, h->pair_count);
     HIPTRY(hipGetLastError());
     unsigned long long cnt = 0;
     HIPTRY(hipMemcpyAsync(&cnt, h->pair_count, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
@@ -1245,6 +1243,16 @@ dss_status dss_get_history(dss_handle *h, int64_t cap, int32_t *pairs, double *x
     (void)hipFree(dp);
     (void)hipFree(dxv);
     return r;
+}
+
+dss_status dss_get_history(dss_handle *h, int64_t cap, int32_t *pairs, double *xi, int64_t *n)
+{
+    return export_history(h, cap, pairs, xi, n, false);
+}
+
+dss_status dss_get_rolling_history(dss_handle *h, int64_t cap, int32_t *pairs, double *xr, int64_t *n)
+{
+    return export_history(h, cap, pairs, xr, n, true);
 }
 
 dss_status dss_get_info(dss_handle *h, dss_info *info)
@@ -1503,6 +1511,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     if (s) return s;
     if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "the adjoint runs on single-box handles");
     if (h->P.ec) return fail(h, DSS_ERR_STATE, "the adjoint does not take the electro-chemical ranges");
+    if (h->P.kr > 0.0) return fail(h, DSS_ERR_STATE, "the adjoint does not take rolling resistance");
     if (h->vel_is_half)
         return fail(h, DSS_ERR_STATE, "the adjoint starts from a state with forces at u^n: call it right after "
                                       "dss_set_particles or dss_compute_forces");
@@ -1721,6 +1730,7 @@ std::vector<StatePart> state_parts(dss_handle *h, int cur, int hh)
             {h->hxi[hh], 3 * N * M * sizeof(double)},
             {h->hcnt[hh], N * sizeof(int)},
             {h->hown[hh], N * sizeof(int)},
+            {h->hxr[hh], h->hxr[hh] ? N * M * 3 * sizeof(double) : 0},
             {h->clk, sizeof(DevClock)},
             {h->sigma_last, 9 * B * sizeof(double)},
             {h->box_diag, 3 * B * sizeof(double)}};
@@ -1759,6 +1769,7 @@ dss_status dss_save_state(dss_handle *h, void *blob, size_t *bytes)
     size_t off = sizeof(hd);
     HIPTRY(hipStreamSynchronize(h->stream));
     for (auto &q : parts) {
+        if (!q.bytes) continue;
         HIPTRY(hipMemcpy(out + off, q.dev, q.bytes, hipMemcpyDeviceToHost));
         off += q.bytes;
     }
@@ -1786,6 +1797,7 @@ dss_status dss_load_state(dss_handle *h, const void *blob, size_t bytes)
     size_t off = sizeof(hd);
     HIPTRY(hipStreamSynchronize(h->stream));
     for (auto &q : parts) {
+        if (!q.bytes) continue;
         HIPTRY(hipMemcpy(q.dev, in + off, q.bytes, hipMemcpyHostToDevice));
         off += q.bytes;
     }

@@ -53,6 +53,7 @@ struct DevParams {
     int ec;                         // 1: electro-chemical forces over their own ranges
     double rext;                    // with ec: longest active range (pair set |r| < max(c s, s + rext))
     double rep_rng, att_rng;        // with ec: surface-distance ranges of repulsion and attraction
+    double kr, mu_r;                // rolling spring stiffness and Coulomb coefficient (kr = 0: off)
 };
 
 // One box: its geometry, shear rate, cell lattice and its ranges in the global numbering
@@ -542,6 +543,7 @@ struct PairOut {
     double Ti[3];   // torque on i
     double Tj[3];   // torque on j
     double xi[3];   // new tangential stretch, oriented i -> j
+    double xr[3];   // new rolling stretch (no orientation), with rolling resistance
     bool contact;
     bool capped;    // the Coulomb cap rescaled the stretch
 };
@@ -561,12 +563,12 @@ __device__ __forceinline__ float sqrt_r(float x) { return __builtin_sqrtf(x); }
 // differences (which cancel the large ambient-flow values) are formed in FP64 and rounded
 // once; the unit vector, coefficients, log/exp, contact model and stresslet are FP32; the
 // results are accumulated in FP64 by the caller.
-template <typename Real>
+template <typename Real, bool Roll = false>
 __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, double dx_d, double dy_d, double dz_d,
                                              double dist,
                                              double ai_d, double aj_d, double yi, double yj, const double4 &Vi,
                                              const double4 &Vj, const double4 &Wi, const double4 &Wj,
-                                             const double xo[3], double *S, PairOut &o)
+                                             const double xo[3], const double xro[3], double *S, PairOut &o)
 {
     // ---------------- FP64 in both modes: gap, lubrication argument, velocity differences
     const double h_d = dist - ai_d - aj_d;
@@ -709,6 +711,39 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
         Tj0 += aj * mx;
         Tj1 += aj * my;
         Tj2 += aj * mz;
+        if constexpr (Roll) {
+            // rolling resistance (Appendix roll): a second spring on the rolling velocity
+            // u_r = a_ij n x (w_i - w_j), a_ij = abar; the same Coulomb limitation with mu_r;
+            // torques T_i = a_ij n x k_r xi^r, T_j = -T_i, no force, no stress
+            const Real dwx = (Real)(Wi.x - Wj.x), dwy = (Real)(Wi.y - Wj.y), dwz = (Real)(Wi.z - Wj.z);
+            const Real urx = abar * (ny * dwz - nz * dwy), ury = abar * (nz * dwx - nx * dwz),
+                       urz = abar * (nx * dwy - ny * dwx);
+            Real rx = (Real)xro[0] + urx * dtR, ry = (Real)xro[1] + ury * dtR, rz = (Real)xro[2] + urz * dtR;
+            const Real rn = rx * nx + ry * ny + rz * nz;
+            rx -= rn * nx;
+            ry -= rn * ny;
+            rz -= rn * nz;
+            const Real capr = (Real)P.mu_r * fabs(fn) * (Real)(1.0 / P.kr);
+            const Real rm = sqrt_r(rx * rx + ry * ry + rz * rz);
+            if (rm >= capr && rm > (Real)0.0) {
+                const Real sc = capr * rcp_r(rm);
+                rx *= sc;
+                ry *= sc;
+                rz *= sc;
+            }
+            o.xr[0] = rx;
+            o.xr[1] = ry;
+            o.xr[2] = rz;
+            const Real frx = (Real)P.kr * rx, fry = (Real)P.kr * ry, frz = (Real)P.kr * rz;
+            const Real qrx = abar * (ny * frz - nz * fry), qry = abar * (nz * frx - nx * frz),
+                       qrz = abar * (nx * fry - ny * frx);
+            Ti0 += qrx;
+            Ti1 += qry;
+            Ti2 += qrz;
+            Tj0 -= qrx;
+            Tj1 -= qry;
+            Tj2 -= qrz;
+        }
     }
     const Real Fex = fe * nx, Fey = fe * ny, Fez = fe * nz;
     o.Fi[0] = FLx + FCx + Fex;
@@ -737,7 +772,8 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
 // evaluation; rows are sorted by partner id, so the scan stops at the first larger key.
 // ----------------------------------------------------------------------------------
 __device__ __forceinline__ bool row_find(const int *__restrict__ hkey, const double *__restrict__ hxi,
-                                         const int *__restrict__ hcnt, int M, int p, int key, double out[3])
+                                         const int *__restrict__ hcnt, int M, int p, int key, double out[3],
+                                         const double *__restrict__ hxr = nullptr, double *outr = nullptr)
 {
     const int n = hcnt[p];
     const int *kr = hkey + (long long)p * M;
@@ -748,6 +784,12 @@ __device__ __forceinline__ bool row_find(const int *__restrict__ hkey, const dou
             out[0] = x[0];
             out[1] = x[1];
             out[2] = x[2];
+            if (hxr) {
+                const double *y = hxr + ((long long)p * M + k) * 3;
+                outr[0] = y[0];
+                outr[1] = y[1];
+                outr[2] = y[2];
+            }
             return true;
         }
         if (kk > key) break;
@@ -764,6 +806,8 @@ struct HistView {
     double *xi_new;
     int *cnt_new;
     int *own_new;          // owner id of each new row
+    const double *xr_old;  // rolling stretches beside xi (null without rolling resistance)
+    double *xr_new;
 };
 
 // ----------------------------------------------------------------------------------
@@ -804,7 +848,7 @@ __device__ __forceinline__ void shell_window(const BoxParams &P, int r, int cx, 
 // Evaluate one listed pair (i at slot gi, j at slot gj): history lookup (stored stretch
 // of this pair in the row of either particle, canonical orientation min id -> max id) and
 // the pair physics.
-template <typename Real>
+template <typename Real, bool Roll = false>
 __device__ __forceinline__ void evaluate_pair(const DevParams &P, double gd, const HistView &H, int gi, int gj, int idi,
                                               int idj,
                                               const double4 &Xi, const double4 &Xj, const double4 &Vi,
@@ -812,19 +856,21 @@ __device__ __forceinline__ void evaluate_pair(const DevParams &P, double gd, con
                                               double dy, double dz, double r2, double *S, PairOut &o)
 {
     double xo[3] = {0.0, 0.0, 0.0};
+    double xro[3] = {0.0, 0.0, 0.0};  // the rolling stretch has no orientation
     const double dist = sqrt(r2);
     if (dist - Xi.w - Xj.w < 0.0) {
         const int pi_ = H.prev ? H.prev[gi] : gi;
         const int pj_ = H.prev ? H.prev[gj] : gj;
-        bool found = row_find(H.key_old, H.xi_old, H.cnt_old, P.M, pi_, idj, xo);
-        if (!found) found = row_find(H.key_old, H.xi_old, H.cnt_old, P.M, pj_, idi, xo);
+        const double *hr = Roll ? H.xr_old : nullptr;
+        bool found = row_find(H.key_old, H.xi_old, H.cnt_old, P.M, pi_, idj, xo, hr, xro);
+        if (!found) found = row_find(H.key_old, H.xi_old, H.cnt_old, P.M, pj_, idi, xo, hr, xro);
         if (found && idi > idj) {
             xo[0] = -xo[0];
             xo[1] = -xo[1];
             xo[2] = -xo[2];
         }
     }
-    pair_physics<Real>(P, gd, dx, dy, dz, dist, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, S, o);
+    pair_physics<Real, Roll>(P, gd, dx, dy, dz, dist, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, xro, S, o);
 }
 
 __device__ __forceinline__ void record_pair(const DevParams &P, int idi, int idj, int *pair_out,
@@ -839,12 +885,19 @@ __device__ __forceinline__ void record_pair(const DevParams &P, int idi, int idj
     }
 }
 
+template <bool Roll = false>
 __device__ __forceinline__ void store_history(const HistView &H, int M, int gi, int slot, int idi, int idj,
                                               const PairOut &o, DevClock *clk)
 {
     if (slot < M) {
         const double sg = idi < idj ? 1.0 : -1.0;
         H.key_new[(long long)gi * M + slot] = idj | (o.capped ? kCapBit : 0);
+        if constexpr (Roll) {
+            double *y = H.xr_new + ((long long)gi * M + slot) * 3;
+            y[0] = o.xr[0];
+            y[1] = o.xr[1];
+            y[2] = o.xr[2];
+        }
         double *x = H.xi_new + ((long long)gi * M + slot) * 3;
         x[0] = sg * o.xi[0];
         x[1] = sg * o.xi[1];
@@ -856,11 +909,14 @@ __device__ __forceinline__ void store_history(const HistView &H, int M, int gi, 
 
 // Sort history row gi by partner id and publish it (the per-row sort of the contact
 // map).  Rows of up to 8 entries are sorted in registers (odd-even transposition on
-// (key, index), then one permuted copy); longer rows by insertion in place.
+// (key, index), then one permuted copy); longer rows by insertion in place.  With rolling
+// resistance the rolling stretches move with their entries.
+template <bool Roll = false>
 __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int fill, int idi)
 {
     int *krow = H.key_new + (long long)gi * M;
     double *xrow = H.xi_new + (long long)gi * M * 3;
+    double *rrow = Roll ? H.xr_new + (long long)gi * M * 3 : nullptr;
     const int nrow = fill < M ? fill : M;
     if (nrow >= 2 && nrow <= 8) {
         int key[8], idx[8];
@@ -888,6 +944,24 @@ __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int
                 x[a][1] = q[1];
                 x[a][2] = q[2];
             }
+        if constexpr (Roll) {
+            double y[8][3];
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+                if (a < nrow) {
+                    const double *q = rrow + 3 * idx[a];
+                    y[a][0] = q[0];
+                    y[a][1] = q[1];
+                    y[a][2] = q[2];
+                }
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+                if (a < nrow) {
+                    rrow[3 * a] = y[a][0];
+                    rrow[3 * a + 1] = y[a][1];
+                    rrow[3 * a + 2] = y[a][2];
+                }
+        }
 #pragma unroll
         for (int a = 0; a < 8; ++a)
             if (a < nrow) {
@@ -900,18 +974,34 @@ __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int
         for (int a = 1; a < nrow; ++a) {
             int key = krow[a];
             double x0 = xrow[3 * a], x1 = xrow[3 * a + 1], x2 = xrow[3 * a + 2];
+            double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+            if constexpr (Roll) {
+                y0 = rrow[3 * a];
+                y1 = rrow[3 * a + 1];
+                y2 = rrow[3 * a + 2];
+            }
             int b = a - 1;
             while (b >= 0 && (krow[b] & kKeyMask) > (key & kKeyMask)) {
                 krow[b + 1] = krow[b];
                 xrow[3 * (b + 1)] = xrow[3 * b];
                 xrow[3 * (b + 1) + 1] = xrow[3 * b + 1];
                 xrow[3 * (b + 1) + 2] = xrow[3 * b + 2];
+                if constexpr (Roll) {
+                    rrow[3 * (b + 1)] = rrow[3 * b];
+                    rrow[3 * (b + 1) + 1] = rrow[3 * b + 1];
+                    rrow[3 * (b + 1) + 2] = rrow[3 * b + 2];
+                }
                 --b;
             }
             krow[b + 1] = key;
             xrow[3 * (b + 1)] = x0;
             xrow[3 * (b + 1) + 1] = x1;
             xrow[3 * (b + 1) + 2] = x2;
+            if constexpr (Roll) {
+                rrow[3 * (b + 1)] = y0;
+                rrow[3 * (b + 1) + 1] = y1;
+                rrow[3 * (b + 1) + 2] = y2;
+            }
         }
     }
     H.cnt_new[gi] = nrow;
@@ -950,7 +1040,7 @@ struct PairTally {
 // shell of particle i, keeps its own side in registers (stored into its own record) and
 // adds the partner side atomically to ft_x.
 // ----------------------------------------------------------------------------------
-template <typename Real>
+template <typename Real, bool Roll>
 __device__ void particle_pairs_global(const DevParams &P, const BoxParams &G, int i, double delta,
                                       const int *__restrict__ cell_start,
                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
@@ -997,7 +1087,7 @@ __device__ void particle_pairs_global(const DevParams &P, const BoxParams &G, in
                 ++tally.npair;
                 if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
                 PairOut o;
-                evaluate_pair<Real>(P, G.gd, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
+                evaluate_pair<Real, Roll>(P, G.gd, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     f[k] += o.Fi[k];
@@ -1012,7 +1102,7 @@ __device__ void particle_pairs_global(const DevParams &P, const BoxParams &G, in
                 atomicAdd(xr + 5, o.Tj[2]);
                 if (o.contact) {
                     ++tally.ncont;
-                    store_history(H, P.M, i, fill, idi, idj, o, clk);
+                    store_history<Roll>(H, P.M, i, fill, idi, idj, o, clk);
                     ++fill;
                 }
             }
@@ -1020,7 +1110,7 @@ __device__ void particle_pairs_global(const DevParams &P, const BoxParams &G, in
             span -= len;
         }
     }
-    finish_row(H, P.M, i, fill, idi);
+    finish_row<Roll>(H, P.M, i, fill, idi);
     tally.fill = max(tally.fill, fill);
     stokes_terms(P, G.gd, Xi, Vi, Wi, f);
     store_ft(B.own + 6LL * i, f);
@@ -1092,7 +1182,7 @@ __host__ __device__ inline size_t tile_lds_bytes(int own_cap, int stage_cap, int
            (size_t)(5 * own_cap + 1) * 4 + (size_t)own_cap * 4;
 }
 
-template <typename Real>
+template <typename Real, bool Roll>
 __device__ __forceinline__ void tile_pair(const DevParams &P, const BoxParams &G, const HistView &H, const TileShared &T,
                                           const TileView &V, int il, int jl, double delta,
                                           const double4 *__restrict__ vel, const double4 *__restrict__ omg,
@@ -1115,7 +1205,7 @@ __device__ __forceinline__ void tile_pair(const DevParams &P, const BoxParams &G
     ++tally.npair;
     if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
     PairOut o;
-    evaluate_pair<Real>(P, G.gd, H, gi, gj, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy, dz, r2, tally.S, o);
+    evaluate_pair<Real, Roll>(P, G.gd, H, gi, gj, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy, dz, r2, tally.S, o);
     double *ai = V.acc + 6 * il;
     double *aj = V.acc + 6 * jl;
     atomicAdd(ai + 0, o.Fi[0]);
@@ -1133,7 +1223,7 @@ __device__ __forceinline__ void tile_pair(const DevParams &P, const BoxParams &G
     if (o.contact) {
         ++tally.ncont;
         const int slot = atomicAdd(&V.rowcnt[il], 1);
-        store_history(H, P.M, gi, slot, idi, idj, o, clk);
+        store_history<Roll>(H, P.M, gi, slot, idi, idj, o, clk);
     }
 }
 
@@ -1183,7 +1273,7 @@ __device__ __forceinline__ int xcd_row(int b, int n)
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-template <typename Real>
+template <typename Real, bool Roll>
 __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
                                                       const int *__restrict__ row_box, const int *__restrict__ cell_start,
                                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
@@ -1396,7 +1486,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
     const int nq = T.qn;
     for (int q = t; q < nq; q += kBlock) {
         const unsigned e = V.queue[q];
-        tile_pair<Real>(P, G, H, T, V, (int)(e >> 16), (int)(e & 0xffffu), delta, vel, omg, clk, pair_out,
+        tile_pair<Real, Roll>(P, G, H, T, V, (int)(e >> 16), (int)(e & 0xffffu), delta, vel, omg, clk, pair_out,
                         pair_count, tally);
     }
     __syncthreads();
@@ -1414,7 +1504,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
         store_ft(B.own + 6LL * gi, f);
         if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
         const int fill = V.rowcnt[il];
-        finish_row(H, P.M, gi, fill, (int)Wi.w);
+        finish_row<Roll>(H, P.M, gi, fill, (int)Wi.w);
         tally.fill = max(tally.fill, fill);
     }
     for (int k = T.ro[1] + t; k < total; k += kBlock) {
@@ -1435,8 +1525,8 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
 // partner records of the row's four shell rows are zero; the row's stress partial as in
 // k_pairs.  Workgroups stride over the list of deferred rows.
 // ----------------------------------------------------------------------------------
-template <typename Real>
-__global__ void __launch_bounds__(kBlock) k_pairs_rows(DevParams P, const BoxParams *__restrict__ boxes,
+template <typename Real, bool Roll>
+__global__ void __launch_bounds__(kBlock, 2) k_pairs_rows(DevParams P, const BoxParams *__restrict__ boxes,
                                                        const int *__restrict__ row_box,
                                                        const int *__restrict__ cell_start,
                                                        const double4 *__restrict__ pa, const double4 *__restrict__ vel,
@@ -1462,7 +1552,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs_rows(DevParams P, const BoxPar
         tally.fill = 0;
         row_bounds(G, grow - G.row_off, cell_start, T);
         for (int i = T.rs[0] + t; i < T.re[0]; i += kBlock)
-            particle_pairs_global<Real>(P, G, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count,
+            particle_pairs_global<Real, Roll>(P, G, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count,
                                         tally);
         const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int r = 1; r < 5; ++r)

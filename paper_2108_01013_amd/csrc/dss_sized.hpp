@@ -15,7 +15,7 @@
 // The owner keeps its side in registers (its own record, with the Stokes terms) and adds the
 // partner side atomically to the atomic force record; the contact-history row of the pair is
 // the owner's.  Classes from wave_cls up take one wavefront per particle (lanes split the
-// stencil rows); the others one lane per particle.
+// stencil rows); the others one lane per particle; both in one launch.
 //
 // Requirements checked on the host: one box, n_x >= 2 R_max + 2, n_y, n_z >= 2 R_max + 1
 // (no cell is reached twice), partial records at most 4096.
@@ -73,7 +73,7 @@ __device__ __forceinline__ void sized_row(const BoxParams &G, const int *__restr
 }
 
 // One listed-candidate test and, for a listed pair, its physics; partner side atomically.
-template <typename Real>
+template <typename Real, bool Roll>
 __device__ __forceinline__ void sized_pair(const DevParams &P, const BoxParams &G, const HistView &H, int i, int j,
                                            int idi, const double4 &Xi, const double4 &Vi, const double4 &Wi,
                                            const double4 &Xj, double delta,
@@ -91,7 +91,7 @@ __device__ __forceinline__ void sized_pair(const DevParams &P, const BoxParams &
     idj = (int)Wj.w;
     ++tally.npair;
     if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
-    evaluate_pair<Real>(P, G.gd, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
+    evaluate_pair<Real, Roll>(P, G.gd, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         f[k] += o.Fi[k];
@@ -111,34 +111,17 @@ __device__ __forceinline__ void sized_pair(const DevParams &P, const BoxParams &
 }
 
 // ----------------------------------------------------------------------------------
-// k_pairs_sized: one lane per particle of the classes below wave_cls (slots [0, n_lane),
-// n_lane = first slot of class wave_cls), workgroups striding over the slots.  Partial
-// record = blockIdx.x.
+// Lane path: one lane per particle of the classes below wave_cls (slots [0, n_lane), n_lane =
+// first slot of class wave_cls), workgroup lb of nlb striding over the slots.
 // ----------------------------------------------------------------------------------
-template <typename Real>
-__global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const BoxParams *__restrict__ boxes,
-                                                        const int *__restrict__ cell_start,
-                                                        const double4 *__restrict__ pa,
-                                                        const double4 *__restrict__ vel,
-                                                        const double4 *__restrict__ omg, ForceBufs B, HistView H,
-                                                        DevClock *__restrict__ clk, double *__restrict__ partials,
-                                                        int *__restrict__ pair_out,
-                                                        unsigned long long *__restrict__ pair_count)
+template <typename Real, bool Roll>
+__device__ __forceinline__ void sized_lane_path(const DevParams &P, const BoxParams &G, const int *__restrict__ cell_start,
+                                                const double4 *__restrict__ pa, const double4 *__restrict__ vel,
+                                                const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
+                                                DevClock *clk, int *pair_out, unsigned long long *pair_count,
+                                                double delta, int n_lane, int lb, int nlb, PairTally &tally)
 {
-    __shared__ double red[kBlock / 64][12];
-    const BoxParams G = boxes[0];
-    const int ncb = G.nc[0] * G.nc[1] * G.nc[2];
-    const int n_lane = P.wave_cls < P.ncls ? cell_start[P.wave_cls * ncb] : P.N;
-    const double delta = le_offset(P, G, clk->step);
-    if (blockIdx.x == 0 && threadIdx.x == 0) clk->deferred = 1;  // the atomic record is in use
-    PairTally tally;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
-    tally.npair = tally.ncont = 0;
-    tally.fill = 0;
-    // XCD-contiguous slot blocks (see xcd_row): neighbouring slots share cells and partners
-    const int lb = xcd_row(blockIdx.x, gridDim.x);
-    for (int i = lb * kBlock + threadIdx.x; i < n_lane; i += gridDim.x * kBlock) {
+    for (int i = lb * kBlock + threadIdx.x; i < n_lane; i += nlb * kBlock) {
         const double4 Xi = pa[i];
         const double4 Vi = vel[i];
         const double4 Wi = omg[i];
@@ -155,20 +138,19 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const Bo
                 sized_row(G, cell_start, pa, i, Xi, ci, cx, cy, cz, dy, dz, delta, [&](int j, const double4 &Xj) {
                     int need, idj = 0;
                     PairOut o;
-                    sized_pair<Real>(P, G, H, i, j, idi, Xi, Vi, Wi, Xj, delta, vel, omg, B, clk, pair_out,
-                                     pair_count, tally, f, need, o, idj);
+                    sized_pair<Real, Roll>(P, G, H, i, j, idi, Xi, Vi, Wi, Xj, delta, vel, omg, B, clk, pair_out,
+                                           pair_count, tally, f, need, o, idj);
                     if (need) {
-                        store_history(H, P.M, i, fill, idi, idj, o, clk);
+                        store_history<Roll>(H, P.M, i, fill, idi, idj, o, clk);
                         ++fill;
                     }
                 });
-        finish_row(H, P.M, i, fill, idi);
+        finish_row<Roll>(H, P.M, i, fill, idi);
         tally.fill = max(tally.fill, fill);
         stokes_terms(P, G.gd, Xi, Vi, Wi, f);
         store_ft(B.own + 6LL * i, f);
         if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
     }
-    reduce_tally(tally, red, partials, P.pstride, blockIdx.x);
 }
 
 // Sort a history row of n entries by partner id with the 64 lanes of a wavefront: every lane
@@ -176,18 +158,21 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const Bo
 // keys, then stores them at their ranks.  Longer rows are sorted by lane 0 alone.
 constexpr int kWaveSortChunks = 4;
 
+template <bool Roll>
 __device__ __forceinline__ void wave_finish_row(const HistView &H, int M, int gi, int fill, int idi)
 {
     const int lane = threadIdx.x & 63;
     const int n = fill < M ? fill : M;
     if (n > 64 * kWaveSortChunks) {
-        if (lane == 0) finish_row(H, M, gi, fill, idi);
+        if (lane == 0) finish_row<Roll>(H, M, gi, fill, idi);
         return;
     }
     int *krow = H.key_new + (long long)gi * M;
     double *xrow = H.xi_new + (long long)gi * M * 3;
+    double *rrow = Roll ? H.xr_new + (long long)gi * M * 3 : nullptr;
     int key[kWaveSortChunks], rank[kWaveSortChunks];
     double x0[kWaveSortChunks], x1[kWaveSortChunks], x2[kWaveSortChunks];
+    double y0[kWaveSortChunks], y1[kWaveSortChunks], y2[kWaveSortChunks];
 #pragma unroll
     for (int m = 0; m < kWaveSortChunks; ++m) {
         const int e = lane + 64 * m;
@@ -197,6 +182,11 @@ __device__ __forceinline__ void wave_finish_row(const HistView &H, int M, int gi
             x0[m] = xrow[3 * e];
             x1[m] = xrow[3 * e + 1];
             x2[m] = xrow[3 * e + 2];
+            if constexpr (Roll) {
+                y0[m] = rrow[3 * e];
+                y1[m] = rrow[3 * e + 1];
+                y2[m] = rrow[3 * e + 2];
+            }
         }
     }
     for (int e = 0; e < n; ++e) {
@@ -216,6 +206,11 @@ __device__ __forceinline__ void wave_finish_row(const HistView &H, int M, int gi
             xrow[3 * d] = x0[m];
             xrow[3 * d + 1] = x1[m];
             xrow[3 * d + 2] = x2[m];
+            if constexpr (Roll) {
+                rrow[3 * d] = y0[m];
+                rrow[3 * d + 1] = y1[m];
+                rrow[3 * d + 2] = y2[m];
+            }
         }
     }
     if (lane == 0) {
@@ -225,36 +220,22 @@ __device__ __forceinline__ void wave_finish_row(const HistView &H, int M, int gi
 }
 
 // ----------------------------------------------------------------------------------
-// k_pairs_sized_wave: one wavefront per particle of the classes from wave_cls up (slots
-// [n_lane, N)); lanes stride over the (2R+1)^2 stencil rows, contacts take their history
-// slots from a per-wavefront LDS counter, the wavefront sums its own side and sorts the row.
-// Partial record = rec0 + blockIdx.x.
+// Wavefront path: one wavefront per particle of the classes from wave_cls up (slots
+// [n_lane, N)), workgroup wb of nwb; lanes stride over the (2R+1)^2 stencil rows, contacts
+// take their history slots from a per-wavefront LDS counter, the wavefront sums its own side
+// and sorts the row.
 // ----------------------------------------------------------------------------------
-template <typename Real>
-__global__ void __launch_bounds__(kBlock, 2) k_pairs_sized_wave(DevParams P, const BoxParams *__restrict__ boxes,
-                                                             const int *__restrict__ cell_start,
-                                                             const double4 *__restrict__ pa,
-                                                             const double4 *__restrict__ vel,
-                                                             const double4 *__restrict__ omg, ForceBufs B,
-                                                             HistView H, DevClock *__restrict__ clk,
-                                                             double *__restrict__ partials, int rec0,
-                                                             int *__restrict__ pair_out,
-                                                             unsigned long long *__restrict__ pair_count)
+template <typename Real, bool Roll>
+__device__ __forceinline__ void sized_wave_path(const DevParams &P, const BoxParams &G, const int *__restrict__ cell_start,
+                                                const double4 *__restrict__ pa, const double4 *__restrict__ vel,
+                                                const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
+                                                DevClock *clk, int *pair_out, unsigned long long *pair_count,
+                                                double delta, int n_lane, int wb, int nwb, int *wfill,
+                                                PairTally &tally)
 {
-    __shared__ double red[kBlock / 64][12];
-    __shared__ int wfill[kBlock / 64];
-    const BoxParams G = boxes[0];
-    const int ncb = G.nc[0] * G.nc[1] * G.nc[2];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int n_lane = P.wave_cls < P.ncls ? cell_start[P.wave_cls * ncb] : P.N;
-    const double delta = le_offset(P, G, clk->step);
-    PairTally tally;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
-    tally.npair = tally.ncont = 0;
-    tally.fill = 0;
-    const int nwave = gridDim.x * (kBlock / 64);
-    for (int i = n_lane + blockIdx.x * (kBlock / 64) + wid; i < P.N; i += nwave) {
+    const int nwave = nwb * (kBlock / 64);
+    for (int i = n_lane + wb * (kBlock / 64) + wid; i < P.N; i += nwave) {
         const double4 Xi = pa[i];
         const double4 Vi = vel[i];
         const double4 Wi = omg[i];
@@ -273,9 +254,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized_wave(DevParams P, con
             sized_row(G, cell_start, pa, i, Xi, ci, cx, cy, cz, dy, dz, delta, [&](int j, const double4 &Xj) {
                 int need, idj = 0;
                 PairOut o;
-                sized_pair<Real>(P, G, H, i, j, idi, Xi, Vi, Wi, Xj, delta, vel, omg, B, clk, pair_out, pair_count,
-                                 tally, f, need, o, idj);
-                if (need) store_history(H, P.M, i, atomicAdd(&wfill[wid], 1), idi, idj, o, clk);
+                sized_pair<Real, Roll>(P, G, H, i, j, idi, Xi, Vi, Wi, Xj, delta, vel, omg, B, clk, pair_out,
+                                       pair_count, tally, f, need, o, idj);
+                if (need) store_history<Roll>(H, P.M, i, atomicAdd(&wfill[wid], 1), idi, idj, o, clk);
             });
         }
         // the row's entries, written by all lanes, are visible to the whole wavefront
@@ -284,7 +265,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized_wave(DevParams P, con
         const int fill = wfill[wid];
 #pragma unroll
         for (int k = 0; k < 6; ++k) f[k] = warp_sum(f[k]);
-        wave_finish_row(H, P.M, i, fill, idi);
+        wave_finish_row<Roll>(H, P.M, i, fill, idi);
         if (lane == 0) {
             tally.fill = max(tally.fill, fill);
             stokes_terms(P, G.gd, Xi, Vi, Wi, f);
@@ -292,7 +273,44 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized_wave(DevParams P, con
             if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
         }
     }
-    reduce_tally(tally, red, partials, P.pstride, rec0 + blockIdx.x);
+}
+
+// ----------------------------------------------------------------------------------
+// k_pairs_sized: workgroups [0, g_wave) take the wavefront path (the long-running large
+// particles start first), the others the lane path over XCD-contiguous slot blocks (see
+// xcd_row; g_wave is a multiple of 8, so the XCD of a lane workgroup is unchanged).  Partial
+// record = blockIdx.x.
+// ----------------------------------------------------------------------------------
+template <typename Real, bool Roll>
+__global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const BoxParams *__restrict__ boxes,
+                                                        const int *__restrict__ cell_start,
+                                                        const double4 *__restrict__ pa,
+                                                        const double4 *__restrict__ vel,
+                                                        const double4 *__restrict__ omg, ForceBufs B, HistView H,
+                                                        DevClock *__restrict__ clk, double *__restrict__ partials,
+                                                        int g_wave, int *__restrict__ pair_out,
+                                                        unsigned long long *__restrict__ pair_count)
+{
+    __shared__ double red[kBlock / 64][12];
+    __shared__ int wfill[kBlock / 64];
+    const BoxParams G = boxes[0];
+    const int ncb = G.nc[0] * G.nc[1] * G.nc[2];
+    const int n_lane = P.wave_cls < P.ncls ? cell_start[P.wave_cls * ncb] : P.N;
+    const double delta = le_offset(P, G, clk->step);
+    if (blockIdx.x == 0 && threadIdx.x == 0) clk->deferred = 1;  // the atomic record is in use
+    PairTally tally;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
+    tally.npair = tally.ncont = 0;
+    tally.fill = 0;
+    const int b = blockIdx.x;
+    if (b < g_wave)
+        sized_wave_path<Real, Roll>(P, G, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, delta, n_lane, b,
+                                    g_wave, wfill, tally);
+    else
+        sized_lane_path<Real, Roll>(P, G, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, delta, n_lane,
+                                    xcd_row(b - g_wave, (int)gridDim.x - g_wave), (int)gridDim.x - g_wave, tally);
+    reduce_tally(tally, red, partials, P.pstride, b);
 }
 
 }  // namespace dss

@@ -25,7 +25,7 @@ STATUS = {0: "DSS_OK", 1: "DSS_ERR_ARG", 2: "DSS_ERR_HIP", 3: "DSS_ERR_CAPACITY"
           5: "DSS_ERR_UNSTABLE", 6: "DSS_ERR_STATE"}
 
 EXPORTS = ["dss_create", "dss_create_batch", "dss_set_particles", "dss_set_particles_batch", "dss_set_step", "dss_build_neighbours", "dss_compute_forces", "dss_step",
-           "dss_read_stress", "dss_read_stress_batch", "dss_get_box_info", "dss_get_state", "dss_get_eval_velocities", "dss_get_pairs", "dss_get_cells",
+           "dss_read_stress", "dss_read_stress_batch", "dss_get_box_info", "dss_get_state", "dss_get_eval_velocities", "dss_get_pairs", "dss_get_cells", "dss_get_rolling_history",
            "dss_get_history", "dss_get_info", "dss_save_state", "dss_load_state", "dss_set_timing",
            "dss_get_timing", "dss_set_tuning", "dss_get_tuning", "dss_adjoint", "dss_last_error",
            "dss_status_string", "dss_destroy"]
@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
                                                   "lambda_D", "a0", "hamaker", "eps_vdw", "eps_lub", "cutoff_factor",
                                                   "dt")]
                 + [("precision", ctypes.c_int32), ("capacity", ctypes.c_int32), ("flags", ctypes.c_int32),
-                   ("reserved", ctypes.c_int32)])
+                   ("reserved", ctypes.c_int32), ("k_roll", ctypes.c_double), ("mu_roll", ctypes.c_double)])
 
 
 class Info(ctypes.Structure):
@@ -103,6 +103,7 @@ def load_library():
         "dss_get_pairs": (st, [H, i64, vp, ctypes.POINTER(i64)]),
         "dss_get_cells": (st, [H, vp, i64, vp, vp]),
         "dss_get_history": (st, [H, i64, vp, vp, ctypes.POINTER(i64)]),
+        "dss_get_rolling_history": (st, [H, i64, vp, vp, ctypes.POINTER(i64)]),
         "dss_get_info": (st, [H, ctypes.POINTER(Info)]),
         "dss_save_state": (st, [H, vp, ctypes.POINTER(ctypes.c_size_t)]),
         "dss_load_state": (st, [H, vp, ctypes.c_size_t]),
@@ -134,6 +135,8 @@ def make_params(p: dict, precision: int = DSS_FP64, capacity: int = 0, flags: in
     s.capacity = int(capacity)
     s.flags = int(flags) | (DSS_FLAG_EC_RANGES if p.get("ec_ranges") else 0)
     s.reserved = 0
+    s.k_roll = float(p.get("kr", 0.0))      # rolling resistance (Appendix roll), off at 0
+    s.mu_roll = float(p.get("mu_r", 0.0))
     return s
 
 
@@ -263,6 +266,14 @@ class Simulation:
         self._check(self.lib.dss_get_box_info(self.h, 0, ctypes.byref(inf)))
         return int(np.prod(dims)) * int(inf.size_classes)
 
+    def box_info(self, b):
+        inf = BoxInfo()
+        self._check(self.lib.dss_get_box_info(self.h, int(b), ctypes.byref(inf)))
+        return {"n_particles": inf.n_particles, "first_id": inf.first_id, "cells": tuple(inf.cells),
+                "first_cell": inf.first_cell, "n_pairs": inf.n_pairs, "n_contacts": inf.n_contacts,
+                "max_row_fill": inf.max_row_fill, "size_classes": inf.size_classes, "L": tuple(inf.L),
+                "shear_rate": inf.shear_rate, "le_offset": inf.le_offset}
+
     def cells(self):
         dims = np.zeros(3, np.int32)
         self._check(self.lib.dss_get_cells(self.h, ctypes.c_void_p(dims.ctypes.data), 0, None, None))
@@ -273,14 +284,16 @@ class Simulation:
                                            ctypes.c_void_p(cs.ctypes.data), ctypes.c_void_p(perm.ctypes.data)))
         return dims, cs, perm
 
-    def history(self):
+    def history(self, rolling=False):
+        """Committed contact history: (pairs (id_min, id_max) sorted, tangential stretches), or
+        with rolling=True the rolling stretches of the same contacts."""
         n = ctypes.c_int64(0)
         cap = max(64, 8 * self.N)
+        fn = self.lib.dss_get_rolling_history if rolling else self.lib.dss_get_history
         while True:
             pr = np.zeros((cap, 2), np.int32)
             xi = np.zeros((cap, 3))
-            s = self.lib.dss_get_history(self.h, cap, ctypes.c_void_p(pr.ctypes.data),
-                                         ctypes.c_void_p(xi.ctypes.data), ctypes.byref(n))
+            s = fn(self.h, cap, ctypes.c_void_p(pr.ctypes.data), ctypes.c_void_p(xi.ctypes.data), ctypes.byref(n))
             if s == 3 and n.value > cap:
                 cap = int(n.value)
                 continue
@@ -440,14 +453,6 @@ class Batch(Simulation):
         self._check(self.lib.dss_read_stress_batch(self.h, last.ctypes.data_as(ctypes.c_void_p),
                                                    mean.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ns)))
         return last.reshape(self.B, 3, 3), mean.reshape(self.B, 3, 3), int(ns.value)
-
-    def box_info(self, b):
-        inf = BoxInfo()
-        self._check(self.lib.dss_get_box_info(self.h, int(b), ctypes.byref(inf)))
-        return {"n_particles": inf.n_particles, "first_id": inf.first_id, "cells": tuple(inf.cells),
-                "first_cell": inf.first_cell, "n_pairs": inf.n_pairs, "n_contacts": inf.n_contacts,
-                "max_row_fill": inf.max_row_fill, "size_classes": inf.size_classes, "L": tuple(inf.L),
-                "shear_rate": inf.shear_rate, "le_offset": inf.le_offset}
 
     def _ncell_total(self, dims):
         last = self.box_info(self.B - 1)

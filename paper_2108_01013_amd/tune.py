@@ -33,6 +33,11 @@ SIZED_CANDIDATES = (
     {"cell_scale": 2.0, "sized": True, "wave_class": 0},
     {"cell_scale": 3.0, "sized": True, "wave_class": 0},
     {"cell_scale": 2.0, "sized": True, "wave_class": 2},
+    {"cell_scale": 2.0, "sized": True, "wave_class": 1},
+    {"cell_scale": 1.5, "sized": True, "wave_class": 2},
+    {"cell_scale": 2.5, "sized": True, "wave_class": 2},
+    {"cell_scale": 1.5, "sized": True, "wave_class": 1},
+    {"cell_scale": 1.25, "sized": True, "wave_class": 2},
 )
 
 
