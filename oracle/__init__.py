@@ -15,6 +15,7 @@ Every function cites the passage it follows in the C source.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -410,3 +411,66 @@ def stress_objective(p, x0, rad, u0, w0, n_steps: int, stress_every: int, weight
         if n % stress_every == 0:
             samples.append(np.asarray(S).reshape(3, 3))
     return float(np.sum(W * np.mean(samples, axis=0))), branch
+
+
+# ----------------------------------------------------------------------------------------------
+# Observables of Sec. 3, written out from their definitions (plain numpy / Python)
+# ----------------------------------------------------------------------------------------------
+def shear_diffusivity(p, y0_unwrapped, y_unwrapped, elapsed):
+    """Eq. (diffY): D_y = <[y(t) - y(t0)]^2> / (2 (t - t0) a0^2 gdot), average over particles;
+    y unwrapped across the sheared y faces (gdot taken as 1 when it is 0)."""
+    dy = np.asarray(y_unwrapped, np.float64) - np.asarray(y0_unwrapped, np.float64)
+    gd = p["shear_rate"] if p["shear_rate"] != 0.0 else 1.0
+    return float(np.mean(dy * dy) / (2.0 * elapsed * p["a0"] ** 2 * gd)) if elapsed > 0 else 0.0
+
+
+def velocity_autocorrelation(v0, v):
+    """Eq. (corrV): C_v = <v'(t) v'(t0)> / <v'(t)^2>, v' the shear-wise velocity fluctuation."""
+    v0 = np.asarray(v0, np.float64)
+    v = np.asarray(v, np.float64)
+    return float(np.sum(v * v0) / np.sum(v * v))
+
+
+def phi_profile(p, y, rad, nbins, a_split):
+    """Local volume fraction along y (Fig. localPhi): for every slab [k, k+1) L_y/nbins of the
+    periodic y axis, the volume of each sphere inside it, pi [a^2 z - z^3/3] between the slab
+    faces clipped to [-a, a] (z measured from the centre), over the slab volume; row 0 for
+    radii <= a_split, row 1 for larger ones."""
+    L = p["L"]
+    dy = L[1] / nbins
+    out = np.zeros((2, nbins))
+    for yc, a in zip(np.asarray(y, np.float64), np.asarray(rad, np.float64)):
+        g = 1 if a > a_split else 0
+        for b in range(int(math.floor((yc - a) / dy)), int(math.floor((yc + a) / dy)) + 1):
+            lo = max(b * dy - yc, -a)
+            hi = min((b + 1) * dy - yc, a)
+            if hi > lo:
+                out[g, b % nbins] += math.pi * ((a * a * hi - hi ** 3 / 3.0) - (a * a * lo - lo ** 3 / 3.0))
+    return out / (L[0] * L[2] * dy)
+
+
+def contact_clusters(N, pairs, cap=None):
+    """Clusters of contacting particles (Fig. histo): connected components of the graph whose
+    edges are the contact pairs, by breadth-first search; returns the histogram h[s - 1] =
+    number of clusters of s particles (sizes >= cap in the last entry)."""
+    cap = cap or N
+    adj = [[] for _ in range(N)]
+    for a, b in np.asarray(pairs, np.int64).reshape(-1, 2):
+        adj[a].append(b)
+        adj[b].append(a)
+    seen = np.zeros(N, bool)
+    hist = np.zeros(cap, np.int64)
+    for s in range(N):
+        if seen[s]:
+            continue
+        seen[s] = True
+        queue, size = [s], 0
+        while queue:
+            v = queue.pop()
+            size += 1
+            for w in adj[v]:
+                if not seen[w]:
+                    seen[w] = True
+                    queue.append(w)
+        hist[min(size, cap) - 1] += 1
+    return hist

@@ -701,3 +701,62 @@ def test_rolling_symmetry_and_switch_off():
             assert np.array_equal(a[k], z[k])
         assert rel(a["TC_i"] - a["TR_i"], z["TC_i"]) < 1e-12
         assert rel(a["TC_j"] + a["TR_i"], z["TC_j"]) < 1e-12
+
+
+# ---------------------------------------------------------------------------------------------
+# Observables (Sec. 3): the slab volumes against the spherical-cap formula V = pi h^2 (3a - h)/3
+# and the sphere volume, the clusters against scipy's connected components and hand graphs,
+# the diffusivity's unwrapping and the autocorrelation on hand values.
+# ---------------------------------------------------------------------------------------------
+def test_phi_profile_slab_volumes():
+    L = 20.0
+    p = params(L=L)
+    nb = 10
+    slab = L * L * (L / nb)
+    a = 0.7
+    # inside one slab: the whole sphere
+    prof = oracle.phi_profile(p, [5.0], [a], nb, 1.0)
+    assert abs(prof[0, 2] * slab - 4 / 3 * math.pi * a ** 3) < 1e-12 and np.count_nonzero(prof) == 1
+    # a cap of height h above the face y = 4: pi h^2 (3a - h) / 3
+    for h in (0.1, 0.35, 0.7, 1.1):
+        yc = 4.0 - a + h
+        prof = oracle.phi_profile(p, [yc], [a], nb, 1.0)
+        cap = math.pi * h * h * (3 * a - h) / 3
+        assert abs(prof[0, 2] * slab - cap) < 1e-12 * max(cap, 1.0)
+    # across the periodic face: the two bins at the ends, summing to the sphere
+    prof = oracle.phi_profile(p, [0.2], [1.4], nb, 1.0)
+    assert prof[1, 9] > 0 and prof[1, 0] > 0 and np.all(prof[0] == 0)
+    assert abs(prof.sum() * slab - 4 / 3 * math.pi * 1.4 ** 3) < 1e-11
+    # many spheres: total over bins = total volume (global volume fraction)
+    rng = np.random.default_rng(3)
+    y = rng.uniform(0, L, 200)
+    r = rng.uniform(1.0, 1.4, 200)
+    prof = oracle.phi_profile(p, y, r, 7, 1.2)
+    assert abs(prof.sum() * L ** 3 / 7 - 4 / 3 * math.pi * np.sum(r ** 3)) < 1e-9
+    assert abs(prof[1].sum() * L ** 3 / 7 - 4 / 3 * math.pi * np.sum(r[r > 1.2] ** 3)) < 1e-9
+
+
+def test_contact_clusters_against_library():
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    assert list(oracle.contact_clusters(5, [(0, 1), (1, 2)])) == [2, 0, 1, 0, 0]        # chain + 2 isolated
+    assert list(oracle.contact_clusters(4, [(0, 1), (1, 2), (0, 2)], cap=2)) == [1, 1]  # triangle in the cap bin
+    rng = np.random.default_rng(9)
+    for N, E in ((50, 30), (400, 380), (1000, 200)):
+        pairs = np.unique(np.sort(rng.integers(0, N, size=(E, 2)), axis=1), axis=0)
+        pairs = pairs[pairs[:, 0] != pairs[:, 1]]
+        g = coo_matrix((np.ones(len(pairs)), (pairs[:, 0], pairs[:, 1])), shape=(N, N))
+        n, lab = connected_components(g, directed=False)
+        sizes = np.bincount(np.bincount(lab), minlength=N + 1)[1:]
+        assert np.array_equal(oracle.contact_clusters(N, pairs), sizes)
+        assert oracle.contact_clusters(N, pairs).sum() == n
+
+
+def test_diffusivity_and_autocorrelation_hand_values():
+    p = params(L=10.0, shear_rate=2.0, a0=1.0)
+    # particle 0 crossed the top face once (y = 9.9 -> 0.05 + L), particle 1 moved down by 0.3
+    y0 = np.array([9.9, 5.0])
+    y1 = np.array([0.05 + 10.0, 4.7])
+    D = oracle.shear_diffusivity(p, y0, y1, 0.5)
+    assert abs(D - ((0.15 ** 2 + 0.3 ** 2) / 2) / (2 * 0.5 * 2.0)) < 1e-15
+    assert oracle.velocity_autocorrelation([1.0, -2.0], [0.5, -1.0]) == (0.5 + 2.0) / (0.25 + 1.0)
