@@ -290,10 +290,32 @@ dss_status dss_load_state(dss_handle *h, const void *blob, size_t bytes);
  * the kernels selected by enable (bit k: kernel k; -1: all; 0: off); every call starts a
  * new accumulation.  dss_get_timing synchronises and returns, for kernel k (0 predict or
  * velocity completion, 1 scan, 2 scatter, 3 pairs, 4 finish, 5 pair adjoint, 6 integrator
- * adjoint, 7 pairs of the rows beyond the tile capacities), the summed duration in ms and the
- * number of timed launches. */
+ * adjoint, 7 pairs of the rows beyond the tile capacities; with size-class stencils 3 is
+ * their one pair kernel), the summed duration in ms and the number of timed launches. */
 dss_status dss_set_timing(dss_handle *h, int enable);
 dss_status dss_get_timing(dss_handle *h, int kernel, double *total_ms, int64_t *launches);
+
+/* Observables of Sec. 3 (single-box handles; DSS_ERR_ARG on a batch).
+ * dss_observe_start: the current state becomes the reference time t0 (synchronises).
+ * dss_observe: out = {D_y, C_v, <[y(t) - y(t0)]^2>, t - t0} at the current state, with
+ *   D_y = <[y(t) - y(t0)]^2> / (2 (t - t0) a0^2 gdot), eq. (diffY) (gdot taken as 1 when 0;
+ *   D_y = 0 at t = t0), y unwrapped across the sheared y faces, and
+ *   C_v = <v'(t) v'(t0)> / <v'(t)^2>, eq. (corrV), v' = u_y; averages over all particles.
+ *   DSS_ERR_STATE before dss_observe_start. */
+dss_status dss_observe_start(dss_handle *h);
+dss_status dss_observe(dss_handle *h, double out[4]);
+
+/* Local volume fraction along y (Fig. localPhi): phi[g nbins + k] = volume of the spheres of
+ * group g (0: radius <= a_split, 1: radius > a_split) inside the slab [k, k+1) L_y / nbins of
+ * the periodic y axis, over the slab volume; 1 <= nbins <= 2048, phi host (2 nbins). */
+dss_status dss_phi_profile(dss_handle *h, int32_t nbins, double a_split, double *phi);
+
+/* Clusters of contacting particles (Fig. histo): connected components of the graph of the
+ * committed contacts (d_ij < 0 at the last step).  hist[s - 1] = number of clusters of s
+ * particles for s < cap, hist[cap - 1] those of cap or more (isolated particles are clusters
+ * of 1); *n_clusters their total, *largest the largest s with hist[s - 1] > 0 (nullable);
+ * host pointers. */
+dss_status dss_contact_clusters(dss_handle *h, int64_t cap, int64_t *hist, int64_t *n_clusters, int64_t *largest);
 
 const char *dss_last_error(const dss_handle *h);
 const char *dss_status_string(dss_status s);

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdss.so")
 SOURCES = [os.path.join(CSRC, "dss_api.hip")]
-HEADERS = [os.path.join(CSRC, h) for h in ("dss_kernels.hpp", "dss_adjoint.hpp", "dss_sized.hpp", "pair_vjp.hpp")] + [
+HEADERS = [os.path.join(CSRC, h) for h in ("dss_kernels.hpp", "dss_adjoint.hpp", "dss_sized.hpp", "dss_observe.hpp", "pair_vjp.hpp")] + [
     os.path.join(ROOT, "include", "dss.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -22,6 +22,7 @@
 #include "dss_kernels.hpp"
 #include "dss_adjoint.hpp"
 #include "dss_sized.hpp"
+#include "dss_observe.hpp"
 
 using namespace dss;
 
@@ -68,6 +69,9 @@ struct dss_handle {
     double *ft_own = nullptr, *ft_nb = nullptr, *ft_x = nullptr;  // force records (ForceBufs)
     int *cell = nullptr, *rank = nullptr, *count = nullptr, *cell_start = nullptr;
     int *prev = nullptr;       // slot -> slot at the previous sort
+    int *img = nullptr;        // y-face crossings by particle id (unwrapped shear-wise position)
+    double *obs_y0 = nullptr, *obs_v0 = nullptr;  // observation reference (dss_observe_start)
+    int64_t obs_step0 = -1;
     int *hkey[2] = {nullptr, nullptr}, *hcnt[2] = {nullptr, nullptr}, *hown[2] = {nullptr, nullptr};
     double *hxi[2] = {nullptr, nullptr};
     double *hxr[2] = {nullptr, nullptr};  // rolling stretches (only with rolling resistance)
@@ -163,7 +167,10 @@ void free_all(dss_handle *h)
         h->hkey[k] = h->hcnt[k] = h->hown[k] = nullptr;
         h->hxi[k] = h->hxr[k] = nullptr;
     }
-    F(h->ft_own); F(h->ft_nb); F(h->ft_x); F(h->prev);
+    F(h->ft_own); F(h->ft_nb); F(h->ft_x); F(h->prev); F(h->img); F(h->obs_y0); F(h->obs_v0);
+    h->img = nullptr;
+    h->obs_y0 = h->obs_v0 = nullptr;
+    h->obs_step0 = -1;
     F(h->cell); F(h->rank);
     F(h->pairs); F(h->pair_count); F(h->clk); F(h->run); F(h->sigma_last); F(h->samples);
     F(h->box_diag);
@@ -611,7 +618,7 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
         TimedLaunch t(h, 0);
         hipExtLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P, h->d_boxes,
                               h->pa[c], h->vel[c], h->omg[c], h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk,
-                              h->cell, h->rank, h->count, h->fb_count);
+                              h->cell, h->rank, h->count, h->fb_count, h->img);
     }
     if (h->scan_tiles > 0) {
         TimedLaunch t(h, 1);
@@ -893,6 +900,8 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     HIPTRY(dalloc(&h->ft_nb, 24 * N));
     HIPTRY(dalloc(&h->ft_x, 6 * N));
     HIPTRY(dalloc(&h->prev, N));
+    HIPTRY(dalloc(&h->img, N));
+    HIPTRY(hipMemsetAsync(h->img, 0, N * sizeof(int), h->stream));
     HIPTRY(dalloc(&h->cell, N));
     HIPTRY(dalloc(&h->rank, N));
     HIPTRY(dalloc(&h->pairs, P.record_pairs ? 2 * P.pair_cap : 2));
@@ -1329,12 +1338,13 @@ struct Snapshot {
     double *hxi = nullptr;
     DevClock *clk = nullptr;
     double *sig = nullptr;  // sigma_last (9) and box_diag (3) of box 0
+    int *img = nullptr;     // y-face crossing counts
     int cur = 0, hh = 0;
     int64_t step = 0;
     bool vel_is_half = false;
     void release()
     {
-        void *ps[] = {pa, vel, omg, ft, cs, hkey, hcnt, hown, hxi, clk, sig};
+        void *ps[] = {pa, vel, omg, ft, cs, hkey, hcnt, hown, hxi, clk, sig, img};
         for (void *q : ps)
             if (q) (void)hipFree(q);
         *this = Snapshot{};
@@ -1356,6 +1366,7 @@ dss_status snap_save(dss_handle *h, Snapshot &s)
         HIPTRY(dalloc(&s.hown, N));
         HIPTRY(dalloc(&s.clk, 1));
         HIPTRY(dalloc(&s.sig, 12));
+        HIPTRY(dalloc(&s.img, N));
     }
     const hipMemcpyKind D = hipMemcpyDeviceToDevice;
     hipStream_t st = h->stream;
@@ -1373,6 +1384,7 @@ dss_status snap_save(dss_handle *h, Snapshot &s)
     HIPTRY(hipMemcpyAsync(s.clk, h->clk, sizeof(DevClock), D, st));
     HIPTRY(hipMemcpyAsync(s.sig, h->sigma_last, 9 * sizeof(double), D, st));
     HIPTRY(hipMemcpyAsync(s.sig + 9, h->box_diag, 3 * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(s.img, h->img, N * sizeof(int), D, st));
     s.cur = h->cur;
     s.hh = h->hh;
     s.step = h->step;
@@ -1399,6 +1411,7 @@ dss_status snap_restore(dss_handle *h, const Snapshot &s)
     HIPTRY(hipMemcpyAsync(h->clk, s.clk, sizeof(DevClock), D, st));
     HIPTRY(hipMemcpyAsync(h->sigma_last, s.sig, 9 * sizeof(double), D, st));
     HIPTRY(hipMemcpyAsync(h->box_diag, s.sig + 9, 3 * sizeof(double), D, st));
+    HIPTRY(hipMemcpyAsync(h->img, s.img, N * sizeof(int), D, st));
     h->cur = s.cur;
     h->hh = s.hh;
     h->step = s.step;
@@ -1731,6 +1744,7 @@ std::vector<StatePart> state_parts(dss_handle *h, int cur, int hh)
             {h->hcnt[hh], N * sizeof(int)},
             {h->hown[hh], N * sizeof(int)},
             {h->hxr[hh], h->hxr[hh] ? N * M * 3 * sizeof(double) : 0},
+            {h->img, N * sizeof(int)},
             {h->clk, sizeof(DevClock)},
             {h->sigma_last, 9 * B * sizeof(double)},
             {h->box_diag, 3 * B * sizeof(double)}};
@@ -1805,6 +1819,155 @@ dss_status dss_load_state(dss_handle *h, const void *blob, size_t bytes)
     h->hh = 0;
     h->step = hd.step;
     h->vel_is_half = hd.vel_is_half != 0;
+    return DSS_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------------
+// Observables (Sec. 3): shear-wise diffusivity and velocity autocorrelation from a
+// reference time, local volume fraction along y, clusters of contacting particles.
+// ----------------------------------------------------------------------------------
+namespace {
+
+// x and u^n by particle id into device buffers (3 N each).
+dss_status state_by_id(dss_handle *h, double *x, double *u)
+{
+    const int grid = (int)((h->N + kBlock - 1) / kBlock);
+    const int c = h->cur;
+    hipLaunchKernelGGL(k_unsort, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c],
+                       h->fb(), h->vel_is_half ? 1 : 0, 1, x, u, (double *)nullptr, (double *)nullptr,
+                       (double *)nullptr);
+    HIPTRY(hipGetLastError());
+    return DSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dss_status dss_observe_start(dss_handle *h)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "observables run on single-box handles");
+    const int64_t N = h->N;
+    if (!h->obs_y0) {
+        HIPTRY(dalloc(&h->obs_y0, N));
+        HIPTRY(dalloc(&h->obs_v0, N));
+    }
+    double *x = nullptr, *u = nullptr;
+    HIPTRY(dalloc(&x, 3 * N));
+    HIPTRY(dalloc(&u, 3 * N));
+    s = state_by_id(h, x, u);
+    if (!s) {
+        const int grid = (int)((N + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_obs_ref, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, h->boxes[0].L[1], x, u, h->img,
+                           h->obs_y0, h->obs_v0);
+        HIPTRY(hipGetLastError());
+        HIPTRY(hipStreamSynchronize(h->stream));
+        h->obs_step0 = h->step;
+    }
+    (void)hipFree(x);
+    (void)hipFree(u);
+    return s;
+}
+
+dss_status dss_observe(dss_handle *h, double out[4])
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (!out) return fail(h, DSS_ERR_ARG, "null output");
+    if (h->obs_step0 < 0) return fail(h, DSS_ERR_STATE, "no reference: call dss_observe_start first");
+    const int64_t N = h->N;
+    const int grid = (int)((N + kBlock - 1) / kBlock);
+    double *x = nullptr, *u = nullptr, *part = nullptr;
+    HIPTRY(dalloc(&x, 3 * N));
+    HIPTRY(dalloc(&u, 3 * N));
+    HIPTRY(dalloc(&part, 3 * (size_t)grid));
+    s = state_by_id(h, x, u);
+    std::vector<double> hp(3 * (size_t)grid);
+    if (!s) {
+        hipLaunchKernelGGL(k_obs_sums, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, h->boxes[0].L[1], x, u, h->img,
+                           h->obs_y0, h->obs_v0, part);
+        HIPTRY(hipGetLastError());
+        HIPTRY(hipMemcpy(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    (void)hipFree(x);
+    (void)hipFree(u);
+    (void)hipFree(part);
+    if (s) return s;
+    double sum[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < grid; ++b)
+        for (int k = 0; k < 3; ++k) sum[k] += hp[3 * (size_t)b + k];
+    const double elapsed = (double)(h->step - h->obs_step0) * h->prm.dt;
+    const double msd = sum[0] / (double)N;
+    const double gd = h->boxes[0].gd != 0.0 ? h->boxes[0].gd : 1.0;
+    out[0] = elapsed > 0.0 ? msd / (2.0 * elapsed * h->prm.a0 * h->prm.a0 * gd) : 0.0;
+    out[1] = sum[2] > 0.0 ? sum[1] / sum[2] : 0.0;
+    out[2] = msd;
+    out[3] = elapsed;
+    return DSS_OK;
+}
+
+dss_status dss_phi_profile(dss_handle *h, int32_t nbins, double a_split, double *phi)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "observables run on single-box handles");
+    if (nbins < 1 || nbins > 2048 || !phi) return fail(h, DSS_ERR_ARG, "nbins in [1, 2048] and phi non-null");
+    const int64_t N = h->N;
+    const int grid = (int)((N + kBlock - 1) / kBlock);
+    double *part = nullptr;
+    HIPTRY(dalloc(&part, 2 * (size_t)nbins * grid));
+    const BoxParams &G = h->boxes[0];
+    hipLaunchKernelGGL(k_phi_profile, dim3(grid), dim3(kBlock), 2 * (size_t)nbins * sizeof(double), h->stream, (int)N,
+                       G.L[1], (int)nbins, a_split, h->pa[h->cur], part);
+    HIPTRY(hipGetLastError());
+    std::vector<double> hp(2 * (size_t)nbins * grid);
+    HIPTRY(hipMemcpy(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost));
+    (void)hipFree(part);
+    const double slab = G.L[0] * G.L[2] * (G.L[1] / (double)nbins);
+    for (int k = 0; k < 2 * nbins; ++k) {
+        double t = 0.0;
+        for (int b = 0; b < grid; ++b) t += hp[(size_t)b * 2 * nbins + k];
+        phi[k] = t / slab;
+    }
+    return DSS_OK;
+}
+
+dss_status dss_contact_clusters(dss_handle *h, int64_t cap, int64_t *hist, int64_t *n_clusters, int64_t *largest)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (cap < 1 || !hist) return fail(h, DSS_ERR_ARG, "cap >= 1 and hist non-null");
+    const int64_t N = h->N;
+    const int grid = (int)((N + kBlock - 1) / kBlock);
+    int *parent = nullptr, *size = nullptr;
+    unsigned long long *dh = nullptr;
+    HIPTRY(dalloc(&parent, N));
+    HIPTRY(dalloc(&size, N));
+    HIPTRY(dalloc(&dh, cap));
+    HIPTRY(hipMemsetAsync(dh, 0, cap * sizeof(unsigned long long), h->stream));
+    hipLaunchKernelGGL(k_cc_init, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, parent, size);
+    hipLaunchKernelGGL(k_cc_hook, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, h->P.M, h->hown[h->hh],
+                       h->hkey[h->hh], h->hcnt[h->hh], parent);
+    hipLaunchKernelGGL(k_cc_count, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, parent, size);
+    hipLaunchKernelGGL(k_cc_hist, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, parent, size, (long long)cap, dh);
+    HIPTRY(hipGetLastError());
+    std::vector<unsigned long long> hh(cap);
+    HIPTRY(hipMemcpy(hh.data(), dh, cap * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    (void)hipFree(parent);
+    (void)hipFree(size);
+    (void)hipFree(dh);
+    int64_t nc = 0, big = 0;
+    for (int64_t k = 0; k < cap; ++k) {
+        hist[k] = (int64_t)hh[k];
+        nc += hist[k];
+        if (hist[k]) big = k + 1;
+    }
+    if (n_clusters) *n_clusters = nc;
+    if (largest) *largest = big;
     return DSS_OK;
 }
 

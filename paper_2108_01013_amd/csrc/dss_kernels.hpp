@@ -392,7 +392,8 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
                                                      double4 *__restrict__ omg, ForceBufs B, int vel_is_half,
                                                      int advance, const DevClock *__restrict__ clk,
                                                      int *__restrict__ cell, int *__restrict__ rank,
-                                                     int *__restrict__ count, int *__restrict__ fb_count)
+                                                     int *__restrict__ count, int *__restrict__ fb_count,
+                                                     int *__restrict__ img)
 {
 #pragma clang fp contract(off)
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -444,10 +445,12 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
             X.y -= G.L[1];
             X.x -= delta;
             V.x -= G.gd * G.L[1];
+            img[(int)W.w] += 1;  // y-face crossings, for the unwrapped shear-wise position
         } else if (X.y < 0.0) {
             X.y += G.L[1];
             X.x += delta;
             V.x += G.gd * G.L[1];
+            img[(int)W.w] -= 1;
         }
         X.x -= G.L[0] * floor(X.x / G.L[0]);
         X.z -= G.L[2] * floor(X.z / G.L[2]);

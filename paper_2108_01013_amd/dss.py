@@ -26,6 +26,7 @@ STATUS = {0: "DSS_OK", 1: "DSS_ERR_ARG", 2: "DSS_ERR_HIP", 3: "DSS_ERR_CAPACITY"
 
 EXPORTS = ["dss_create", "dss_create_batch", "dss_set_particles", "dss_set_particles_batch", "dss_set_step", "dss_build_neighbours", "dss_compute_forces", "dss_step",
            "dss_read_stress", "dss_read_stress_batch", "dss_get_box_info", "dss_get_state", "dss_get_eval_velocities", "dss_get_pairs", "dss_get_cells", "dss_get_rolling_history",
+           "dss_observe_start", "dss_observe", "dss_phi_profile", "dss_contact_clusters",
            "dss_get_history", "dss_get_info", "dss_save_state", "dss_load_state", "dss_set_timing",
            "dss_get_timing", "dss_set_tuning", "dss_get_tuning", "dss_adjoint", "dss_last_error",
            "dss_status_string", "dss_destroy"]
@@ -104,6 +105,10 @@ def load_library():
         "dss_get_cells": (st, [H, vp, i64, vp, vp]),
         "dss_get_history": (st, [H, i64, vp, vp, ctypes.POINTER(i64)]),
         "dss_get_rolling_history": (st, [H, i64, vp, vp, ctypes.POINTER(i64)]),
+        "dss_observe_start": (st, [H]),
+        "dss_observe": (st, [H, vp]),
+        "dss_phi_profile": (st, [H, ctypes.c_int32, ctypes.c_double, vp]),
+        "dss_contact_clusters": (st, [H, i64, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "dss_get_info": (st, [H, ctypes.POINTER(Info)]),
         "dss_save_state": (st, [H, vp, ctypes.POINTER(ctypes.c_size_t)]),
         "dss_load_state": (st, [H, vp, ctypes.c_size_t]),
@@ -358,6 +363,32 @@ class Simulation:
                                          ctypes.c_void_p(wt.ctypes.data), ctypes.byref(J),
                                          ctypes.c_void_p(th.ctypes.data), *[q[0] for q in ptrs], 1))
         return J.value, th[0], th[1]
+
+    def observe_start(self):
+        """The current state becomes the reference time of observe()."""
+        self._check(self.lib.dss_observe_start(self.h))
+
+    def observe(self) -> dict:
+        """Shear-wise diffusivity D_y (eq. diffY) and velocity autocorrelation C_v (eq. corrV)
+        since observe_start, with the mean squared shear-wise displacement and t - t0."""
+        out = np.zeros(4)
+        self._check(self.lib.dss_observe(self.h, ctypes.c_void_p(out.ctypes.data)))
+        return {"D_y": out[0], "C_v": out[1], "msd_y": out[2], "elapsed": out[3]}
+
+    def phi_profile(self, nbins: int, a_split: float) -> np.ndarray:
+        """Local volume fraction along y: (2, nbins), row 0 radius <= a_split, row 1 larger."""
+        phi = np.zeros(2 * nbins)
+        self._check(self.lib.dss_phi_profile(self.h, int(nbins), float(a_split), ctypes.c_void_p(phi.ctypes.data)))
+        return phi.reshape(2, nbins)
+
+    def contact_clusters(self, cap: int | None = None) -> np.ndarray:
+        """Histogram of the sizes of clusters of contacting particles: h[s - 1] clusters of s."""
+        cap = int(cap or self.N)
+        hist = np.zeros(cap, np.int64)
+        nc, big = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(self.lib.dss_contact_clusters(self.h, cap, ctypes.c_void_p(hist.ctypes.data), ctypes.byref(nc),
+                                                  ctypes.byref(big)))
+        return hist
 
     def save_state(self) -> bytes:
         """Snapshot of the whole time-stepping state (host bytes)."""
