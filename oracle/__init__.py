@@ -45,12 +45,13 @@ def build() -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double * 3)] + [(n, ctypes.c_double) for n in (
         "shear_rate", "eta0", "rho", "kn", "kt", "gamma_n", "mu", "F_ER", "lambda_D", "a0",
-        "hamaker", "eps_vdw", "eps_lub", "cutoff_factor", "dt", "ec_ranges", "kr", "mu_r")]
+        "hamaker", "eps_vdw", "eps_lub", "cutoff_factor", "dt", "ec_ranges", "kr", "mu_r", "wave_amp",
+        "wave_n")]
 
 
 # optional parameters and their defaults (R18: electro-chemical forces over their own ranges;
-# R19: rolling resistance, off at k_r = 0)
-_OPTIONAL = {"ec_ranges": 0.0, "kr": 0.0, "mu_r": 0.0}
+# R19: rolling resistance, off at k_r = 0; R20: wavy shear, off at wave_amp = 0)
+_OPTIONAL = {"ec_ranges": 0.0, "kr": 0.0, "mu_r": 0.0, "wave_amp": 0.0, "wave_n": 0.0}
 
 
 PARAM_NAMES = [f[0] for f in _Params._fields_]
@@ -83,9 +84,10 @@ def lib():
         "orc_lub_matrix": (None, [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _c_double_p,
                                   _c_double_p]),
         "orc_lub_strain_terms": (None, [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _c_double_p,
-                                        _c_double_p]),
-        "orc_pair_eval": (None, [P, ctypes.c_double, ctypes.c_double, _c_double_p, _c_double_p, _c_double_p,
-                                 _c_double_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p]),
+                                        ctypes.c_double, ctypes.c_double, _c_double_p]),
+        "orc_pair_eval": (None, [P, ctypes.c_double, ctypes.c_double, _c_double_p, ctypes.c_double, ctypes.c_double,
+                                 _c_double_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
+                                 _c_double_p]),
         "orc_forces": (ctypes.c_int64, [P, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
                                         ctypes.c_int64, ctypes.c_int, ctypes.c_int64, _c_int32_p, _c_double_p,
                                         _c_double_p, ctypes.c_int64, _c_int32_p, _c_double_p, _c_double_p,
@@ -227,19 +229,24 @@ def lub_matrix(p, ai, aj, h, n) -> np.ndarray:
     return R
 
 
-def lub_strain_terms(p, ai, aj, h, n) -> np.ndarray:
-    """The 12-vector (F_i, F_j, T_i, T_j) of eq. (rlu1) applied to (n, n, n_perp_i, n_perp_j)."""
+def lub_strain_terms(p, ai, aj, h, n, yi=0.0, yj=0.0) -> np.ndarray:
+    """The 12-vector (F_i, F_j, T_i, T_j) of eq. (rlu1) applied to (n, n, n_perp_i, n_perp_j),
+    with the ambient strain of each column taken at that particle's height."""
     out = np.zeros(12)
-    lib().orc_lub_strain_terms(ctypes.byref(_params(p)), float(ai), float(aj), float(h), _d(_f64(n)), _d(out))
+    lib().orc_lub_strain_terms(ctypes.byref(_params(p)), float(ai), float(aj), float(h), _d(_f64(n)), float(yi),
+                               float(yj), _d(out))
     return out
 
 
-def pair_eval(p, ai, aj, r, upi, upj, wi, wj, xi_old=(0.0, 0.0, 0.0), xr_old=(0.0, 0.0, 0.0)) -> dict:
+def pair_eval(p, ai, aj, r, upi, upj, wi, wj, xi_old=(0.0, 0.0, 0.0), xr_old=(0.0, 0.0, 0.0), yi=0.0,
+              yj=0.0) -> dict:
     """One listed pair; velocities u' are fluctuations u - U_inf(x), w raw angular velocities;
-    xi_old, xr_old: stored tangential and rolling stretches."""
+    xi_old, xr_old: stored tangential and rolling stretches; yi, yj: the wrapped heights of the
+    two particles (the ambient rotation and strain depend on them in the wavy shear)."""
     out = np.zeros(PAIR_OUT)
-    lib().orc_pair_eval(ctypes.byref(_params(p)), float(ai), float(aj), _d(_f64(r)), _d(_f64(upi)),
-                        _d(_f64(upj)), _d(_f64(wi)), _d(_f64(wj)), _d(_f64(xi_old)), _d(_f64(xr_old)), _d(out))
+    lib().orc_pair_eval(ctypes.byref(_params(p)), float(ai), float(aj), _d(_f64(r)), float(yi), float(yj),
+                        _d(_f64(upi)), _d(_f64(upj)), _d(_f64(wi)), _d(_f64(wj)), _d(_f64(xi_old)),
+                        _d(_f64(xr_old)), _d(out))
     return {
         "FL_i": out[0:3], "FL_j": out[3:6], "TL_i": out[6:9], "TL_j": out[9:12],
         "FC_i": out[12:15], "FC_j": out[15:18], "TC_i": out[18:21], "TC_j": out[21:24],
@@ -317,17 +324,30 @@ class State:
                                                          self.history.rolling().copy()))
 
 
+def _wave(p):
+    """(W, k) of the wavy shear, eq. (uinf), k = 2 pi n / L_y; W = 0 for the simple shear."""
+    return float(p.get("wave_amp", 0.0)), 2.0 * math.pi * float(p.get("wave_n", 0.0)) / p["L"][1]
+
+
 def ambient_velocity(p, x):
-    """U_inf(x) = (gdot y, 0, 0) for the simple shear of Sec. 2."""
+    """U_inf(x) = (gdot y + W sin(k y), 0, 0): the simple shear of Sec. 2 with the wave of eq. (uinf)."""
     x = _f64(x, (-1, 3))
     U = np.zeros_like(x)
     U[:, 0] = p["shear_rate"] * x[:, 1]
+    W, k = _wave(p)
+    if W != 0.0:
+        U[:, 0] += W * np.sin(k * x[:, 1])
     return U
 
 
-def ambient_rotation(p, N):
+def ambient_rotation(p, N, x=None):
+    """Omega_inf = (0, 0, -(gdot + W k cos(k y)) / 2) at each particle (x needed for the wave)."""
     W = np.zeros((N, 3))
-    W[:, 2] = -0.5 * p["shear_rate"]
+    Wa, k = _wave(p)
+    if Wa != 0.0:
+        W[:, 2] = -0.5 * (p["shear_rate"] + Wa * k * np.cos(k * _f64(x, (-1, 3))[:, 1]))
+    else:
+        W[:, 2] = -0.5 * p["shear_rate"]
     return W
 
 
@@ -349,7 +369,7 @@ def init_state(p, x, rad, u=None, w=None, use_cells=False):
     x = _f64(x, (-1, 3)).copy()
     rad = _f64(rad).copy()
     u = ambient_velocity(p, x) if u is None else _f64(u, (-1, 3)).copy()
-    w = ambient_rotation(p, len(rad)) if w is None else _f64(w, (-1, 3)).copy()
+    w = ambient_rotation(p, len(rad), x) if w is None else _f64(w, (-1, 3)).copy()
     F, T, S, H, npairs = forces(p, x, u, w, rad, 0, None, use_cells)
     a, aw = accelerations(p, rad, F, T)
     return State(x, u, w, a, aw, rad, 0, History()), F, T, S

@@ -37,6 +37,13 @@
  *       |F_nor| including the dashpot; xi_old = 0 at first contact;
  *   R12 every listed pair (|r| < c (a_i + a_j)) gets lubrication; repulsion and
  *       attraction are truncated at the same list.
+ *   R20 wavy shear, eq. (uinf): U_inf = (gdot y + W sin(k y), 0, 0), k = 2 pi n / L_y,
+ *       so Omega_inf(y) = (0, 0, -(gdot + W k cos(k y)) / 2) and E_inf_xy(y) = E_inf_yx(y) =
+ *       (gdot + W k cos(k y)) / 2 at each particle's own wrapped y; Faxen terms of eq. (rst)
+ *       (F = -6 pi eta0 a [u - U_inf - a^2/6 lap U_inf]) and of the stresslet S^S
+ *       ((1 + a^2/10 lap) E_inf_i); R'(E) takes E_i and E_j at the two particles; the
+ *       2 eta0 E_inf of eq. (stress) is the box average (gdot/2: the wave averages out); the
+ *       sine part is periodic in y, so the Lees-Edwards shift stays gdot L_y.
  *   R19 rolling resistance (Appendix roll), with k_r > 0: a second spring per
  *       contact, xi^r* = T(xi^r_old + u_r dt) with u_r = a_ij (n x w_i - n x w_j),
  *       a_ij = 2 a_i a_j / (a_i + a_j), capped when |xi^r*| >= mu_r |F_nor| / k_r
@@ -82,32 +89,61 @@ typedef struct {
     double ec_ranges;     /* 1: electro-chemical forces over their own ranges (R18) */
     double kr;            /* rolling spring stiffness k_r (0: no rolling resistance, R19) */
     double mu_r;          /* rolling Coulomb coefficient (R19) */
+    double wave_amp;      /* amplitude W of the wavy shear, eq. (uinf) (0: simple shear, R20) */
+    double wave_n;        /* spatial periods n of the wave in L_y */
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
-/* Ambient flow: simple shear along x, gradient along y (Sec. 2):             */
-/*   U_inf(x) = (gdot y, 0, 0), Omega_inf = (0, 0, -gdot/2),                  */
-/*   E_inf_12 = E_inf_21 = gdot/2.                                            */
+/* Ambient flow: shear along x, gradient along y (Sec. 2), with the wave of   */
+/* eq. (uinf) (R20):                                                          */
+/*   U_inf(x) = (gdot y + W sin(k y), 0, 0),  k = 2 pi n / L_y,               */
+/*   dU/dy = gdot + W k cos(k y),  Omega_inf = (0, 0, -dU/dy / 2),            */
+/*   E_inf_12 = E_inf_21 = dU/dy / 2;  W = 0 is the simple shear.             */
 /* ------------------------------------------------------------------------- */
+static double wave_k(const orc_params *p) { return 2.0 * M_PI * p->wave_n / p->L[1]; }
+
+static double shear_at(const orc_params *p, double y) /* dU/dy */
+{
+    if (p->wave_amp == 0.0) return p->shear_rate;
+    double k = wave_k(p);
+    return p->shear_rate + p->wave_amp * k * cos(k * y);
+}
+
 static void ambient_U(const orc_params *p, const double *x, double *U)
 {
     U[0] = p->shear_rate * x[1];
+    if (p->wave_amp != 0.0) U[0] += p->wave_amp * sin(wave_k(p) * x[1]);
     U[1] = 0.0;
     U[2] = 0.0;
 }
 
-static void ambient_Omega(const orc_params *p, double *W)
+static void ambient_Omega(const orc_params *p, double y, double *W)
 {
     W[0] = 0.0;
     W[1] = 0.0;
-    W[2] = -0.5 * p->shear_rate;
+    W[2] = -0.5 * shear_at(p, y);
 }
 
-static void ambient_E(const orc_params *p, double E[3][3])
+static void ambient_E(const orc_params *p, double y, double E[3][3])
 {
     memset(E, 0, 9 * sizeof(double));
-    E[0][1] = 0.5 * p->shear_rate;
-    E[1][0] = 0.5 * p->shear_rate;
+    E[0][1] = 0.5 * shear_at(p, y);
+    E[1][0] = 0.5 * shear_at(p, y);
+}
+
+/* Faxen Laplacians: lap U_inf = (-W k^2 sin(k y), 0, 0); lap E_inf_xy = -W k^3 cos(k y) / 2 */
+static double lap_Ux(const orc_params *p, double y)
+{
+    if (p->wave_amp == 0.0) return 0.0;
+    double k = wave_k(p);
+    return -p->wave_amp * k * k * sin(k * y);
+}
+
+static double lap_Exy(const orc_params *p, double y)
+{
+    if (p->wave_amp == 0.0) return 0.0;
+    double k = wave_k(p);
+    return -0.5 * p->wave_amp * k * k * k * cos(k * y);
 }
 
 /* small vector helpers */
@@ -556,30 +592,40 @@ void orc_lub_matrix(const orc_params *p, double ai, double aj, double h, const d
         for (int b = 0; b < a; ++b) R[a][b] = R[b][a];
 }
 
-/* eq. (rlu1) applied to (n, n, n_perp_i, n_perp_j) (readings R3, R4): returns
- * the 12-vector (F_i, F_j, T_i, T_j) of the ambient-strain terms. */
-void orc_lub_strain_terms(const orc_params *p, double ai, double aj, double h, const double *n, double *out12)
+/* The strain quantities of eq. (rlu1) for the ambient strain at height y:
+ * P = E : N - Tr E / 3, Q n = 2 E n - 2 (E : N) n, n_perp = 2 n x (E n) (R3, R4). */
+static void strain_terms_at(const orc_params *p, double y, const double *n, double *P, double *Qn, double *nperp)
 {
-    lub_coeffs c;
-    lubrication_coefficients(p, ai, aj, h, &c);
     double E[3][3];
-    ambient_E(p, E); /* E_i = E_j = E_inf for a linear ambient flow */
+    ambient_E(p, y, E);
     double EN = 0.0, trE = E[0][0] + E[1][1] + E[2][2];
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) EN += E[a][b] * n[a] * n[b];
-    double P = EN - trE / 3.0; /* P I = (E : N - Tr E / 3) I */
-    double Qn[3];              /* Q n = (2 E - 2 (E : N) I) n */
+    *P = EN - trE / 3.0;
     double En[3];
     matvec3((const double (*)[3])E, n, En);
     for (int a = 0; a < 3; ++a) Qn[a] = 2.0 * En[a] - 2.0 * EN * n[a];
-    double nperp[3];
     cross3(n, En, nperp);
-    for (int a = 0; a < 3; ++a) nperp[a] *= 2.0; /* n_perp = 2 n x (E n), R4 */
+    for (int a = 0; a < 3; ++a) nperp[a] *= 2.0;
+}
+
+/* eq. (rlu1) applied to (n, n, n_perp_i, n_perp_j) (readings R3, R4): returns
+ * the 12-vector (F_i, F_j, T_i, T_j) of the ambient-strain terms; column i of
+ * the matrix takes the strain E_i at particle i (height yi), column j E_j (R20;
+ * E_i = E_j for the simple shear). */
+void orc_lub_strain_terms(const orc_params *p, double ai, double aj, double h, const double *n, double yi,
+                          double yj, double *out12)
+{
+    lub_coeffs c;
+    lubrication_coefficients(p, ai, aj, h, &c);
+    double Pi, Pj, Qi[3], Qj[3], npi[3], npj[3];
+    strain_terms_at(p, yi, n, &Pi, Qi, npi);
+    strain_terms_at(p, yj, n, &Pj, Qj, npj);
     for (int a = 0; a < 3; ++a) {
-        out12[a] = (c.XG_ii * P * n[a] + c.YG_ii * Qn[a]) + (c.XG_ji * P * n[a] + c.YG_ji * Qn[a]);
-        out12[3 + a] = (c.XG_ij * P * n[a] + c.YG_ij * Qn[a]) + (c.XG_jj * P * n[a] + c.YG_jj * Qn[a]);
-        out12[6 + a] = c.YH_ii * nperp[a] + c.YH_ji * nperp[a];
-        out12[9 + a] = c.YH_ij * nperp[a] + c.YH_jj * nperp[a];
+        out12[a] = (c.XG_ii * Pi * n[a] + c.YG_ii * Qi[a]) + (c.XG_ji * Pj * n[a] + c.YG_ji * Qj[a]);
+        out12[3 + a] = (c.XG_ij * Pi * n[a] + c.YG_ij * Qi[a]) + (c.XG_jj * Pj * n[a] + c.YG_jj * Qj[a]);
+        out12[6 + a] = c.YH_ii * npi[a] + c.YH_ji * npj[a];
+        out12[9 + a] = c.YH_ij * npi[a] + c.YH_jj * npj[a];
     }
 }
 
@@ -597,8 +643,8 @@ void orc_lub_strain_terms(const orc_params *p, double ai, double aj, double h, c
 /* ------------------------------------------------------------------------- */
 #define ORC_PAIR_OUT 67
 
-void orc_pair_eval(const orc_params *p, double ai, double aj, const double *r, const double *upi,
-                   const double *upj, const double *wi, const double *wj, const double *xi_old,
+void orc_pair_eval(const orc_params *p, double ai, double aj, const double *r, double yi, double yj,
+                   const double *upi, const double *upj, const double *wi, const double *wj, const double *xi_old,
                    const double *xr_old, double *out)
 {
     memset(out, 0, ORC_PAIR_OUT * sizeof(double));
@@ -607,19 +653,20 @@ void orc_pair_eval(const orc_params *p, double ai, double aj, const double *r, c
     double h = dist - ai - aj; /* surface distance d_ij */
 
     /* --- lubrication, eq. (hydro): F = -R_Lub . (u'_i, u'_j, w'_i, w'_j) + R'(E) . (n, n, n_perp) */
-    double W[3];
-    ambient_Omega(p, W);
+    double Wi[3], Wj[3];
+    ambient_Omega(p, yi, Wi);
+    ambient_Omega(p, yj, Wj);
     double V[12];
     for (int a = 0; a < 3; ++a) {
         V[a] = upi[a];
         V[3 + a] = upj[a];
-        V[6 + a] = wi[a] - W[a];
-        V[9 + a] = wj[a] - W[a];
+        V[6 + a] = wi[a] - Wi[a];
+        V[9 + a] = wj[a] - Wj[a];
     }
     double R[12][12];
     orc_lub_matrix(p, ai, aj, h, n, &R[0][0]);
     double strain[12];
-    orc_lub_strain_terms(p, ai, aj, h, n, strain);
+    orc_lub_strain_terms(p, ai, aj, h, n, yi, yj, strain);
     double FL[12];
     for (int a = 0; a < 12; ++a) {
         double acc = 0.0;
@@ -637,8 +684,10 @@ void orc_pair_eval(const orc_params *p, double ai, double aj, const double *r, c
     for (int a = 0; a < 12; ++a) out[a] = FL[a];
 
     /* true relative velocity u_j - u_i of the image pair: the ambient flow
-     * difference across r is gdot r_y along x for simple shear */
+     * difference across r is gdot r_y along x for simple shear, plus the
+     * difference of the wave at the two wrapped heights (R20) */
     double du[3] = {upj[0] - upi[0] + p->shear_rate * r[1], upj[1] - upi[1], upj[2] - upi[2]};
+    if (p->wave_amp != 0.0) du[0] += p->wave_amp * (sin(wave_k(p) * yj) - sin(wave_k(p) * yi));
 
     /* --- contact, eqs. (contact0), (csi) */
     if (h < 0.0) {
@@ -802,18 +851,19 @@ int64_t orc_forces(const orc_params *p, int64_t N, const double *x, const double
         }
         int64_t e = history_find(nh_old, hpair_old, a, b);
         double zero[3] = {0.0, 0.0, 0.0};
-        orc_pair_eval(p, rad[a], rad[b], r, upa, upb, w + 3 * a, w + 3 * b, e >= 0 ? hxi_old + 3 * e : zero,
+        orc_pair_eval(p, rad[a], rad[b], r, x[3 * a + 1], x[3 * b + 1], upa, upb, w + 3 * a, w + 3 * b,
+                      e >= 0 ? hxi_old + 3 * e : zero,
                       (e >= 0 && hxr_old) ? hxr_old + 3 * e : zero, res + (size_t)k * ORC_PAIR_OUT);
     }
 
-    /* per-particle terms: Stokes drag and torque, eq. (rst) (the Faxen
-     * Laplacian vanishes for a linear ambient flow) */
-    double W[3];
-    ambient_Omega(p, W);
+    /* per-particle terms: Stokes drag and torque, eq. (rst), with the Faxen
+     * Laplacian of the wave (zero for the simple shear, R20) */
     for (int64_t i = 0; i < N; ++i) {
-        double U[3];
+        double U[3], W[3];
         ambient_U(p, x + 3 * i, U);
+        ambient_Omega(p, x[3 * i + 1], W);
         double a = rad[i];
+        if (p->wave_amp != 0.0) U[0] += a * a / 6.0 * lap_Ux(p, x[3 * i + 1]);
         for (int c = 0; c < 3; ++c) {
             F[3 * i + c] = -6.0 * M_PI * p->eta0 * a * (u[3 * i + c] - U[c]);
             T[3 * i + c] = -8.0 * M_PI * p->eta0 * a * a * a * (w[3 * i + c] - W[c]);
@@ -847,15 +897,24 @@ int64_t orc_forces(const orc_params *p, int64_t N, const double *x, const double
         }
     }
     *nh_new = nh;
-    /* bulk stress, eq. (stress): 2 eta0 E + (1/V)(sum_i S^S_i + sum_pairs S) */
+    /* bulk stress, eq. (stress): 2 eta0 <E> + (1/V)(sum_i S^S_i + sum_pairs S);
+     * <E> the box average of the ambient strain (gdot/2: the wave averages out) */
     double E[3][3];
-    ambient_E(p, E);
+    memset(E, 0, sizeof(E));
+    E[0][1] = E[1][0] = 0.5 * p->shear_rate;
     double V = p->L[0] * p->L[1] * p->L[2];
+    double SSxy = 0.0; /* sum_i 20/3 pi eta0 a^3 (1 + a^2/10 lap) E_i, xy component */
     double sum_a3 = 0.0;
     for (int64_t i = 0; i < N; ++i) sum_a3 += rad[i] * rad[i] * rad[i];
+    if (p->wave_amp != 0.0)
+        for (int64_t i = 0; i < N; ++i) {
+            double a = rad[i], y = x[3 * i + 1];
+            SSxy += 20.0 / 3.0 * M_PI * p->eta0 * a * a * a * (0.5 * shear_at(p, y) + a * a / 10.0 * lap_Exy(p, y));
+        }
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
             double SS = 20.0 / 3.0 * M_PI * p->eta0 * sum_a3 * E[a][b];
+            if (p->wave_amp != 0.0) SS = ((a == 0 && b == 1) || (a == 1 && b == 0)) ? SSxy : 0.0;
             Sigma[3 * a + b] = 2.0 * p->eta0 * E[a][b] + (SS + S[3 * a + b]) / V;
         }
     free(res);

@@ -760,3 +760,56 @@ def test_diffusivity_and_autocorrelation_hand_values():
     D = oracle.shear_diffusivity(p, y0, y1, 0.5)
     assert abs(D - ((0.15 ** 2 + 0.3 ** 2) / 2) / (2 * 0.5 * 2.0)) < 1e-15
     assert oracle.velocity_autocorrelation([1.0, -2.0], [0.5, -1.0]) == (0.5 + 2.0) / (0.25 + 1.0)
+
+
+# ---------------------------------------------------------------------------------------------
+# R20: wavy shear, eq. (uinf).  A free sphere at height y relaxes, with the discrete solution of
+# P7, to the Faxen velocity u_x* = gdot y + W sin(k y) (1 - a^2 k^2 / 6) and to the local
+# rotation -(gdot + W k cos(k y)) / 2; the stress of free spheres is the Faxen stresslet sum;
+# each column of R'(E) takes its own particle's strain (linearity), and each column is
+# force-free (action-reaction); W = 0 leaves every result unchanged.
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("a,y", [(1.0, 3.3), (1.4, 14.1)])
+def test_free_sphere_in_wavy_shear(a, y):
+    L = 20.0
+    gd, Wa, nw = 0.7, 4.0, 2.0
+    p = params(L=L, shear_rate=gd, dt=2e-3, wave_amp=Wa, wave_n=nw)
+    k = 2 * math.pi * nw / L
+    x = np.array([[7.0, y, 9.0]])
+    rad = np.array([a])
+    st, F, T, S = oracle.init_state(p, x, rad, u=np.zeros((1, 3)), w=np.zeros((1, 3)))
+    zr = p["dt"] * 15.0 * p["eta0"] / (p["rho"] * a * a)
+    zt = p["dt"] * 9.0 * p["eta0"] / (2.0 * p["rho"] * a * a)
+    ux_star = gd * y + Wa * math.sin(k * y) * (1.0 - a * a * k * k / 6.0)
+    wz_star = -0.5 * (gd + Wa * k * math.cos(k * y))
+    for n in range(1, 300):
+        st, F, T, S, npairs, _ = oracle.step(p, st)
+        assert npairs == 0
+        fz = 1.0 - (1.0 - zr / 2) ** 2 * (1.0 - zr) ** (n - 1)
+        ft = 1.0 - (1.0 - zt / 2) ** 2 * (1.0 - zt) ** (n - 1)
+        assert abs(st.w[0, 2] - wz_star * fz) <= 1e-12 * abs(wz_star)
+        assert abs(st.u[0, 0] - ux_star * ft) <= 1e-12 * abs(ux_star)
+    # stress of the free sphere: eta0 gdot + (20/3 pi eta0 a^3 (E_xy(y) + a^2/10 lap E_xy)) / V
+    Exy = 0.5 * (gd + Wa * k * math.cos(k * y))
+    lapE = -0.5 * Wa * k ** 3 * math.cos(k * y)
+    want = p["eta0"] * gd + 20.0 / 3.0 * math.pi * p["eta0"] * a ** 3 * (Exy + a * a / 10.0 * lapE) / L ** 3
+    assert abs(S[0, 1] - want) < 1e-14 and abs(S[1, 0] - want) < 1e-14 and abs(S[0, 0]) < 1e-15
+
+
+def test_wavy_strain_columns():
+    p = params(L=20.0, shear_rate=0.5, wave_amp=3.0, wave_n=1.0)
+    p0 = params(L=20.0, shear_rate=0.5)
+    rng = np.random.default_rng(4)
+    for _ in range(10):
+        n = unit(rng.normal(size=3))
+        ai, aj, h = 1.0, 1.4, 0.03 * rng.random()
+        yi, yj = rng.uniform(0, 20, 2)
+        sij = oracle.lub_strain_terms(p, ai, aj, h, n, yi, yj)
+        sji = oracle.lub_strain_terms(p, ai, aj, h, n, yj, yi)
+        sii = oracle.lub_strain_terms(p, ai, aj, h, n, yi, yi)
+        sjj = oracle.lub_strain_terms(p, ai, aj, h, n, yj, yj)
+        assert np.max(np.abs(sij + sji - sii - sjj)) <= 1e-12 * np.max(np.abs(sii) + np.abs(sjj))
+        assert np.max(np.abs(sij[0:3] + sij[3:6])) <= 1e-12 * np.max(np.abs(sij))       # force-free
+        assert not np.allclose(sij, sii)                                                  # E_j matters
+        assert np.array_equal(oracle.lub_strain_terms(p0, ai, aj, h, n, yi, yj),
+                              oracle.lub_strain_terms(p0, ai, aj, h, n))                 # W = 0: uniform
