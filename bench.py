@@ -112,12 +112,15 @@ def measured_traffic():
 
 def roofline(timing, N, ncell, contacts, capacity, traffic=None):
     ms_pairs, n_pairs_launch = timing["k_pairs"]
+    name = timing.get("name", "k_pairs")
+    if name != "k_pairs":
+        traffic = None      # the counters were taken on the row-tile kernel
     avg_pairs_s = ms_pairs / max(n_pairs_launch, 1) * 1e-3
     bytes_launch = pairs_kernel_bytes(N, ncell, contacts, capacity)
     achieved = bytes_launch / avg_pairs_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None if traffic is None else int(traffic),
-            "kernel": "k_pairs", "avg_launch_us": round(avg_pairs_s * 1e6, 3),
+            "kernel": name, "avg_launch_us": round(avg_pairs_s * 1e6, 3),
             "bytes_per_launch": int(bytes_launch)}
 
 
@@ -163,14 +166,22 @@ def run_single(args):
     from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Simulation
     prec = DSS_FP64 if args.precision == "fp64" else DSS_MIXED
     torch.cuda.set_device(0)
-    p = w.params
+    p = dict(w.params)
+    physics = []
+    if args.rolling:
+        p.update(kr=0.05 * p["kn"], mu_r=0.1)
+        physics.append("rolling resistance k_r=0.05 k_n mu_r=0.1")
+    if args.ec_ranges:
+        p.update(ec_ranges=True, hamaker=1e-3)
+        physics.append("electro-chemical ranges (repulsion < 20 lambda_D, attraction A=1e-3 < 4 a0)")
     sim = Simulation(p, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
     sim.set_particles(w.x, w.rad)
     N = len(w.rad)
     tuned = maybe_tune(sim, args)
-    el, timing, breakdown = timed_run(sim, N, args, 10)
+    el, timing, breakdown = timed_run(sim, N, args, 10, kernels=["k_pairs", "k_pairs_rows"])
     info = sim.info()
     _, sigma_mean, nsamp = sim.read_stress()
+    obs = observables_timing(sim) if args.observables else None
     if info["error_flags"]:
         print(f"# device error flags {info['error_flags']}", file=sys.stderr)
         sys.exit(1)
@@ -183,18 +194,50 @@ def run_single(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"single box N={N} bidisperse 1:1.4 equal volume, phi=0.55, LE shear rate 1, "
-                               f"mu=1, dt=1e-4, stress every 10 steps, {args.precision}",
+                               f"mu=1, dt=1e-4, stress every 10 steps, {args.precision}"
+                               + "".join(", " + x for x in physics),
                    "N": N, "phi": 0.55, "precision": args.precision},
-        "roofline": roofline(timing, N, ncell, info["n_contacts"], info["capacity"],
-                             measured_traffic() if args.precision == "fp64" and N == 100_000 else None),
+        "roofline": roofline(dominant_pairs(timing), N, ncell, info["n_contacts"], info["capacity"],
+                             measured_traffic() if args.precision == "fp64" and N == 100_000 and not physics
+                             else None),
         "cpu_baseline": cpu,
         "kernels": kernel_table(breakdown),
+        "observables_ms": obs,
         "tuning": tuned or sim.tuning(),
         "diagnostics": {"n_pairs": info["n_pairs"], "n_contacts": info["n_contacts"],
                         "max_row_fill": info["max_row_fill"], "capacity": info["capacity"],
                         "cells": info["cells"], "stress_samples": nsamp,
                         "eta_r_mean": float(sigma_mean[0, 1] / (p["eta0"] * p["shear_rate"]))},
     }
+
+
+def dominant_pairs(timing):
+    """The pair kernel that took longer over the timed region: the row tiles (k_pairs) or the
+    rows they deferred to the per-particle path (k_pairs_rows), under the name k_pairs."""
+    dom = max(("k_pairs", "k_pairs_rows"), key=lambda k: timing.get(k, (0.0, 0))[0])
+    return {"k_pairs": timing[dom], "name": dom}
+
+
+def observables_timing(sim):
+    """Wall time of each observable call after the timed region (each synchronises)."""
+    out = {}
+    t0 = time.perf_counter()
+    sim.observe_start()
+    out["observe_start"] = (time.perf_counter() - t0) * 1e3
+    sim.step(10, sync=True)
+    t0 = time.perf_counter()
+    ob = sim.observe()
+    out["observe"] = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    sim.phi_profile(64, 1.2)
+    out["phi_profile_64"] = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    h = sim.contact_clusters()
+    out["contact_clusters"] = (time.perf_counter() - t0) * 1e3
+    out = {k: round(v, 3) for k, v in out.items()}
+    nz = [i + 1 for i in range(len(h)) if h[i]]
+    out.update(D_y=ob["D_y"], C_v=ob["C_v"], largest_cluster=max(nz) if nz else 0)
+    return out
 
 
 def run_poly(args):
@@ -422,6 +465,10 @@ def main():
     ap.add_argument("--workload-cache", default=None, help="npz file to reuse the single-box workload")
     ap.add_argument("--copy-probe", action="store_true", help="end with plain 256 MiB device copies")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--rolling", action="store_true", help="single: with rolling resistance")
+    ap.add_argument("--ec-ranges", action="store_true",
+                    help="single: electro-chemical forces over their own ranges (with attraction)")
+    ap.add_argument("--observables", action="store_true", help="single: time the observables after the run")
     args = ap.parse_args()
     if args.tune is None:
         args.tune = 1 if args.mode == "sweep" else 0
