@@ -89,6 +89,10 @@ typedef struct {
     int32_t reserved;     /* must be 0 */
     double k_roll;        /* rolling spring stiffness k_r of Appendix roll (0 = no rolling resistance) */
     double mu_roll;       /* Coulomb coefficient of the rolling spring: |xi^r| <= mu_roll |F_nor| / k_r */
+    double wave_amp;      /* amplitude W of the wavy shear of eq. uinf, U_inf = (gdot y + W sin(k y), 0, 0),
+                           * k = 2 pi wave_n / L_y, with the Faxen terms of eqs. rst and stresslet
+                           * (0 = simple shear; not with the adjoint) */
+    double wave_n;        /* whole periods n of the wave along L_y (>= 1 when wave_amp != 0) */
 } dss_params;
 
 /* Diagnostics of the most recent force evaluation. */

@@ -482,8 +482,11 @@ dss_status setup_lattice(dss_handle *h)
         P.stage_cap = stage_cap;
         P.qcap = qcap;
     }
-    for (const void *k : {(const void *)k_pairs<double, false>, (const void *)k_pairs<float, false>,
-                          (const void *)k_pairs<double, true>, (const void *)k_pairs<float, true>})
+    for (const void *k :
+         {(const void *)k_pairs<double, false, false>, (const void *)k_pairs<float, false, false>,
+          (const void *)k_pairs<double, true, false>, (const void *)k_pairs<float, true, false>,
+          (const void *)k_pairs<double, false, true>, (const void *)k_pairs<float, false, true>,
+          (const void *)k_pairs<double, true, true>, (const void *)k_pairs<float, true, true>})
         HIPTRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->tile_lds));
     h->finish_r = (max_rows_box + 1023) / 1024;
     P.pstride = (std::max(nrow, max_rows_box) + 63) / 64 * 64;
@@ -512,12 +515,12 @@ enum EvalMode { EVAL_STEP = 0, EVAL_SORT = 1, EVAL_INPLACE = 2 };
 // The pair kernels of one evaluation: size-class stencils (lane and wavefront paths), or
 // the row tiles followed by the rows they deferred.  Real: FP64 or mixed arithmetic; Roll:
 // rolling resistance.
-template <typename Real, bool Roll>
+template <typename Real, bool Roll, bool Wave>
 void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
 {
     if (h->P.sized) {
         TimedLaunch t(h, 3);
-        hipExtLaunchKernelGGL(k_pairs_sized<Real, Roll>, dim3(h->sized_grid[0] + h->sized_grid[1]), dim3(kBlock), 0,
+        hipExtLaunchKernelGGL(k_pairs_sized<Real, Roll, Wave>, dim3(h->sized_grid[0] + h->sized_grid[1]), dim3(kBlock), 0,
                               h->stream, t.e0, t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf],
                               h->omg[buf], h->fb(), H, h->clk, h->partials, h->sized_grid[1], h->pairs,
                               h->pair_count);
@@ -525,7 +528,7 @@ void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
     }
     {
         TimedLaunch t(h, 3);
-        hipExtLaunchKernelGGL(k_pairs<Real, Roll>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0,
+        hipExtLaunchKernelGGL(k_pairs<Real, Roll, Wave>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0,
                               t.e1, 0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
                               h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, h->fb_rows,
                               h->fb_count);
@@ -537,7 +540,7 @@ void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
         TimedLaunch t(h, 7);
         const int hint = h->deferred_hint < 0 ? 64 : h->deferred_hint + h->deferred_hint / 4 + 8;
         const int grid = h->tune.tiled ? std::min(h->nrow_total, hint) : h->nrow_total;
-        hipExtLaunchKernelGGL(k_pairs_rows<Real, Roll>, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P,
+        hipExtLaunchKernelGGL(k_pairs_rows<Real, Roll, Wave>, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P,
                               h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(),
                               H, h->clk, h->partials, h->pairs, h->pair_count, (const int *)h->fb_rows,
                               (const int *)h->fb_count);
@@ -558,13 +561,17 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, boo
     H.xr_old = h->hxr[h->hh];
     H.xr_new = h->hxr[1 - h->hh];
     if (h->P.record_pairs) HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
-    const bool roll = h->P.kr > 0.0;
-    if (h->prm.precision == DSS_MIXED) {
-        if (roll) launch_pair_kernels<float, true>(h, buf, H);
-        else launch_pair_kernels<float, false>(h, buf, H);
-    } else {
-        if (roll) launch_pair_kernels<double, true>(h, buf, H);
-        else launch_pair_kernels<double, false>(h, buf, H);
+    const bool roll = h->P.kr > 0.0, wave = h->P.wave_amp != 0.0;
+    const int v = (h->prm.precision == DSS_MIXED ? 4 : 0) | (roll ? 2 : 0) | (wave ? 1 : 0);
+    switch (v) {
+    case 0: launch_pair_kernels<double, false, false>(h, buf, H); break;
+    case 1: launch_pair_kernels<double, false, true>(h, buf, H); break;
+    case 2: launch_pair_kernels<double, true, false>(h, buf, H); break;
+    case 3: launch_pair_kernels<double, true, true>(h, buf, H); break;
+    case 4: launch_pair_kernels<float, false, false>(h, buf, H); break;
+    case 5: launch_pair_kernels<float, false, true>(h, buf, H); break;
+    case 6: launch_pair_kernels<float, true, false>(h, buf, H); break;
+    default: launch_pair_kernels<float, true, true>(h, buf, H); break;
     }
     if (!finish) return DSS_OK;
     TimedLaunch t(h, 4);
@@ -730,7 +737,9 @@ static bool valid_params(const dss_params *p)
 {
     return (p->L[0] > 0 && p->L[1] > 0 && p->L[2] > 0) && p->dt > 0 && p->cutoff_factor > 0 && p->rho > 0 &&
            p->a0 > 0 && p->reserved == 0 && p->capacity >= 0 && p->k_roll >= 0 && p->mu_roll >= 0 &&
-           std::isfinite(p->k_roll) && std::isfinite(p->mu_roll) &&
+           std::isfinite(p->k_roll) && std::isfinite(p->mu_roll) && std::isfinite(p->wave_amp) &&
+           p->wave_n >= 0 && p->wave_n <= 1e6 && p->wave_n == std::floor(p->wave_n) &&
+           (p->wave_amp == 0.0 || p->wave_n >= 1) &&
            (p->precision == DSS_FP64 || p->precision == DSS_MIXED) && p->eps_lub > 0 &&
            std::isfinite(p->shear_rate);
 }
@@ -829,6 +838,7 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
         a_max = std::max(a_max, box_amax[b]);
         for (int d = 0; d < 3; ++d) G.L[d] = q.L[d];
         G.gd = q.shear_rate;
+        G.wk = 2.0 * kPi * q.wave_n / q.L[1];  // wave number of the wavy shear, eq. uinf
         G.part_off = (int)part;
         G.n_part = (int)n_per_box[b];
         part += n_per_box[b];
@@ -852,6 +862,7 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     P.rext = P.ec ? std::max(P.rep_rng, P.att_rng) : 0.0;
     P.kr = p.k_roll;
     P.mu_r = p.mu_roll;
+    P.wave_amp = p.wave_amp;
     // recorded pairs: 32 per particle, plus with the ranges the pairs of a uniform gas within
     // the longest cutoff (N_b^2 / V_b x 4/3 pi r_c^3 per box, twice the expected count)
     P.pair_cap = 0;
@@ -951,7 +962,7 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     h->tune_pending = false;
     const int grid = (int)((N + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_load, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, dx, dr, du, dw, dpb, h->d_boxes,
-                       h->pa[0], h->vel[0], h->omg[0], h->fb());
+                       h->pa[0], h->vel[0], h->omg[0], h->fb(), h->P.wave_amp);
     HIPTRY(hipGetLastError());
     h->loaded = true;
     dss_status s = evaluate(h, EVAL_SORT);
@@ -1525,6 +1536,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "the adjoint runs on single-box handles");
     if (h->P.ec) return fail(h, DSS_ERR_STATE, "the adjoint does not take the electro-chemical ranges");
     if (h->P.kr > 0.0) return fail(h, DSS_ERR_STATE, "the adjoint does not take rolling resistance");
+    if (h->P.wave_amp != 0.0) return fail(h, DSS_ERR_STATE, "the adjoint does not take the wavy shear");
     if (h->vel_is_half)
         return fail(h, DSS_ERR_STATE, "the adjoint starts from a state with forces at u^n: call it right after "
                                       "dss_set_particles or dss_compute_forces");

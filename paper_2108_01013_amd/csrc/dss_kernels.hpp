@@ -54,6 +54,7 @@ struct DevParams {
     double rext;                    // with ec: longest active range (pair set |r| < max(c s, s + rext))
     double rep_rng, att_rng;        // with ec: surface-distance ranges of repulsion and attraction
     double kr, mu_r;                // rolling spring stiffness and Coulomb coefficient (kr = 0: off)
+    double wave_amp;                // amplitude W of the wavy shear, eq. uinf (0: simple shear)
 };
 
 // One box: its geometry, shear rate, cell lattice and its ranges in the global numbering
@@ -69,6 +70,7 @@ struct BoxParams {
     int part_off;      // first particle id of the box
     int n_part;        // particles of the box
     int nrec;          // stress partial records of the box (from row_off; its cell rows when tiled)
+    double wk;         // wave number 2 pi n / L_y of the wavy shear
 };
 
 // Device-side clock and error flags.  step = time index of the state.
@@ -105,6 +107,13 @@ __device__ __forceinline__ int cell_coord(double xd, double cw, int n)
     c = c < 0 ? 0 : c;
     c = c > n - 1 ? n - 1 : c;
     return c;
+}
+
+// Local shear rate dU/dy of the ambient flow at height y: gdot, plus W k cos(k y) in the
+// wavy shear U_inf = (gdot y + W sin(k y), 0, 0) of eq. uinf.
+__device__ __forceinline__ double shear_at(const DevParams &P, double gd, double wk, double y)
+{
+    return P.wave_amp != 0.0 ? gd + P.wave_amp * wk * cos(wk * y) : gd;
 }
 
 // Size class of radius a under size-class stencils (stencil radius class + 1 cells).
@@ -566,9 +575,9 @@ __device__ __forceinline__ float sqrt_r(float x) { return __builtin_sqrtf(x); }
 // differences (which cancel the large ambient-flow values) are formed in FP64 and rounded
 // once; the unit vector, coefficients, log/exp, contact model and stresslet are FP32; the
 // results are accumulated in FP64 by the caller.
-template <typename Real, bool Roll = false>
-__device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, double dx_d, double dy_d, double dz_d,
-                                             double dist,
+template <typename Real, bool Roll = false, bool Wave = false>
+__device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, double wk, double dx_d, double dy_d,
+                                             double dz_d, double dist,
                                              double ai_d, double aj_d, double yi, double yj, const double4 &Vi,
                                              const double4 &Vj, const double4 &Wi, const double4 &Wj,
                                              const double xo[3], const double xro[3], double *S, PairOut &o)
@@ -595,7 +604,19 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
         rep_on = h_d < P.rep_rng;
         att_on = h_d < P.att_rng;
     }
-    const Real dux = (Real)((Vj.x - gd_d * yj) - (Vi.x - gd_d * yi));
+    // wavy shear: the ambient flow, rotation and strain at each particle's own height
+    constexpr bool wavy = Wave;
+    double si = gd_d, sj = gd_d, wvi = 0.0, wvj = 0.0;
+    double uxi = Vi.x - gd_d * yi, uxj = Vj.x - gd_d * yj;
+    if (wavy) {
+        si = shear_at(P, gd_d, wk, yi);
+        sj = shear_at(P, gd_d, wk, yj);
+        wvi = P.wave_amp * sin(wk * yi);
+        wvj = P.wave_amp * sin(wk * yj);
+        uxi -= wvi;
+        uxj -= wvj;
+    }
+    const Real dux = (Real)(uxj - uxi);
     const Real duy = (Real)(Vj.y - Vi.y);
     const Real duz = (Real)(Vj.z - Vi.z);
     const Real h = (Real)h_d;
@@ -607,8 +628,9 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
     const Real ai = (Real)ai_d, aj = (Real)aj_d;
     const Real s = ai + aj;
     const Real gd = (Real)gd_d;
-    const Real wix = (Real)Wi.x, wiy = (Real)Wi.y, wiz = (Real)(Wi.z + 0.5 * gd_d);
-    const Real wjx = (Real)Wj.x, wjy = (Real)Wj.y, wjz = (Real)(Wj.z + 0.5 * gd_d);
+    const Real gbar = wavy ? (Real)(0.5 * (si + sj)) : gd;  // shear of the mean strain (E_i + E_j) / 2
+    const Real wix = (Real)Wi.x, wiy = (Real)Wi.y, wiz = (Real)(Wi.z + 0.5 * si);
+    const Real wjx = (Real)Wj.x, wjy = (Real)Wj.y, wjz = (Real)(Wj.z + 0.5 * sj);
 
     // ---------------- lubrication
     const Real K = (Real)P.k6;
@@ -622,9 +644,9 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
     const Real YCii = K * (Real)(8.0 / 15.0) * ai2 * ai * aj * is * lg;
     const Real YCij = K * (Real)(2.0 / 15.0) * ai2 * aj2 * is * lg;
     const Real YCjj = K * (Real)(8.0 / 15.0) * ai * aj2 * aj * is * lg;
-    // v = du + s E n, E n = gd/2 (n_y, n_x, 0)
-    const Real vx = dux + s * (Real)0.5 * gd * ny;
-    const Real vy = duy + s * (Real)0.5 * gd * nx;
+    // v = du + s E n, E n = gd/2 (n_y, n_x, 0) (the mean strain in the wavy shear)
+    const Real vx = dux + s * (Real)0.5 * gbar * ny;
+    const Real vy = duy + s * (Real)0.5 * gbar * nx;
     const Real vz = duz;
     const Real vn = vx * nx + vy * ny + vz * nz;
     // n x w'
@@ -646,6 +668,37 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
     Real Tj0 = YBj * nvx - YCij * tix - YCjj * tjx;
     Real Tj1 = YBj * nvy - YCij * tiy - YCjj * tjy;
     Real Tj2 = YBj * nvz - YCij * tiz - YCjj * tjz;
+    Real FLxw = FLx, FLyw = FLy, FLzw = FLz;
+    if (wavy) {
+        // strain difference D = (E_j - E_i) / 2, D_xy = (s_j - s_i) / 4: the columns of R'(E)
+        // taken at their own particles differ from the mean-strain form by
+        //   dF_i = (X^G_ji - X^G_ii) P(D) n + (Y^G_ji - Y^G_ii) Q(D) n = -dF_j,
+        //   dT_i = (Y^H_ji - Y^H_ii) n_perp(D),  dT_j = (Y^H_jj - Y^H_ij) n_perp(D),
+        // with the coefficient differences of the Appendix A table in a_i, alpha = a_j / a_i
+        const Real d = (Real)(0.25 * (sj - si));
+        const Real Dnx = d * ny, Dny = d * nx;                   // D n
+        const Real PD = (Real)2.0 * d * nx * ny;                 // n.D.n (Tr D = 0)
+        const Real QDx = (Real)2.0 * (Dnx - PD * nx), QDy = (Real)2.0 * (Dny - PD * ny), QDz = (Real)-2.0 * PD * nz;
+        const Real pnx = (Real)2.0 * (-nz * Dny), pny = (Real)2.0 * (nz * Dnx), pnz = (Real)2.0 * (nx * Dny - ny * Dnx);
+        const Real al = aj * rcp_r(ai), op = (Real)1.0 + al;
+        const Real op2 = op * op, op3 = op2 * op;
+        const Real dXG = K * (Real)2.0 * ai2 * aj2 * (aj - ai) * is3 * invg;
+        const Real dYG = K * (Real)(4.0 / 15.0) * ai2 * al * (al - (Real)1.0) * (al * al - al + (Real)1.0) *
+                         rcp_r(op3) * lg;
+        const Real a3 = ai2 * ai;
+        const Real dHi = K * (Real)(1.0 / 15.0) * a3 * al * (al * al + (Real)9.0 * al - (Real)4.0) * rcp_r(op2) * lg;
+        const Real dHj = K * (Real)(1.0 / 15.0) * a3 * al * al * ((Real)4.0 * al * al - (Real)9.0 * al - (Real)1.0) *
+                         rcp_r(op2) * lg;
+        FLxw += dXG * PD * nx + dYG * QDx;
+        FLyw += dXG * PD * ny + dYG * QDy;
+        FLzw += dXG * PD * nz + dYG * QDz;
+        Ti0 += dHi * pnx;
+        Ti1 += dHi * pny;
+        Ti2 += dHi * pnz;
+        Tj0 += dHj * pnx;
+        Tj1 += dHj * pny;
+        Tj2 += dHj * pnz;
+    }
 
     // ---------------- electro-chemical (central): repulsion eq. rep, attraction eq. att
     const Real abar = (Real)2.0 * ai * aj * is;
@@ -665,7 +718,8 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
     o.xi[0] = o.xi[1] = o.xi[2] = 0.0;
     if (o.contact) {
         // true relative velocity of the image pair: ambient difference gd r_y along x
-        const Real Dx = dux + gd * dy, Dy = duy, Dz = duz;
+        // (plus the wave's difference at the two heights)
+        const Real Dx = dux + gd * dy + (Real)(wvj - wvi), Dy = duy, Dz = duz;
         const Real un = Dx * nx + Dy * ny + Dz * nz;
         const Real fn = (Real)P.kn * h + (Real)P.gn * un;
         const Real Fnx = fn * nx, Fny = fn * ny, Fnz = fn * nz;
@@ -749,9 +803,9 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
         }
     }
     const Real Fex = fe * nx, Fey = fe * ny, Fez = fe * nz;
-    o.Fi[0] = FLx + FCx + Fex;
-    o.Fi[1] = FLy + FCy + Fey;
-    o.Fi[2] = FLz + FCz + Fez;
+    o.Fi[0] = FLxw + FCx + Fex;
+    o.Fi[1] = FLyw + FCy + Fey;
+    o.Fi[2] = FLzw + FCz + Fez;
     o.Ti[0] = Ti0;
     o.Ti[1] = Ti1;
     o.Ti[2] = Ti2;
@@ -761,7 +815,7 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
     // stresslet r (x) F_i of the pair, the lubrication part symmetrised (eq. stresslet)
     {
         const Real r[3] = {dx, dy, dz};
-        const Real FL[3] = {FLx, FLy, FLz};
+        const Real FL[3] = {FLxw, FLyw, FLzw};
         const Real FO[3] = {FCx + Fex, FCy + Fey, FCz + Fez};
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -851,9 +905,9 @@ __device__ __forceinline__ void shell_window(const BoxParams &P, int r, int cx, 
 // Evaluate one listed pair (i at slot gi, j at slot gj): history lookup (stored stretch
 // of this pair in the row of either particle, canonical orientation min id -> max id) and
 // the pair physics.
-template <typename Real, bool Roll = false>
-__device__ __forceinline__ void evaluate_pair(const DevParams &P, double gd, const HistView &H, int gi, int gj, int idi,
-                                              int idj,
+template <typename Real, bool Roll = false, bool Wave = false>
+__device__ __forceinline__ void evaluate_pair(const DevParams &P, double gd, double wk, const HistView &H, int gi,
+                                              int gj, int idi, int idj,
                                               const double4 &Xi, const double4 &Xj, const double4 &Vi,
                                               const double4 &Wi, const double4 &Vj, const double4 &Wj, double dx,
                                               double dy, double dz, double r2, double *S, PairOut &o)
@@ -873,7 +927,7 @@ __device__ __forceinline__ void evaluate_pair(const DevParams &P, double gd, con
             xo[2] = -xo[2];
         }
     }
-    pair_physics<Real, Roll>(P, gd, dx, dy, dz, dist, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, xro, S, o);
+    pair_physics<Real, Roll, Wave>(P, gd, wk, dx, dy, dz, dist, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, xro, S, o);
 }
 
 __device__ __forceinline__ void record_pair(const DevParams &P, int idi, int idj, int *pair_out,
@@ -1013,17 +1067,33 @@ __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int
 
 // Stokes drag and rotational drag of one particle (eq. rst), added to f (force 0..2,
 // torque 3..5).
-__device__ __forceinline__ void stokes_terms(const DevParams &P, double gd, const double4 &Xi, const double4 &Vi,
-                                             const double4 &Wi, double f[6])
+// In the wavy shear the drag takes the Faxen term, F = -6 pi eta0 a [u - U_inf - a^2/6 lap U_inf]
+// (lap U_inf = (-W k^2 sin(k y), 0, 0)), the torque the local rotation, and the Stokes stresslet
+// (1 + a^2/10 lap) E_inf(y) (lap E_xy = -W k^3 cos(k y) / 2) adds its deviation from the uniform
+// 20/3 pi eta0 a^3 gdot/2 (which the host adds for every particle) to S.
+template <bool Wave>
+__device__ __forceinline__ void stokes_terms(const DevParams &P, const BoxParams &G, const double4 &Xi,
+                                             const double4 &Vi, const double4 &Wi, double f[6], double *S)
 {
     const double K = P.k6;
-    f[0] += -K * Xi.w * (Vi.x - gd * Xi.y);
+    const double gd = G.gd;
+    double ux = Vi.x - gd * Xi.y, sy = gd;
+    if constexpr (Wave) {
+        const double a = Xi.w, k = G.wk, sn = sin(k * Xi.y), cs = cos(k * Xi.y);
+        ux -= P.wave_amp * sn * (1.0 - a * a * k * k / 6.0);
+        sy = gd + P.wave_amp * k * cs;
+        const double ss = (20.0 / 3.0) * kPi * P.eta0 * a * a * a *
+                          (0.5 * (sy - gd) + a * a / 10.0 * (-0.5 * P.wave_amp * k * k * k * cs));
+        S[1] += ss;
+        S[3] += ss;
+    }
+    f[0] += -K * Xi.w * ux;
     f[1] += -K * Xi.w * Vi.y;
     f[2] += -K * Xi.w * Vi.z;
     const double KR = P.k8 * Xi.w * Xi.w * Xi.w;
     f[3] += -KR * Wi.x;
     f[4] += -KR * Wi.y;
-    f[5] += -KR * (Wi.z + 0.5 * gd);
+    f[5] += -KR * (Wi.z + 0.5 * sy);
 }
 
 __device__ __forceinline__ bool finite6(const double f[6])
@@ -1043,7 +1113,7 @@ struct PairTally {
 // shell of particle i, keeps its own side in registers (stored into its own record) and
 // adds the partner side atomically to ft_x.
 // ----------------------------------------------------------------------------------
-template <typename Real, bool Roll>
+template <typename Real, bool Roll, bool Wave>
 __device__ void particle_pairs_global(const DevParams &P, const BoxParams &G, int i, double delta,
                                       const int *__restrict__ cell_start,
                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
@@ -1090,7 +1160,7 @@ __device__ void particle_pairs_global(const DevParams &P, const BoxParams &G, in
                 ++tally.npair;
                 if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
                 PairOut o;
-                evaluate_pair<Real, Roll>(P, G.gd, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
+                evaluate_pair<Real, Roll, Wave>(P, G.gd, G.wk, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     f[k] += o.Fi[k];
@@ -1115,7 +1185,7 @@ __device__ void particle_pairs_global(const DevParams &P, const BoxParams &G, in
     }
     finish_row<Roll>(H, P.M, i, fill, idi);
     tally.fill = max(tally.fill, fill);
-    stokes_terms(P, G.gd, Xi, Vi, Wi, f);
+    stokes_terms<Wave>(P, G, Xi, Vi, Wi, f, tally.S);
     store_ft(B.own + 6LL * i, f);
     if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
 }
@@ -1185,7 +1255,7 @@ __host__ __device__ inline size_t tile_lds_bytes(int own_cap, int stage_cap, int
            (size_t)(5 * own_cap + 1) * 4 + (size_t)own_cap * 4;
 }
 
-template <typename Real, bool Roll>
+template <typename Real, bool Roll, bool Wave>
 __device__ __forceinline__ void tile_pair(const DevParams &P, const BoxParams &G, const HistView &H, const TileShared &T,
                                           const TileView &V, int il, int jl, double delta,
                                           const double4 *__restrict__ vel, const double4 *__restrict__ omg,
@@ -1208,7 +1278,7 @@ __device__ __forceinline__ void tile_pair(const DevParams &P, const BoxParams &G
     ++tally.npair;
     if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
     PairOut o;
-    evaluate_pair<Real, Roll>(P, G.gd, H, gi, gj, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy, dz, r2, tally.S, o);
+    evaluate_pair<Real, Roll, Wave>(P, G.gd, G.wk, H, gi, gj, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy, dz, r2, tally.S, o);
     double *ai = V.acc + 6 * il;
     double *aj = V.acc + 6 * jl;
     atomicAdd(ai + 0, o.Fi[0]);
@@ -1276,7 +1346,7 @@ __device__ __forceinline__ int xcd_row(int b, int n)
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-template <typename Real, bool Roll>
+template <typename Real, bool Roll, bool Wave>
 __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
                                                       const int *__restrict__ row_box, const int *__restrict__ cell_start,
                                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
@@ -1489,7 +1559,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
     const int nq = T.qn;
     for (int q = t; q < nq; q += kBlock) {
         const unsigned e = V.queue[q];
-        tile_pair<Real, Roll>(P, G, H, T, V, (int)(e >> 16), (int)(e & 0xffffu), delta, vel, omg, clk, pair_out,
+        tile_pair<Real, Roll, Wave>(P, G, H, T, V, (int)(e >> 16), (int)(e & 0xffffu), delta, vel, omg, clk, pair_out,
                         pair_count, tally);
     }
     __syncthreads();
@@ -1503,7 +1573,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
         double f[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) f[c] = V.acc[6 * il + c];
-        stokes_terms(P, G.gd, Xi, Vi, Wi, f);
+        stokes_terms<Wave>(P, G, Xi, Vi, Wi, f, tally.S);
         store_ft(B.own + 6LL * gi, f);
         if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
         const int fill = V.rowcnt[il];
@@ -1528,7 +1598,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
 // partner records of the row's four shell rows are zero; the row's stress partial as in
 // k_pairs.  Workgroups stride over the list of deferred rows.
 // ----------------------------------------------------------------------------------
-template <typename Real, bool Roll>
+template <typename Real, bool Roll, bool Wave>
 __global__ void __launch_bounds__(kBlock, 2) k_pairs_rows(DevParams P, const BoxParams *__restrict__ boxes,
                                                        const int *__restrict__ row_box,
                                                        const int *__restrict__ cell_start,
@@ -1555,7 +1625,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_rows(DevParams P, const Box
         tally.fill = 0;
         row_bounds(G, grow - G.row_off, cell_start, T);
         for (int i = T.rs[0] + t; i < T.re[0]; i += kBlock)
-            particle_pairs_global<Real, Roll>(P, G, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count,
+            particle_pairs_global<Real, Roll, Wave>(P, G, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count,
                                         tally);
         const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int r = 1; r < 5; ++r)
@@ -1666,22 +1736,26 @@ __global__ void __launch_bounds__(kBlock) k_load(int N, const double *__restrict
                                                   const double *__restrict__ u, const double *__restrict__ w,
                                                   const int *__restrict__ pbox, const BoxParams *__restrict__ boxes,
                                                   double4 *__restrict__ pa, double4 *__restrict__ vel,
-                                                  double4 *__restrict__ omg, ForceBufs B)
+                                                  double4 *__restrict__ omg, ForceBufs B, double wave_amp)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int b = pbox[p];
-    const double gd = boxes[b].gd;
+    const double gd = boxes[b].gd, wk = boxes[b].wk;
+    const double y = x[3 * p + 1];
+    // ambient velocity and rotation at the particle (with the wave of eq. uinf)
+    const double Ux = wave_amp != 0.0 ? gd * y + wave_amp * sin(wk * y) : gd * y;
+    const double Wz = wave_amp != 0.0 ? -0.5 * (gd + wave_amp * wk * cos(wk * y)) : -0.5 * gd;
     pa[p] = make_double4(x[3 * p], x[3 * p + 1], x[3 * p + 2], rad[p]);
     // vel.w carries the particle's box index through every reorder
     if (u)
         vel[p] = make_double4(u[3 * p], u[3 * p + 1], u[3 * p + 2], (double)b);
     else
-        vel[p] = make_double4(gd * x[3 * p + 1], 0.0, 0.0, (double)b);
+        vel[p] = make_double4(Ux, 0.0, 0.0, (double)b);
     if (w)
         omg[p] = make_double4(w[3 * p], w[3 * p + 1], w[3 * p + 2], (double)p);
     else
-        omg[p] = make_double4(0.0, 0.0, -0.5 * gd, (double)p);
+        omg[p] = make_double4(0.0, 0.0, Wz, (double)p);
     const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     store_ft(B.own + 6LL * p, z);
     store_ft(B.x + 6LL * p, z);

@@ -73,7 +73,7 @@ __device__ __forceinline__ void sized_row(const BoxParams &G, const int *__restr
 }
 
 // One listed-candidate test and, for a listed pair, its physics; partner side atomically.
-template <typename Real, bool Roll>
+template <typename Real, bool Roll, bool Wave>
 __device__ __forceinline__ void sized_pair(const DevParams &P, const BoxParams &G, const HistView &H, int i, int j,
                                            int idi, const double4 &Xi, const double4 &Vi, const double4 &Wi,
                                            const double4 &Xj, double delta,
@@ -91,7 +91,7 @@ __device__ __forceinline__ void sized_pair(const DevParams &P, const BoxParams &
     idj = (int)Wj.w;
     ++tally.npair;
     if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
-    evaluate_pair<Real, Roll>(P, G.gd, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
+    evaluate_pair<Real, Roll, Wave>(P, G.gd, G.wk, H, i, j, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy2, dz2, r2, tally.S, o);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         f[k] += o.Fi[k];
@@ -114,7 +114,7 @@ __device__ __forceinline__ void sized_pair(const DevParams &P, const BoxParams &
 // Lane path: one lane per particle of the classes below wave_cls (slots [0, n_lane), n_lane =
 // first slot of class wave_cls), workgroup lb of nlb striding over the slots.
 // ----------------------------------------------------------------------------------
-template <typename Real, bool Roll>
+template <typename Real, bool Roll, bool Wave>
 __device__ __forceinline__ void sized_lane_path(const DevParams &P, const BoxParams &G, const int *__restrict__ cell_start,
                                                 const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                                 const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
@@ -138,7 +138,7 @@ __device__ __forceinline__ void sized_lane_path(const DevParams &P, const BoxPar
                 sized_row(G, cell_start, pa, i, Xi, ci, cx, cy, cz, dy, dz, delta, [&](int j, const double4 &Xj) {
                     int need, idj = 0;
                     PairOut o;
-                    sized_pair<Real, Roll>(P, G, H, i, j, idi, Xi, Vi, Wi, Xj, delta, vel, omg, B, clk, pair_out,
+                    sized_pair<Real, Roll, Wave>(P, G, H, i, j, idi, Xi, Vi, Wi, Xj, delta, vel, omg, B, clk, pair_out,
                                            pair_count, tally, f, need, o, idj);
                     if (need) {
                         store_history<Roll>(H, P.M, i, fill, idi, idj, o, clk);
@@ -147,7 +147,7 @@ __device__ __forceinline__ void sized_lane_path(const DevParams &P, const BoxPar
                 });
         finish_row<Roll>(H, P.M, i, fill, idi);
         tally.fill = max(tally.fill, fill);
-        stokes_terms(P, G.gd, Xi, Vi, Wi, f);
+        stokes_terms<Wave>(P, G, Xi, Vi, Wi, f, tally.S);
         store_ft(B.own + 6LL * i, f);
         if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
     }
@@ -225,7 +225,7 @@ __device__ __forceinline__ void wave_finish_row(const HistView &H, int M, int gi
 // take their history slots from a per-wavefront LDS counter, the wavefront sums its own side
 // and sorts the row.
 // ----------------------------------------------------------------------------------
-template <typename Real, bool Roll>
+template <typename Real, bool Roll, bool Wave>
 __device__ __forceinline__ void sized_wave_path(const DevParams &P, const BoxParams &G, const int *__restrict__ cell_start,
                                                 const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                                 const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
@@ -254,7 +254,7 @@ __device__ __forceinline__ void sized_wave_path(const DevParams &P, const BoxPar
             sized_row(G, cell_start, pa, i, Xi, ci, cx, cy, cz, dy, dz, delta, [&](int j, const double4 &Xj) {
                 int need, idj = 0;
                 PairOut o;
-                sized_pair<Real, Roll>(P, G, H, i, j, idi, Xi, Vi, Wi, Xj, delta, vel, omg, B, clk, pair_out,
+                sized_pair<Real, Roll, Wave>(P, G, H, i, j, idi, Xi, Vi, Wi, Xj, delta, vel, omg, B, clk, pair_out,
                                        pair_count, tally, f, need, o, idj);
                 if (need) store_history<Roll>(H, P.M, i, atomicAdd(&wfill[wid], 1), idi, idj, o, clk);
             });
@@ -268,7 +268,7 @@ __device__ __forceinline__ void sized_wave_path(const DevParams &P, const BoxPar
         wave_finish_row<Roll>(H, P.M, i, fill, idi);
         if (lane == 0) {
             tally.fill = max(tally.fill, fill);
-            stokes_terms(P, G.gd, Xi, Vi, Wi, f);
+            stokes_terms<Wave>(P, G, Xi, Vi, Wi, f, tally.S);
             store_ft(B.own + 6LL * i, f);
             if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
         }
@@ -281,7 +281,7 @@ __device__ __forceinline__ void sized_wave_path(const DevParams &P, const BoxPar
 // xcd_row; g_wave is a multiple of 8, so the XCD of a lane workgroup is unchanged).  Partial
 // record = blockIdx.x.
 // ----------------------------------------------------------------------------------
-template <typename Real, bool Roll>
+template <typename Real, bool Roll, bool Wave>
 __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const BoxParams *__restrict__ boxes,
                                                         const int *__restrict__ cell_start,
                                                         const double4 *__restrict__ pa,
@@ -305,10 +305,10 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const Bo
     tally.fill = 0;
     const int b = blockIdx.x;
     if (b < g_wave)
-        sized_wave_path<Real, Roll>(P, G, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, delta, n_lane, b,
+        sized_wave_path<Real, Roll, Wave>(P, G, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, delta, n_lane, b,
                                     g_wave, wfill, tally);
     else
-        sized_lane_path<Real, Roll>(P, G, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, delta, n_lane,
+        sized_lane_path<Real, Roll, Wave>(P, G, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, delta, n_lane,
                                     xcd_row(b - g_wave, (int)gridDim.x - g_wave), (int)gridDim.x - g_wave, tally);
     reduce_tally(tally, red, partials, P.pstride, b);
 }

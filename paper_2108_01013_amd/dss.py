@@ -44,7 +44,8 @@ class Params(ctypes.Structure):
                                                   "lambda_D", "a0", "hamaker", "eps_vdw", "eps_lub", "cutoff_factor",
                                                   "dt")]
                 + [("precision", ctypes.c_int32), ("capacity", ctypes.c_int32), ("flags", ctypes.c_int32),
-                   ("reserved", ctypes.c_int32), ("k_roll", ctypes.c_double), ("mu_roll", ctypes.c_double)])
+                   ("reserved", ctypes.c_int32), ("k_roll", ctypes.c_double), ("mu_roll", ctypes.c_double),
+                   ("wave_amp", ctypes.c_double), ("wave_n", ctypes.c_double)])
 
 
 class Info(ctypes.Structure):
@@ -142,6 +143,8 @@ def make_params(p: dict, precision: int = DSS_FP64, capacity: int = 0, flags: in
     s.reserved = 0
     s.k_roll = float(p.get("kr", 0.0))      # rolling resistance (Appendix roll), off at 0
     s.mu_roll = float(p.get("mu_r", 0.0))
+    s.wave_amp = float(p.get("wave_amp", 0.0))   # wavy shear (eq. uinf), off at 0
+    s.wave_n = float(p.get("wave_n", 0.0))
     return s
 
 

@@ -41,8 +41,8 @@ def test_status_strings_without_gpu():
 
 def test_params_struct_layout():
     from paper_2108_01013_amd import dss
-    # 3 + 15 doubles, 4 int32, then the 2 doubles of the rolling spring
-    assert ctypes.sizeof(dss.Params) == 18 * 8 + 4 * 4 + 2 * 8
+    # 3 + 15 doubles, 4 int32, then the 2 doubles of the rolling spring and 2 of the wave
+    assert ctypes.sizeof(dss.Params) == 18 * 8 + 4 * 4 + 4 * 8
     assert dss.Params.precision.offset == 18 * 8
     assert dss.Params.k_roll.offset == 18 * 8 + 4 * 4
     assert ctypes.sizeof(dss.Tuning) == 2 * 8 + 6 * 4 and dss.Tuning.sized.offset == 24
