@@ -261,7 +261,7 @@ def run_poly(args):
     torch.cuda.set_device(0)
     p = w.params
     sim = Simulation(p, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
-    sim.set_tuning(sized=True, cell_scale=2.0)
+    sim.set_tuning(sized=True, cell_scale=args.cell_scale or 1.5, wave_class=args.wave_class)
     sim.set_particles(w.x, w.rad)
     N = len(w.rad)
     tuned = maybe_tune(sim, args)
@@ -474,6 +474,8 @@ def main():
     ap.add_argument("--ec-ranges", action="store_true",
                     help="single: electro-chemical forces over their own ranges (with attraction)")
     ap.add_argument("--observables", action="store_true", help="single: time the observables after the run")
+    ap.add_argument("--cell-scale", type=float, default=None, help="poly: lattice spacing over 2 c a_min (1.5)")
+    ap.add_argument("--wave-class", type=int, default=2, help="poly: first size class on a wavefront (2)")
     args = ap.parse_args()
     if args.tune is None:
         args.tune = 1 if args.mode == "sweep" else 0

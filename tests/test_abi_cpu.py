@@ -71,3 +71,14 @@ def test_create_batch_rejects_mixed_physics_without_touching_the_device():
     arr = (dss.Params * 2)(dss.make_params(a), dss.make_params(b))
     assert lib.dss_create_batch(arr, 0, None, ctypes.byref(h)) == 1
     assert ctypes.sizeof(dss.BoxInfo) == 8 + 8 + 12 + 4 + 8 + 8 + 4 + 4 + 24 + 8 + 8
+
+
+@pytest.mark.parametrize("over", [dict(wave_amp=2.0, wave_n=0.5), dict(wave_amp=2.0, wave_n=0.0),
+                                  dict(kr=-1.0), dict(mu_r=-0.1)])
+def test_create_rejects_bad_extension_params_without_touching_the_device(over):
+    from paper_2108_01013_amd import dss, synth
+    lib = dss.load_library()
+    p = dss.make_params(synth.default_params([10.0, 10.0, 10.0], **over))
+    h = ctypes.c_void_p()
+    assert lib.dss_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    assert not h.value

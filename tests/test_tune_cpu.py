@@ -51,3 +51,15 @@ def test_autotune_picks_fastest_and_caches(tmp_path):
                                        (1000, 0.51, "B1:N2^10:phi0.50:ratio1.40:prec0")])
 def test_workload_key(N, phi, key):
     assert tune.workload_key(FakeSim(N, phi)) == key
+
+
+def test_size_class_candidates_only_for_one_wide_box():
+    wide = FakeSim(N=500_000)
+    wide.size_ratio = 9.98
+    assert any(c.get("sized") for c in tune.candidates_for(wide))
+    assert all(c["sized"] is False for c in tune.CANDIDATES)
+    narrow = FakeSim(N=100_000)
+    assert tune.candidates_for(narrow) == tune.CANDIDATES
+    batch = FakeSim(N=20_000, B=8)
+    batch.size_ratio = 9.98
+    assert tune.candidates_for(batch) == tune.CANDIDATES
