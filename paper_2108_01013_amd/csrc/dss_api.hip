@@ -38,6 +38,7 @@ struct dss_handle {
     int *d_row_box = nullptr;         // cell row -> box
     double *box_diag = nullptr;       // nbox x 3: listed pairs, contacts, largest history row
     int *tile_sum = nullptr;          // totals of the multi-workgroup scan
+    int *cs_local = nullptr;          // tile-local cell starts of the parallel scan (up to 16 tiles)
     int *fb_rows = nullptr, *fb_count = nullptr;  // rows deferred to the per-particle path
     int deferred_hint = -1;           // deferred rows at the last synchronised evaluation
     int ncell_total = 0, nrow_total = 0;
@@ -147,7 +148,8 @@ void free_lattice(dss_handle *h)
         if (p) (void)hipFree(p);
     };
     destroy_graphs(h);
-    F(h->count); F(h->cell_start); F(h->tile_sum); F(h->partials); F(h->d_boxes); F(h->d_row_box);
+    F(h->count); F(h->cell_start); F(h->tile_sum); F(h->cs_local); F(h->partials); F(h->d_boxes); F(h->d_row_box);
+    h->cs_local = nullptr;
     F(h->fb_rows); F(h->fb_count);
     h->count = h->cell_start = h->tile_sum = h->d_row_box = h->fb_rows = h->fb_count = nullptr;
     h->partials = nullptr;
@@ -492,7 +494,8 @@ dss_status setup_lattice(dss_handle *h)
     P.pstride = (std::max(nrow, max_rows_box) + 63) / 64 * 64;
     HIPTRY(dalloc(&h->count, ncell_pad));
     HIPTRY(dalloc(&h->cell_start, ncell_pad));
-    HIPTRY(dalloc(&h->tile_sum, std::max(h->scan_tiles, 1)));
+    HIPTRY(dalloc(&h->tile_sum, std::max(h->scan_tiles, 16)));
+    HIPTRY(dalloc(&h->cs_local, ncell_pad));
     HIPTRY(dalloc(&h->partials, 12 * (size_t)P.pstride));
     HIPTRY(dalloc(&h->d_boxes, B));
     HIPTRY(dalloc(&h->d_row_box, nrow));
@@ -634,24 +637,19 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
         hipExtLaunchKernelGGL(k_scan_add, dim3(h->scan_tiles), dim3(1024), 0, h->stream, (hipEvent_t) nullptr, t.e1,
                               0, h->cell_start, h->tile_sum, 4 * 1024, h->clk, advance);
     } else {
+        // one workgroup per tile of 4096 cells, in parallel; k_scatter adds the tile offsets
         TimedLaunch t(h, 1);
-#define DSS_SCAN(C4)                                                                                            \
-    case C4:                                                                                                    \
-        hipExtLaunchKernelGGL(k_scan<C4>, dim3(1), dim3(1024), 0, h->stream, t.e0, t.e1, 0, h->count,            \
-                              h->cell_start, h->clk, advance, (int *)nullptr);                          \
-        break;
-        switch (h->scan_c4) {
-            DSS_SCAN(1) DSS_SCAN(2) DSS_SCAN(3) DSS_SCAN(4) DSS_SCAN(5) DSS_SCAN(6) DSS_SCAN(7) DSS_SCAN(8)
-            DSS_SCAN(9) DSS_SCAN(10) DSS_SCAN(11) DSS_SCAN(12) DSS_SCAN(13) DSS_SCAN(14) DSS_SCAN(15) DSS_SCAN(16)
-        default:
-            return fail(h, DSS_ERR_BOX, "cell lattice too large for the scan");
-        }
-#undef DSS_SCAN
+        if (h->scan_c4 < 1 || h->scan_c4 > 16) return fail(h, DSS_ERR_BOX, "cell lattice too large for the scan");
+        hipExtLaunchKernelGGL(k_scan<1>, dim3(h->scan_c4), dim3(1024), 0, h->stream, t.e0, t.e1, 0, h->count,
+                              h->cs_local, h->clk, advance, h->tile_sum);
     }
     {
         TimedLaunch t(h, 2);
+        const bool tiles = h->scan_tiles == 0;
         hipExtLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, N, h->cell, h->rank,
-                              h->cell_start, h->pa[c], h->vel[c], h->omg[c], h->pa[o], h->vel[o], h->omg[o], h->prev);
+                              tiles ? h->cs_local : h->cell_start, h->tile_sum, tiles ? h->scan_c4 : 0,
+                              h->ncell_total + 1, h->cell_start, h->clk, advance, h->pa[c], h->vel[c], h->omg[c],
+                              h->pa[o], h->vel[o], h->omg[o], h->prev);
     }
     dss_status s = launch_pairs(h, o, h->prev, advance, finish);
     if (s) return s;

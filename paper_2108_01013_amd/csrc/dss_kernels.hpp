@@ -522,18 +522,43 @@ __global__ void __launch_bounds__(kBlock) k_complete(DevParams P, const double4 
 // ----------------------------------------------------------------------------------
 // k_scatter: move every particle to its sorted slot, remember its previous slot (where
 // its contact-history row of the last step lives).
+// With ntile > 0 (at most 16 tiles of 4096 cells) the counts were scanned tile by tile in
+// parallel (cs_local, tile totals in tile_sum): every workgroup forms the tile offsets
+// (one wavefront scan), slots are cs_local + offset, the workgroups write the final
+// cell_start over a grid stride, and the clock advances here.  With ntile = 0 cs_local is
+// the final cell_start.
 // ----------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_scatter(int N, const int *__restrict__ cell, const int *__restrict__ rank,
-                                                     const int *__restrict__ cell_start,
-                                                     const double4 *__restrict__ pa_in,
+                                                     const int *__restrict__ cs_local,
+                                                     const int *__restrict__ tile_sum, int ntile, int ncell1,
+                                                     int *__restrict__ cell_start, DevClock *__restrict__ clk,
+                                                     int advance, const double4 *__restrict__ pa_in,
                                                      const double4 *__restrict__ vel_in,
                                                      const double4 *__restrict__ omg_in, double4 *__restrict__ pa_out,
                                                      double4 *__restrict__ vel_out, double4 *__restrict__ omg_out,
                                                      int *__restrict__ prev)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int off[16];
+    const int t = threadIdx.x;
+    if (ntile > 0) {
+        if (t < 64) {
+            const int v = t < ntile ? tile_sum[t] : 0;
+            int incl = v;
+            for (int o = 1; o < 16; o <<= 1) {
+                const int u = __shfl_up(incl, o, 64);
+                if ((t & 63) >= o) incl += u;
+            }
+            if (t < 16) off[t] = incl - v;
+        }
+        __syncthreads();
+        if (blockIdx.x == 0 && t == 0 && advance) clk->step += 1;
+        for (int q = blockIdx.x * blockDim.x + t; q < ncell1; q += gridDim.x * blockDim.x)
+            cell_start[q] = cs_local[q] + off[q >> 12];
+    }
+    int p = blockIdx.x * blockDim.x + t;
     if (p >= N) return;
-    int dst = cell_start[cell[p]] + rank[p];
+    const int c = cell[p];
+    int dst = (ntile > 0 ? cs_local[c] + off[c >> 12] : cs_local[c]) + rank[p];
     pa_out[dst] = pa_in[p];
     vel_out[dst] = vel_in[p];
     omg_out[dst] = omg_in[p];
