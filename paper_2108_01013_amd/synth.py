@@ -180,17 +180,19 @@ def _sweep_box(args):
     return bidisperse_box(int(n), phi, seed=seed + 17 * b)
 
 
-def config_sweep(B: int = 64, seed: int = 3, n_lo: int = 2000, n_hi: int = 50_000, workers: int = 0):
+def config_sweep(B: int = 64, seed: int = 3, n_lo: int = 2000, n_hi: int = 50_000, workers: int = 0,
+                 start_method: str = "fork"):
     """Flow-curve sweep: B bidisperse boxes (1 : 1.4, equal volumes), N_b uniform on
     {n_lo .. n_hi}, phi_b = SWEEP_PHI[b mod 5], shear rate 10^(-2 + 3 b / (B - 1)) spanning
     three decades.  Returns (workloads, shear rates).  workers > 1 relaxes the boxes in that
-    many processes (call before any GPU work: the pool forks)."""
+    many processes: forked before any GPU work, or started afresh ("spawn") in a process that
+    already uses the GPU (the workers only run numpy and scipy)."""
     rng = np.random.default_rng(seed)
     sizes = rng.integers(n_lo, n_hi + 1, size=B)
     jobs = [(b, sizes[b], SWEEP_PHI[b % len(SWEEP_PHI)], seed) for b in range(B)]
     if workers > 1:
         import multiprocessing as mp
-        with mp.get_context("fork").Pool(workers) as pool:
+        with mp.get_context(start_method).Pool(workers) as pool:
             ws = pool.map(_sweep_box, jobs, chunksize=1)
     else:
         ws = [_sweep_box(j) for j in jobs]

@@ -167,3 +167,16 @@ def test_batch_stress_sampling_per_box():
     assert ns == 4
     assert rel_inf(mean, np.mean(ref, axis=0)) < 1e-7
     sim.close()
+
+
+def test_batch_full_sweep_sampled():
+    """The full 64-box sweep of the benchmark (sum N = 1.54M, phi 0.40-0.58, shear rates 1e-2 to
+    1e1, several-workgroup scan) in its launch configuration: two lockstep steps, with six
+    boxes spread over the volume fractions and shear rates checked against the oracle."""
+    say("case: full 64-box sweep, sampled boxes")
+    ws, gds = synth.config_sweep(B=64, workers=16, start_method="spawn")
+    check = [0, 13, 26, 39, 52, 63]
+    sim, contacts = run_lockstep(ws, gds, steps=2, use_cells=True, check=check)
+    assert sim.N == sum(len(w.rad) for w in ws) > 1_000_000
+    assert contacts > 0
+    sim.close()
