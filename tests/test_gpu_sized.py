@@ -163,3 +163,32 @@ def test_sized_needs_one_box():
     with pytest.raises(DssError):
         b.set_tuning(sized=True)
     b.close()
+
+
+def test_full_size_high_ratio_initial_evaluation():
+    """Size ratio 10 at its full size (N = 500k, lognormal radii on [1, 10], phi = 0.55) on the
+    size-class stencils in the benchmark's configuration (spacing 1.5, wavefronts from stencil
+    radius 3), FP64: the pair set bit-identical to the oracle's cell search and every force,
+    torque and the stress within 1e-10.  The centres are uniform at random without relaxation
+    (a relaxed packing of this size takes many minutes to generate; one evaluation does not
+    need it), so the set holds deep overlaps as well as near misses."""
+    from paper_2108_01013_amd.dss import Simulation
+    N = 500_000
+    rad = synth.lognormal_radii(N, seed=3)
+    L = synth.box_for_fraction(rad, 0.55)
+    x = np.random.default_rng(1003).uniform(0.0, L, size=(N, 3))
+    p = synth.default_params([L, L, L])
+    say("case: full-size size ratio 10, N=500k, initial evaluation")
+    sim = Simulation(p, record_pairs=True)
+    sim.set_tuning(sized=True, cell_scale=1.5, wave_class=2)
+    sim.set_particles(x, rad)
+    assert sim.box_info(0)["size_classes"] >= 6
+    pg = sim.pairs()
+    po = oracle.pairs_cells(p, x, rad, 0.0)
+    assert len(po) > N and np.array_equal(pg, po)
+    s = sim.state()
+    F, T, S, H, npairs = oracle.forces(p, x, s["u"], s["w"], rad, 0, use_cells=True)
+    assert rel_inf(s["F"], F) < TOL_F and rel_inf(s["T"], T) < TOL_F
+    last, _, _ = sim.read_stress()
+    assert rel_inf(last, S) < TOL_F
+    sim.close()
