@@ -485,10 +485,14 @@ dss_status setup_lattice(dss_handle *h)
         P.qcap = qcap;
     }
     for (const void *k :
-         {(const void *)k_pairs<double, false, false>, (const void *)k_pairs<float, false, false>,
-          (const void *)k_pairs<double, true, false>, (const void *)k_pairs<float, true, false>,
-          (const void *)k_pairs<double, false, true>, (const void *)k_pairs<float, false, true>,
-          (const void *)k_pairs<double, true, true>, (const void *)k_pairs<float, true, true>})
+         {(const void *)k_pairs<double, false, false, true>, (const void *)k_pairs<float, false, false, true>,
+          (const void *)k_pairs<double, true, false, true>, (const void *)k_pairs<float, true, false, true>,
+          (const void *)k_pairs<double, false, true, true>, (const void *)k_pairs<float, false, true, true>,
+          (const void *)k_pairs<double, true, true, true>, (const void *)k_pairs<float, true, true, true>,
+          (const void *)k_pairs<double, false, false, false>, (const void *)k_pairs<float, false, false, false>,
+          (const void *)k_pairs<double, true, false, false>, (const void *)k_pairs<float, true, false, false>,
+          (const void *)k_pairs<double, false, true, false>, (const void *)k_pairs<float, false, true, false>,
+          (const void *)k_pairs<double, true, true, false>, (const void *)k_pairs<float, true, true, false>})
         HIPTRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->tile_lds));
     h->finish_r = (max_rows_box + 1023) / 1024;
     P.pstride = (std::max(nrow, max_rows_box) + 63) / 64 * 64;
@@ -517,13 +521,14 @@ enum EvalMode { EVAL_STEP = 0, EVAL_SORT = 1, EVAL_INPLACE = 2 };
 
 // The pair kernels of one evaluation: size-class stencils (lane and wavefront paths), or
 // the row tiles followed by the rows they deferred.  Real: FP64 or mixed arithmetic; Roll:
-// rolling resistance.
-template <typename Real, bool Roll, bool Wave>
+// rolling resistance; Wave: the wavy ambient shear; Sum: the stress and counters are summed
+// (k_finish follows), else the tile and stencil kernels skip them.
+template <typename Real, bool Roll, bool Wave, bool Sum>
 void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
 {
     if (h->P.sized) {
         TimedLaunch t(h, 3);
-        hipExtLaunchKernelGGL(k_pairs_sized<Real, Roll, Wave>, dim3(h->sized_grid[0] + h->sized_grid[1]), dim3(kBlock), 0,
+        hipExtLaunchKernelGGL(k_pairs_sized<Real, Roll, Wave, Sum>, dim3(h->sized_grid[0] + h->sized_grid[1]), dim3(kBlock), 0,
                               h->stream, t.e0, t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf],
                               h->omg[buf], h->fb(), H, h->clk, h->partials, h->sized_grid[1], h->pairs,
                               h->pair_count);
@@ -531,7 +536,7 @@ void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
     }
     {
         TimedLaunch t(h, 3);
-        hipExtLaunchKernelGGL(k_pairs<Real, Roll, Wave>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0,
+        hipExtLaunchKernelGGL(k_pairs<Real, Roll, Wave, Sum>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0,
                               t.e1, 0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
                               h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, h->fb_rows,
                               h->fb_count);
@@ -565,16 +570,24 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, boo
     H.xr_new = h->hxr[1 - h->hh];
     if (h->P.record_pairs) HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
     const bool roll = h->P.kr > 0.0, wave = h->P.wave_amp != 0.0;
-    const int v = (h->prm.precision == DSS_MIXED ? 4 : 0) | (roll ? 2 : 0) | (wave ? 1 : 0);
+    const int v = (finish ? 8 : 0) | (h->prm.precision == DSS_MIXED ? 4 : 0) | (roll ? 2 : 0) | (wave ? 1 : 0);
     switch (v) {
-    case 0: launch_pair_kernels<double, false, false>(h, buf, H); break;
-    case 1: launch_pair_kernels<double, false, true>(h, buf, H); break;
-    case 2: launch_pair_kernels<double, true, false>(h, buf, H); break;
-    case 3: launch_pair_kernels<double, true, true>(h, buf, H); break;
-    case 4: launch_pair_kernels<float, false, false>(h, buf, H); break;
-    case 5: launch_pair_kernels<float, false, true>(h, buf, H); break;
-    case 6: launch_pair_kernels<float, true, false>(h, buf, H); break;
-    default: launch_pair_kernels<float, true, true>(h, buf, H); break;
+    case 0: launch_pair_kernels<double, false, false, false>(h, buf, H); break;
+    case 1: launch_pair_kernels<double, false, true, false>(h, buf, H); break;
+    case 2: launch_pair_kernels<double, true, false, false>(h, buf, H); break;
+    case 3: launch_pair_kernels<double, true, true, false>(h, buf, H); break;
+    case 4: launch_pair_kernels<float, false, false, false>(h, buf, H); break;
+    case 5: launch_pair_kernels<float, false, true, false>(h, buf, H); break;
+    case 6: launch_pair_kernels<float, true, false, false>(h, buf, H); break;
+    case 7: launch_pair_kernels<float, true, true, false>(h, buf, H); break;
+    case 8: launch_pair_kernels<double, false, false, true>(h, buf, H); break;
+    case 9: launch_pair_kernels<double, false, true, true>(h, buf, H); break;
+    case 10: launch_pair_kernels<double, true, false, true>(h, buf, H); break;
+    case 11: launch_pair_kernels<double, true, true, true>(h, buf, H); break;
+    case 12: launch_pair_kernels<float, false, false, true>(h, buf, H); break;
+    case 13: launch_pair_kernels<float, false, true, true>(h, buf, H); break;
+    case 14: launch_pair_kernels<float, true, false, true>(h, buf, H); break;
+    default: launch_pair_kernels<float, true, true, true>(h, buf, H); break;
     }
     if (!finish) return DSS_OK;
     TimedLaunch t(h, 4);

@@ -1256,6 +1256,9 @@ __device__ __forceinline__ void reduce_tally(PairTally &tally, double (*red)[12]
 //       particles of the other four shell rows: partner-side force records.
 // Tile capacities (P.own_cap, P.stage_cap, P.qcap) are sized from the mean row
 // occupancy; a row beyond them takes the per-particle path.  The LDS layout is dynamic.
+// Sum: the row's stress and counters are reduced into its partial record.  Steps whose
+// stress is not summed take Sum = false, and the compiler drops the stresslet arithmetic
+// and its accumulators (the forces, torques and history are the same).
 // ----------------------------------------------------------------------------------
 struct TileShared {
     int rs[5], re[5], ro[6], rbase[5], rcross[5];
@@ -1371,7 +1374,7 @@ __device__ __forceinline__ int xcd_row(int b, int n)
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-template <typename Real, bool Roll, bool Wave>
+template <typename Real, bool Roll, bool Wave, bool Sum>
 __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
                                                       const int *__restrict__ row_box, const int *__restrict__ cell_start,
                                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
@@ -1613,7 +1616,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
         for (int c = 0; c < 6; ++c) f[c] = V.acc[6 * k + c];
         store_ft(B.nb + 6LL * ((r - 1) * B.n + g), f);
     }
-    reduce_tally(tally, T.red, partials, P.pstride, grow);
+    if constexpr (Sum) reduce_tally(tally, T.red, partials, P.pstride, grow);
 }
 
 // ----------------------------------------------------------------------------------

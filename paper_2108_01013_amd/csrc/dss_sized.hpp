@@ -279,9 +279,9 @@ __device__ __forceinline__ void sized_wave_path(const DevParams &P, const BoxPar
 // k_pairs_sized: workgroups [0, g_wave) take the wavefront path (the long-running large
 // particles start first), the others the lane path over XCD-contiguous slot blocks (see
 // xcd_row; g_wave is a multiple of 8, so the XCD of a lane workgroup is unchanged).  Partial
-// record = blockIdx.x.
+// record = blockIdx.x, written only when Sum (a step whose stress is summed).
 // ----------------------------------------------------------------------------------
-template <typename Real, bool Roll, bool Wave>
+template <typename Real, bool Roll, bool Wave, bool Sum>
 __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const BoxParams *__restrict__ boxes,
                                                         const int *__restrict__ cell_start,
                                                         const double4 *__restrict__ pa,
@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const Bo
     else
         sized_lane_path<Real, Roll, Wave>(P, G, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, delta, n_lane,
                                     xcd_row(b - g_wave, (int)gridDim.x - g_wave), (int)gridDim.x - g_wave, tally);
-    reduce_tally(tally, red, partials, P.pstride, b);
+    if constexpr (Sum) reduce_tally(tally, red, partials, P.pstride, b);
 }
 
 }  // namespace dss

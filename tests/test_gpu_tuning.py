@@ -193,3 +193,48 @@ def test_save_and_load_state():
     assert e.value.status == 1
     other.close()
     sim.close()
+
+
+@pytest.mark.parametrize("sized,precision", [(False, 0), (False, 1), (True, 0)])
+def test_stress_summed_only_on_sampled_steps(sized, precision):
+    """Steps between stress samples run the pair kernels without the stress and counters; the
+    dynamics and the samples equal those of a run that sums the stress on every step.  FP64:
+    to the reordering of the atomic sums.  Mixed: the FP32 products that fed only the stresslet
+    are gone, so the compiler fuses some multiply-adds of the pair terms differently: FP32
+    roundings of the size of the mixed path's own error (F, T within a few 1e-7 of FP64 per
+    evaluation), held to the mixed path's bar of 1e-5."""
+    from paper_2108_01013_amd.dss import Simulation
+    if sized:
+        rad = synth.lognormal_radii(3000, seed=7)
+        L = synth.box_for_fraction(rad, 0.55)
+        x = synth.relax_positions(rad, L, seed=8)
+        p = synth.default_params([L, L, L])
+    else:
+        w = synth.bidisperse_box(4000, 0.55, seed=13)
+        x, rad, p = w.x, w.rad, w.params
+    say(f"case: stress on sampled steps only, sized={sized} precision={precision}")
+    runs = []
+    for every_step in (False, True):
+        sim = Simulation(p, precision=precision)
+        sim.set_tuning(sized=sized)
+        sim.set_particles(x, rad)
+        if every_step:
+            lasts = []
+            for n in range(1, 21):
+                sim.step(1)
+                if n % 5 == 0:
+                    lasts.append(sim.read_stress()[0])
+            mean = np.mean(lasts, axis=0)
+        else:
+            sim.step(20, stress_every=5)
+            _, mean, ns = sim.read_stress()
+            assert ns == 4
+        runs.append((sim.state(), sim.read_stress()[0], mean, sim.info()))
+        sim.close()
+    (s1, l1, m1, i1), (s2, l2, m2, i2) = runs
+    assert i1["error_flags"] == 0 and i1["n_pairs"] == i2["n_pairs"] and i1["n_contacts"] == i2["n_contacts"]
+    tol_state, tol_ft = (1e-12, 1e-8) if precision == 0 else (1e-6, 1e-5)
+    for k in ("x", "u", "w"):
+        assert rel_inf(s1[k], s2[k]) < tol_state, (k, rel_inf(s1[k], s2[k]))
+    for a, b, k in ((s1["F"], s2["F"], "F"), (s1["T"], s2["T"], "T"), (l1, l2, "last"), (m1, m2, "mean")):
+        assert rel_inf(a, b) < tol_ft, (k, rel_inf(a, b))
