@@ -185,6 +185,25 @@ __device__ __forceinline__ bool image_listed(const double4 &Xi, const double4 &X
     return r2 < rc * rc;
 }
 
+// image_listed with the contact guess of a listed pair: 0 not listed, 1 listed, 2 listed with
+// r2 < (a_i + a_j)^2.  The guess only orders the pair queue (contacts last, so the history
+// lookups and the contact springs run in few wavefronts); evaluate_pair decides contact.
+__device__ __forceinline__ int image_class(const double4 &Xi, const double4 &Xj, double sy, double sxd, double sx,
+                                           double sz, double cf, double rext)
+{
+#pragma clang fp contract(off)
+    double dx = Xj.x - Xi.x, dy = Xj.y - Xi.y, dz = Xj.z - Xi.z;
+    dy = dy + sy;
+    dx = dx + sxd;
+    dx = dx + sx;
+    dz = dz + sz;
+    const double r2 = (dx * dx + dy * dy) + dz * dz;
+    const double s = Xi.w + Xj.w;
+    double rc = cf * s;
+    if (rext > 0.0) rc = fmax(rc, s + rext);
+    return r2 < rc * rc ? (r2 < s * s ? 2 : 1) : 0;
+}
+
 __device__ __forceinline__ double pmass(const DevParams &P, double a)
 {
 #pragma clang fp contract(off)
@@ -1522,11 +1541,13 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
     // every lane running the same straight-line test: the nearest-image vector is the
     // difference plus the shifts of the candidate's range (y face with its x offset, x period,
     // z period), added in the order and with the values of the general formula (same IEEE
-    // result for every listed pair).  Hits are kept as a bit mask per lane; a block scan of
-    // the hit counts gives every lane its slots in the pair queue (no atomics).
+    // result for every listed pair).  Hits are kept as bit masks per lane (all hits, and the
+    // probable contacts); a block scan of the two hit counts (packed in one word: at most
+    // 64 kBlock candidates) gives every lane its slots in the pair queue, the other pairs
+    // first and the probable contacts last (no atomics).
     if (!T.ovf) {
         const int lane = t & 63, wid = t >> 6;
-        auto test = [&](unsigned wd) -> bool {
+        auto test = [&](unsigned wd) -> int {
             const int jl = (int)(wd & 0x3fffu);
             const int il = (int)((wd >> 14) & 0xfffu);
             const int cross = (int)((wd >> 26) & 3u) - 1;
@@ -1534,20 +1555,21 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
             const double sxd = cross > 0 ? delta : (cross < 0 ? -delta : 0.0);
             const double sx = (double)((int)((wd >> 28) & 7u) - 4) * G.L[0];
             const double sz = (wd >> 31) ? G.L[2] : 0.0;
-            return image_listed(V.sp[il], V.sp[jl], sy, sxd, sx, sz, P.cf, P.ec ? P.rext : 0.0);
+            return image_class(V.sp[il], V.sp[jl], sy, sxd, sx, sz, P.cf, P.ec ? P.rext : 0.0);
         };
-        unsigned long long bits = 0ull;
+        unsigned long long bits = 0ull, cbits = 0ull;
         int j = 0;
         for (int k = t; k < ncand; k += 2 * kBlock, j += 2) {
             const int k2 = k + kBlock;
             const unsigned w0 = cand[k];
             const unsigned w1 = k2 < ncand ? cand[k2] : w0;
-            const bool h0 = test(w0);
-            const bool h1 = test(w1) && k2 < ncand;
-            bits |= (h0 ? 1ull : 0ull) << j;
-            bits |= (h1 ? 1ull : 0ull) << (j + 1);
+            const int h0 = test(w0);
+            const int h1 = k2 < ncand ? test(w1) : 0;
+            bits |= (unsigned long long)(h0 != 0) << j | (unsigned long long)(h1 != 0) << (j + 1);
+            cbits |= (unsigned long long)(h0 == 2) << j | (unsigned long long)(h1 == 2) << (j + 1);
         }
-        const int c = __popcll(bits);
+        const int cc = __popcll(cbits);
+        const int c = (__popcll(bits) - cc) | (cc << 16);
         int incl = c;
         for (int o = 1; o < 64; o <<= 1) {
             const int u = __shfl_up(incl, o, 64);
@@ -1556,19 +1578,22 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
         if (lane == 63) T.wsum[wid] = incl;
         __syncthreads();
         int q = incl - c;
-        int nhit = 0;
+        int tot = 0;
         for (int w = 0; w < kBlock / 64; ++w) {
             q += w < wid ? T.wsum[w] : 0;
-            nhit += T.wsum[w];
+            tot += T.wsum[w];
         }
+        const int nfar = tot & 0xffff, nhit = nfar + (tot >> 16);
         if (nhit > P.qcap) {
             if (t == 0) T.ovf = 1;
         } else {
+            int qf = q & 0xffff, qc = nfar + (q >> 16);
             while (bits) {
                 const int jj = __ffsll((long long)bits) - 1;
+                const bool ct = (cbits >> jj) & 1ull;
                 bits &= bits - 1ull;
                 const unsigned wd = cand[t + jj * kBlock];
-                V.queue[q++] = (((wd >> 14) & 0xfffu) << 16) | (wd & 0x3fffu);
+                V.queue[ct ? qc++ : qf++] = (((wd >> 14) & 0xfffu) << 16) | (wd & 0x3fffu);
             }
             if (t == 0) T.qn = nhit;
         }
