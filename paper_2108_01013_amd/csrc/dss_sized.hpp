@@ -12,10 +12,13 @@
 // Ownership: a pair is found once, by its larger member under the key (a, slot): i scans
 // classes 0 .. k_i of every cell of its (2 R_i + 1)^3 stencil (2 R_i + 2 x-cells in a row
 // reached across a sheared y face), and within its own class only partners of smaller key.
-// The owner keeps its side in registers (its own record, with the Stokes terms) and adds the
-// partner side atomically to the atomic force record; the contact-history row of the pair is
-// the owner's.  Classes from wave_cls up take one wavefront per particle (lanes split the
-// stencil rows); the others one lane per particle; both in one launch.
+// The owner's side goes into its own record (with the Stokes terms), the partner side
+// atomically into the atomic force record; the contact-history row of the pair is the
+// owner's.  Classes from wave_cls up take one wavefront per particle (lanes split the stencil
+// rows); the others one lane per particle; both in one launch.  Scans queue their listed
+// pairs in LDS and the pair physics runs on the queue with every lane busy, instead of in
+// the lane that found the pair (a wavefront would otherwise run the physics for one or two
+// hit lanes at a time).
 //
 // Requirements checked on the host: one box, n_x >= 2 R_max + 2, n_y, n_z >= 2 R_max + 1
 // (no cell is reached twice), partial records at most 4096.
@@ -25,16 +28,26 @@
 
 namespace dss {
 
-// Candidates of particle i (slot i, class ci) in stencil row (dz, dy): both pieces of the
-// (wrapped) x window, classes 0 .. ci.  Calls visit(j, x_j) for every slot j of smaller key.
-template <typename Visit>
-__device__ __forceinline__ void sized_row(const BoxParams &G, const int *__restrict__ cell_start,
-                                          const double4 *__restrict__ pa, int i, const double4 &Xi, int ci, int cx,
-                                          int cy, int cz, int dy, int dz, double delta, Visit &&visit)
+// Stencil cursor of particle i (slot i, class ci): stencil rows q = q0, q0 + qstep, ... of the
+// (2R+1)^2 rows (dz, dy), both pieces of each row's (wrapped) x window, classes 0 .. ci, and
+// the slots of each (row, piece, class) cell range.  Resumable: a scan that cannot queue a
+// listed candidate stops on it and takes it up again in the next round.
+struct StencilCursor {
+    int q, part, k;     // stencil row, window piece, class
+    int j, je;          // slot range of (q, part, k); the next candidate is j
+    int done;
+};
+
+// Slot range of the cursor's (row, piece, class).  A row reached across a sheared y face is
+// the window of 2R + 2 x-cells around the displaced position (images shifted by +delta at the
+// top face, so the window is centred on x - delta there, on x + delta at the bottom face).
+__device__ __forceinline__ void cursor_range(const BoxParams &G, const int *__restrict__ cell_start, int ci, int cx,
+                                             int cy, int cz, double delta, StencilCursor &C)
 {
 #pragma clang fp contract(off)
     const int nxc = G.nc[0], nyc = G.nc[1], nzc = G.nc[2];
-    const int R = ci + 1;
+    const int R = ci + 1, side = 2 * R + 1;
+    const int dz = C.q / side - R, dy = C.q - (C.q / side) * side - R;
     int zz = cz + dz;
     zz = zz < 0 ? zz + nzc : (zz >= nzc ? zz - nzc : zz);
     int yy = cy + dy;
@@ -42,7 +55,6 @@ __device__ __forceinline__ void sized_row(const BoxParams &G, const int *__restr
     yy = yy < 0 ? yy + nyc : (yy >= nyc ? yy - nyc : yy);
     int xlo, xhi;
     if (cross != 0) {
-        // top face: images displaced by +delta, so look around x - delta; bottom: x + delta
         const double sh = cross > 0 ? -delta : delta;
         const int k0 = (int)floor(((double)cx * G.cw[0] + sh) / G.cw[0]);
         xlo = k0 - R;
@@ -51,28 +63,68 @@ __device__ __forceinline__ void sized_row(const BoxParams &G, const int *__restr
         xlo = cx - R;
         xhi = cx + R;
     }
-    const int ncb = nxc * nyc * nzc;
-    const int rowc = G.cell_off + (zz * nyc + yy) * nxc;
-    int xl = ((xlo % nxc) + nxc) % nxc;
-    int span = xhi - xlo + 1;
-    for (int part = 0; part < 2 && span > 0; ++part) {
-        const int len = (xl + span <= nxc) ? span : nxc - xl;
-        for (int k = 0; k <= ci; ++k) {
-            const int c0 = k * ncb + rowc + xl;
-            const int jb = cell_start[c0];
-            const int je = cell_start[c0 + len];
-            for (int j = jb; j < je; ++j) {
-                const double4 Xj = pa[j];
-                if (k == ci && !(Xj.w < Xi.w || (Xj.w == Xi.w && j < i))) continue;
-                visit(j, Xj);
+    const int xl = ((xlo % nxc) + nxc) % nxc;
+    const int span = xhi - xlo + 1;
+    const int len0 = (xl + span <= nxc) ? span : nxc - xl;
+    const int x0 = C.part == 0 ? xl : 0;
+    const int len = C.part == 0 ? len0 : span - len0;
+    if (len <= 0) {
+        C.j = C.je = 0;
+        return;
+    }
+    const int c0 = C.k * (nxc * nyc * nzc) + G.cell_off + (zz * nyc + yy) * nxc + x0;
+    C.j = cell_start[c0];
+    C.je = cell_start[c0 + len];
+}
+
+__device__ __forceinline__ void cursor_start(const BoxParams &G, const int *__restrict__ cell_start, int ci, int cx,
+                                             int cy, int cz, double delta, int q0, bool active, StencilCursor &C)
+{
+    const int side = 2 * ci + 3;
+    C.q = q0;
+    C.part = 0;
+    C.k = 0;
+    C.j = C.je = 0;
+    C.done = (!active || q0 >= side * side) ? 1 : 0;
+    if (!C.done) cursor_range(G, cell_start, ci, cx, cy, cz, delta, C);
+}
+
+// Scan of the listed candidates (pairs of smaller partner key within class ci): push(j) queues
+// candidate j and returns false when the queue is full, which ends the scan on j.
+template <typename Push>
+__device__ __forceinline__ void cursor_scan(const DevParams &P, const BoxParams &G, const int *__restrict__ cell_start,
+                                            const double4 *__restrict__ pa, int i, const double4 &Xi, int ci, int cx,
+                                            int cy, int cz, double delta, int qstep, StencilCursor &C, Push &&push)
+{
+    const int side = 2 * ci + 3;
+    while (!C.done) {
+        if (C.j < C.je) {
+            const int j = C.j;
+            const double4 Xj = pa[j];
+            if (C.k != ci || Xj.w < Xi.w || (Xj.w == Xi.w && j < i)) {
+                double dx, dy, dz, r2;
+                min_image(G, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy, dz);
+                if (listed(P, dx, dy, dz, Xi.w, Xj.w, r2) && !push(j)) return;
             }
+            C.j = j + 1;
+        } else {
+            if (++C.k > ci) {
+                C.k = 0;
+                if (++C.part > 1) {
+                    C.part = 0;
+                    C.q += qstep;
+                    if (C.q >= side * side) {
+                        C.done = 1;
+                        return;
+                    }
+                }
+            }
+            cursor_range(G, cell_start, ci, cx, cy, cz, delta, C);
         }
-        xl = 0;
-        span -= len;
     }
 }
 
-// One listed-candidate test and, for a listed pair, its physics; partner side atomically.
+// Physics of a queued pair (i, j), partner side atomically; own side added to f.
 template <typename Real, bool Roll, bool Wave>
 __device__ __forceinline__ void sized_pair(const DevParams &P, const BoxParams &G, const HistView &H, int i, int j,
                                            int idi, const double4 &Xi, const double4 &Vi, const double4 &Wi,
@@ -110,46 +162,104 @@ __device__ __forceinline__ void sized_pair(const DevParams &P, const BoxParams &
     }
 }
 
+// LDS of a workgroup: the lane path's own-side sums, history slot counters and pair queue, or
+// the wavefront path's per-wavefront partner queues.
+constexpr int kLaneQ = 4096;
+constexpr int kWaveQ = 512;
+struct LaneShared {
+    double acc[kBlock * 6];
+    int cnt[kBlock];
+    int qj[kLaneQ];
+    unsigned char qi[kLaneQ];
+    int qn;
+};
+struct WaveShared {
+    int qj[kBlock / 64][kWaveQ];
+    int qn[kBlock / 64];
+    int fill[kBlock / 64];
+};
+union SizedShared {
+    LaneShared l;
+    WaveShared w;
+};
+
 // ----------------------------------------------------------------------------------
 // Lane path: one lane per particle of the classes below wave_cls (slots [0, n_lane), n_lane =
-// first slot of class wave_cls), workgroup lb of nlb striding over the slots.
+// first slot of class wave_cls); workgroup lb of nlb takes blocks of kBlock consecutive slots.
+// Every lane scans its stencil and queues its listed candidates in LDS; when the queue is full
+// or every scan has ended, all lanes evaluate the queued pairs (own side by LDS atomics,
+// history slots from per-particle LDS counters), and the scans resume.
 // ----------------------------------------------------------------------------------
 template <typename Real, bool Roll, bool Wave>
 __device__ __forceinline__ void sized_lane_path(const DevParams &P, const BoxParams &G, const int *__restrict__ cell_start,
                                                 const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                                 const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
                                                 DevClock *clk, int *pair_out, unsigned long long *pair_count,
-                                                double delta, int n_lane, int lb, int nlb, PairTally &tally)
+                                                double delta, int n_lane, int lb, int nlb, PairTally &tally,
+                                                LaneShared &S)
 {
-    for (int i = lb * kBlock + threadIdx.x; i < n_lane; i += nlb * kBlock) {
-        const double4 Xi = pa[i];
-        const double4 Vi = vel[i];
-        const double4 Wi = omg[i];
-        const int idi = (int)Wi.w;
+    const int t = threadIdx.x;
+    for (int base = lb * kBlock; base < n_lane; base += nlb * kBlock) {
+        const int i = base + t;
+        const bool act = i < n_lane;
+        const double4 Xi = pa[act ? i : base];
         const int ci = size_class(P, Xi.w);
-        const int R = ci + 1;
         const int cx = cell_coord(Xi.x, G.cw[0], G.nc[0]);
         const int cy = cell_coord(Xi.y, G.cw[1], G.nc[1]);
         const int cz = cell_coord(Xi.z, G.cw[2], G.nc[2]);
-        double f[6] = {0, 0, 0, 0, 0, 0};
-        int fill = 0;
-        for (int dz = -R; dz <= R; ++dz)
-            for (int dy = -R; dy <= R; ++dy)
-                sized_row(G, cell_start, pa, i, Xi, ci, cx, cy, cz, dy, dz, delta, [&](int j, const double4 &Xj) {
-                    int need, idj = 0;
-                    PairOut o;
-                    sized_pair<Real, Roll, Wave>(P, G, H, i, j, idi, Xi, Vi, Wi, Xj, delta, vel, omg, B, clk, pair_out,
-                                           pair_count, tally, f, need, o, idj);
-                    if (need) {
-                        store_history<Roll>(H, P.M, i, fill, idi, idj, o, clk);
-                        ++fill;
-                    }
-                });
-        finish_row<Roll>(H, P.M, i, fill, idi);
-        tally.fill = max(tally.fill, fill);
-        stokes_terms<Wave>(P, G, Xi, Vi, Wi, f, tally.S);
-        store_ft(B.own + 6LL * i, f);
-        if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
+        StencilCursor C;
+        cursor_start(G, cell_start, ci, cx, cy, cz, delta, 0, act, C);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) S.acc[6 * t + k] = 0.0;
+        S.cnt[t] = 0;
+        if (t == 0) S.qn = 0;
+        __syncthreads();
+        for (;;) {
+            cursor_scan(P, G, cell_start, pa, i, Xi, ci, cx, cy, cz, delta, 1, C, [&](int j) -> bool {
+                const int e = atomicAdd(&S.qn, 1);
+                if (e >= kLaneQ) return false;
+                S.qj[e] = j;
+                S.qi[e] = (unsigned char)t;
+                return true;
+            });
+            __syncthreads();
+            const int nq = min(S.qn, kLaneQ);
+            for (int e = t; e < nq; e += kBlock) {
+                const int il = S.qi[e];
+                const int gi = base + il;
+                const int j = S.qj[e];
+                const double4 Xa = pa[gi];
+                const double4 Va = vel[gi];
+                const double4 Wa = omg[gi];
+                const int ida = (int)Wa.w;
+                double f[6] = {0, 0, 0, 0, 0, 0};
+                int need, idj = 0;
+                PairOut o;
+                sized_pair<Real, Roll, Wave>(P, G, H, gi, j, ida, Xa, Va, Wa, pa[j], delta, vel, omg, B, clk, pair_out,
+                                             pair_count, tally, f, need, o, idj);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) atomicAdd(&S.acc[6 * il + k], f[k]);
+                if (need) store_history<Roll>(H, P.M, gi, atomicAdd(&S.cnt[il], 1), ida, idj, o, clk);
+            }
+            if (__syncthreads_and(C.done)) break;
+            if (t == 0) S.qn = 0;
+            __syncthreads();
+        }
+        if (act) {
+            const double4 Vi = vel[i];
+            const double4 Wi = omg[i];
+            const int idi = (int)Wi.w;
+            double f[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) f[k] = S.acc[6 * t + k];
+            const int fill = S.cnt[t];
+            finish_row<Roll>(H, P.M, i, fill, idi);
+            tally.fill = max(tally.fill, fill);
+            stokes_terms<Wave>(P, G, Xi, Vi, Wi, f, tally.S);
+            store_ft(B.own + 6LL * i, f);
+            if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
+        }
+        __syncthreads();
     }
 }
 
@@ -221,48 +331,70 @@ __device__ __forceinline__ void wave_finish_row(const HistView &H, int M, int gi
 
 // ----------------------------------------------------------------------------------
 // Wavefront path: one wavefront per particle of the classes from wave_cls up (slots
-// [n_lane, N)), workgroup wb of nwb; lanes stride over the (2R+1)^2 stencil rows, contacts
-// take their history slots from a per-wavefront LDS counter, the wavefront sums its own side
-// and sorts the row.
+// [n_lane, N)), workgroup wb of nwb.  Lanes stride over the (2R+1)^2 stencil rows and queue
+// the listed candidates in the wavefront's LDS queue; when it is full or every lane's scan has
+// ended, the 64 lanes evaluate the queued pairs (contacts take their history slots from a
+// per-wavefront counter), and the scans resume.  The wavefront sums its own side and sorts
+// the row.
 // ----------------------------------------------------------------------------------
 template <typename Real, bool Roll, bool Wave>
 __device__ __forceinline__ void sized_wave_path(const DevParams &P, const BoxParams &G, const int *__restrict__ cell_start,
                                                 const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                                 const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
                                                 DevClock *clk, int *pair_out, unsigned long long *pair_count,
-                                                double delta, int n_lane, int wb, int nwb, int *wfill,
+                                                double delta, int n_lane, int wb, int nwb, WaveShared &S,
                                                 PairTally &tally)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nwave = nwb * (kBlock / 64);
+    int *const qj = S.qj[wid];
     for (int i = n_lane + wb * (kBlock / 64) + wid; i < P.N; i += nwave) {
         const double4 Xi = pa[i];
         const double4 Vi = vel[i];
         const double4 Wi = omg[i];
         const int idi = (int)Wi.w;
         const int ci = size_class(P, Xi.w);
-        const int R = ci + 1, side = 2 * R + 1;
         const int cx = cell_coord(Xi.x, G.cw[0], G.nc[0]);
         const int cy = cell_coord(Xi.y, G.cw[1], G.nc[1]);
         const int cz = cell_coord(Xi.z, G.cw[2], G.nc[2]);
-        if (lane == 0) wfill[wid] = 0;
+        if (lane == 0) {
+            S.fill[wid] = 0;
+            S.qn[wid] = 0;
+        }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        StencilCursor C;
+        cursor_start(G, cell_start, ci, cx, cy, cz, delta, lane, true, C);
         double f[6] = {0, 0, 0, 0, 0, 0};
-        for (int q = lane; q < side * side; q += 64) {
-            const int dz = q / side - R, dy = q % side - R;
-            sized_row(G, cell_start, pa, i, Xi, ci, cx, cy, cz, dy, dz, delta, [&](int j, const double4 &Xj) {
+        for (;;) {
+            cursor_scan(P, G, cell_start, pa, i, Xi, ci, cx, cy, cz, delta, 64, C, [&](int j) -> bool {
+                const int e = atomicAdd(&S.qn[wid], 1);
+                if (e >= kWaveQ) return false;
+                qj[e] = j;
+                return true;
+            });
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const int nq = min(S.qn[wid], kWaveQ);
+            for (int e = lane; e < nq; e += 64) {
+                const int j = qj[e];
                 int need, idj = 0;
                 PairOut o;
-                sized_pair<Real, Roll, Wave>(P, G, H, i, j, idi, Xi, Vi, Wi, Xj, delta, vel, omg, B, clk, pair_out,
-                                       pair_count, tally, f, need, o, idj);
-                if (need) store_history<Roll>(H, P.M, i, atomicAdd(&wfill[wid], 1), idi, idj, o, clk);
-            });
+                sized_pair<Real, Roll, Wave>(P, G, H, i, j, idi, Xi, Vi, Wi, pa[j], delta, vel, omg, B, clk, pair_out,
+                                             pair_count, tally, f, need, o, idj);
+                if (need) store_history<Roll>(H, P.M, i, atomicAdd(&S.fill[wid], 1), idi, idj, o, clk);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (__all(C.done)) break;
+            if (lane == 0) S.qn[wid] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
         // the row's entries, written by all lanes, are visible to the whole wavefront
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        const int fill = wfill[wid];
+        const int fill = S.fill[wid];
 #pragma unroll
         for (int k = 0; k < 6; ++k) f[k] = warp_sum(f[k]);
         wave_finish_row<Roll>(H, P.M, i, fill, idi);
@@ -272,6 +404,8 @@ __device__ __forceinline__ void sized_wave_path(const DevParams &P, const BoxPar
             store_ft(B.own + 6LL * i, f);
             if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -292,7 +426,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const Bo
                                                         unsigned long long *__restrict__ pair_count)
 {
     __shared__ double red[kBlock / 64][12];
-    __shared__ int wfill[kBlock / 64];
+    __shared__ SizedShared U;
     const BoxParams G = boxes[0];
     const int ncb = G.nc[0] * G.nc[1] * G.nc[2];
     const int n_lane = P.wave_cls < P.ncls ? cell_start[P.wave_cls * ncb] : P.N;
@@ -306,10 +440,11 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const Bo
     const int b = blockIdx.x;
     if (b < g_wave)
         sized_wave_path<Real, Roll, Wave>(P, G, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, delta, n_lane, b,
-                                    g_wave, wfill, tally);
+                                          g_wave, U.w, tally);
     else
         sized_lane_path<Real, Roll, Wave>(P, G, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, delta, n_lane,
-                                    xcd_row(b - g_wave, (int)gridDim.x - g_wave), (int)gridDim.x - g_wave, tally);
+                                          xcd_row(b - g_wave, (int)gridDim.x - g_wave), (int)gridDim.x - g_wave, tally,
+                                          U.l);
     if constexpr (Sum) reduce_tally(tally, red, partials, P.pstride, b);
 }
 
