@@ -174,8 +174,12 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
  *               (dss_get_cells returns size_classes x n_cells + 1 starts); one box only
  *               (DSS_ERR_ARG on a batch handle); tile_scale and tiled are then unused;
  *   wave_class: with sized, size classes from this one up (stencil radius wave_class + 1
- *               and more) take one wavefront per particle; 0 = 3.
- * Defaults: {1, 1, 1, 1, 0, 0}.  reserved must be 0. */
+ *               and more) take one wavefront per particle; 0 = 3;
+ *   queue_cap:  with sized, the length of the LDS queues of listed pairs (a workgroup's on
+ *               the lane path, up to 4096; a wavefront's, up to 512), so that a scan stops
+ *               and resumes after every queue_cap pairs; 0 = the full length, any other
+ *               value only for checking the stop-and-resume path (it costs time).
+ * Defaults: {1, 1, 1, 1, 0, 0, 0}.  reserved must be 0. */
 typedef struct {
     double cell_scale;
     double tile_scale;
@@ -183,7 +187,8 @@ typedef struct {
     int32_t graph;
     int32_t sized;
     int32_t wave_class;
-    int32_t reserved[2];
+    int32_t queue_cap;
+    int32_t reserved;
 } dss_tuning;
 
 /* Set the launch tuning.  Before dss_set_particles it applies to the first lattice; after,

@@ -48,7 +48,7 @@ struct dss_handle {
     std::vector<double> rad_host;     // radii by id (size-class counts of the stencil path)
     int sized_grid[2] = {0, 0};       // lane and wavefront workgroups of k_pairs_sized
     double max_mean_row = 0.0;        // mean particles per cell row of the densest box
-    dss_tuning tune{1.0, 1.0, 1, 1, 0, 0, {0, 0}};
+    dss_tuning tune{1.0, 1.0, 1, 1, 0, 0, 0, 0};
     bool tune_pending = false;        // lattice to rebuild before the next time step
     // HIP graphs of one time step, keyed by (current buffers, committed history buffers,
     // half-step velocities, stress summation)
@@ -530,8 +530,8 @@ void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
         TimedLaunch t(h, 3);
         hipExtLaunchKernelGGL(k_pairs_sized<Real, Roll, Wave, Sum>, dim3(h->sized_grid[0] + h->sized_grid[1]), dim3(kBlock), 0,
                               h->stream, t.e0, t.e1, 0, h->P, h->d_boxes, h->cell_start, h->pa[buf], h->vel[buf],
-                              h->omg[buf], h->fb(), H, h->clk, h->partials, h->sized_grid[1], h->pairs,
-                              h->pair_count);
+                              h->omg[buf], h->fb(), H, h->clk, h->partials, h->sized_grid[1], h->tune.queue_cap,
+                              h->pairs, h->pair_count);
         return;
     }
     {
@@ -1001,9 +1001,9 @@ dss_status dss_set_tuning(dss_handle *h, const dss_tuning *t)
     if (!h || !t) return DSS_ERR_ARG;
     if (!(t->cell_scale >= 1.0 && t->cell_scale <= 4.0) || !(t->tile_scale >= 0.25 && t->tile_scale <= 4.0) ||
         (t->tiled != 0 && t->tiled != 1) || (t->graph != 0 && t->graph != 1) || (t->sized != 0 && t->sized != 1) ||
-        t->wave_class < 0 || t->wave_class > 64 || t->reserved[0] || t->reserved[1])
+        t->wave_class < 0 || t->wave_class > 64 || t->queue_cap < 0 || t->reserved)
         return fail(h, DSS_ERR_ARG, "tuning out of range (cell_scale in [1, 4], tile_scale in [0.25, 4], "
-                                    "wave_class in [0, 64], flags 0/1)");
+                                    "wave_class in [0, 64], queue_cap >= 0, flags 0/1)");
     if (t->sized && h->nbox != 1) return fail(h, DSS_ERR_ARG, "size-class stencils need a handle of one box");
     if (h->loaded) {
         // the lattice must still be legal for every box
@@ -1017,8 +1017,9 @@ dss_status dss_set_tuning(dss_handle *h, const dss_tuning *t)
     const bool lattice = t->cell_scale != h->tune.cell_scale || t->tile_scale != h->tune.tile_scale ||
                          t->tiled != h->tune.tiled || t->sized != h->tune.sized ||
                          t->wave_class != h->tune.wave_class;
+    // the captured graphs hold the queue length as a kernel argument
+    if (!t->graph || t->queue_cap != h->tune.queue_cap) destroy_graphs(h);
     h->tune = *t;
-    if (!t->graph) destroy_graphs(h);
     if (h->loaded && lattice) h->tune_pending = true;
     return DSS_OK;
 }

@@ -195,10 +195,11 @@ __device__ __forceinline__ void sized_lane_path(const DevParams &P, const BoxPar
                                                 const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                                 const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
                                                 DevClock *clk, int *pair_out, unsigned long long *pair_count,
-                                                double delta, int n_lane, int lb, int nlb, PairTally &tally,
+                                                double delta, int n_lane, int lb, int nlb, int qcap, PairTally &tally,
                                                 LaneShared &S)
 {
     const int t = threadIdx.x;
+    const int cap = qcap > 0 && qcap < kLaneQ ? qcap : kLaneQ;
     for (int base = lb * kBlock; base < n_lane; base += nlb * kBlock) {
         const int i = base + t;
         const bool act = i < n_lane;
@@ -217,13 +218,13 @@ __device__ __forceinline__ void sized_lane_path(const DevParams &P, const BoxPar
         for (;;) {
             cursor_scan(P, G, cell_start, pa, i, Xi, ci, cx, cy, cz, delta, 1, C, [&](int j) -> bool {
                 const int e = atomicAdd(&S.qn, 1);
-                if (e >= kLaneQ) return false;
+                if (e >= cap) return false;
                 S.qj[e] = j;
                 S.qi[e] = (unsigned char)t;
                 return true;
             });
             __syncthreads();
-            const int nq = min(S.qn, kLaneQ);
+            const int nq = min(S.qn, cap);
             for (int e = t; e < nq; e += kBlock) {
                 const int il = S.qi[e];
                 const int gi = base + il;
@@ -342,10 +343,11 @@ __device__ __forceinline__ void sized_wave_path(const DevParams &P, const BoxPar
                                                 const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                                 const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
                                                 DevClock *clk, int *pair_out, unsigned long long *pair_count,
-                                                double delta, int n_lane, int wb, int nwb, WaveShared &S,
+                                                double delta, int n_lane, int wb, int nwb, int qcap, WaveShared &S,
                                                 PairTally &tally)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int cap = qcap > 0 && qcap < kWaveQ ? qcap : kWaveQ;
     const int nwave = nwb * (kBlock / 64);
     int *const qj = S.qj[wid];
     for (int i = n_lane + wb * (kBlock / 64) + wid; i < P.N; i += nwave) {
@@ -369,13 +371,13 @@ __device__ __forceinline__ void sized_wave_path(const DevParams &P, const BoxPar
         for (;;) {
             cursor_scan(P, G, cell_start, pa, i, Xi, ci, cx, cy, cz, delta, 64, C, [&](int j) -> bool {
                 const int e = atomicAdd(&S.qn[wid], 1);
-                if (e >= kWaveQ) return false;
+                if (e >= cap) return false;
                 qj[e] = j;
                 return true;
             });
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            const int nq = min(S.qn[wid], kWaveQ);
+            const int nq = min(S.qn[wid], cap);
             for (int e = lane; e < nq; e += 64) {
                 const int j = qj[e];
                 int need, idj = 0;
@@ -422,7 +424,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const Bo
                                                         const double4 *__restrict__ vel,
                                                         const double4 *__restrict__ omg, ForceBufs B, HistView H,
                                                         DevClock *__restrict__ clk, double *__restrict__ partials,
-                                                        int g_wave, int *__restrict__ pair_out,
+                                                        int g_wave, int qcap, int *__restrict__ pair_out,
                                                         unsigned long long *__restrict__ pair_count)
 {
     __shared__ double red[kBlock / 64][12];
@@ -440,11 +442,11 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_sized(DevParams P, const Bo
     const int b = blockIdx.x;
     if (b < g_wave)
         sized_wave_path<Real, Roll, Wave>(P, G, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, delta, n_lane, b,
-                                          g_wave, U.w, tally);
+                                          g_wave, qcap, U.w, tally);
     else
         sized_lane_path<Real, Roll, Wave>(P, G, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count, delta, n_lane,
-                                          xcd_row(b - g_wave, (int)gridDim.x - g_wave), (int)gridDim.x - g_wave, tally,
-                                          U.l);
+                                          xcd_row(b - g_wave, (int)gridDim.x - g_wave), (int)gridDim.x - g_wave, qcap,
+                                          tally, U.l);
     if constexpr (Sum) reduce_tally(tally, red, partials, P.pstride, b);
 }
 

@@ -156,6 +156,24 @@ def test_sized_bidisperse_ties():
     sim.close()
 
 
+@pytest.mark.parametrize("queue_cap", [1, 7, 64])
+def test_sized_queue_stop_and_resume(poly_box, queue_cap):
+    """Pair queues of queue_cap entries, so every stencil scan stops on a full queue and resumes
+    after the queue is evaluated, many times per evaluation (at the full queue length this box
+    never fills them): lane and wavefront paths, lockstep against the oracle as above."""
+    w = poly_box
+    p = w.params
+    say(f"case: sized N=3000 queue_cap={queue_cap}")
+    sim = _sim(p, record_pairs=True)
+    sim.set_tuning(sized=True, wave_class=2, queue_cap=queue_cap)
+    assert sim.tuning()["queue_cap"] == queue_cap
+    sim.set_particles(w.x, w.rad)
+    sim.step(2)
+    contacts = lockstep(sim, p, w, 2, 2, TOL_F)
+    assert contacts > 0
+    sim.close()
+
+
 def test_sized_needs_one_box():
     from paper_2108_01013_amd.dss import Batch, DssError
     w = synth.config_small()
