@@ -195,8 +195,10 @@ def test_save_and_load_state():
     sim.close()
 
 
-@pytest.mark.parametrize("sized,precision", [(False, 0), (False, 1), (True, 0)])
-def test_stress_summed_only_on_sampled_steps(sized, precision):
+@pytest.mark.parametrize("sized,precision,tiled,physics", [
+    (False, 0, True, None), (False, 1, True, None), (True, 0, True, None), (False, 0, False, None),
+    (False, 0, True, "rolling"), (False, 0, True, "wavy")])
+def test_stress_summed_only_on_sampled_steps(sized, precision, tiled, physics):
     """Steps between stress samples run the pair kernels without the stress and counters; the
     dynamics and the samples equal those of a run that sums the stress on every step.  FP64:
     to the reordering of the atomic sums.  Mixed: the FP32 products that fed only the stresslet
@@ -212,11 +214,15 @@ def test_stress_summed_only_on_sampled_steps(sized, precision):
     else:
         w = synth.bidisperse_box(4000, 0.55, seed=13)
         x, rad, p = w.x, w.rad, w.params
-    say(f"case: stress on sampled steps only, sized={sized} precision={precision}")
+    if physics == "rolling":
+        p = dict(p, kr=0.05 * p["kn"], mu_r=0.1)
+    elif physics == "wavy":
+        p = dict(p, wave_amp=20.0 * p["shear_rate"] * p["a0"], wave_n=1.0)
+    say(f"case: stress on sampled steps only, sized={sized} precision={precision} tiled={tiled} {physics}")
     runs = []
     for every_step in (False, True):
         sim = Simulation(p, precision=precision)
-        sim.set_tuning(sized=sized)
+        sim.set_tuning(sized=sized, tiled=tiled)
         sim.set_particles(x, rad)
         if every_step:
             lasts = []
