@@ -409,24 +409,35 @@ def test_high_size_ratio(poly_box, tiled, precision):
     sim.close()
 
 
-def test_free_trajectory_100_steps():
-    """100 steps of the small workload (N = 1000) run freely on the GPU and on the oracle from
-    the same initial state, with no state passed between them: positions (nearest image),
-    velocities, rotations and the mean of the ten stress samples.  Not a bitwise contract:
-    the force atomics sum in another order at every evaluation and the contacts amplify the
-    difference.  Measured: 3.6e-15 in position, 8.5e-15 / 9.3e-15 in u / w, 3.9e-16 in the
-    mean stress; the bound is 1e-10 of the largest value."""
-    w = synth.config_small()
-    p = w.params
-    say("case: free trajectory, 100 steps, N=1000")
-    sim = _sim(p)
-    sim.set_particles(w.x, w.rad)
+@pytest.mark.parametrize("case", ["fp64", "mixed", "sized"])
+def test_free_trajectory_100_steps(case):
+    """100 steps run freely on the GPU and on the oracle from the same initial state, with no
+    state passed between them: positions (nearest image), velocities, rotations and the mean of
+    the ten stress samples.  fp64 and mixed: the small workload (N = 1000); sized: lognormal
+    radii on [1, 10] (N = 3000) on the size-class stencils.  Not a bitwise contract: the force
+    atomics sum in another order at every evaluation and the contacts amplify the difference.
+    Measured (fp64): 3.6e-15 in position, 8.5e-15 / 9.3e-15 in u / w, 3.9e-16 in the mean
+    stress.  Bounds: 1e-10 of the largest value in FP64, 1e-5 in mixed precision."""
+    if case == "sized":
+        rad = synth.lognormal_radii(3000, seed=7)
+        L = synth.box_for_fraction(rad, 0.55)
+        x = synth.relax_positions(rad, L, seed=8)
+        p = synth.default_params([L, L, L])
+    else:
+        w = synth.config_small()
+        x, rad, p = w.x, w.rad, w.params
+    tol = 1e-5 if case == "mixed" else 1e-10
+    say(f"case: free trajectory, 100 steps, {case} N={len(rad)}")
+    sim = _sim(p, precision=1 if case == "mixed" else 0)
+    if case == "sized":
+        sim.set_tuning(sized=True, wave_class=2)
+    sim.set_particles(x, rad)
     sim.step(100, stress_every=10)
     s = sim.state()
     _, mean_g, ns = sim.read_stress()
     sim.close()
     assert ns == 10
-    st, F, T, S = oracle.init_state(p, w.x, w.rad)
+    st, F, T, S = oracle.init_state(p, x, rad)
     samples = []
     for n in range(1, 101):
         st, F, T, S, npairs, _ = oracle.step(p, st, use_cells=True)
@@ -437,5 +448,5 @@ def test_free_trajectory_100_steps():
     dx = np.array([oracle.min_image(p, delta, a, b) for a, b in zip(st.x, s["x"])])
     ex = float(np.max(np.abs(dx)))
     eu, ew, es = rel_inf(s["u"], st.u), rel_inf(s["w"], st.w), rel_inf(mean_g, mean_o)
-    say(f"100-step deviations: |dx|max {ex:.2e}, u {eu:.2e}, w {ew:.2e}, mean Sigma {es:.2e}")
-    assert ex <= 1e-10 * p["a0"] and eu < 1e-10 and ew < 1e-10 and es < 1e-10
+    say(f"100-step deviations ({case}): |dx|max {ex:.2e}, u {eu:.2e}, w {ew:.2e}, mean Sigma {es:.2e}")
+    assert ex <= tol * p["a0"] and eu < tol and ew < tol and es < tol
