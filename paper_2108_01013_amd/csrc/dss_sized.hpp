@@ -28,26 +28,44 @@
 
 namespace dss {
 
-// Stencil cursor of particle i (slot i, class ci): stencil rows q = q0, q0 + qstep, ... of the
-// (2R+1)^2 rows (dz, dy), both pieces of each row's (wrapped) x window, classes 0 .. ci, and
-// the slots of each (row, piece, class) cell range.  Resumable: a scan that cannot queue a
-// listed candidate stops on it and takes it up again in the next round.
+// Stencil cursor of particle i (slot i, class ci): items (row, window piece, class) over the
+// stencil rows q = q0, q0 + qstep, ... of the (2R+1)^2 rows (dz, dy), both pieces of each
+// row's (wrapped) x window, classes 0 .. ci, and the slots of each item's cell range.  The
+// range of the following item is requested when an item begins, so that its cell-start loads
+// overlap the candidates of the current one.  Resumable: a scan that cannot queue a listed
+// candidate stops on it and takes it up again in the next round.
 struct StencilCursor {
-    int q, part, k;     // stencil row, window piece, class
-    int j, je;          // slot range of (q, part, k); the next candidate is j
+    int q, part, k;     // current item: stencil row, window piece, class
+    int j, je;          // its slot range; the next candidate is j
     int done;
+    int nq, npart, nk;  // the following item, its range already requested
+    int nj, nje;
+    int ndone;
 };
 
-// Slot range of the cursor's (row, piece, class).  A row reached across a sheared y face is
-// the window of 2R + 2 x-cells around the displaced position (images shifted by +delta at the
-// top face, so the window is centred on x - delta there, on x + delta at the bottom face).
-__device__ __forceinline__ void cursor_range(const BoxParams &G, const int *__restrict__ cell_start, int ci, int cx,
-                                             int cy, int cz, double delta, StencilCursor &C)
+// The item after (q, part, k) for a lane striding qstep rows: classes, then pieces, then rows.
+__device__ __forceinline__ void item_advance(int ci, int qstep, int &q, int &part, int &k, int &done)
+{
+    if (++k > ci) {
+        k = 0;
+        if (++part > 1) {
+            part = 0;
+            q += qstep;
+            if (q >= (2 * ci + 3) * (2 * ci + 3)) done = 1;
+        }
+    }
+}
+
+// Slot range [j, je) of item (q, part, k).  A row reached across a sheared y face is the
+// window of 2R + 2 x-cells around the displaced position (images shifted by +delta at the top
+// face, so the window is centred on x - delta there, on x + delta at the bottom face).
+__device__ __forceinline__ void item_range(const BoxParams &G, const int *__restrict__ cell_start, int ci, int cx,
+                                           int cy, int cz, double delta, int q, int part, int k, int &j, int &je)
 {
 #pragma clang fp contract(off)
     const int nxc = G.nc[0], nyc = G.nc[1], nzc = G.nc[2];
     const int R = ci + 1, side = 2 * R + 1;
-    const int dz = C.q / side - R, dy = C.q - (C.q / side) * side - R;
+    const int dz = q / side - R, dy = q - (q / side) * side - R;
     int zz = cz + dz;
     zz = zz < 0 ? zz + nzc : (zz >= nzc ? zz - nzc : zz);
     int yy = cy + dy;
@@ -66,19 +84,33 @@ __device__ __forceinline__ void cursor_range(const BoxParams &G, const int *__re
     const int xl = ((xlo % nxc) + nxc) % nxc;
     const int span = xhi - xlo + 1;
     const int len0 = (xl + span <= nxc) ? span : nxc - xl;
-    const int x0 = C.part == 0 ? xl : 0;
-    const int len = C.part == 0 ? len0 : span - len0;
+    const int x0 = part == 0 ? xl : 0;
+    const int len = part == 0 ? len0 : span - len0;
     if (len <= 0) {
-        C.j = C.je = 0;
+        j = je = 0;
         return;
     }
-    const int c0 = C.k * (nxc * nyc * nzc) + G.cell_off + (zz * nyc + yy) * nxc + x0;
-    C.j = cell_start[c0];
-    C.je = cell_start[c0 + len];
+    const int c0 = k * (nxc * nyc * nzc) + G.cell_off + (zz * nyc + yy) * nxc + x0;
+    j = cell_start[c0];
+    je = cell_start[c0 + len];
+}
+
+// Request the range of the following item (or mark the cursor's end).
+__device__ __forceinline__ void cursor_prefetch(const BoxParams &G, const int *__restrict__ cell_start, int ci, int cx,
+                                                int cy, int cz, double delta, int qstep, StencilCursor &C)
+{
+    C.nq = C.q;
+    C.npart = C.part;
+    C.nk = C.k;
+    C.ndone = 0;
+    C.nj = C.nje = 0;
+    item_advance(ci, qstep, C.nq, C.npart, C.nk, C.ndone);
+    if (!C.ndone) item_range(G, cell_start, ci, cx, cy, cz, delta, C.nq, C.npart, C.nk, C.nj, C.nje);
 }
 
 __device__ __forceinline__ void cursor_start(const BoxParams &G, const int *__restrict__ cell_start, int ci, int cx,
-                                             int cy, int cz, double delta, int q0, bool active, StencilCursor &C)
+                                             int cy, int cz, double delta, int q0, int qstep, bool active,
+                                             StencilCursor &C)
 {
     const int side = 2 * ci + 3;
     C.q = q0;
@@ -86,7 +118,12 @@ __device__ __forceinline__ void cursor_start(const BoxParams &G, const int *__re
     C.k = 0;
     C.j = C.je = 0;
     C.done = (!active || q0 >= side * side) ? 1 : 0;
-    if (!C.done) cursor_range(G, cell_start, ci, cx, cy, cz, delta, C);
+    C.nq = C.npart = C.nk = C.nj = C.nje = 0;
+    C.ndone = 1;
+    if (!C.done) {
+        item_range(G, cell_start, ci, cx, cy, cz, delta, C.q, C.part, C.k, C.j, C.je);
+        cursor_prefetch(G, cell_start, ci, cx, cy, cz, delta, qstep, C);
+    }
 }
 
 // Scan of the listed candidates (pairs of smaller partner key within class ci): push(j) queues
@@ -96,7 +133,6 @@ __device__ __forceinline__ void cursor_scan(const DevParams &P, const BoxParams 
                                             const double4 *__restrict__ pa, int i, const double4 &Xi, int ci, int cx,
                                             int cy, int cz, double delta, int qstep, StencilCursor &C, Push &&push)
 {
-    const int side = 2 * ci + 3;
     while (!C.done) {
         if (C.j < C.je) {
             const int j = C.j;
@@ -108,18 +144,14 @@ __device__ __forceinline__ void cursor_scan(const DevParams &P, const BoxParams 
             }
             C.j = j + 1;
         } else {
-            if (++C.k > ci) {
-                C.k = 0;
-                if (++C.part > 1) {
-                    C.part = 0;
-                    C.q += qstep;
-                    if (C.q >= side * side) {
-                        C.done = 1;
-                        return;
-                    }
-                }
-            }
-            cursor_range(G, cell_start, ci, cx, cy, cz, delta, C);
+            // the following item, whose range was requested when this one began
+            C.q = C.nq;
+            C.part = C.npart;
+            C.k = C.nk;
+            C.j = C.nj;
+            C.je = C.nje;
+            C.done = C.ndone;
+            if (!C.done) cursor_prefetch(G, cell_start, ci, cx, cy, cz, delta, qstep, C);
         }
     }
 }
@@ -209,7 +241,7 @@ __device__ __forceinline__ void sized_lane_path(const DevParams &P, const BoxPar
         const int cy = cell_coord(Xi.y, G.cw[1], G.nc[1]);
         const int cz = cell_coord(Xi.z, G.cw[2], G.nc[2]);
         StencilCursor C;
-        cursor_start(G, cell_start, ci, cx, cy, cz, delta, 0, act, C);
+        cursor_start(G, cell_start, ci, cx, cy, cz, delta, 0, 1, act, C);
 #pragma unroll
         for (int k = 0; k < 6; ++k) S.acc[6 * t + k] = 0.0;
         S.cnt[t] = 0;
@@ -366,7 +398,7 @@ __device__ __forceinline__ void sized_wave_path(const DevParams &P, const BoxPar
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         StencilCursor C;
-        cursor_start(G, cell_start, ci, cx, cy, cz, delta, lane, true, C);
+        cursor_start(G, cell_start, ci, cx, cy, cz, delta, lane, 64, true, C);
         double f[6] = {0, 0, 0, 0, 0, 0};
         for (;;) {
             cursor_scan(P, G, cell_start, pa, i, Xi, ci, cx, cy, cz, delta, 64, C, [&](int j) -> bool {
