@@ -213,8 +213,10 @@ dss_status dss_compute_forces(dss_handle *h);
 
 /* Advance n_steps time steps.  If stress_every > 0, the stress tensor is sampled at
  * every step whose time index is a multiple of stress_every; the samples of this call
- * are returned by dss_read_stress.  Does not synchronise unless sync != 0 (then device
- * error flags are checked). */
+ * are returned by dss_read_stress.  The stress and the pair and contact counters are
+ * summed only on those steps and on the last step of the call (the other steps skip the
+ * stresslet; their forces, torques and history are the same).  Does not synchronise
+ * unless sync != 0 (then device error flags are checked). */
 dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sync);
 
 /* Stress of the last force evaluation (sigma_last, 9 values, row-major Sigma_ab) and the
