@@ -60,8 +60,8 @@ typedef enum { DSS_FP64 = 0, DSS_MIXED = 1 } dss_precision;
  * surface distance d_ij < 20 lambda_D, attraction, eq. att, while d_ij < 4 a0; lubrication
  * stays on |r| < cutoff_factor (a_i + a_j).  The pair set (and the cell lattice) then covers
  * |r| < max(cutoff_factor (a_i + a_j), a_i + a_j + the longest active range).  Without the
- * flag both forces are truncated at the lubrication list.  Not with size-class stencils or
- * the adjoint (DSS_ERR_ARG / DSS_ERR_STATE). */
+ * flag both forces are truncated at the lubrication list.  Not with size-class stencils
+ * (DSS_ERR_ARG).  With the adjoint the three ranges are held fixed like the pair set. */
 #define DSS_FLAG_EC_RANGES 2
 
 /* Physical and numerical parameters (units are the caller's; the defaults used by the
@@ -279,7 +279,9 @@ dss_status dss_get_box_info(dss_handle *h, int32_t box, dss_box_info *info);
  * a segment of ckpt_every recorded steps).  On return the handle stands at the end of the
  * run, as after dss_step(h, n_steps, stress_every, 1).  Requires a single-box handle whose
  * forces were evaluated at u^n (right after dss_set_particles or dss_compute_forces: else
- * DSS_ERR_STATE) and at least one stress sample in the run (else DSS_ERR_ARG). */
+ * DSS_ERR_STATE) and at least one stress sample in the run (else DSS_ERR_ARG).  Takes the
+ * electro-chemical ranges (which pair is inside which range is held fixed); rolling
+ * resistance and the wavy shear are refused (DSS_ERR_STATE). */
 dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress_every, int64_t ckpt_every, const double *weight,
                        double *J, double *dJ_dparams, double *dJ_dx, double *dJ_du, double *dJ_dw, int on_device);
 

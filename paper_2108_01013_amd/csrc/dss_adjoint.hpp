@@ -194,6 +194,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
         PairConst C;
         C.k6 = P.k6; C.kn = P.kn; C.kt = P.kt; C.gn = P.gn; C.mu = P.mu; C.fer = P.fer; C.a0 = P.a0;
         C.lamd = P.lamd; C.ham = P.ham; C.eps_vdw = P.eps_vdw; C.eps_lub = P.eps_lub; C.dt = P.dt;
+        C.ec = P.ec; C.cf = P.cf; C.rep_rng = P.rep_rng; C.att_rng = P.att_rng;
         PairGrad g = {};
         pair_vjp(C, G.gd, r, tp.rad[a], tp.rad[b], xa[1], xb[1], tp.u + 3LL * a, tp.u + 3LL * b, tp.w + 3LL * a,
                  tp.w + 3LL * b, xo, bar, g, nullptr, f_contact, f_capped);

@@ -188,6 +188,25 @@ void free_all(dss_handle *h)
     h->loaded = false;
 }
 
+// Capacity of the recorded pair list: 32 per particle, plus with the electro-chemical ranges
+// the pairs of a uniform gas within the longest cutoff (N_b^2 / V_b x 4/3 pi r_c^3 per box,
+// twice the expected count).
+long long pair_record_capacity(const DevParams &P, const std::vector<BoxParams> &boxes,
+                               const std::vector<double> &box_amax, const int64_t *n_per_box)
+{
+    double extra = 0.0, N = 0.0;
+    for (size_t b = 0; b < boxes.size(); ++b) {
+        N += (double)n_per_box[b];
+        if (P.ec && P.rext > 0.0) {
+            const double rc = 2.0 * box_amax[b] + P.rext;
+            const double V = boxes[b].L[0] * boxes[b].L[1] * boxes[b].L[2];
+            extra += (double)n_per_box[b] * (double)n_per_box[b] / V * (4.0 / 3.0) * kPi * rc * rc * rc;
+        }
+    }
+    const double cap = 32.0 * N + 64.0 + std::min(extra, 0.5 * N * N);
+    return (long long)std::min(cap, 2.0e9);
+}
+
 // Row capacity of the reduced history matrix: the shell of thickness 2 a_min around the
 // largest particle, in units of the smallest particle's volume (Sec. 2.1).
 int paper_capacity(double a_max, double a_min)
@@ -874,20 +893,7 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     P.kr = p.k_roll;
     P.mu_r = p.mu_roll;
     P.wave_amp = p.wave_amp;
-    // recorded pairs: 32 per particle, plus with the ranges the pairs of a uniform gas within
-    // the longest cutoff (N_b^2 / V_b x 4/3 pi r_c^3 per box, twice the expected count)
-    P.pair_cap = 0;
-    if (P.record_pairs) {
-        double extra = 0.0;
-        if (P.ec && P.rext > 0.0)
-            for (int b = 0; b < B; ++b) {
-                const double rc = 2.0 * box_amax[b] + P.rext;
-                const double V = boxes[b].L[0] * boxes[b].L[1] * boxes[b].L[2];
-                extra += (double)n_per_box[b] * (double)n_per_box[b] / V * (4.0 / 3.0) * kPi * rc * rc * rc;
-            }
-        const double cap = 32.0 * (double)N + 64.0 + std::min(extra, 0.5 * (double)N * (double)N);
-        P.pair_cap = (long long)std::min(cap, 2.0e9);
-    }
+    P.pair_cap = P.record_pairs ? pair_record_capacity(P, boxes, box_amax, n_per_box) : 0;
     // the lattice is checked before anything is freed or allocated
     {
         std::vector<BoxParams> trial = boxes;
@@ -1546,7 +1552,6 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     dss_status s = require_loaded(h);
     if (s) return s;
     if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "the adjoint runs on single-box handles");
-    if (h->P.ec) return fail(h, DSS_ERR_STATE, "the adjoint does not take the electro-chemical ranges");
     if (h->P.kr > 0.0) return fail(h, DSS_ERR_STATE, "the adjoint does not take rolling resistance");
     if (h->P.wave_amp != 0.0) return fail(h, DSS_ERR_STATE, "the adjoint does not take the wavy shear");
     if (h->vel_is_half)
@@ -1564,7 +1569,9 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     // pair recording for the tape
     const int rec0 = h->P.record_pairs;
     if (!rec0) {
-        const int64_t cap = 32 * (int64_t)N + 64;
+        std::vector<int64_t> nb(h->boxes.size());
+        for (size_t b = 0; b < h->boxes.size(); ++b) nb[b] = h->boxes[b].n_part;
+        const int64_t cap = pair_record_capacity(h->P, h->boxes, h->box_amax, nb.data());
         if (h->P.pair_cap < cap) {
             if (h->pairs) HIPTRY(hipFree(h->pairs));
             h->pairs = nullptr;

@@ -24,6 +24,10 @@ namespace dss {
 // Constants the pair function reads (eta0 through k6 = 6 pi eta0).
 struct PairConst {
     double k6, kn, kt, gn, mu, fer, a0, lamd, ham, eps_vdw, eps_lub, dt;
+    // electro-chemical ranges (reading R18): lubrication only for |r| < cf (a_i + a_j),
+    // repulsion for h < rep_rng, attraction for h < att_rng; ec = 0 keeps every term on
+    int ec = 0;
+    double cf = 0.0, rep_rng = 0.0, att_rng = 0.0;
 };
 
 // Cotangents of the outputs.  S: 9 weights of the pair's stresslet entries S_ab.
@@ -67,14 +71,20 @@ DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], do
                             int force_contact = -1, int force_capped = -1)
 {
     // ------------------------------------------------------------------ primal
-    const double dist = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double dist = sqrt(r2);
     const double h = dist - ai - aj;
     const double s = ai + aj;
     const double dsr = 2.0 * h / s;
     const bool dpos = dsr > 0.0;
     const double gg = (dpos ? dsr : 0.0) + C.eps_lub;
-    const double invg = 1.0 / gg;
-    const double lg = -log(gg);
+    // the gates are piecewise constant: a term switched off has no value and no gradient
+    const double rl = C.cf * s;
+    const bool lub_on = !C.ec || r2 < rl * rl;
+    const bool rep_on = !C.ec || h < C.rep_rng;
+    const bool att_on = !C.ec || h < C.att_rng;
+    const double invg = lub_on ? 1.0 / gg : 0.0;
+    const double lg = lub_on ? -log(gg) : 0.0;
     const double dux = (uj[0] - gd * yj) - (ui[0] - gd * yi);
     const double duy = uj[1] - ui[1], duz = uj[2] - ui[2];
     const double inv_d = 1.0 / dist;
@@ -112,10 +122,10 @@ DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], do
     const double abar = 2.0 * ai * aj * is;
     const double E = h >= 0.0 ? (C.lamd > 0.0 ? exp(-h / C.lamd) : 0.0) : 1.0;
     double fe = 0.0;
-    if (C.fer != 0.0) fe -= (C.fer / C.a0) * abar * E;
+    if (C.fer != 0.0 && rep_on) fe -= (C.fer / C.a0) * abar * E;
     const double ev = C.eps_vdw * abar;
     const double Q = (h >= 0.0 ? h * h : 0.0) + ev * ev;
-    if (C.ham != 0.0) fe += C.ham * abar / (12.0 * Q);
+    if (C.ham != 0.0 && att_on) fe += C.ham * abar / (12.0 * Q);
     const bool contact = force_contact >= 0 ? force_contact != 0 : h < 0.0;
     double FC[3] = {0.0, 0.0, 0.0}, Ft[3] = {0.0, 0.0, 0.0}, xpp[3] = {0.0, 0.0, 0.0};
     double D[3] = {0.0, 0.0, 0.0}, t[3] = {0.0, 0.0, 0.0}, sv[3] = {0.0, 0.0, 0.0}, xs[3] = {0.0, 0.0, 0.0};
@@ -188,11 +198,11 @@ DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], do
     // FO = FC + fe n
     const double feb = vdot(FOb, n);
     vaxpy(fe, FOb, nb);
-    if (C.fer != 0.0) {
+    if (C.fer != 0.0 && rep_on) {
         g.fer += -(abar / C.a0) * E * feb;
         if (h >= 0.0 && C.lamd > 0.0) hb += (C.fer / C.a0) * abar * E * feb / C.lamd;
     }
-    if (C.ham != 0.0 && h >= 0.0) hb += -C.ham * abar * 2.0 * h / (12.0 * Q * Q) * feb;
+    if (C.ham != 0.0 && att_on && h >= 0.0) hb += -C.ham * abar * 2.0 * h / (12.0 * Q * Q) * feb;
     double Tib[3] = {bar.Ti[0], bar.Ti[1], bar.Ti[2]}, Tjb[3] = {bar.Tj[0], bar.Tj[1], bar.Tj[2]};
     if (contact) {
         // m = n x Ft feeds T_i += a_i m, T_j += a_j m
@@ -317,7 +327,7 @@ DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], do
         // coefficients: X = c invg, Y = c lg, invg = 1 / g, lg = -log g, g = max(2h/s, 0) + eps
         const double invgb = cXA * XAb;
         const double lgb = cYA * YAb + cYBi * YBib + cYBj * YBjb + cYCii * YCiib + cYCij * YCijb + cYCjj * YCjjb;
-        const double ggb = -invg * invg * invgb - lgb / gg;
+        const double ggb = lub_on ? -invg * invg * invgb - lgb / gg : 0.0;
         if (dpos) hb += 2.0 / s * ggb;
     }
     // w' = w + (0, 0, gd / 2)

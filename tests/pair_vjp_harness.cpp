@@ -1,6 +1,7 @@
 // CPU harness for the pair VJP of the HIP library (built by test_pair_vjp_cpu.py with g++).
 // in: gd, r[3], ai, aj, yi, yj, ui[3], uj[3], wi[3], wj[3], xo[3], mu, fer  (25 values)
-// cst: k6, kn, kt, gn, a0, lamd, ham, eps_vdw, eps_lub, dt                   (10 values)
+// cst: k6, kn, kt, gn, a0, lamd, ham, eps_vdw, eps_lub, dt,
+//      ec, cf, rep_rng, att_rng                                              (14 values)
 // bar: Fi, Ti, Tj, xi (12), S (9)                                          (21 values)
 // grad: r[3], yi, yj, ui[3], uj[3], wi[3], wj[3], xo[3], mu, fer            (22 values)
 // val: Fi, Ti, Tj, xi, S, contact, capped                                  (23 values)
@@ -11,6 +12,7 @@ extern "C" void pair_vjp_host(const double *in, const double *cst, const double 
     dss::PairConst C;
     C.k6 = cst[0]; C.kn = cst[1]; C.kt = cst[2]; C.gn = cst[3]; C.a0 = cst[4]; C.lamd = cst[5];
     C.ham = cst[6]; C.eps_vdw = cst[7]; C.eps_lub = cst[8]; C.dt = cst[9];
+    C.ec = cst[10] != 0.0 ? 1 : 0; C.cf = cst[11]; C.rep_rng = cst[12]; C.att_rng = cst[13];
     C.mu = in[23];
     C.fer = in[24];
     dss::PairBar b;

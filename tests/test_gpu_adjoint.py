@@ -115,6 +115,108 @@ def test_adjoint_state_vs_oracle_fd(window, which):
     assert checked == 3
 
 
+def gate_counts(p, x, rad, step):
+    """Listed pairs inside the lubrication range, |r| < c (a_i + a_j), and inside the ranges of
+    repulsion (h < 20 lambda_D) and attraction (h < 4 a0) at time index step (reading R18)."""
+    delta = oracle.le_offset(p, step)
+    pr = oracle.pairs_cells(p, x, rad, delta)
+    a, b = pr[:, 0], pr[:, 1]
+    L = np.asarray(p["L"], np.float64)
+    d = x[b] - x[a]
+    up, dn = d[:, 1] > L[1] / 2, d[:, 1] < -L[1] / 2
+    d[up, 1] -= L[1]
+    d[up, 0] -= delta
+    d[dn, 1] += L[1]
+    d[dn, 0] += delta
+    d[:, 0] -= L[0] * np.rint(d[:, 0] / L[0])
+    d[:, 2] -= L[2] * np.rint(d[:, 2] / L[2])
+    dist = np.sqrt(np.sum(d * d, axis=1))
+    s = rad[a] + rad[b]
+    h = dist - s
+    return (int(np.sum(dist < p["cutoff_factor"] * s)), int(np.sum(h < 20.0 * p["lambda_D"])),
+            int(np.sum(h < 4.0 * p["a0"])))
+
+
+def ec_objective(p, x0, rad, u0, w0, W, K=20, se=5):
+    """The oracle's J of the run, with a branch record that also holds the gate counts of every
+    evaluation: a finite difference that moves a pair across the edge of a range (where its
+    force jumps) leaves the branch."""
+    st, F, T, S = oracle.init_state(p, x0, rad, u0, w0, use_cells=True)
+    samples, br = [], [gate_counts(p, st.x, rad, 0)]
+    for n in range(1, K + 1):
+        st, F, T, S, npairs, _ = oracle.step(p, st, use_cells=True)
+        br.append((npairs, st.history.pairs.tobytes(), gate_counts(p, st.x, rad, n)))
+        if n % se == 0:
+            samples.append(np.asarray(S).reshape(3, 3))
+    return float(np.sum(W * np.mean(samples, axis=0))), br
+
+
+def test_adjoint_ec_ranges_vs_oracle_fd(window):
+    """Electro-chemical forces over their own ranges (reading R18: attraction A = 2e-3 out to
+    4 a0, repulsion to 20 lambda_D, lubrication only inside 1.1 (a_i + a_j)): J, dJ/dF_ER and
+    two directions of dJ/dx0 (40 particles moved each) against central differences of the
+    oracle's objective.  N = 4000 at phi = 0.45, so that the lattice of the longer cutoff still
+    has 4 x 3 x 3 cells; mu = 1 (the sliding contacts are the window's concern).  The
+    forces jump at the edges of the ranges, so the branch record of the finite differences
+    also holds the number of pairs inside each range at every evaluation; at this size a
+    direction can also cross a stick-slip switch of a Coulomb cap, so a difference is kept
+    only when two step sizes agree."""
+    _, _, _, _, W = window
+    w = synth.bidisperse_box(4000, 0.45, seed=23)
+    p = dict(w.params, mu=1.0, ec_ranges=1, hamaker=2e-3)
+    u0 = oracle.ambient_velocity(p, w.x)
+    w0 = oracle.ambient_rotation(p, len(w.rad))
+    say("case: adjoint with the electro-chemical ranges N=4000")
+    r, info, mean, ns = gpu_adjoint(p, w, u0, w0, W)
+    J0, br0 = ec_objective(p, w.x, w.rad, u0, w0, W)
+    assert abs(r["J"] - J0) <= 1e-10 * abs(J0)
+
+    def central(perturb, eps):
+        vals = []
+        for sgn in (1.0, -1.0):
+            pp, x, u, ww = perturb(sgn * eps)
+            J, br = ec_objective(pp, x, w.rad, u, ww, W)
+            if br != br0:
+                return None
+            vals.append(J)
+        return (vals[0] - vals[1]) / (2 * eps)
+
+    def fd_ec(perturb, eps):
+        """Central difference at eps, kept only if the one at eps / 3 agrees: a contact that
+        switches between stick and slip at its Coulomb cap within the step (a kink of J that
+        the branch record does not hold) makes the two differ."""
+        g1 = central(perturb, eps)
+        g2 = central(perturb, eps / 3.0) if g1 is not None else None
+        if g1 is None or g2 is None or abs(g1 - g2) > 2e-6 * abs(g1) + 1e-7:
+            return None
+        return g1
+
+    g = fd_ec(lambda e: (dict(p, F_ER=p["F_ER"] + e), w.x, u0, w0), EPS["F_ER"])
+    assert g is not None, "finite difference left the branch of the run"
+    say(f"d J / d F_ER: adjoint {r['dF_ER']:.10e}  oracle FD {g:.10e}")
+    assert abs(r["dF_ER"] - g) <= 1e-3 * abs(g) + 1e-8
+    rng = np.random.default_rng(11)
+    L = np.array(p["L"])
+    checked = 0
+    for d in range(12):
+        if checked == 2:
+            break
+        # 40 particles moved per direction: few contacts change, so few kinks are met
+        v = np.zeros_like(w.x)
+        moved = rng.choice(len(w.rad), 40, replace=False)
+        v[moved] = rng.normal(size=(40, 3))
+        v[np.any((w.x < 1e-4) | (w.x > L - 1e-4), axis=1)] = 0.0
+        gx = fd_ec(lambda e: (p, w.x + e * v, u0, w0), EPS["x"])
+        if gx is None:
+            say(f"direction {d}: a pair crosses a cutoff, a range edge or a Coulomb cap; skipped")
+            continue
+        ad = float(np.sum(r["dx"] * v))
+        say(f"direction {d}: adjoint {ad:.10e}  oracle FD {gx:.10e}")
+        assert abs(ad - gx) <= 1e-5 * abs(gx) + 1e-6, (d, ad, gx)
+        checked += 1
+    assert checked == 2
+
+
 def test_adjoint_checkpoint_spacing_invariance(window):
     """The gradient does not depend on the checkpoint spacing (1 segment vs segments of 3)."""
     w, p, u0, w0, W = window

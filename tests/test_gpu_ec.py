@@ -78,8 +78,3 @@ def test_ec_ranges_refusals(ec_box):
     with pytest.raises(DssError):
         sim.set_particles(w.x, w.rad)
     sim.close()
-    sim = Simulation(w.params)
-    sim.set_particles(w.x, w.rad)
-    with pytest.raises(DssError):
-        sim.adjoint(4, 2, 2)
-    sim.close()
