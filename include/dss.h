@@ -280,8 +280,10 @@ dss_status dss_get_box_info(dss_handle *h, int32_t box, dss_box_info *info);
  * run, as after dss_step(h, n_steps, stress_every, 1).  Requires a single-box handle whose
  * forces were evaluated at u^n (right after dss_set_particles or dss_compute_forces: else
  * DSS_ERR_STATE) and at least one stress sample in the run (else DSS_ERR_ARG).  Takes the
- * electro-chemical ranges (which pair is inside which range is held fixed); rolling
- * resistance and the wavy shear are refused (DSS_ERR_STATE). */
+ * electro-chemical ranges (which pair is inside which range is held fixed) and rolling
+ * resistance (Appendix roll: the rolling stretch is carried and differentiated like the
+ * tangential one, its Coulomb limit taken as in the run); the wavy shear is refused
+ * (DSS_ERR_STATE). */
 dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress_every, int64_t ckpt_every, const double *weight,
                        double *J, double *dJ_dparams, double *dJ_dx, double *dJ_du, double *dJ_dw, int on_device);
 

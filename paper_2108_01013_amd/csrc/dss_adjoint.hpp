@@ -36,9 +36,9 @@ __device__ __forceinline__ long long canon_find(const int *__restrict__ key, con
 // row of its smaller id; pass 2 sorts every row by partner id.  ccnt must be zero on entry.
 __global__ void __launch_bounds__(kBlock) k_canon_fill(int N, int M, const int *__restrict__ own,
                                                        const int *__restrict__ key, const double *__restrict__ xi,
-                                                       const int *__restrict__ cnt, int *__restrict__ ckey,
-                                                       double *__restrict__ cxi, int *__restrict__ ccnt,
-                                                       DevClock *__restrict__ clk)
+                                                       const double *__restrict__ xr, const int *__restrict__ cnt,
+                                                       int *__restrict__ ckey, double *__restrict__ cxi,
+                                                       int *__restrict__ ccnt, DevClock *__restrict__ clk, int sw)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
@@ -52,10 +52,17 @@ __global__ void __launch_bounds__(kBlock) k_canon_fill(int N, int M, const int *
         if (s < M) {
             ckey[(long long)a * M + s] = b | (kw & kCapBit);
             const double *x = xi + ((long long)p * M + k) * 3;
-            double *y = cxi + ((long long)a * M + s) * 3;
+            double *y = cxi + ((long long)a * M + s) * sw;
             y[0] = x[0];
             y[1] = x[1];
             y[2] = x[2];
+            if (sw == 6) {
+                // the rolling stretch has no orientation: it is stored as it is
+                const double *z = xr + ((long long)p * M + k) * 3;
+                y[3] = z[0];
+                y[4] = z[1];
+                y[5] = z[2];
+            }
         } else {
             atomicOr(&clk->err, kErrRowOverflow);
         }
@@ -63,7 +70,7 @@ __global__ void __launch_bounds__(kBlock) k_canon_fill(int N, int M, const int *
 }
 
 __global__ void __launch_bounds__(kBlock) k_canon_sort(int N, int M, int *__restrict__ ckey, double *__restrict__ cxi,
-                                                       int *__restrict__ ccnt)
+                                                       int *__restrict__ ccnt, int sw)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= N) return;
@@ -71,22 +78,19 @@ __global__ void __launch_bounds__(kBlock) k_canon_sort(int N, int M, int *__rest
     n = n < M ? n : M;
     ccnt[a] = n;
     int *kr = ckey + (long long)a * M;
-    double *xr = cxi + (long long)a * M * 3;
+    double *xr = cxi + (long long)a * M * sw;
     for (int i = 1; i < n; ++i) {
         const int k = kr[i];
-        const double x0 = xr[3 * i], x1 = xr[3 * i + 1], x2 = xr[3 * i + 2];
+        double v[6];
+        for (int c = 0; c < sw; ++c) v[c] = xr[sw * i + c];
         int j = i - 1;
         while (j >= 0 && (kr[j] & kKeyMask) > (k & kKeyMask)) {
             kr[j + 1] = kr[j];
-            xr[3 * (j + 1)] = xr[3 * j];
-            xr[3 * (j + 1) + 1] = xr[3 * j + 1];
-            xr[3 * (j + 1) + 2] = xr[3 * j + 2];
+            for (int c = 0; c < sw; ++c) xr[sw * (j + 1) + c] = xr[sw * j + c];
             --j;
         }
         kr[j + 1] = k;
-        xr[3 * (j + 1)] = x0;
-        xr[3 * (j + 1) + 1] = x1;
-        xr[3 * (j + 1) + 2] = x2;
+        for (int c = 0; c < sw; ++c) xr[sw * (j + 1) + c] = v[c];
     }
 }
 
@@ -95,7 +99,7 @@ __global__ void __launch_bounds__(kBlock) k_canon_sort(int N, int M, int *__rest
 __global__ void __launch_bounds__(kBlock) k_canon_rekey(int N, int M, const int *__restrict__ keyA,
                                                         const int *__restrict__ cntA, const double *__restrict__ gA,
                                                         const int *__restrict__ keyB, const int *__restrict__ cntB,
-                                                        double *__restrict__ gB)
+                                                        double *__restrict__ gB, int sw)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= N) return;
@@ -103,21 +107,19 @@ __global__ void __launch_bounds__(kBlock) k_canon_rekey(int N, int M, const int 
     for (int k = 0; k < n; ++k) {
         const long long q = (long long)a * M + k;
         const long long s = canon_find(keyA, cntA, M, a, keyB[q] & kKeyMask);
-        gB[3 * q] = s >= 0 ? gA[3 * s] : 0.0;
-        gB[3 * q + 1] = s >= 0 ? gA[3 * s + 1] : 0.0;
-        gB[3 * q + 2] = s >= 0 ? gA[3 * s + 2] : 0.0;
+        for (int c = 0; c < sw; ++c) gB[sw * q + c] = s >= 0 ? gA[sw * s + c] : 0.0;
     }
 }
 
 // Clear the stretch adjoints of the contacts in canonical rows (the entries that exist).
 __global__ void __launch_bounds__(kBlock) k_canon_zero(int N, int M, const int *__restrict__ cnt,
-                                                       double *__restrict__ g)
+                                                       double *__restrict__ g, int sw)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= N) return;
     const int n = cnt[a];
-    double *r = g + (long long)a * M * 3;
-    for (int k = 0; k < 3 * n; ++k) r[k] = 0.0;
+    double *r = g + (long long)a * M * sw;
+    for (int k = 0; k < sw * n; ++k) r[k] = 0.0;
 }
 
 __device__ __forceinline__ void atomic_add3(double *p, double a, double b, double c)
@@ -144,6 +146,7 @@ struct VjpTape {
     const int *key_old, *cnt_old;    // canonical rows before the step (null: empty)
     const double *xi_old;
     const int *key_new, *cnt_new;    // canonical rows after the step (null: not committed)
+    int sw;                          // stretch entries per contact: 3, or 6 with the rolling stretch
 };
 
 __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, long long step, int npairs,
@@ -162,15 +165,16 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
         const double *xa = tp.x + 3LL * a, *xb = tp.x + 3LL * b;
         double r[3];
         min_image(G, delta, xa[0], xa[1], xa[2], xb[0], xb[1], xb[2], r[0], r[1], r[2]);
-        double xo[3] = {0.0, 0.0, 0.0};
+        const int sw = tp.sw;
+        double xo[3] = {0.0, 0.0, 0.0}, xro[3] = {0.0, 0.0, 0.0};
         long long pold = -1;
         if (tp.key_old) {
             pold = canon_find(tp.key_old, tp.cnt_old, P.M, a, b);
-            if (pold >= 0) {
-                xo[0] = tp.xi_old[3 * pold];
-                xo[1] = tp.xi_old[3 * pold + 1];
-                xo[2] = tp.xi_old[3 * pold + 2];
-            }
+            if (pold >= 0)
+                for (int c = 0; c < 3; ++c) {
+                    xo[c] = tp.xi_old[sw * pold + c];
+                    if (sw == 6) xro[c] = tp.xi_old[sw * pold + 3 + c];
+                }
         }
         PairBar bar;
         for (int c = 0; c < 3; ++c) {
@@ -178,6 +182,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
             bar.Ti[c] = Tb[3LL * a + c];
             bar.Tj[c] = Tb[3LL * b + c];
             bar.xi[c] = 0.0;
+            bar.xr[c] = 0.0;
         }
         // branch of the forward run: a pair is a contact after the step iff its rows hold it,
         // and the rows record whether its Coulomb cap was active (at the initial evaluation,
@@ -188,16 +193,20 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
             f_contact = pn >= 0 ? 1 : 0;
             f_capped = pn >= 0 ? ((tp.key_new[pn] & kCapBit) ? 1 : 0) : 0;
             if (pn >= 0 && xib_new)
-                for (int c = 0; c < 3; ++c) bar.xi[c] = xib_new[3 * pn + c];
+                for (int c = 0; c < 3; ++c) {
+                    bar.xi[c] = xib_new[sw * pn + c];
+                    if (sw == 6) bar.xr[c] = xib_new[sw * pn + 3 + c];
+                }
         }
         for (int c = 0; c < 9; ++c) bar.S[c] = Sb ? Sb[c] : 0.0;
         PairConst C;
         C.k6 = P.k6; C.kn = P.kn; C.kt = P.kt; C.gn = P.gn; C.mu = P.mu; C.fer = P.fer; C.a0 = P.a0;
         C.lamd = P.lamd; C.ham = P.ham; C.eps_vdw = P.eps_vdw; C.eps_lub = P.eps_lub; C.dt = P.dt;
         C.ec = P.ec; C.cf = P.cf; C.rep_rng = P.rep_rng; C.att_rng = P.att_rng;
+        C.roll = sw == 6 ? 1 : 0; C.kr = P.kr; C.mu_r = P.mu_r;
         PairGrad g = {};
         pair_vjp(C, G.gd, r, tp.rad[a], tp.rad[b], xa[1], xb[1], tp.u + 3LL * a, tp.u + 3LL * b, tp.w + 3LL * a,
-                 tp.w + 3LL * b, xo, bar, g, nullptr, f_contact, f_capped);
+                 tp.w + 3LL * b, xo, bar, g, nullptr, f_contact, f_capped, xro);
         atomic_add3(ax + 3LL * a, -g.r[0], -g.r[1] + g.yi, -g.r[2]);
         atomic_add3(ax + 3LL * b, g.r[0], g.r[1] + g.yj, g.r[2]);
         atomic_add3(au + 3LL * a, g.ui[0], g.ui[1], g.ui[2]);
@@ -205,7 +214,10 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
         atomic_add3(aw + 3LL * a, g.wi[0], g.wi[1], g.wi[2]);
         atomic_add3(aw + 3LL * b, g.wj[0], g.wj[1], g.wj[2]);
         if (pold >= 0 && xib_old)
-            for (int c = 0; c < 3; ++c) xib_old[3 * pold + c] = g.xo[c];
+            for (int c = 0; c < 3; ++c) {
+                xib_old[sw * pold + c] = g.xo[c];
+                if (sw == 6) xib_old[sw * pold + 3 + c] = g.xro[c];
+            }
         gmu = g.mu;
         gfer = g.fer;
     }

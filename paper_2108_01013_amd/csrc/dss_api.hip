@@ -1365,6 +1365,7 @@ struct Snapshot {
     int *cs = nullptr;      // cell_start, n_cells + 1
     int *hkey = nullptr, *hcnt = nullptr, *hown = nullptr;
     double *hxi = nullptr;
+    double *hxr = nullptr;  // rolling stretches (only with rolling resistance)
     DevClock *clk = nullptr;
     double *sig = nullptr;  // sigma_last (9) and box_diag (3) of box 0
     int *img = nullptr;     // y-face crossing counts
@@ -1373,7 +1374,7 @@ struct Snapshot {
     bool vel_is_half = false;
     void release()
     {
-        void *ps[] = {pa, vel, omg, ft, cs, hkey, hcnt, hown, hxi, clk, sig, img};
+        void *ps[] = {pa, vel, omg, ft, cs, hkey, hcnt, hown, hxi, hxr, clk, sig, img};
         for (void *q : ps)
             if (q) (void)hipFree(q);
         *this = Snapshot{};
@@ -1391,6 +1392,7 @@ dss_status snap_save(dss_handle *h, Snapshot &s)
         HIPTRY(dalloc(&s.cs, (size_t)h->ncell_total + 1));
         HIPTRY(dalloc(&s.hkey, N * M));
         HIPTRY(dalloc(&s.hxi, 3 * N * M));
+        if (h->hxr[h->hh]) HIPTRY(dalloc(&s.hxr, 3 * N * M));
         HIPTRY(dalloc(&s.hcnt, N));
         HIPTRY(dalloc(&s.hown, N));
         HIPTRY(dalloc(&s.clk, 1));
@@ -1408,6 +1410,7 @@ dss_status snap_save(dss_handle *h, Snapshot &s)
     HIPTRY(hipMemcpyAsync(s.cs, h->cell_start, ((size_t)h->ncell_total + 1) * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(s.hkey, h->hkey[h->hh], N * M * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(s.hxi, h->hxi[h->hh], 3 * N * M * sizeof(double), D, st));
+    if (s.hxr) HIPTRY(hipMemcpyAsync(s.hxr, h->hxr[h->hh], 3 * N * M * sizeof(double), D, st));
     HIPTRY(hipMemcpyAsync(s.hcnt, h->hcnt[h->hh], N * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(s.hown, h->hown[h->hh], N * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(s.clk, h->clk, sizeof(DevClock), D, st));
@@ -1435,6 +1438,7 @@ dss_status snap_restore(dss_handle *h, const Snapshot &s)
     HIPTRY(hipMemcpyAsync(h->cell_start, s.cs, ((size_t)h->ncell_total + 1) * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(h->hkey[s.hh], s.hkey, N * M * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(h->hxi[s.hh], s.hxi, 3 * N * M * sizeof(double), D, st));
+    if (s.hxr) HIPTRY(hipMemcpyAsync(h->hxr[s.hh], s.hxr, 3 * N * M * sizeof(double), D, st));
     HIPTRY(hipMemcpyAsync(h->hcnt[s.hh], s.hcnt, N * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(h->hown[s.hh], s.hown, N * sizeof(int), D, st));
     HIPTRY(hipMemcpyAsync(h->clk, s.clk, sizeof(DevClock), D, st));
@@ -1448,13 +1452,17 @@ dss_status snap_restore(dss_handle *h, const Snapshot &s)
     return DSS_OK;
 }
 
+// Stretch entries per contact in the canonical rows: the tangential stretch, and the rolling
+// stretch after it when rolling resistance is on.
+int stretch_width(const dss_handle *h) { return h->P.kr > 0.0 ? 6 : 3; }
+
 // One recorded evaluation: state by id, listed pairs, committed history in canonical rows.
 struct TapeEntry {
     double *x = nullptr, *u = nullptr, *w = nullptr;
     int *pairs = nullptr;
     int64_t npairs = 0;
     int *ckey = nullptr, *ccnt = nullptr;
-    double *cxi = nullptr;
+    double *cxi = nullptr;  // per contact: xi, then xi^r with rolling resistance
     void release()
     {
         void *ps[] = {x, u, w, pairs, ckey, ccnt, cxi};
@@ -1473,7 +1481,7 @@ dss_status tape_alloc(dss_handle *h, TapeEntry &t)
     HIPTRY(dalloc(&t.pairs, 2 * h->P.pair_cap));
     HIPTRY(dalloc(&t.ckey, N * M));
     HIPTRY(dalloc(&t.ccnt, N));
-    HIPTRY(dalloc(&t.cxi, 3 * N * M));
+    HIPTRY(dalloc(&t.cxi, stretch_width(h) * N * M));
     return DSS_OK;
 }
 
@@ -1483,9 +1491,10 @@ dss_status tape_rows(dss_handle *h, TapeEntry &t)
     const int N = (int)h->N, M = h->P.M;
     const int grid = (N + kBlock - 1) / kBlock;
     HIPTRY(hipMemsetAsync(t.ccnt, 0, N * sizeof(int), h->stream));
+    const int sw = stretch_width(h);
     hipLaunchKernelGGL(k_canon_fill, dim3(grid), dim3(kBlock), 0, h->stream, N, M, h->hown[h->hh], h->hkey[h->hh],
-                       h->hxi[h->hh], h->hcnt[h->hh], t.ckey, t.cxi, t.ccnt, h->clk);
-    hipLaunchKernelGGL(k_canon_sort, dim3(grid), dim3(kBlock), 0, h->stream, N, M, t.ckey, t.cxi, t.ccnt);
+                       h->hxi[h->hh], h->hxr[h->hh], h->hcnt[h->hh], t.ckey, t.cxi, t.ccnt, h->clk, sw);
+    hipLaunchKernelGGL(k_canon_sort, dim3(grid), dim3(kBlock), 0, h->stream, N, M, t.ckey, t.cxi, t.ccnt, sw);
     HIPTRY(hipGetLastError());
     return DSS_OK;
 }
@@ -1552,7 +1561,6 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     dss_status s = require_loaded(h);
     if (s) return s;
     if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "the adjoint runs on single-box handles");
-    if (h->P.kr > 0.0) return fail(h, DSS_ERR_STATE, "the adjoint does not take rolling resistance");
     if (h->P.wave_amp != 0.0) return fail(h, DSS_ERR_STATE, "the adjoint does not take the wavy shear");
     if (h->vel_is_half)
         return fail(h, DSS_ERR_STATE, "the adjoint starts from a state with forces at u^n: call it right after "
@@ -1627,12 +1635,13 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     HIPTRY(W.get(&ax, n3)); HIPTRY(W.get(&au, n3)); HIPTRY(W.get(&aw, n3));
     HIPTRY(W.get(&Fb, n3)); HIPTRY(W.get(&Tb, n3)); HIPTRY(W.get(&Fb2, n3)); HIPTRY(W.get(&Tb2, n3));
     HIPTRY(W.get(&theta, 2)); HIPTRY(W.get(&rad, N)); HIPTRY(W.get(&Sb, 9));
-    HIPTRY(W.get(&xibA, 3 * (size_t)N * M)); HIPTRY(W.get(&xibB, 3 * (size_t)N * M));
+    const int sw = stretch_width(h);
+    HIPTRY(W.get(&xibA, sw * (size_t)N * M)); HIPTRY(W.get(&xibB, sw * (size_t)N * M));
     HIPTRY(W.get(&bkey, (size_t)N * M)); HIPTRY(W.get(&bcnt, N));
     double *zero_list[] = {xb, ub, wb, ax, au, aw, Fb, Tb, Fb2, Tb2};
     for (double *q : zero_list) HIPTRY(hipMemsetAsync(q, 0, n3 * sizeof(double), h->stream));
     HIPTRY(hipMemsetAsync(theta, 0, 2 * sizeof(double), h->stream));
-    HIPTRY(hipMemsetAsync(xibA, 0, 3 * (size_t)N * M * sizeof(double), h->stream));
+    HIPTRY(hipMemsetAsync(xibA, 0, sw * (size_t)N * M * sizeof(double), h->stream));
     HIPTRY(hipMemsetAsync(bcnt, 0, N * sizeof(int), h->stream));
     {
         const double V = h->prm.L[0] * h->prm.L[1] * h->prm.L[2];
@@ -1679,14 +1688,14 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         if (seg < nck - 1) {
             // stretch adjoints at the segment boundary: rows of the later segment -> this one
             hipLaunchKernelGGL(k_canon_rekey, dim3(grid), dim3(kBlock), 0, h->stream, N, M, bkey, bcnt, xib_in,
-                               W.tape[len].ckey, W.tape[len].ccnt, xib_out);
+                               W.tape[len].ckey, W.tape[len].ccnt, xib_out, sw);
             std::swap(xib_in, xib_out);
         }
         for (int64_t k = len; k >= 1; --k) {
             const int64_t n = s0 + k;
             const TapeEntry &T1 = W.tape[k], &T0 = W.tape[k - 1];
-            hipLaunchKernelGGL(k_canon_zero, dim3(grid), dim3(kBlock), 0, h->stream, N, M, T0.ccnt, xib_out);
-            VjpTape tp{T1.pairs, T1.x, T1.u, T1.w, rad, T0.ckey, T0.ccnt, T0.cxi, T1.ckey, T1.ccnt};
+            hipLaunchKernelGGL(k_canon_zero, dim3(grid), dim3(kBlock), 0, h->stream, N, M, T0.ccnt, xib_out, sw);
+            VjpTape tp{T1.pairs, T1.x, T1.u, T1.w, rad, T0.ckey, T0.ccnt, T0.cxi, T1.ckey, T1.ccnt, sw};
             const bool sampled = n >= first && (n - first) % stress_every == 0;
             const int pgrid = (int)std::max<int64_t>(1, (T1.npairs + kBlock - 1) / kBlock);
             {
@@ -1714,7 +1723,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     {
         // the evaluation at the initial state; the stretch of the initial history is held fixed
         const TapeEntry &T0 = W.tape[0];
-        VjpTape tp{T0.pairs, T0.x, T0.u, T0.w, rad, T0.ckey, T0.ccnt, T0.cxi, nullptr, nullptr};
+        VjpTape tp{T0.pairs, T0.x, T0.u, T0.w, rad, T0.ckey, T0.ccnt, T0.cxi, nullptr, nullptr, sw};
         const int pgrid = (int)std::max<int64_t>(1, (T0.npairs + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_pairs_vjp, dim3(pgrid), dim3(kBlock), 0, h->stream, Prec, G, (long long)n0,
                            (int)T0.npairs, tp, (const double *)nullptr, (double *)nullptr, Fb, Tb,

@@ -28,22 +28,30 @@ struct PairConst {
     // repulsion for h < rep_rng, attraction for h < att_rng; ec = 0 keeps every term on
     int ec = 0;
     double cf = 0.0, rep_rng = 0.0, att_rng = 0.0;
+    // rolling resistance (reading R19): a spring k_r on u_r = abar n x (w_i - w_j) with the
+    // Coulomb limit mu_r |F_nor| / k_r, torques T_i = abar n x k_r xi^r = -T_j; roll = 0: none
+    int roll = 0;
+    double kr = 0.0, mu_r = 0.0;
 };
 
 // Cotangents of the outputs.  S: 9 weights of the pair's stresslet entries S_ab.
 struct PairBar {
     double Fi[3], Ti[3], Tj[3], xi[3], S[9];
+    double xr[3] = {0.0, 0.0, 0.0};   // of the new rolling stretch
 };
 
 // Gradients with respect to the inputs.
 struct PairGrad {
     double r[3], yi, yj, ui[3], uj[3], wi[3], wj[3], xo[3], mu, fer;
+    double xro[3];                    // of the stored rolling stretch
 };
 
 // Primal outputs (for checks against the forward).
 struct PairVal {
     double Fi[3], Ti[3], Tj[3], xi[3], S[9];
     bool contact, capped;
+    double xr[3];
+    bool rcapped;                     // the rolling stretch was limited
 };
 
 DSS_HD inline double vdot(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -68,7 +76,7 @@ DSS_HD inline void vaxpy(double s, const double a[3], double out[3])
 DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], double ai, double aj, double yi,
                             double yj, const double ui[3], const double uj[3], const double Wi[3], const double Wj[3],
                             const double xo[3], const PairBar &bar, PairGrad &g, PairVal *val,
-                            int force_contact = -1, int force_capped = -1)
+                            int force_contact = -1, int force_capped = -1, const double *xro = nullptr)
 {
     // ------------------------------------------------------------------ primal
     const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -132,6 +140,12 @@ DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], do
     double xp[3] = {0.0, 0.0, 0.0};
     double fn = 0.0, tn = 0.0, xsn = 0.0, cap = 0.0, xm = 0.0, sc = 1.0;
     bool capped = false;
+    // rolling spring: angular velocity difference, u_r / abar, unprojected and projected
+    // stretch, capped stretch, its spring force and n x force
+    double dwr[3] = {0.0, 0.0, 0.0}, urr[3] = {0.0, 0.0, 0.0}, qrr[3] = {0.0, 0.0, 0.0}, prr[3] = {0.0, 0.0, 0.0};
+    double xrr[3] = {0.0, 0.0, 0.0}, frr[3] = {0.0, 0.0, 0.0}, qtr[3] = {0.0, 0.0, 0.0};
+    double qrn = 0.0, capr = 0.0, prm = 0.0, rsc = 1.0;
+    bool rcapped = false;
     if (contact) {
         D[0] = dux + gd * r[1];
         D[1] = duy;
@@ -163,6 +177,27 @@ DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], do
             Ti[k] += ai * m[k];
             Tj[k] += aj * m[k];
         }
+        if (C.roll) {
+            // xi^r' = P_n(xi^r_old + u_r dt), capped at mu_r |fn| / k_r; T_i += abar n x k_r xi^r'
+            for (int k = 0; k < 3; ++k) dwr[k] = Wi[k] - Wj[k];
+            vcross(n, dwr, urr);
+            for (int k = 0; k < 3; ++k) qrr[k] = (xro ? xro[k] : 0.0) + abar * urr[k] * C.dt;
+            qrn = vdot(qrr, n);
+            for (int k = 0; k < 3; ++k) prr[k] = qrr[k] - qrn * n[k];
+            capr = C.mu_r * fabs(fn) / C.kr;
+            prm = sqrt(vdot(prr, prr));
+            rcapped = prm >= capr && prm > 0.0;
+            rsc = rcapped ? capr / prm : 1.0;
+            for (int k = 0; k < 3; ++k) {
+                xrr[k] = rsc * prr[k];
+                frr[k] = C.kr * xrr[k];
+            }
+            vcross(n, frr, qtr);
+            for (int k = 0; k < 3; ++k) {
+                Ti[k] += abar * qtr[k];
+                Tj[k] -= abar * qtr[k];
+            }
+        }
     }
     double FO[3];
     for (int k = 0; k < 3; ++k) FO[k] = FC[k] + fe * n[k];
@@ -172,6 +207,8 @@ DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], do
             val->Ti[k] = Ti[k];
             val->Tj[k] = Tj[k];
             val->xi[k] = xpp[k];
+            val->xr[k] = xrr[k];
+            val->rcapped = rcapped;
         }
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) val->S[3 * a + b] = 0.5 * (r[a] * FL[b] + r[b] * FL[a]) + r[a] * FO[b];
@@ -216,6 +253,43 @@ DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], do
         for (int k = 0; k < 3; ++k) Ftb[k] += FOb[k];
         double fnb = vdot(FOb, n);
         vaxpy(fn, FOb, nb);
+        if (C.roll) {
+            // T_i += abar qt, T_j -= abar qt, qt = n x fr, fr = k_r xr
+            double qtb[3], frb[3], xrb[3], prb[3], qb2[3], urb[3], dwb[3], t2[3];
+            for (int k = 0; k < 3; ++k) qtb[k] = abar * (Tib[k] - Tjb[k]);
+            vcross(frr, qtb, t2);
+            vaxpy(1.0, t2, nb);
+            vcross(qtb, n, frb);
+            for (int k = 0; k < 3; ++k) xrb[k] = C.kr * frb[k] + bar.xr[k];
+            // xr = rsc p, rsc = capr / |p| when capped, capr = mu_r |fn| / k_r
+            if (rcapped) {
+                const double sb = vdot(xrb, prr);
+                const double caprb = sb / prm;
+                const double prmb = -sb * capr / (prm * prm);
+                for (int k = 0; k < 3; ++k) prb[k] = rsc * xrb[k] + prmb * prr[k] / prm;
+                fnb += (fn > 0.0 ? 1.0 : (fn < 0.0 ? -1.0 : 0.0)) * C.mu_r / C.kr * caprb;
+            } else {
+                for (int k = 0; k < 3; ++k) prb[k] = xrb[k];
+            }
+            // p = q - (q.n) n
+            const double pbn = vdot(prb, n);
+            for (int k = 0; k < 3; ++k) {
+                qb2[k] = prb[k] - pbn * n[k];
+                nb[k] += -pbn * qrr[k] - qrn * prb[k];
+            }
+            // q = xro + abar (n x dw) dt
+            for (int k = 0; k < 3; ++k) {
+                g.xro[k] += qb2[k];
+                urb[k] = abar * C.dt * qb2[k];
+            }
+            vcross(dwr, urb, t2);
+            vaxpy(1.0, t2, nb);
+            vcross(urb, n, dwb);
+            for (int k = 0; k < 3; ++k) {
+                g.wi[k] += dwb[k];
+                g.wj[k] -= dwb[k];
+            }
+        }
         double xpb[3] = {0.0, 0.0, 0.0};
         if (C.kt > 0.0) {
             double xppb[3];

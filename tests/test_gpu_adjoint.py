@@ -217,6 +217,70 @@ def test_adjoint_ec_ranges_vs_oracle_fd(window):
     assert checked == 2
 
 
+def test_adjoint_rolling_resistance_vs_oracle_fd(window):
+    """Rolling resistance (reading R19: k_r = 0.5 k_n, mu_r = 0.1) on the N = 400 window: J,
+    dJ/dmu and two directions each of dJ/dx0 and dJ/dw0 against central differences of the
+    oracle's objective.  The rolling stretch is carried from step to step like the tangential
+    one, so its adjoint crosses every step and every checkpoint segment; on this window rolling
+    moves dJ/dw0 by about 2 %, far above the tolerance.  A rolling spring
+    can reach its Coulomb limit within a finite difference (a kink that the branch record does
+    not hold), so a difference is kept only when two step sizes agree."""
+    w, p0, u0, w0, W = window
+    p = dict(p0, kr=0.5 * p0["kn"], mu_r=0.1)
+    say("case: adjoint with rolling resistance N=400")
+    r, info, mean, ns = gpu_adjoint(p, w, u0, w0, W)
+    J0, br0 = oracle.stress_objective(p, w.x, w.rad, u0, w0, 20, 5, W)
+    Jn, _ = oracle.stress_objective(p0, w.x, w.rad, u0, w0, 20, 5, W)
+    assert abs(r["J"] - J0) <= 1e-10 * abs(J0)
+    assert abs(J0 - Jn) > 1e-6 * abs(Jn)     # the rolling torques change the run
+
+    def central(perturb, eps):
+        vals = []
+        for sgn in (1.0, -1.0):
+            pp, x, u, ww = perturb(sgn * eps)
+            J, br = oracle.stress_objective(pp, x, w.rad, u, ww, 20, 5, W)
+            if br != br0:
+                return None
+            vals.append(J)
+        return (vals[0] - vals[1]) / (2 * eps)
+
+    def fd_two(perturb, eps):
+        g1 = central(perturb, eps)
+        g2 = central(perturb, eps / 3.0) if g1 is not None else None
+        if g1 is None or g2 is None or abs(g1 - g2) > 2e-6 * abs(g1) + 1e-7:
+            return None
+        return g1
+
+    g = fd_two(lambda e: (dict(p, mu=p["mu"] + e), w.x, u0, w0), EPS["mu"])
+    assert g is not None, "finite difference left the branch of the run"
+    say(f"d J / d mu: adjoint {r['dmu']:.10e}  oracle FD {g:.10e}")
+    assert abs(r["dmu"] - g) <= 1e-5 * abs(g) + 1e-8
+    L = np.array(p["L"])
+    for which, seed in (("x", 31), ("w", 32)):
+        rng = np.random.default_rng(seed)
+        checked = 0
+        for d in range(10):
+            if checked == 2:
+                break
+            v = rng.normal(size=w.x.shape)
+            if which == "x":
+                v[np.any((w.x < 1e-4) | (w.x > L - 1e-4), axis=1)] = 0.0
+                pert = lambda e: (p, w.x + e * v, u0, w0)  # noqa: E731
+            else:
+                pert = lambda e: (p, w.x, u0, w0 + e * v)  # noqa: E731
+            # dJ/dw0 along a direction is ~1e-2 against J ~ 12: a step of 1e-5 keeps the rounding
+            # noise of J below the two-step agreement
+            gv = fd_two(pert, EPS[which] if which == "x" else 1e-5)
+            if gv is None:
+                say(f"d{which} direction {d}: a pair crosses a cutoff or a Coulomb limit; skipped")
+                continue
+            ad = float(np.sum(r["d" + which] * v))
+            say(f"d{which} direction {d}: adjoint {ad:.10e}  oracle FD {gv:.10e}")
+            assert abs(ad - gv) <= 1e-5 * abs(gv) + 1e-6, (which, d, ad, gv)
+            checked += 1
+        assert checked == 2, which
+
+
 def test_adjoint_checkpoint_spacing_invariance(window):
     """The gradient does not depend on the checkpoint spacing (1 segment vs segments of 3)."""
     w, p, u0, w0, W = window

@@ -109,8 +109,6 @@ def test_rolling_snapshot_and_refusals():
     ha, hb = a.history(rolling=True), b.history(rolling=True)
     assert np.array_equal(ha[0], hb[0]) and len(ha[0]) > 0
     assert rel_inf(hb[1], ha[1]) < 1e-9
-    with pytest.raises(DssError):
-        a.adjoint(4, 2, 2)
     c = Simulation(w.params)
     c.set_particles(w.x, w.rad)
     with pytest.raises(DssError):

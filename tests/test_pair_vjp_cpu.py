@@ -27,25 +27,28 @@ def lib(tmp_path_factory):
 
 
 def call(L, x, cst, bar):
-    grad = np.zeros(22)
-    val = np.zeros(23)
+    grad = np.zeros(25)
+    val = np.zeros(27)
     ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
     x = np.ascontiguousarray(x, np.float64)
     L.pair_vjp_host(ptr(x), ptr(cst), ptr(bar), ptr(grad), ptr(val))
     return grad, val
 
 
-# differentiable inputs inside the 25-value input vector (gd, a_i, a_j are constants)
-DIFF = [1, 2, 3, 6, 7] + list(range(8, 23)) + [23, 24]
+# differentiable inputs inside the 28-value input vector (gd, a_i, a_j are constants)
+DIFF = [1, 2, 3, 6, 7] + list(range(8, 23)) + [23, 24, 25, 26, 27]
+# outputs paired with the 24 cotangents: F_i, T_i, T_j, xi, S (val[0:21]) and xr (val[23:26])
+OUT = list(range(21)) + [23, 24, 25]
 
 
 def make_case(kind, rng, balanced=False):
     ai, aj = 1.0, 1.4
     n = rng.normal(size=3)
     n /= np.linalg.norm(n)
-    gap = {"lub": 0.08, "attr": 0.05, "stick": -2e-3, "slip": -2e-3, "ec_far": 0.6, "ec_rep_off": 1.5}[kind]
+    gap = {"lub": 0.08, "attr": 0.05, "stick": -2e-3, "slip": -2e-3, "ec_far": 0.6, "ec_rep_off": 1.5,
+           "roll_stick": -2e-3, "roll_slip": -2e-3}[kind]
     r = (ai + aj + gap) * n
-    x = np.zeros(25)
+    x = np.zeros(28)
     x[0] = 0.7                       # shear rate
     x[1:4] = r
     x[4], x[5] = ai, aj
@@ -55,14 +58,21 @@ def make_case(kind, rng, balanced=False):
     x[20:23] = xi_dir / np.linalg.norm(xi_dir) * (1e-6 if kind == "stick" else 5e-3)
     x[23] = 0.5 if kind == "slip" else 1e3     # mu
     x[24] = 1.3                                 # F_ER
+    roll = kind.startswith("roll")
+    if roll:
+        # a stored rolling stretch tangent to n: small (stick) or beyond the rolling cap (slip)
+        xr_dir = np.cross(n, rng.normal(size=3))
+        x[25:28] = xr_dir / np.linalg.norm(xr_dir) * (1e-6 if kind == "roll_stick" else 5e-2)
     ec = kind.startswith("ec")
     ham = 0.2 if kind == "attr" or ec else 0.0
     # electro-chemical ranges: repulsion below 1.0, attraction below 4.0 (surface distance)
     ranges = [1.0, 1.1, 1.0, 4.0] if ec else [0.0, 1.1, 0.0, 0.0]
-    cst = np.array([6 * np.pi, 4e5, 4e5 * 2 / 7, 0.04, 1.0, 0.05, ham, 0.01, 0.02, 1e-4] + ranges)
+    rolling = [1.0, 0.05 * 4e5, 0.1] if roll else [0.0, 0.0, 0.0]
+    cst = np.array([6 * np.pi, 4e5, 4e5 * 2 / 7, 0.04, 1.0, 0.05, ham, 0.01, 0.02, 1e-4] + ranges + rolling)
     if balanced:
         # constants that make every term of the same order, so that no term hides in the tolerance
-        cst = np.array([0.5, 50.0, 20.0, 5.0, 1.0, 0.3, ham, 0.01, 0.02, 0.05] + ranges)
+        rolling = [1.0, 10.0, 10.0 if kind == "roll_stick" else 0.05] if roll else [0.0, 0.0, 0.0]
+        cst = np.array([0.5, 50.0, 20.0, 5.0, 1.0, 0.3, ham, 0.01, 0.02, 0.05] + ranges + rolling)
         if kind == "slip":
             x[23] = 0.05
         if kind == "stick":
@@ -71,32 +81,35 @@ def make_case(kind, rng, balanced=False):
 
 
 @pytest.mark.parametrize("balanced", [False, True])
-@pytest.mark.parametrize("kind", ["lub", "attr", "stick", "slip", "ec_far", "ec_rep_off"])
+@pytest.mark.parametrize("kind", ["lub", "attr", "stick", "slip", "ec_far", "ec_rep_off", "roll_stick",
+                                  "roll_slip"])
 def test_pair_vjp_matches_finite_differences(lib, kind, balanced):
-    rng = np.random.default_rng({"lub": 1, "attr": 2, "stick": 3, "slip": 4, "ec_far": 5, "ec_rep_off": 6}[kind])
+    rng = np.random.default_rng({"lub": 1, "attr": 2, "stick": 3, "slip": 4, "ec_far": 5, "ec_rep_off": 6,
+                                 "roll_stick": 7, "roll_slip": 8}[kind])
     x, cst = make_case(kind, rng, balanced)
-    bar = rng.normal(size=21)
+    bar = rng.normal(size=24)
     g, val = call(lib, x, cst, bar)
-    assert val[21] == (1.0 if kind in ("stick", "slip") else 0.0)
+    assert val[21] == (1.0 if kind in ("stick", "slip") or kind.startswith("roll") else 0.0)
     assert val[22] == (1.0 if kind == "slip" else 0.0)   # the intended branch of the Coulomb cap
+    assert val[26] == (1.0 if kind == "roll_slip" else 0.0)   # and of the rolling cap
     if kind.startswith("ec"):
         # beyond the lubrication range only central forces: no torques, F along r
         assert np.all(val[3:9] == 0.0)
         assert np.linalg.norm(np.cross(val[0:3], x[1:4])) <= 1e-14 * np.linalg.norm(val[0:3]) * np.linalg.norm(x[1:4])
     if kind == "ec_rep_off":
         assert g[21] == 0.0                                  # beyond the repulsion range: no F_ER
-    fd = np.zeros(22)
+    fd = np.zeros(25)
     for k, idx in enumerate(DIFF):
         eps = 1e-6 * max(1.0, abs(x[idx]))
-        if idx in (20, 21, 22):
+        if idx in (20, 21, 22, 25, 26, 27):
             eps = 1e-9
         xp, xm = x.copy(), x.copy()
         xp[idx] += eps
         xm[idx] -= eps
         _, vp = call(lib, xp, cst, bar)
         _, vm = call(lib, xm, cst, bar)
-        assert vp[21] == vm[21] == val[21] and vp[22] == vm[22] == val[22]
-        fd[k] = np.dot(bar, (vp[:21] - vm[:21]) / (2 * eps))
+        assert vp[21] == vm[21] == val[21] and vp[22] == vm[22] == val[22] and vp[26] == vm[26] == val[26]
+        fd[k] = np.dot(bar, (vp[OUT] - vm[OUT]) / (2 * eps))
     scale = np.max(np.abs(fd))
     err = np.max(np.abs(g - fd)) / scale
     assert err < 1e-6, (kind, err, np.argmax(np.abs(g - fd)))
@@ -107,7 +120,7 @@ def test_pair_vjp_action_reaction_and_translation(lib):
     ambient flow) leaves the pair unchanged: the gradients of those directions vanish."""
     rng = np.random.default_rng(7)
     x, cst = make_case("stick", rng)
-    bar = rng.normal(size=21)
+    bar = rng.normal(size=24)
     g, _ = call(lib, x, cst, bar)
     # d/dy of a common y shift of both particles, with the ambient velocity following it
     gd = x[0]
