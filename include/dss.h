@@ -60,8 +60,9 @@ typedef enum { DSS_FP64 = 0, DSS_MIXED = 1 } dss_precision;
  * surface distance d_ij < 20 lambda_D, attraction, eq. att, while d_ij < 4 a0; lubrication
  * stays on |r| < cutoff_factor (a_i + a_j).  The pair set (and the cell lattice) then covers
  * |r| < max(cutoff_factor (a_i + a_j), a_i + a_j + the longest active range).  Without the
- * flag both forces are truncated at the lubrication list.  Not with size-class stencils
- * (DSS_ERR_ARG).  With the adjoint the three ranges are held fixed like the pair set. */
+ * flag both forces are truncated at the lubrication list.  With size-class stencils a
+ * particle's reach becomes 2 max(cutoff_factor, 1) a + the longest range.  With the adjoint
+ * the three ranges are held fixed like the pair set. */
 #define DSS_FLAG_EC_RANGES 2
 
 /* Physical and numerical parameters (units are the caller's; the defaults used by the
@@ -161,7 +162,7 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
  * stress do not depend on them (the summation order of the force atomics aside).
  *   cell_scale: lattice spacing = cell_scale x the box's largest pair cutoff (>= 1, <= 4;
  *               1 = the smallest legal cells); larger cells mean fewer, fuller cell rows;
- *               with size-class stencils, cell_scale x the smallest pair cutoff 2 c a_min;
+ *               with size-class stencils, cell_scale x the reach of the smallest particle;
  *   tile_scale: scale (0.25 .. 4) of the k_pairs row-tile capacities, which are sized from
  *               the mean occupancy of a cell row; rows beyond them take the per-particle path;
  *   tiled:      1 = stage cell rows in LDS; 0 = every row takes the per-particle path;
@@ -169,8 +170,9 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
  *               not while kernel timing is on or pairs are recorded);
  *   sized:      1 = size-class stencils for boxes of high size ratio (Section 2.2: cells
  *               fitted to the smallest particles, the stencil widened for larger ones): a
- *               particle of radius a searches a stencil of radius R(a) = floor(2 c a / cw) + 1
- *               cells, each pair is found by its larger member, the sort is class-major
+ *               particle of radius a searches a stencil of radius R(a) = floor(reach(a) / cw)
+ *               + 1 cells, reach(a) = 2 c a (with DSS_FLAG_EC_RANGES 2 max(c, 1) a + the
+ *               longest range), each pair is found by its larger member, the sort is class-major
  *               (dss_get_cells returns size_classes x n_cells + 1 starts); one box only
  *               (DSS_ERR_ARG on a batch handle); tile_scale and tiled are then unused;
  *   wave_class: with sized, size classes from this one up (stencil radius wave_class + 1

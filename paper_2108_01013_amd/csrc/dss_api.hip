@@ -301,18 +301,18 @@ dss_status require_loaded(dss_handle *h)
     return DSS_OK;
 }
 
-// Size classes of the stencil path: class of radius a = floor(a cls_mul) (the same product
-// on host and device), ncls classes.
+// Size classes of the stencil path: class of radius a = floor(a cls_mul + cls_add), ncls
+// classes (cls_add = 0 without the electro-chemical ranges).
 struct SizeClasses {
     int ncls = 1;
-    double cls_mul = 0.0;
+    double cls_mul = 0.0, cls_add = 0.0;
 };
 
 // Cell lattice of every box: spacing >= cell_scale times the box's largest pair cutoff
 // 2 c a_max (with a 1e-9 margin), boxes numbered one after the other.  Returns false (and
 // why) when a box has fewer than 4 x 3 x 3 cells or more than 4096 cell rows.
-// Size-class stencils (one box): spacing >= cell_scale times the smallest pair cutoff
-// 2 c a_min, coarsened until the largest stencil (R_max = ncls cells) fits the box without
+// Size-class stencils (one box): spacing >= cell_scale times the reach of the smallest
+// particle (2 c a_min, or 2 max(c, 1) a_min + rext with the electro-chemical ranges), coarsened until the largest stencil (R_max = ncls cells) fits the box without
 // reaching a cell twice: n_x >= 2 R_max + 2 (the window of a sheared row), n_y, n_z >=
 // 2 R_max + 1.  Cells are numbered class-major: ncls x n_x n_y n_z sort keys.
 bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, double amin, double cf,
@@ -324,12 +324,13 @@ bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, 
             why = "size-class stencils need a handle of one box";
             return false;
         }
-        if (rext > 0.0) {
-            why = "size-class stencils do not take the electro-chemical ranges";
-            return false;
-        }
+        // reach of a particle of radius a: every partner of radius <= a lies within it.  The
+        // lubrication cutoff c (a_i + a_j) gives 2 c a; with the electro-chemical ranges the
+        // cutoff max(c (a_i + a_j), a_i + a_j + rext) is bounded by 2 max(c, 1) a + rext.
+        const double cm = rext > 0.0 ? 2.0 * std::max(cf, 1.0) : 2.0 * cf;
+        const double ca = rext > 0.0 ? rext : 0.0;
         BoxParams &G = boxes[0];
-        const double rc = cf * 2.0 * amin * (1.0 + 1e-9) * cell_scale;
+        const double rc = (cm * amin + ca) * (1.0 + 1e-9) * cell_scale;
         int n[3];
         for (int d = 0; d < 3; ++d) n[d] = std::max(1, (int)std::floor(G.L[d] / rc));
         for (;;) {
@@ -338,8 +339,9 @@ bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, 
                 return false;
             }
             const double cwmin = std::min(G.L[0] / n[0], std::min(G.L[1] / n[1], G.L[2] / n[2]));
-            sc.cls_mul = cf * 2.0 * (1.0 + 1e-9) / cwmin;
-            sc.ncls = (int)std::floor(amax[0] * sc.cls_mul) + 1;
+            sc.cls_mul = cm * (1.0 + 1e-9) / cwmin;
+            sc.cls_add = ca * (1.0 + 1e-9) / cwmin;
+            sc.ncls = (int)std::floor(amax[0] * sc.cls_mul + sc.cls_add) + 1;
             if (n[0] >= 2 * sc.ncls + 2 && n[1] >= 2 * sc.ncls + 1 && n[2] >= 2 * sc.ncls + 1) break;
             for (int d = 0; d < 3; ++d) n[d] -= std::max(1, n[d] / 16);
         }
@@ -426,13 +428,14 @@ dss_status setup_lattice(dss_handle *h)
         P.sized = sized ? 1 : 0;
         P.ncls = sc.ncls;
         P.cls_mul = sc.cls_mul;
+        P.cls_add = sc.cls_add;
         P.wave_cls = h->tune.wave_class > 0 ? h->tune.wave_class : 3;
         h->sized_grid[0] = h->sized_grid[1] = 0;
         if (sized) {
             ncell *= sc.ncls;
             int64_t n_big = 0;
             for (double a : h->rad_host)
-                n_big += std::min((int)std::floor(a * sc.cls_mul), sc.ncls - 1) >= P.wave_cls ? 1 : 0;
+                n_big += std::min((int)std::floor(a * sc.cls_mul + sc.cls_add), sc.ncls - 1) >= P.wave_cls ? 1 : 0;
             const int64_t n_lane = h->N - n_big;
             // wavefront workgroups in multiples of 8 (one per XCD), launched first
             const int g_wave =

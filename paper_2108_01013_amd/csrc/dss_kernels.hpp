@@ -49,7 +49,7 @@ struct DevParams {
     int sized;                      // 1: size-class stencils (class-major cell numbering)
     int ncls;                       // size classes (stencil radius of class k: k + 1 cells)
     int wave_cls;                   // classes from this one up take a wavefront per particle
-    double cls_mul;                 // class of radius a: floor(a cls_mul)
+    double cls_mul, cls_add;        // class of radius a: floor(a cls_mul + cls_add)
     int ec;                         // 1: electro-chemical forces over their own ranges
     double rext;                    // with ec: longest active range (pair set |r| < max(c s, s + rext))
     double rep_rng, att_rng;        // with ec: surface-distance ranges of repulsion and attraction
@@ -120,7 +120,7 @@ __device__ __forceinline__ double shear_at(const DevParams &P, double gd, double
 __device__ __forceinline__ int size_class(const DevParams &P, double a)
 {
 #pragma clang fp contract(off)
-    const int k = (int)floor(a * P.cls_mul);
+    const int k = (int)floor(a * P.cls_mul + P.cls_add);
     return k < 0 ? 0 : (k > P.ncls - 1 ? P.ncls - 1 : k);
 }
 

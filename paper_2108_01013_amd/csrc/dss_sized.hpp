@@ -5,7 +5,9 @@
 // Lattice: spacing cw >= cell_scale x 2 c a_min.  Particle i of radius a_i belongs to size
 // class k_i = floor(a_i cls_mul), cls_mul = 2 c (1 + 1e-9) / min(cw); its stencil radius is
 // R_i = k_i + 1 cells, so R_i cw > 2 c a_i >= c (a_i + a_j) for every partner j with
-// a_j <= a_i.  The counting sort is class-major (cell id = k n_cells + cell), so the slots of
+// a_j <= a_i.  With the electro-chemical ranges the reach is 2 max(c, 1) a_i + rext, which
+// bounds max(c (a_i + a_j), a_i + a_j + rext): the class is floor(a_i cls_mul + cls_add) with
+// cls_add = rext (1 + 1e-9) / min(cw), on a lattice of spacing >= the smallest reach.  The counting sort is class-major (cell id = k n_cells + cell), so the slots of
 // class k are one contiguous, spatially sorted block, and a wavefront of consecutive slots
 // holds one class (uniform stencil work).
 //

@@ -70,11 +70,55 @@ def test_ec_ranges_lockstep(ec_box, precision):
     sim.close()
 
 
-def test_ec_ranges_refusals(ec_box):
-    from paper_2108_01013_amd.dss import DssError, Simulation
-    w = ec_box
-    sim = Simulation(w.params)
-    sim.set_tuning(sized=True)
-    with pytest.raises(DssError):
-        sim.set_particles(w.x, w.rad)
+@pytest.fixture(scope="module")
+def ec_poly_box():
+    rad = synth.lognormal_radii(4000, hi=5.0, seed=13)
+    L = synth.box_for_fraction(rad, 0.45)
+    x = synth.relax_positions(rad, L, seed=14)
+    p = synth.default_params([L, L, L], hamaker=1e-3, F_ER=1.0, ec_ranges=True)
+    return synth.Workload("lognormal N=4000 on [1, 5], phi=0.45, attraction", x, rad, L, p)
+
+
+@pytest.mark.parametrize("wave_class", [0, 1])
+def test_ec_ranges_size_class_stencils(ec_poly_box, wave_class):
+    """The electro-chemical ranges on the size-class stencils: a particle's class follows its
+    reach 2 max(c, 1) a + 4 a0, which bounds every pair cutoff max(c (a_i + a_j), a_i + a_j +
+    4 a0) of a partner no larger than itself.  Lognormal radii on [1, 5] (three classes, 5x the
+    lubrication list); wave_class 0 (default split) and 1 (classes 1 and up on wavefronts).
+    Pair sets bit-identical to the oracle's brute force, F, T, Sigma and history within 1e-10,
+    three steps in lockstep."""
+    from paper_2108_01013_amd.dss import Simulation
+    w = ec_poly_box
+    p = w.params
+    say(f"case: electro-chemical ranges on size-class stencils N=4000 wave_class={wave_class}")
+    sim = Simulation(p, record_pairs=True)
+    sim.set_tuning(sized=True, wave_class=wave_class)
+    sim.set_particles(w.x, w.rad)
+    assert sim.box_info(0)["size_classes"] >= 3
+    n_lub = len(oracle.pairs_brute(dict(p, ec_ranges=False), w.x, w.rad, 0.0))
+    assert sim.info()["n_pairs"] > 4 * n_lub
+    assert np.array_equal(sim.pairs(), oracle.pairs_brute(p, w.x, w.rad, 0.0))
+    sim.step(2)
+    hp, hx = sim.history()
+    for k in range(3):
+        s = sim.state()
+        a, aw = oracle.accelerations(p, w.rad, s["F"], s["T"])
+        st = oracle.State(s["x"], s["u"], s["w"], a, aw, w.rad.copy(), 2 + k,
+                          oracle.History(hp.astype(np.int32), hx))
+        x_o = oracle.kick_drift(p, st)[0]
+        sim.step(1)
+        s1 = sim.state()
+        uh, wh = sim.eval_velocities()
+        assert np.array_equal(s1["x"], x_o)
+        delta = oracle.le_offset(p, 3 + k)
+        assert np.array_equal(sim.pairs(), oracle.pairs_brute(p, s1["x"], w.rad, delta)), f"step {k}: pairs"
+        F, T, S, H, npairs = oracle.forces(p, s1["x"], uh, wh, w.rad, 3 + k, st.history)
+        assert rel_inf(s1["F"], F) < TOL_F, f"step {k}: F {rel_inf(s1['F'], F)}"
+        assert rel_inf(s1["T"], T) < TOL_F, f"step {k}: T {rel_inf(s1['T'], T)}"
+        last, _, _ = sim.read_stress()
+        assert rel_inf(last, S) < TOL_F, f"step {k}: Sigma"
+        hp, hx = sim.history()
+        assert np.array_equal(hp, H.pairs)
+        if len(hp):
+            assert np.max(np.abs(hx - H.xi)) <= 1e-10 * np.max(np.abs(H.xi))
     sim.close()
