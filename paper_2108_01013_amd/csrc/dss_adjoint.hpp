@@ -34,11 +34,12 @@ __device__ __forceinline__ long long canon_find(const int *__restrict__ key, con
 // Committed history rows (slot rows with owner ids and partner keys, stretch oriented from
 // the smaller to the larger id) -> canonical rows by id.  Pass 1 appends each contact to the
 // row of its smaller id; pass 2 sorts every row by partner id.  ccnt must be zero on entry.
+template <int sw>
 __global__ void __launch_bounds__(kBlock) k_canon_fill(int N, int M, const int *__restrict__ own,
                                                        const int *__restrict__ key, const double *__restrict__ xi,
                                                        const double *__restrict__ xr, const int *__restrict__ cnt,
                                                        int *__restrict__ ckey, double *__restrict__ cxi,
-                                                       int *__restrict__ ccnt, DevClock *__restrict__ clk, int sw)
+                                                       int *__restrict__ ccnt, DevClock *__restrict__ clk)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
@@ -69,8 +70,9 @@ __global__ void __launch_bounds__(kBlock) k_canon_fill(int N, int M, const int *
     }
 }
 
+template <int sw>
 __global__ void __launch_bounds__(kBlock) k_canon_sort(int N, int M, int *__restrict__ ckey, double *__restrict__ cxi,
-                                                       int *__restrict__ ccnt, int sw)
+                                                       int *__restrict__ ccnt)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= N) return;
@@ -96,10 +98,11 @@ __global__ void __launch_bounds__(kBlock) k_canon_sort(int N, int M, int *__rest
 
 // Stretch adjoints from canonical rows A to canonical rows B (the same contacts, possibly
 // laid out differently): every contact of B takes the adjoint of its match in A, or 0.
+template <int sw>
 __global__ void __launch_bounds__(kBlock) k_canon_rekey(int N, int M, const int *__restrict__ keyA,
                                                         const int *__restrict__ cntA, const double *__restrict__ gA,
                                                         const int *__restrict__ keyB, const int *__restrict__ cntB,
-                                                        double *__restrict__ gB, int sw)
+                                                        double *__restrict__ gB)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= N) return;
@@ -112,8 +115,9 @@ __global__ void __launch_bounds__(kBlock) k_canon_rekey(int N, int M, const int 
 }
 
 // Clear the stretch adjoints of the contacts in canonical rows (the entries that exist).
+template <int sw>
 __global__ void __launch_bounds__(kBlock) k_canon_zero(int N, int M, const int *__restrict__ cnt,
-                                                       double *__restrict__ g, int sw)
+                                                       double *__restrict__ g)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= N) return;

@@ -1495,9 +1495,11 @@ dss_status tape_rows(dss_handle *h, TapeEntry &t)
     const int grid = (N + kBlock - 1) / kBlock;
     HIPTRY(hipMemsetAsync(t.ccnt, 0, N * sizeof(int), h->stream));
     const int sw = stretch_width(h);
-    hipLaunchKernelGGL(k_canon_fill, dim3(grid), dim3(kBlock), 0, h->stream, N, M, h->hown[h->hh], h->hkey[h->hh],
-                       h->hxi[h->hh], h->hxr[h->hh], h->hcnt[h->hh], t.ckey, t.cxi, t.ccnt, h->clk, sw);
-    hipLaunchKernelGGL(k_canon_sort, dim3(grid), dim3(kBlock), 0, h->stream, N, M, t.ckey, t.cxi, t.ccnt, sw);
+    auto fill = sw == 6 ? k_canon_fill<6> : k_canon_fill<3>;
+    auto sort = sw == 6 ? k_canon_sort<6> : k_canon_sort<3>;
+    hipLaunchKernelGGL(fill, dim3(grid), dim3(kBlock), 0, h->stream, N, M, h->hown[h->hh], h->hkey[h->hh],
+                       h->hxi[h->hh], h->hxr[h->hh], h->hcnt[h->hh], t.ckey, t.cxi, t.ccnt, h->clk);
+    hipLaunchKernelGGL(sort, dim3(grid), dim3(kBlock), 0, h->stream, N, M, t.ckey, t.cxi, t.ccnt);
     HIPTRY(hipGetLastError());
     return DSS_OK;
 }
@@ -1690,14 +1692,15 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         if (s) break;
         if (seg < nck - 1) {
             // stretch adjoints at the segment boundary: rows of the later segment -> this one
-            hipLaunchKernelGGL(k_canon_rekey, dim3(grid), dim3(kBlock), 0, h->stream, N, M, bkey, bcnt, xib_in,
-                               W.tape[len].ckey, W.tape[len].ccnt, xib_out, sw);
+            hipLaunchKernelGGL(sw == 6 ? k_canon_rekey<6> : k_canon_rekey<3>, dim3(grid), dim3(kBlock), 0, h->stream,
+                               N, M, bkey, bcnt, xib_in, W.tape[len].ckey, W.tape[len].ccnt, xib_out);
             std::swap(xib_in, xib_out);
         }
         for (int64_t k = len; k >= 1; --k) {
             const int64_t n = s0 + k;
             const TapeEntry &T1 = W.tape[k], &T0 = W.tape[k - 1];
-            hipLaunchKernelGGL(k_canon_zero, dim3(grid), dim3(kBlock), 0, h->stream, N, M, T0.ccnt, xib_out, sw);
+            hipLaunchKernelGGL(sw == 6 ? k_canon_zero<6> : k_canon_zero<3>, dim3(grid), dim3(kBlock), 0, h->stream, N,
+                               M, T0.ccnt, xib_out);
             VjpTape tp{T1.pairs, T1.x, T1.u, T1.w, rad, T0.ckey, T0.ccnt, T0.cxi, T1.ckey, T1.ccnt, sw};
             const bool sampled = n >= first && (n - first) % stress_every == 0;
             const int pgrid = (int)std::max<int64_t>(1, (T1.npairs + kBlock - 1) / kBlock);
