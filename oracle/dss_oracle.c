@@ -55,6 +55,13 @@
  *       attraction while d_ij < 4 a0; lubrication stays on |r| < c (a_i + a_j);
  *       the pair set is every pair inside any of these ranges.
  *
+ * Beyond the invariants, three parts are pinned against hand-evaluated values of
+ * the Appendix A table and closed forms: the magnitude of the log-singular Y
+ * coefficients (tangential lubrication over sizes and gaps; the equal-sphere value
+ * a/6 of Jeffrey and Onishi), the lubrication stresslet S^L (squeeze and sliding
+ * pairs, and the stress power of a sheared pair), and which particle's strain
+ * enters each column of R'(E).
+ *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no FMA contraction, so
  * the pair test r^2 < r_c^2 is evaluated as written).
  */

@@ -813,3 +813,144 @@ def test_wavy_strain_columns():
         assert not np.allclose(sij, sii)                                                  # E_j matters
         assert np.array_equal(oracle.lub_strain_terms(p0, ai, aj, h, n, yi, yj),
                               oracle.lub_strain_terms(p0, ai, aj, h, n))                 # W = 0: uniform
+
+
+# ---------------------------------------------------------------------------------------------
+# Magnitude of the log-singular Y coefficients (Appendix A: Y = g^Y log(1 / (d* + eps))).  A pair
+# sliding past another in quiescent fluid feels only the tangential block: F_i = 6 pi eta0
+# g^{Y^A_ii} ln(1/(d* + eps)) v t, F_j = -F_i.  Hand-evaluated values over sizes, size ratios and
+# gaps (tests/golden/lubrication_tangential.txt); for equal spheres g = a/6, Jeffrey and Onishi's
+# equal-sphere coefficient.  A base-10 logarithm, eps outside the logarithm or a wrong a_i power
+# fails.  The rigid-rotation pin then ties Y^B and Y^C to this magnitude.
+# ---------------------------------------------------------------------------------------------
+def _rows(name):
+    return [l.split() for l in open(os.path.join(GOLDEN, name)) if l.strip() and not l.startswith("#")]
+
+
+def test_tangential_lubrication_golden():
+    rows = _rows("lubrication_tangential.txt")
+    assert len(rows) >= 6
+    for ai, aj, h, eps, val in rows:
+        ai, aj, h, eps, val = map(float, (ai, aj, h, eps, val))
+        p = params(shear_rate=0.0, eta0=1.3, eps_lub=eps)
+        n = unit([0.3, -0.5, 0.8])
+        t = unit(np.cross(n, [1.0, 0.0, 0.0]))
+        v = 0.29
+        out = oracle.pair_eval(p, ai, aj, (ai + aj + h) * n, np.zeros(3), v * t, np.zeros(3), np.zeros(3))
+        expect = 6.0 * math.pi * p["eta0"] * val * v * t
+        assert rel(out["FL_i"], expect) < 1e-12, (ai, aj, h)
+        assert rel(out["FL_j"], -expect) < 1e-12, (ai, aj, h)
+
+
+# ---------------------------------------------------------------------------------------------
+# Lubrication stresslet S^L = 1/2 [r (x) F^L_i + (r (x) F^L_i)^T] (eq. stresslet).
+#  - Squeeze: with the Reynolds closed form F^L_i = -6 pi eta0 (a_i a_j/(a_i+a_j))^2 v / h_eff n,
+#    S^L = |r| F n (x) n.
+#  - Sliding: with the golden tangential force, S^L = |r|/2 (n (x) F_t + F_t (x) n) (symmetric).
+#  - In a box: a lubricated pair carried by the ambient shear (u' = 0, w' = 0, no contact, no
+#    repulsion) raises Sigma_xy above the Einstein value by exactly F_i.(E r) / (gdot V) (the
+#    stress power of the pair equals the work rate of its force on the affine relative motion),
+#    and that excess is positive and Sigma stays symmetric.  Dropping S^L, flipping its sign or
+#    leaving it unsymmetrised fails.
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("ai,aj,h", [(1.0, 1.4, 0.01), (2.5, 1.0, 0.0), (1.0, 1.0, 0.07)])
+def test_lubrication_stresslet_squeeze(ai, aj, h):
+    p = params(shear_rate=0.0, eta0=1.7)
+    n = unit([0.3, -0.5, 0.8])
+    r = (ai + aj + h) * n
+    v = 0.37
+    out = oracle.pair_eval(p, ai, aj, r, np.zeros(3), -v * n, np.zeros(3), np.zeros(3))
+    astar = ai * aj / (ai + aj)
+    heff = h + p["eps_lub"] * (ai + aj) / 2.0
+    F = -6.0 * math.pi * p["eta0"] * astar ** 2 * v / heff
+    assert rel(out["SL"], np.linalg.norm(r) * F * np.outer(n, n)) < 1e-12
+
+
+def test_lubrication_stresslet_sliding():
+    ai, aj, h, eps, val = map(float, _rows("lubrication_tangential.txt")[3])
+    p = params(shear_rate=0.0, eta0=1.3, eps_lub=eps)
+    n = unit([0.3, -0.5, 0.8])
+    t = unit(np.cross(n, [1.0, 0.0, 0.0]))
+    v = 0.29
+    r = (ai + aj + h) * n
+    out = oracle.pair_eval(p, ai, aj, r, np.zeros(3), v * t, np.zeros(3), np.zeros(3))
+    Ft = 6.0 * math.pi * p["eta0"] * val * v * t
+    expect = 0.5 * np.linalg.norm(r) * (np.outer(n, Ft) + np.outer(Ft, n))
+    assert rel(out["SL"], expect) < 1e-12
+    assert np.array_equal(out["SL"], out["SL"].T)
+
+
+@pytest.mark.parametrize("nvec", [[1.0, 1.0, 0.0], [1.0, -1.0, 0.0], [0.3, 0.8, -0.5], [-0.7, 0.2, 0.6]])
+def test_sheared_pair_stress_above_einstein(nvec):
+    L = 30.0
+    gd = 0.8
+    p = params(L=L, shear_rate=gd, F_ER=0.0, eta0=1.1)
+    ai, aj, h = 1.0, 1.4, 0.02
+    n = unit(nvec)
+    r = (ai + aj + h) * n
+    x0 = np.array([12.0, 14.0, 15.0])
+    x = np.array([x0, x0 + r])
+    rad = np.array([ai, aj])
+    u = oracle.ambient_velocity(p, x)
+    w = oracle.ambient_rotation(p, 2, x)
+    F, T, S, H, npairs = oracle.forces(p, x, u, w, rad, 0)
+    assert npairs == 1 and len(H.pairs) == 0
+    V = L ** 3
+    phi = (4.0 / 3.0) * math.pi * np.sum(rad ** 3) / V
+    einstein = p["eta0"] * gd * (1.0 + 2.5 * phi)
+    E = np.zeros((3, 3))
+    E[0, 1] = E[1, 0] = gd / 2.0
+    excess = S[0, 1] - einstein
+    power = float(F[0] @ (E @ r)) / (gd * V)
+    assert excess > 0.0
+    assert abs(excess - power) <= 1e-12 * abs(power)
+    assert abs(S[0, 1] - S[1, 0]) <= 1e-14 * abs(S[0, 1])
+
+
+# ---------------------------------------------------------------------------------------------
+# Columns of R'(E) (eq. rlu1): column i takes the ambient strain at particle i, column j the
+# strain at j.  In the wavy shear with no mean shear, the local strain vanishes at k y = pi/2
+# (cos = 0) and is W k at y = 0, so one column at a time is switched on; each must give the
+# printed coefficients of its own column (golden values of the Appendix A table,
+# tests/golden/lubrication_g.txt).  A swap of the columns (F_i taking g^{X^G_ji} with the strain
+# at i) fails for any alpha != 1.
+# ---------------------------------------------------------------------------------------------
+def _golden_g():
+    from fractions import Fraction
+    g = {}
+    for ai, aj, name, val in _rows("lubrication_g.txt"):
+        g[(float(Fraction(ai)), float(Fraction(aj)), name)] = float(Fraction(val))
+    return g
+
+
+@pytest.mark.parametrize("ai,aj", [(1.0, 1.4), (2.5, 3.5)])
+@pytest.mark.parametrize("h", [0.0, 0.04])
+@pytest.mark.parametrize("col", ["i", "j"])
+def test_strain_columns_golden(ai, aj, h, col):
+    L, Wa = 20.0, 3.0
+    p = params(L=L, shear_rate=0.0, wave_amp=Wa, wave_n=1.0)
+    k = 2.0 * math.pi / L
+    g = _golden_g()
+    n = unit([0.6, 0.7, -0.4])
+    s = Wa * k                        # local shear rate at y = 0; zero at y = L/4
+    E = np.zeros((3, 3))
+    E[0, 1] = E[1, 0] = s / 2.0
+    P = float(n @ E @ n)              # E : N - Tr E / 3 (traceless E)
+    Qn = 2.0 * E @ n - 2.0 * P * n
+    nperp = 2.0 * np.cross(n, E @ n)
+    eps = p["eps_lub"]
+    d = 2.0 * h / (ai + aj)
+    X = 1.0 / (d + eps)
+    Y = math.log(1.0 / (d + eps))
+    K = 6.0 * math.pi * p["eta0"]
+    if col == "i":
+        yi, yj = 0.0, L / 4.0
+        names = ("XG_ii", "YG_ii", "XG_ij", "YG_ij", "YH_ii", "YH_ij")
+    else:
+        yi, yj = L / 4.0, 0.0
+        names = ("XG_ji", "YG_ji", "XG_jj", "YG_jj", "YH_ji", "YH_jj")
+    c = [g[(ai, aj, nm)] for nm in names]
+    want = np.concatenate([K * (c[0] * X * P * n + c[1] * Y * Qn), K * (c[2] * X * P * n + c[3] * Y * Qn),
+                           K * c[4] * Y * nperp, K * c[5] * Y * nperp])
+    got = oracle.lub_strain_terms(p, ai, aj, h, n, yi, yj)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
