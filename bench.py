@@ -1,12 +1,16 @@
 """Throughput of the dense-suspension time step on one MI355X.
 
 Workload: N = 100 000 bidisperse spheres (radii 1 and 1.4, equal volumes), phi = 0.55, simple
-shear rate 1 under Lees-Edwards boundaries, mu = 1, dt = 1e-4, stress sampled every 10 steps.
-Inputs are seeded synthetic packings already resident in device memory when timing starts.
+shear rate 1 under Lees-Edwards boundaries, mu = 1, dt = 1e-4, stress sampled every 10 steps,
+timed after a pre-shear of one strain unit (10 000 steps) so that the contact network and the
+contact history are those of a sheared suspension.  Inputs are seeded synthetic packings
+already resident in device memory when timing starts.
 
-Prints one JSON line: particle-steps/s, the roofline of the dominant kernel (k_pairs) from HIP
-events recorded on the library's stream over the timed region, and the FP64 CPU oracle timed on
-a bounded sample of the same workload.
+Prints one JSON line: particle-steps/s of the graph-replayed step (wall clock between device
+synchronisations), the roofline of the dominant kernel (k_pairs) from HIP events recorded on
+the library's stream around its launches in a second pass over as many steps, the per-kernel
+table, the mixed-precision, batched-sweep and adjoint modes on the same GPU (``modes``), and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -24,13 +28,13 @@ HBM_PEAK_GBS = 8000.0
 
 
 def pairs_kernel_bytes(N: int, ncell: int, contacts: int, capacity: int) -> float:
-    """Compulsory bytes of one k_pairs launch in the FP64 layout.
-
-    per particle: pa, vel, omg records read (3 x 32 B), frc, trq written (2 x 32 B), its old-row
-    slot (inv 4 B) and count (4 B), new row count and owner (8 B);
-    per cell: cell_start (4 B);
-    per contact (each stored once): old key + xi read (4 + 24 B), new key + xi written (4 + 24 B)."""
-    return N * (3 * 32 + 2 * 32 + 4 + 4 + 8) + 4.0 * (ncell + 1) + contacts * (28 + 28)
+    """Algorithmic bytes of one pair-kernel launch (FP64), the per-unit figures of the step's
+    compulsory traffic times the units of one launch:
+    per particle: the sorted record read (x, u_half, w_half 3 x 24 B, radius 8 B, id 4 B = 84 B),
+    F and T written (48 B), its history row count and slot (8 B);
+    per contact (each stored once): the old key + stretch read (4 + 24 B) and the new one
+    written (4 + 24 B).  ncell and capacity do not enter (kept for the callers)."""
+    return N * (84 + 48 + 8) + contacts * (28 + 28)
 
 
 def cpu_baseline(w, seconds: float = 10.0, label: str = "the same"):
@@ -67,25 +71,48 @@ def maybe_tune(sim, args):
                        for t in rec.get("trials", [])]}
 
 
-def timed_run(sim, N, args, stress_every, kernels=("k_pairs",)):
-    """Warm-up, then the timed region with HIP events around the pair kernel(s); then an
-    untimed per-kernel breakdown (kernel timing replaces graph replay by direct launches).
-    Returns (seconds, pair-kernel timing, breakdown)."""
+def timed_run(sim, N, args, stress_every, kernels=("k_pairs",), steps=None, warmup=None):
+    """Warm-up, then the timed region: `steps` graph-replayed steps between two device
+    synchronisations (kernel timing off).  Then, from where that left off, as many steps with HIP
+    events around the pair kernel(s) (direct launches: the events are recorded by the launches
+    themselves), and a per-kernel breakdown over at most 50 steps.
+    Returns (seconds of the timed region, pair-kernel timing, breakdown)."""
     import torch
-    sim.step(args.warmup, stress_every=stress_every, sync=True)
-    torch.cuda.synchronize()
-    sim.set_timing(True, kernels=list(kernels))
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    sim.set_timing(False)
+    sim.step(warmup, stress_every=stress_every, sync=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(args.steps, stress_every=stress_every, sync=False)
+    sim.step(steps, stress_every=stress_every, sync=False)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    sim.set_timing(True, kernels=list(kernels))
+    sim.step(steps, stress_every=stress_every, sync=True)
     timing = sim.timing()
     sim.set_timing(True)
-    sim.step(min(args.steps, 50), stress_every=stress_every, sync=True)
+    sim.step(min(steps, 50), stress_every=stress_every, sync=True)
     breakdown = sim.timing()
     sim.set_timing(False)
     return el, timing, breakdown
+
+
+def preshear(sim, steps: int, chunk: int = 1000):
+    """Shear the box for `steps` steps before timing, in chunks that each end with a check of the
+    device error flags (the run stops at the first one)."""
+    from paper_2108_01013_amd.dss import DssError
+    done = 0
+    t0 = time.perf_counter()
+    try:
+        while done < steps:
+            k = min(chunk, steps - done)
+            sim.step(k, stress_every=0, sync=True)
+            done += k
+    except DssError as e:
+        print(f"# pre-shear stopped after {done} steps: {e}", file=sys.stderr, flush=True)
+        sys.exit(1)
+    print(f"# pre-shear: {done} steps in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return done
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pairs_fp64_N100k_hbm_traffic.txt")
@@ -161,6 +188,7 @@ def run_single(args):
     t_gen = time.perf_counter()
     w = cached_workload(args, lambda: synth.config_single_box(N=args.N or 100_000))
     print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    mode_inputs = mode_workloads(args) if args.modes else None
     import torch
 
     from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Simulation
@@ -178,6 +206,8 @@ def run_single(args):
     sim.set_particles(w.x, w.rad)
     N = len(w.rad)
     tuned = maybe_tune(sim, args)
+    sheared = preshear(sim, args.preshear)
+    blob = sim.save_state() if mode_inputs else None
     el, timing, breakdown = timed_run(sim, N, args, 10)
     info = sim.info()
     _, sigma_mean, nsamp = sim.read_stress()
@@ -186,6 +216,20 @@ def run_single(args):
         print(f"# device error flags {info['error_flags']}", file=sys.stderr)
         sys.exit(1)
     ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2])
+    roof = roofline(dominant_pairs(timing, breakdown), N, ncell, info["n_contacts"], info["capacity"],
+                    measured_traffic() if args.precision == "fp64" and N == 100_000 and not physics else None)
+    table = kernel_table(breakdown)
+    sim.close()
+    modes = None
+    if mode_inputs:
+        modes = {"fp64": {"value": round(N * args.steps / el, 1), "ms_per_step": round(el / args.steps * 1e3, 5),
+                          "roofline_frac": roof["frac"], "kernel": roof["kernel"]}}
+        modes["mixed"] = mode_mixed(w, p, blob, args)
+        modes["sweep"] = mode_sweep(*mode_inputs[0], args)
+        modes["adjoint"] = mode_adjoint(mode_inputs[1], args)
+        base = modes["fp64"]["ms_per_step"] / N
+        for k in ("mixed", "sweep", "adjoint"):
+            modes[k]["per_particle_step_vs_fp64"] = round(base / (modes[k]["ms_per_step"] / modes[k]["N"]), 4)
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_seconds, "the same N=100k phi=0.55")
     return {
         "metric": "particle-steps/s at N=100k phi=0.55; mixed/batched/adjoint vs plain FP64",
@@ -194,21 +238,88 @@ def run_single(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"single box N={N} bidisperse 1:1.4 equal volume, phi=0.55, LE shear rate 1, "
-                               f"mu=1, dt=1e-4, stress every 10 steps, {args.precision}"
+                               f"mu=1, dt=1e-4, stress every 10 steps, {args.precision}, timed after "
+                               f"{sheared} steps of pre-shear, graph-replayed steps"
                                + "".join(", " + x for x in physics),
-                   "N": N, "phi": 0.55, "precision": args.precision},
-        "roofline": roofline(dominant_pairs(timing, breakdown), N, ncell, info["n_contacts"], info["capacity"],
-                             measured_traffic() if args.precision == "fp64" and N == 100_000 and not physics
-                             else None),
+                   "N": N, "phi": 0.55, "precision": args.precision, "preshear_steps": sheared},
+        "roofline": roof,
         "cpu_baseline": cpu,
-        "kernels": kernel_table(breakdown),
+        "kernels": table,
+        "modes": modes,
         "observables_ms": obs,
-        "tuning": tuned or sim.tuning(),
+        "tuning": tuned or None,
         "diagnostics": {"n_pairs": info["n_pairs"], "n_contacts": info["n_contacts"],
+                        "contacts_per_particle": round(info["n_contacts"] / N, 4),
                         "max_row_fill": info["max_row_fill"], "capacity": info["capacity"],
                         "cells": info["cells"], "stress_samples": nsamp,
                         "eta_r_mean": float(sigma_mean[0, 1] / (p["eta0"] * p["shear_rate"]))},
     }
+
+
+def mode_workloads(args):
+    """Inputs of the mode comparison: the 64-box sweep and the N = 50k adjoint box, generated
+    before the GPU is touched (the sweep's boxes are relaxed in forked processes)."""
+    from paper_2108_01013_amd import synth
+    t0 = time.perf_counter()
+    sweep = synth.config_sweep(B=args.boxes, workers=args.workers)
+    wa = synth.bidisperse_box(50_000, 0.56, seed=5)
+    print(f"# mode workloads generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return sweep, wa
+
+
+def mode_mixed(w, p, blob, args):
+    """Mixed precision on the same pre-sheared state (the FP64 run's snapshot)."""
+    import torch
+
+    from paper_2108_01013_amd.dss import DSS_MIXED, Simulation
+    sim = Simulation(p, precision=DSS_MIXED, stream=torch.cuda.current_stream().cuda_stream)
+    sim.set_particles(w.x, w.rad)
+    sim.load_state(blob)
+    N = len(w.rad)
+    el, timing, breakdown = timed_run(sim, N, args, 10)
+    info = sim.info()
+    ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2])
+    roof = roofline(dominant_pairs(timing, breakdown), N, ncell, info["n_contacts"], info["capacity"])
+    sim.close()
+    return {"value": round(N * args.steps / el, 1), "ms_per_step": round(el / args.steps * 1e3, 5), "N": N,
+            "workload": "the FP64 box's pre-sheared state, FP32 pair arithmetic with FP64 gap and sums",
+            "roofline": roof, "contacts_per_particle": round(info["n_contacts"] / N, 4)}
+
+
+def measure_sweep(ws, gds, args, tune: bool, preshear_steps: int):
+    import numpy as np
+    import torch
+
+    from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Batch
+    prec = DSS_FP64 if args.precision == "fp64" else DSS_MIXED
+    params = [dict(w.params, shear_rate=g) for w, g in zip(ws, gds)]
+    sim = Batch(params, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
+    sim.set_particles([w.x for w in ws], [w.rad for w in ws])
+    N = sim.N
+    tuned = maybe_tune(sim, args) if tune else None
+    sheared = preshear(sim, preshear_steps)
+    el, timing, breakdown = timed_run(sim, N, args, 10)
+    info = sim.info()
+    _, sigma_mean, nsamp = sim.read_stress()
+    if info["error_flags"]:
+        print(f"# device error flags {info['error_flags']}", file=sys.stderr)
+        sys.exit(1)
+    boxes = [sim.box_info(b) for b in range(sim.B)]
+    ncell = int(sum(np.prod(b["cells"]) for b in boxes))
+    eta = [float(sigma_mean[b, 0, 1] / (params[b]["eta0"] * gds[b])) for b in range(sim.B)]
+    res = dict(N=N, B=sim.B, el=el, sheared=sheared, info=info, nsamp=nsamp, eta=eta, ncell=ncell,
+               roof=roofline(dominant_pairs(timing, breakdown), N, ncell, info["n_contacts"], info["capacity"]),
+               table=kernel_table(breakdown), tuning=tuned or sim.tuning())
+    sim.close()
+    return res
+
+
+def mode_sweep(ws, gds, args):
+    r = measure_sweep(ws, gds, args, tune=False, preshear_steps=args.sweep_preshear)
+    return {"value": round(r["N"] * args.steps / r["el"], 1), "ms_per_step": round(r["el"] / args.steps * 1e3, 5),
+            "N": r["N"], "workload": f"{r['B']} boxes, N_b uniform on 2000..50000, phi 0.40..0.58, shear rate "
+                                     f"1e-2..1e1, one graph per step, after {r['sheared']} steps of pre-shear",
+            "roofline": r["roof"], "contacts_per_particle": round(r["info"]["n_contacts"] / r["N"], 4)}
 
 
 def dominant_pairs(timing, breakdown):
@@ -306,8 +417,6 @@ def run_poly(args):
 
 
 def run_sweep(args):
-    import numpy as np
-
     from paper_2108_01013_amd import synth
 
     # the boxes are relaxed in a process pool, before anything loads the HIP runtime
@@ -315,45 +424,32 @@ def run_sweep(args):
     ws, gds = synth.config_sweep(B=args.boxes, workers=args.workers)
     print(f"# {len(ws)} boxes generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     import torch
-
-    from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Batch
-    prec = DSS_FP64 if args.precision == "fp64" else DSS_MIXED
     torch.cuda.set_device(0)
-    params = [dict(w.params, shear_rate=g) for w, g in zip(ws, gds)]
-    sim = Batch(params, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
-    sim.set_particles([w.x for w in ws], [w.rad for w in ws])
-    N = sim.N
-    tuned = maybe_tune(sim, args)
-    el, timing, breakdown = timed_run(sim, N, args, 10)
-    info = sim.info()
-    _, sigma_mean, nsamp = sim.read_stress()
-    if info["error_flags"]:
-        print(f"# device error flags {info['error_flags']}", file=sys.stderr)
-        sys.exit(1)
-    boxes = [sim.box_info(b) for b in range(sim.B)]
-    ncell = int(sum(np.prod(b["cells"]) for b in boxes))
-    eta = [float(sigma_mean[b, 0, 1] / (params[b]["eta0"] * gds[b])) for b in range(sim.B)]
+    r = measure_sweep(ws, gds, args, tune=bool(args.tune), preshear_steps=args.sweep_preshear)
+    N, info = r["N"], r["info"]
     mid = min(range(len(ws)), key=lambda b: abs(len(ws[b].rad) - 20_000))
     cpu = None if args.no_cpu_baseline else cpu_baseline(ws[mid], args.cpu_seconds,
                                                          f"box {mid} of the sweep (phi={synth.SWEEP_PHI[mid % 5]})")
     return {
         "metric": "particle-steps/s, batched flow-curve sweep",
-        "value": round(N * args.steps / el, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 5), "higher_is_better": True,
+        "value": round(N * args.steps / r["el"], 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r["el"] / args.steps * 1e3, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{sim.B} boxes, N_b uniform on 2000..50000 (sum {N}), phi_b in "
+        "config": {"workload": f"{r['B']} boxes, N_b uniform on 2000..50000 (sum {N}), phi_b in "
                                f"{list(synth.SWEEP_PHI)}, shear rate 1e-2..1e1, bidisperse 1:1.4, mu=1, "
-                               f"dt=1e-4, stress every 10 steps, {args.precision}",
-                   "boxes": sim.B, "N": N, "precision": args.precision},
-        "roofline": roofline(timing, N, ncell, info["n_contacts"], info["capacity"]),
+                               f"dt=1e-4, stress every 10 steps, {args.precision}, after {r['sheared']} steps "
+                               f"of pre-shear",
+                   "boxes": r["B"], "N": N, "precision": args.precision},
+        "roofline": r["roof"],
         "cpu_baseline": cpu,
-        "kernels": kernel_table(breakdown),
-        "tuning": tuned or sim.tuning(),
+        "kernels": r["table"],
+        "tuning": r["tuning"],
         "diagnostics": {"n_pairs": info["n_pairs"], "n_contacts": info["n_contacts"],
+                        "contacts_per_particle": round(info["n_contacts"] / N, 4),
                         "max_row_fill": info["max_row_fill"], "capacity": info["capacity"],
-                        "cells_total": ncell, "stress_samples": nsamp,
-                        "eta_r_mean": [round(e, 4) for e in eta]},
+                        "cells_total": r["ncell"], "stress_samples": r["nsamp"],
+                        "eta_r_mean": [round(e, 4) for e in r["eta"]]},
     }
 
 
@@ -365,28 +461,23 @@ def vjp_kernel_bytes(N: int, pairs: int, contacts: int) -> float:
     return N * (80 + 48 + 144) + pairs * 8 + contacts * (56 + 48)
 
 
-def run_adjoint(args):
+def measure_adjoint(w, args, precision: str, K: int, C: int, warmup: int):
+    """Adjoint of the mean Sigma_xy over K steps from w's packing: returns the wall time of the
+    adjoint call, the forward-only wall time of K steps, the VJP kernel's roofline and the result."""
     import numpy as np
-
-    from paper_2108_01013_amd import synth
-
-    t_gen = time.perf_counter()
-    N = args.N or 50_000
-    w = synth.bidisperse_box(N, 0.56, seed=5)
-    print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     import torch
 
     from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Simulation
-    torch.cuda.set_device(0)
     p = w.params
-    prec = DSS_FP64 if args.precision == "fp64" else DSS_MIXED
-    K, se, C = args.steps, 10, args.ckpt
+    N = len(w.rad)
+    prec = DSS_FP64 if precision == "fp64" else DSS_MIXED
+    se = 10
     Wt = np.zeros((3, 3))
     Wt[0, 1] = 1.0
     sim = Simulation(p, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
     sim.set_particles(w.x, w.rad)
     # warm-up: a short adjoint (allocations, first launches), then back to a state at u^n
-    sim.adjoint(min(args.warmup, K) or 1, 1, C, Wt)
+    sim.adjoint(min(warmup, K) or 1, 1, C, Wt)
     sim.compute_forces()
     torch.cuda.synchronize()
     # forward only, for the ratio
@@ -403,6 +494,7 @@ def run_adjoint(args):
     tm = sim.timing()
     sim.set_timing(False)
     info = sim.info()
+    sim.close()
     ms, nl = tm["k_pairs_vjp"]
     avg = ms / max(nl, 1) * 1e-3
     bytes_launch = vjp_kernel_bytes(N, info["n_pairs"], info["n_contacts"])
@@ -410,11 +502,39 @@ def run_adjoint(args):
     roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_pairs_vjp",
             "avg_launch_us": round(avg * 1e6, 3), "bytes_per_launch": int(bytes_launch)}
+    return dict(N=N, K=K, C=C, se=se, el=el, fwd=fwd, roof=roof, r=r, info=info)
+
+
+def mode_adjoint(w, args):
+    a = measure_adjoint(w, args, "mixed", 200, 20, args.warmup)
+    return {"value": round(a["N"] * a["K"] / a["el"], 1), "ms_per_step": round(a["el"] / a["K"] * 1e3, 5),
+            "N": a["N"], "workload": "gradient of mean Sigma_xy over 200 steps, N=50k bidisperse phi=0.56, "
+                                     "mixed-precision forward, FP64 reverse, checkpoints every 20 steps; "
+                                     "value counts forward, recompute and reverse",
+            "roofline": a["roof"], "adjoint_over_forward": round(a["el"] / a["fwd"], 3)}
+
+
+def run_adjoint(args):
+    import numpy as np
+
+    from paper_2108_01013_amd import synth
+
+    t_gen = time.perf_counter()
+    N = args.N or 50_000
+    w = synth.bidisperse_box(N, 0.56, seed=5)
+    print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    import torch
+    torch.cuda.set_device(0)
+    K, C = args.steps, args.ckpt
+    a = measure_adjoint(w, args, args.precision, K, C, args.warmup)
+    r, info = a["r"], a["info"]
     cpu = None
     if not args.no_cpu_baseline:
         # the oracle's forward objective on a bounded window; its gradient would be 2 runs per
         # component by finite differences
         import oracle
+        Wt = np.zeros((3, 3))
+        Wt[0, 1] = 1.0
         small = synth.bidisperse_box(2000, 0.56, seed=5)
         u0 = oracle.ambient_velocity(small.params, small.x)
         w0 = oracle.ambient_rotation(small.params, len(small.rad))
@@ -428,6 +548,7 @@ def run_adjoint(args):
                "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"{k} oracle runs of the stress objective, N=2000 phi=0.56, 20 steps each, {ec:.1f} s; "
                          "a finite-difference gradient costs 2 such runs per component"}
+    el = a["el"]
     return {
         "metric": "adjoint particle-steps/s (forward + checkpointed recompute + reverse)",
         "value": round(N * K / el, 1), "unit": "particle-steps/s", "n_gpus": 1, "steps": K,
@@ -435,13 +556,13 @@ def run_adjoint(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"adjoint of mean Sigma_xy over {K} steps, N={N} bidisperse 1:1.4, phi=0.56, "
-                               f"stress every {se}, checkpoints every {C}, gradients w.r.t. x0, u0, w0, mu, F_ER, "
-                               f"forward in {args.precision}, reverse in FP64",
+                               f"stress every {a['se']}, checkpoints every {C}, gradients w.r.t. x0, u0, w0, mu, "
+                               f"F_ER, forward in {args.precision}, reverse in FP64",
                    "N": N, "ckpt_every": C, "precision": args.precision},
-        "roofline": roof,
+        "roofline": a["roof"],
         "cpu_baseline": cpu,
-        "forward_only_ms_per_step": round(fwd / K * 1e3, 5),
-        "adjoint_over_forward": round(el / fwd, 3),
+        "forward_only_ms_per_step": round(a["fwd"] / K * 1e3, 5),
+        "adjoint_over_forward": round(el / a["fwd"], 3),
         "diagnostics": {"J": r["J"], "dJ_dmu": r["dmu"], "dJ_dF_ER": r["dF_ER"],
                         "grad_x_norm": float(np.linalg.norm(r["dx"])), "n_pairs": info["n_pairs"],
                         "n_contacts": info["n_contacts"]},
@@ -476,6 +597,11 @@ def main():
     ap.add_argument("--observables", action="store_true", help="single: time the observables after the run")
     ap.add_argument("--cell-scale", type=float, default=None, help="poly: lattice spacing over 2 c a_min (1.5)")
     ap.add_argument("--wave-class", type=int, default=2, help="poly: first size class on a wavefront (2)")
+    ap.add_argument("--preshear", type=int, default=10_000,
+                    help="single: steps sheared before timing (10000 = one strain unit at dt = 1e-4)")
+    ap.add_argument("--sweep-preshear", type=int, default=1000, help="sweep: steps sheared before timing")
+    ap.add_argument("--modes", type=int, default=1,
+                    help="single: 1 = also time mixed precision, the 64-box sweep and the adjoint (N=50k)")
     args = ap.parse_args()
     if args.tune is None:
         args.tune = 1 if args.mode == "sweep" else 0

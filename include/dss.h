@@ -206,14 +206,27 @@ dss_status dss_get_tuning(dss_handle *h, dss_tuning *t);
  * n < 0. */
 dss_status dss_set_step(dss_handle *h, int64_t n);
 
-/* Counting sort of the current positions into the cell lattice (no time advance). */
+/* Neighbour build of Sec. 2.1 (Figs. alg, alg2) at the current positions, without time
+ * advance: cell id of every particle, counting sort into the cell lattice (histogram, exclusive
+ * scan, scatter into cell-major order), the committed contact history moved with its
+ * particles to their new sorted slots, then the half-shell pair search and the forces at the
+ * current state (as dss_compute_forces).  A lattice set by dss_set_tuning takes effect here.
+ * The cell lattice and order are read back with dss_get_cells.  Errors: DSS_ERR_STATE before
+ * dss_set_particles, DSS_ERR_BOX for a pending lattice that is too small, DSS_ERR_CAPACITY /
+ * DSS_ERR_UNSTABLE from the device flags (synchronises). */
 dss_status dss_build_neighbours(dss_handle *h);
 
-/* Forces, torques and stress at the current state (positions, velocities u^n, the
- * current contact history), without advancing time or the history. */
+/* Forces, torques and stress of eqs. (hydro), (contact0), (csi), (rep), (att), (rst) and
+ * (stress), (stresslet) at the current state (positions, velocities u^n, the current contact
+ * history) over the pairs of the half-shell search of Sec. 2.1 in the current sorted order,
+ * without advancing time or the history.  Synchronises; errors as dss_build_neighbours. */
 dss_status dss_compute_forces(dss_handle *h);
 
-/* Advance n_steps time steps.  If stress_every > 0, the stress tensor is sampled at
+/* Advance n_steps time steps of the modified velocity-Verlet scheme of Sec. 2.1 (numerical
+ * algorithm): half kick and drift, the Lees-Edwards wrap of eq. (le), the counting sort and
+ * half-shell search, the pair and particle forces of eqs. (hydro)-(att), the contact history
+ * of the memory paragraph (rows sorted by partner id, entries of separated pairs dropped) and
+ * the finishing kick.  If stress_every > 0, the stress tensor is sampled at
  * every step whose time index is a multiple of stress_every; the samples of this call
  * are returned by dss_read_stress.  The stress and the pair and contact counters are
  * summed only on those steps and on the last step of the call (the other steps skip the

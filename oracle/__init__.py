@@ -26,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dss_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libdss_oracle.so")
 
-PAIR_OUT = 67
+PAIR_OUT = 69
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -88,10 +88,10 @@ def lib():
         "orc_pair_eval": (None, [P, ctypes.c_double, ctypes.c_double, _c_double_p, ctypes.c_double, ctypes.c_double,
                                  _c_double_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
                                  _c_double_p]),
-        "orc_forces": (ctypes.c_int64, [P, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
-                                        ctypes.c_int64, ctypes.c_int, ctypes.c_int64, _c_int32_p, _c_double_p,
-                                        _c_double_p, ctypes.c_int64, _c_int32_p, _c_double_p, _c_double_p,
-                                        _c_int64_p, _c_double_p, _c_double_p, _c_double_p]),
+        "orc_forces_ex": (ctypes.c_int64, [P, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
+                                           ctypes.c_int64, ctypes.c_int, ctypes.c_int64, _c_int32_p, _c_double_p,
+                                           _c_double_p, ctypes.c_int64, _c_int32_p, _c_double_p, _c_double_p,
+                                           _c_int32_p, _c_int64_p, _c_double_p, _c_double_p, _c_double_p]),
         "orc_kick_drift": (None, [P, ctypes.c_int64, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p,
                                   _c_double_p, _c_double_p, _c_double_p, _c_double_p]),
         "orc_finish": (None, [P, ctypes.c_int64, _c_double_p, _c_double_p, _c_double_p, _c_double_p,
@@ -253,6 +253,7 @@ def pair_eval(p, ai, aj, r, upi, upj, wi, wj, xi_old=(0.0, 0.0, 0.0), xr_old=(0.
         "FE_i": out[24:27], "FE_j": out[27:30],
         "SL": out[30:39].reshape(3, 3), "SC": out[39:48].reshape(3, 3), "SE": out[48:57].reshape(3, 3),
         "xi": out[57:60], "contact": bool(out[60] != 0.0), "xr": out[61:64], "TR_i": out[64:67],
+        "capped": bool(out[67] != 0.0), "rcapped": bool(out[68] != 0.0),
     }
 
 
@@ -262,10 +263,14 @@ def pair_eval(p, ai, aj, r, upi, upj, wi, wj, xi_old=(0.0, 0.0, 0.0), xr_old=(0.
 @dataclass
 class History:
     """Map {(a, b), a < b} -> xi (tangential stretch oriented for (a, b)) and xr (rolling
-    stretch, the same from either side; zeros without rolling resistance), sorted by (a, b)."""
+    stretch, the same from either side; zeros without rolling resistance), sorted by (a, b).
+    capped: per entry, bit 0 set when the Coulomb cap of eq. (csi) limited xi at the evaluation
+    that wrote it (the contact slides), bit 1 when the rolling limit limited xr (None when not
+    recorded, e.g. a history built from the GPU's export)."""
     pairs: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int32))
     xi: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     xr: np.ndarray | None = None
+    capped: np.ndarray | None = None
 
     def rolling(self):
         return np.zeros_like(self.xi) if self.xr is None else self.xr
@@ -295,15 +300,17 @@ def forces(p, x, u, w, rad, step, history: History | None = None, use_cells=Fals
         hp_new = np.zeros((hcap, 2), np.int32)
         hx_new = np.zeros((hcap, 3))
         hr_new = np.zeros((hcap, 3))
+        hc_new = np.zeros(hcap, np.int32)
         nh = ctypes.c_int64(0)
-        np_ = lib().orc_forces(ctypes.byref(_params(p)), N, _d(x), _d(u), _d(w), _d(rad), int(step),
-                               int(bool(use_cells)), len(hp), _i32(hp), _d(hx), _d(hr), hcap, _i32(hp_new),
-                               _d(hx_new), _d(hr_new), ctypes.byref(nh), _d(F), _d(T), _d(S))
+        np_ = lib().orc_forces_ex(ctypes.byref(_params(p)), N, _d(x), _d(u), _d(w), _d(rad), int(step),
+                                  int(bool(use_cells)), len(hp), _i32(hp), _d(hx), _d(hr), hcap, _i32(hp_new),
+                                  _d(hx_new), _d(hr_new), _i32(hc_new), ctypes.byref(nh), _d(F), _d(T), _d(S))
         if np_ >= 0:
             break
         hcap = int(nh.value)
     k = int(nh.value)
-    return F, T, S.reshape(3, 3), History(hp_new[:k].copy(), hx_new[:k].copy(), hr_new[:k].copy()), int(np_)
+    return F, T, S.reshape(3, 3), History(hp_new[:k].copy(), hx_new[:k].copy(), hr_new[:k].copy(),
+                                          hc_new[:k].copy()), int(np_)
 
 
 @dataclass
@@ -321,7 +328,9 @@ class State:
     def copy(self):
         return State(self.x.copy(), self.u.copy(), self.w.copy(), self.alpha.copy(), self.alpha_w.copy(),
                      self.rad.copy(), self.step, History(self.history.pairs.copy(), self.history.xi.copy(),
-                                                         self.history.rolling().copy()))
+                                                         self.history.rolling().copy(),
+                                                         None if self.history.capped is None
+                                                         else self.history.capped.copy()))
 
 
 def _wave(p):
@@ -419,15 +428,18 @@ def rheology(Sigma, p):
 def stress_objective(p, x0, rad, u0, w0, n_steps: int, stress_every: int, weight, use_cells=False):
     """J = sum_ab weight_ab mean_samples(Sigma_ab) over a run of n_steps steps from (x0, u0, w0)
     with an empty initial history, Sigma sampled at the time indices that are multiples of
-    stress_every (eq. stress).  Also returns the run's branch record per step (listed pairs
-    and contact pairs), so that a finite difference of J can be checked to stay on one
-    branch.  The adjoint's reference is the central finite difference of this function."""
+    stress_every (eq. stress).  Also returns the run's branch record per step (the number of
+    listed pairs, the contact pairs, and each contact's stick/slip state: whether the Coulomb
+    cap, and with rolling resistance the rolling limit, bound at that step), so that a finite
+    difference of J can be checked to stay on one branch: J is smooth in the inputs while none
+    of these changes.  The adjoint's reference is the central finite difference of this
+    function."""
     st, F, T, S = init_state(p, x0, rad, u0, w0, use_cells)
     W = np.asarray(weight, dtype=np.float64).reshape(3, 3)
     samples, branch = [], []
     for n in range(1, n_steps + 1):
         st, F, T, S, npairs, _ = step(p, st, use_cells)
-        branch.append((npairs, st.history.pairs.tobytes()))
+        branch.append((npairs, st.history.pairs.tobytes(), st.history.capped.tobytes()))
         if n % stress_every == 0:
             samples.append(np.asarray(S).reshape(3, 3))
     return float(np.sum(W * np.mean(samples, axis=0))), branch

@@ -647,8 +647,10 @@ void orc_lub_strain_terms(const orc_params *p, double ai, double aj, double h, c
 /*   [30:39] S^L  [39:48] S^C  [48:57] S^E   (row-major 3x3)                  */
 /*   [57:60] xi_new  [60] 1 if in contact (d_ij < 0) else 0                   */
 /*   [61:64] xr_new  [64:67] rolling torque on i (included in T^C_i, T^C_j)   */
+/*   [67] 1 if the Coulomb cap of eq. (csi) rescaled xi_new (slip), else 0    */
+/*   [68] 1 if the rolling limit rescaled xr_new, else 0                      */
 /* ------------------------------------------------------------------------- */
-#define ORC_PAIR_OUT 67
+#define ORC_PAIR_OUT 69
 
 void orc_pair_eval(const orc_params *p, double ai, double aj, const double *r, double yi, double yj,
                    const double *upi, const double *upj, const double *wi, const double *wj, const double *xi_old,
@@ -718,8 +720,10 @@ void orc_pair_eval(const orc_params *p, double ai, double aj, const double *r, d
             double fn_mag = sqrt(dot3(Fn, Fn));
             double cap = p->mu * fn_mag / p->kt;
             double xim = sqrt(dot3(xi, xi));
-            if (xim >= cap && xim > 0.0)
+            if (xim >= cap && xim > 0.0) {
                 for (int a = 0; a < 3; ++a) xi[a] *= cap / xim;
+                out[67] = 1.0;
+            }
             for (int a = 0; a < 3; ++a) Ft[a] = p->kt * xi[a];
         } else {
             for (int a = 0; a < 3; ++a) xi[a] = 0.0;
@@ -748,8 +752,10 @@ void orc_pair_eval(const orc_params *p, double ai, double aj, const double *r, d
             double fn_mag = sqrt(dot3(Fn, Fn));
             double cap = p->mu_r * fn_mag / p->kr;
             double xm = sqrt(dot3(xr, xr));
-            if (xm >= cap && xm > 0.0)
+            if (xm >= cap && xm > 0.0) {
                 for (int a = 0; a < 3; ++a) xr[a] *= cap / xm;
+                out[68] = 1.0;
+            }
             double Fr[3], Tr[3];
             for (int a = 0; a < 3; ++a) Fr[a] = p->kr * xr[a]; /* pseudo-force */
             cross3(n, Fr, Tr);
@@ -827,10 +833,15 @@ static int64_t history_find(int64_t nh, const int32_t *hpair, int32_t a, int32_t
 /* step: time index of the state (sets the Lees-Edwards offset).              */
 /* Returns the number of listed pairs, or -1 if a capacity was too small.     */
 /* ------------------------------------------------------------------------- */
-int64_t orc_forces(const orc_params *p, int64_t N, const double *x, const double *u, const double *w,
-                   const double *rad, int64_t step, int use_cells, int64_t nh_old, const int32_t *hpair_old,
-                   const double *hxi_old, const double *hxr_old, int64_t hcap, int32_t *hpair_new,
-                   double *hxi_new, double *hxr_new, int64_t *nh_new, double *F, double *T, double *Sigma)
+/* hcap_new (nullable): per new history entry, bit 0 set when the Coulomb cap   */
+/* rescaled its stretch at this evaluation, bit 1 when the rolling limit did  */
+/* (the stick/slip state of the contact, part of the run's branch).           */
+/* ------------------------------------------------------------------------- */
+int64_t orc_forces_ex(const orc_params *p, int64_t N, const double *x, const double *u, const double *w,
+                      const double *rad, int64_t step, int use_cells, int64_t nh_old, const int32_t *hpair_old,
+                      const double *hxi_old, const double *hxr_old, int64_t hcap, int32_t *hpair_new,
+                      double *hxi_new, double *hxr_new, int32_t *hcap_new, int64_t *nh_new, double *F, double *T,
+                      double *Sigma)
 {
     double delta = orc_le_offset(p, step);
     int64_t cap = 16 * N + 16;
@@ -897,6 +908,7 @@ int64_t orc_forces(const orc_params *p, int64_t N, const double *x, const double
                 for (int c = 0; c < 3; ++c) hxi_new[3 * nh + c] = o[57 + c];
                 if (hxr_new)
                     for (int c = 0; c < 3; ++c) hxr_new[3 * nh + c] = o[61 + c];
+                if (hcap_new) hcap_new[nh] = (o[67] != 0.0 ? 1 : 0) | (o[68] != 0.0 ? 2 : 0);
             } else {
                 overflow = 1;
             }
@@ -927,6 +939,16 @@ int64_t orc_forces(const orc_params *p, int64_t N, const double *x, const double
     free(res);
     free(pairs);
     return overflow ? -1 : np;
+}
+
+/* orc_forces_ex without the stick/slip record. */
+int64_t orc_forces(const orc_params *p, int64_t N, const double *x, const double *u, const double *w,
+                   const double *rad, int64_t step, int use_cells, int64_t nh_old, const int32_t *hpair_old,
+                   const double *hxi_old, const double *hxr_old, int64_t hcap, int32_t *hpair_new,
+                   double *hxi_new, double *hxr_new, int64_t *nh_new, double *F, double *T, double *Sigma)
+{
+    return orc_forces_ex(p, N, x, u, w, rad, step, use_cells, nh_old, hpair_old, hxi_old, hxr_old, hcap, hpair_new,
+                         hxi_new, hxr_new, NULL, nh_new, F, T, Sigma);
 }
 
 /* ------------------------------------------------------------------------- */

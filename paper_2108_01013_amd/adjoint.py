@@ -22,11 +22,16 @@ class StressObjective(torch.autograd.Function):
                 precision=DSS_FP64):
         p = dict(params, mu=float(mu), F_ER=float(fer))
         ctx.theta_dev = tuple(t.device if torch.is_tensor(t) else None for t in (mu, fer))
-        sim = Simulation(p, precision=precision)
+        dev = x0.device
+        if dev.type == "cuda":
+            # device tensors go to the library as device pointers, on torch's current stream
+            sim = Simulation(p, precision=precision, stream=torch.cuda.current_stream(dev).cuda_stream)
+            inputs = tuple(t.detach().to(dev, torch.float64).contiguous() for t in (x0, radius, u0, w0))
+        else:
+            sim = Simulation(p, precision=precision)
+            inputs = tuple(t.detach().to("cpu", torch.float64).contiguous().numpy() for t in (x0, radius, u0, w0))
         try:
-            dev = x0.device
-            cpu = lambda t: t.detach().to("cpu", torch.float64).contiguous().numpy()  # noqa: E731
-            sim.set_particles(cpu(x0), cpu(radius), cpu(u0), cpu(w0))
+            sim.set_particles(*inputs)
             wt = np.asarray(weight, np.float64).reshape(3, 3)
             if any(ctx.needs_input_grad[:5]):
                 if dev.type == "cuda":

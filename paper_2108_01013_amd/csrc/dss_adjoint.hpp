@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(kBlock) k_canon_fill(int N, int M, const int *
         const int a = id < partner ? id : partner, b = id < partner ? partner : id;
         const int s = atomicAdd(&ccnt[a], 1);
         if (s < M) {
-            ckey[(long long)a * M + s] = b | (kw & kCapBit);
+            ckey[(long long)a * M + s] = b | (kw & (kCapBit | kRollCapBit));
             const double *x = xi + ((long long)p * M + k) * 3;
             double *y = cxi + ((long long)a * M + s) * sw;
             y[0] = x[0];
@@ -189,13 +189,14 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
             bar.xr[c] = 0.0;
         }
         // branch of the forward run: a pair is a contact after the step iff its rows hold it,
-        // and the rows record whether its Coulomb cap was active (at the initial evaluation,
-        // which commits no rows, the branch is recomputed)
-        int f_contact = -1, f_capped = -1;
+        // and the rows record whether its Coulomb cap and its rolling limit were active (at the
+        // initial evaluation, which commits no rows, the branch is recomputed)
+        int f_contact = -1, f_capped = -1, f_rcapped = -1;
         if (tp.key_new) {
             const long long pn = canon_find(tp.key_new, tp.cnt_new, P.M, a, b);
             f_contact = pn >= 0 ? 1 : 0;
             f_capped = pn >= 0 ? ((tp.key_new[pn] & kCapBit) ? 1 : 0) : 0;
+            f_rcapped = pn >= 0 ? ((tp.key_new[pn] & kRollCapBit) ? 1 : 0) : 0;
             if (pn >= 0 && xib_new)
                 for (int c = 0; c < 3; ++c) {
                     bar.xi[c] = xib_new[sw * pn + c];
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
         C.roll = sw == 6 ? 1 : 0; C.kr = P.kr; C.mu_r = P.mu_r;
         PairGrad g = {};
         pair_vjp(C, G.gd, r, tp.rad[a], tp.rad[b], xa[1], xb[1], tp.u + 3LL * a, tp.u + 3LL * b, tp.w + 3LL * a,
-                 tp.w + 3LL * b, xo, bar, g, nullptr, f_contact, f_capped, xro);
+                 tp.w + 3LL * b, xo, bar, g, nullptr, f_contact, f_capped, xro, f_rcapped);
         atomic_add3(ax + 3LL * a, -g.r[0], -g.r[1] + g.yi, -g.r[2]);
         atomic_add3(ax + 3LL * b, g.r[0], g.r[1] + g.yj, g.r[2]);
         atomic_add3(au + 3LL * a, g.ui[0], g.ui[1], g.ui[2]);

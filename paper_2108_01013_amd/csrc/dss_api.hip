@@ -78,6 +78,7 @@ struct dss_handle {
     double *hxr[2] = {nullptr, nullptr};  // rolling stretches (only with rolling resistance)
     int *pairs = nullptr;
     unsigned long long *pair_count = nullptr;
+    unsigned long long *hist_count = nullptr;  // counter of the history export (second word of pair_count)
     DevClock *clk = nullptr;
     DevRun *run = nullptr;
     double *sigma_last = nullptr;
@@ -181,6 +182,7 @@ void free_all(dss_handle *h)
     h->prev = nullptr;
     h->cell = h->rank = h->pairs = nullptr;
     h->pair_count = nullptr;
+    h->hist_count = nullptr;
     h->clk = nullptr;
     h->run = nullptr;
     h->sigma_last = h->samples = nullptr;
@@ -539,7 +541,9 @@ dss_status setup_lattice(dss_handle *h)
 //   EVAL_STEP:    a full time step: drift + kick, counting sort, pairs; history committed.
 //   EVAL_SORT:    counting sort of the current positions, then pairs (initial evaluation).
 //   EVAL_INPLACE: pairs at the current state and order (velocities completed to u^n).
-enum EvalMode { EVAL_STEP = 0, EVAL_SORT = 1, EVAL_INPLACE = 2 };
+//   EVAL_RESORT:  counting sort of the current positions (velocities completed to u^n), the
+//                 committed history moved to the new slots, then pairs; no time advance.
+enum EvalMode { EVAL_STEP = 0, EVAL_SORT = 1, EVAL_INPLACE = 2, EVAL_RESORT = 3 };
 
 // The pair kernels of one evaluation: size-class stencils (lane and wavefront paths), or
 // the row tiles followed by the rows they deferred.  Real: FP64 or mixed arithmetic; Roll:
@@ -686,7 +690,16 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
                               h->ncell_total + 1, h->cell_start, h->clk, advance, h->pa[c], h->vel[c], h->omg[c],
                               h->pa[o], h->vel[o], h->omg[o], h->prev);
     }
-    dss_status s = launch_pairs(h, o, h->prev, advance, finish);
+    if (mode == EVAL_RESORT) {
+        // the committed rows follow their particles; the pair kernels then find them in place
+        const int hn = 1 - h->hh;
+        hipLaunchKernelGGL(k_history_move, dim3(grid), dim3(kBlock), 0, h->stream, N, h->P.M, h->prev,
+                           h->hkey[h->hh], h->hxi[h->hh], h->hxr[h->hh], h->hcnt[h->hh], h->hown[h->hh], h->hkey[hn],
+                           h->hxi[hn], h->hxr[hn], h->hcnt[hn], h->hown[hn]);
+        HIPTRY(hipGetLastError());
+        h->hh = hn;
+    }
+    dss_status s = launch_pairs(h, o, mode == EVAL_RESORT ? nullptr : h->prev, advance, finish);
     if (s) return s;
     HIPTRY(hipGetLastError());
     commit_eval(h, advance != 0);
@@ -839,7 +852,7 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
         if (n_per_box[b] < 1) return fail(h, DSS_ERR_ARG, "every box needs at least one particle");
         N += n_per_box[b];
     }
-    if (N > (int64_t)0x3fffffff) return fail(h, DSS_ERR_ARG, "too many particles");
+    if (N > (int64_t)kKeyMask) return fail(h, DSS_ERR_ARG, "too many particles (ids must stay below 2^29)");
     const dss_params &p = h->prm;
     // host copies for validation and the lattice sizes
     std::vector<double> hx(3 * N), hr(N);
@@ -936,7 +949,8 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     HIPTRY(dalloc(&h->cell, N));
     HIPTRY(dalloc(&h->rank, N));
     HIPTRY(dalloc(&h->pairs, P.record_pairs ? 2 * P.pair_cap : 2));
-    HIPTRY(dalloc(&h->pair_count, 1));
+    HIPTRY(dalloc(&h->pair_count, 2));
+    h->hist_count = h->pair_count + 1;
     HIPTRY(dalloc(&h->clk, 1));
     HIPTRY(dalloc(&h->run, 1));
     HIPTRY(dalloc(&h->sigma_last, 9 * (size_t)B));
@@ -1001,7 +1015,7 @@ dss_status dss_set_particles(dss_handle *h, int64_t N, const double *x, const do
 {
     if (!h) return DSS_ERR_ARG;
     if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "a batch handle takes dss_set_particles_batch");
-    if (N < 1 || N > (int64_t)0x3fffffff || !x || !radius) return fail(h, DSS_ERR_ARG, "N < 1 or null x / radius");
+    if (N < 1 || N > (int64_t)kKeyMask || !x || !radius) return fail(h, DSS_ERR_ARG, "N < 1 or null x / radius");
     return dss_set_particles_batch(h, &N, x, radius, u, omega, on_device);
 }
 
@@ -1059,8 +1073,15 @@ dss_status dss_build_neighbours(dss_handle *h)
 {
     dss_status s = require_loaded(h);
     if (s) return s;
-    // a rebuild is an evaluation without time advance; its forces equal the current ones
-    return dss_compute_forces(h);
+    if (h->tune_pending) {
+        // a new lattice takes effect at this counting sort
+        s = setup_lattice(h);
+        if (s) return s;
+        h->tune_pending = false;
+    }
+    s = evaluate(h, EVAL_RESORT);
+    if (s) return s;
+    return check_flags(h);
 }
 
 dss_status dss_compute_forces(dss_handle *h)
@@ -1264,14 +1285,15 @@ static dss_status export_history(dss_handle *h, int64_t cap, int32_t *pairs, dou
     const int64_t room = std::max<int64_t>(cap, 1);
     HIPTRY(dalloc(&dp, 2 * room));
     HIPTRY(dalloc(&dxv, 3 * room));
-    HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
+    // its own counter: the listed-pair count of the last evaluation stays for dss_get_pairs
+    HIPTRY(hipMemsetAsync(h->hist_count, 0, sizeof(unsigned long long), h->stream));
     const int grid = (int)((h->N + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_history_export, dim3(grid), dim3(kBlock), 0, h->stream, (int)h->N, h->P.M, h->hown[h->hh],
                        h->hkey[h->hh], rolling ? h->hxr[h->hh] : h->hxi[h->hh], h->hcnt[h->hh], (long long)cap, dp,
-                       dxv, h->pair_count);
+                       dxv, h->hist_count);
     HIPTRY(hipGetLastError());
     unsigned long long cnt = 0;
-    HIPTRY(hipMemcpyAsync(&cnt, h->pair_count, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipMemcpyAsync(&cnt, h->hist_count, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
     HIPTRY(hipStreamSynchronize(h->stream));
     *n = (int64_t)cnt;
     dss_status r = DSS_OK;

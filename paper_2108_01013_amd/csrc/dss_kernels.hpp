@@ -27,9 +27,11 @@ constexpr unsigned kErrRowOverflow = 1u;
 constexpr unsigned kErrNonFinite = 2u;
 constexpr unsigned kErrPairBuffer = 4u;
 
-// A history entry's key is the partner id (below 2^30) with bit 30 set when the contact's
-// Coulomb cap was active at the step that wrote it (read by the adjoint).
-constexpr int kKeyMask = 0x3fffffff;
+// A history entry's key is the partner id (below 2^29) with bit 30 set when the contact's
+// Coulomb cap was active at the step that wrote it and bit 29 when its rolling limit was (the
+// stick/slip branch of the step, read by the adjoint).
+constexpr int kKeyMask = 0x1fffffff;
+constexpr int kRollCapBit = 0x20000000;
 constexpr int kCapBit = 0x40000000;
 
 // Physical constants and capacities shared by all boxes of a handle.
@@ -602,6 +604,7 @@ struct PairOut {
     double xr[3];   // new rolling stretch (no orientation), with rolling resistance
     bool contact;
     bool capped;    // the Coulomb cap rescaled the stretch
+    bool rcapped;   // the rolling limit rescaled the rolling stretch
 };
 
 // Arithmetic of the pair physics in type Real: double (FP64 mode) or float (mixed mode).
@@ -759,6 +762,7 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
     Real FCx = 0, FCy = 0, FCz = 0;
     o.contact = h_d < 0.0;
     o.capped = false;
+    o.rcapped = false;
     o.xi[0] = o.xi[1] = o.xi[2] = 0.0;
     if (o.contact) {
         // true relative velocity of the image pair: ambient difference gd r_y along x
@@ -831,6 +835,7 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
                 rx *= sc;
                 ry *= sc;
                 rz *= sc;
+                o.rcapped = true;
             }
             o.xr[0] = rx;
             o.xr[1] = ry;
@@ -869,33 +874,73 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
 }
 
 // ----------------------------------------------------------------------------------
-// History lookup: row of the particle that was at sorted slot p in the previous
-// evaluation; rows are sorted by partner id, so the scan stops at the first larger key.
+// History lookup (Sec. 2.1, memory paragraph: a stored stretch is sought over the sorted row).
+// The row of the particle at sorted slot p of the previous evaluation holds n = hcnt[p]
+// entries sorted by partner id.  The first kRowHead keys are read together with the count
+// (independent loads, in flight at once, clamped into the row's capacity); a key beyond them,
+// in a row longer than kRowHead, is found by bisection over the sorted rest.
 // ----------------------------------------------------------------------------------
+constexpr int kRowHead = 8;
+
+struct RowHead {
+    int n;
+    int key[kRowHead];
+};
+
+__device__ __forceinline__ void row_head(const int *__restrict__ hkey, const int *__restrict__ hcnt, int M, int p,
+                                         RowHead &r)
+{
+    const int *kr = hkey + (long long)p * M;
+#pragma unroll
+    for (int k = 0; k < kRowHead; ++k) r.key[k] = kr[k < M ? k : M - 1];
+    r.n = hcnt[p];
+}
+
+// Entry index of partner `key` in the row read into r (row of slot p), or -1.
+__device__ __forceinline__ int row_index(const int *__restrict__ hkey, int M, int p, const RowHead &r, int key)
+{
+    int idx = -1;
+#pragma unroll
+    for (int k = 0; k < kRowHead; ++k)
+        if (k < r.n && (r.key[k] & kKeyMask) == key) idx = k;
+    if (idx < 0 && r.n > kRowHead && (r.key[kRowHead - 1] & kKeyMask) < key) {
+        const int *kr = hkey + (long long)p * M;
+        int lo = kRowHead, hi = r.n;   // the key, if present, is in [lo, hi)
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const int km = kr[mid] & kKeyMask;
+            if (km == key) {
+                idx = mid;
+                break;
+            }
+            if (km < key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+    }
+    return idx;
+}
+
 __device__ __forceinline__ bool row_find(const int *__restrict__ hkey, const double *__restrict__ hxi,
                                          const int *__restrict__ hcnt, int M, int p, int key, double out[3],
                                          const double *__restrict__ hxr = nullptr, double *outr = nullptr)
 {
-    const int n = hcnt[p];
-    const int *kr = hkey + (long long)p * M;
-    for (int k = 0; k < n; ++k) {
-        const int kk = kr[k] & kKeyMask;
-        if (kk == key) {
-            const double *x = hxi + ((long long)p * M + k) * 3;
-            out[0] = x[0];
-            out[1] = x[1];
-            out[2] = x[2];
-            if (hxr) {
-                const double *y = hxr + ((long long)p * M + k) * 3;
-                outr[0] = y[0];
-                outr[1] = y[1];
-                outr[2] = y[2];
-            }
-            return true;
-        }
-        if (kk > key) break;
+    RowHead r;
+    row_head(hkey, hcnt, M, p, r);
+    const int k = row_index(hkey, M, p, r, key);
+    if (k < 0) return false;
+    const double *x = hxi + ((long long)p * M + k) * 3;
+    out[0] = x[0];
+    out[1] = x[1];
+    out[2] = x[2];
+    if (hxr) {
+        const double *y = hxr + ((long long)p * M + k) * 3;
+        outr[0] = y[0];
+        outr[1] = y[1];
+        outr[2] = y[2];
     }
-    return false;
+    return true;
 }
 
 struct HistView {
@@ -960,15 +1005,31 @@ __device__ __forceinline__ void evaluate_pair(const DevParams &P, double gd, dou
     double xro[3] = {0.0, 0.0, 0.0};  // the rolling stretch has no orientation
     const double dist = sqrt(r2);
     if (dist - Xi.w - Xj.w < 0.0) {
+        // the stored stretch is in the row of i (partner j) or, when the owner changed with the
+        // cells, in the row of j (partner i): both row heads are read at once
         const int pi_ = H.prev ? H.prev[gi] : gi;
         const int pj_ = H.prev ? H.prev[gj] : gj;
-        const double *hr = Roll ? H.xr_old : nullptr;
-        bool found = row_find(H.key_old, H.xi_old, H.cnt_old, P.M, pi_, idj, xo, hr, xro);
-        if (!found) found = row_find(H.key_old, H.xi_old, H.cnt_old, P.M, pj_, idi, xo, hr, xro);
-        if (found && idi > idj) {
-            xo[0] = -xo[0];
-            xo[1] = -xo[1];
-            xo[2] = -xo[2];
+        RowHead ri, rj;
+        row_head(H.key_old, H.cnt_old, P.M, pi_, ri);
+        row_head(H.key_old, H.cnt_old, P.M, pj_, rj);
+        int p = pi_;
+        int k = row_index(H.key_old, P.M, pi_, ri, idj);
+        if (k < 0) {
+            p = pj_;
+            k = row_index(H.key_old, P.M, pj_, rj, idi);
+        }
+        if (k >= 0) {
+            const double sg = idi > idj ? -1.0 : 1.0;
+            const double *x = H.xi_old + ((long long)p * P.M + k) * 3;
+            xo[0] = sg * x[0];
+            xo[1] = sg * x[1];
+            xo[2] = sg * x[2];
+            if constexpr (Roll) {
+                const double *y = H.xr_old + ((long long)p * P.M + k) * 3;
+                xro[0] = y[0];
+                xro[1] = y[1];
+                xro[2] = y[2];
+            }
         }
     }
     pair_physics<Real, Roll, Wave>(P, gd, wk, dx, dy, dz, dist, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, xro, S, o);
@@ -992,7 +1053,7 @@ __device__ __forceinline__ void store_history(const HistView &H, int M, int gi, 
 {
     if (slot < M) {
         const double sg = idi < idj ? 1.0 : -1.0;
-        H.key_new[(long long)gi * M + slot] = idj | (o.capped ? kCapBit : 0);
+        H.key_new[(long long)gi * M + slot] = idj | (o.capped ? kCapBit : 0) | (o.rcapped ? kRollCapBit : 0);
         if constexpr (Roll) {
             double *y = H.xr_new + ((long long)gi * M + slot) * 3;
             y[0] = o.xr[0];
@@ -1008,9 +1069,57 @@ __device__ __forceinline__ void store_history(const HistView &H, int M, int gi, 
     }
 }
 
+// Heap sort of the n entries of a history row by partner id, in place: O(n log n) key
+// reads and entry moves (partner ids in a row are distinct).  The stretches, and the rolling
+// stretches when rrow is set, move with their keys.
+template <bool Roll>
+__device__ __forceinline__ void heap_sort_row(int *krow, double *xrow, double *rrow, int n)
+{
+    auto swap_e = [&](int a, int b) {
+        const int tk = krow[a];
+        krow[a] = krow[b];
+        krow[b] = tk;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double tx = xrow[3 * a + c];
+            xrow[3 * a + c] = xrow[3 * b + c];
+            xrow[3 * b + c] = tx;
+            if constexpr (Roll) {
+                const double ty = rrow[3 * a + c];
+                rrow[3 * a + c] = rrow[3 * b + c];
+                rrow[3 * b + c] = ty;
+            }
+        }
+    };
+    // sift the entry at `root` down the max-heap of the first `end` entries
+    auto sift = [&](int root, int end) {
+        int kr = krow[root] & kKeyMask;
+        for (;;) {
+            int c = 2 * root + 1;
+            if (c >= end) break;
+            int kc = krow[c] & kKeyMask;
+            if (c + 1 < end) {
+                const int k2 = krow[c + 1] & kKeyMask;
+                if (k2 > kc) {
+                    ++c;
+                    kc = k2;
+                }
+            }
+            if (kr >= kc) break;
+            swap_e(root, c);
+            root = c;
+        }
+    };
+    for (int r = n / 2 - 1; r >= 0; --r) sift(r, n);
+    for (int e = n - 1; e > 0; --e) {
+        swap_e(0, e);
+        sift(0, e);
+    }
+}
+
 // Sort history row gi by partner id and publish it (the per-row sort of the contact
 // map).  Rows of up to 8 entries are sorted in registers (odd-even transposition on
-// (key, index), then one permuted copy); longer rows by insertion in place.  With rolling
+// (key, index), then one permuted copy); longer rows by a heap sort in place.  With rolling
 // resistance the rolling stretches move with their entries.
 template <bool Roll = false>
 __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int fill, int idi)
@@ -1072,38 +1181,7 @@ __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int
                 xrow[3 * a + 2] = x[a][2];
             }
     } else if (nrow > 8) {
-        for (int a = 1; a < nrow; ++a) {
-            int key = krow[a];
-            double x0 = xrow[3 * a], x1 = xrow[3 * a + 1], x2 = xrow[3 * a + 2];
-            double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-            if constexpr (Roll) {
-                y0 = rrow[3 * a];
-                y1 = rrow[3 * a + 1];
-                y2 = rrow[3 * a + 2];
-            }
-            int b = a - 1;
-            while (b >= 0 && (krow[b] & kKeyMask) > (key & kKeyMask)) {
-                krow[b + 1] = krow[b];
-                xrow[3 * (b + 1)] = xrow[3 * b];
-                xrow[3 * (b + 1) + 1] = xrow[3 * b + 1];
-                xrow[3 * (b + 1) + 2] = xrow[3 * b + 2];
-                if constexpr (Roll) {
-                    rrow[3 * (b + 1)] = rrow[3 * b];
-                    rrow[3 * (b + 1) + 1] = rrow[3 * b + 1];
-                    rrow[3 * (b + 1) + 2] = rrow[3 * b + 2];
-                }
-                --b;
-            }
-            krow[b + 1] = key;
-            xrow[3 * (b + 1)] = x0;
-            xrow[3 * (b + 1) + 1] = x1;
-            xrow[3 * (b + 1) + 2] = x2;
-            if constexpr (Roll) {
-                rrow[3 * (b + 1)] = y0;
-                rrow[3 * (b + 1) + 1] = y1;
-                rrow[3 * (b + 1) + 2] = y2;
-            }
-        }
+        heap_sort_row<Roll>(krow, xrow, rrow, nrow);
     }
     H.cnt_new[gi] = nrow;
     H.own_new[gi] = idi;
@@ -1744,6 +1822,40 @@ __global__ void __launch_bounds__(1024) k_finish(const BoxParams *__restrict__ b
             }
         } else {
             run->box_diag[3 * b + (t - 9)] = x;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// k_history_move: after a counting sort without time advance, the committed contact history
+// follows its particles to their new slots: row q of the new buffers = row prev[q] of the
+// old ones (keys, stretches, rolling stretches when xr_old is set, fill, owner id).
+// ----------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_history_move(int N, int M, const int *__restrict__ prev,
+                                                          const int *__restrict__ key_old,
+                                                          const double *__restrict__ xi_old,
+                                                          const double *__restrict__ xr_old,
+                                                          const int *__restrict__ cnt_old,
+                                                          const int *__restrict__ own_old, int *__restrict__ key_new,
+                                                          double *__restrict__ xi_new, double *__restrict__ xr_new,
+                                                          int *__restrict__ cnt_new, int *__restrict__ own_new)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    const int p = prev[q];
+    const int n = cnt_old[p];
+    cnt_new[q] = n;
+    own_new[q] = own_old[p];
+    for (int k = 0; k < n; ++k) {
+        const long long src = (long long)p * M + k, dst = (long long)q * M + k;
+        key_new[dst] = key_old[src];
+        xi_new[3 * dst] = xi_old[3 * src];
+        xi_new[3 * dst + 1] = xi_old[3 * src + 1];
+        xi_new[3 * dst + 2] = xi_old[3 * src + 2];
+        if (xr_old) {
+            xr_new[3 * dst] = xr_old[3 * src];
+            xr_new[3 * dst + 1] = xr_old[3 * src + 1];
+            xr_new[3 * dst + 2] = xr_old[3 * src + 2];
         }
     }
 }

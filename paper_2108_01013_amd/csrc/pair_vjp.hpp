@@ -71,12 +71,14 @@ DSS_HD inline void vaxpy(double s, const double a[3], double out[3])
     out[2] += s * a[2];
 }
 
-// g must be zero on entry; val may be null.  force_contact / force_capped: the branch to
-// differentiate (0 or 1, as decided by the forward run), or -1 to decide it here.
+// g must be zero on entry; val may be null.  force_contact / force_capped / force_rcapped: the
+// branch to differentiate (0 or 1, as decided by the forward run: contact, Coulomb cap, rolling
+// limit), or -1 to decide it here.
 DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], double ai, double aj, double yi,
                             double yj, const double ui[3], const double uj[3], const double Wi[3], const double Wj[3],
                             const double xo[3], const PairBar &bar, PairGrad &g, PairVal *val,
-                            int force_contact = -1, int force_capped = -1, const double *xro = nullptr)
+                            int force_contact = -1, int force_capped = -1, const double *xro = nullptr,
+                            int force_rcapped = -1)
 {
     // ------------------------------------------------------------------ primal
     const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -186,7 +188,7 @@ DSS_HD inline void pair_vjp(const PairConst &C, double gd, const double r[3], do
             for (int k = 0; k < 3; ++k) prr[k] = qrr[k] - qrn * n[k];
             capr = C.mu_r * fabs(fn) / C.kr;
             prm = sqrt(vdot(prr, prr));
-            rcapped = prm >= capr && prm > 0.0;
+            rcapped = (force_rcapped >= 0 ? force_rcapped != 0 : prm >= capr) && prm > 0.0;
             rsc = rcapped ? capr / prm : 1.0;
             for (int k = 0; k < 3; ++k) {
                 xrr[k] = rsc * prr[k];

@@ -17,13 +17,14 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_roofline_entry():
-    """The roofline entry prices one launch at its compulsory bytes over the measured average
-    launch time, against the 8 TB/s HBM peak; traffic only for the row-tile kernel."""
+    """The roofline entry prices one launch at its algorithmic bytes (140 B per particle, 56 B per
+    contact) over the measured average launch time, against the 8 TB/s HBM peak; traffic only for
+    the row-tile kernel."""
     sys.path.insert(0, ROOT)
     import bench
     N, ncell, contacts = 100_000, 33 ** 3, 38_875
     b = bench.pairs_kernel_bytes(N, ncell, contacts, 37)
-    assert b == N * 176 + 4 * (ncell + 1) + 56 * contacts
+    assert b == N * 140 + 56 * contacts
     timing = {"k_pairs": (50 * 0.05, 50)}         # 50 launches of 50 us (ms total, launches)
     r = bench.roofline(timing, N, ncell, contacts, 37, traffic=4.9e7)
     assert abs(r["avg_launch_us"] - 50.0) < 1e-9

@@ -3,7 +3,8 @@ differences of the FP64 oracle's stress objective J = mean_samples(Sigma_xy).
 
 The derivative is that of the run with its pair set, contact states and Coulomb-cap states
 held fixed, so every finite difference is checked to stay on the unperturbed run's branch
-(same listed-pair counts and contact sets at every step).  Window: N = 400 bidisperse
+(same listed-pair counts, contact sets and stick/slip states of every contact at every step,
+from the oracle's branch record).  Window: N = 400 bidisperse
 spheres at phi = 0.52, mu = 0.1 (sliding contacts, so dJ/dmu != 0), 20 steps, stress every 5,
 checkpoints every 7 steps (segments of 7, 7, 6: the segment boundaries and a ragged last
 segment are crossed)."""
@@ -145,7 +146,7 @@ def ec_objective(p, x0, rad, u0, w0, W, K=20, se=5):
     samples, br = [], [gate_counts(p, st.x, rad, 0)]
     for n in range(1, K + 1):
         st, F, T, S, npairs, _ = oracle.step(p, st, use_cells=True)
-        br.append((npairs, st.history.pairs.tobytes(), gate_counts(p, st.x, rad, n)))
+        br.append((npairs, st.history.pairs.tobytes(), st.history.capped.tobytes(), gate_counts(p, st.x, rad, n)))
         if n % se == 0:
             samples.append(np.asarray(S).reshape(3, 3))
     return float(np.sum(W * np.mean(samples, axis=0))), br
@@ -158,9 +159,8 @@ def test_adjoint_ec_ranges_vs_oracle_fd(window):
     oracle's objective.  N = 4000 at phi = 0.45, so that the lattice of the longer cutoff still
     has 4 x 3 x 3 cells; mu = 1 (the sliding contacts are the window's concern).  The
     forces jump at the edges of the ranges, so the branch record of the finite differences
-    also holds the number of pairs inside each range at every evaluation; at this size a
-    direction can also cross a stick-slip switch of a Coulomb cap, so a difference is kept
-    only when two step sizes agree."""
+    also holds the number of pairs inside each range at every evaluation, beside the contact
+    sets and the stick/slip state of every contact."""
     _, _, _, _, W = window
     w = synth.bidisperse_box(4000, 0.45, seed=23)
     p = dict(w.params, mu=1.0, ec_ranges=1, hamaker=2e-3)
@@ -181,17 +181,7 @@ def test_adjoint_ec_ranges_vs_oracle_fd(window):
             vals.append(J)
         return (vals[0] - vals[1]) / (2 * eps)
 
-    def fd_ec(perturb, eps):
-        """Central difference at eps, kept only if the one at eps / 3 agrees: a contact that
-        switches between stick and slip at its Coulomb cap within the step (a kink of J that
-        the branch record does not hold) makes the two differ."""
-        g1 = central(perturb, eps)
-        g2 = central(perturb, eps / 3.0) if g1 is not None else None
-        if g1 is None or g2 is None or abs(g1 - g2) > 2e-6 * abs(g1) + 1e-7:
-            return None
-        return g1
-
-    g = fd_ec(lambda e: (dict(p, F_ER=p["F_ER"] + e), w.x, u0, w0), EPS["F_ER"])
+    g = central(lambda e: (dict(p, F_ER=p["F_ER"] + e), w.x, u0, w0), EPS["F_ER"])
     assert g is not None, "finite difference left the branch of the run"
     say(f"d J / d F_ER: adjoint {r['dF_ER']:.10e}  oracle FD {g:.10e}")
     assert abs(r["dF_ER"] - g) <= 1e-3 * abs(g) + 1e-8
@@ -206,7 +196,7 @@ def test_adjoint_ec_ranges_vs_oracle_fd(window):
         moved = rng.choice(len(w.rad), 40, replace=False)
         v[moved] = rng.normal(size=(40, 3))
         v[np.any((w.x < 1e-4) | (w.x > L - 1e-4), axis=1)] = 0.0
-        gx = fd_ec(lambda e: (p, w.x + e * v, u0, w0), EPS["x"])
+        gx = central(lambda e: (p, w.x + e * v, u0, w0), EPS["x"])
         if gx is None:
             say(f"direction {d}: a pair crosses a cutoff, a range edge or a Coulomb cap; skipped")
             continue
@@ -222,9 +212,8 @@ def test_adjoint_rolling_resistance_vs_oracle_fd(window):
     dJ/dmu and two directions each of dJ/dx0 and dJ/dw0 against central differences of the
     oracle's objective.  The rolling stretch is carried from step to step like the tangential
     one, so its adjoint crosses every step and every checkpoint segment; on this window rolling
-    moves dJ/dw0 by about 2 %, far above the tolerance.  A rolling spring
-    can reach its Coulomb limit within a finite difference (a kink that the branch record does
-    not hold), so a difference is kept only when two step sizes agree."""
+    moves dJ/dw0 by about 2 %, far above the tolerance.  The branch record holds whether each
+    rolling spring is at its Coulomb limit, beside the tangential stick/slip state."""
     w, p0, u0, w0, W = window
     p = dict(p0, kr=0.5 * p0["kn"], mu_r=0.1)
     say("case: adjoint with rolling resistance N=400")
@@ -244,14 +233,7 @@ def test_adjoint_rolling_resistance_vs_oracle_fd(window):
             vals.append(J)
         return (vals[0] - vals[1]) / (2 * eps)
 
-    def fd_two(perturb, eps):
-        g1 = central(perturb, eps)
-        g2 = central(perturb, eps / 3.0) if g1 is not None else None
-        if g1 is None or g2 is None or abs(g1 - g2) > 2e-6 * abs(g1) + 1e-7:
-            return None
-        return g1
-
-    g = fd_two(lambda e: (dict(p, mu=p["mu"] + e), w.x, u0, w0), EPS["mu"])
+    g = central(lambda e: (dict(p, mu=p["mu"] + e), w.x, u0, w0), EPS["mu"])
     assert g is not None, "finite difference left the branch of the run"
     say(f"d J / d mu: adjoint {r['dmu']:.10e}  oracle FD {g:.10e}")
     assert abs(r["dmu"] - g) <= 1e-5 * abs(g) + 1e-8
@@ -269,8 +251,8 @@ def test_adjoint_rolling_resistance_vs_oracle_fd(window):
             else:
                 pert = lambda e: (p, w.x, u0, w0 + e * v)  # noqa: E731
             # dJ/dw0 along a direction is ~1e-2 against J ~ 12: a step of 1e-5 keeps the rounding
-            # noise of J below the two-step agreement
-            gv = fd_two(pert, EPS[which] if which == "x" else 1e-5)
+            # noise of J (~1e-13) far below the tolerance
+            gv = central(pert, EPS[which] if which == "x" else 1e-5)
             if gv is None:
                 say(f"d{which} direction {d}: a pair crosses a cutoff or a Coulomb limit; skipped")
                 continue
@@ -367,11 +349,102 @@ def test_adjoint_mixed_forward(window):
     assert abs(r["J"] - J0) <= 1e-5 * abs(J0)
     g = fd(p, w, u0, w0, W, br0, lambda e: (dict(p, mu=p["mu"] + e), w.x, u0, w0), EPS["mu"])
     assert g is not None and abs(r["dmu"] - g) <= 1e-4 * abs(g)
-    v = np.random.default_rng(9).normal(size=w.x.shape)
+    rng = np.random.default_rng(9)
     L = np.array(p["L"])
-    v[np.any((w.x < 1e-4) | (w.x > L - 1e-4), axis=1)] = 0.0
-    g = fd(p, w, u0, w0, W, br0, lambda e: (p, w.x + e * v, u0, w0), EPS["x"])
-    if g is not None:
+    checked = 0
+    for d in range(8):
+        v = rng.normal(size=w.x.shape)
+        v[np.any((w.x < 1e-4) | (w.x > L - 1e-4), axis=1)] = 0.0
+        g = fd(p, w, u0, w0, W, br0, lambda e: (p, w.x + e * v, u0, w0), EPS["x"])
+        if g is None:
+            say(f"mixed forward: direction {d} leaves the branch; skipped")
+            continue
         ad = float(np.sum(r["dx"] * v))
         say(f"mixed forward: d J / d x0 . v adjoint {ad:.8e} oracle FD {g:.8e}")
         assert abs(ad - g) <= 1e-4 * abs(g)
+        checked += 1
+        break
+    assert checked == 1
+
+
+def test_adjoint_config5_vs_oracle_fd():
+    """The adjoint workload at its full size: N = 50k bidisperse spheres at phi = 0.56, a 20-step
+    window from the relaxed packing (stress every 10, checkpoints every 10, so a segment boundary
+    is crossed).  J, dJ/dmu, dJ/dF_ER and one localized direction of dJ/dx0 (40 particles moved)
+    against central finite differences of the FP64 oracle at eps = 1e-6, each kept only when
+    both perturbed runs stay on the unperturbed run's branch (pair sets, contact sets and the
+    stick/slip state of every contact at every step; a smaller eps is tried when one does not).
+    Both forward precisions: FP64 (tolerance 1e-5) and mixed (FP32 pair arithmetic, tolerance
+    1e-4; the gradient is that of the mixed run's own trajectory).  A central difference cannot
+    resolve a derivative below the rounding of J itself: each bound adds 4 ulp(J) / (2 eps)
+    (J ~ 17 and eps = 1e-6 give 7e-9, about 3e-5 of dJ/dF_ER ~ 2.6e-4), and dJ/dF_ER is also
+    checked at eps = 1e-4 (resolution 7e-11), where the 1e-5 bound is far above the noise."""
+    from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Simulation
+    w = synth.bidisperse_box(50_000, 0.56, seed=5)
+    p = w.params
+    u0 = oracle.ambient_velocity(p, w.x)
+    w0 = oracle.ambient_rotation(p, len(w.rad))
+    W = np.zeros((3, 3))
+    W[0, 1] = 1.0
+    K, se, C = 20, 10, 10
+    say("case: adjoint N=50000 phi=0.56, 20-step window, FP64 and mixed forward")
+    res = {}
+    for prec in (DSS_FP64, DSS_MIXED):
+        sim = Simulation(p, precision=prec)
+        sim.set_particles(w.x, w.rad, u0, w0)
+        res[prec] = sim.adjoint(K, se, C, W)
+        sim.close()
+    J0, br0 = oracle.stress_objective(p, w.x, w.rad, u0, w0, K, se, W, use_cells=True)
+    say(f"J: oracle {J0:.12e}  FP64 {res[DSS_FP64]['J']:.12e}  mixed {res[DSS_MIXED]['J']:.12e}")
+    assert abs(res[DSS_FP64]["J"] - J0) <= 1e-10 * abs(J0)
+    assert abs(res[DSS_MIXED]["J"] - J0) <= 1e-5 * abs(J0)
+    n_slip = sum(int(np.count_nonzero(np.frombuffer(b[2], np.int32) & 1)) for b in br0)
+    say(f"sliding contact-steps in the window: {n_slip}")
+    assert n_slip > 0          # else dJ/dmu would vanish identically
+
+    def central(perturb, steps=(1e-6, 2.5e-7, 6.25e-8)):
+        for eps in steps:
+            vals = []
+            for sgn in (1.0, -1.0):
+                pp, x = perturb(sgn * eps)
+                J, br = oracle.stress_objective(pp, x, w.rad, u0, w0, K, se, W, use_cells=True)
+                if br != br0:
+                    break
+                vals.append(J)
+            if len(vals) == 2:
+                return (vals[0] - vals[1]) / (2 * eps), eps
+            say(f"eps {eps:g}: a perturbed run leaves the branch")
+        return None, None
+
+    def check(name, ad, g, eps):
+        noise = 4.0 * float(np.spacing(abs(J0))) / (2.0 * eps)
+        e64 = abs(ad[DSS_FP64] - g)
+        emx = abs(ad[DSS_MIXED] - g)
+        say(f"{name}: oracle FD {g:.10e} (eps {eps:g}, resolution {noise:.1e})  FP64 {ad[DSS_FP64]:.10e} "
+            f"(rel {e64 / abs(g):.2e})  mixed {ad[DSS_MIXED]:.10e} (rel {emx / abs(g):.2e})")
+        assert e64 <= 1e-5 * abs(g) + noise, (name, e64)
+        assert emx <= 1e-4 * abs(g) + noise, (name, emx)
+
+    for name, key in (("mu", "dmu"), ("F_ER", "dF_ER")):
+        g, eps = central(lambda e: (dict(p, **{name: p[name] + e}), w.x))
+        assert g is not None, name
+        check("dJ/d" + name, {k: v[key] for k, v in res.items()}, g, eps)
+    g, eps = central(lambda e: (dict(p, F_ER=p["F_ER"] + e), w.x), steps=(1e-4, 2.5e-5))
+    assert g is not None
+    check("dJ/dF_ER", {k: v["dF_ER"] for k, v in res.items()}, g, eps)
+    rng = np.random.default_rng(41)
+    L = np.array(p["L"])
+    checked = 0
+    for d in range(8):
+        v = np.zeros_like(w.x)
+        moved = rng.choice(len(w.rad), 40, replace=False)
+        v[moved] = rng.normal(size=(40, 3))
+        v[np.any((w.x < 1e-4) | (w.x > L - 1e-4), axis=1)] = 0.0
+        g, eps = central(lambda e: (p, w.x + e * v))
+        if g is None:
+            say(f"x0 direction {d}: leaves the branch; another 40 particles")
+            continue
+        check(f"dJ/dx0 . v (direction {d})", {k: float(np.sum(r["dx"] * v)) for k, r in res.items()}, g, eps)
+        checked += 1
+        break
+    assert checked == 1

@@ -234,6 +234,7 @@ def test_hooke_two_spheres():
     rad = np.array([ai, aj])
     F, T, S, H, npairs = oracle.forces(p, x, np.zeros((2, 3)), np.zeros((2, 3)), rad, 0)
     assert npairs == 1 and len(H.pairs) == 1
+    assert list(H.capped) == [0]                       # a spring at rest sticks
     assert rel(F[0], -p["kn"] * delta * n) < 1e-9
     assert rel(F[1], p["kn"] * delta * n) < 1e-9
     expect = -(np.linalg.norm(r) * p["kn"] * delta / L ** 3) * np.outer(n, n)
@@ -261,6 +262,7 @@ def test_coulomb_sliding_sequence():
         expect = min(k * v * p["dt"], cap)
         capped_seen |= k * v * p["dt"] > cap
         assert out["contact"]
+        assert out["capped"] == (k * v * p["dt"] >= cap) and not out["rcapped"]   # the slip flag
         assert abs(xi[1] - expect) <= 1e-12 * cap and xi[0] == 0.0 and xi[2] == 0.0
         Ft = p["kt"] * xi
         assert rel(out["FC_i"], -p["kn"] * delta * n + Ft) < 1e-12
@@ -674,6 +676,7 @@ def test_rolling_spring_sequence():
         assert rel(e["TC_j"], -e["TC_i"]) < 1e-12                # only the rolling torque acts
         assert rel(e["TC_i"], e["TR_i"]) < 1e-12
         assert rel(e["FC_i"], p["kn"] * h * n) < 1e-11           # no rolling force (h from |r|)
+        assert e["rcapped"] == (k * np.linalg.norm(ur) * p["dt"] >= cap) and not e["capped"]
         saturated = saturated or want == cap
     assert saturated
 
