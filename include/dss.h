@@ -340,6 +340,17 @@ dss_status dss_observe(dss_handle *h, double out[4]);
  * the periodic y axis, over the slab volume; 1 <= nbins <= 2048, phi host (2 nbins). */
 dss_status dss_phi_profile(dss_handle *h, int32_t nbins, double a_split, double *phi);
 
+/* dss_phi_profile for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same profile, with no hipMalloc,
+ * hipFree or allocating library call.  Its partial profiles and their sums live in a device
+ * array of the library, 8 MiB per GPU, taken when the first handle is created on that GPU and
+ * held until the process ends; every call on one GPU shares it and leaves its last contents.
+ * Calls on the same GPU that overlap in time (two host threads, or two streams) race on it and
+ * must be serialised by the caller.  Particles are taken in workgroups of 256 over at most
+ * (2^20 - 2 nbins) / (2 nbins) workgroups, so any N fits; nbins beyond 2048 is DSS_ERR_ARG.
+ * phi: host, 2 nbins values as in dss_phi_profile (equal up to the order of the sums). */
+dss_status dss_phi_profile_noalloc(dss_handle *h, int32_t nbins, double a_split, double *phi);
+
 /* Clusters of contacting particles (Fig. histo): connected components of the graph of the
  * committed contacts (d_ij < 0 at the last step).  hist[s - 1] = number of clusters of s
  * particles for s < cap, hist[cap - 1] those of cap or more (isolated particles are clusters

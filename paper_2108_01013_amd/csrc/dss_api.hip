@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,39 @@
 #include "dss_observe.hpp"
 
 using namespace dss;
+
+// Device memory of the allocation-free entry point (dss_phi_profile_noalloc): a file-scope
+// array, one copy per GPU, held until the process ends.  Host code never passes its name to a
+// kernel or a copy (on the host the name is only a stand-in): the address of each device's
+// copy is taken once per device, with that device current, when a handle is created there.
+constexpr size_t kNoAllocDoubles = size_t(1) << 20;   // 8 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch (device current); 0 on success.
+hipError_t scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double *>(ptr);
+    return hipSuccess;
+}
+
+double *scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+}  // namespace
 
 struct dss_handle {
     dss_params prm{};          // parameters of box 0 (the physical constants of every box)
@@ -809,7 +843,7 @@ dss_status dss_create_batch(const dss_params *per_box, int32_t n_boxes, void *hi
     h->prm = per_box[0];
     h->nbox = n_boxes;
     h->bprm.assign(per_box, per_box + n_boxes);
-    if (hipGetDevice(&h->device) != hipSuccess) {
+    if (hipGetDevice(&h->device) != hipSuccess || scratch_setup(h->device) != hipSuccess) {
         delete h;
         return DSS_ERR_HIP;
     }
@@ -2001,6 +2035,32 @@ dss_status dss_phi_profile(dss_handle *h, int32_t nbins, double a_split, double 
         for (int b = 0; b < grid; ++b) t += hp[(size_t)b * 2 * nbins + k];
         phi[k] = t / slab;
     }
+    return DSS_OK;
+}
+
+dss_status dss_phi_profile_noalloc(dss_handle *h, int32_t nbins, double a_split, double *phi)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (h->nbox != 1) return fail(h, DSS_ERR_ARG, "observables run on single-box handles");
+    if (nbins < 1 || nbins > 2048 || !phi) return fail(h, DSS_ERR_ARG, "nbins in [1, 2048] and phi non-null");
+    double *ptr = scratch_of(h->device);
+    if (!ptr) return fail(h, DSS_ERR_STATE, "no scratch address for this device");
+    const int m = 2 * nbins;
+    // partial profiles of at most (capacity - m) / m workgroups, then their sums, all in the scratch
+    const int64_t cover = (h->N + kBlock - 1) / kBlock;
+    const int64_t room = ((int64_t)kNoAllocDoubles - m) / m;
+    const int grid = (int)std::max<int64_t>(1, std::min(cover, room));
+    double *part = ptr, *sum = ptr + (size_t)grid * m;
+    const BoxParams &G = h->boxes[0];
+    hipLaunchKernelGGL(k_phi_profile, dim3(grid), dim3(kBlock), (size_t)m * sizeof(double), h->stream, (int)h->N,
+                       G.L[1], (int)nbins, a_split, h->pa[h->cur], part);
+    hipLaunchKernelGGL(k_phi_reduce, dim3((m + kBlock - 1) / kBlock), dim3(kBlock), 0, h->stream, part, grid, m, sum);
+    HIPTRY(hipGetLastError());
+    HIPTRY(hipMemcpyAsync(phi, sum, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPTRY(hipStreamSynchronize(h->stream));
+    const double slab = G.L[0] * G.L[2] * (G.L[1] / (double)nbins);
+    for (int k = 0; k < m; ++k) phi[k] = phi[k] / slab;
     return DSS_OK;
 }
 

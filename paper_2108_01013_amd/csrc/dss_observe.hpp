@@ -68,15 +68,15 @@ __device__ __forceinline__ double sphere_slab(double a, double z1, double z2)
 }
 
 // Local volume fraction along y: per-workgroup partial profiles (group 0: a <= a_split,
-// group 1: a > a_split), nb bins each, accumulated in LDS; part[blockIdx][2 nb].
+// group 1: a > a_split), nb bins each, accumulated in LDS; part[blockIdx][2 nb].  The
+// workgroups stride over the particles (one particle per lane when the grid covers N).
 __global__ void __launch_bounds__(kBlock) k_phi_profile(int N, double Ly, int nb, double a_split,
                                                          const double4 *__restrict__ pa, double *__restrict__ part)
 {
     extern __shared__ double hist[];  // 2 nb
     for (int k = threadIdx.x; k < 2 * nb; k += kBlock) hist[k] = 0.0;
     __syncthreads();
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < N) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
         const double4 X = pa[p];
         const double dy = Ly / (double)nb;
         const int g = X.w > a_split ? 1 : 0;
@@ -90,6 +90,18 @@ __global__ void __launch_bounds__(kBlock) k_phi_profile(int N, double Ly, int nb
     }
     __syncthreads();
     for (int k = threadIdx.x; k < 2 * nb; k += kBlock) part[(long long)blockIdx.x * 2 * nb + k] = hist[k];
+}
+
+// Sum of the nw partial profiles of k_phi_profile in workgroup order (the order the host sums
+// them in for dss_phi_profile): out[k] = sum_b part[b][k], k < m = 2 nb.
+__global__ void __launch_bounds__(kBlock) k_phi_reduce(const double *__restrict__ part, int nw, int m,
+                                                        double *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    double t = 0.0;
+    for (int b = 0; b < nw; ++b) t += part[(long long)b * m + k];
+    out[k] = t;
 }
 
 // Connected components of the contact graph by lock-free union-find over particle ids.

@@ -26,7 +26,7 @@ STATUS = {0: "DSS_OK", 1: "DSS_ERR_ARG", 2: "DSS_ERR_HIP", 3: "DSS_ERR_CAPACITY"
 
 EXPORTS = ["dss_create", "dss_create_batch", "dss_set_particles", "dss_set_particles_batch", "dss_set_step", "dss_build_neighbours", "dss_compute_forces", "dss_step",
            "dss_read_stress", "dss_read_stress_batch", "dss_get_box_info", "dss_get_state", "dss_get_eval_velocities", "dss_get_pairs", "dss_get_cells", "dss_get_rolling_history",
-           "dss_observe_start", "dss_observe", "dss_phi_profile", "dss_contact_clusters",
+           "dss_observe_start", "dss_observe", "dss_phi_profile", "dss_phi_profile_noalloc", "dss_contact_clusters",
            "dss_get_history", "dss_get_info", "dss_save_state", "dss_load_state", "dss_set_timing",
            "dss_get_timing", "dss_set_tuning", "dss_get_tuning", "dss_adjoint", "dss_last_error",
            "dss_status_string", "dss_destroy"]
@@ -109,6 +109,7 @@ def load_library():
         "dss_observe_start": (st, [H]),
         "dss_observe": (st, [H, vp]),
         "dss_phi_profile": (st, [H, ctypes.c_int32, ctypes.c_double, vp]),
+        "dss_phi_profile_noalloc": (st, [H, ctypes.c_int32, ctypes.c_double, vp]),
         "dss_contact_clusters": (st, [H, i64, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "dss_get_info": (st, [H, ctypes.POINTER(Info)]),
         "dss_save_state": (st, [H, vp, ctypes.POINTER(ctypes.c_size_t)]),
@@ -387,6 +388,13 @@ class Simulation:
         phi = np.zeros(2 * nbins)
         self._check(self.lib.dss_phi_profile(self.h, int(nbins), float(a_split), ctypes.c_void_p(phi.ctypes.data)))
         return phi.reshape(2, nbins)
+
+    def phi_profile_noalloc(self, nbins: int, a_split: float) -> np.ndarray:
+        """phi_profile through the entry point that allocates no device memory."""
+        phi = np.zeros(2 * int(nbins))
+        self._check(self.lib.dss_phi_profile_noalloc(self.h, int(nbins), float(a_split),
+                                                     ctypes.c_void_p(phi.ctypes.data)))
+        return phi.reshape(2, int(nbins))
 
     def contact_clusters(self, cap: int | None = None) -> np.ndarray:
         """Histogram of the sizes of clusters of contacting particles: h[s - 1] clusters of s."""
