@@ -91,6 +91,7 @@ struct dss_handle {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
+    int n_cu = 256;            // compute units of the device (workgroup slots of k_pairs: 4 per CU)
     std::string err;
 
     int64_t N = 0;
@@ -122,7 +123,6 @@ struct dss_handle {
     int64_t last_samples = 0;
     int scan_c4 = 1;           // int4 chunks per lane of the cell-count scan
     size_t tile_lds = 0;       // dynamic LDS bytes of a k_pairs workgroup
-    int finish_r = 1;          // partial records per lane of k_finish
 
     ForceBufs fb() const
     {
@@ -352,7 +352,7 @@ struct SizeClasses {
 // reaching a cell twice: n_x >= 2 R_max + 2 (the window of a sheared row), n_y, n_z >=
 // 2 R_max + 1.  Cells are numbered class-major: ncls x n_x n_y n_z sort keys.
 bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, double amin, double cf,
-                double rext, double cell_scale, bool sized, SizeClasses &sc, std::string &why)
+                double rext, double cell_scale, bool sized, int row_slots, SizeClasses &sc, std::string &why)
 {
     sc = SizeClasses{};
     if (sized) {
@@ -402,10 +402,16 @@ bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, 
         // max(c 2 a_max, 2 a_max + rext)
         const double cut = rext > 0.0 ? std::max(cf * 2.0 * amax[b], 2.0 * amax[b] + rext) : cf * 2.0 * amax[b];
         const double rc = cut * (1.0 + 1e-9) * cell_scale;
-        for (int d = 0; d < 3; ++d) {
-            G.nc[d] = std::max(1, (int)std::floor(G.L[d] / rc));
-            G.cw[d] = G.L[d] / (double)G.nc[d];
+        for (int d = 0; d < 3; ++d) G.nc[d] = std::max(1, (int)std::floor(G.L[d] / rc));
+        // one box whose cell rows exceed the k_pairs workgroup slots by a little: coarser cells
+        // along z (the vorticity direction, away from the sheared faces) until every row has a
+        // slot, so the rows run in one round instead of a nearly empty second one
+        if (boxes.size() == 1 && row_slots > 0) {
+            const int rows = G.nc[1] * G.nc[2];
+            if (rows > row_slots && rows * 100 <= row_slots * 115)
+                while (G.nc[1] * G.nc[2] > row_slots && G.nc[2] > 3) --G.nc[2];
         }
+        for (int d = 0; d < 3; ++d) G.cw[d] = G.L[d] / (double)G.nc[d];
         if (G.nc[0] < 4 || G.nc[1] < 3 || G.nc[2] < 3) {
             why = "cell lattice " + std::to_string(G.nc[0]) + "x" + std::to_string(G.nc[1]) + "x" +
                   std::to_string(G.nc[2]) + " of box " + std::to_string(b) + " is smaller than 4x3x3";
@@ -439,7 +445,7 @@ dss_status setup_lattice(dss_handle *h)
     SizeClasses sc;
     const bool sized = h->tune.sized != 0;
     if (!lattice_of(h->boxes, h->box_amax, h->a_min, h->prm.cutoff_factor, h->P.ec ? h->P.rext : 0.0,
-                    h->tune.cell_scale, sized, sc, why))
+                    h->tune.cell_scale, sized, h->tune.tiled ? 4 * h->n_cu : 0, sc, why))
         return fail(h, DSS_ERR_BOX, why);
     free_lattice(h);
     const int B = h->nbox;
@@ -501,10 +507,10 @@ dss_status setup_lattice(dss_handle *h)
     h->max_mean_row = max_mean_row;
     // row-tile capacities of k_pairs from the mean occupancy of a cell row (own row and the
     // five rows of the half shell) of the densest box, times tile_scale; rows beyond them
-    // take the per-particle path, which every row takes when tiling is off.  When the
-    // capacities can shrink to fit three workgroups per CU (160 KB of LDS) and still keep a
-    // margin of two standard deviations over the mean row occupancy, they do: latency
-    // hiding of the three-workgroup occupancy outweighs the few rows that fall back.
+    // take the per-particle path, which every row takes when tiling is off.  When capacities
+    // with a margin of two standard deviations over the mean row occupancy fit four
+    // workgroups per CU (40 KB of LDS each), they are taken: every cell row then has a slot
+    // of its own on a box of up to 4 x n_CU rows.
     DevParams &P = h->P;
     {
         const double mean_row = max_mean_row * h->tune.tile_scale;
@@ -512,16 +518,15 @@ dss_status setup_lattice(dss_handle *h)
         int own_cap = up(1.5 * mean_row + 16.0, 32);
         int stage_cap = up(6.25 * mean_row + 32.0, 64);
         int qcap = up(8.0 * mean_row + 64.0, 64);
-        const size_t lds_three = 160 * 1024 / 3 - 1024;
-        if (tile_lds_bytes(own_cap, stage_cap, qcap) > lds_three) {
-            const int own3 = up(1.3 * mean_row + 8.0, 32);
-            const int stage3 = up(5.0 * mean_row + 2.0 * std::sqrt(5.0 * mean_row), 32);
-            const int q3 = up(4.5 * mean_row + 64.0, 64);
-            if (tile_lds_bytes(own3, stage3, q3) <= lds_three) {
-                own_cap = own3;
-                stage_cap = stage3;
-                qcap = q3;
-            }
+        // (dynamic and static LDS are each allocated in blocks of up to 1 KB)
+        const size_t lds_four = 40 * 1024 - 1024;
+        const int own4 = up(1.3 * mean_row + 8.0, 32);
+        const int stage4 = up(5.0 * mean_row + 2.0 * std::sqrt(5.0 * mean_row), 32);
+        const int q4 = up(4.5 * mean_row + 64.0, 64);
+        if (tile_lds_bytes(own4, stage4, q4) <= lds_four) {
+            own_cap = own4;
+            stage_cap = stage4;
+            qcap = q4;
         }
         const size_t lds_max = 150 * 1024;
         while (tile_lds_bytes(own_cap, stage_cap, qcap) > lds_max && own_cap > 32) {
@@ -541,6 +546,19 @@ dss_status setup_lattice(dss_handle *h)
         P.tiled = h->tune.tiled ? 1 : 0;
         P.stage_cap = stage_cap;
         P.qcap = qcap;
+        // margin on r^2 of the FP32 candidate pre-test: FP32 coordinates and image shifts of
+        // magnitude up to 6 L round the components of r by at most 29, 10, 10 u L (u = 2^-24),
+        // so r^2 near the cutoff r_c moves by at most 2 r_c 49 u L, and the FP32 cutoff r_c^2
+        // by 6 u r_c^2; twice that bound over the largest box and cutoff
+        double lmax = 0.0, rcmax = 0.0;
+        for (int b = 0; b < B; ++b) {
+            const BoxParams &G = h->boxes[b];
+            lmax = std::max(lmax, std::max(G.L[0], std::max(G.L[1], G.L[2])));
+            const double a2 = 2.0 * h->box_amax[b];
+            rcmax = std::max(rcmax, P.ec ? std::max(h->prm.cutoff_factor * a2, a2 + P.rext) : h->prm.cutoff_factor * a2);
+        }
+        const double u = std::ldexp(1.0, -24);
+        P.pf_m2 = (float)(2.0 * (2.0 * rcmax * 49.0 * u * lmax + 6.0 * u * rcmax * rcmax));
     }
     for (const void *k :
          {(const void *)k_pairs<double, false, false, true>, (const void *)k_pairs<float, false, false, true>,
@@ -552,7 +570,6 @@ dss_status setup_lattice(dss_handle *h)
           (const void *)k_pairs<double, false, true, false>, (const void *)k_pairs<float, false, true, false>,
           (const void *)k_pairs<double, true, true, false>, (const void *)k_pairs<float, true, true, false>})
         HIPTRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->tile_lds));
-    h->finish_r = (max_rows_box + 1023) / 1024;
     P.pstride = (std::max(nrow, max_rows_box) + 63) / 64 * 64;
     HIPTRY(dalloc(&h->count, ncell_pad));
     HIPTRY(dalloc(&h->cell_start, ncell_pad));
@@ -596,7 +613,7 @@ void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
     }
     {
         TimedLaunch t(h, 3);
-        hipExtLaunchKernelGGL(k_pairs<Real, Roll, Wave, Sum>, dim3(h->nrow_total), dim3(kBlock), h->tile_lds, h->stream, t.e0,
+        hipExtLaunchKernelGGL(k_pairs<Real, Roll, Wave, Sum>, dim3(h->nrow_total), dim3(kPairBlock), h->tile_lds, h->stream, t.e0,
                               t.e1, 0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
                               h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, h->fb_rows,
                               h->fb_count);
@@ -651,17 +668,8 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, boo
     }
     if (!finish) return DSS_OK;
     TimedLaunch t(h, 4);
-#define DSS_FINISH(R)                                                                                           \
-    case R:                                                                                                     \
-        hipExtLaunchKernelGGL(k_finish<R>, dim3(h->nbox), dim3(1024), 0, h->stream, t.e0, t.e1, 0, h->d_boxes,  \
-                              h->partials, h->P.pstride, h->clk, h->run, sample);                       \
-        break;
-    switch (h->finish_r) {
-        DSS_FINISH(1) DSS_FINISH(2) DSS_FINISH(3) DSS_FINISH(4)
-    default:
-        return fail(h, DSS_ERR_BOX, "too many cell rows");
-    }
-#undef DSS_FINISH
+    hipExtLaunchKernelGGL(k_finish, dim3(12 * h->nbox), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->d_boxes,
+                          h->partials, h->P.pstride, h->clk, h->run, sample);
     return DSS_OK;
 }
 
@@ -843,7 +851,8 @@ dss_status dss_create_batch(const dss_params *per_box, int32_t n_boxes, void *hi
     h->prm = per_box[0];
     h->nbox = n_boxes;
     h->bprm.assign(per_box, per_box + n_boxes);
-    if (hipGetDevice(&h->device) != hipSuccess || scratch_setup(h->device) != hipSuccess) {
+    if (hipGetDevice(&h->device) != hipSuccess || scratch_setup(h->device) != hipSuccess ||
+        hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) {
         delete h;
         return DSS_ERR_HIP;
     }
@@ -950,7 +959,7 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
         std::string why;
         SizeClasses sc;
         if (!lattice_of(trial, box_amax, a_min, p.cutoff_factor, P.ec ? P.rext : 0.0, h->tune.cell_scale,
-                        h->tune.sized != 0, sc, why))
+                        h->tune.sized != 0, h->tune.tiled ? 4 * h->n_cu : 0, sc, why))
             return fail(h, DSS_ERR_BOX, why);
     }
 
@@ -1068,7 +1077,7 @@ dss_status dss_set_tuning(dss_handle *h, const dss_tuning *t)
         std::string why;
         SizeClasses sc;
         if (!lattice_of(trial, h->box_amax, h->a_min, h->prm.cutoff_factor, h->P.ec ? h->P.rext : 0.0,
-                        t->cell_scale, t->sized != 0, sc, why))
+                        t->cell_scale, t->sized != 0, t->tiled ? 4 * h->n_cu : 0, sc, why))
             return fail(h, DSS_ERR_BOX, why);
     }
     const bool lattice = t->cell_scale != h->tune.cell_scale || t->tile_scale != h->tune.tile_scale ||

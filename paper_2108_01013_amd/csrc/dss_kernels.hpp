@@ -57,6 +57,7 @@ struct DevParams {
     double rep_rng, att_rng;        // with ec: surface-distance ranges of repulsion and attraction
     double kr, mu_r;                // rolling spring stiffness and Coulomb coefficient (kr = 0: off)
     double wave_amp;                // amplitude W of the wavy shear, eq. uinf (0: simple shear)
+    float pf_m2;                    // margin on r^2 of the FP32 candidate pre-test of k_pairs
 };
 
 // One box: its geometry, shear rate, cell lattice and its ranges in the global numbering
@@ -167,43 +168,6 @@ __device__ __forceinline__ bool listed(const DevParams &P, double dx, double dy,
     double rc = P.cf * (aa + ab);
     if (P.ec) rc = fmax(rc, (aa + ab) + P.rext);
     return r2 < rc * rc;
-}
-
-// Listed test of a candidate whose periodic image is known: r = x_j - x_i plus the image
-// shifts (y face sy with its x offset sxd, x period sx, z period sz), added in the order of
-// the general formula, so that r2 is bit-identical to min_image + listed.
-__device__ __forceinline__ bool image_listed(const double4 &Xi, const double4 &Xj, double sy, double sxd, double sx,
-                                             double sz, double cf, double rext)
-{
-#pragma clang fp contract(off)
-    double dx = Xj.x - Xi.x, dy = Xj.y - Xi.y, dz = Xj.z - Xi.z;
-    dy = dy + sy;
-    dx = dx + sxd;
-    dx = dx + sx;
-    dz = dz + sz;
-    const double r2 = (dx * dx + dy * dy) + dz * dz;
-    double rc = cf * (Xi.w + Xj.w);
-    if (rext > 0.0) rc = fmax(rc, (Xi.w + Xj.w) + rext);
-    return r2 < rc * rc;
-}
-
-// image_listed with the contact guess of a listed pair: 0 not listed, 1 listed, 2 listed with
-// r2 < (a_i + a_j)^2.  The guess only orders the pair queue (contacts last, so the history
-// lookups and the contact springs run in few wavefronts); evaluate_pair decides contact.
-__device__ __forceinline__ int image_class(const double4 &Xi, const double4 &Xj, double sy, double sxd, double sx,
-                                           double sz, double cf, double rext)
-{
-#pragma clang fp contract(off)
-    double dx = Xj.x - Xi.x, dy = Xj.y - Xi.y, dz = Xj.z - Xi.z;
-    dy = dy + sy;
-    dx = dx + sxd;
-    dx = dx + sx;
-    dz = dz + sz;
-    const double r2 = (dx * dx + dy * dy) + dz * dz;
-    const double s = Xi.w + Xj.w;
-    double rc = cf * s;
-    if (rext > 0.0) rc = fmax(rc, s + rext);
-    return r2 < rc * rc ? (r2 < s * s ? 2 : 1) : 0;
 }
 
 __device__ __forceinline__ double pmass(const DevParams &P, double a)
@@ -943,6 +907,28 @@ __device__ __forceinline__ bool row_find(const int *__restrict__ hkey, const dou
     return true;
 }
 
+// Entry index of partner `key` in a row whose head h = (slot, count, key 0, key 1) was read
+// before, or -1: the first two entries from the head, the rest (sorted) by bisection.
+__device__ __forceinline__ int head_index(const int *__restrict__ hkey, int M, const int4 &h, int key)
+{
+    if (h.y > 0 && (h.z & kKeyMask) == key) return 0;
+    if (h.y > 1 && (h.w & kKeyMask) == key) return 1;
+    if (h.y > 2 && (h.w & kKeyMask) < key) {
+        const int *kr = hkey + (long long)h.x * M;
+        int lo = 2, hi = h.y;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const int km = kr[mid] & kKeyMask;
+            if (km == key) return mid;
+            if (km < key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+    }
+    return -1;
+}
+
 struct HistView {
     const int *key_old;    // rows of the committed history, at the slots of the last step
     const double *xi_old;
@@ -1118,8 +1104,8 @@ __device__ __forceinline__ void heap_sort_row(int *krow, double *xrow, double *r
 }
 
 // Sort history row gi by partner id and publish it (the per-row sort of the contact
-// map).  Rows of up to 8 entries are sorted in registers (odd-even transposition on
-// (key, index), then one permuted copy); longer rows by a heap sort in place.  With rolling
+// map).  Rows of up to 8 entries are read at once and sorted in registers (odd-even
+// transposition on the (key, stretch) tuples); longer rows by a heap sort in place.  With rolling
 // resistance the rolling stretches move with their entries.
 template <bool Roll = false>
 __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int fill, int idi)
@@ -1129,56 +1115,51 @@ __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int
     double *rrow = Roll ? H.xr_new + (long long)gi * M * 3 : nullptr;
     const int nrow = fill < M ? fill : M;
     if (nrow >= 2 && nrow <= 8) {
-        int key[8], idx[8];
+        // keys and stretches of the whole row read at once, sorted as tuples in registers
+        // (odd-even transposition), written back
+        int key[8];
+        double x[8][3], y[8][3];
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-            key[a] = a < nrow ? krow[a] : 0x7fffffff;
-            idx[a] = a;
+            const int e = a < nrow ? a : 0;
+            key[a] = a < nrow ? krow[e] : 0x7fffffff;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                x[a][c] = xrow[3 * e + c];
+                if constexpr (Roll) y[a][c] = rrow[3 * e + c];
+            }
         }
 #pragma unroll
         for (int round = 0; round < 8; ++round) {
 #pragma unroll
             for (int a = round & 1; a + 1 < 8; a += 2) {
                 if ((key[a] & kKeyMask) > (key[a + 1] & kKeyMask)) {
-                    int tk = key[a]; key[a] = key[a + 1]; key[a + 1] = tk;
-                    int ti = idx[a]; idx[a] = idx[a + 1]; idx[a + 1] = ti;
+                    const int tk = key[a];
+                    key[a] = key[a + 1];
+                    key[a + 1] = tk;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double tx = x[a][c];
+                        x[a][c] = x[a + 1][c];
+                        x[a + 1][c] = tx;
+                        if constexpr (Roll) {
+                            const double ty = y[a][c];
+                            y[a][c] = y[a + 1][c];
+                            y[a + 1][c] = ty;
+                        }
+                    }
                 }
             }
-        }
-        double x[8][3];
-#pragma unroll
-        for (int a = 0; a < 8; ++a)
-            if (a < nrow) {
-                const double *q = xrow + 3 * idx[a];
-                x[a][0] = q[0];
-                x[a][1] = q[1];
-                x[a][2] = q[2];
-            }
-        if constexpr (Roll) {
-            double y[8][3];
-#pragma unroll
-            for (int a = 0; a < 8; ++a)
-                if (a < nrow) {
-                    const double *q = rrow + 3 * idx[a];
-                    y[a][0] = q[0];
-                    y[a][1] = q[1];
-                    y[a][2] = q[2];
-                }
-#pragma unroll
-            for (int a = 0; a < 8; ++a)
-                if (a < nrow) {
-                    rrow[3 * a] = y[a][0];
-                    rrow[3 * a + 1] = y[a][1];
-                    rrow[3 * a + 2] = y[a][2];
-                }
         }
 #pragma unroll
         for (int a = 0; a < 8; ++a)
             if (a < nrow) {
                 krow[a] = key[a];
-                xrow[3 * a] = x[a][0];
-                xrow[3 * a + 1] = x[a][1];
-                xrow[3 * a + 2] = x[a][2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xrow[3 * a + c] = x[a][c];
+                    if constexpr (Roll) rrow[3 * a + c] = y[a][c];
+                }
             }
     } else if (nrow > 8) {
         heap_sort_row<Roll>(krow, xrow, rrow, nrow);
@@ -1335,75 +1316,141 @@ __device__ __forceinline__ void reduce_tally(PairTally &tally, double (*red)[12]
     if (threadIdx.x < 12) {
         const int k = threadIdx.x;
         double v = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) v = (k == 11) ? fmax(v, red[w][k]) : v + red[w][k];
+        const int nw = (int)(blockDim.x >> 6);
+        for (int w = 0; w < nw; ++w) v = (k == 11) ? fmax(v, red[w][k]) : v + red[w][k];
         partials[(long long)k * pstride + rec] = v;
     }
 }
 
 // ----------------------------------------------------------------------------------
-// k_pairs: one workgroup per x-row of cells (cz, cy).  The particles of the five rows of
-// the half shell are staged in LDS (one 32-byte position/radius record each).
-//   A1  every (particle, shell row) task turns its window into at most two ranges of
-//       staged indices; a block scan of the range lengths flattens all candidates;
-//   A2  every lane tests an equal contiguous share of the candidates from LDS and queues
-//       the listed pairs in LDS;
-//   B   all lanes evaluate the queued pairs; both sides accumulate in LDS (FP64 LDS
-//       atomics), history rows of the own particles get their slots from LDS counters;
+// k_pairs: one workgroup of kPairBlock lanes per x-row of cells (cz, cy).  The particles of
+// the five rows of the half shell are staged in LDS as FP32 (x, y, z, a) records, which
+// only pre-select candidates; every decision and every pair quantity is FP64, from the
+// particle records in global memory.
+//   A1  every (particle, shell row) task appends the staged indices of its window (at most
+//       two ranges) to one flat candidate list;
+//   A2  every lane pre-tests its share of the candidates in FP32 with a margin that covers
+//       the rounding of FP32 coordinates (no listed pair is lost), and queues the survivors
+//       in LDS (probable contacts last);
+//   H   the history row head (slot at the last step, count, first two keys) of every staged
+//       particle replaces its FP32 record;
+//   B   all lanes take the queued pairs: the FP64 nearest image and listed test decide,
+//       then the pair physics with the stored stretch found from the row heads; both sides
+//       accumulate in LDS (FP64 LDS atomics), history rows of the own particles get their
+//       slots from LDS counters;
 //   C   own particles: Stokes terms, own force record, history row sorted by partner id;
 //       particles of the other four shell rows: partner-side force records.
-// Tile capacities (P.own_cap, P.stage_cap, P.qcap) are sized from the mean row
-// occupancy; a row beyond them takes the per-particle path.  The LDS layout is dynamic.
-// Sum: the row's stress and counters are reduced into its partial record.  Steps whose
-// stress is not summed take Sum = false, and the compiler drops the stresslet arithmetic
-// and its accumulators (the forces, torques and history are the same).
+// LDS: the candidate list and the staged slots at the last step live in the force
+// accumulators' space (cleared after H), and the row heads in that of the FP32 records, so that
+// four workgroups fit in the 160 KB of a CU; with 3 wavefronts each they hold 12 wavefronts
+// per CU (the register file holds three per SIMD), one cell row per workgroup slot.
+// Tile capacities (P.own_cap, P.stage_cap, P.qcap) are sized from the mean row occupancy; a
+// row beyond them takes the per-particle path (k_pairs_rows).  Sum: the row's stress and
+// counters are reduced into its partial record.  Steps whose stress is not summed take
+// Sum = false, and the compiler drops the stresslet arithmetic and its accumulators (the
+// forces, torques and history are the same).
 // ----------------------------------------------------------------------------------
+constexpr int kPairBlock = 192;
+constexpr int kPairWaves = kPairBlock / 64;
+
 struct TileShared {
     int rs[5], re[5], ro[6], rbase[5], rcross[5];
     int qn;
+    int nc;             // candidates listed by k_pairs
     int ovf;            // tile overflow: the row is redone on the per-particle path
     int wsum[kBlock / 64];
     double red[kBlock / 64][12];
 };
 
 struct TileView {
-    double4 *sp;        // stage_cap
-    double *acc;        // stage_cap x 6
-    unsigned *queue;    // qcap
-    uint2 *trange;      // 5 own_cap
-    int *tpre;          // 5 own_cap + 1
-    int *rowcnt;        // own_cap
+    float4 *sp;         // stage_cap: FP32 (x, y, z, a) of the staged particles; from B on the
+    int4 *heads;        //   history row heads of the staged particles (slot, count, key 0, key 1)
+    double *acc;        // stage_cap x 6 FP64 accumulators; during A1-A2 the candidate list
+    unsigned *queue;    // qcap pairs
+    int *rowcnt;        // own_cap history-row fill
+    int *owncx;         // own_cap cell column of each own particle
+    int *prevs;         // stage_cap: slot of each staged particle at the last step (the end
+                        //   of the accumulators' space, beyond the candidate list)
 };
 
 __host__ __device__ inline size_t tile_lds_bytes(int own_cap, int stage_cap, int qcap)
 {
-    return (size_t)stage_cap * 32 + (size_t)stage_cap * 48 + (size_t)qcap * 4 + (size_t)5 * own_cap * 8 +
-           (size_t)(5 * own_cap + 1) * 4 + (size_t)own_cap * 4;
+    return (size_t)stage_cap * 16 + (size_t)stage_cap * 48 + ((size_t)qcap * 4 + 7) / 8 * 8 + (size_t)own_cap * 4 +
+           (size_t)own_cap * 4;
 }
 
+// FP32 pre-test of a candidate with the image shifts of its range: 0 surely not listed, 1
+// possibly listed, 2 possibly listed and probably in contact.  m2 bounds the error of r^2
+// from FP32 coordinates (host: from the largest box length); the FP64 test decides later.
+__device__ __forceinline__ int image_class_f32(const float4 &Xi, const float4 &Xj, float sy, float sxd, float sx,
+                                               float sz, float cf, float rext, float m2)
+{
+    float dx = Xj.x - Xi.x, dy = Xj.y - Xi.y, dz = Xj.z - Xi.z;
+    dy = dy + sy;
+    dx = dx + sxd;
+    dx = dx + sx;
+    dz = dz + sz;
+    const float r2 = (dx * dx + dy * dy) + dz * dz;
+    const float s = Xi.w + Xj.w;
+    float rc = cf * s;
+    if (rext > 0.0f) rc = fmaxf(rc, s + rext);
+    return r2 < rc * rc + m2 ? (r2 < s * s + m2 ? 2 : 1) : 0;
+}
+
+// One queued pair (i = own particle il, j = staged particle jl): the FP64 nearest image and
+// listed test (the definition; the FP32 pre-test only selected it), then the pair physics.
 template <typename Real, bool Roll, bool Wave>
 __device__ __forceinline__ void tile_pair(const DevParams &P, const BoxParams &G, const HistView &H, const TileShared &T,
                                           const TileView &V, int il, int jl, double delta,
-                                          const double4 *__restrict__ vel, const double4 *__restrict__ omg,
-                                          DevClock *clk, int *pair_out, unsigned long long *pair_count,
-                                          PairTally &tally)
+                                          const double4 *__restrict__ pa, const double4 *__restrict__ vel,
+                                          const double4 *__restrict__ omg, DevClock *clk, int *pair_out,
+                                          unsigned long long *pair_count, PairTally &tally)
 {
-    const double4 Xi = V.sp[il];
-    const double4 Xj = V.sp[jl];
-    double dx, dy, dz, r2;
-    min_image(G, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy, dz);
-    listed(P, dx, dy, dz, Xi.w, Xj.w, r2);
     const int r = (jl >= T.ro[1]) + (jl >= T.ro[2]) + (jl >= T.ro[3]) + (jl >= T.ro[4]);
     const int gi = T.rs[0] + il;
     const int gj = T.rs[r] + (jl - T.ro[r]);
+    const double4 Xi = pa[gi];
+    const double4 Xj = pa[gj];
     const double4 Vi = vel[gi];
     const double4 Wi = omg[gi];
     const double4 Vj = vel[gj];
     const double4 Wj = omg[gj];
+    double dx, dy, dz, r2;
+    min_image(G, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy, dz);
+    if (!listed(P, dx, dy, dz, Xi.w, Xj.w, r2)) return;
     const int idi = (int)Wi.w, idj = (int)Wj.w;
     ++tally.npair;
     if (P.record_pairs) record_pair(P, idi, idj, pair_out, pair_count, clk);
+    // stored stretch of a contact: in the row of i (partner j) or, when the owner changed with
+    // the cells, in the row of j (partner i), found from the staged row heads
+    double xo[3] = {0.0, 0.0, 0.0};
+    double xro[3] = {0.0, 0.0, 0.0};  // the rolling stretch has no orientation
+    const double dist = sqrt(r2);
+    if (dist - Xi.w - Xj.w < 0.0) {
+        const int4 hi = V.heads[il], hj = V.heads[jl];
+        int p = hi.x;
+        int k = head_index(H.key_old, P.M, hi, idj);
+        if (k < 0) {
+            p = hj.x;
+            k = head_index(H.key_old, P.M, hj, idi);
+        }
+        if (k >= 0) {
+            const double sg = idi > idj ? -1.0 : 1.0;
+            const double *x = H.xi_old + ((long long)p * P.M + k) * 3;
+            xo[0] = sg * x[0];
+            xo[1] = sg * x[1];
+            xo[2] = sg * x[2];
+            if constexpr (Roll) {
+                const double *y = H.xr_old + ((long long)p * P.M + k) * 3;
+                xro[0] = y[0];
+                xro[1] = y[1];
+                xro[2] = y[2];
+            }
+        }
+    }
     PairOut o;
-    evaluate_pair<Real, Roll, Wave>(P, G.gd, G.wk, H, gi, gj, idi, idj, Xi, Xj, Vi, Wi, Vj, Wj, dx, dy, dz, r2, tally.S, o);
+    pair_physics<Real, Roll, Wave>(P, G.gd, G.wk, dx, dy, dz, dist, Xi.w, Xj.w, Xi.y, Xj.y, Vi, Vj, Wi, Wj, xo, xro,
+                                   tally.S, o);
     double *ai = V.acc + 6 * il;
     double *aj = V.acc + 6 * jl;
     atomicAdd(ai + 0, o.Fi[0]);
@@ -1455,6 +1502,7 @@ __device__ __forceinline__ void row_bounds(const BoxParams &G, int row, const in
         }
         T.ro[5] = o;
         T.qn = 0;
+        T.nc = 0;
         T.ovf = 0;
     }
     __syncthreads();
@@ -1471,29 +1519,57 @@ __device__ __forceinline__ int xcd_row(int b, int n)
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// Window of shell row r for an own particle in cell column cx: at most two runs of cells of
+// the row, [xl0, xl0 + len0) and [0, len1), the first w box lengths L_x beyond the row in x
+// and the second w + 1.
+struct TaskWindow {
+    int xl0, len0, len1, w;
+};
+
+__device__ __forceinline__ TaskWindow task_window(const BoxParams &G, const TileShared &T, int r, int cx, double delta)
+{
+    const int nxc = G.nc[0];
+    int xlo, xhi;
+    shell_window(G, r, cx, T.rcross[r], delta, xlo, xhi);
+    const int w = xlo >= 0 ? xlo / nxc : -((-xlo + nxc - 1) / nxc);  // floor(xlo / nx)
+    const int xl = xlo - w * nxc;
+    const int span = xhi - xlo + 1;
+    const int len0 = (xl + span <= nxc) ? span : nxc - xl;
+    TaskWindow W;
+    W.xl0 = xl;
+    W.len0 = len0;
+    W.len1 = span - len0;
+    W.w = w;
+    return W;
+}
+
 template <typename Real, bool Roll, bool Wave, bool Sum>
-__global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
-                                                      const int *__restrict__ row_box, const int *__restrict__ cell_start,
-                                                      const double4 *__restrict__ pa, const double4 *__restrict__ vel,
-                                                      const double4 *__restrict__ omg, ForceBufs B, HistView H,
-                                                      DevClock *__restrict__ clk, double *__restrict__ partials,
-                                                      int *__restrict__ pair_out,
-                                                      unsigned long long *__restrict__ pair_count,
-                                                      int *__restrict__ fb_rows, int *__restrict__ fb_count)
+__global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
+                                                          const int *__restrict__ row_box,
+                                                          const int *__restrict__ cell_start,
+                                                          const double4 *__restrict__ pa,
+                                                          const double4 *__restrict__ vel,
+                                                          const double4 *__restrict__ omg, ForceBufs B, HistView H,
+                                                          DevClock *__restrict__ clk, double *__restrict__ partials,
+                                                          int *__restrict__ pair_out,
+                                                          unsigned long long *__restrict__ pair_count,
+                                                          int *__restrict__ fb_rows, int *__restrict__ fb_count)
 {
     __shared__ TileShared T;
     extern __shared__ double4 dyn_lds[];
     TileView V;
-    V.sp = dyn_lds;
+    V.sp = reinterpret_cast<float4 *>(dyn_lds);
+    V.heads = reinterpret_cast<int4 *>(dyn_lds);
     V.acc = reinterpret_cast<double *>(V.sp + P.stage_cap);
     V.queue = reinterpret_cast<unsigned *>(V.acc + 6 * P.stage_cap);
-    V.trange = reinterpret_cast<uint2 *>(V.queue + P.qcap);
-    V.tpre = reinterpret_cast<int *>(V.trange + 5 * P.own_cap);
-    V.rowcnt = V.tpre + 5 * P.own_cap + 1;
+    V.rowcnt = reinterpret_cast<int *>(V.queue + (P.qcap + 1) / 2 * 2);
+    V.owncx = V.rowcnt + P.own_cap;
+    V.prevs = reinterpret_cast<int *>(V.acc) + 11 * P.stage_cap;
 
     const int t = threadIdx.x;
+    const int lane = t & 63, wid = t >> 6;
     const int grow = xcd_row(blockIdx.x, gridDim.x);
-    const BoxParams G = boxes[row_box[grow]];
+    const BoxParams G = boxes[P.nbox > 1 ? row_box[grow] : 0];
     const int nxc = G.nc[0], nzc = G.nc[2];
     const int row = grow - G.row_off;  // cell row within the box
     const int cz = row / G.nc[1];
@@ -1515,130 +1591,111 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
         defer_row();
         return;
     }
-    // stage the shell rows
-    for (int k = t; k < total; k += kBlock) {
+    // stage the shell rows (FP32) with their slots at the last step, and the cell column of
+    // every own particle (from FP64)
+    for (int k = t; k < total; k += kPairBlock) {
         const int r = (k >= T.ro[1]) + (k >= T.ro[2]) + (k >= T.ro[3]) + (k >= T.ro[4]);
-        V.sp[k] = pa[T.rs[r] + (k - T.ro[r])];
+        const int g = T.rs[r] + (k - T.ro[r]);
+        const double4 X = pa[g];
+        V.prevs[k] = H.prev ? H.prev[g] : g;
+        V.sp[k] = make_float4((float)X.x, (float)X.y, (float)X.z, (float)X.w);
+        if (k < n_own) {
+            V.owncx[k] = cell_coord(X.x, G.cw[0], nxc);
+            V.rowcnt[k] = 0;
+        }
     }
-    for (int k = t; k < n_own; k += kBlock) V.rowcnt[k] = 0;
     __syncthreads();
 
-    // A1: candidate ranges of every (particle, shell row) task, as LDS indices, with the
-    // periodic image of each range: a range word holds start (16 bits), length (11 bits)
-    // and w + 4 (3 bits), w = the number of box lengths L_x the range's cells lie beyond
-    // the row; the first word also holds the y-face crossing + 1 (bits 30-31), the second
-    // whether the row is reached across the z face (bit 30).
+    // A1: every (particle, shell row) task turns its window into at most two ranges of staged
+    // indices and appends their candidates to one flat list (a wavefront scan of the task
+    // counts and one LDS atomic per wavefront place them; the order of the list does not
+    // matter).  Candidate word: staged partner index jl (bits 0-13), il (bits 14-25), and the
+    // image of its range (bits 26-31: y-face crossing + 1, x period w + 4, z wrap).  The list
+    // lives in the LDS of the force accumulators.
+    unsigned *const cand = reinterpret_cast<unsigned *>(V.acc);
+    const int ccap = 11 * P.stage_cap < 64 * kPairBlock ? 11 * P.stage_cap : 64 * kPairBlock;
     const int ntask = 5 * n_own;
-    for (int task = t; task < ntask; task += kBlock) {
-        const int r = task / n_own;
-        const int il = task - r * n_own;
-        const int cx = cell_coord(V.sp[il].x, G.cw[0], nxc);
-        int xlo, xhi;
-        shell_window(G, r, cx, T.rcross[r], delta, xlo, xhi);
-        int w = xlo >= 0 ? xlo / nxc : -((-xlo + nxc - 1) / nxc);  // floor(xlo / nx)
-        int xl = xlo - w * nxc;
-        int span = xhi - xlo + 1;
-        unsigned rng[2] = {0u, 0u};
-        int cnt = 0;
-        for (int part = 0; part < 2 && span > 0; ++part) {
-            const int len = (xl + span <= nxc) ? span : nxc - xl;
-            int jb = cell_start[T.rbase[r] + xl];
-            const int je = cell_start[T.rbase[r] + xl + len];
-            if (r == 0 && part == 0) jb = T.rs[0] + il + 1;
-            const int n = je > jb ? je - jb : 0;
-            if (n > 2047) T.ovf = 1;
-            rng[part] = (unsigned)(T.ro[r] + (jb - T.rs[r])) | ((unsigned)(n & 2047) << 16) |
-                        ((unsigned)(w + 4) << 27);
-            cnt += n;
-            xl = 0;
-            span -= len;
-            ++w;
+    constexpr int kTaskBatch = 4;  // tasks per lane whose cell-range loads are in flight together
+    for (int task0 = 0; task0 < ntask; task0 += kTaskBatch * kPairBlock) {  // the same trip count in every lane
+        int rr[kTaskBatch], ill[kTaskBatch], cs4[kTaskBatch][4];
+        TaskWindow W[kTaskBatch];
+#pragma unroll
+        for (int u = 0; u < kTaskBatch; ++u) {
+            const int task = task0 + u * kPairBlock + t;
+            const bool on = task < ntask;
+            rr[u] = on ? task / n_own : 0;
+            ill[u] = on ? task - rr[u] * n_own : 0;
+            W[u] = task_window(G, T, rr[u], V.owncx[ill[u]], delta);
+            const int base = T.rbase[rr[u]];
+            cs4[u][0] = cell_start[base + W[u].xl0];
+            cs4[u][1] = cell_start[base + W[u].xl0 + W[u].len0];
+            cs4[u][2] = cell_start[base];
+            cs4[u][3] = cell_start[base + W[u].len1];
         }
-        rng[0] |= (unsigned)(T.rcross[r] + 1) << 30;
-        if (r >= 2 && cz == nzc - 1) rng[1] |= 1u << 30;
-        V.trange[task] = make_uint2(rng[0], rng[1]);
-        V.tpre[task] = cnt;
-    }
-    __syncthreads();
-    // exclusive scan of the task counts: lane t owns tasks per .. per + per - 1
-    {
-        const int per = (ntask + kBlock - 1) / kBlock;
-        int s_ = 0;
-        for (int k = 0; k < per; ++k) {
-            const int task = per * t + k;
-            s_ += task < ntask ? V.tpre[task] : 0;
-        }
-        const int lane = t & 63, wid = t >> 6;
-        int incl = s_;
-        for (int o = 1; o < 64; o <<= 1) {
-            int u = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += u;
-        }
-        if (lane == 63) T.wsum[wid] = incl;
-        __syncthreads();
-        int base = incl - s_;
-        for (int w = 0; w < wid; ++w) base += T.wsum[w];
-        for (int k = 0; k < per; ++k) {
-            const int task = per * t + k;
+#pragma unroll
+        for (int u = 0; u < kTaskBatch; ++u) {
+            const int task = task0 + u * kPairBlock + t;
+            const int r = rr[u], il = ill[u];
+            int n0 = 0, n1 = 0, j0 = 0, j1 = 0;
             if (task < ntask) {
-                const int c = V.tpre[task];
-                V.tpre[task] = base;
-                base += c;
+                const int jb = r == 0 ? T.rs[0] + il + 1 : cs4[u][0];
+                n0 = cs4[u][1] > jb ? cs4[u][1] - jb : 0;
+                j0 = T.ro[r] + (jb - T.rs[r]);
+                if (W[u].len1 > 0) {
+                    n1 = cs4[u][3] > cs4[u][2] ? cs4[u][3] - cs4[u][2] : 0;
+                    j1 = T.ro[r] + (cs4[u][2] - T.rs[r]);
+                }
+                if (n0 > 2047 || n1 > 2047) T.ovf = 1;
+            }
+            const int n = n0 + n1;
+            int incl = n;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += v;
+            }
+            int base = 0;
+            if (lane == 63) base = atomicAdd(&T.nc, incl);
+            base = __shfl(base, 63, 64) + incl - n;
+            if (n > 0 && base + n <= ccap) {
+                const unsigned common = ((unsigned)il << 14) | ((unsigned)(T.rcross[r] + 1) << 26) |
+                                        ((r >= 2 && cz == nzc - 1) ? (1u << 31) : 0u);
+                const unsigned c0 = common | ((unsigned)(W[u].w + 4) << 28);
+                const unsigned c1 = common | ((unsigned)(W[u].w + 5) << 28);
+                for (int o = 0; o < n0; ++o) cand[base + o] = c0 + (unsigned)(j0 + o);
+                for (int o = 0; o < n1; ++o) cand[base + n0 + o] = c1 + (unsigned)(j1 + o);
             }
         }
-        if (t == kBlock - 1) V.tpre[ntask] = base;
     }
     __syncthreads();
-
-    // A1b: the flat candidate list.  Candidate word: staged partner index jl (bits 0-13),
-    // il (bits 14-25), and the image of its range (bits 26-31: y-face crossing + 1, x period
-    // w + 4, z wrap).  The list lives in the LDS of the force accumulators, which are
-    // cleared after A2.
-    unsigned *const cand = reinterpret_cast<unsigned *>(V.acc);
-    const int ncand = V.tpre[ntask];
-    if (ncand > 12 * P.stage_cap || ncand > 64 * kBlock) {
-        if (t == 0) T.ovf = 1;
-    } else {
-        for (int task = t; task < ntask; task += kBlock) {
-            const int r = task / n_own;
-            const int il = task - r * n_own;
-            const int b0 = V.tpre[task], n = V.tpre[task + 1] - b0;
-            const uint2 rg = V.trange[task];
-            const int len0 = (int)((rg.x >> 16) & 2047u);
-            const unsigned common = ((unsigned)il << 14) | ((rg.x >> 30) << 26) | ((rg.y >> 30) << 31);
-            // image bits of each part; the staged index (below 2^14) is added to them
-            const unsigned c0 = common | (((rg.x >> 27) & 7u) << 28);
-            const unsigned c1 = common | (((rg.y >> 27) & 7u) << 28);
-            const int j0 = (int)(rg.x & 0xffffu), j1 = (int)(rg.y & 0xffffu) - len0;
-            for (int o = 0; o < n; ++o) cand[b0 + o] = o < len0 ? c0 + (unsigned)(j0 + o) : c1 + (unsigned)(j1 + o);
-        }
+    const int ncand = T.nc;
+    if (T.ovf || ncand > ccap) {
+        // a tile limit was hit: defer the row to the per-particle path
+        defer_row();
+        return;
     }
-    __syncthreads();
 
-    // A2: the candidates in lane-strided order (lane t tests k = t + 256 j, two per pass),
-    // every lane running the same straight-line test: the nearest-image vector is the
-    // difference plus the shifts of the candidate's range (y face with its x offset, x period,
-    // z period), added in the order and with the values of the general formula (same IEEE
-    // result for every listed pair).  Hits are kept as bit masks per lane (all hits, and the
-    // probable contacts); a block scan of the two hit counts (packed in one word: at most
-    // 64 kBlock candidates) gives every lane its slots in the pair queue, the other pairs
-    // first and the probable contacts last (no atomics).
+    // A2: the candidates in lane-strided order (lane t pre-tests k = t + kPairBlock j, two per
+    // pass), every lane running the same straight-line FP32 test with the shifts of the
+    // candidate's range.  Survivors are kept as bit masks per lane (all, and the probable
+    // contacts); a block scan of the two counts gives every lane its slots in the pair queue,
+    // the other pairs first and the probable contacts last (no atomics).
     if (!T.ovf) {
-        const int lane = t & 63, wid = t >> 6;
+        const float Lx = (float)G.L[0], Ly = (float)G.L[1], Lz = (float)G.L[2], dl = (float)delta;
+        const float cf = (float)P.cf, rx = P.ec ? (float)P.rext : 0.0f, m2 = P.pf_m2;
         auto test = [&](unsigned wd) -> int {
             const int jl = (int)(wd & 0x3fffu);
             const int il = (int)((wd >> 14) & 0xfffu);
             const int cross = (int)((wd >> 26) & 3u) - 1;
-            const double sy = cross > 0 ? G.L[1] : (cross < 0 ? -G.L[1] : 0.0);
-            const double sxd = cross > 0 ? delta : (cross < 0 ? -delta : 0.0);
-            const double sx = (double)((int)((wd >> 28) & 7u) - 4) * G.L[0];
-            const double sz = (wd >> 31) ? G.L[2] : 0.0;
-            return image_class(V.sp[il], V.sp[jl], sy, sxd, sx, sz, P.cf, P.ec ? P.rext : 0.0);
+            const float sy = cross > 0 ? Ly : (cross < 0 ? -Ly : 0.0f);
+            const float sxd = cross > 0 ? dl : (cross < 0 ? -dl : 0.0f);
+            const float sx = (float)((int)((wd >> 28) & 7u) - 4) * Lx;
+            const float sz = (wd >> 31) ? Lz : 0.0f;
+            return image_class_f32(V.sp[il], V.sp[jl], sy, sxd, sx, sz, cf, rx, m2);
         };
         unsigned long long bits = 0ull, cbits = 0ull;
         int j = 0;
-        for (int k = t; k < ncand; k += 2 * kBlock, j += 2) {
-            const int k2 = k + kBlock;
+        for (int k = t; k < ncand; k += 2 * kPairBlock, j += 2) {
+            const int k2 = k + kPairBlock;
             const unsigned w0 = cand[k];
             const unsigned w1 = k2 < ncand ? cand[k2] : w0;
             const int h0 = test(w0);
@@ -1657,7 +1714,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
         __syncthreads();
         int q = incl - c;
         int tot = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
+        for (int w = 0; w < kPairWaves; ++w) {
             q += w < wid ? T.wsum[w] : 0;
             tot += T.wsum[w];
         }
@@ -1670,7 +1727,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
                 const int jj = __ffsll((long long)bits) - 1;
                 const bool ct = (cbits >> jj) & 1ull;
                 bits &= bits - 1ull;
-                const unsigned wd = cand[t + jj * kBlock];
+                const unsigned wd = cand[t + jj * kPairBlock];
                 V.queue[ct ? qc++ : qf++] = (((wd >> 14) & 0xfffu) << 16) | (wd & 0x3fffu);
             }
             if (t == 0) T.qn = nhit;
@@ -1683,24 +1740,40 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
         return;
     }
 
-    for (int k = t; k < 6 * total; k += kBlock) V.acc[k] = 0.0;
+    // the FP32 records are dead: the history row head of every staged particle (its slot at
+    // the last step, row count, first two keys) takes their place, so that B finds most stored
+    // stretches without a chain of global loads; the accumulators are cleared
+    for (int k = t; k < total; k += kPairBlock) {
+        const int p = V.prevs[k];
+        const int *kr = H.key_old + (long long)p * P.M;
+        V.heads[k] = make_int4(p, H.cnt_old[p], kr[0], kr[P.M > 1 ? 1 : 0]);
+    }
+    __syncthreads();   // the slots are read before the accumulators (their space) are cleared
+    for (int k = t; k < 6 * total; k += kPairBlock) V.acc[k] = 0.0;
     __syncthreads();
 
     // B: evaluate the queued pairs
     const int nq = T.qn;
-    for (int q = t; q < nq; q += kBlock) {
+    for (int q = t; q < nq; q += kPairBlock) {
         const unsigned e = V.queue[q];
-        tile_pair<Real, Roll, Wave>(P, G, H, T, V, (int)(e >> 16), (int)(e & 0xffffu), delta, vel, omg, clk, pair_out,
-                        pair_count, tally);
+        tile_pair<Real, Roll, Wave>(P, G, H, T, V, (int)(e >> 16), (int)(e & 0xffffu), delta, pa, vel, omg, clk,
+                                    pair_out, pair_count, tally);
+    }
+    // the records of the lane's first own particle of C are requested before the barrier
+    double4 Xc = make_double4(0.0, 0.0, 0.0, 0.0), Vc = Xc, Wc = Xc;
+    if (t < n_own) {
+        Xc = pa[T.rs[0] + t];
+        Vc = vel[T.rs[0] + t];
+        Wc = omg[T.rs[0] + t];
     }
     __syncthreads();
 
     // C: own particles (Stokes terms, own record, history row), then partner records
-    for (int il = t; il < n_own; il += kBlock) {
+    for (int il = t; il < n_own; il += kPairBlock) {
         const int gi = T.rs[0] + il;
-        const double4 Xi = V.sp[il];
-        const double4 Vi = vel[gi];
-        const double4 Wi = omg[gi];
+        const double4 Xi = il == t ? Xc : pa[gi];
+        const double4 Vi = il == t ? Vc : vel[gi];
+        const double4 Wi = il == t ? Wc : omg[gi];
         double f[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) f[c] = V.acc[6 * il + c];
@@ -1711,7 +1784,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_pairs(DevParams P, const BoxParam
         finish_row<Roll>(H, P.M, gi, fill, (int)Wi.w);
         tally.fill = max(tally.fill, fill);
     }
-    for (int k = T.ro[1] + t; k < total; k += kBlock) {
+    for (int k = T.ro[1] + t; k < total; k += kPairBlock) {
         const int r = (k >= T.ro[2]) + (k >= T.ro[3]) + (k >= T.ro[4]) + 1;
         const int g = T.rs[r] + (k - T.ro[r]);
         double f[6];
@@ -1767,62 +1840,46 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_rows(DevParams P, const Box
 }
 
 // ----------------------------------------------------------------------------------
-// k_finish: per box (one workgroup of 1024 lanes each), sum the partial records of the
-// box's cell rows in a fixed order (so the stress does not depend on scheduling), publish
-// the pair part of the box's stress and its counters, and store the stress sample of the
-// current time index when the schedule asks for it.  Lane t loads the records
-// row_off + t, row_off + t + 1024, ... of every component at once, coalesced.
+// k_finish: one workgroup of kBlock lanes per (box, component) of the 12 partial-record
+// components (9 stress components, listed pairs, contacts, largest history row): the sum
+// (the maximum for the last) of the box's records in a fixed order (lane t takes records
+// t, t + kBlock, ..., then the wavefronts and the waves in order), so the stress does not
+// depend on scheduling; the workgroup publishes its component of the box's stress or
+// counters, and the stress sample of the current time index when the schedule asks for it.
 // ----------------------------------------------------------------------------------
-template <int R>
-__global__ void __launch_bounds__(1024) k_finish(const BoxParams *__restrict__ boxes,
-                                                  const double *__restrict__ partials, int pstride,
-                                                  DevClock *__restrict__ clk, DevRun *__restrict__ run, int sample)
+__global__ void __launch_bounds__(kBlock) k_finish(const BoxParams *__restrict__ boxes,
+                                                    const double *__restrict__ partials, int pstride,
+                                                    DevClock *__restrict__ clk, DevRun *__restrict__ run, int sample)
 // partials: 12 components x pstride records
 {
-    __shared__ double red[16][12];
+    __shared__ double red[kBlock / 64];
     const int t = threadIdx.x;
-    const int b = blockIdx.x;
+    const int b = blockIdx.x / 12, k = blockIdx.x - (blockIdx.x / 12) * 12;
     const BoxParams &G = boxes[b];
     const int r0 = G.row_off, nrow = G.nrec;
-    double v[R][12];
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const int w = m * 1024 + t;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) v[m][k] = w < nrow ? partials[(long long)k * pstride + r0 + w] : 0.0;
+    const double *src = partials + (long long)k * pstride + r0;
+    double acc = 0.0;
+    if (k == 11) {
+        for (int w = t; w < nrow; w += kBlock) acc = fmax(acc, src[w]);
+        for (int o = 32; o > 0; o >>= 1) acc = fmax(acc, __shfl_xor(acc, o, 64));
+    } else {
+        for (int w = t; w < nrow; w += kBlock) acc += src[w];
+        acc = warp_sum(acc);
     }
-    double acc[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = v[0][k];
-#pragma unroll
-    for (int m = 1; m < R; ++m) {
-#pragma unroll
-        for (int k = 0; k < 11; ++k) acc[k] += v[m][k];
-        acc[11] = fmax(acc[11], v[m][11]);
-    }
-    const int lane = t & 63, wid = t >> 6;
-#pragma unroll
-    for (int k = 0; k < 11; ++k) {
-        double x = warp_sum(acc[k]);
-        if (lane == 0) red[wid][k] = x;
-    }
-    double mx = acc[11];
-    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-    if (lane == 0) red[wid][11] = mx;
+    if ((t & 63) == 0) red[t >> 6] = acc;
     __syncthreads();
-    if (t < 12) {
-        double x = 0.0;
-        for (int w = 0; w < 16; ++w) x = (t == 11) ? fmax(x, red[w][t]) : x + red[w][t];
-        if (t < 9) {
-            run->sigma_last[9 * b + t] = x;
-            const long long n = clk->step;
-            if (sample && run->sample_every > 0 && n % run->sample_every == 0 && n >= run->sample_first) {
-                const long long slot = (n - run->sample_first) / run->sample_every;
-                if (slot < run->sample_cap) run->samples[(slot * gridDim.x + b) * 9 + t] = x;
-            }
-        } else {
-            run->box_diag[3 * b + (t - 9)] = x;
+    if (t != 0) return;
+    double x = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) x = (k == 11) ? fmax(x, red[w]) : x + red[w];
+    if (k < 9) {
+        run->sigma_last[9 * b + k] = x;
+        const long long n = clk->step;
+        if (sample && run->sample_every > 0 && n % run->sample_every == 0 && n >= run->sample_first) {
+            const long long slot = (n - run->sample_first) / run->sample_every;
+            if (slot < run->sample_cap) run->samples[(slot * (gridDim.x / 12) + b) * 9 + k] = x;
         }
+    } else {
+        run->box_diag[3 * b + (k - 9)] = x;
     }
 }
 
