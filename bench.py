@@ -203,10 +203,22 @@ def run_single(args):
         p.update(ec_ranges=True, hamaker=1e-3)
         physics.append("electro-chemical ranges (repulsion < 20 lambda_D, attraction A=1e-3 < 4 a0)")
     sim = Simulation(p, precision=prec, stream=torch.cuda.current_stream().cuda_stream)
+    if args.sized:
+        sim.set_tuning(sized=True, cell_scale=args.cell_scale or 1.0, wave_class=args.wave_class)
+        physics.append(f"size-class stencils (cell scale {args.cell_scale or 1.0}, wavefronts from class {args.wave_class})")
     sim.set_particles(w.x, w.rad)
     N = len(w.rad)
     tuned = maybe_tune(sim, args)
-    sheared = preshear(sim, args.preshear)
+    if args.state_cache and os.path.exists(args.state_cache):
+        # the pre-sheared state of an earlier run of the same command (profiling passes)
+        sim.load_state(open(args.state_cache, "rb").read())
+        sheared = int(sim.info()["step"])
+        print(f"# pre-sheared state loaded (time index {sheared})", file=sys.stderr, flush=True)
+    else:
+        sheared = preshear(sim, args.preshear)
+        if args.state_cache:
+            with open(args.state_cache, "wb") as f:
+                f.write(sim.save_state())
     blob = sim.save_state() if mode_inputs else None
     el, timing, breakdown = timed_run(sim, N, args, 10)
     info = sim.info()
@@ -216,8 +228,12 @@ def run_single(args):
         print(f"# device error flags {info['error_flags']}", file=sys.stderr)
         sys.exit(1)
     ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2])
+    ncell *= sim.box_info(0)["size_classes"]
     roof = roofline(dominant_pairs(timing, breakdown), N, ncell, info["n_contacts"], info["capacity"],
                     measured_traffic() if args.precision == "fp64" and N == 100_000 and not physics else None)
+    if args.sized and roof["kernel"] == "k_pairs":
+        roof["kernel"] = "k_pairs_sized"
+        roof["traffic"] = None
     table = kernel_table(breakdown)
     sim.close()
     modes = None
@@ -589,12 +605,15 @@ def main():
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload-cache", default=None, help="npz file to reuse the single-box workload")
+    ap.add_argument("--state-cache", default=None,
+                    help="single: file holding the pre-sheared state (written by the first run, loaded by later ones)")
     ap.add_argument("--copy-probe", action="store_true", help="end with plain 256 MiB device copies")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--rolling", action="store_true", help="single: with rolling resistance")
     ap.add_argument("--ec-ranges", action="store_true",
                     help="single: electro-chemical forces over their own ranges (with attraction)")
     ap.add_argument("--observables", action="store_true", help="single: time the observables after the run")
+    ap.add_argument("--sized", action="store_true", help="single: size-class stencils instead of the row tiles")
     ap.add_argument("--cell-scale", type=float, default=None, help="poly: lattice spacing over 2 c a_min (1.5)")
     ap.add_argument("--wave-class", type=int, default=2, help="poly: first size class on a wavefront (2)")
     ap.add_argument("--preshear", type=int, default=10_000,

@@ -1103,9 +1103,80 @@ __device__ __forceinline__ void heap_sort_row(int *krow, double *xrow, double *r
     }
 }
 
+// Stretches of a history row in the order idx (n <= 16 entries): entry idx[a] is gathered
+// into entry t0 + a of the free end of the row (t0 >= n), eight at a time, then the n entries
+// are copied back to the front; the two ranges never overlap.
+template <bool Roll>
+__device__ __forceinline__ void permute_row_entries(double *xrow, double *rrow, const int idx[16], int n, int t0)
+{
+    constexpr int kBatch = Roll ? 4 : 8;
+#pragma unroll
+    for (int b0 = 0; b0 < 16; b0 += kBatch) {
+        const double *__restrict__ src = xrow;
+        double *__restrict__ dst = xrow + 3 * t0;
+        double v[kBatch][3];
+#pragma unroll
+        for (int a = 0; a < kBatch; ++a) {
+            const int e = b0 + a < n ? idx[b0 + a] : 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[a][c] = src[3 * e + c];
+        }
+#pragma unroll
+        for (int a = 0; a < kBatch; ++a)
+            if (b0 + a < n)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dst[3 * (b0 + a) + c] = v[a][c];
+        if constexpr (Roll) {
+            const double *__restrict__ rs = rrow;
+            double *__restrict__ rd = rrow + 3 * t0;
+#pragma unroll
+            for (int a = 0; a < kBatch; ++a) {
+                const int e = b0 + a < n ? idx[b0 + a] : 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[a][c] = rs[3 * e + c];
+            }
+#pragma unroll
+            for (int a = 0; a < kBatch; ++a)
+                if (b0 + a < n)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) rd[3 * (b0 + a) + c] = v[a][c];
+        }
+    }
+#pragma unroll
+    for (int b0 = 0; b0 < 16; b0 += kBatch) {
+        const double *__restrict__ src = xrow + 3 * t0;
+        double *__restrict__ dst = xrow;
+        double v[kBatch][3];
+#pragma unroll
+        for (int a = 0; a < kBatch; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[a][c] = b0 + a < n ? src[3 * (b0 + a) + c] : 0.0;
+#pragma unroll
+        for (int a = 0; a < kBatch; ++a)
+            if (b0 + a < n)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dst[3 * (b0 + a) + c] = v[a][c];
+        if constexpr (Roll) {
+            const double *__restrict__ rs = rrow + 3 * t0;
+            double *__restrict__ rd = rrow;
+#pragma unroll
+            for (int a = 0; a < kBatch; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[a][c] = b0 + a < n ? rs[3 * (b0 + a) + c] : 0.0;
+#pragma unroll
+            for (int a = 0; a < kBatch; ++a)
+                if (b0 + a < n)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) rd[3 * (b0 + a) + c] = v[a][c];
+        }
+    }
+}
+
 // Sort history row gi by partner id and publish it (the per-row sort of the contact
 // map).  Rows of up to 8 entries are read at once and sorted in registers (odd-even
-// transposition on the (key, stretch) tuples); longer rows by a heap sort in place.  With rolling
+// transposition on the (key, stretch) tuples); rows of up to 16 (at most half the capacity) by
+// their keys and entry indices in registers, the stretches then moved through the free end of
+// the row; longer rows by a heap sort in place.  With rolling
 // resistance the rolling stretches move with their entries.
 template <bool Roll = false>
 __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int fill, int idi)
@@ -1161,7 +1232,36 @@ __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int
                     if constexpr (Roll) rrow[3 * a + c] = y[a][c];
                 }
             }
-    } else if (nrow > 8) {
+    } else if (nrow > 8 && nrow <= 16 && 2 * nrow <= M) {
+        // keys sorted with their entry indices in registers (odd-even transposition); the
+        // entries are gathered in the new order into the free end of the row, then copied back
+        // (disjoint ranges: the loads of a batch are in flight together)
+        int key[16], idx[16];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+            key[a] = a < nrow ? krow[a] : 0x7fffffff;
+            idx[a] = a;
+        }
+#pragma unroll
+        for (int round = 0; round < 16; ++round) {
+#pragma unroll
+            for (int a = round & 1; a + 1 < 16; a += 2) {
+                if ((key[a] & kKeyMask) > (key[a + 1] & kKeyMask)) {
+                    const int tk = key[a];
+                    key[a] = key[a + 1];
+                    key[a + 1] = tk;
+                    const int ti = idx[a];
+                    idx[a] = idx[a + 1];
+                    idx[a + 1] = ti;
+                }
+            }
+        }
+        const int t0 = M - nrow;
+        permute_row_entries<Roll>(xrow, rrow, idx, nrow, t0);
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            if (a < nrow) krow[a] = key[a];
+    } else if (nrow > 16) {
         heap_sort_row<Roll>(krow, xrow, rrow, nrow);
     }
     H.cnt_new[gi] = nrow;
@@ -1319,6 +1419,47 @@ __device__ __forceinline__ void reduce_tally(PairTally &tally, double (*red)[12]
         const int nw = (int)(blockDim.x >> 6);
         for (int w = 0; w < nw; ++w) v = (k == 11) ? fmax(v, red[w][k]) : v + red[w][k];
         partials[(long long)k * pstride + rec] = v;
+    }
+}
+
+// The two parts of reduce_tally for a kernel that knows its sums before its rows: the sums
+// (9 stress components, pairs, contacts; components 0..10), then the largest row (11).
+__device__ __forceinline__ void reduce_sums(const PairTally &tally, double (*red)[12], double *__restrict__ partials,
+                                            int pstride, int rec)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        double v = warp_sum(tally.S[k]);
+        if (lane == 0) red[wid][k] = v;
+    }
+    long long np_ = warp_sum_ll(tally.npair), nc_ = warp_sum_ll(tally.ncont);
+    if (lane == 0) {
+        red[wid][9] = (double)np_;
+        red[wid][10] = (double)nc_;
+    }
+    __syncthreads();
+    if (threadIdx.x < 11) {
+        const int k = threadIdx.x;
+        double v = 0.0;
+        const int nw = (int)(blockDim.x >> 6);
+        for (int w = 0; w < nw; ++w) v += red[w][k];
+        partials[(long long)k * pstride + rec] = v;
+    }
+}
+
+__device__ __forceinline__ void reduce_fill(int fill, double (*red)[12], double *__restrict__ partials, int pstride,
+                                            int rec)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int mf = warp_max(fill);
+    if (lane == 0) red[wid][11] = (double)mf;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        const int nw = (int)(blockDim.x >> 6);
+        for (int w = 0; w < nw; ++w) v = fmax(v, red[w][11]);
+        partials[11LL * pstride + rec] = v;
     }
 }
 
@@ -1766,6 +1907,9 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
         Vc = vel[T.rs[0] + t];
         Wc = omg[T.rs[0] + t];
     }
+    // the sums are complete (C adds to the stress only in the wavy shear): reduced here, so that
+    // their registers are free in C
+    if constexpr (Sum && !Wave) reduce_sums(tally, T.red, partials, P.pstride, grow);
     __syncthreads();
 
     // C: own particles (Stokes terms, own record, history row), then partner records
@@ -1792,7 +1936,12 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
         for (int c = 0; c < 6; ++c) f[c] = V.acc[6 * k + c];
         store_ft(B.nb + 6LL * ((r - 1) * B.n + g), f);
     }
-    if constexpr (Sum) reduce_tally(tally, T.red, partials, P.pstride, grow);
+    if constexpr (Sum) {
+        if constexpr (Wave)
+            reduce_tally(tally, T.red, partials, P.pstride, grow);
+        else
+            reduce_fill(tally.fill, T.red, partials, P.pstride, grow);
+    }
 }
 
 // ----------------------------------------------------------------------------------

@@ -210,3 +210,47 @@ def test_full_size_high_ratio_initial_evaluation():
     last, _, _ = sim.read_stress()
     assert rel_inf(last, S) < TOL_F
     sim.close()
+
+
+def test_full_size_high_ratio_mixed_lockstep():
+    """Size ratio 10 at its full size in its benchmark's configuration: mixed precision on the
+    size-class stencils (spacing 1.5, wavefronts from stencil radius 3), N = 500k lognormal radii
+    on [1, 10] at phi = 0.55.  Two time steps in lockstep with the FP64 oracle: pair sets
+    bit-identical, F, T, Sigma and the committed stretches within 1e-5, the second step reading
+    the history rows that the first committed (the rows of the large particles, sorted by partner
+    id, hold tens of entries).  The centres are uniform at random, as in the initial-evaluation
+    test (relaxing this size takes many minutes), so most particles start in contact."""
+    from paper_2108_01013_amd.dss import DSS_MIXED, Simulation
+    N = 500_000
+    rad = synth.lognormal_radii(N, seed=3)
+    L = synth.box_for_fraction(rad, 0.55)
+    x = np.random.default_rng(1003).uniform(0.0, L, size=(N, 3))
+    p = synth.default_params([L, L, L])
+    say("case: full-size size ratio 10, N=500k, mixed, two lockstep steps")
+    sim = Simulation(p, record_pairs=True, precision=DSS_MIXED)
+    sim.set_tuning(sized=True, cell_scale=1.5, wave_class=2)
+    sim.set_particles(x, rad)
+    hp = np.zeros((0, 2), np.int32)
+    hx = np.zeros((0, 3))
+    for k in range(2):
+        s0 = sim.state()
+        a, aw = oracle.accelerations(p, rad, s0["F"], s0["T"])
+        st = oracle.State(s0["x"], s0["u"], s0["w"], a, aw, rad.copy(), k, oracle.History(hp.astype(np.int32), hx))
+        x_o = oracle.kick_drift(p, st)[0]
+        sim.step(1)
+        s1 = sim.state()
+        uh, wh = sim.eval_velocities()
+        assert np.array_equal(s1["x"], x_o), f"step {k}: positions"
+        assert np.array_equal(sim.pairs(), oracle.pairs_cells(p, s1["x"], rad, oracle.le_offset(p, k + 1))), k
+        F, T, S, H, npairs = oracle.forces(p, s1["x"], uh, wh, rad, k + 1, st.history, use_cells=True)
+        say(f"step {k}: F {rel_inf(s1['F'], F):.2e} T {rel_inf(s1['T'], T):.2e}")
+        assert rel_inf(s1["F"], F) < TOL_MIXED and rel_inf(s1["T"], T) < TOL_MIXED
+        last, _, _ = sim.read_stress()
+        assert rel_inf(last, S) < TOL_MIXED
+        hp, hx = sim.history()
+        assert len(hp) > N and np.array_equal(hp, H.pairs)
+        assert np.max(np.abs(hx - H.xi)) <= TOL_MIXED * np.max(np.abs(H.xi))
+    info = sim.info()
+    say(f"contacts {info['n_contacts']}, largest history row {info['max_row_fill']} of {info['capacity']}")
+    assert info["error_flags"] == 0 and info["max_row_fill"] > 32
+    sim.close()
