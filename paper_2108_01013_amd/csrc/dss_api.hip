@@ -405,11 +405,14 @@ bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, 
         for (int d = 0; d < 3; ++d) G.nc[d] = std::max(1, (int)std::floor(G.L[d] / rc));
         // one box whose cell rows exceed the k_pairs workgroup slots by a little: coarser cells
         // along z (the vorticity direction, away from the sheared faces) until every row has a
-        // slot, so the rows run in one round instead of a nearly empty second one
+        // slot, so the rows run in one round instead of a nearly empty second one.  The rows
+        // are kept 1/64 below the slots: with every slot taken, a few workgroups have been seen
+        // to wait for a slot of a finished row at launch
         if (boxes.size() == 1 && row_slots > 0) {
             const int rows = G.nc[1] * G.nc[2];
-            if (rows > row_slots && rows * 100 <= row_slots * 115)
-                while (G.nc[1] * G.nc[2] > row_slots && G.nc[2] > 3) --G.nc[2];
+            const int fit = row_slots - row_slots / 64;
+            if (rows > fit && rows * 100 <= row_slots * 115)
+                while (G.nc[1] * G.nc[2] > fit && G.nc[2] > 3) --G.nc[2];
         }
         for (int d = 0; d < 3; ++d) G.cw[d] = G.L[d] / (double)G.nc[d];
         if (G.nc[0] < 4 || G.nc[1] < 3 || G.nc[2] < 3) {
@@ -521,7 +524,7 @@ dss_status setup_lattice(dss_handle *h)
         // (dynamic and static LDS are each allocated in blocks of up to 1 KB)
         const size_t lds_four = 40 * 1024 - 1024;
         const int own4 = up(1.3 * mean_row + 8.0, 32);
-        const int stage4 = up(5.0 * mean_row + 2.0 * std::sqrt(5.0 * mean_row), 32);
+        const int stage4 = up(5.0 * mean_row + 2.0 * std::sqrt(5.0 * mean_row), 16);
         const int q4 = up(4.5 * mean_row + 64.0, 64);
         if (tile_lds_bytes(own4, stage4, q4) <= lds_four) {
             own_cap = own4;
@@ -934,6 +937,7 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     }
     DevParams P{};
     P.eta0 = p.eta0; P.rho = p.rho; P.kn = p.kn; P.kt = p.kt; P.gn = p.gamma_n;
+    P.inv_kt = p.kt > 0.0 ? 1.0 / p.kt : 0.0;
     P.mu = p.mu; P.fer = p.F_ER; P.lamd = p.lambda_D; P.a0 = p.a0; P.ham = p.hamaker; P.eps_vdw = p.eps_vdw;
     P.eps_lub = p.eps_lub; P.cf = p.cutoff_factor; P.dt = p.dt;
     P.k6 = 6.0 * kPi * p.eta0;
@@ -950,6 +954,7 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
     P.att_rng = p.hamaker != 0.0 ? 4.0 * p.a0 : 0.0;
     P.rext = P.ec ? std::max(P.rep_rng, P.att_rng) : 0.0;
     P.kr = p.k_roll;
+    P.inv_kr = p.k_roll > 0.0 ? 1.0 / p.k_roll : 0.0;
     P.mu_r = p.mu_roll;
     P.wave_amp = p.wave_amp;
     P.pair_cap = P.record_pairs ? pair_record_capacity(P, boxes, box_amax, n_per_box) : 0;

@@ -56,6 +56,7 @@ struct DevParams {
     double rext;                    // with ec: longest active range (pair set |r| < max(c s, s + rext))
     double rep_rng, att_rng;        // with ec: surface-distance ranges of repulsion and attraction
     double kr, mu_r;                // rolling spring stiffness and Coulomb coefficient (kr = 0: off)
+    double inv_kt, inv_kr;          // 1 / kt, 1 / kr (0 when the spring is off)
     double wave_amp;                // amplitude W of the wavy shear, eq. uinf (0: simple shear)
     float pf_m2;                    // margin on r^2 of the FP32 candidate pre-test of k_pairs
 };
@@ -751,7 +752,7 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
         xz -= xn * nz;
         Real Ftx = 0, Fty = 0, Ftz = 0;
         if (P.kt > 0.0) {
-            const Real cap = (Real)P.mu * fabs(fn) * (Real)(1.0 / P.kt);
+            const Real cap = (Real)P.mu * fabs(fn) * (Real)P.inv_kt;
             const Real xm = sqrt_r(xx * xx + xy * xy + xz * xz);
             if (xm >= cap && xm > (Real)0.0) {
                 o.capped = true;
@@ -792,7 +793,7 @@ __device__ __forceinline__ void pair_physics(const DevParams &P, double gd_d, do
             rx -= rn * nx;
             ry -= rn * ny;
             rz -= rn * nz;
-            const Real capr = (Real)P.mu_r * fabs(fn) * (Real)(1.0 / P.kr);
+            const Real capr = (Real)P.mu_r * fabs(fn) * (Real)P.inv_kr;
             const Real rm = sqrt_r(rx * rx + ry * ry + rz * rz);
             if (rm >= capr && rm > (Real)0.0) {
                 const Real sc = capr * rcp_r(rm);
