@@ -61,8 +61,12 @@ typedef enum { DSS_FP64 = 0, DSS_MIXED = 1 } dss_precision;
  * stays on |r| < cutoff_factor (a_i + a_j).  The pair set (and the cell lattice) then covers
  * |r| < max(cutoff_factor (a_i + a_j), a_i + a_j + the longest active range).  Without the
  * flag both forces are truncated at the lubrication list.  With size-class stencils a
- * particle's reach becomes 2 max(cutoff_factor, 1) a + the longest range.  With the adjoint
- * the three ranges are held fixed like the pair set. */
+ * particle's reach becomes 2 max(cutoff_factor, 1) a + the longest range.  On a handle of one
+ * box without size classes (cutoff_factor >= 1) the lattice stays that of the lubrication
+ * list when the longest reach 2 a_max + the longest range spans fewer than half the cell rows
+ * along y and z and half of L_x: the pairs beyond the list then take a pass of their own
+ * (central forces only), and the pair set is the same.  With the adjoint the three ranges
+ * are held fixed like the pair set. */
 #define DSS_FLAG_EC_RANGES 2
 
 /* Physical and numerical parameters (units are the caller's; the defaults used by the
@@ -122,6 +126,9 @@ typedef struct {
     double L[3];
     double shear_rate;
     double le_offset;      /* Lees-Edwards offset of the current state */
+    int32_t ec_far_rows[2]; /* with DSS_FLAG_EC_RANGES on a lattice of the lubrication list: reach
+                             * (cell rows along y, z) of the pass over the pairs beyond it; 0, 0
+                             * when the lattice covers the whole pair set */
 } dss_box_info;
 
 /* Create a handle.  p is copied.  hip_stream: a hipStream_t of the current device, or
@@ -320,8 +327,9 @@ dss_status dss_load_state(dss_handle *h, const void *blob, size_t bytes);
  * the kernels selected by enable (bit k: kernel k; -1: all; 0: off); every call starts a
  * new accumulation.  dss_get_timing synchronises and returns, for kernel k (0 predict or
  * velocity completion, 1 scan, 2 scatter, 3 pairs, 4 finish, 5 pair adjoint, 6 integrator
- * adjoint, 7 pairs of the rows beyond the tile capacities; with size-class stencils 3 is
- * their one pair kernel), the summed duration in ms and the number of timed launches. */
+ * adjoint, 7 pairs of the rows beyond the tile capacities, 8 electro-chemical pairs beyond
+ * the lubrication list; with size-class stencils 3 is their one pair kernel), the summed
+ * duration in ms and the number of timed launches. */
 dss_status dss_set_timing(dss_handle *h, int enable);
 dss_status dss_get_timing(dss_handle *h, int kernel, double *total_ms, int64_t *launches);
 

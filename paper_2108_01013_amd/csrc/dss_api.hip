@@ -81,6 +81,7 @@ struct dss_handle {
     double a_min = 0.0;               // smallest radius of all boxes
     std::vector<double> rad_host;     // radii by id (size-class counts of the stencil path)
     int sized_grid[2] = {0, 0};       // lane and wavefront workgroups of k_pairs_sized
+    int ec_grid = 0;                  // workgroups of k_pairs_ec (0: no far-pair pass)
     double max_mean_row = 0.0;        // mean particles per cell row of the densest box
     dss_tuning tune{1.0, 1.0, 1, 1, 0, 0, 0, 0};
     bool tune_pending = false;        // lattice to rebuild before the next time step
@@ -137,7 +138,7 @@ struct dss_handle {
     DevRun run_host{};
 
     // kernel timing with events on the stream
-    static constexpr int kKernels = 8;
+    static constexpr int kKernels = 9;
     unsigned timing = 0;       // bit k: time kernel k
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<int, int>>> ev_marks;  // (kernel, (start event, stop event))
@@ -342,6 +343,7 @@ dss_status require_loaded(dss_handle *h)
 struct SizeClasses {
     int ncls = 1;
     double cls_mul = 0.0, cls_add = 0.0;
+    int ec_ry = 0, ec_rz = 0;   // > 0: electro-chemical far pairs on their own pass (k_pairs_ec)
 };
 
 // Cell lattice of every box: spacing >= cell_scale times the box's largest pair cutoff
@@ -351,6 +353,8 @@ struct SizeClasses {
 // particle (2 c a_min, or 2 max(c, 1) a_min + rext with the electro-chemical ranges), coarsened until the largest stencil (R_max = ncls cells) fits the box without
 // reaching a cell twice: n_x >= 2 R_max + 2 (the window of a sheared row), n_y, n_z >=
 // 2 R_max + 1.  Cells are numbered class-major: ncls x n_x n_y n_z sort keys.
+// Electro-chemical ranges on one box without size classes: the lattice of the lubrication
+// list when the far-pair pass fits it (sc.ec_ry, sc.ec_rz > 0), else that of the whole set.
 bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, double amin, double cf,
                 double rext, double cell_scale, bool sized, int row_slots, SizeClasses &sc, std::string &why)
 {
@@ -393,6 +397,26 @@ bool lattice_of(std::vector<BoxParams> &boxes, const std::vector<double> &amax, 
             return false;
         }
         return true;
+    }
+    // Electro-chemical ranges on one box: first the lattice of the lubrication list alone, the
+    // pairs beyond it on the far-pair pass, whose reach of R_y, R_z cell rows must stay below
+    // half the box (2 R + 1 distinct rows, and a box length beyond twice the reach along x);
+    // else the lattice of the whole pair set.
+    const bool try_split = rext > 0.0 && cf >= 1.0 && boxes.size() == 1;
+    if (try_split) {
+        std::vector<BoxParams> trial = boxes;
+        if (lattice_of(trial, amax, amin, cf, 0.0, cell_scale, false, row_slots, sc, why)) {
+            const BoxParams &G = trial[0];
+            const double reach = (2.0 * amax[0] + rext) * (1.0 + 1e-9);
+            const int ry = (int)std::ceil(reach / G.cw[1]), rz = (int)std::ceil(reach / G.cw[2]);
+            if (G.nc[1] >= 2 * ry + 1 && G.nc[2] >= 2 * rz + 1 && G.L[0] >= 2.0 * reach + G.cw[0]) {
+                boxes = trial;
+                sc.ec_ry = ry;
+                sc.ec_rz = rz;
+                return true;
+            }
+        }
+        sc = SizeClasses{};
     }
     int64_t ncell = 0;
     int nrow = 0;
@@ -476,6 +500,18 @@ dss_status setup_lattice(dss_handle *h)
         P.cls_add = sc.cls_add;
         P.wave_cls = h->tune.wave_class > 0 ? h->tune.wave_class : 3;
         h->sized_grid[0] = h->sized_grid[1] = 0;
+        // electro-chemical far pairs: one k_pairs_ec workgroup per kBlock / kEcLanes particles,
+        // whose stress partials follow the cell rows' records of the box
+        P.ec_split = sc.ec_ry > 0 ? 1 : 0;
+        P.ec_ry = sc.ec_ry;
+        P.ec_rz = sc.ec_rz;
+        P.ec_amax = h->box_amax[0];
+        h->ec_grid = 0;
+        if (P.ec_split) {
+            h->ec_grid = (int)((h->N * kEcLanes + kBlock - 1) / kBlock);
+            h->boxes[0].nrec += h->ec_grid;
+            max_rows_box = h->boxes[0].nrec;
+        }
         if (sized) {
             ncell *= sc.ncls;
             int64_t n_big = 0;
@@ -558,7 +594,8 @@ dss_status setup_lattice(dss_handle *h)
             const BoxParams &G = h->boxes[b];
             lmax = std::max(lmax, std::max(G.L[0], std::max(G.L[1], G.L[2])));
             const double a2 = 2.0 * h->box_amax[b];
-            rcmax = std::max(rcmax, P.ec ? std::max(h->prm.cutoff_factor * a2, a2 + P.rext) : h->prm.cutoff_factor * a2);
+            rcmax = std::max(rcmax, (P.ec && !P.ec_split) ? std::max(h->prm.cutoff_factor * a2, a2 + P.rext)
+                                                          : h->prm.cutoff_factor * a2);
         }
         const double u = std::ldexp(1.0, -24);
         P.pf_m2 = (float)(2.0 * (2.0 * rcmax * 49.0 * u * lmax + 6.0 * u * rcmax * rcmax));
@@ -613,6 +650,15 @@ void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
                               h->omg[buf], h->fb(), H, h->clk, h->partials, h->sized_grid[1], h->tune.queue_cap,
                               h->pairs, h->pair_count);
         return;
+    }
+    if (h->P.ec_split) {
+        // the far electro-chemical pairs first: plain stores into the atomic record, which the
+        // deferred rows below add to
+        TimedLaunch t(h, 8);
+        const BoxParams &G = h->boxes[0];
+        hipExtLaunchKernelGGL(k_pairs_ec<Sum>, dim3(h->ec_grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P,
+                              h->d_boxes, h->cell_start, h->pa[buf], h->omg[buf], h->ft_x, h->clk, h->partials,
+                              G.row_off + G.nc[1] * G.nc[2], h->pairs, h->pair_count);
     }
     {
         TimedLaunch t(h, 3);
@@ -1420,6 +1466,8 @@ dss_status dss_get_box_info(dss_handle *h, int32_t box, dss_box_info *info)
     info->shear_rate = G.gd;
     double t = (double)c.step * h->prm.dt;
     info->le_offset = std::fmod(G.gd * G.L[1] * t, G.L[0]);
+    info->ec_far_rows[0] = h->P.ec_split ? h->P.ec_ry : 0;
+    info->ec_far_rows[1] = h->P.ec_split ? h->P.ec_rz : 0;
     return DSS_OK;
 }
 

@@ -58,6 +58,10 @@ struct DevParams {
     double kr, mu_r;                // rolling spring stiffness and Coulomb coefficient (kr = 0: off)
     double inv_kt, inv_kr;          // 1 / kt, 1 / kr (0 when the spring is off)
     double wave_amp;                // amplitude W of the wavy shear, eq. uinf (0: simple shear)
+    int ec_split;                   // with ec: the lattice and the pair kernels cover the lubrication
+                                    //   list c (a_i + a_j); k_pairs_ec takes the pairs beyond it
+    int ec_ry, ec_rz;               // with ec_split: reach of k_pairs_ec in cell rows along y and z
+    double ec_amax;                 // with ec_split: largest radius
     float pf_m2;                    // margin on r^2 of the FP32 candidate pre-test of k_pairs
 };
 
@@ -167,7 +171,7 @@ __device__ __forceinline__ bool listed(const DevParams &P, double dx, double dy,
 #pragma clang fp contract(off)
     r2 = (dx * dx + dy * dy) + dz * dz;
     double rc = P.cf * (aa + ab);
-    if (P.ec) rc = fmax(rc, (aa + ab) + P.rext);
+    if (P.ec && !P.ec_split) rc = fmax(rc, (aa + ab) + P.rext);
     return r2 < rc * rc;
 }
 
@@ -379,8 +383,8 @@ __global__ void __launch_bounds__(1024) k_scan_add(int *__restrict__ cell_start,
 //   vel_is_half = 1: vel holds the half-step velocity u^{n-1/2} of the forces, and
 //   u^n = u^{n-1/2} + dt/2 F^n / m completes the previous step.
 // The atomic force record is read, and cleared for the next evaluation, only when the last
-// evaluation deferred rows to the per-particle path (clk->deferred > 0); otherwise it is
-// already zero.
+// evaluation deferred rows to the per-particle path (clk->deferred > 0) or k_pairs_ec wrote
+// it (ec_split); otherwise it is already zero.
 // ----------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams *__restrict__ boxes,
                                                      double4 *__restrict__ pa, double4 *__restrict__ vel,
@@ -406,7 +410,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
     double I = 0.4 * m * a * a;
     double f[6];
     total_ft(B, p, f, false);
-    if (clk->deferred) {
+    if (clk->deferred || P.ec_split) {
         double e[6];
         load_ft(B.x + 6LL * p, e);
 #pragma unroll
@@ -1823,7 +1827,7 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
     // the other pairs first and the probable contacts last (no atomics).
     if (!T.ovf) {
         const float Lx = (float)G.L[0], Ly = (float)G.L[1], Lz = (float)G.L[2], dl = (float)delta;
-        const float cf = (float)P.cf, rx = P.ec ? (float)P.rext : 0.0f, m2 = P.pf_m2;
+        const float cf = (float)P.cf, rx = (P.ec && !P.ec_split) ? (float)P.rext : 0.0f, m2 = P.pf_m2;
         auto test = [&](unsigned wd) -> int {
             const int jl = (int)(wd & 0x3fffu);
             const int il = (int)((wd >> 14) & 0xfffu);
@@ -1987,6 +1991,193 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_rows(DevParams P, const Box
         reduce_tally(tally, T.red, partials, P.pstride, grow);
         __syncthreads();
     }
+}
+
+// ----------------------------------------------------------------------------------
+// k_pairs_ec: with the electro-chemical ranges (Fig. elch: repulsion, eq. rep, while the
+// surface distance is below 20 lambda_D, attraction, eq. att, below 4 a0) on a lattice sized
+// for the lubrication list alone, the pairs beyond that list, c (a_i + a_j) <= |r| <
+// a_i + a_j + rext.  Such a pair carries only the central electro-chemical force (no
+// lubrication, no contact since c >= 1, no torque).  Each particle gathers its own force over
+// the cell rows within its reach a_i + a_max + rext (rows whose y-z distance exceeds it are
+// skipped; a row reached across a y face is searched around the x shifted by the
+// Lees-Edwards offset, as in the half shell), so every pair is seen from both sides and
+// nothing is accumulated across particles: the force goes to the atomic record by a plain
+// store (the row tiles' deferred rows add to it afterwards).  kEcLanes consecutive lanes share
+// a particle, each taking every kEcLanes-th row of its (2 R_z + 1) x (2 R_y + 1) rows, and
+// their sums are combined by a fixed butterfly, so that enough wavefronts are in flight to
+// cover the latency of the candidate loads.  A lane only tests its candidates and keeps the
+// far ones in LDS; their forces are taken when some lane of the wavefront could overflow its
+// kEcBuf entries (and at the end), by all lanes at once, so the force arithmetic runs about
+// once per far pair instead of once per candidate of the wavefront.  The split of the pair set is exact: the tiles
+// take r^2 < (c s)^2 and this kernel (c s)^2 <= r^2 < (s + rext)^2 with the same FP64 r^2
+// (the nearest image is antisymmetric), whose union is the list r^2 < max(c s, s + rext)^2.
+// Each side adds half of the pair's stresslet r (x) F_i; the pair is counted and recorded by
+// its smaller slot.  Sum: the stress and pair count of the workgroup go to partial record
+// rec0 + block.
+// ----------------------------------------------------------------------------------
+constexpr int kEcLanes = 8;
+constexpr int kEcBuf = 16;  // far partners a lane holds before their forces are taken
+constexpr int kEcChunk = 4;  // candidate loads of a lane in flight together
+
+// Central electro-chemical force of a far pair (i, j) on i, r = x_j - x_i (eqs. rep, att).
+__device__ __forceinline__ double ec_far_force(const DevParams &P, double dist, double ai, double aj)
+{
+    const double h = dist - ai - aj;
+    const double abar = 2.0 * ai * aj / (ai + aj);
+    double fe = 0.0;
+    if (P.fer != 0.0 && h < P.rep_rng) fe -= P.fer_a0 * abar * (P.lamd > 0.0 ? exp(-h * P.inv_lamd) : 0.0);
+    if (P.ham != 0.0 && h < P.att_rng) {
+        const double e = P.eps_vdw * abar;
+        fe += P.ham * abar / (12.0 * (h * h + e * e));
+    }
+    return fe;
+}
+
+template <bool Sum>
+__global__ void __launch_bounds__(kBlock) k_pairs_ec(DevParams P, const BoxParams *__restrict__ boxes,
+                                                      const int *__restrict__ cell_start,
+                                                      const double4 *__restrict__ pa,
+                                                      const double4 *__restrict__ omg, double *__restrict__ fx,
+                                                      DevClock *__restrict__ clk, double *__restrict__ partials,
+                                                      int rec0, int *__restrict__ pair_out,
+                                                      unsigned long long *__restrict__ pair_count)
+{
+    __shared__ double red[kBlock / 64][12];
+    __shared__ int fbuf[kEcBuf][kBlock];  // far partners of each lane, taken in wavefront-uniform flushes
+    const int t = threadIdx.x;
+    const int sub = t & (kEcLanes - 1);
+    const int i = (blockIdx.x * kBlock + t) / kEcLanes;
+    const BoxParams G = boxes[0];
+    PairTally tally;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
+    tally.npair = tally.ncont = 0;
+    tally.fill = 0;
+    double f[3] = {0.0, 0.0, 0.0};
+    const bool on = i < P.N;
+    const double4 Xi = on ? pa[i] : make_double4(0.0, 0.0, 0.0, 1.0);
+    const double delta = le_offset(P, G, clk->step);
+    const int idi = (on && P.record_pairs) ? (int)omg[i].w : 0;
+    int nb = 0;
+    // forces of the buffered far partners (every lane of the wavefront at once)
+    auto flush = [&]() {
+        for (int b = 0; b < nb; ++b) {
+            const int j = fbuf[b][t];
+            const double4 Xj = pa[j];
+            double dx, dy_, dz_;
+            min_image(G, delta, Xi.x, Xi.y, Xi.z, Xj.x, Xj.y, Xj.z, dx, dy_, dz_);
+            double r2;
+            {
+#pragma clang fp contract(off)
+                r2 = (dx * dx + dy_ * dy_) + dz_ * dz_;
+            }
+            const double dist = sqrt(r2);
+            const double g = ec_far_force(P, dist, Xi.w, Xj.w) / dist;
+            const double F[3] = {g * dx, g * dy_, g * dz_};
+            f[0] += F[0];
+            f[1] += F[1];
+            f[2] += F[2];
+            if constexpr (Sum) {
+                const double r[3] = {dx, dy_, dz_};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) tally.S[3 * a + c] += 0.5 * r[a] * F[c];
+            }
+            if (i < j) {
+                ++tally.npair;
+                if (P.record_pairs) record_pair(P, idi, (int)omg[j].w, pair_out, pair_count, clk);
+            }
+        }
+        nb = 0;
+    };
+    const int nxc = G.nc[0], nyc = G.nc[1], nzc = G.nc[2];
+    const int cy = cell_coord(Xi.y, G.cw[1], nyc), cz = cell_coord(Xi.z, G.cw[2], nzc);
+    const double reach = Xi.w + P.ec_amax + P.rext;  // >= a_i + a_j + rext for every j
+    const int ny = 2 * P.ec_ry + 1, nrows = on ? ny * (2 * P.ec_rz + 1) : 0;
+    for (int q = sub; q < nrows; q += kEcLanes) {
+        const int dz = q / ny - P.ec_rz, dy = q - (q / ny) * ny - P.ec_ry;
+        const int zu = cz + dz, yu = cy + dy;
+        const double zlo = (double)zu * G.cw[2], ylo = (double)yu * G.cw[1];
+        const double ez = fmax(0.0, fmax(zlo - Xi.z, Xi.z - (zlo + G.cw[2])));
+        const double ey = fmax(0.0, fmax(ylo - Xi.y, Xi.y - (ylo + G.cw[1])));
+        const double e2 = ey * ey + ez * ez;
+        if (e2 >= reach * reach) continue;
+        const int zz = zu < 0 ? zu + nzc : (zu >= nzc ? zu - nzc : zu);
+        const int cross = yu >= nyc ? 1 : (yu < 0 ? -1 : 0);
+        const int yy = yu < 0 ? yu + nyc : (yu >= nyc ? yu - nyc : yu);
+        // images across the top face are displaced by +delta: look around x - delta; a partner
+        // within reach lies within sqrt(reach^2 - e^2) along x of the row at y-z distance e
+        const double xs = Xi.x + (cross > 0 ? -delta : (cross < 0 ? delta : 0.0));
+        const double hw = sqrt(reach * reach - e2);
+        const int xlo = (int)floor((xs - hw) / G.cw[0]);
+        const int xhi = (int)floor((xs + hw) / G.cw[0]);
+        int span = xhi - xlo + 1;
+        // a window of the whole row (never on a lattice that passes the host's check) takes the
+        // nearest image candidate by candidate; otherwise every candidate of a part has the
+        // image of the part: y and z shifts of the row, the Lees-Edwards shift of a row across
+        // a y face, and the period of the part along x.  These are the operations min_image
+        // applies to a partner within reach (the periodic shifts are exact), so r^2 is the same
+        // to the bit; a partner beyond reach stays beyond it under either image.
+        const bool whole = span >= nxc;
+        span = whole ? nxc : span;
+        const int w0 = xlo >= 0 ? xlo / nxc : -((-xlo + nxc - 1) / nxc);  // floor(xlo / n_x)
+        int xl = xlo - w0 * nxc;
+        const double sy = cross > 0 ? G.L[1] : (cross < 0 ? -G.L[1] : 0.0);
+        const double sxd = cross > 0 ? delta : (cross < 0 ? -delta : 0.0);
+        const double sz = zu >= nzc ? G.L[2] : (zu < 0 ? -G.L[2] : 0.0);
+        const int rbase = G.cell_off + (zz * nyc + yy) * nxc;
+        for (int part = 0; part < 2 && span > 0; ++part) {
+            const int len = (xl + span <= nxc) ? span : nxc - xl;
+            const int jb = cell_start[rbase + xl];
+            const int je = cell_start[rbase + xl + len];
+            const double sxw = (double)(w0 + part) * G.L[0];
+            // candidates in chunks of kEcChunk whose loads are in flight together
+            for (int j0 = jb; j0 < je; j0 += kEcChunk) {
+                if (__any(nb > kEcBuf - kEcChunk)) flush();
+                double4 Xc[kEcChunk];
+#pragma unroll
+                for (int u = 0; u < kEcChunk; ++u) Xc[u] = pa[j0 + u < je ? j0 + u : j0];
+#pragma unroll
+                for (int u = 0; u < kEcChunk; ++u) {
+                    const int j = j0 + u;
+                    bool far;
+                    {
+#pragma clang fp contract(off)
+                        double dx, dy_, dz_;
+                        if (whole) {
+                            min_image(G, delta, Xi.x, Xi.y, Xi.z, Xc[u].x, Xc[u].y, Xc[u].z, dx, dy_, dz_);
+                        } else {
+                            dx = ((Xc[u].x - Xi.x) + sxd) + sxw;
+                            dy_ = (Xc[u].y - Xi.y) + sy;
+                            dz_ = (Xc[u].z - Xi.z) + sz;
+                        }
+                        const double r2 = (dx * dx + dy_ * dy_) + dz_ * dz_;
+                        const double s = Xi.w + Xc[u].w;
+                        const double rl = P.cf * s, re = s + P.rext;
+                        far = j < je && j != i && !(r2 < rl * rl) && r2 < re * re;
+                    }
+                    if (far) fbuf[nb++][t] = j;
+                }
+            }
+            xl = 0;
+            span -= len;
+        }
+    }
+    flush();
+    // the particle's force: the kEcLanes partial sums combined in a fixed order
+#pragma unroll
+    for (int o = 1; o < kEcLanes; o <<= 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[c] += __shfl_xor(f[c], o, 64);
+    }
+    if (on && sub == 0) {
+        const double out[6] = {f[0], f[1], f[2], 0.0, 0.0, 0.0};
+        store_ft(fx + 6LL * i, out);
+        if (!finite6(out)) atomicOr(&clk->err, kErrNonFinite);
+    }
+    if constexpr (Sum) reduce_tally(tally, red, partials, P.pstride, rec0 + blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------------

@@ -58,7 +58,7 @@ class BoxInfo(ctypes.Structure):
     _fields_ = [("n_particles", ctypes.c_int64), ("first_id", ctypes.c_int64), ("cells", ctypes.c_int32 * 3),
                 ("first_cell", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("n_contacts", ctypes.c_int64),
                 ("max_row_fill", ctypes.c_int32), ("size_classes", ctypes.c_int32), ("L", ctypes.c_double * 3),
-                ("shear_rate", ctypes.c_double), ("le_offset", ctypes.c_double)]
+                ("shear_rate", ctypes.c_double), ("le_offset", ctypes.c_double), ("ec_far_rows", ctypes.c_int32 * 2)]
 
 
 class Tuning(ctypes.Structure):
@@ -281,7 +281,7 @@ class Simulation:
         return {"n_particles": inf.n_particles, "first_id": inf.first_id, "cells": tuple(inf.cells),
                 "first_cell": inf.first_cell, "n_pairs": inf.n_pairs, "n_contacts": inf.n_contacts,
                 "max_row_fill": inf.max_row_fill, "size_classes": inf.size_classes, "L": tuple(inf.L),
-                "shear_rate": inf.shear_rate, "le_offset": inf.le_offset}
+                "shear_rate": inf.shear_rate, "le_offset": inf.le_offset, "ec_far_rows": tuple(inf.ec_far_rows)}
 
     def cells(self):
         dims = np.zeros(3, np.int32)
@@ -313,7 +313,7 @@ class Simulation:
         return pr[order], xi[order]
 
     KERNELS = ("k_predict", "k_scan", "k_scatter", "k_pairs", "k_finish", "k_pairs_vjp", "k_integrate_vjp",
-               "k_pairs_rows")
+               "k_pairs_rows", "k_pairs_ec")
 
     def set_tuning(self, cell_scale=None, tile_scale=None, tiled=None, graph=None, sized=None, wave_class=None,
                    queue_cap=None):

@@ -71,7 +71,7 @@ def test_create_batch_rejects_mixed_physics_without_touching_the_device():
     assert not h.value
     arr = (dss.Params * 2)(dss.make_params(a), dss.make_params(b))
     assert lib.dss_create_batch(arr, 0, None, ctypes.byref(h)) == 1
-    assert ctypes.sizeof(dss.BoxInfo) == 8 + 8 + 12 + 4 + 8 + 8 + 4 + 4 + 24 + 8 + 8
+    assert ctypes.sizeof(dss.BoxInfo) == 8 + 8 + 12 + 4 + 8 + 8 + 4 + 4 + 24 + 8 + 8 + 8
 
 
 @pytest.mark.parametrize("over", [dict(wave_amp=2.0, wave_n=0.5), dict(wave_amp=2.0, wave_n=0.0),
