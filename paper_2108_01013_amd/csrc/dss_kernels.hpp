@@ -1498,6 +1498,7 @@ __device__ __forceinline__ void reduce_fill(int fill, double (*red)[12], double 
 // ----------------------------------------------------------------------------------
 constexpr int kPairBlock = 192;
 constexpr int kPairWaves = kPairBlock / 64;
+constexpr int kHeadPre = 3;  // row heads per lane requested before A2
 
 struct TileShared {
     int rs[5], re[5], ro[6], rbase[5], rcross[5];
@@ -1654,6 +1655,57 @@ __device__ __forceinline__ void row_bounds(const BoxParams &G, int row, const in
     __syncthreads();
 }
 
+// row_bounds with the cell starts of the five rows staged in LDS (csl, 5 (n_x + 1) entries:
+// row r's start of cell c at csl[r (n_x + 1) + c], its end at csl[r (n_x + 1) + n_x]), so that
+// the windows of A1 are read from LDS.  Ends with a barrier.
+__device__ __forceinline__ void row_bounds_staged(const BoxParams &G, int row, const int *__restrict__ cell_start,
+                                                  TileShared &T, int *csl)
+{
+    const int t = threadIdx.x;
+    const int nxc = G.nc[0], nyc = G.nc[1], nzc = G.nc[2];
+    const int cz = row / nyc, cy = row - (row / nyc) * nyc;
+    for (int k = t; k < 5 * (nxc + 1); k += blockDim.x) {
+        const int r = k / (nxc + 1), c = k - r * (nxc + 1);
+        int dz, dy;
+        shell_row(r, dz, dy);
+        int zz = cz + dz;
+        zz = zz >= nzc ? zz - nzc : zz;
+        int yy = cy + dy;
+        const int cross = yy >= nyc ? 1 : (yy < 0 ? -1 : 0);
+        yy = yy < 0 ? yy + nyc : (yy >= nyc ? yy - nyc : yy);
+        const int base = G.cell_off + (zz * nyc + yy) * nxc;
+        csl[k] = cell_start[base + c];
+        if (c == 0) {
+            T.rbase[r] = base;
+            T.rcross[r] = cross;
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        int o = 0;
+        for (int r = 0; r < 5; ++r) {
+            T.rs[r] = csl[r * (nxc + 1)];
+            T.re[r] = csl[r * (nxc + 1) + nxc];
+            T.ro[r] = o;
+            o += T.re[r] - T.rs[r];
+        }
+        T.ro[5] = o;
+        T.qn = 0;
+        T.nc = 0;
+        T.ovf = 0;
+    }
+    __syncthreads();
+}
+
+// Workgroup barrier that orders LDS accesses only: global loads in flight stay in flight
+// (__syncthreads also waits for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Cell row of workgroup b of n.  Workgroups are dispatched to the 8 XCDs in turn (b mod 8),
 // each XCD with its own L2; this bijection gives every XCD one contiguous run of rows, so the
 // shell rows a workgroup stages were mostly fetched into the same L2 by its neighbours.
@@ -1725,7 +1777,13 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
     for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
     tally.npair = tally.ncont = 0;
     tally.fill = 0;
-    row_bounds(G, row, cell_start, T);
+    // the cell starts of the five rows in LDS (in the queue's space, free until A2) when they fit
+    int *const csl = reinterpret_cast<int *>(V.queue);
+    const bool cs_staged = 5 * (nxc + 1) <= P.qcap;
+    if (cs_staged)
+        row_bounds_staged(G, row, cell_start, T, csl);
+    else
+        row_bounds(G, row, cell_start, T);
     const int n_own = T.re[0] - T.rs[0];
     const int total = T.ro[5];
     // a row beyond the tile capacities (or one that hits a tile limit below) is left to
@@ -1772,11 +1830,19 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
             rr[u] = on ? task / n_own : 0;
             ill[u] = on ? task - rr[u] * n_own : 0;
             W[u] = task_window(G, T, rr[u], V.owncx[ill[u]], delta);
-            const int base = T.rbase[rr[u]];
-            cs4[u][0] = cell_start[base + W[u].xl0];
-            cs4[u][1] = cell_start[base + W[u].xl0 + W[u].len0];
-            cs4[u][2] = cell_start[base];
-            cs4[u][3] = cell_start[base + W[u].len1];
+            if (cs_staged) {
+                const int *cr = csl + rr[u] * (nxc + 1);
+                cs4[u][0] = cr[W[u].xl0];
+                cs4[u][1] = cr[W[u].xl0 + W[u].len0];
+                cs4[u][2] = cr[0];
+                cs4[u][3] = cr[W[u].len1];
+            } else {
+                const int base = T.rbase[rr[u]];
+                cs4[u][0] = cell_start[base + W[u].xl0];
+                cs4[u][1] = cell_start[base + W[u].xl0 + W[u].len0];
+                cs4[u][2] = cell_start[base];
+                cs4[u][3] = cell_start[base + W[u].len1];
+            }
         }
 #pragma unroll
         for (int u = 0; u < kTaskBatch; ++u) {
@@ -1820,6 +1886,20 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
         return;
     }
 
+    // the history row heads of the first kHeadPre staged particles of every lane are requested
+    // now, so that their loads are in flight during A2; they are written over the FP32
+    // records (which A2 still reads) after it
+    int4 hpre[kHeadPre];
+#pragma unroll
+    for (int m = 0; m < kHeadPre; ++m) {
+        const int k = t + m * kPairBlock;
+        if (k < total) {
+            const int p = V.prevs[k];
+            const int *kr = H.key_old + (long long)p * P.M;
+            hpre[m] = make_int4(p, H.cnt_old[p], kr[0], kr[P.M > 1 ? 1 : 0]);
+        }
+    }
+
     // A2: the candidates in lane-strided order (lane t pre-tests k = t + kPairBlock j, two per
     // pass), every lane running the same straight-line FP32 test with the shifts of the
     // candidate's range.  Survivors are kept as bit masks per lane (all, and the probable
@@ -1857,7 +1937,7 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
             if (lane >= o) incl += u;
         }
         if (lane == 63) T.wsum[wid] = incl;
-        __syncthreads();
+        lds_barrier();  // the row heads requested above stay in flight
         int q = incl - c;
         int tot = 0;
         for (int w = 0; w < kPairWaves; ++w) {
@@ -1879,7 +1959,7 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
             if (t == 0) T.qn = nhit;
         }
     }
-    __syncthreads();
+    lds_barrier();
     if (T.ovf) {
         // a tile limit was hit: discard the tile and defer the row to the per-particle path
         defer_row();
@@ -1889,7 +1969,12 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
     // the FP32 records are dead: the history row head of every staged particle (its slot at
     // the last step, row count, first two keys) takes their place, so that B finds most stored
     // stretches without a chain of global loads; the accumulators are cleared
-    for (int k = t; k < total; k += kPairBlock) {
+#pragma unroll
+    for (int m = 0; m < kHeadPre; ++m) {
+        const int k = t + m * kPairBlock;
+        if (k < total) V.heads[k] = hpre[m];
+    }
+    for (int k = t + kHeadPre * kPairBlock; k < total; k += kPairBlock) {
         const int p = V.prevs[k];
         const int *kr = H.key_old + (long long)p * P.M;
         V.heads[k] = make_int4(p, H.cnt_old[p], kr[0], kr[P.M > 1 ? 1 : 0]);
