@@ -180,3 +180,20 @@ def test_batch_full_sweep_sampled():
     assert sim.N == sum(len(w.rad) for w in ws) > 1_000_000
     assert contacts > 0
     sim.close()
+
+
+def test_batch_ec_ranges_lockstep():
+    """Electro-chemical ranges with attraction on a batch of two boxes: batches keep the whole
+    pair set on their lattice (no far-pair pass), so every cell row is taken on the per-particle
+    path.  Three lockstep steps per box against the oracle: positions and pair sets
+    bit-identical, F, T, Sigma and history within 1e-10."""
+    ws = []
+    for n, phi, seed in ((3000, 0.45, 61), (4000, 0.5, 62)):
+        w = synth.bidisperse_box(n, phi, seed=seed)
+        p = dict(w.params, hamaker=1e-3, F_ER=1.0, ec_ranges=True)
+        ws.append(synth.Workload(f"bidisperse N={n} phi={phi}, attraction", w.x, w.rad, w.L, p))
+    say("case: batch of 2 boxes with electro-chemical ranges")
+    sim, contacts = run_lockstep(ws, [0.5, 2.0], steps=3, use_cells=True)
+    for b in range(2):
+        assert sim.box_info(b)["ec_far_rows"] == (0, 0)
+    sim.close()
