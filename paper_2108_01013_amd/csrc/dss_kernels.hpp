@@ -1487,9 +1487,12 @@ __device__ __forceinline__ void reduce_fill(int fill, double (*red)[12], double 
 //   C   own particles: Stokes terms, own force record, history row sorted by partner id;
 //       particles of the other four shell rows: partner-side force records.
 // LDS: the candidate list and the staged slots at the last step live in the force
-// accumulators' space (cleared after H), and the row heads in that of the FP32 records, so that
-// four workgroups fit in the 160 KB of a CU; with 3 wavefronts each they hold 12 wavefronts
-// per CU (the register file holds three per SIMD), one cell row per workgroup slot.
+// accumulators' space (cleared after H), the row heads in that of the FP32 records, and the
+// cell starts of the five rows (read by A1) in that of the pair queue, so that four
+// workgroups fit in the 160 KB of a CU; with 3 wavefronts each they hold 12 wavefronts per CU
+// (the register file holds three per SIMD), one cell row per workgroup slot (the host keeps
+// the rows of one box below the slots).  The row heads are requested before A2, whose
+// barriers order LDS only, so their loads overlap the candidate tests.
 // Tile capacities (P.own_cap, P.stage_cap, P.qcap) are sized from the mean row occupancy; a
 // row beyond them takes the per-particle path (k_pairs_rows).  Sum: the row's stress and
 // counters are reduced into its partial record.  Steps whose stress is not summed take
@@ -2091,14 +2094,15 @@ __global__ void __launch_bounds__(kBlock, 2) k_pairs_rows(DevParams P, const Box
 // store (the row tiles' deferred rows add to it afterwards).  kEcLanes consecutive lanes share
 // a particle, each taking every kEcLanes-th row of its (2 R_z + 1) x (2 R_y + 1) rows, and
 // their sums are combined by a fixed butterfly, so that enough wavefronts are in flight to
-// cover the latency of the candidate loads.  A lane only tests its candidates and keeps the
-// far ones in LDS; their forces are taken when some lane of the wavefront could overflow its
-// kEcBuf entries (and at the end), by all lanes at once, so the force arithmetic runs about
-// once per far pair instead of once per candidate of the wavefront.  The split of the pair set is exact: the tiles
-// take r^2 < (c s)^2 and this kernel (c s)^2 <= r^2 < (s + rext)^2 with the same FP64 r^2
-// (the nearest image is antisymmetric), whose union is the list r^2 < max(c s, s + rext)^2.
-// Each side adds half of the pair's stresslet r (x) F_i; the pair is counted and recorded by
-// its smaller slot.  Sum: the stress and pair count of the workgroup go to partial record
+// cover the latency of the candidate loads.  A lane only tests its candidates (four loads in
+// flight, each with the image of its window part) and keeps the far ones in LDS; their forces
+// are taken when some lane of the wavefront could overflow its kEcBuf entries (and at the
+// end), by all lanes at once, so the force arithmetic runs about once per far pair instead
+// of once per candidate of the wavefront.  The split of the pair set is exact: the tiles take
+// r^2 < (c s)^2 and this kernel (c s)^2 <= r^2 < (s + rext)^2 with the same FP64 r^2 (the
+// nearest image is antisymmetric), whose union is the list r^2 < max(c s, s + rext)^2.  Each
+// side adds half of the pair's stresslet r (x) F_i; the pair is counted and recorded by its
+// smaller slot.  Sum: the stress and pair count of the workgroup go to partial record
 // rec0 + block.
 // ----------------------------------------------------------------------------------
 constexpr int kEcLanes = 8;
