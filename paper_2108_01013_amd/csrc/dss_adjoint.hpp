@@ -126,23 +126,19 @@ __global__ void __launch_bounds__(kBlock) k_canon_zero(int N, int M, const int *
     for (int k = 0; k < sw * n; ++k) r[k] = 0.0;
 }
 
-__device__ __forceinline__ void atomic_add3(double *p, double a, double b, double c)
-{
-    atomicAdd(p, a);
-    atomicAdd(p + 1, b);
-    atomicAdd(p + 2, c);
-}
-
 // ----------------------------------------------------------------------------------
 // k_pairs_vjp: reverse of the pair terms of one force evaluation (time index `step`).
-// One lane per listed pair (a, b), a < b, r = x_b - x_a (Lees-Edwards minimum image):
-// the stretch before the step is looked up in the canonical rows of the previous
-// history, the cotangents of the pair's outputs are gathered (force cotangent
-// Fb_a - Fb_b since F_b = -F_a, torque cotangents, the stretch cotangent from the rows
-// after the step, the stress weights), and pair_vjp pulls them back.  Gradients are
-// added into ax, au, aw by id (FP64 atomics), the old-stretch adjoint is stored at the
-// contact's position in the previous rows, and the parameter gradients (mu, F_ER) are
-// summed per workgroup, then added once.
+// For a listed pair (a, b), a < b, r = x_b - x_a (Lees-Edwards minimum image), the
+// stretch before the step is looked up in the canonical rows of the previous history, the
+// cotangents of the pair's outputs are gathered (force cotangent Fb_a - Fb_b since
+// F_b = -F_a, torque cotangents, the stretch cotangent from the rows after the step, the
+// stress weights), and pair_vjp pulls them back (vjp_of_pair), one lane per pair.  The
+// cotangents of both particles' x, u, w are stored with the pair (18 doubles, plain
+// stores), and k_pairs_vjp_sum adds them to each particle over its recorded pairs (an
+// adjacency of integer codes built per evaluation: counts, their scan, and the lists written
+// by this kernel), so no FP64 atomics remain; the old-stretch adjoint is stored at the
+// contact's position in the previous rows, and the parameter gradients (mu, F_ER) are summed
+// per workgroup, then added once.
 // ----------------------------------------------------------------------------------
 struct VjpTape {
     const int *pairs;       // 2 x npairs (id_min, id_max)
@@ -153,75 +149,111 @@ struct VjpTape {
     int sw;                          // stretch entries per contact: 3, or 6 with the rolling stretch
 };
 
+// The reverse pass of recorded pair k of a tape entry: its ids (a < b), the position of its
+// stretch in the previous canonical rows (or -1), and its PairGrad.
+__device__ __forceinline__ void vjp_of_pair(const DevParams &P, const BoxParams &G, long long step, int k,
+                                            const VjpTape &tp, const double *__restrict__ xib_new,
+                                            const double *__restrict__ Fb, const double *__restrict__ Tb,
+                                            const double *__restrict__ Sb, int &a, int &b, long long &pold,
+                                            PairGrad &g)
+{
+    a = tp.pairs[2 * k];
+    b = tp.pairs[2 * k + 1];
+    const double delta = le_offset(P, G, step);
+    const double *xa = tp.x + 3LL * a, *xb = tp.x + 3LL * b;
+    double r[3];
+    min_image(G, delta, xa[0], xa[1], xa[2], xb[0], xb[1], xb[2], r[0], r[1], r[2]);
+    const int sw = tp.sw;
+    double xo[3] = {0.0, 0.0, 0.0}, xro[3] = {0.0, 0.0, 0.0};
+    pold = -1;
+    if (tp.key_old) {
+        pold = canon_find(tp.key_old, tp.cnt_old, P.M, a, b);
+        if (pold >= 0)
+            for (int c = 0; c < 3; ++c) {
+                xo[c] = tp.xi_old[sw * pold + c];
+                if (sw == 6) xro[c] = tp.xi_old[sw * pold + 3 + c];
+            }
+    }
+    PairBar bar;
+    for (int c = 0; c < 3; ++c) {
+        bar.Fi[c] = Fb[3LL * a + c] - Fb[3LL * b + c];
+        bar.Ti[c] = Tb[3LL * a + c];
+        bar.Tj[c] = Tb[3LL * b + c];
+        bar.xi[c] = 0.0;
+        bar.xr[c] = 0.0;
+    }
+    // branch of the forward run: a pair is a contact after the step iff its rows hold it,
+    // and the rows record whether its Coulomb cap and its rolling limit were active (at the
+    // initial evaluation, which commits no rows, the branch is recomputed)
+    int f_contact = -1, f_capped = -1, f_rcapped = -1;
+    if (tp.key_new) {
+        const long long pn = canon_find(tp.key_new, tp.cnt_new, P.M, a, b);
+        f_contact = pn >= 0 ? 1 : 0;
+        f_capped = pn >= 0 ? ((tp.key_new[pn] & kCapBit) ? 1 : 0) : 0;
+        f_rcapped = pn >= 0 ? ((tp.key_new[pn] & kRollCapBit) ? 1 : 0) : 0;
+        if (pn >= 0 && xib_new)
+            for (int c = 0; c < 3; ++c) {
+                bar.xi[c] = xib_new[sw * pn + c];
+                if (sw == 6) bar.xr[c] = xib_new[sw * pn + 3 + c];
+            }
+    }
+    for (int c = 0; c < 9; ++c) bar.S[c] = Sb ? Sb[c] : 0.0;
+    PairConst C;
+    C.k6 = P.k6; C.kn = P.kn; C.kt = P.kt; C.gn = P.gn; C.mu = P.mu; C.fer = P.fer; C.a0 = P.a0;
+    C.lamd = P.lamd; C.ham = P.ham; C.eps_vdw = P.eps_vdw; C.eps_lub = P.eps_lub; C.dt = P.dt;
+    C.ec = P.ec; C.cf = P.cf; C.rep_rng = P.rep_rng; C.att_rng = P.att_rng;
+    C.roll = sw == 6 ? 1 : 0; C.kr = P.kr; C.mu_r = P.mu_r;
+    pair_vjp(C, G.gd, r, tp.rad[a], tp.rad[b], xa[1], xb[1], tp.u + 3LL * a, tp.u + 3LL * b, tp.w + 3LL * a,
+             tp.w + 3LL * b, xo, bar, g, nullptr, f_contact, f_capped, xro, f_rcapped);
+}
+
+// Adjacency of the recorded pairs of a tape entry: k_adj_count counts the pairs of every id
+// (deg, zero on entry); after the exclusive scan deg -> off, k_pairs_vjp writes each pair's
+// code 2 k + side (side 0: the smaller id a, 1: b) into the list of each of its two ids (pos
+// zero on entry).
+// The order inside a list depends on scheduling; so does the order of the sums below it, as
+// with any floating-point accumulation on the GPU.
+__global__ void __launch_bounds__(kBlock) k_adj_count(int npairs, const int *__restrict__ pairs, int *__restrict__ deg)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npairs) return;
+    atomicAdd(&deg[pairs[2 * k]], 1);
+    atomicAdd(&deg[pairs[2 * k + 1]], 1);
+}
+
 __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, long long step, int npairs,
                                                       VjpTape tp, const double *__restrict__ xib_new,
                                                       double *__restrict__ xib_old, const double *__restrict__ Fb,
                                                       const double *__restrict__ Tb, const double *__restrict__ Sb,
-                                                      double *__restrict__ ax, double *__restrict__ au,
-                                                      double *__restrict__ aw, double *__restrict__ theta_b)
+                                                      double *__restrict__ gpair, double *__restrict__ theta_b,
+                                                      const int *__restrict__ off, int *__restrict__ pos,
+                                                      int *__restrict__ adj)
 {
     __shared__ double red[kBlock / 64][2];
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     double gmu = 0.0, gfer = 0.0;
     if (k < npairs) {
-        const int a = tp.pairs[2 * k], b = tp.pairs[2 * k + 1];
-        const double delta = le_offset(P, G, step);
-        const double *xa = tp.x + 3LL * a, *xb = tp.x + 3LL * b;
-        double r[3];
-        min_image(G, delta, xa[0], xa[1], xa[2], xb[0], xb[1], xb[2], r[0], r[1], r[2]);
-        const int sw = tp.sw;
-        double xo[3] = {0.0, 0.0, 0.0}, xro[3] = {0.0, 0.0, 0.0};
-        long long pold = -1;
-        if (tp.key_old) {
-            pold = canon_find(tp.key_old, tp.cnt_old, P.M, a, b);
-            if (pold >= 0)
-                for (int c = 0; c < 3; ++c) {
-                    xo[c] = tp.xi_old[sw * pold + c];
-                    if (sw == 6) xro[c] = tp.xi_old[sw * pold + 3 + c];
-                }
+        // the pair's entries in the adjacency lists of its two ids (their atomics overlap
+        // the pair's arithmetic)
+        {
+            const int a0 = tp.pairs[2 * k], b0 = tp.pairs[2 * k + 1];
+            adj[off[a0] + atomicAdd(&pos[a0], 1)] = 2 * k;
+            adj[off[b0] + atomicAdd(&pos[b0], 1)] = 2 * k + 1;
         }
-        PairBar bar;
-        for (int c = 0; c < 3; ++c) {
-            bar.Fi[c] = Fb[3LL * a + c] - Fb[3LL * b + c];
-            bar.Ti[c] = Tb[3LL * a + c];
-            bar.Tj[c] = Tb[3LL * b + c];
-            bar.xi[c] = 0.0;
-            bar.xr[c] = 0.0;
-        }
-        // branch of the forward run: a pair is a contact after the step iff its rows hold it,
-        // and the rows record whether its Coulomb cap and its rolling limit were active (at the
-        // initial evaluation, which commits no rows, the branch is recomputed)
-        int f_contact = -1, f_capped = -1, f_rcapped = -1;
-        if (tp.key_new) {
-            const long long pn = canon_find(tp.key_new, tp.cnt_new, P.M, a, b);
-            f_contact = pn >= 0 ? 1 : 0;
-            f_capped = pn >= 0 ? ((tp.key_new[pn] & kCapBit) ? 1 : 0) : 0;
-            f_rcapped = pn >= 0 ? ((tp.key_new[pn] & kRollCapBit) ? 1 : 0) : 0;
-            if (pn >= 0 && xib_new)
-                for (int c = 0; c < 3; ++c) {
-                    bar.xi[c] = xib_new[sw * pn + c];
-                    if (sw == 6) bar.xr[c] = xib_new[sw * pn + 3 + c];
-                }
-        }
-        for (int c = 0; c < 9; ++c) bar.S[c] = Sb ? Sb[c] : 0.0;
-        PairConst C;
-        C.k6 = P.k6; C.kn = P.kn; C.kt = P.kt; C.gn = P.gn; C.mu = P.mu; C.fer = P.fer; C.a0 = P.a0;
-        C.lamd = P.lamd; C.ham = P.ham; C.eps_vdw = P.eps_vdw; C.eps_lub = P.eps_lub; C.dt = P.dt;
-        C.ec = P.ec; C.cf = P.cf; C.rep_rng = P.rep_rng; C.att_rng = P.att_rng;
-        C.roll = sw == 6 ? 1 : 0; C.kr = P.kr; C.mu_r = P.mu_r;
+        int a, b;
+        long long pold;
         PairGrad g = {};
-        pair_vjp(C, G.gd, r, tp.rad[a], tp.rad[b], xa[1], xb[1], tp.u + 3LL * a, tp.u + 3LL * b, tp.w + 3LL * a,
-                 tp.w + 3LL * b, xo, bar, g, nullptr, f_contact, f_capped, xro, f_rcapped);
-        atomic_add3(ax + 3LL * a, -g.r[0], -g.r[1] + g.yi, -g.r[2]);
-        atomic_add3(ax + 3LL * b, g.r[0], g.r[1] + g.yj, g.r[2]);
-        atomic_add3(au + 3LL * a, g.ui[0], g.ui[1], g.ui[2]);
-        atomic_add3(au + 3LL * b, g.uj[0], g.uj[1], g.uj[2]);
-        atomic_add3(aw + 3LL * a, g.wi[0], g.wi[1], g.wi[2]);
-        atomic_add3(aw + 3LL * b, g.wj[0], g.wj[1], g.wj[2]);
+        vjp_of_pair(P, G, step, k, tp, xib_new, Fb, Tb, Sb, a, b, pold, g);
+        // the two sides: (x, u, w) cotangents of a, then of b
+        const double o[18] = {-g.r[0], -g.r[1] + g.yi, -g.r[2], g.ui[0], g.ui[1], g.ui[2], g.wi[0], g.wi[1], g.wi[2],
+                              g.r[0],  g.r[1] + g.yj,  g.r[2],  g.uj[0], g.uj[1], g.uj[2], g.wj[0], g.wj[1], g.wj[2]};
+        double2 *q = reinterpret_cast<double2 *>(gpair + 18LL * k);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) q[c] = make_double2(o[2 * c], o[2 * c + 1]);
         if (pold >= 0 && xib_old)
             for (int c = 0; c < 3; ++c) {
-                xib_old[sw * pold + c] = g.xo[c];
-                if (sw == 6) xib_old[sw * pold + 3 + c] = g.xro[c];
+                xib_old[tp.sw * pold + c] = g.xo[c];
+                if (tp.sw == 6) xib_old[tp.sw * pold + 3 + c] = g.xro[c];
             }
         gmu = g.mu;
         gfer = g.fer;
@@ -242,6 +274,30 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
         }
         atomicAdd(theta_b, s0);
         atomicAdd(theta_b + 1, s1);
+    }
+}
+
+// The pair cotangents of every particle summed over its recorded pairs (the adjacency of the
+// evaluation) and added to ax, au, aw: one lane per particle, one writer per entry.
+__global__ void __launch_bounds__(kBlock) k_pairs_vjp_sum(int N, const int *__restrict__ off,
+                                                          const int *__restrict__ adj,
+                                                          const double *__restrict__ gpair, double *__restrict__ ax,
+                                                          double *__restrict__ au, double *__restrict__ aw)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    double s[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int e1 = off[p + 1];
+    for (int e = off[p]; e < e1; ++e) {
+        const int code = adj[e];
+        const double *g = gpair + 18LL * (code >> 1) + 9 * (code & 1);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) s[c] += g[c];
+    }
+    for (int c = 0; c < 3; ++c) {
+        ax[3LL * p + c] += s[c];
+        au[3LL * p + c] += s[3 + c];
+        aw[3LL * p + c] += s[6 + c];
     }
 }
 

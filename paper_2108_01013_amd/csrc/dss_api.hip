@@ -1761,6 +1761,16 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     const int sw = stretch_width(h);
     HIPTRY(W.get(&xibA, sw * (size_t)N * M)); HIPTRY(W.get(&xibB, sw * (size_t)N * M));
     HIPTRY(W.get(&bkey, (size_t)N * M)); HIPTRY(W.get(&bcnt, N));
+    // adjacency of the recorded pairs (per evaluation): degrees, their scan (tiles of 16384
+    // ids, the multi-workgroup scan of the counting sort), fill positions, pair codes
+    const int adj_tiles = (int)((N + 1 + 16383) / 16384);
+    int *adeg = nullptr, *aoff = nullptr, *apos = nullptr, *aadj = nullptr, *atile = nullptr;
+    HIPTRY(W.get(&adeg, (size_t)adj_tiles * 16384)); HIPTRY(W.get(&aoff, (size_t)adj_tiles * 16384));
+    HIPTRY(W.get(&apos, (size_t)N)); HIPTRY(W.get(&aadj, 2 * (size_t)std::max<int64_t>(h->P.pair_cap, 1)));
+    HIPTRY(W.get(&atile, (size_t)std::max(adj_tiles, 16)));
+    double *agrad = nullptr;  // 18 cotangents per recorded pair
+    HIPTRY(W.get(&agrad, 18 * (size_t)std::max<int64_t>(h->P.pair_cap, 1)));
+    HIPTRY(hipMemsetAsync(adeg, 0, (size_t)adj_tiles * 16384 * sizeof(int), h->stream));
     double *zero_list[] = {xb, ub, wb, ax, au, aw, Fb, Tb, Fb2, Tb2};
     for (double *q : zero_list) HIPTRY(hipMemsetAsync(q, 0, n3 * sizeof(double), h->stream));
     HIPTRY(hipMemsetAsync(theta, 0, 2 * sizeof(double), h->stream));
@@ -1781,6 +1791,28 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     DevParams Prec = h->P;
     Prec.record_pairs = 1;
     const BoxParams G = h->boxes[0];
+    // the reverse of the pair terms of evaluation n from tape entry T1: the adjacency of its
+    // pairs, then the per-particle gather
+    auto pairs_vjp = [&](const TapeEntry &T1, const VjpTape &tp, int64_t n, const double *xin, double *xout,
+                         const double *sb) -> hipError_t {
+        const int np = (int)T1.npairs;
+        const int pg = std::max(1, (np + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_adj_count, dim3(pg), dim3(kBlock), 0, h->stream, np, (const int *)T1.pairs, adeg);
+        hipLaunchKernelGGL(k_scan<4>, dim3(adj_tiles), dim3(1024), 0, h->stream, adeg, aoff, h->clk, 0, atile);
+        hipLaunchKernelGGL(k_scan_add, dim3(adj_tiles), dim3(1024), 0, h->stream, aoff, (const int *)atile, 4 * 1024,
+                           h->clk, 0);
+        hipError_t e = hipMemsetAsync(apos, 0, (size_t)N * sizeof(int), h->stream);
+        if (e != hipSuccess) return e;
+        {
+            TimedLaunch tl(h, 5);
+            hipExtLaunchKernelGGL(k_pairs_vjp, dim3(pg), dim3(kBlock), 0, h->stream, tl.e0, tl.e1, 0, Prec, G,
+                                  (long long)n, np, tp, xin, xout, Fb, Tb, sb, agrad, theta, (const int *)aoff, apos,
+                                  aadj);
+        }
+        hipLaunchKernelGGL(k_pairs_vjp_sum, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, (const int *)aoff,
+                           (const int *)aadj, (const double *)agrad, ax, au, aw);
+        return hipGetLastError();
+    };
     double *xib_in = xibA, *xib_out = xibB;
     h->P.record_pairs = 1;
     for (int64_t seg = nck - 1; seg >= 0; --seg) {
@@ -1821,13 +1853,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
                                M, T0.ccnt, xib_out);
             VjpTape tp{T1.pairs, T1.x, T1.u, T1.w, rad, T0.ckey, T0.ccnt, T0.cxi, T1.ckey, T1.ccnt, sw};
             const bool sampled = n >= first && (n - first) % stress_every == 0;
-            const int pgrid = (int)std::max<int64_t>(1, (T1.npairs + kBlock - 1) / kBlock);
-            {
-                TimedLaunch tl(h, 5);
-                hipExtLaunchKernelGGL(k_pairs_vjp, dim3(pgrid), dim3(kBlock), 0, h->stream, tl.e0, tl.e1, 0, Prec, G,
-                                      (long long)n, (int)T1.npairs, tp, xib_in, xib_out, Fb, Tb,
-                                      sampled ? Sb : (const double *)nullptr, ax, au, aw, theta);
-            }
+            HIPTRY(pairs_vjp(T1, tp, n, xib_in, xib_out, sampled ? Sb : (const double *)nullptr));
             const double c = (n - 1 == n0) ? 0.5 : 1.0;
             {
                 TimedLaunch ti(h, 6);
@@ -1848,10 +1874,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         // the evaluation at the initial state; the stretch of the initial history is held fixed
         const TapeEntry &T0 = W.tape[0];
         VjpTape tp{T0.pairs, T0.x, T0.u, T0.w, rad, T0.ckey, T0.ccnt, T0.cxi, nullptr, nullptr, sw};
-        const int pgrid = (int)std::max<int64_t>(1, (T0.npairs + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_pairs_vjp, dim3(pgrid), dim3(kBlock), 0, h->stream, Prec, G, (long long)n0,
-                           (int)T0.npairs, tp, (const double *)nullptr, (double *)nullptr, Fb, Tb,
-                           (const double *)nullptr, ax, au, aw, theta);
+        HIPTRY(pairs_vjp(T0, tp, n0, (const double *)nullptr, (double *)nullptr, (const double *)nullptr));
         hipLaunchKernelGGL(k_integrate_vjp, dim3(grid), dim3(kBlock), 0, h->stream, Prec, G.gd, N, 0.0, 1, rad, Fb, Tb,
                            ax, au, aw, xb, ub, wb, Fb2, Tb2);
         HIPTRY(hipGetLastError());
