@@ -210,7 +210,7 @@ __device__ __forceinline__ void vjp_of_pair(const DevParams &P, const BoxParams 
 // Adjacency of the recorded pairs of a tape entry: k_adj_count counts the pairs of every id
 // (deg, zero on entry); after the exclusive scan deg -> off, k_pairs_vjp writes each pair's
 // code 2 k + side (side 0: the smaller id a, 1: b) into the list of each of its two ids (pos
-// zero on entry).
+// zero on entry; k_pairs_vjp_sum clears it again).
 // The order inside a list depends on scheduling; so does the order of the sums below it, as
 // with any floating-point accumulation on the GPU.
 __global__ void __launch_bounds__(kBlock) k_adj_count(int npairs, const int *__restrict__ pairs, int *__restrict__ deg)
@@ -282,10 +282,12 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
 __global__ void __launch_bounds__(kBlock) k_pairs_vjp_sum(int N, const int *__restrict__ off,
                                                           const int *__restrict__ adj,
                                                           const double *__restrict__ gpair, double *__restrict__ ax,
-                                                          double *__restrict__ au, double *__restrict__ aw)
+                                                          double *__restrict__ au, double *__restrict__ aw,
+                                                          int *__restrict__ pos)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
+    pos[p] = 0;  // the fill positions start at zero for the next evaluation
     double s[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int e1 = off[p + 1];
     for (int e = off[p]; e < e1; ++e) {

@@ -58,6 +58,8 @@ double *scratch_of(int device)
     std::lock_guard<std::mutex> lk(g_scratch_mu);
     return g_scratch_ptr[device];
 }
+
+struct AdjointScratch;
 }  // namespace
 
 struct dss_handle {
@@ -144,9 +146,15 @@ struct dss_handle {
     std::vector<std::pair<int, std::pair<int, int>>> ev_marks;  // (kernel, (start event, stop event))
     double kernel_ms[kKernels] = {};
     int64_t kernel_launches[kKernels] = {};
+    // the adjoint's device workspace (checkpoints, tape, reverse buffers), kept for the next
+    // call of the same shapes; adj_key holds the shapes it was allocated for
+    AdjointScratch *adj_ws = nullptr;
+    int64_t adj_key[8] = {};
 };
 
 namespace {
+
+void release_adjoint_ws(dss_handle *h);
 
 const char *kStatusText[] = {"ok", "invalid argument", "HIP error", "capacity exceeded", "cell lattice too small",
                              "non-finite force or torque", "call out of order"};
@@ -197,6 +205,7 @@ void free_all(dss_handle *h)
     auto F = [](void *p) {
         if (p) (void)hipFree(p);
     };
+    release_adjoint_ws(h);
     free_lattice(h);
     for (int k = 0; k < 2; ++k) {
         F(h->pa[k]); F(h->vel[k]); F(h->omg[k]);
@@ -1505,7 +1514,8 @@ struct Snapshot {
 dss_status snap_save(dss_handle *h, Snapshot &s)
 {
     const int64_t N = h->N, M = h->P.M;
-    if (!s.pa) {
+    if (!s.img) {  // allocated last: a snapshot without it is released and allocated whole
+        s.release();
         HIPTRY(dalloc(&s.pa, N));
         HIPTRY(dalloc(&s.vel, N));
         HIPTRY(dalloc(&s.omg, N));
@@ -1622,9 +1632,17 @@ dss_status tape_rows(dss_handle *h, TapeEntry &t)
     return DSS_OK;
 }
 
-// State by id and the listed pairs of the last evaluation -> tape entry.
-// The pair count goes to a device slot; the host reads the counts of a whole segment at once.
-dss_status tape_state(dss_handle *h, TapeEntry &t, unsigned long long *count_slot)
+// Point the pair recording of the next evaluation at a tape entry: the listed pairs go to
+// its buffer and their count to its device slot (the host reads the counts of a whole
+// segment at once).
+void record_into(dss_handle *h, TapeEntry &t, unsigned long long *count_slot)
+{
+    h->pairs = t.pairs;
+    h->pair_count = count_slot;
+}
+
+// State by id at the last evaluation -> tape entry.
+dss_status tape_state(dss_handle *h, TapeEntry &t)
 {
     const int N = (int)h->N;
     const int grid = (N + kBlock - 1) / kBlock;
@@ -1632,10 +1650,6 @@ dss_status tape_state(dss_handle *h, TapeEntry &t, unsigned long long *count_slo
     hipLaunchKernelGGL(k_unsort, dim3(grid), dim3(kBlock), 0, h->stream, h->P, h->pa[c], h->vel[c], h->omg[c],
                        h->fb(), h->vel_is_half ? 1 : 0, 0, t.x, t.u, t.w, (double *)nullptr, (double *)nullptr);
     HIPTRY(hipGetLastError());
-    HIPTRY(hipMemcpyAsync(count_slot, h->pair_count, sizeof(unsigned long long), hipMemcpyDeviceToDevice,
-                          h->stream));
-    HIPTRY(hipMemcpyAsync(t.pairs, h->pairs, 2 * (size_t)h->P.pair_cap * sizeof(int), hipMemcpyDeviceToDevice,
-                          h->stream));
     return DSS_OK;
 }
 
@@ -1653,25 +1667,59 @@ dss_status tape_counts(dss_handle *h, std::vector<TapeEntry> &tape, const unsign
     return DSS_OK;
 }
 
+// The adjoint's device workspace.  Every call takes its buffers in the same order; a call
+// with the shapes of the last one finds them allocated (get() hands out the next buffer of
+// the list when it is large enough), so repeated calls allocate and free nothing.
 struct AdjointScratch {
     std::vector<Snapshot> ck;
     Snapshot fin;
     std::vector<TapeEntry> tape;
-    std::vector<void *> bufs;
+    std::vector<std::pair<void *, size_t>> bufs;  // (buffer, bytes)
+    size_t next = 0;
     ~AdjointScratch()
     {
         for (auto &s : ck) s.release();
         fin.release();
         for (auto &t : tape) t.release();
-        for (void *q : bufs)
-            if (q) (void)hipFree(q);
+        for (auto &b : bufs)
+            if (b.first) (void)hipFree(b.first);
     }
     template <class T>
     hipError_t get(T **p, size_t n)
     {
+        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        if (next < bufs.size() && bufs[next].second >= bytes) {
+            *p = static_cast<T *>(bufs[next++].first);
+            return hipSuccess;
+        }
+        if (next == bufs.size()) bufs.push_back({nullptr, 0});
+        if (bufs[next].first) (void)hipFree(bufs[next].first);
+        bufs[next] = {nullptr, 0};
         hipError_t e = dalloc(p, n);
-        if (e == hipSuccess) bufs.push_back((void *)*p);
+        if (e == hipSuccess) bufs[next++] = {static_cast<void *>(*p), bytes};
         return e;
+    }
+};
+
+void release_adjoint_ws(dss_handle *h)
+{
+    delete h->adj_ws;
+    h->adj_ws = nullptr;
+}
+
+// While the recompute records pairs straight into the tape entries, the handle's own pair
+// buffer and count are set aside; they come back (with the recording flag) when the reverse
+// sweep ends, also on an error return.
+struct PairRecordGuard {
+    dss_handle *h;
+    int *pairs;
+    unsigned long long *count;
+    int rec;
+    ~PairRecordGuard()
+    {
+        h->pairs = pairs;
+        h->pair_count = count;
+        h->P.record_pairs = rec;
     }
 };
 
@@ -1710,9 +1758,19 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
             h->P.pair_cap = cap;
         }
     }
-    AdjointScratch W;
     const int64_t nck = (K + C - 1) / C;
-    W.ck.resize(nck);
+    {
+        // the workspace of the last call serves when its shapes are these
+        const int64_t key[8] = {N, M, h->ncell_total, h->hxr[h->hh] ? 1 : 0, h->P.pair_cap, stretch_width(h), 0, 0};
+        if (h->adj_ws && !std::equal(key, key + 8, h->adj_key)) release_adjoint_ws(h);
+        if (!h->adj_ws) {
+            h->adj_ws = new AdjointScratch;
+            std::copy(key, key + 8, h->adj_key);
+        }
+    }
+    AdjointScratch &W = *h->adj_ws;
+    W.next = 0;
+    if ((int64_t)W.ck.size() < nck) W.ck.resize(nck);
 
     // ---------------- forward run with checkpoints and stress samples
     if (ns > h->sample_cap_alloc) {
@@ -1771,6 +1829,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     double *agrad = nullptr;  // 18 cotangents per recorded pair
     HIPTRY(W.get(&agrad, 18 * (size_t)std::max<int64_t>(h->P.pair_cap, 1)));
     HIPTRY(hipMemsetAsync(adeg, 0, (size_t)adj_tiles * 16384 * sizeof(int), h->stream));
+    HIPTRY(hipMemsetAsync(apos, 0, (size_t)N * sizeof(int), h->stream));
     double *zero_list[] = {xb, ub, wb, ax, au, aw, Fb, Tb, Fb2, Tb2};
     for (double *q : zero_list) HIPTRY(hipMemsetAsync(q, 0, n3 * sizeof(double), h->stream));
     HIPTRY(hipMemsetAsync(theta, 0, 2 * sizeof(double), h->stream));
@@ -1783,9 +1842,11 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         HIPTRY(hipMemcpyAsync(Sb, sb, sizeof(sb), hipMemcpyHostToDevice, h->stream));
     }
     hipLaunchKernelGGL(k_rad_by_id, dim3(grid), dim3(kBlock), 0, h->stream, N, h->pa[h->cur], h->omg[h->cur], rad);
-    W.tape.resize(C + 1);
-    for (auto &t : W.tape) {
-        s = tape_alloc(h, t);
+    if ((int64_t)W.tape.size() < C + 1) W.tape.resize(C + 1);
+    for (int64_t k = 0; k <= C; ++k) {
+        if (W.tape[k].cxi) continue;  // allocated last: the entry is whole
+        W.tape[k].release();
+        s = tape_alloc(h, W.tape[k]);
         if (s) return s;
     }
     DevParams Prec = h->P;
@@ -1801,8 +1862,6 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         hipLaunchKernelGGL(k_scan<4>, dim3(adj_tiles), dim3(1024), 0, h->stream, adeg, aoff, h->clk, 0, atile);
         hipLaunchKernelGGL(k_scan_add, dim3(adj_tiles), dim3(1024), 0, h->stream, aoff, (const int *)atile, 4 * 1024,
                            h->clk, 0);
-        hipError_t e = hipMemsetAsync(apos, 0, (size_t)N * sizeof(int), h->stream);
-        if (e != hipSuccess) return e;
         {
             TimedLaunch tl(h, 5);
             hipExtLaunchKernelGGL(k_pairs_vjp, dim3(pg), dim3(kBlock), 0, h->stream, tl.e0, tl.e1, 0, Prec, G,
@@ -1810,10 +1869,11 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
                                   aadj);
         }
         hipLaunchKernelGGL(k_pairs_vjp_sum, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, (const int *)aoff,
-                           (const int *)aadj, (const double *)agrad, ax, au, aw);
+                           (const int *)aadj, (const double *)agrad, ax, au, aw, apos);
         return hipGetLastError();
     };
     double *xib_in = xibA, *xib_out = xibB;
+    PairRecordGuard guard{h, h->pairs, h->pair_count, rec0};
     h->P.record_pairs = 1;
     for (int64_t seg = nck - 1; seg >= 0; --seg) {
         const int64_t s0 = n0 + seg * C;
@@ -1824,15 +1884,17 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         if (s) break;
         if (seg == 0) {
             // the evaluation at the initial state (pairs, state by id)
+            record_into(h, W.tape[0], slots);
             s = evaluate(h, EVAL_INPLACE);
             if (s) break;
-            s = tape_state(h, W.tape[0], slots);
+            s = tape_state(h, W.tape[0]);
             if (s) break;
         }
         for (int64_t k = 1; k <= len; ++k) {
+            record_into(h, W.tape[k], slots + k);
             s = evaluate(h, EVAL_STEP, false);
             if (s) break;
-            s = tape_state(h, W.tape[k], slots + k);
+            s = tape_state(h, W.tape[k]);
             if (s) break;
             s = tape_rows(h, W.tape[k]);
             if (s) break;
@@ -1868,6 +1930,8 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         HIPTRY(hipMemcpyAsync(bcnt, W.tape[0].ccnt, N * sizeof(int), hipMemcpyDeviceToDevice, h->stream));
         HIPTRY(hipGetLastError());
     }
+    h->pairs = guard.pairs;
+    h->pair_count = guard.count;
     h->P.record_pairs = rec0;
     if (s) return s;
     {

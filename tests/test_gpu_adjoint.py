@@ -274,6 +274,31 @@ def test_adjoint_checkpoint_spacing_invariance(window):
     assert abs(a["dmu"] - b["dmu"]) <= 1e-8 * abs(a["dmu"])
 
 
+def test_adjoint_workspace_reuse(window):
+    """Calls on one handle reuse the adjoint's device workspace (checkpoints, tape, reverse
+    buffers): repeated calls from the same state, and a call with more checkpoints and a
+    shorter segment in between, give the gradients of a fresh handle."""
+    from paper_2108_01013_amd.dss import Simulation
+    w, p, u0, w0, W = window
+    say("case: adjoint workspace reuse N=400")
+    sim = Simulation(p)
+    sim.set_particles(w.x, w.rad, u0, w0)
+    blob = sim.save_state()
+    runs = []
+    for K, se, C in ((20, 5, 7), (20, 5, 7), (12, 4, 3), (20, 5, 7)):
+        sim.load_state(blob)
+        runs.append(sim.adjoint(K, se, C, W))
+    sim.close()
+    ref20, *_ = gpu_adjoint(p, w, u0, w0, W)
+    ref12, *_ = gpu_adjoint(p, w, u0, w0, W, K=12, se=4, C=3)
+    for r, ref in zip(runs, (ref20, ref20, ref12, ref20)):
+        assert abs(r["J"] - ref["J"]) <= 1e-12 * abs(ref["J"])
+        for k in ("dx", "du", "dw"):
+            assert np.max(np.abs(r[k] - ref[k])) <= 1e-12 * np.max(np.abs(ref[k])), k
+        for k in ("dmu", "dF_ER"):
+            assert abs(r[k] - ref[k]) <= 1e-12 * abs(ref[k]), k
+
+
 def test_adjoint_torch_function(window):
     """torch.autograd through StressObjective equals the direct adjoint."""
     import torch
