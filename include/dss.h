@@ -298,7 +298,9 @@ dss_status dss_get_box_info(dss_handle *h, int32_t box, dss_box_info *info);
  * (the step is smooth between these events); the contact history at the call is held
  * fixed.  State is checkpointed every ckpt_every steps and each segment is recomputed
  * forward before its reverse sweep (memory: one state and history copy per checkpoint plus
- * a segment of ckpt_every recorded steps).  On return the handle stands at the end of the
+ * a segment of ckpt_every recorded steps).  This device workspace stays with the handle
+ * and serves the next call of the same particle count, lattice and recording capacity
+ * without allocating; dss_set_particles and dss_destroy free it.  On return the handle stands at the end of the
  * run, as after dss_step(h, n_steps, stress_every, 1).  Requires a single-box handle whose
  * forces were evaluated at u^n (right after dss_set_particles or dss_compute_forces: else
  * DSS_ERR_STATE) and at least one stress sample in the run (else DSS_ERR_ARG).  Takes the
