@@ -59,6 +59,42 @@ double *scratch_of(int device)
     return g_scratch_ptr[device];
 }
 
+// Device buffers handed out in a fixed order and kept for the next round of the same
+// requests: get() returns the next buffer of the list when it is large enough, else frees it
+// and allocates anew; rewind() starts a round, so a repeated sequence of requests allocates
+// nothing.
+struct DevList {
+    std::vector<std::pair<void *, size_t>> bufs;  // (buffer, bytes)
+    size_t next = 0;
+    void rewind() { next = 0; }
+    template <class T>
+    hipError_t get(T **p, size_t n)
+    {
+        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        if (next < bufs.size() && bufs[next].second >= bytes) {
+            *p = static_cast<T *>(bufs[next++].first);
+            return hipSuccess;
+        }
+        if (next == bufs.size()) bufs.push_back({nullptr, 0});
+        if (bufs[next].first) (void)hipFree(bufs[next].first);
+        bufs[next] = {nullptr, 0};
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) return e;
+        bufs[next++] = {q, bytes};
+        *p = static_cast<T *>(q);
+        return hipSuccess;
+    }
+    void release()
+    {
+        for (auto &b : bufs)
+            if (b.first) (void)hipFree(b.first);
+        bufs.clear();
+        next = 0;
+    }
+    ~DevList() { release(); }
+};
+
 struct AdjointScratch;
 }  // namespace
 
@@ -150,6 +186,7 @@ struct dss_handle {
     // call of the same shapes; adj_key holds the shapes it was allocated for
     AdjointScratch *adj_ws = nullptr;
     int64_t adj_key[8] = {};
+    DevList obs_ws;  // work buffers of the observables, kept between calls
 };
 
 namespace {
@@ -206,6 +243,7 @@ void free_all(dss_handle *h)
         if (p) (void)hipFree(p);
     };
     release_adjoint_ws(h);
+    h->obs_ws.release();
     free_lattice(h);
     for (int k = 0; k < 2; ++k) {
         F(h->pa[k]); F(h->vel[k]); F(h->omg[k]);
@@ -1667,37 +1705,23 @@ dss_status tape_counts(dss_handle *h, std::vector<TapeEntry> &tape, const unsign
     return DSS_OK;
 }
 
-// The adjoint's device workspace.  Every call takes its buffers in the same order; a call
-// with the shapes of the last one finds them allocated (get() hands out the next buffer of
-// the list when it is large enough), so repeated calls allocate and free nothing.
+// The adjoint's device workspace: checkpoints, tape entries and the reverse buffers (a
+// DevList: a call with the shapes of the last one allocates nothing).
 struct AdjointScratch {
     std::vector<Snapshot> ck;
     Snapshot fin;
     std::vector<TapeEntry> tape;
-    std::vector<std::pair<void *, size_t>> bufs;  // (buffer, bytes)
-    size_t next = 0;
+    DevList bufs;
     ~AdjointScratch()
     {
         for (auto &s : ck) s.release();
         fin.release();
         for (auto &t : tape) t.release();
-        for (auto &b : bufs)
-            if (b.first) (void)hipFree(b.first);
     }
     template <class T>
     hipError_t get(T **p, size_t n)
     {
-        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
-        if (next < bufs.size() && bufs[next].second >= bytes) {
-            *p = static_cast<T *>(bufs[next++].first);
-            return hipSuccess;
-        }
-        if (next == bufs.size()) bufs.push_back({nullptr, 0});
-        if (bufs[next].first) (void)hipFree(bufs[next].first);
-        bufs[next] = {nullptr, 0};
-        hipError_t e = dalloc(p, n);
-        if (e == hipSuccess) bufs[next++] = {static_cast<void *>(*p), bytes};
-        return e;
+        return bufs.get(p, n);
     }
 };
 
@@ -1769,7 +1793,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         }
     }
     AdjointScratch &W = *h->adj_ws;
-    W.next = 0;
+    W.bufs.rewind();
     if ((int64_t)W.ck.size() < nck) W.ck.resize(nck);
 
     // ---------------- forward run with checkpoints and stress samples
@@ -2108,8 +2132,9 @@ dss_status dss_observe_start(dss_handle *h)
         HIPTRY(dalloc(&h->obs_v0, N));
     }
     double *x = nullptr, *u = nullptr;
-    HIPTRY(dalloc(&x, 3 * N));
-    HIPTRY(dalloc(&u, 3 * N));
+    h->obs_ws.rewind();
+    HIPTRY(h->obs_ws.get(&x, 3 * N));
+    HIPTRY(h->obs_ws.get(&u, 3 * N));
     s = state_by_id(h, x, u);
     if (!s) {
         const int grid = (int)((N + kBlock - 1) / kBlock);
@@ -2119,8 +2144,6 @@ dss_status dss_observe_start(dss_handle *h)
         HIPTRY(hipStreamSynchronize(h->stream));
         h->obs_step0 = h->step;
     }
-    (void)hipFree(x);
-    (void)hipFree(u);
     return s;
 }
 
@@ -2133,9 +2156,10 @@ dss_status dss_observe(dss_handle *h, double out[4])
     const int64_t N = h->N;
     const int grid = (int)((N + kBlock - 1) / kBlock);
     double *x = nullptr, *u = nullptr, *part = nullptr;
-    HIPTRY(dalloc(&x, 3 * N));
-    HIPTRY(dalloc(&u, 3 * N));
-    HIPTRY(dalloc(&part, 3 * (size_t)grid));
+    h->obs_ws.rewind();
+    HIPTRY(h->obs_ws.get(&x, 3 * N));
+    HIPTRY(h->obs_ws.get(&u, 3 * N));
+    HIPTRY(h->obs_ws.get(&part, 3 * (size_t)grid));
     s = state_by_id(h, x, u);
     std::vector<double> hp(3 * (size_t)grid);
     if (!s) {
@@ -2144,9 +2168,6 @@ dss_status dss_observe(dss_handle *h, double out[4])
         HIPTRY(hipGetLastError());
         HIPTRY(hipMemcpy(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost));
     }
-    (void)hipFree(x);
-    (void)hipFree(u);
-    (void)hipFree(part);
     if (s) return s;
     double sum[3] = {0.0, 0.0, 0.0};
     for (int b = 0; b < grid; ++b)
@@ -2170,14 +2191,14 @@ dss_status dss_phi_profile(dss_handle *h, int32_t nbins, double a_split, double 
     const int64_t N = h->N;
     const int grid = (int)((N + kBlock - 1) / kBlock);
     double *part = nullptr;
-    HIPTRY(dalloc(&part, 2 * (size_t)nbins * grid));
+    h->obs_ws.rewind();
+    HIPTRY(h->obs_ws.get(&part, 2 * (size_t)nbins * grid));
     const BoxParams &G = h->boxes[0];
     hipLaunchKernelGGL(k_phi_profile, dim3(grid), dim3(kBlock), 2 * (size_t)nbins * sizeof(double), h->stream, (int)N,
                        G.L[1], (int)nbins, a_split, h->pa[h->cur], part);
     HIPTRY(hipGetLastError());
     std::vector<double> hp(2 * (size_t)nbins * grid);
     HIPTRY(hipMemcpy(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost));
-    (void)hipFree(part);
     const double slab = G.L[0] * G.L[2] * (G.L[1] / (double)nbins);
     for (int k = 0; k < 2 * nbins; ++k) {
         double t = 0.0;
@@ -2222,9 +2243,10 @@ dss_status dss_contact_clusters(dss_handle *h, int64_t cap, int64_t *hist, int64
     const int grid = (int)((N + kBlock - 1) / kBlock);
     int *parent = nullptr, *size = nullptr;
     unsigned long long *dh = nullptr;
-    HIPTRY(dalloc(&parent, N));
-    HIPTRY(dalloc(&size, N));
-    HIPTRY(dalloc(&dh, cap));
+    h->obs_ws.rewind();
+    HIPTRY(h->obs_ws.get(&parent, N));
+    HIPTRY(h->obs_ws.get(&size, N));
+    HIPTRY(h->obs_ws.get(&dh, cap));
     HIPTRY(hipMemsetAsync(dh, 0, cap * sizeof(unsigned long long), h->stream));
     hipLaunchKernelGGL(k_cc_init, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, parent, size);
     hipLaunchKernelGGL(k_cc_hook, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, h->P.M, h->hown[h->hh],
@@ -2234,9 +2256,6 @@ dss_status dss_contact_clusters(dss_handle *h, int64_t cap, int64_t *hist, int64
     HIPTRY(hipGetLastError());
     std::vector<unsigned long long> hh(cap);
     HIPTRY(hipMemcpy(hh.data(), dh, cap * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-    (void)hipFree(parent);
-    (void)hipFree(size);
-    (void)hipFree(dh);
     int64_t nc = 0, big = 0;
     for (int64_t k = 0; k < cap; ++k) {
         hist[k] = (int64_t)hh[k];

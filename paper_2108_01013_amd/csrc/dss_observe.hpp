@@ -106,15 +106,22 @@ __global__ void __launch_bounds__(kBlock) k_phi_reduce(const double *__restrict_
 
 // Connected components of the contact graph by lock-free union-find over particle ids.
 // parent[v] <= v at all times (a root is hooked under a smaller root only), so every find
-// walks a strictly decreasing chain and ends.
-__device__ __forceinline__ int cc_find(const int *parent, int v)
+// walks a strictly decreasing chain and ends.  The find splits the path it walks: each
+// visited node is pointed at its grandparent, which is still an ancestor no larger than it,
+// and only non-roots are written (hooks change roots only, by compare-and-swap), so the
+// invariant holds under concurrent finds and hooks while chains stay short.
+__device__ __forceinline__ int cc_find(int *parent, int v)
 {
-    int p = __atomic_load_n(&parent[v], __ATOMIC_RELAXED);
-    while (p != v) {
-        v = p;
-        p = __atomic_load_n(&parent[v], __ATOMIC_RELAXED);
+    int cur = __atomic_load_n(&parent[v], __ATOMIC_RELAXED);
+    if (cur == v) return v;
+    int prev = v;
+    for (;;) {
+        const int next = __atomic_load_n(&parent[cur], __ATOMIC_RELAXED);
+        if (next == cur) return cur;
+        __atomic_store_n(&parent[prev], next, __ATOMIC_RELAXED);
+        prev = cur;
+        cur = next;
     }
-    return v;
 }
 
 __global__ void __launch_bounds__(kBlock) k_cc_init(int N, int *__restrict__ parent, int *__restrict__ size)
@@ -147,7 +154,7 @@ __global__ void __launch_bounds__(kBlock) k_cc_hook(int N, int M, const int *__r
 }
 
 // Cluster sizes: size[root] = particles under root.
-__global__ void __launch_bounds__(kBlock) k_cc_count(int N, const int *parent, int *__restrict__ size)
+__global__ void __launch_bounds__(kBlock) k_cc_count(int N, int *parent, int *__restrict__ size)
 {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= N) return;

@@ -90,4 +90,8 @@ def test_contact_clusters(mu, hamaker):
         g = sim.contact_clusters(cap)
         o = oracle.contact_clusters(4000, pairs, cap)
         assert np.array_equal(g, o), (cap, np.flatnonzero(g != o)[:10])
+    # the observables share the handle's work buffers: other requests in between
+    x = sim.state()["x"]
+    assert np.max(np.abs(sim.phi_profile(64, 1.2) - oracle.phi_profile(p, x[:, 1], w.rad, 64, 1.2))) <= 1e-12
+    assert np.array_equal(sim.contact_clusters(4000), oracle.contact_clusters(4000, pairs, 4000))
     sim.close()
