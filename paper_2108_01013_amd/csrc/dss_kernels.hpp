@@ -1177,14 +1177,55 @@ __device__ __forceinline__ void permute_row_entries(double *xrow, double *rrow, 
     }
 }
 
+// Stretches of a history row in the order idx (n <= 16 entries) through a buffer of the
+// lane's own in LDS (row_pool_doubles, rolling stretches in its second half): the whole row
+// is loaded at once and parked in the buffer, then written back gathered in the new order, so
+// the row costs one round of global loads instead of the two passes through its free end.
+template <bool Roll>
+constexpr int row_pool_doubles()
+{
+    return (Roll ? 2 : 1) * 16 * 3;
+}
+
+template <bool Roll>
+__device__ __forceinline__ void permute_row_entries_lds(double *xrow, double *rrow, const int idx[16], int n,
+                                                        double *buf)
+{
+#pragma unroll
+    for (int part = 0; part < (Roll ? 2 : 1); ++part) {
+        double *row = part ? rrow : xrow;
+        double *b = buf + part * 48;
+#pragma unroll
+        for (int b0 = 0; b0 < 16; b0 += 8) {
+            double v[8][3];
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[a][c] = b0 + a < n ? row[3 * (b0 + a) + c] : 0.0;
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+                if (b0 + a < n)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) b[3 * (b0 + a) + c] = v[a][c];
+        }
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            if (a < n)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) row[3 * a + c] = b[3 * idx[a] + c];
+    }
+}
+
 // Sort history row gi by partner id and publish it (the per-row sort of the contact
 // map).  Rows of up to 8 entries are read at once and sorted in registers (odd-even
 // transposition on the (key, stretch) tuples); rows of up to 16 (at most half the capacity) by
-// their keys and entry indices in registers, the stretches then moved through the free end of
-// the row; longer rows by a heap sort in place.  With rolling
+// their keys and entry indices in registers, the stretches then moved through a buffer in LDS
+// when the caller gives a pool of them and one is free (pool_next counts the buffers taken),
+// else through the free end of the row; longer rows by a heap sort in place.  With rolling
 // resistance the rolling stretches move with their entries.
 template <bool Roll = false>
-__device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int fill, int idi)
+__device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int fill, int idi,
+                                           double *pool = nullptr, int *pool_next = nullptr, int pool_bufs = 0)
 {
     int *krow = H.key_new + (long long)gi * M;
     double *xrow = H.xi_new + (long long)gi * M * 3;
@@ -1237,10 +1278,11 @@ __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int
                     if constexpr (Roll) rrow[3 * a + c] = y[a][c];
                 }
             }
-    } else if (nrow > 8 && nrow <= 16 && 2 * nrow <= M) {
+    } else if (nrow > 8 && nrow <= 16 && (pool_bufs > 0 || 2 * nrow <= M)) {
         // keys sorted with their entry indices in registers (odd-even transposition); the
-        // entries are gathered in the new order into the free end of the row, then copied back
-        // (disjoint ranges: the loads of a batch are in flight together)
+        // entries are gathered in the new order through an LDS buffer, or into the free end of
+        // the row and then copied back (disjoint ranges: the loads of a batch are in flight
+        // together)
         int key[16], idx[16];
 #pragma unroll
         for (int a = 0; a < 16; ++a) {
@@ -1261,8 +1303,13 @@ __device__ __forceinline__ void finish_row(const HistView &H, int M, int gi, int
                 }
             }
         }
-        const int t0 = M - nrow;
-        permute_row_entries<Roll>(xrow, rrow, idx, nrow, t0);
+        const int buf = pool_bufs > 0 ? atomicAdd(pool_next, 1) : pool_bufs;
+        if (buf < pool_bufs)
+            permute_row_entries_lds<Roll>(xrow, rrow, idx, nrow, pool + (size_t)buf * row_pool_doubles<Roll>());
+        else if (2 * nrow <= M)
+            permute_row_entries<Roll>(xrow, rrow, idx, nrow, M - nrow);
+        else
+            heap_sort_row<Roll>(krow, xrow, rrow, nrow);
 #pragma unroll
         for (int a = 0; a < 16; ++a)
             if (a < nrow) krow[a] = key[a];
@@ -1508,6 +1555,7 @@ struct TileShared {
     int qn;
     int nc;             // candidates listed by k_pairs
     int ovf;            // tile overflow: the row is redone on the per-particle path
+    int rpool;          // LDS row buffers taken in C (in the pair queue's space)
     int wsum[kBlock / 64];
     double red[kBlock / 64][12];
 };
@@ -2003,9 +2051,14 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
     // the sums are complete (C adds to the stress only in the wavy shear): reduced here, so that
     // their registers are free in C
     if constexpr (Sum && !Wave) reduce_sums(tally, T.red, partials, P.pstride, grow);
+    if (t == 0) T.rpool = 0;
     __syncthreads();
 
-    // C: own particles (Stokes terms, own record, history row), then partner records
+    // C: own particles (Stokes terms, own record, history row), then partner records.  The
+    // pair queue is dead: its space holds the LDS buffers of the history rows of 9-16 entries.
+    double *const row_pool = reinterpret_cast<double *>(V.queue);
+    const int row_bufs =
+        (int)((size_t)(P.qcap + 1) / 2 * 2 * sizeof(unsigned) / (row_pool_doubles<Roll>() * sizeof(double)));
     for (int il = t; il < n_own; il += kPairBlock) {
         const int gi = T.rs[0] + il;
         const double4 Xi = il == t ? Xc : pa[gi];
@@ -2018,7 +2071,7 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
         store_ft(B.own + 6LL * gi, f);
         if (!finite6(f)) atomicOr(&clk->err, kErrNonFinite);
         const int fill = V.rowcnt[il];
-        finish_row<Roll>(H, P.M, gi, fill, (int)Wi.w);
+        finish_row<Roll>(H, P.M, gi, fill, (int)Wi.w, row_pool, &T.rpool, row_bufs);
         tally.fill = max(tally.fill, fill);
     }
     for (int k = T.ro[1] + t; k < total; k += kPairBlock) {
