@@ -187,8 +187,12 @@ dss_status dss_set_particles_batch(dss_handle *h, const int64_t *n_per_box, cons
  *   queue_cap:  with sized, the length of the LDS queues of listed pairs (a workgroup's on
  *               the lane path, up to 4096; a wavefront's, up to 512), so that a scan stops
  *               and resumes after every queue_cap pairs; 0 = the full length, any other
- *               value only for checking the stop-and-resume path (it costs time).
- * Defaults: {1, 1, 1, 1, 0, 0, 0}.  reserved must be 0. */
+ *               value only for checking the stop-and-resume path (it costs time);
+ *   adj_cap:    the capacity of the per-particle lists of recorded pairs in the reverse
+ *               sweep of dss_adjoint (0 = 32, at most 4096); the pairs of a particle beyond
+ *               it are added from an overflow list with atomics, so a small value only
+ *               checks that path.
+ * Defaults: {1, 1, 1, 1, 0, 0, 0, 0}. */
 typedef struct {
     double cell_scale;
     double tile_scale;
@@ -197,7 +201,7 @@ typedef struct {
     int32_t sized;
     int32_t wave_class;
     int32_t queue_cap;
-    int32_t reserved;
+    int32_t adj_cap;
 } dss_tuning;
 
 /* Set the launch tuning.  Before dss_set_particles it applies to the first lattice; after,

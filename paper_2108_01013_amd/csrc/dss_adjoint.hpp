@@ -134,9 +134,10 @@ __global__ void __launch_bounds__(kBlock) k_canon_zero(int N, int M, const int *
 // F_b = -F_a, torque cotangents, the stretch cotangent from the rows after the step, the
 // stress weights), and pair_vjp pulls them back (vjp_of_pair), one lane per pair.  The
 // cotangents of both particles' x, u, w are stored with the pair (18 doubles, plain
-// stores), and k_pairs_vjp_sum adds them to each particle over its recorded pairs (an
-// adjacency of integer codes built per evaluation: counts, their scan, and the lists written
-// by this kernel), so no FP64 atomics remain; the old-stretch adjoint is stored at the
+// stores), and k_pairs_vjp_sum adds them to each particle over its recorded pairs (a list of
+// integer codes per particle, of fixed capacity, written by this kernel; the codes beyond a
+// full list go to an overflow list whose entries k_adj_overflow adds with FP64 atomics, so
+// there are none on the common path); the old-stretch adjoint is stored at the
 // contact's position in the previous rows, and the parameter gradients (mu, F_ER) are summed
 // per workgroup, then added once.
 // ----------------------------------------------------------------------------------
@@ -207,18 +208,23 @@ __device__ __forceinline__ void vjp_of_pair(const DevParams &P, const BoxParams 
              tp.w + 3LL * b, xo, bar, g, nullptr, f_contact, f_capped, xro, f_rcapped);
 }
 
-// Adjacency of the recorded pairs of a tape entry: k_adj_count counts the pairs of every id
-// (deg, zero on entry); after the exclusive scan deg -> off, k_pairs_vjp writes each pair's
-// code 2 k + side (side 0: the smaller id a, 1: b) into the list of each of its two ids (pos
-// zero on entry; k_pairs_vjp_sum clears it again).
+// Lists of the recorded pairs of a tape entry by particle: each pair's code 2 k + side (side 0:
+// the smaller id a, 1: b) goes to the list of each of its ids, list p holding at most cap
+// codes at adj[p cap ..] (pos[p] counts them, zero on entry; k_pairs_vjp_sum clears it); a
+// code beyond a full list goes, with its id, to the overflow list (ovf_n entries, zero on
+// entry; k_pairs_vjp_sum clears it too).
 // The order inside a list depends on scheduling; so does the order of the sums below it, as
 // with any floating-point accumulation on the GPU.
-__global__ void __launch_bounds__(kBlock) k_adj_count(int npairs, const int *__restrict__ pairs, int *__restrict__ deg)
+constexpr int kAdjCap = 32;  // default capacity of a particle's list
+
+__device__ __forceinline__ void adj_push(int id, int code, int cap, int *__restrict__ pos, int *__restrict__ adj,
+                                         unsigned *__restrict__ ovf_n, int2 *__restrict__ ovf)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= npairs) return;
-    atomicAdd(&deg[pairs[2 * k]], 1);
-    atomicAdd(&deg[pairs[2 * k + 1]], 1);
+    const int slot = atomicAdd(&pos[id], 1);
+    if (slot < cap)
+        adj[(long long)id * cap + slot] = code;
+    else
+        ovf[atomicAdd(ovf_n, 1u)] = make_int2(id, code);
 }
 
 __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, long long step, int npairs,
@@ -226,20 +232,17 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
                                                       double *__restrict__ xib_old, const double *__restrict__ Fb,
                                                       const double *__restrict__ Tb, const double *__restrict__ Sb,
                                                       double *__restrict__ gpair, double *__restrict__ theta_b,
-                                                      const int *__restrict__ off, int *__restrict__ pos,
-                                                      int *__restrict__ adj)
+                                                      int cap, int *__restrict__ pos, int *__restrict__ adj,
+                                                      unsigned *__restrict__ ovf_n, int2 *__restrict__ ovf)
 {
     __shared__ double red[kBlock / 64][2];
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     double gmu = 0.0, gfer = 0.0;
     if (k < npairs) {
-        // the pair's entries in the adjacency lists of its two ids (their atomics overlap
-        // the pair's arithmetic)
-        {
-            const int a0 = tp.pairs[2 * k], b0 = tp.pairs[2 * k + 1];
-            adj[off[a0] + atomicAdd(&pos[a0], 1)] = 2 * k;
-            adj[off[b0] + atomicAdd(&pos[b0], 1)] = 2 * k + 1;
-        }
+        // the pair's entries in the lists of its two ids (their atomics overlap the pair's
+        // arithmetic)
+        adj_push(tp.pairs[2 * k], 2 * k, cap, pos, adj, ovf_n, ovf);
+        adj_push(tp.pairs[2 * k + 1], 2 * k + 1, cap, pos, adj, ovf_n, ovf);
         int a, b;
         long long pold;
         PairGrad g = {};
@@ -279,19 +282,43 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
 
 // The pair cotangents of every particle summed over its recorded pairs (the adjacency of the
 // evaluation) and added to ax, au, aw: one lane per particle, one writer per entry.
-__global__ void __launch_bounds__(kBlock) k_pairs_vjp_sum(int N, const int *__restrict__ off,
+// Codes beyond full lists: their cotangents added with FP64 atomics (a fixed grid striding over
+// the overflow list; runs before k_pairs_vjp_sum, whose additions then include these).
+__global__ void __launch_bounds__(kBlock) k_adj_overflow(const unsigned *__restrict__ ovf_n,
+                                                         const int2 *__restrict__ ovf,
+                                                         const double *__restrict__ gpair, double *__restrict__ ax,
+                                                         double *__restrict__ au, double *__restrict__ aw)
+{
+    const unsigned n = *ovf_n;
+    for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int2 v = ovf[e];
+        const double *g = gpair + 18LL * (v.y >> 1) + 9 * (v.y & 1);
+        for (int c = 0; c < 3; ++c) {
+            atomicAdd(&ax[3LL * v.x + c], g[c]);
+            atomicAdd(&au[3LL * v.x + c], g[3 + c]);
+            atomicAdd(&aw[3LL * v.x + c], g[6 + c]);
+        }
+    }
+}
+
+// Per particle: the cotangents of its listed codes added in list order to its adjoints; the
+// list positions and the overflow count are cleared for the next evaluation.
+__global__ void __launch_bounds__(kBlock) k_pairs_vjp_sum(int N, int cap, int *__restrict__ pos,
                                                           const int *__restrict__ adj,
                                                           const double *__restrict__ gpair, double *__restrict__ ax,
                                                           double *__restrict__ au, double *__restrict__ aw,
-                                                          int *__restrict__ pos)
+                                                          unsigned *__restrict__ ovf_n)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) *ovf_n = 0u;
     if (p >= N) return;
-    pos[p] = 0;  // the fill positions start at zero for the next evaluation
+    const int m = pos[p];
+    pos[p] = 0;
+    const int n = m < cap ? m : cap;
     double s[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const int e1 = off[p + 1];
-    for (int e = off[p]; e < e1; ++e) {
-        const int code = adj[e];
+    const int *lst = adj + (long long)p * cap;
+    for (int e = 0; e < n; ++e) {
+        const int code = lst[e];
         const double *g = gpair + 18LL * (code >> 1) + 9 * (code & 1);
 #pragma unroll
         for (int c = 0; c < 9; ++c) s[c] += g[c];

@@ -1165,9 +1165,9 @@ dss_status dss_set_tuning(dss_handle *h, const dss_tuning *t)
     if (!h || !t) return DSS_ERR_ARG;
     if (!(t->cell_scale >= 1.0 && t->cell_scale <= 4.0) || !(t->tile_scale >= 0.25 && t->tile_scale <= 4.0) ||
         (t->tiled != 0 && t->tiled != 1) || (t->graph != 0 && t->graph != 1) || (t->sized != 0 && t->sized != 1) ||
-        t->wave_class < 0 || t->wave_class > 64 || t->queue_cap < 0 || t->reserved)
+        t->wave_class < 0 || t->wave_class > 64 || t->queue_cap < 0 || t->adj_cap < 0 || t->adj_cap > 4096)
         return fail(h, DSS_ERR_ARG, "tuning out of range (cell_scale in [1, 4], tile_scale in [0.25, 4], "
-                                    "wave_class in [0, 64], queue_cap >= 0, flags 0/1)");
+                                    "wave_class in [0, 64], queue_cap >= 0, adj_cap in [0, 4096], flags 0/1)");
     if (t->sized && h->nbox != 1) return fail(h, DSS_ERR_ARG, "size-class stencils need a handle of one box");
     if (h->loaded) {
         // the lattice must still be legal for every box
@@ -1843,17 +1843,19 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     const int sw = stretch_width(h);
     HIPTRY(W.get(&xibA, sw * (size_t)N * M)); HIPTRY(W.get(&xibB, sw * (size_t)N * M));
     HIPTRY(W.get(&bkey, (size_t)N * M)); HIPTRY(W.get(&bcnt, N));
-    // adjacency of the recorded pairs (per evaluation): degrees, their scan (tiles of 16384
-    // ids, the multi-workgroup scan of the counting sort), fill positions, pair codes
-    const int adj_tiles = (int)((N + 1 + 16383) / 16384);
-    int *adeg = nullptr, *aoff = nullptr, *apos = nullptr, *aadj = nullptr, *atile = nullptr;
-    HIPTRY(W.get(&adeg, (size_t)adj_tiles * 16384)); HIPTRY(W.get(&aoff, (size_t)adj_tiles * 16384));
-    HIPTRY(W.get(&apos, (size_t)N)); HIPTRY(W.get(&aadj, 2 * (size_t)std::max<int64_t>(h->P.pair_cap, 1)));
-    HIPTRY(W.get(&atile, (size_t)std::max(adj_tiles, 16)));
+    // the recorded pairs by particle (per evaluation): lists of acap codes, their fill counts,
+    // and the overflow list of the codes beyond a full list (at most every code)
+    const int acap = h->tune.adj_cap > 0 ? h->tune.adj_cap : kAdjCap;
+    const size_t ncode = 2 * (size_t)std::max<int64_t>(h->P.pair_cap, 1);
+    int *apos = nullptr, *aadj = nullptr;
+    unsigned *aovf_n = nullptr;
+    int2 *aovf = nullptr;
+    HIPTRY(W.get(&apos, (size_t)N)); HIPTRY(W.get(&aadj, (size_t)N * acap));
+    HIPTRY(W.get(&aovf_n, 1)); HIPTRY(W.get(&aovf, ncode));
     double *agrad = nullptr;  // 18 cotangents per recorded pair
     HIPTRY(W.get(&agrad, 18 * (size_t)std::max<int64_t>(h->P.pair_cap, 1)));
-    HIPTRY(hipMemsetAsync(adeg, 0, (size_t)adj_tiles * 16384 * sizeof(int), h->stream));
     HIPTRY(hipMemsetAsync(apos, 0, (size_t)N * sizeof(int), h->stream));
+    HIPTRY(hipMemsetAsync(aovf_n, 0, sizeof(unsigned), h->stream));
     double *zero_list[] = {xb, ub, wb, ax, au, aw, Fb, Tb, Fb2, Tb2};
     for (double *q : zero_list) HIPTRY(hipMemsetAsync(q, 0, n3 * sizeof(double), h->stream));
     HIPTRY(hipMemsetAsync(theta, 0, 2 * sizeof(double), h->stream));
@@ -1876,24 +1878,22 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     DevParams Prec = h->P;
     Prec.record_pairs = 1;
     const BoxParams G = h->boxes[0];
-    // the reverse of the pair terms of evaluation n from tape entry T1: the adjacency of its
-    // pairs, then the per-particle gather
+    // the reverse of the pair terms of evaluation n from tape entry T1: the pair VJP (which also
+    // lists each pair under its two ids), the overflow codes, then the per-particle sums
     auto pairs_vjp = [&](const TapeEntry &T1, const VjpTape &tp, int64_t n, const double *xin, double *xout,
                          const double *sb) -> hipError_t {
         const int np = (int)T1.npairs;
         const int pg = std::max(1, (np + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_adj_count, dim3(pg), dim3(kBlock), 0, h->stream, np, (const int *)T1.pairs, adeg);
-        hipLaunchKernelGGL(k_scan<4>, dim3(adj_tiles), dim3(1024), 0, h->stream, adeg, aoff, h->clk, 0, atile);
-        hipLaunchKernelGGL(k_scan_add, dim3(adj_tiles), dim3(1024), 0, h->stream, aoff, (const int *)atile, 4 * 1024,
-                           h->clk, 0);
         {
             TimedLaunch tl(h, 5);
             hipExtLaunchKernelGGL(k_pairs_vjp, dim3(pg), dim3(kBlock), 0, h->stream, tl.e0, tl.e1, 0, Prec, G,
-                                  (long long)n, np, tp, xin, xout, Fb, Tb, sb, agrad, theta, (const int *)aoff, apos,
-                                  aadj);
+                                  (long long)n, np, tp, xin, xout, Fb, Tb, sb, agrad, theta, acap, apos, aadj, aovf_n,
+                                  aovf);
         }
-        hipLaunchKernelGGL(k_pairs_vjp_sum, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, (const int *)aoff,
-                           (const int *)aadj, (const double *)agrad, ax, au, aw, apos);
+        hipLaunchKernelGGL(k_adj_overflow, dim3(64), dim3(kBlock), 0, h->stream, (const unsigned *)aovf_n,
+                           (const int2 *)aovf, (const double *)agrad, ax, au, aw);
+        hipLaunchKernelGGL(k_pairs_vjp_sum, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, acap, apos,
+                           (const int *)aadj, (const double *)agrad, ax, au, aw, aovf_n);
         return hipGetLastError();
     };
     double *xib_in = xibA, *xib_out = xibB;

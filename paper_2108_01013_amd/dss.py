@@ -64,7 +64,7 @@ class BoxInfo(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("cell_scale", ctypes.c_double), ("tile_scale", ctypes.c_double), ("tiled", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("sized", ctypes.c_int32), ("wave_class", ctypes.c_int32),
-                ("queue_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("queue_cap", ctypes.c_int32), ("adj_cap", ctypes.c_int32)]
 
 
 _lib = None
@@ -316,15 +316,18 @@ class Simulation:
                "k_pairs_rows", "k_pairs_ec")
 
     def set_tuning(self, cell_scale=None, tile_scale=None, tiled=None, graph=None, sized=None, wave_class=None,
-                   queue_cap=None):
+                   queue_cap=None, adj_cap=None):
         """Change launch tuning (results do not depend on it); unspecified fields keep their value.
         sized: size-class stencils (one box); wave_class: first size class on one wavefront per
         particle (0 = default); queue_cap: length of the size-class pair queues (0 = full; a
-        small value exercises the scans' stop and resume)."""
+        small value exercises the scans' stop and resume); adj_cap: capacity of the adjoint's
+        per-particle pair lists (0 = default; a small value exercises the overflow list)."""
         t = Tuning()
         self._check(self.lib.dss_get_tuning(self.h, ctypes.byref(t)))
         if queue_cap is not None:
             t.queue_cap = int(queue_cap)
+        if adj_cap is not None:
+            t.adj_cap = int(adj_cap)
         if sized is not None:
             t.sized = int(bool(sized))
         if wave_class is not None:
@@ -423,7 +426,7 @@ class Simulation:
         self._check(self.lib.dss_get_tuning(self.h, ctypes.byref(t)))
         return {"cell_scale": t.cell_scale, "tile_scale": t.tile_scale, "tiled": bool(t.tiled),
                 "graph": bool(t.graph), "sized": bool(t.sized), "wave_class": int(t.wave_class),
-                "queue_cap": int(t.queue_cap)}
+                "queue_cap": int(t.queue_cap), "adj_cap": int(t.adj_cap)}
 
     def set_timing(self, enable=True, kernels=None):
         """Time the named kernels (all if None) with HIP events; enable=False stops."""

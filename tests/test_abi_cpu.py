@@ -46,7 +46,7 @@ def test_params_struct_layout():
     assert dss.Params.precision.offset == 18 * 8
     assert dss.Params.k_roll.offset == 18 * 8 + 4 * 4
     assert ctypes.sizeof(dss.Tuning) == 2 * 8 + 6 * 4 and dss.Tuning.sized.offset == 24
-    assert dss.Tuning.queue_cap.offset == 32 and dss.Tuning.reserved.offset == 36
+    assert dss.Tuning.queue_cap.offset == 32 and dss.Tuning.adj_cap.offset == 36
     assert ctypes.sizeof(dss.Info) == 8 + 8 + 12 + 4 + 8 + 8 + 4 + 4 + 8
 
 

@@ -299,6 +299,29 @@ def test_adjoint_workspace_reuse(window):
             assert abs(r[k] - ref[k]) <= 1e-12 * abs(ref[k]), k
 
 
+@pytest.mark.parametrize("cap", [1, 3])
+def test_adjoint_pair_list_overflow(window, cap):
+    """Per-particle lists of recorded pairs cut to cap entries (tuning adj_cap), so that most
+    particles' pairs go through the overflow list: the gradients equal the default's."""
+    from paper_2108_01013_amd.dss import DssError, Simulation
+    w, p, u0, w0, W = window
+    say(f"case: adjoint pair lists of {cap} N=400")
+    sim = Simulation(p)
+    with pytest.raises(DssError):
+        sim.set_tuning(adj_cap=5000)
+    sim.set_tuning(adj_cap=cap)
+    assert sim.tuning()["adj_cap"] == cap
+    sim.set_particles(w.x, w.rad, u0, w0)
+    r = sim.adjoint(20, 5, 7, W)
+    sim.close()
+    ref, *_ = gpu_adjoint(p, w, u0, w0, W)
+    assert abs(r["J"] - ref["J"]) <= 1e-12 * abs(ref["J"])
+    for k in ("dx", "du", "dw"):
+        assert np.max(np.abs(r[k] - ref[k])) <= 1e-12 * np.max(np.abs(ref[k])), k
+    for k in ("dmu", "dF_ER"):
+        assert abs(r[k] - ref[k]) <= 1e-12 * abs(ref[k]), k
+
+
 def test_adjoint_torch_function(window):
     """torch.autograd through StressObjective equals the direct adjoint."""
     import torch
