@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(kBlock) k_canon_zero(int N, int M, const int *
 // cotangents of both particles' x, u, w are stored with the pair (18 doubles, plain
 // stores), and k_pairs_vjp_sum adds them to each particle over its recorded pairs (a list of
 // integer codes per particle, of fixed capacity, written by this kernel; the codes beyond a
-// full list go to an overflow list whose entries k_adj_overflow adds with FP64 atomics, so
+// full list go to an overflow list whose entries k_pairs_vjp_sum adds with FP64 atomics, so
 // there are none on the common path); the old-stretch adjoint is stored at the
 // contact's position in the previous rows, and the parameter gradients (mu, F_ER) are summed
 // per workgroup, then added once.
@@ -212,7 +212,7 @@ __device__ __forceinline__ void vjp_of_pair(const DevParams &P, const BoxParams 
 // the smaller id a, 1: b) goes to the list of each of its ids, list p holding at most cap
 // codes at adj[p cap ..] (pos[p] counts them, zero on entry; k_pairs_vjp_sum clears it); a
 // code beyond a full list goes, with its id, to the overflow list (ovf_n entries, zero on
-// entry; k_pairs_vjp_sum clears it too).
+// entry; k_integrate_vjp clears the count).
 // The order inside a list depends on scheduling; so does the order of the sums below it, as
 // with any floating-point accumulation on the GPU.
 constexpr int kAdjCap = 32;  // default capacity of a particle's list
@@ -282,15 +282,21 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
 
 // The pair cotangents of every particle summed over its recorded pairs (the adjacency of the
 // evaluation) and added to ax, au, aw: one lane per particle, one writer per entry.
-// Codes beyond full lists: their cotangents added with FP64 atomics (a fixed grid striding over
-// the overflow list; runs before k_pairs_vjp_sum, whose additions then include these).
-__global__ void __launch_bounds__(kBlock) k_adj_overflow(const unsigned *__restrict__ ovf_n,
-                                                         const int2 *__restrict__ ovf,
-                                                         const double *__restrict__ gpair, double *__restrict__ ax,
-                                                         double *__restrict__ au, double *__restrict__ aw)
+// Per particle: the cotangents of its listed codes added in list order to its adjoints (the
+// list positions cleared for the next evaluation); the codes of the overflow list, beyond full
+// lists, are added by the same grid with FP64 atomics, and so are the list sums of the
+// particles that overflowed, whose adjoints have more than one writer.  k_integrate_vjp
+// clears the overflow count afterwards.
+__global__ void __launch_bounds__(kBlock) k_pairs_vjp_sum(int N, int cap, int *__restrict__ pos,
+                                                          const int *__restrict__ adj,
+                                                          const unsigned *__restrict__ ovf_n,
+                                                          const int2 *__restrict__ ovf,
+                                                          const double *__restrict__ gpair, double *__restrict__ ax,
+                                                          double *__restrict__ au, double *__restrict__ aw)
 {
-    const unsigned n = *ovf_n;
-    for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned no = *ovf_n;
+    for (unsigned e = p; e < no; e += gridDim.x * blockDim.x) {
         const int2 v = ovf[e];
         const double *g = gpair + 18LL * (v.y >> 1) + 9 * (v.y & 1);
         for (int c = 0; c < 3; ++c) {
@@ -299,18 +305,6 @@ __global__ void __launch_bounds__(kBlock) k_adj_overflow(const unsigned *__restr
             atomicAdd(&aw[3LL * v.x + c], g[6 + c]);
         }
     }
-}
-
-// Per particle: the cotangents of its listed codes added in list order to its adjoints; the
-// list positions and the overflow count are cleared for the next evaluation.
-__global__ void __launch_bounds__(kBlock) k_pairs_vjp_sum(int N, int cap, int *__restrict__ pos,
-                                                          const int *__restrict__ adj,
-                                                          const double *__restrict__ gpair, double *__restrict__ ax,
-                                                          double *__restrict__ au, double *__restrict__ aw,
-                                                          unsigned *__restrict__ ovf_n)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) *ovf_n = 0u;
     if (p >= N) return;
     const int m = pos[p];
     pos[p] = 0;
@@ -323,10 +317,18 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp_sum(int N, int cap, int *_
 #pragma unroll
         for (int c = 0; c < 9; ++c) s[c] += g[c];
     }
-    for (int c = 0; c < 3; ++c) {
-        ax[3LL * p + c] += s[c];
-        au[3LL * p + c] += s[3 + c];
-        aw[3LL * p + c] += s[6 + c];
+    if (m > cap) {
+        for (int c = 0; c < 3; ++c) {
+            atomicAdd(&ax[3LL * p + c], s[c]);
+            atomicAdd(&au[3LL * p + c], s[3 + c]);
+            atomicAdd(&aw[3LL * p + c], s[6 + c]);
+        }
+    } else {
+        for (int c = 0; c < 3; ++c) {
+            ax[3LL * p + c] += s[c];
+            au[3LL * p + c] += s[3 + c];
+            aw[3LL * p + c] += s[6 + c];
+        }
     }
 }
 
@@ -346,9 +348,11 @@ __global__ void __launch_bounds__(kBlock) k_integrate_vjp(DevParams P, double gd
                                                           double *__restrict__ ax, double *__restrict__ au,
                                                           double *__restrict__ aw, double *__restrict__ xb,
                                                           double *__restrict__ ub, double *__restrict__ wb,
-                                                          double *__restrict__ Fb_prev, double *__restrict__ Tb_prev)
+                                                          double *__restrict__ Fb_prev, double *__restrict__ Tb_prev,
+                                                          unsigned *__restrict__ ovf_n)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) *ovf_n = 0u;  // the pair sums of this evaluation are complete
     if (p >= N) return;
     const double a = rad[p];
     const double K = P.k6 * a, KR = P.k8 * a * a * a;

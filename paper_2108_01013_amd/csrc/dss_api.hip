@@ -1879,7 +1879,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     Prec.record_pairs = 1;
     const BoxParams G = h->boxes[0];
     // the reverse of the pair terms of evaluation n from tape entry T1: the pair VJP (which also
-    // lists each pair under its two ids), the overflow codes, then the per-particle sums
+    // lists each pair under its two ids), then the per-particle sums
     auto pairs_vjp = [&](const TapeEntry &T1, const VjpTape &tp, int64_t n, const double *xin, double *xout,
                          const double *sb) -> hipError_t {
         const int np = (int)T1.npairs;
@@ -1890,10 +1890,9 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
                                   (long long)n, np, tp, xin, xout, Fb, Tb, sb, agrad, theta, acap, apos, aadj, aovf_n,
                                   aovf);
         }
-        hipLaunchKernelGGL(k_adj_overflow, dim3(64), dim3(kBlock), 0, h->stream, (const unsigned *)aovf_n,
-                           (const int2 *)aovf, (const double *)agrad, ax, au, aw);
         hipLaunchKernelGGL(k_pairs_vjp_sum, dim3(grid), dim3(kBlock), 0, h->stream, (int)N, acap, apos,
-                           (const int *)aadj, (const double *)agrad, ax, au, aw, aovf_n);
+                           (const int *)aadj, (const unsigned *)aovf_n, (const int2 *)aovf, (const double *)agrad,
+                           ax, au, aw);
         return hipGetLastError();
     };
     double *xib_in = xibA, *xib_out = xibB;
@@ -1944,7 +1943,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
             {
                 TimedLaunch ti(h, 6);
                 hipExtLaunchKernelGGL(k_integrate_vjp, dim3(grid), dim3(kBlock), 0, h->stream, ti.e0, ti.e1, 0, Prec,
-                                      G.gd, N, c, 0, rad, Fb, Tb, ax, au, aw, xb, ub, wb, Fb2, Tb2);
+                                      G.gd, N, c, 0, rad, Fb, Tb, ax, au, aw, xb, ub, wb, Fb2, Tb2, aovf_n);
             }
             std::swap(Fb, Fb2);
             std::swap(Tb, Tb2);
@@ -1964,7 +1963,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         VjpTape tp{T0.pairs, T0.x, T0.u, T0.w, rad, T0.ckey, T0.ccnt, T0.cxi, nullptr, nullptr, sw};
         HIPTRY(pairs_vjp(T0, tp, n0, (const double *)nullptr, (double *)nullptr, (const double *)nullptr));
         hipLaunchKernelGGL(k_integrate_vjp, dim3(grid), dim3(kBlock), 0, h->stream, Prec, G.gd, N, 0.0, 1, rad, Fb, Tb,
-                           ax, au, aw, xb, ub, wb, Fb2, Tb2);
+                           ax, au, aw, xb, ub, wb, Fb2, Tb2, aovf_n);
         HIPTRY(hipGetLastError());
     }
     s = check_flags(h);
