@@ -280,8 +280,6 @@ __global__ void __launch_bounds__(kBlock) k_pairs_vjp(DevParams P, BoxParams G, 
     }
 }
 
-// The pair cotangents of every particle summed over its recorded pairs (the adjacency of the
-// evaluation) and added to ax, au, aw: one lane per particle, one writer per entry.
 // Per particle: the cotangents of its listed codes added in list order to its adjoints (the
 // list positions cleared for the next evaluation); the codes of the overflow list, beyond full
 // lists, are added by the same grid with FP64 atomics, and so are the list sums of the
