@@ -684,7 +684,7 @@ dss_status setup_lattice(dss_handle *h)
 enum EvalMode { EVAL_STEP = 0, EVAL_SORT = 1, EVAL_INPLACE = 2, EVAL_RESORT = 3 };
 
 // The pair kernels of one evaluation: size-class stencils (lane and wavefront paths), or
-// the row tiles followed by the rows they deferred.  Real: FP64 or mixed arithmetic; Roll:
+// the row tiles followed by the rows they deferred (k_pairs_rows; see rows_in_place).  Real: FP64 or mixed arithmetic; Roll:
 // rolling resistance; Wave: the wavy ambient shear; Sum: the stress and counters are summed
 // (k_finish follows), else the tile and stencil kernels skip them.
 template <typename Real, bool Roll, bool Wave, bool Sum>
@@ -714,10 +714,11 @@ void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
                               h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, h->fb_rows,
                               h->fb_count);
     }
-    {
-        // deferred rows: workgroups striding over the list, as many as the rows deferred at
-        // the last synchronised evaluation (a few when that is unknown or none), one per row
-        // when every row takes the per-particle path
+    if constexpr (!rows_in_place<Real, Roll, Wave>()) {
+        // deferred rows (the instantiations that do not take them in place): workgroups
+        // striding over the list, as many as the rows deferred at the last synchronised
+        // evaluation (a few when that is unknown or none), one per row when every row takes
+        // the per-particle path
         TimedLaunch t(h, 7);
         const int hint = h->deferred_hint < 0 ? 64 : h->deferred_hint + h->deferred_hint / 4 + 8;
         const int grid = h->tune.tiled ? std::min(h->nrow_total, hint) : h->nrow_total;

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace dss {
 
 constexpr double kPi = 3.14159265358979323846;
@@ -85,7 +87,9 @@ struct BoxParams {
 struct DevClock {
     long long step;
     unsigned err;
-    int deferred;   // rows k_pairs left to the per-particle path at the last evaluation
+    int deferred;   // the atomic force record is in use: rows the FP64 k_pairs left to k_pairs_rows at
+                    // the last evaluation, or 1 (per-particle rows of the mixed k_pairs, size-class
+                    // stencils); cleared by k_scatter
 };
 
 // Run descriptor of a dss_step call: stress sampling schedule.
@@ -530,6 +534,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int N, const int *__restrict
 {
     __shared__ int off[16];
     const int t = threadIdx.x;
+    if (blockIdx.x == 0 && t == 0) clk->deferred = 0;  // set again by the rows of this step's pair kernels
     if (ntile > 0) {
         if (t < 64) {
             const int v = t < ntile ? tile_sum[t] : 0;
@@ -1369,7 +1374,7 @@ struct PairTally {
 // adds the partner side atomically to ft_x.
 // ----------------------------------------------------------------------------------
 template <typename Real, bool Roll, bool Wave>
-__device__ void particle_pairs_global(const DevParams &P, const BoxParams &G, int i, double delta,
+__device__ __forceinline__ void particle_pairs_global(const DevParams &P, const BoxParams &G, int i, double delta,
                                       const int *__restrict__ cell_start,
                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
                                       const double4 *__restrict__ omg, const ForceBufs &B, const HistView &H,
@@ -1547,6 +1552,15 @@ __device__ __forceinline__ void reduce_fill(int fill, double (*red)[12], double 
 // forces, torques and history are the same).
 // ----------------------------------------------------------------------------------
 constexpr int kPairBlock = 192;
+
+// The k_pairs instantiations that take their rows beyond the tile capacities in place (the
+// others leave them to k_pairs_rows): the mixed kernel without rolling resistance and wavy
+// shear, whose FP32 physics leaves room for the per-particle path in the tile's registers.
+template <typename Real, bool Roll, bool Wave>
+__host__ __device__ constexpr bool rows_in_place()
+{
+    return std::is_same<Real, float>::value && !Roll && !Wave;
+}
 constexpr int kPairWaves = kPairBlock / 64;
 constexpr int kHeadPre = 3;  // row heads per lane requested before A2
 
@@ -1837,15 +1851,27 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
         row_bounds(G, row, cell_start, T);
     const int n_own = T.re[0] - T.rs[0];
     const int total = T.ro[5];
-    // a row beyond the tile capacities (or one that hits a tile limit below) is left to
-    // k_pairs_rows, which takes it on the per-particle path; nothing of it is written here
+    // a row beyond the tile capacities (or one that hits a tile limit below) takes the
+    // per-particle path: in the plain mixed kernel here, by its own workgroup (the FP32 physics
+    // leaves the registers for it; the partner sides go to the atomic record, which k_predict
+    // then reads), in the others in k_pairs_rows (inlined here it would spill the tile path);
+    // nothing of the tile is written
     auto defer_row = [&]() {
-        if (t == 0) fb_rows[atomicAdd(fb_count, 1)] = grow;
+        if constexpr (rows_in_place<Real, Roll, Wave>()) {
+            for (int i = T.rs[0] + t; i < T.re[0]; i += kPairBlock)
+                particle_pairs_global<Real, Roll, Wave>(P, G, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out,
+                                                        pair_count, tally);
+            const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int r = 1; r < 5; ++r)
+                for (int g = T.rs[r] + t; g < T.re[r]; g += kPairBlock) store_ft(B.nb + 6LL * ((r - 1) * B.n + g), z);
+            if (t == 0) clk->deferred = 1;
+            if constexpr (Sum) reduce_tally(tally, T.red, partials, P.pstride, grow);
+        } else {
+            if (t == 0) fb_rows[atomicAdd(fb_count, 1)] = grow;
+        }
     };
-    if (!P.tiled || n_own > P.own_cap || total > P.stage_cap) {
-        defer_row();
-        return;
-    }
+    if (!P.tiled || n_own > P.own_cap || total > P.stage_cap) goto per_particle;
+  {  // the tile path (every exit to per_particle is workgroup-uniform)
     // stage the shell rows (FP32) with their slots at the last step, and the cell column of
     // every own particle (from FP64)
     for (int k = t; k < total; k += kPairBlock) {
@@ -1931,11 +1957,7 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
     }
     __syncthreads();
     const int ncand = T.nc;
-    if (T.ovf || ncand > ccap) {
-        // a tile limit was hit: defer the row to the per-particle path
-        defer_row();
-        return;
-    }
+    if (T.ovf || ncand > ccap) goto per_particle;  // a tile limit was hit
 
     // the history row heads of the first kHeadPre staged particles of every lane are requested
     // now, so that their loads are in flight during A2; they are written over the FP32
@@ -2011,11 +2033,7 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
         }
     }
     lds_barrier();
-    if (T.ovf) {
-        // a tile limit was hit: discard the tile and defer the row to the per-particle path
-        defer_row();
-        return;
-    }
+    if (T.ovf) goto per_particle;  // a tile limit was hit: the tile is discarded
 
     // the FP32 records are dead: the history row head of every staged particle (its slot at
     // the last step, row count, first two keys) takes their place, so that B finds most stored
@@ -2088,6 +2106,10 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
         else
             reduce_fill(tally.fill, T.red, partials, P.pstride, grow);
     }
+    return;
+  }
+per_particle:
+    defer_row();
 }
 
 // ----------------------------------------------------------------------------------

@@ -25,7 +25,8 @@ class FakeSim:
         self.calls.append(dict(kw))
 
     def step(self, n, sync=True):
-        cost = 1e-4 * (1.0 + abs(self.t["tile_scale"] - 1.5) + (0.0 if self.t["tiled"] else 2.0))
+        # milliseconds per step, so that the ranking survives the host's scheduling jitter
+        cost = 2e-3 * (1.0 + abs(self.t["tile_scale"] - 1.5) + (0.0 if self.t["tiled"] else 2.0))
         time.sleep(cost * n)
 
 
