@@ -806,7 +806,7 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
         TimedLaunch t(h, 0);
         hipExtLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P, h->d_boxes,
                               h->pa[c], h->vel[c], h->omg[c], h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk,
-                              h->cell, h->rank, h->count, h->fb_count, h->img);
+                              h->cell, h->rank, h->count, h->fb_count, h->img, h->boxes[0]);
     }
     if (h->scan_tiles > 0) {
         TimedLaunch t(h, 1);

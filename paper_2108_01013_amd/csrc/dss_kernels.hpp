@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
                                                      int advance, const DevClock *__restrict__ clk,
                                                      int *__restrict__ cell, int *__restrict__ rank,
                                                      int *__restrict__ count, int *__restrict__ fb_count,
-                                                     int *__restrict__ img)
+                                                     int *__restrict__ img, BoxParams G0)
 {
 #pragma clang fp contract(off)
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -407,7 +407,9 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
     double4 X = pa[p];
     double4 V = vel[p];
     double4 W = omg[p];
-    const BoxParams &G = boxes[(int)V.w];
+    // the box of the particle: the table entry of a batch, else the kernel argument (no
+    // load that waits for the particle record)
+    auto body = [&](const BoxParams &G) {
     const double dt = P.dt;
     double a = X.w;
     double m = pmass(P, a);
@@ -466,6 +468,11 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
     int cz = cell_coord(X.z, G.cw[2], G.nc[2]);
     c = G.cell_off + (cz * G.nc[1] + cy) * G.nc[0] + cx;
     if (P.sized) c += size_class(P, X.w) * (G.nc[0] * G.nc[1] * G.nc[2]);
+    };
+    if (P.nbox > 1)
+        body(boxes[(int)V.w]);
+    else
+        body(G0);
     }
     // histogram rank: lanes of a wavefront with equal consecutive cell ids (the input is
     // sorted by the previous step's cells) form runs; the first lane of a run claims the
