@@ -66,6 +66,9 @@ double *scratch_of(int device)
 struct DevList {
     std::vector<std::pair<void *, size_t>> bufs;  // (buffer, bytes)
     size_t next = 0;
+    DevList() = default;
+    DevList(const DevList &) = delete;  // owns its buffers
+    DevList &operator=(const DevList &) = delete;
     void rewind() { next = 0; }
     template <class T>
     hipError_t get(T **p, size_t n)
