@@ -127,8 +127,10 @@ struct dss_handle {
     dss_tuning tune{1.0, 1.0, 1, 1, 0, 0, 0, 0};
     bool tune_pending = false;        // lattice to rebuild before the next time step
     // HIP graphs of one time step, keyed by (current buffers, committed history buffers,
-    // half-step velocities, stress summation)
+    // half-step velocities, stress summation), and of runs of steps (the same key for the
+    // first step, the run length and which of its steps sum the stress)
     hipGraphExec_t graph[16] = {};
+    std::vector<std::pair<uint64_t, hipGraphExec_t>> run_graphs;
     bool graph_broken = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -224,6 +226,9 @@ void destroy_graphs(dss_handle *h)
         if (g) (void)hipGraphExecDestroy(g);
         g = nullptr;
     }
+    for (auto &g : h->run_graphs)
+        if (g.second) (void)hipGraphExecDestroy(g.second);
+    h->run_graphs.clear();
 }
 
 void free_lattice(dss_handle *h)
@@ -884,6 +889,46 @@ dss_status graph_step(dss_handle *h, bool finish)
     return DSS_OK;
 }
 
+// n consecutive time steps (n <= kRunSteps) through one HIP graph: bit k of `finish` sums the
+// stress at step k.  One launch for the run, so the steps follow each other without the gap
+// that separates two graph launches on the device.
+constexpr int kRunSteps = 16;
+dss_status graph_run(dss_handle *h, int n, unsigned finish)
+{
+    const uint64_t key = (uint64_t)h->cur | ((uint64_t)h->hh << 1) | ((uint64_t)(h->vel_is_half ? 1 : 0) << 2) |
+                         ((uint64_t)n << 3) | ((uint64_t)finish << 8);
+    hipGraphExec_t ge = nullptr;
+    for (auto &g : h->run_graphs)
+        if (g.first == key) ge = g.second;
+    const int cur = h->cur, hh = h->hh;
+    const bool vih = h->vel_is_half;
+    const int64_t step = h->step;
+    if (!ge) {
+        hipGraph_t g = nullptr;
+        HIPTRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        dss_status s = DSS_OK;
+        for (int k = 0; k < n && !s; ++k) s = evaluate(h, EVAL_STEP, (finish >> k) & 1u);
+        hipError_t e = hipStreamEndCapture(h->stream, &g);
+        // the capture recorded the launches without running them
+        h->cur = cur;
+        h->hh = hh;
+        h->vel_is_half = vih;
+        h->step = step;
+        if (s) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return fail(h, DSS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(h, DSS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        h->run_graphs.push_back({key, ge});
+    }
+    HIPTRY(hipGraphLaunch(ge, h->stream));
+    for (int k = 0; k < n; ++k) commit_eval(h, true);
+    return DSS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1271,11 +1316,25 @@ dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sy
         h->tune_pending = false;
     }
     const bool graphs = h->tune.graph && !h->graph_broken && h->timing == 0 && !h->P.record_pairs;
-    for (int64_t k = 0; k < n_steps; ++k) {
-        // the stress and counters are summed only when a sample is due and after the last step
-        const int64_t n_next = h->step + 1;
-        const bool finish = k == n_steps - 1 || (stress_every > 0 && n_next % stress_every == 0);
-        s = graphs ? graph_step(h, finish) : evaluate(h, EVAL_STEP, finish);
+    // the stress and counters are summed only when a sample is due and after the last step
+    const int64_t step0 = h->step;
+    auto finish_at = [&](int64_t k) {  // k: the step's index within the call
+        return k == n_steps - 1 || (stress_every > 0 && (step0 + k + 1) % stress_every == 0);
+    };
+    // with graphs, runs of steps as one launch: as long as the sampling period (2 .. 16) when
+    // there is one, so that the runs of a call repeat, else kRunSteps / 2
+    const int64_t run = stress_every >= 2 && stress_every <= kRunSteps ? stress_every : kRunSteps / 2;
+    for (int64_t k = 0; k < n_steps;) {
+        if (graphs && n_steps - k >= 2) {
+            const int n = (int)std::min<int64_t>(run, n_steps - k);
+            unsigned mask = 0;
+            for (int j = 0; j < n; ++j) mask |= (finish_at(k + j) ? 1u : 0u) << j;
+            s = graph_run(h, n, mask);
+            k += n;
+        } else {
+            s = graphs ? graph_step(h, finish_at(k)) : evaluate(h, EVAL_STEP, finish_at(k));
+            k += 1;
+        }
         if (s) return s;
     }
     if (sync) return check_flags(h);
