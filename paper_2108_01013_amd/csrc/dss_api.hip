@@ -1831,14 +1831,15 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     const int64_t ns = (n0 + K - first) / stress_every + 1;
     const int N = (int)h->N, M = h->P.M;
     const int grid = (N + kBlock - 1) / kBlock;
-    destroy_graphs(h);
-    // pair recording for the tape
+    // pair recording for the tape (a larger buffer: the graphs, which hold the buffer and the
+    // capacity, are captured again)
     const int rec0 = h->P.record_pairs;
     if (!rec0) {
         std::vector<int64_t> nb(h->boxes.size());
         for (size_t b = 0; b < h->boxes.size(); ++b) nb[b] = h->boxes[b].n_part;
         const int64_t cap = pair_record_capacity(h->P, h->boxes, h->box_amax, nb.data());
         if (h->P.pair_cap < cap) {
+            destroy_graphs(h);
             if (h->pairs) HIPTRY(hipFree(h->pairs));
             h->pairs = nullptr;
             HIPTRY(dalloc(&h->pairs, 2 * cap));
@@ -1874,14 +1875,29 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     h->run_host.box_diag = h->box_diag;
     HIPTRY(hipMemcpyAsync(h->run, &h->run_host, sizeof(DevRun), hipMemcpyHostToDevice, h->stream));
     h->last_samples = ns;
-    for (int64_t k = 0; k < K; ++k) {
+    // the steps between checkpoints in graph runs, as dss_step takes them (the timing of the
+    // reverse kernels does not stop them)
+    const unsigned fwd_timed = h->timing & ~((1u << 5) | (1u << 6));
+    const bool graphs = h->tune.graph && !h->graph_broken && fwd_timed == 0 && !h->P.record_pairs;
+    const int64_t step0 = h->step;
+    auto finish_at = [&](int64_t k) { return k == K - 1 || (step0 + k + 1) % stress_every == 0; };
+    const int64_t run = stress_every >= 2 && stress_every <= kRunSteps ? stress_every : kRunSteps / 2;
+    for (int64_t k = 0; k < K;) {
         if (k % C == 0) {
             s = snap_save(h, W.ck[k / C]);
             if (s) return s;
         }
-        const int64_t n_next = h->step + 1;
-        const bool finish = k == K - 1 || n_next % stress_every == 0;
-        s = evaluate(h, EVAL_STEP, finish);
+        const int64_t seg_end = std::min<int64_t>(K, (k / C + 1) * C);  // the next checkpoint
+        if (graphs && seg_end - k >= 2) {
+            const int n = (int)std::min<int64_t>(run, seg_end - k);
+            unsigned mask = 0;
+            for (int j = 0; j < n; ++j) mask |= (finish_at(k + j) ? 1u : 0u) << j;
+            s = graph_run(h, n, mask);
+            k += n;
+        } else {
+            s = evaluate(h, EVAL_STEP, finish_at(k));
+            k += 1;
+        }
         if (s) return s;
     }
     double last[9], mean[9];
