@@ -347,11 +347,19 @@ __global__ void __launch_bounds__(kBlock) k_integrate_vjp(DevParams P, double gd
                                                           double *__restrict__ aw, double *__restrict__ xb,
                                                           double *__restrict__ ub, double *__restrict__ wb,
                                                           double *__restrict__ Fb_prev, double *__restrict__ Tb_prev,
-                                                          unsigned *__restrict__ ovf_n)
+                                                          unsigned *__restrict__ ovf_n, const int *__restrict__ zcnt,
+                                                          double *__restrict__ zbuf, int M, int sw)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0) *ovf_n = 0u;  // the pair sums of this evaluation are complete
     if (p >= N) return;
+    // the stretch adjoints that the next reverse step writes, cleared over the canonical rows
+    // of its earlier history (the buffer this step's pair VJP has finished reading)
+    if (zcnt) {
+        double *r = zbuf + (long long)p * M * sw;
+        const int n = sw * zcnt[p];
+        for (int k = 0; k < n; ++k) r[k] = 0.0;
+    }
     const double a = rad[p];
     const double K = P.k6 * a, KR = P.k8 * a * a * a;
     const double m = pmass(P, a), I = 0.4 * m * a * a;

@@ -750,7 +750,6 @@ dss_status launch_pairs(dss_handle *h, int buf, const int *prev, int sample, boo
     H.own_new = h->hown[1 - h->hh];
     H.xr_old = h->hxr[h->hh];
     H.xr_new = h->hxr[1 - h->hh];
-    if (h->P.record_pairs) HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
     const bool roll = h->P.kr > 0.0, wave = h->P.wave_amp != 0.0;
     const int v = (finish ? 8 : 0) | (h->prm.precision == DSS_MIXED ? 4 : 0) | (roll ? 2 : 0) | (wave ? 1 : 0);
     switch (v) {
@@ -804,6 +803,7 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
         }
         HIPTRY(hipMemsetAsync(h->ft_x, 0, 6 * h->N * sizeof(double), h->stream));
         HIPTRY(hipMemsetAsync(h->fb_count, 0, sizeof(int), h->stream));
+        if (h->P.record_pairs) HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
         dss_status s = launch_pairs(h, c, nullptr, 0, true);
         if (s) return s;
         HIPTRY(hipGetLastError());
@@ -814,7 +814,8 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
         TimedLaunch t(h, 0);
         hipExtLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P, h->d_boxes,
                               h->pa[c], h->vel[c], h->omg[c], h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk,
-                              h->cell, h->rank, h->count, h->fb_count, h->img, h->boxes[0]);
+                              h->cell, h->rank, h->count, h->fb_count, h->img, h->boxes[0],
+                              h->P.record_pairs ? h->pair_count : (unsigned long long *)nullptr);
     }
     if (h->scan_tiles > 0) {
         TimedLaunch t(h, 1);
@@ -2013,8 +2014,11 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         for (int64_t k = len; k >= 1; --k) {
             const int64_t n = s0 + k;
             const TapeEntry &T1 = W.tape[k], &T0 = W.tape[k - 1];
-            hipLaunchKernelGGL(sw == 6 ? k_canon_zero<6> : k_canon_zero<3>, dim3(grid), dim3(kBlock), 0, h->stream, N,
-                               M, T0.ccnt, xib_out);
+            // the stretch adjoints this step writes start at zero over the rows of T0 (after the
+            // first step of the segment, the previous step's k_integrate_vjp cleared them)
+            if (k == len)
+                hipLaunchKernelGGL(sw == 6 ? k_canon_zero<6> : k_canon_zero<3>, dim3(grid), dim3(kBlock), 0, h->stream,
+                                   N, M, T0.ccnt, xib_out);
             VjpTape tp{T1.pairs, T1.x, T1.u, T1.w, rad, T0.ckey, T0.ccnt, T0.cxi, T1.ckey, T1.ccnt, sw};
             const bool sampled = n >= first && (n - first) % stress_every == 0;
             HIPTRY(pairs_vjp(T1, tp, n, xib_in, xib_out, sampled ? Sb : (const double *)nullptr));
@@ -2022,7 +2026,8 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
             {
                 TimedLaunch ti(h, 6);
                 hipExtLaunchKernelGGL(k_integrate_vjp, dim3(grid), dim3(kBlock), 0, h->stream, ti.e0, ti.e1, 0, Prec,
-                                      G.gd, N, c, 0, rad, Fb, Tb, ax, au, aw, xb, ub, wb, Fb2, Tb2, aovf_n);
+                                      G.gd, N, c, 0, rad, Fb, Tb, ax, au, aw, xb, ub, wb, Fb2, Tb2, aovf_n,
+                                      k >= 2 ? (const int *)W.tape[k - 2].ccnt : (const int *)nullptr, xib_in, M, sw);
             }
             std::swap(Fb, Fb2);
             std::swap(Tb, Tb2);
@@ -2042,7 +2047,7 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         VjpTape tp{T0.pairs, T0.x, T0.u, T0.w, rad, T0.ckey, T0.ccnt, T0.cxi, nullptr, nullptr, sw};
         HIPTRY(pairs_vjp(T0, tp, n0, (const double *)nullptr, (double *)nullptr, (const double *)nullptr));
         hipLaunchKernelGGL(k_integrate_vjp, dim3(grid), dim3(kBlock), 0, h->stream, Prec, G.gd, N, 0.0, 1, rad, Fb, Tb,
-                           ax, au, aw, xb, ub, wb, Fb2, Tb2, aovf_n);
+                           ax, au, aw, xb, ub, wb, Fb2, Tb2, aovf_n, (const int *)nullptr, (double *)nullptr, M, sw);
         HIPTRY(hipGetLastError());
     }
     s = check_flags(h);

@@ -396,11 +396,15 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
                                                      int advance, const DevClock *__restrict__ clk,
                                                      int *__restrict__ cell, int *__restrict__ rank,
                                                      int *__restrict__ count, int *__restrict__ fb_count,
-                                                     int *__restrict__ img, BoxParams G0)
+                                                     int *__restrict__ img, BoxParams G0,
+                                                     unsigned long long *__restrict__ pair_count)
 {
 #pragma clang fp contract(off)
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) *fb_count = 0;  // rows deferred by this step's k_pairs
+    if (p == 0) {
+        *fb_count = 0;                   // rows deferred by this step's k_pairs
+        if (pair_count) *pair_count = 0;  // the pairs this step's pair kernels record
+    }
     const bool active = p < P.N;
     int c = -1;
     if (active) {
