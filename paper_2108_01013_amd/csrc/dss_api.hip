@@ -191,6 +191,9 @@ struct dss_handle {
     // call of the same shapes; adj_key holds the shapes it was allocated for
     AdjointScratch *adj_ws = nullptr;
     int64_t adj_key[8] = {};
+    // while set, k_predict also writes the state it reads (positions, evaluation velocities and
+    // spins) by particle id: the adjoint's tape entry of the previous evaluation
+    double *tape_x = nullptr, *tape_u = nullptr, *tape_w = nullptr;
     DevList obs_ws;  // work buffers of the observables, kept between calls
 };
 
@@ -815,7 +818,8 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
         hipExtLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P, h->d_boxes,
                               h->pa[c], h->vel[c], h->omg[c], h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk,
                               h->cell, h->rank, h->count, h->fb_count, h->img, h->boxes[0],
-                              h->P.record_pairs ? h->pair_count : (unsigned long long *)nullptr);
+                              h->P.record_pairs ? h->pair_count : (unsigned long long *)nullptr, h->tape_x,
+                              h->tape_u, h->tape_w);
     }
     if (h->scan_tiles > 0) {
         TimedLaunch t(h, 1);
@@ -1808,6 +1812,7 @@ struct PairRecordGuard {
         h->pairs = pairs;
         h->pair_count = count;
         h->P.record_pairs = rec;
+        h->tape_x = h->tape_u = h->tape_w = nullptr;
     }
 };
 
@@ -1986,22 +1991,28 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
         s = tape_rows(h, W.tape[0]);
         if (s) break;
         if (seg == 0) {
-            // the evaluation at the initial state (pairs, state by id)
+            // the evaluation at the initial state (its pairs; its state by id is written by the
+            // next step's k_predict, which reads that state)
             record_into(h, W.tape[0], slots);
             s = evaluate(h, EVAL_INPLACE);
-            if (s) break;
-            s = tape_state(h, W.tape[0]);
             if (s) break;
         }
         for (int64_t k = 1; k <= len; ++k) {
             record_into(h, W.tape[k], slots + k);
+            // the state of evaluation k - 1 by id, written by this step's k_predict (the tape
+            // entry 0 of a later segment is not read)
+            const bool prev = seg == 0 || k >= 2;
+            h->tape_x = prev ? W.tape[k - 1].x : nullptr;
+            h->tape_u = prev ? W.tape[k - 1].u : nullptr;
+            h->tape_w = prev ? W.tape[k - 1].w : nullptr;
             s = evaluate(h, EVAL_STEP, false);
-            if (s) break;
-            s = tape_state(h, W.tape[k]);
+            h->tape_x = h->tape_u = h->tape_w = nullptr;
             if (s) break;
             s = tape_rows(h, W.tape[k]);
             if (s) break;
         }
+        if (s) break;
+        s = tape_state(h, W.tape[len]);  // the segment's last evaluation
         if (s) break;
         s = tape_counts(h, W.tape, slots, seg == 0 ? 0 : 1, (int)len);
         if (s) break;

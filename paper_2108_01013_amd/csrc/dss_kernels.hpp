@@ -397,7 +397,9 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
                                                      int *__restrict__ cell, int *__restrict__ rank,
                                                      int *__restrict__ count, int *__restrict__ fb_count,
                                                      int *__restrict__ img, BoxParams G0,
-                                                     unsigned long long *__restrict__ pair_count)
+                                                     unsigned long long *__restrict__ pair_count,
+                                                     double *__restrict__ tx, double *__restrict__ tu,
+                                                     double *__restrict__ tw)
 {
 #pragma clang fp contract(off)
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -411,6 +413,13 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
     double4 X = pa[p];
     double4 V = vel[p];
     double4 W = omg[p];
+    if (tx) {
+        // the state as read, by id (the adjoint's tape of the previous evaluation)
+        const long long id = (long long)W.w;
+        tx[3 * id] = X.x; tx[3 * id + 1] = X.y; tx[3 * id + 2] = X.z;
+        tu[3 * id] = V.x; tu[3 * id + 1] = V.y; tu[3 * id + 2] = V.z;
+        tw[3 * id] = W.x; tw[3 * id + 1] = W.y; tw[3 * id + 2] = W.z;
+    }
     // the box of the particle: the table entry of a batch, else the kernel argument (no
     // load that waits for the particle record)
     auto body = [&](const BoxParams &G) {
