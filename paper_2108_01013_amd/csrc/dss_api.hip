@@ -194,6 +194,7 @@ struct dss_handle {
     // while set, k_predict also writes the state it reads (positions, evaluation velocities and
     // spins) by particle id: the adjoint's tape entry of the previous evaluation
     double *tape_x = nullptr, *tape_u = nullptr, *tape_w = nullptr;
+    int *tape_zero = nullptr;  // while set, k_predict also clears these N counts
     DevList obs_ws;  // work buffers of the observables, kept between calls
 };
 
@@ -819,7 +820,7 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
                               h->pa[c], h->vel[c], h->omg[c], h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk,
                               h->cell, h->rank, h->count, h->fb_count, h->img, h->boxes[0],
                               h->P.record_pairs ? h->pair_count : (unsigned long long *)nullptr, h->tape_x,
-                              h->tape_u, h->tape_w);
+                              h->tape_u, h->tape_w, h->tape_zero);
     }
     if (h->scan_tiles > 0) {
         TimedLaunch t(h, 1);
@@ -1722,12 +1723,13 @@ dss_status tape_alloc(dss_handle *h, TapeEntry &t)
     return DSS_OK;
 }
 
-// Committed history -> canonical rows of a tape entry.
-dss_status tape_rows(dss_handle *h, TapeEntry &t)
+// Committed history -> canonical rows of a tape entry (their counts start at zero: cleared
+// here, or already by the evaluation's k_predict when cleared = true).
+dss_status tape_rows(dss_handle *h, TapeEntry &t, bool cleared = false)
 {
     const int N = (int)h->N, M = h->P.M;
     const int grid = (N + kBlock - 1) / kBlock;
-    HIPTRY(hipMemsetAsync(t.ccnt, 0, N * sizeof(int), h->stream));
+    if (!cleared) HIPTRY(hipMemsetAsync(t.ccnt, 0, N * sizeof(int), h->stream));
     const int sw = stretch_width(h);
     auto fill = sw == 6 ? k_canon_fill<6> : k_canon_fill<3>;
     auto sort = sw == 6 ? k_canon_sort<6> : k_canon_sort<3>;
@@ -1813,6 +1815,7 @@ struct PairRecordGuard {
         h->pair_count = count;
         h->P.record_pairs = rec;
         h->tape_x = h->tape_u = h->tape_w = nullptr;
+        h->tape_zero = nullptr;
     }
 };
 
@@ -2005,10 +2008,12 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
             h->tape_x = prev ? W.tape[k - 1].x : nullptr;
             h->tape_u = prev ? W.tape[k - 1].u : nullptr;
             h->tape_w = prev ? W.tape[k - 1].w : nullptr;
+            h->tape_zero = W.tape[k].ccnt;  // the counts of this step's canonical rows
             s = evaluate(h, EVAL_STEP, false);
             h->tape_x = h->tape_u = h->tape_w = nullptr;
+            h->tape_zero = nullptr;
             if (s) break;
-            s = tape_rows(h, W.tape[k]);
+            s = tape_rows(h, W.tape[k], true);
             if (s) break;
         }
         if (s) break;

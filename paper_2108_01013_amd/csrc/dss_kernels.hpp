@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
                                                      int *__restrict__ img, BoxParams G0,
                                                      unsigned long long *__restrict__ pair_count,
                                                      double *__restrict__ tx, double *__restrict__ tu,
-                                                     double *__restrict__ tw)
+                                                     double *__restrict__ tw, int *__restrict__ tz)
 {
 #pragma clang fp contract(off)
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -407,6 +407,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
         *fb_count = 0;                   // rows deferred by this step's k_pairs
         if (pair_count) *pair_count = 0;  // the pairs this step's pair kernels record
     }
+    if (tz && p < P.N) tz[p] = 0;  // counts the adjoint's tape fills after this evaluation
     const bool active = p < P.N;
     int c = -1;
     if (active) {
