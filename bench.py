@@ -82,6 +82,8 @@ def timed_run(sim, N, args, stress_every, kernels=("k_pairs",), steps=None, warm
     warmup = args.warmup if warmup is None else warmup
     sim.set_timing(False)
     sim.step(warmup, stress_every=stress_every, sync=True)
+    # the graphs of the timed call are captured now, so that it replays them only
+    sim.prepare_steps(steps, stress_every=stress_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps, stress_every=stress_every, sync=False)
@@ -497,6 +499,8 @@ def measure_adjoint(w, args, precision: str, K: int, C: int, warmup: int):
     sim.compute_forces()
     torch.cuda.synchronize()
     # forward only, for the ratio
+    sim.prepare_steps(K, stress_every=se)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(K, stress_every=se, sync=True)
     fwd = time.perf_counter() - t0

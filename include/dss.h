@@ -245,6 +245,15 @@ dss_status dss_compute_forces(dss_handle *h);
  * unless sync != 0 (then device error flags are checked). */
 dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sync);
 
+/* Capture, without running anything, the HIP graphs that dss_step(h, n_steps, stress_every, .)
+ * from the current state will replay (runs of consecutive steps: as many as the sampling period
+ * when it is 2 .. 16, else 8, each run one graph launch; a last single step is captured when it
+ * runs), so that the call itself spends no time capturing.  Leaves the state as it is.  Does
+ * nothing when graphs are off (tuning, kernel timing, pair recording) or a lattice change is
+ * pending; errors as dss_step.  Not part of the method: a host-side preparation for callers
+ * that time or schedule the steps. */
+dss_status dss_prepare_steps(dss_handle *h, int64_t n_steps, int64_t stress_every);
+
 /* Stress of the last force evaluation (sigma_last, 9 values, row-major Sigma_ab) and the
  * mean over the samples of the last dss_step call (sigma_mean, nullable); n_samples
  * receives the sample count (nullable).  Sigma = 2 eta0 E_inf + (1/V)(sum_i S^S_i +

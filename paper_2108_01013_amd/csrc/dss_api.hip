@@ -897,43 +897,76 @@ dss_status graph_step(dss_handle *h, bool finish)
 
 // n consecutive time steps (n <= kRunSteps) through one HIP graph: bit k of `finish` sums the
 // stress at step k.  One launch for the run, so the steps follow each other without the gap
-// that separates two graph launches on the device.
+// that separates two graph launches on the device.  run_graph finds or captures the graph of
+// the run from the current buffers (capturing records the launches without running them, and
+// leaves the handle's state as it was); graph_run launches it and advances the state.
 constexpr int kRunSteps = 16;
-dss_status graph_run(dss_handle *h, int n, unsigned finish)
+dss_status run_graph(dss_handle *h, int n, unsigned finish, hipGraphExec_t *out)
 {
     const uint64_t key = (uint64_t)h->cur | ((uint64_t)h->hh << 1) | ((uint64_t)(h->vel_is_half ? 1 : 0) << 2) |
                          ((uint64_t)n << 3) | ((uint64_t)finish << 8);
-    hipGraphExec_t ge = nullptr;
     for (auto &g : h->run_graphs)
-        if (g.first == key) ge = g.second;
+        if (g.first == key) {
+            *out = g.second;
+            return DSS_OK;
+        }
     const int cur = h->cur, hh = h->hh;
     const bool vih = h->vel_is_half;
     const int64_t step = h->step;
-    if (!ge) {
-        hipGraph_t g = nullptr;
-        HIPTRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        dss_status s = DSS_OK;
-        for (int k = 0; k < n && !s; ++k) s = evaluate(h, EVAL_STEP, (finish >> k) & 1u);
-        hipError_t e = hipStreamEndCapture(h->stream, &g);
-        // the capture recorded the launches without running them
-        h->cur = cur;
-        h->hh = hh;
-        h->vel_is_half = vih;
-        h->step = step;
-        if (s) {
-            if (g) (void)hipGraphDestroy(g);
-            return s;
-        }
-        if (e != hipSuccess) return fail(h, DSS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return fail(h, DSS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-        h->run_graphs.push_back({key, ge});
+    hipGraph_t g = nullptr;
+    HIPTRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    dss_status s = DSS_OK;
+    for (int k = 0; k < n && !s; ++k) s = evaluate(h, EVAL_STEP, (finish >> k) & 1u);
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    h->cur = cur;
+    h->hh = hh;
+    h->vel_is_half = vih;
+    h->step = step;
+    if (s) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
     }
+    if (e != hipSuccess) return fail(h, DSS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(h, DSS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    h->run_graphs.push_back({key, ge});
+    // its first launch should not pay for setting it up on the device
+    HIPTRY(hipGraphUpload(ge, h->stream));
+    *out = ge;
+    return DSS_OK;
+}
+
+dss_status graph_run(dss_handle *h, int n, unsigned finish)
+{
+    hipGraphExec_t ge = nullptr;
+    dss_status s = run_graph(h, n, finish, &ge);
+    if (s) return s;
     HIPTRY(hipGraphLaunch(ge, h->stream));
     for (int k = 0; k < n; ++k) commit_eval(h, true);
     return DSS_OK;
 }
+
+// The runs of a dss_step call of n_steps steps sampling every stress_every: a run of steps
+// starting at index k of the call (its length, and which of its steps sum the stress), or a
+// single step when fewer than two remain.
+struct StepRuns {
+    int64_t n_steps, stress_every, step0, run;
+    StepRuns(int64_t n, int64_t se, int64_t s0)
+        : n_steps(n), stress_every(se), step0(s0), run(se >= 2 && se <= kRunSteps ? se : kRunSteps / 2) {}
+    bool finish_at(int64_t k) const  // k: the step's index within the call
+    {
+        return k == n_steps - 1 || (stress_every > 0 && (step0 + k + 1) % stress_every == 0);
+    }
+    int length_at(int64_t k) const { return n_steps - k >= 2 ? (int)std::min<int64_t>(run, n_steps - k) : 1; }
+    unsigned mask_at(int64_t k, int n) const
+    {
+        unsigned mask = 0;
+        for (int j = 0; j < n; ++j) mask |= (finish_at(k + j) ? 1u : 0u) << j;
+        return mask;
+    }
+};
 
 }  // namespace
 
@@ -1322,29 +1355,50 @@ dss_status dss_step(dss_handle *h, int64_t n_steps, int64_t stress_every, int sy
         h->tune_pending = false;
     }
     const bool graphs = h->tune.graph && !h->graph_broken && h->timing == 0 && !h->P.record_pairs;
-    // the stress and counters are summed only when a sample is due and after the last step
-    const int64_t step0 = h->step;
-    auto finish_at = [&](int64_t k) {  // k: the step's index within the call
-        return k == n_steps - 1 || (stress_every > 0 && (step0 + k + 1) % stress_every == 0);
-    };
+    // the stress and counters are summed only when a sample is due and after the last step;
     // with graphs, runs of steps as one launch: as long as the sampling period (2 .. 16) when
     // there is one, so that the runs of a call repeat, else kRunSteps / 2
-    const int64_t run = stress_every >= 2 && stress_every <= kRunSteps ? stress_every : kRunSteps / 2;
+    const StepRuns R(n_steps, stress_every, h->step);
     for (int64_t k = 0; k < n_steps;) {
-        if (graphs && n_steps - k >= 2) {
-            const int n = (int)std::min<int64_t>(run, n_steps - k);
-            unsigned mask = 0;
-            for (int j = 0; j < n; ++j) mask |= (finish_at(k + j) ? 1u : 0u) << j;
-            s = graph_run(h, n, mask);
-            k += n;
-        } else {
-            s = graphs ? graph_step(h, finish_at(k)) : evaluate(h, EVAL_STEP, finish_at(k));
-            k += 1;
-        }
+        const int n = graphs ? R.length_at(k) : 1;
+        if (n >= 2)
+            s = graph_run(h, n, R.mask_at(k, n));
+        else
+            s = graphs ? graph_step(h, R.finish_at(k)) : evaluate(h, EVAL_STEP, R.finish_at(k));
+        k += n;
         if (s) return s;
     }
     if (sync) return check_flags(h);
     return DSS_OK;
+}
+
+dss_status dss_prepare_steps(dss_handle *h, int64_t n_steps, int64_t stress_every)
+{
+    dss_status s = require_loaded(h);
+    if (s) return s;
+    if (n_steps < 0 || stress_every < 0) return fail(h, DSS_ERR_ARG, "negative n_steps or stress_every");
+    const bool graphs = h->tune.graph && !h->graph_broken && h->timing == 0 && !h->P.record_pairs;
+    if (!graphs || h->tune_pending) return DSS_OK;  // direct launches, or a lattice change comes first
+    // walk the call's runs as dss_step will, capturing the graphs it does not have yet; only
+    // the handle's bookkeeping of the buffers advances, and it is put back
+    const int cur = h->cur, hh = h->hh;
+    const bool vih = h->vel_is_half;
+    const int64_t step = h->step;
+    const StepRuns R(n_steps, stress_every, h->step);
+    for (int64_t k = 0; k < n_steps && !s;) {
+        const int n = R.length_at(k);
+        if (n >= 2) {
+            hipGraphExec_t ge = nullptr;
+            s = run_graph(h, n, R.mask_at(k, n), &ge);
+        }
+        for (int j = 0; j < n; ++j) commit_eval(h, true);
+        k += n;
+    }
+    h->cur = cur;
+    h->hh = hh;
+    h->vel_is_half = vih;
+    h->step = step;
+    return s;
 }
 
 dss_status dss_read_stress_batch(dss_handle *h, double *sigma_last, double *sigma_mean, int64_t *n_samples)
@@ -1888,25 +1942,19 @@ extern "C" dss_status dss_adjoint(dss_handle *h, int64_t n_steps, int64_t stress
     // reverse kernels does not stop them)
     const unsigned fwd_timed = h->timing & ~((1u << 5) | (1u << 6));
     const bool graphs = h->tune.graph && !h->graph_broken && fwd_timed == 0 && !h->P.record_pairs;
-    const int64_t step0 = h->step;
-    auto finish_at = [&](int64_t k) { return k == K - 1 || (step0 + k + 1) % stress_every == 0; };
-    const int64_t run = stress_every >= 2 && stress_every <= kRunSteps ? stress_every : kRunSteps / 2;
+    const StepRuns R(K, stress_every, h->step);
     for (int64_t k = 0; k < K;) {
         if (k % C == 0) {
             s = snap_save(h, W.ck[k / C]);
             if (s) return s;
         }
         const int64_t seg_end = std::min<int64_t>(K, (k / C + 1) * C);  // the next checkpoint
-        if (graphs && seg_end - k >= 2) {
-            const int n = (int)std::min<int64_t>(run, seg_end - k);
-            unsigned mask = 0;
-            for (int j = 0; j < n; ++j) mask |= (finish_at(k + j) ? 1u : 0u) << j;
-            s = graph_run(h, n, mask);
-            k += n;
-        } else {
-            s = evaluate(h, EVAL_STEP, finish_at(k));
-            k += 1;
-        }
+        const int n = graphs && seg_end - k >= 2 ? (int)std::min<int64_t>(R.run, seg_end - k) : 1;
+        if (n >= 2)
+            s = graph_run(h, n, R.mask_at(k, n));
+        else
+            s = evaluate(h, EVAL_STEP, R.finish_at(k));
+        k += n;
         if (s) return s;
     }
     double last[9], mean[9];

@@ -24,7 +24,7 @@ DSS_FLAG_EC_RANGES = 2
 STATUS = {0: "DSS_OK", 1: "DSS_ERR_ARG", 2: "DSS_ERR_HIP", 3: "DSS_ERR_CAPACITY", 4: "DSS_ERR_BOX",
           5: "DSS_ERR_UNSTABLE", 6: "DSS_ERR_STATE"}
 
-EXPORTS = ["dss_create", "dss_create_batch", "dss_set_particles", "dss_set_particles_batch", "dss_set_step", "dss_build_neighbours", "dss_compute_forces", "dss_step",
+EXPORTS = ["dss_create", "dss_create_batch", "dss_set_particles", "dss_set_particles_batch", "dss_set_step", "dss_build_neighbours", "dss_compute_forces", "dss_step", "dss_prepare_steps",
            "dss_read_stress", "dss_read_stress_batch", "dss_get_box_info", "dss_get_state", "dss_get_eval_velocities", "dss_get_pairs", "dss_get_cells", "dss_get_rolling_history",
            "dss_observe_start", "dss_observe", "dss_phi_profile", "dss_phi_profile_noalloc", "dss_contact_clusters",
            "dss_get_history", "dss_get_info", "dss_save_state", "dss_load_state", "dss_set_timing",
@@ -99,6 +99,7 @@ def load_library():
         "dss_build_neighbours": (st, [H]),
         "dss_compute_forces": (st, [H]),
         "dss_step": (st, [H, i64, i64, ctypes.c_int]),
+        "dss_prepare_steps": (st, [H, i64, i64]),
         "dss_read_stress": (st, [H, vp, vp, ctypes.POINTER(i64)]),
         "dss_get_state": (st, [H, vp, vp, vp, vp, vp, ctypes.c_int]),
         "dss_get_eval_velocities": (st, [H, vp, vp, ctypes.c_int]),
@@ -232,6 +233,11 @@ class Simulation:
 
     def step(self, n=1, stress_every=0, sync=True):
         self._check(self.lib.dss_step(self.h, int(n), int(stress_every), int(bool(sync))))
+
+    def prepare_steps(self, n, stress_every=0):
+        """Capture the graphs that step(n, stress_every) from the current state will replay,
+        without running anything."""
+        self._check(self.lib.dss_prepare_steps(self.h, int(n), int(stress_every)))
 
     def read_stress(self):
         last = np.zeros(9)

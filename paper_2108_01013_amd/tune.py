@@ -98,7 +98,10 @@ def autotune(sim, trial_steps: int = 20, cache_path: str | None = None, candidat
             sim.set_tuning(**cand, graph=True)
         except DssError:
             continue   # lattice not legal for this workload
-        sim.step(2, sync=True)           # lattice rebuild and graph capture happen here
+        sim.step(2, sync=True)           # the lattice is rebuilt here
+        prepare = getattr(sim, "prepare_steps", None)
+        if prepare:
+            prepare(trial_steps)         # and the graphs of the timed steps captured
         t0 = time.perf_counter()
         sim.step(trial_steps, sync=True)
         ms = (time.perf_counter() - t0) / trial_steps * 1e3

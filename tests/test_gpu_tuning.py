@@ -127,6 +127,36 @@ def test_graph_replay_equals_direct_launches():
     assert rel_inf(m1, m2) < 1e-8 and rel_inf(l1, l2) < 1e-8
 
 
+def test_prepare_steps_then_step():
+    """dss_prepare_steps captures the graphs of a call without running anything: the state is
+    unchanged by it, and the call that follows gives what an unprepared handle gives."""
+    from paper_2108_01013_amd.dss import Simulation
+    w = synth.config_small()
+    p = w.params
+    say("case: prepare_steps N=1000")
+    out = []
+    for prepare in (True, False):
+        sim = Simulation(p)
+        sim.set_particles(w.x, w.rad)
+        sim.step(13, stress_every=10)
+        if prepare:
+            before = sim.state()
+            sim.prepare_steps(37, stress_every=10)
+            after = sim.state()
+            assert sim.info()["step"] == 13
+            for k in ("x", "u", "w", "F", "T"):
+                assert np.array_equal(before[k], after[k]), k
+        sim.step(37, stress_every=10)
+        last, mean, ns = sim.read_stress()
+        out.append((sim.state(), last, mean, ns, sim.info()))
+        sim.close()
+    (s1, l1, m1, n1, i1), (s2, l2, m2, n2, i2) = out
+    assert n1 == n2 == 4 and i1["step"] == i2["step"] == 50
+    assert rel_inf(s1["x"], s2["x"]) < 1e-12
+    assert rel_inf(s1["F"], s2["F"]) < 1e-8
+    assert rel_inf(m1, m2) < 1e-8 and rel_inf(l1, l2) < 1e-8
+
+
 def test_autotune_batch_then_cache(tmp_path):
     from paper_2108_01013_amd import tune
     from paper_2108_01013_amd.dss import Batch
