@@ -15,6 +15,7 @@ the FP64 CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -85,10 +86,15 @@ def timed_run(sim, N, args, stress_every, kernels=("k_pairs",), steps=None, warm
     # the graphs of the timed call are captured now, so that it replays them only
     sim.prepare_steps(steps, stress_every=stress_every)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps, stress_every=stress_every, sync=False)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    gc.collect()
+    gc.disable()  # no collection of the host's objects inside the timed region
+    try:
+        t0 = time.perf_counter()
+        sim.step(steps, stress_every=stress_every, sync=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    finally:
+        gc.enable()
     sim.set_timing(True, kernels=list(kernels))
     sim.step(steps, stress_every=stress_every, sync=True)
     timing = sim.timing()
