@@ -901,6 +901,7 @@ dss_status graph_step(dss_handle *h, bool finish)
 // the run from the current buffers (capturing records the launches without running them, and
 // leaves the handle's state as it was); graph_run launches it and advances the state.
 constexpr int kRunSteps = 16;
+constexpr size_t kMaxRunGraphs = 64;  // graphs of runs kept per handle
 dss_status run_graph(dss_handle *h, int n, unsigned finish, hipGraphExec_t *out)
 {
     const uint64_t key = (uint64_t)h->cur | ((uint64_t)h->hh << 1) | ((uint64_t)(h->vel_is_half ? 1 : 0) << 2) |
@@ -910,6 +911,12 @@ dss_status run_graph(dss_handle *h, int n, unsigned finish, hipGraphExec_t *out)
             *out = g.second;
             return DSS_OK;
         }
+    if (h->run_graphs.size() >= kMaxRunGraphs) {
+        // calls of many different shapes: start the collection afresh
+        for (auto &r : h->run_graphs)
+            if (r.second) (void)hipGraphExecDestroy(r.second);
+        h->run_graphs.clear();
+    }
     const int cur = h->cur, hh = h->hh;
     const bool vih = h->vel_is_half;
     const int64_t step = h->step;
