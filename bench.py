@@ -196,7 +196,6 @@ def run_single(args):
     t_gen = time.perf_counter()
     w = cached_workload(args, lambda: synth.config_single_box(N=args.N or 100_000))
     print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
-    mode_inputs = mode_workloads(args) if args.modes else None
     import torch
 
     from paper_2108_01013_amd.dss import DSS_FP64, DSS_MIXED, Simulation
@@ -227,8 +226,10 @@ def run_single(args):
         if args.state_cache:
             with open(args.state_cache, "wb") as f:
                 f.write(sim.save_state())
-    blob = sim.save_state() if mode_inputs else None
     el, timing, breakdown = timed_run(sim, N, args, 10)
+    # the mixed mode continues from here (a host snapshot taken before the timed run would
+    # leave its copy in the device's caches and slow the first timed steps)
+    blob = sim.save_state() if args.modes else None
     info = sim.info()
     _, sigma_mean, nsamp = sim.read_stress()
     obs = observables_timing(sim) if args.observables else None
@@ -245,6 +246,10 @@ def run_single(args):
     table = kernel_table(breakdown)
     sim.close()
     modes = None
+    # the inputs of the mode comparison are made after the timed run (their worker processes
+    # start afresh, since this process already uses the GPU), so that nothing of them runs
+    # before or beside it
+    mode_inputs = mode_workloads(args, start_method="spawn") if args.modes else None
     if mode_inputs:
         modes = {"fp64": {"value": round(N * args.steps / el, 1), "ms_per_step": round(el / args.steps * 1e3, 5),
                           "roofline_frac": roof["frac"], "kernel": roof["kernel"]}}
@@ -280,19 +285,21 @@ def run_single(args):
     }
 
 
-def mode_workloads(args):
-    """Inputs of the mode comparison: the 64-box sweep and the N = 50k adjoint box, generated
-    before the GPU is touched (the sweep's boxes are relaxed in forked processes)."""
+def mode_workloads(args, start_method="fork"):
+    """Inputs of the mode comparison: the 64-box sweep and the N = 50k adjoint box (the
+    sweep's boxes are relaxed in worker processes: forked before the GPU is touched, else
+    spawned)."""
     from paper_2108_01013_amd import synth
     t0 = time.perf_counter()
-    sweep = synth.config_sweep(B=args.boxes, workers=args.workers)
+    sweep = synth.config_sweep(B=args.boxes, workers=args.workers, start_method=start_method)
     wa = synth.bidisperse_box(50_000, 0.56, seed=5)
     print(f"# mode workloads generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     return sweep, wa
 
 
 def mode_mixed(w, p, blob, args):
-    """Mixed precision on the same pre-sheared state (the FP64 run's snapshot)."""
+    """Mixed precision from the sheared state the FP64 run ended in (its snapshot), after at
+    least 20 warm-up steps (the snapshot's upload passes through the device's caches)."""
     import torch
 
     from paper_2108_01013_amd.dss import DSS_MIXED, Simulation
@@ -300,7 +307,7 @@ def mode_mixed(w, p, blob, args):
     sim.set_particles(w.x, w.rad)
     sim.load_state(blob)
     N = len(w.rad)
-    el, timing, breakdown = timed_run(sim, N, args, 10)
+    el, timing, breakdown = timed_run(sim, N, args, 10, warmup=max(args.warmup, 20))
     info = sim.info()
     ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2])
     roof = roofline(dominant_pairs(timing, breakdown), N, ncell, info["n_contacts"], info["capacity"])
