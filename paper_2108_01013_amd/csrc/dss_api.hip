@@ -721,10 +721,24 @@ void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
     }
     {
         TimedLaunch t(h, 3);
+        RowArgs R;
+        R.P = h->P;
+        R.B = h->fb();
+        R.H = H;
+        R.boxes = h->d_boxes;
+        R.row_box = h->d_row_box;
+        R.cell_start = h->cell_start;
+        R.pa = h->pa[buf];
+        R.vel = h->vel[buf];
+        R.omg = h->omg[buf];
+        R.clk = h->clk;
+        R.partials = h->partials;
+        R.pair_out = h->pairs;
+        R.pair_count = h->pair_count;
         hipExtLaunchKernelGGL(k_pairs<Real, Roll, Wave, Sum>, dim3(h->nrow_total), dim3(kPairBlock), h->tile_lds, h->stream, t.e0,
                               t.e1, 0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
                               h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, h->fb_rows,
-                              h->fb_count);
+                              h->fb_count, R);
     }
     if constexpr (!rows_in_place<Real, Roll, Wave>()) {
         // deferred rows (the instantiations that do not take them in place): workgroups

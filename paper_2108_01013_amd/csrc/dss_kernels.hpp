@@ -87,9 +87,9 @@ struct BoxParams {
 struct DevClock {
     long long step;
     unsigned err;
-    int deferred;   // the atomic force record is in use: rows the FP64 k_pairs left to k_pairs_rows at
-                    // the last evaluation, or 1 (per-particle rows of the mixed k_pairs, size-class
-                    // stencils); cleared by k_scatter
+    int deferred;   // the atomic force record is in use: rows k_pairs left to k_pairs_rows at the
+                    // last evaluation (rolling resistance, wavy shear), or 1 (per-particle rows taken
+                    // by k_pairs itself, size-class stencils); cleared by k_scatter
 };
 
 // Run descriptor of a dss_step call: stress sampling schedule.
@@ -1567,20 +1567,21 @@ __device__ __forceinline__ void reduce_fill(int fill, double (*red)[12], double 
 // the rows of one box below the slots).  The row heads are requested before A2, whose
 // barriers order LDS only, so their loads overlap the candidate tests.
 // Tile capacities (P.own_cap, P.stage_cap, P.qcap) are sized from the mean row occupancy; a
-// row beyond them takes the per-particle path (k_pairs_rows).  Sum: the row's stress and
+// row beyond them takes the per-particle path (see rows_in_place).  Sum: the row's stress and
 // counters are reduced into its partial record.  Steps whose stress is not summed take
 // Sum = false, and the compiler drops the stresslet arithmetic and its accumulators (the
 // forces, torques and history are the same).
 // ----------------------------------------------------------------------------------
 constexpr int kPairBlock = 192;
 
-// The k_pairs instantiations that take their rows beyond the tile capacities in place (the
-// others leave them to k_pairs_rows): the mixed kernel without rolling resistance and wavy
-// shear, whose FP32 physics leaves room for the per-particle path in the tile's registers.
+// The k_pairs instantiations that take their rows beyond the tile capacities themselves (the
+// others, with rolling resistance or the wavy shear, leave them to k_pairs_rows): the mixed
+// kernel inlines the per-particle path (its FP32 physics leaves the registers for it), the
+// FP64 one calls it out of line (row_per_particle).
 template <typename Real, bool Roll, bool Wave>
 __host__ __device__ constexpr bool rows_in_place()
 {
-    return std::is_same<Real, float>::value && !Roll && !Wave;
+    return !Roll && !Wave;
 }
 constexpr int kPairWaves = kPairBlock / 64;
 constexpr int kHeadPre = 3;  // row heads per lane requested before A2
@@ -1827,6 +1828,49 @@ __device__ __forceinline__ TaskWindow task_window(const BoxParams &G, const Tile
     return W;
 }
 
+// The arguments of the per-particle path inside k_pairs, as a kernel argument of its own: the
+// call reads them from the kernel's argument segment where it is made, while values passed from
+// the tile path's own arguments were copied to memory at the kernel's start, on every row.
+struct RowArgs {
+    DevParams P;
+    ForceBufs B;
+    HistView H;
+    const BoxParams *boxes;
+    const int *row_box;
+    const int *cell_start;
+    const double4 *pa, *vel, *omg;
+    DevClock *clk;
+    double *partials;
+    int *pair_out;
+    unsigned long long *pair_count;
+};
+
+// One cell row on the per-particle path, taken by the k_pairs workgroup that found it beyond its
+// tile (the FP64 kernel).  Kept out of line: the FP64 physics of a lane's whole half shell
+// needs more registers than the tile path leaves, and as a call its spills stay on this rare
+// path (nothing of the tile is live at the call), where inlined they spilled the tile path.
+template <typename Real, bool Roll, bool Wave, bool Sum>
+__device__ __noinline__ void row_per_particle(RowArgs R, int grow, TileShared &T)
+{
+    const DevParams &P = R.P;
+    const int t = threadIdx.x;
+    const BoxParams G = R.boxes[P.nbox > 1 ? R.row_box[grow] : 0];
+    const double delta = le_offset(P, G, R.clk->step);
+    PairTally tally;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
+    tally.npair = tally.ncont = 0;
+    tally.fill = 0;
+    for (int i = T.rs[0] + t; i < T.re[0]; i += kPairBlock)
+        particle_pairs_global<Real, Roll, Wave>(P, G, i, delta, R.cell_start, R.pa, R.vel, R.omg, R.B, R.H, R.clk,
+                                                R.pair_out, R.pair_count, tally);
+    const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int r = 1; r < 5; ++r)
+        for (int g = T.rs[r] + t; g < T.re[r]; g += kPairBlock) store_ft(R.B.nb + 6LL * ((r - 1) * R.B.n + g), z);
+    if (t == 0) R.clk->deferred = 1;
+    if constexpr (Sum) reduce_tally(tally, T.red, R.partials, P.pstride, grow);
+}
+
 template <typename Real, bool Roll, bool Wave, bool Sum>
 __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxParams *__restrict__ boxes,
                                                           const int *__restrict__ row_box,
@@ -1837,7 +1881,8 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
                                                           DevClock *__restrict__ clk, double *__restrict__ partials,
                                                           int *__restrict__ pair_out,
                                                           unsigned long long *__restrict__ pair_count,
-                                                          int *__restrict__ fb_rows, int *__restrict__ fb_count)
+                                                          int *__restrict__ fb_rows, int *__restrict__ fb_count,
+                                                          RowArgs R)
 {
     __shared__ TileShared T;
     extern __shared__ double4 dyn_lds[];
@@ -1873,12 +1918,14 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
     const int n_own = T.re[0] - T.rs[0];
     const int total = T.ro[5];
     // a row beyond the tile capacities (or one that hits a tile limit below) takes the
-    // per-particle path: in the plain mixed kernel here, by its own workgroup (the FP32 physics
-    // leaves the registers for it; the partner sides go to the atomic record, which k_predict
-    // then reads), in the others in k_pairs_rows (inlined here it would spill the tile path);
-    // nothing of the tile is written
+    // per-particle path: without rolling resistance and wavy shear by its own workgroup (the
+    // partner sides go to the atomic record, which k_predict then reads; inlined in the mixed
+    // kernel, a call in the FP64 one), in the others in k_pairs_rows; nothing of the tile is
+    // written
     auto defer_row = [&]() {
-        if constexpr (rows_in_place<Real, Roll, Wave>()) {
+        if constexpr (rows_in_place<Real, Roll, Wave>() && std::is_same<Real, double>::value) {
+            row_per_particle<Real, Roll, Wave, Sum>(R, grow, T);
+        } else if constexpr (rows_in_place<Real, Roll, Wave>()) {
             for (int i = T.rs[0] + t; i < T.re[0]; i += kPairBlock)
                 particle_pairs_global<Real, Roll, Wave>(P, G, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out,
                                                         pair_count, tally);
@@ -2134,11 +2181,12 @@ per_particle:
 }
 
 // ----------------------------------------------------------------------------------
-// k_pairs_rows: the cell rows that k_pairs deferred (beyond the tile capacities), on the
-// per-particle path: one lane per own particle walks its half shell with global loads, keeps
-// its own side in registers and adds the partner side to the atomic force record; the
-// partner records of the row's four shell rows are zero; the row's stress partial as in
-// k_pairs.  Workgroups stride over the list of deferred rows.
+// k_pairs_rows: the cell rows that k_pairs deferred (beyond the tile capacities, in the kernels
+// with rolling resistance or the wavy shear), on the per-particle path: one lane per own
+// particle walks its half shell with global loads, keeps its own side in registers and adds
+// the partner side to the atomic force record; the partner records of the row's four shell
+// rows are zero; the row's stress partial as in k_pairs.  Workgroups stride over the list of
+// deferred rows.
 // ----------------------------------------------------------------------------------
 template <typename Real, bool Roll, bool Wave>
 __global__ void __launch_bounds__(kBlock, 2) k_pairs_rows(DevParams P, const BoxParams *__restrict__ boxes,
