@@ -60,13 +60,15 @@ def lockstep(sim, p, rad, n0, nsteps, tol):
     return worst_xr
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_rolling_lockstep(precision):
+@pytest.mark.parametrize("precision,tiled", [(0, True), (1, True), (0, False), (1, False)])
+def test_rolling_lockstep(precision, tiled):
+    """Row tiles, or (tiled False) every row on the per-particle path of the deferred rows."""
     from paper_2108_01013_amd.dss import Simulation
     w = synth.config_small()
     p = rolling(w.params)
-    say(f"case: rolling N=1000 precision={precision}")
+    say(f"case: rolling N=1000 precision={precision} tiled={tiled}")
     sim = Simulation(p, record_pairs=True, precision=precision)
+    sim.set_tuning(tiled=tiled)
     sim.set_particles(w.x, w.rad)
     sim.step(5)
     xr = lockstep(sim, p, w.rad, 5, 5, TOL_F if precision == 0 else TOL_MIXED)

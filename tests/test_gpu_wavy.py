@@ -79,13 +79,15 @@ def lockstep(sim, p, rad, n0, nsteps, tol):
             assert np.max(np.abs(hx - H.xi)) <= max(tol, 1e-10) * np.max(np.abs(H.xi))
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_wavy_lockstep(precision):
+@pytest.mark.parametrize("precision,tiled", [(0, True), (1, True), (0, False), (1, False)])
+def test_wavy_lockstep(precision, tiled):
+    """Row tiles, or (tiled False) every row on the per-particle path of the deferred rows."""
     from paper_2108_01013_amd.dss import DssError, Simulation
     w = synth.config_small()
     p = wavy(w.params)
-    say(f"case: wavy shear N=1000 precision={precision}")
+    say(f"case: wavy shear N=1000 precision={precision} tiled={tiled}")
     sim = Simulation(p, record_pairs=True, precision=precision)
+    sim.set_tuning(tiled=tiled)
     sim.set_particles(w.x, w.rad)
     s0 = sim.state()
     assert rel_inf(s0["u"], oracle.ambient_velocity(p, w.x)) < 1e-15
