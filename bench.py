@@ -238,7 +238,7 @@ def run_single(args):
         sys.exit(1)
     ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2])
     ncell *= sim.box_info(0)["size_classes"]
-    roof = roofline(dominant_pairs(timing, breakdown), N, ncell, info["n_contacts"], info["capacity"],
+    roof = roofline(timing, N, ncell, info["n_contacts"], info["capacity"],
                     measured_traffic() if args.precision == "fp64" and N == 100_000 and not physics else None)
     if args.sized and roof["kernel"] == "k_pairs":
         roof["kernel"] = "k_pairs_sized"
@@ -310,7 +310,7 @@ def mode_mixed(w, p, blob, args):
     el, timing, breakdown = timed_run(sim, N, args, 10, warmup=max(args.warmup, 20))
     info = sim.info()
     ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2])
-    roof = roofline(dominant_pairs(timing, breakdown), N, ncell, info["n_contacts"], info["capacity"])
+    roof = roofline(timing, N, ncell, info["n_contacts"], info["capacity"])
     sim.close()
     return {"value": round(N * args.steps / el, 1), "ms_per_step": round(el / args.steps * 1e3, 5), "N": N,
             "workload": "the FP64 box's pre-sheared state, FP32 pair arithmetic with FP64 gap and sums",
@@ -339,7 +339,7 @@ def measure_sweep(ws, gds, args, tune: bool, preshear_steps: int):
     ncell = int(sum(np.prod(b["cells"]) for b in boxes))
     eta = [float(sigma_mean[b, 0, 1] / (params[b]["eta0"] * gds[b])) for b in range(sim.B)]
     res = dict(N=N, B=sim.B, el=el, sheared=sheared, info=info, nsamp=nsamp, eta=eta, ncell=ncell,
-               roof=roofline(dominant_pairs(timing, breakdown), N, ncell, info["n_contacts"], info["capacity"]),
+               roof=roofline(timing, N, ncell, info["n_contacts"], info["capacity"]),
                table=kernel_table(breakdown), tuning=tuned or sim.tuning())
     sim.close()
     return res
@@ -351,18 +351,6 @@ def mode_sweep(ws, gds, args):
             "N": r["N"], "workload": f"{r['B']} boxes, N_b uniform on 2000..50000, phi 0.40..0.58, shear rate "
                                      f"1e-2..1e1, one graph per step, after {r['sheared']} steps of pre-shear",
             "roofline": r["roof"], "contacts_per_particle": round(r["info"]["n_contacts"] / r["N"], 4)}
-
-
-def dominant_pairs(timing, breakdown):
-    """The pair kernel that takes longer: the row tiles (k_pairs, timed over the timed region)
-    or, when the per-kernel pass shows it longer, the rows they deferred to the per-particle
-    path (k_pairs_rows, timed in that pass)."""
-    def avg(t, k):
-        ms, n = t.get(k, (0.0, 0))
-        return ms / max(n, 1)
-    if avg(breakdown, "k_pairs_rows") > avg(breakdown, "k_pairs"):
-        return {"k_pairs": breakdown["k_pairs_rows"], "name": "k_pairs_rows"}
-    return {"k_pairs": timing["k_pairs"], "name": "k_pairs"}
 
 
 def observables_timing(sim):
@@ -407,7 +395,7 @@ def run_poly(args):
     sim.set_particles(w.x, w.rad)
     N = len(w.rad)
     tuned = maybe_tune(sim, args)
-    el, timing, breakdown = timed_run(sim, N, args, 10, kernels=["k_pairs", "k_pairs_rows"])
+    el, timing, breakdown = timed_run(sim, N, args, 10)
     info = sim.info()
     _, sigma_mean, nsamp = sim.read_stress()
     if info["error_flags"]:
@@ -418,10 +406,8 @@ def run_poly(args):
     names = {"k_pairs": "k_pairs_sized"} if sized else {}
     box = sim.box_info(0)
     ncell = int(info["cells"][0] * info["cells"][1] * info["cells"][2]) * int(box["size_classes"])
-    # dominant pair kernel of the timed region
-    dom = max(("k_pairs", "k_pairs_rows"), key=lambda k: timing.get(k, (0.0, 0))[0])
-    roof = roofline({"k_pairs": timing[dom]}, N, ncell, info["n_contacts"], info["capacity"])
-    roof["kernel"] = names.get(dom, dom)
+    roof = roofline(timing, N, ncell, info["n_contacts"], info["capacity"])
+    roof["kernel"] = names.get("k_pairs", "k_pairs")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds, "the same N=500k lognormal")

@@ -342,9 +342,8 @@ dss_status dss_load_state(dss_handle *h, const void *blob, size_t bytes);
  * the kernels selected by enable (bit k: kernel k; -1: all; 0: off); every call starts a
  * new accumulation.  dss_get_timing synchronises and returns, for kernel k (0 predict or
  * velocity completion, 1 scan, 2 scatter, 3 pairs, 4 finish, 5 pair adjoint, 6 integrator
- * adjoint, 7 pairs of the rows beyond the tile capacities, 8 electro-chemical pairs beyond
- * the lubrication list; with size-class stencils 3 is their one pair kernel), the summed
- * duration in ms and the number of timed launches. */
+ * adjoint, 7 electro-chemical pairs beyond the lubrication list; with size-class stencils 3
+ * is their one pair kernel), the summed duration in ms and the number of timed launches. */
 dss_status dss_set_timing(dss_handle *h, int enable);
 dss_status dss_get_timing(dss_handle *h, int kernel, double *total_ms, int64_t *launches);
 

@@ -114,8 +114,6 @@ struct dss_handle {
     double *box_diag = nullptr;       // nbox x 3: listed pairs, contacts, largest history row
     int *tile_sum = nullptr;          // totals of the multi-workgroup scan
     int *cs_local = nullptr;          // tile-local cell starts of the parallel scan (up to 16 tiles)
-    int *fb_rows = nullptr, *fb_count = nullptr;  // rows deferred to the per-particle path
-    int deferred_hint = -1;           // deferred rows at the last synchronised evaluation
     int ncell_total = 0, nrow_total = 0;
     int scan_tiles = 0;               // 0: one-workgroup scan (scan_c4), else workgroups of 16384 cells
     std::vector<double> box_amax;     // largest radius per box
@@ -181,7 +179,7 @@ struct dss_handle {
     DevRun run_host{};
 
     // kernel timing with events on the stream
-    static constexpr int kKernels = 9;
+    static constexpr int kKernels = 8;
     unsigned timing = 0;       // bit k: time kernel k
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<int, int>>> ev_marks;  // (kernel, (start event, stop event))
@@ -243,8 +241,7 @@ void free_lattice(dss_handle *h)
     destroy_graphs(h);
     F(h->count); F(h->cell_start); F(h->tile_sum); F(h->cs_local); F(h->partials); F(h->d_boxes); F(h->d_row_box);
     h->cs_local = nullptr;
-    F(h->fb_rows); F(h->fb_count);
-    h->count = h->cell_start = h->tile_sum = h->d_row_box = h->fb_rows = h->fb_count = nullptr;
+    h->count = h->cell_start = h->tile_sum = h->d_row_box = nullptr;
     h->partials = nullptr;
     h->d_boxes = nullptr;
 }
@@ -326,7 +323,6 @@ dss_status check_flags(dss_handle *h)
     DevClock c;
     HIPTRY(hipMemcpyAsync(&c, h->clk, sizeof(c), hipMemcpyDeviceToHost, h->stream));
     HIPTRY(hipStreamSynchronize(h->stream));
-    h->deferred_hint = c.deferred;
     if (c.err & kErrNonFinite) return fail(h, DSS_ERR_UNSTABLE, "non-finite force or torque");
     if (c.err & kErrRowOverflow) {
         std::vector<double> d;
@@ -601,7 +597,6 @@ dss_status setup_lattice(dss_handle *h)
     }
     h->ncell_total = (int)ncell;
     h->nrow_total = nrow;
-    h->deferred_hint = -1;
     h->max_mean_row = max_mean_row;
     // row-tile capacities of k_pairs from the mean occupancy of a cell row (own row and the
     // five rows of the half shell) of the densest box, times tile_scale; rows beyond them
@@ -677,9 +672,6 @@ dss_status setup_lattice(dss_handle *h)
     HIPTRY(dalloc(&h->partials, 12 * (size_t)P.pstride));
     HIPTRY(dalloc(&h->d_boxes, B));
     HIPTRY(dalloc(&h->d_row_box, nrow));
-    HIPTRY(dalloc(&h->fb_rows, nrow));
-    HIPTRY(dalloc(&h->fb_count, 1));
-    HIPTRY(hipMemsetAsync(h->fb_count, 0, sizeof(int), h->stream));
     HIPTRY(hipMemcpyAsync(h->d_boxes, h->boxes.data(), B * sizeof(BoxParams), hipMemcpyHostToDevice, h->stream));
     HIPTRY(hipMemcpyAsync(h->d_row_box, row_box.data(), nrow * sizeof(int), hipMemcpyHostToDevice, h->stream));
     HIPTRY(hipMemsetAsync(h->partials, 0, 12 * (size_t)P.pstride * sizeof(double), h->stream));
@@ -696,9 +688,11 @@ dss_status setup_lattice(dss_handle *h)
 enum EvalMode { EVAL_STEP = 0, EVAL_SORT = 1, EVAL_INPLACE = 2, EVAL_RESORT = 3 };
 
 // The pair kernels of one evaluation: size-class stencils (lane and wavefront paths), or
-// the row tiles followed by the rows they deferred (k_pairs_rows; see rows_in_place).  Real: FP64 or mixed arithmetic; Roll:
-// rolling resistance; Wave: the wavy ambient shear; Sum: the stress and counters are summed
-// (k_finish follows), else the tile and stencil kernels skip them.
+// the row tiles (a row beyond their capacities on the per-particle path, by its own
+// workgroup), after the electro-chemical far pairs when they have a pass of their own.
+// Real: FP64 or mixed arithmetic; Roll: rolling resistance; Wave: the wavy ambient shear;
+// Sum: the stress and counters are summed (k_finish follows), else the tile and stencil
+// kernels skip them.
 template <typename Real, bool Roll, bool Wave, bool Sum>
 void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
 {
@@ -713,7 +707,7 @@ void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
     if (h->P.ec_split) {
         // the far electro-chemical pairs first: plain stores into the atomic record, which the
         // deferred rows below add to
-        TimedLaunch t(h, 8);
+        TimedLaunch t(h, 7);
         const BoxParams &G = h->boxes[0];
         hipExtLaunchKernelGGL(k_pairs_ec<Sum>, dim3(h->ec_grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P,
                               h->d_boxes, h->cell_start, h->pa[buf], h->omg[buf], h->ft_x, h->clk, h->partials,
@@ -737,21 +731,7 @@ void launch_pair_kernels(dss_handle *h, int buf, const HistView &H)
         R.pair_count = h->pair_count;
         hipExtLaunchKernelGGL(k_pairs<Real, Roll, Wave, Sum>, dim3(h->nrow_total), dim3(kPairBlock), h->tile_lds, h->stream, t.e0,
                               t.e1, 0, h->P, h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf],
-                              h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, h->fb_rows,
-                              h->fb_count, R);
-    }
-    if constexpr (!rows_in_place<Real, Roll, Wave>()) {
-        // deferred rows (the instantiations that do not take them in place): workgroups
-        // striding over the list, as many as the rows deferred at the last synchronised
-        // evaluation (a few when that is unknown or none), one per row when every row takes
-        // the per-particle path
-        TimedLaunch t(h, 7);
-        const int hint = h->deferred_hint < 0 ? 64 : h->deferred_hint + h->deferred_hint / 4 + 8;
-        const int grid = h->tune.tiled ? std::min(h->nrow_total, hint) : h->nrow_total;
-        hipExtLaunchKernelGGL(k_pairs_rows<Real, Roll, Wave>, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P,
-                              h->d_boxes, h->d_row_box, h->cell_start, h->pa[buf], h->vel[buf], h->omg[buf], h->fb(),
-                              H, h->clk, h->partials, h->pairs, h->pair_count, (const int *)h->fb_rows,
-                              (const int *)h->fb_count);
+                              h->omg[buf], h->fb(), H, h->clk, h->partials, h->pairs, h->pair_count, R);
     }
 }
 
@@ -820,7 +800,6 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
                                   h->vel[c], h->omg[c], h->fb());
         }
         HIPTRY(hipMemsetAsync(h->ft_x, 0, 6 * h->N * sizeof(double), h->stream));
-        HIPTRY(hipMemsetAsync(h->fb_count, 0, sizeof(int), h->stream));
         if (h->P.record_pairs) HIPTRY(hipMemsetAsync(h->pair_count, 0, sizeof(unsigned long long), h->stream));
         dss_status s = launch_pairs(h, c, nullptr, 0, true);
         if (s) return s;
@@ -832,7 +811,7 @@ dss_status evaluate(dss_handle *h, EvalMode mode, bool finish = true)
         TimedLaunch t(h, 0);
         hipExtLaunchKernelGGL(k_predict, dim3(grid), dim3(kBlock), 0, h->stream, t.e0, t.e1, 0, h->P, h->d_boxes,
                               h->pa[c], h->vel[c], h->omg[c], h->fb(), h->vel_is_half ? 1 : 0, advance, h->clk,
-                              h->cell, h->rank, h->count, h->fb_count, h->img, h->boxes[0],
+                              h->cell, h->rank, h->count, h->img, h->boxes[0],
                               h->P.record_pairs ? h->pair_count : (unsigned long long *)nullptr, h->tape_x,
                               h->tape_u, h->tape_w, h->tape_zero);
     }

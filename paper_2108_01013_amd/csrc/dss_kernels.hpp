@@ -87,9 +87,8 @@ struct BoxParams {
 struct DevClock {
     long long step;
     unsigned err;
-    int deferred;   // the atomic force record is in use: rows k_pairs left to k_pairs_rows at the
-                    // last evaluation (rolling resistance, wavy shear), or 1 (per-particle rows taken
-                    // by k_pairs itself, size-class stencils); cleared by k_scatter
+    int deferred;   // 1: the atomic force record is in use (rows of k_pairs on the per-particle
+                    // path, size-class stencils); cleared by k_scatter
 };
 
 // Run descriptor of a dss_step call: stress sampling schedule.
@@ -387,7 +386,7 @@ __global__ void __launch_bounds__(1024) k_scan_add(int *__restrict__ cell_start,
 //   vel_is_half = 1: vel holds the half-step velocity u^{n-1/2} of the forces, and
 //   u^n = u^{n-1/2} + dt/2 F^n / m completes the previous step.
 // The atomic force record is read, and cleared for the next evaluation, only when the last
-// evaluation deferred rows to the per-particle path (clk->deferred > 0) or k_pairs_ec wrote
+// evaluation took rows on the per-particle path (clk->deferred > 0) or k_pairs_ec wrote
 // it (ec_split); otherwise it is already zero.
 // ----------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams *__restrict__ boxes,
@@ -395,18 +394,14 @@ __global__ void __launch_bounds__(kBlock) k_predict(DevParams P, const BoxParams
                                                      double4 *__restrict__ omg, ForceBufs B, int vel_is_half,
                                                      int advance, const DevClock *__restrict__ clk,
                                                      int *__restrict__ cell, int *__restrict__ rank,
-                                                     int *__restrict__ count, int *__restrict__ fb_count,
-                                                     int *__restrict__ img, BoxParams G0,
+                                                     int *__restrict__ count, int *__restrict__ img, BoxParams G0,
                                                      unsigned long long *__restrict__ pair_count,
                                                      double *__restrict__ tx, double *__restrict__ tu,
                                                      double *__restrict__ tw, int *__restrict__ tz)
 {
 #pragma clang fp contract(off)
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) {
-        *fb_count = 0;                   // rows deferred by this step's k_pairs
-        if (pair_count) *pair_count = 0;  // the pairs this step's pair kernels record
-    }
+    if (p == 0 && pair_count) *pair_count = 0;  // the pairs this step's pair kernels record
     if (tz && p < P.N) tz[p] = 0;  // counts the adjoint's tape fills after this evaluation
     const bool active = p < P.N;
     int c = -1;
@@ -1567,21 +1562,20 @@ __device__ __forceinline__ void reduce_fill(int fill, double (*red)[12], double 
 // the rows of one box below the slots).  The row heads are requested before A2, whose
 // barriers order LDS only, so their loads overlap the candidate tests.
 // Tile capacities (P.own_cap, P.stage_cap, P.qcap) are sized from the mean row occupancy; a
-// row beyond them takes the per-particle path (see rows_in_place).  Sum: the row's stress and
+// row beyond them takes the per-particle path, by its own workgroup.  Sum: the row's stress and
 // counters are reduced into its partial record.  Steps whose stress is not summed take
 // Sum = false, and the compiler drops the stresslet arithmetic and its accumulators (the
 // forces, torques and history are the same).
 // ----------------------------------------------------------------------------------
 constexpr int kPairBlock = 192;
 
-// The k_pairs instantiations that take their rows beyond the tile capacities themselves (the
-// others, with rolling resistance or the wavy shear, leave them to k_pairs_rows): the mixed
-// kernel inlines the per-particle path (its FP32 physics leaves the registers for it), the
-// FP64 one calls it out of line (row_per_particle).
+// The k_pairs instantiation that inlines the per-particle path of a row beyond the tile
+// capacities: the mixed kernel without rolling resistance and wavy shear, whose FP32 physics
+// leaves the registers for it; the others call it out of line (row_per_particle).
 template <typename Real, bool Roll, bool Wave>
-__host__ __device__ constexpr bool rows_in_place()
+__host__ __device__ constexpr bool rows_inlined()
 {
-    return !Roll && !Wave;
+    return std::is_same<Real, float>::value && !Roll && !Wave;
 }
 constexpr int kPairWaves = kPairBlock / 64;
 constexpr int kHeadPre = 3;  // row heads per lane requested before A2
@@ -1846,9 +1840,10 @@ struct RowArgs {
 };
 
 // One cell row on the per-particle path, taken by the k_pairs workgroup that found it beyond its
-// tile (the FP64 kernel).  Kept out of line: the FP64 physics of a lane's whole half shell
-// needs more registers than the tile path leaves, and as a call its spills stay on this rare
-// path (nothing of the tile is live at the call), where inlined they spilled the tile path.
+// tile (every kernel but the plain mixed one).  Kept out of line: the physics of a lane's whole
+// half shell needs more registers than the tile path leaves, and as a call its spills stay on
+// this rare path (nothing of the tile is live at the call), where inlined they spilled the
+// tile path.
 template <typename Real, bool Roll, bool Wave, bool Sum>
 __device__ __noinline__ void row_per_particle(RowArgs R, int grow, TileShared &T)
 {
@@ -1880,9 +1875,7 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
                                                           const double4 *__restrict__ omg, ForceBufs B, HistView H,
                                                           DevClock *__restrict__ clk, double *__restrict__ partials,
                                                           int *__restrict__ pair_out,
-                                                          unsigned long long *__restrict__ pair_count,
-                                                          int *__restrict__ fb_rows, int *__restrict__ fb_count,
-                                                          RowArgs R)
+                                                          unsigned long long *__restrict__ pair_count, RowArgs R)
 {
     __shared__ TileShared T;
     extern __shared__ double4 dyn_lds[];
@@ -1918,14 +1911,13 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
     const int n_own = T.re[0] - T.rs[0];
     const int total = T.ro[5];
     // a row beyond the tile capacities (or one that hits a tile limit below) takes the
-    // per-particle path: without rolling resistance and wavy shear by its own workgroup (the
-    // partner sides go to the atomic record, which k_predict then reads; inlined in the mixed
-    // kernel, a call in the FP64 one), in the others in k_pairs_rows; nothing of the tile is
-    // written
+    // per-particle path by its own workgroup (the partner sides go to the atomic record, which
+    // k_predict then reads; inlined in the plain mixed kernel, a call in the others); nothing
+    // of the tile is written
     auto defer_row = [&]() {
-        if constexpr (rows_in_place<Real, Roll, Wave>() && std::is_same<Real, double>::value) {
+        if constexpr (!rows_inlined<Real, Roll, Wave>()) {
             row_per_particle<Real, Roll, Wave, Sum>(R, grow, T);
-        } else if constexpr (rows_in_place<Real, Roll, Wave>()) {
+        } else {
             for (int i = T.rs[0] + t; i < T.re[0]; i += kPairBlock)
                 particle_pairs_global<Real, Roll, Wave>(P, G, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out,
                                                         pair_count, tally);
@@ -1934,8 +1926,6 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
                 for (int g = T.rs[r] + t; g < T.re[r]; g += kPairBlock) store_ft(B.nb + 6LL * ((r - 1) * B.n + g), z);
             if (t == 0) clk->deferred = 1;
             if constexpr (Sum) reduce_tally(tally, T.red, partials, P.pstride, grow);
-        } else {
-            if (t == 0) fb_rows[atomicAdd(fb_count, 1)] = grow;
         }
     };
     if (!P.tiled || n_own > P.own_cap || total > P.stage_cap) goto per_particle;
@@ -2178,51 +2168,6 @@ __global__ void __launch_bounds__(kPairBlock, 3) k_pairs(DevParams P, const BoxP
   }
 per_particle:
     defer_row();
-}
-
-// ----------------------------------------------------------------------------------
-// k_pairs_rows: the cell rows that k_pairs deferred (beyond the tile capacities, in the kernels
-// with rolling resistance or the wavy shear), on the per-particle path: one lane per own
-// particle walks its half shell with global loads, keeps its own side in registers and adds
-// the partner side to the atomic force record; the partner records of the row's four shell
-// rows are zero; the row's stress partial as in k_pairs.  Workgroups stride over the list of
-// deferred rows.
-// ----------------------------------------------------------------------------------
-template <typename Real, bool Roll, bool Wave>
-__global__ void __launch_bounds__(kBlock, 2) k_pairs_rows(DevParams P, const BoxParams *__restrict__ boxes,
-                                                       const int *__restrict__ row_box,
-                                                       const int *__restrict__ cell_start,
-                                                       const double4 *__restrict__ pa, const double4 *__restrict__ vel,
-                                                       const double4 *__restrict__ omg, ForceBufs B, HistView H,
-                                                       DevClock *__restrict__ clk, double *__restrict__ partials,
-                                                       int *__restrict__ pair_out,
-                                                       unsigned long long *__restrict__ pair_count,
-                                                       const int *__restrict__ fb_rows,
-                                                       const int *__restrict__ fb_count)
-{
-    __shared__ TileShared T;
-    const int t = threadIdx.x;
-    const int n = *fb_count;
-    if (blockIdx.x == 0 && t == 0) clk->deferred = n;
-    for (int e = blockIdx.x; e < n; e += gridDim.x) {
-        const int grow = fb_rows[e];
-        const BoxParams G = boxes[row_box[grow]];
-        const double delta = le_offset(P, G, clk->step);
-        PairTally tally;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) tally.S[k] = 0.0;
-        tally.npair = tally.ncont = 0;
-        tally.fill = 0;
-        row_bounds(G, grow - G.row_off, cell_start, T);
-        for (int i = T.rs[0] + t; i < T.re[0]; i += kBlock)
-            particle_pairs_global<Real, Roll, Wave>(P, G, i, delta, cell_start, pa, vel, omg, B, H, clk, pair_out, pair_count,
-                                        tally);
-        const double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int r = 1; r < 5; ++r)
-            for (int g = T.rs[r] + t; g < T.re[r]; g += kBlock) store_ft(B.nb + 6LL * ((r - 1) * B.n + g), z);
-        reduce_tally(tally, T.red, partials, P.pstride, grow);
-        __syncthreads();
-    }
 }
 
 // ----------------------------------------------------------------------------------

@@ -319,7 +319,7 @@ class Simulation:
         return pr[order], xi[order]
 
     KERNELS = ("k_predict", "k_scan", "k_scatter", "k_pairs", "k_finish", "k_pairs_vjp", "k_integrate_vjp",
-               "k_pairs_rows", "k_pairs_ec")
+               "k_pairs_ec")
 
     def set_tuning(self, cell_scale=None, tile_scale=None, tiled=None, graph=None, sized=None, wave_class=None,
                    queue_cap=None, adj_cap=None):

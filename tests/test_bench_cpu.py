@@ -30,5 +30,5 @@ def test_roofline_entry():
     assert abs(r["avg_launch_us"] - 50.0) < 1e-9
     assert abs(r["achieved"] - round(b / 50e-6 / 1e9, 2)) < 1e-9 and r["peak"] == 8000.0
     assert abs(r["frac"] - round(r["achieved"] / 8000.0, 5)) < 1e-12 and r["traffic"] == 49_000_000
-    timing["name"] = "k_pairs_rows"
+    timing["name"] = "k_pairs_sized"                # counters taken on the row tiles only
     assert bench.roofline(timing, N, ncell, contacts, 37, traffic=4.9e7)["traffic"] is None

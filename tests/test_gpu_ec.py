@@ -155,7 +155,7 @@ def test_ec_far_pass_lockstep_20k(ec_big_box, precision):
     assert bi["ec_far_rows"][0] > 0
     assert np.array_equal(sim.cells()[0], oracle.cell_dims(dict(p, ec_ranges=False), w.rad.max()))
     assert np.array_equal(sim.pairs(), oracle.pairs_cells(p, w.x, w.rad, 0.0))
-    sim.set_timing(True, ["k_pairs", "k_pairs_rows", "k_pairs_ec"])
+    sim.set_timing(True, ["k_pairs", "k_pairs_ec"])
     sim.step(2)
     hp, hx = sim.history()
     for k in range(2):
@@ -181,5 +181,5 @@ def test_ec_far_pass_lockstep_20k(ec_big_box, precision):
         assert np.array_equal(hp, H.pairs)
     t = sim.timing()
     assert t["k_pairs_ec"][1] > 0
-    say(f"k_pairs {t['k_pairs']}, deferred rows {t['k_pairs_rows']}, far pass {t['k_pairs_ec']}")
+    say(f"k_pairs {t['k_pairs']}, far pass {t['k_pairs_ec']}")
     sim.close()
