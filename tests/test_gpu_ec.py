@@ -34,14 +34,17 @@ def ec_box():
     return synth.Workload("bidisperse N=4000 phi=0.45, attraction", w.x, w.rad, w.L, p)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_ec_ranges_lockstep(ec_box, precision):
+@pytest.mark.parametrize("precision,tiled", [(0, True), (1, True), (0, False)])
+def test_ec_ranges_lockstep(ec_box, precision, tiled):
+    """tiled False: every row of the lubrication list on the per-particle path, whose partner
+    sides add to the atomic record after the far pass stored into it."""
     from paper_2108_01013_amd.dss import Simulation
     w = ec_box
     p = w.params
     tol = TOL_F if precision == 0 else TOL_MIXED
-    say(f"case: electro-chemical ranges N=4000 precision={precision}")
+    say(f"case: electro-chemical ranges N=4000 precision={precision} tiled={tiled}")
     sim = Simulation(p, record_pairs=True, precision=precision)
+    sim.set_tuning(tiled=tiled)
     sim.set_particles(w.x, w.rad)
     dims = sim.cells()[0]
     # one box: the lattice of the lubrication list, the pairs beyond it on their own pass
