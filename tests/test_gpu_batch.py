@@ -58,10 +58,11 @@ def check_box(sim, b, ws, s1, uh, wh, pairs, cs, perm, hist, nstep, use_cells):
     return S, H, npairs
 
 
-def run_lockstep(ws, gds, steps, step0=0, use_cells=False, check=None):
+def run_lockstep(ws, gds, steps, step0=0, use_cells=False, check=None, tiled=True):
     from paper_2108_01013_amd.dss import Batch
     params = [dict(w.params, shear_rate=g) for w, g in zip(ws, gds)]
     sim = Batch(params, record_pairs=True)
+    sim.set_tuning(tiled=tiled)
     sim.set_particles([w.x for w in ws], [w.rad for w in ws])
     B = len(ws)
     if step0:
@@ -123,6 +124,17 @@ def test_batch_lockstep_small(step0):
         bi = sim.box_info(b)
         p = sim.params_list[b]
         assert bi["le_offset"] == oracle.le_offset(p, step0 + 6)
+    sim.close()
+
+
+def test_batch_lockstep_per_particle_rows():
+    """Every cell row of every box on the per-particle path (tiling off): each row finds its
+    box in the table."""
+    ws = small_boxes()
+    gds = [0.01, 0.1, 1.0, 3.0, 10.0]
+    say("case: batch lockstep 5 boxes, every row on the per-particle path")
+    sim, contacts = run_lockstep(ws, gds, steps=3, tiled=False)
+    assert contacts > 0
     sim.close()
 
 
