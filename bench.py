@@ -82,13 +82,16 @@ def timed_run(sim, N, args, stress_every, kernels=("k_pairs",), steps=None, warm
     steps = args.steps if steps is None else steps
     warmup = args.warmup if warmup is None else warmup
     sim.set_timing(False)
-    sim.step(warmup, stress_every=stress_every, sync=True)
-    # the graphs of the timed call are captured now, so that it replays them only
-    sim.prepare_steps(steps, stress_every=stress_every)
-    torch.cuda.synchronize()
+    # the host's garbage is collected before the warm-up, and no collection runs from there to
+    # the end of the timed region: a collection takes ≈ 50 ms, and the device left idle that
+    # long ran the timed steps that followed 3-4 % slower
     gc.collect()
-    gc.disable()  # no collection of the host's objects inside the timed region
+    gc.disable()
     try:
+        sim.step(warmup, stress_every=stress_every, sync=True)
+        # the graphs of the timed call are captured now, so that it replays them only
+        sim.prepare_steps(steps, stress_every=stress_every)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim.step(steps, stress_every=stress_every, sync=False)
         torch.cuda.synchronize()
